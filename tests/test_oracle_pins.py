@@ -1,0 +1,432 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test fixes one part of the oracle with something independent of it:
+closed forms of the paper's equations, invariants of the compositing sum,
+finite differences of the oracle's own forward (for its hand-written adjoint),
+and library routines (torch's L1 / cross-entropy / Adam) where the paper's
+definition is exactly such a routine.
+
+  P1  Eq. 5 + Eq. 6: fronto-parallel isotropic surfel -> analytic Gaussian footprint
+  P2  Eq. 5 (orthographic J): Sigma' = k^2 [W Sigma W^T]_2x2 + eps I, any rotation
+  P2b Eq. 2 + Eq. 5 with J from a numerically differentiated pinhole projection
+  P3  Eq. 6: sum_k w_k = 1 - T_final; outputs linear in colour / semantics
+  P4  Eq. 6: an opaque front stack hides everything behind it (bit-identical)
+  P5  Eq. 6: 0 <= A < 1, A = 1 - T_final, n_last <= list length
+  P6  sort (Sec. 3.3.1): ties ordered by id, ranges partition the pairs, the
+      tile rectangle covers every pixel that passes the 3-sigma test
+  P7  adjoint of Eq. 5-6 vs central finite differences of the FP64 forward
+  P8  adjoint of the projection vs finite differences of the projection
+  P9  Eq. 7-9, 12 vs torch l1 / cross_entropy in FP64
+  P10 Adam vs torch.optim.Adam in FP64
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2405_14342_amd import synth
+
+OPTS = oracle.Opts()
+
+
+def quat_wxyz(R):
+    x, y, z, w = Rotation.from_matrix(R).as_quat()
+    return np.array([w, x, y, z])
+
+
+def frontal_scene(positions, s, alpha, rgb=None, sem=None, W=128, H=96, f=100.0):
+    """Surfels facing a camera at (0,0,1.5) that looks along +x (yaw 0, pitch 0)."""
+    n = len(positions)
+    Rm = np.array([[0, 0, 1], [-1, 0, 0], [0, -1, 0]], float)   # columns r1, r2, normal
+    q = np.tile(quat_wxyz(Rm)[:, None], (1, n))
+    P = np.asarray(positions, float)
+    rgb = np.full((3, n), 0.5) if rgb is None else rgb
+    sem = np.zeros((2, n)) if sem is None else sem
+    cam = synth.pinhole_camera((0.0, 0.0, 1.5), 0.0, 0.0, W, H, f, cull=False)
+    s2 = np.tile(np.broadcast_to(np.asarray(s, float), (n,))[None], (2, 1))
+    return synth.custom_scene(P[:, 0], P[:, 1], P[:, 2], q, s2,
+                              np.broadcast_to(np.asarray(alpha, float), (n,)), rgb, sem, [cam])
+
+
+# ---------------------------------------------------------------- P1
+
+@pytest.mark.parametrize("pos", [(5.0, 0.0, 1.5), (5.0, 1.2, 2.1), (4.0, -1.5, 0.7)])
+def test_p1_frontal_isotropic_footprint(pos):
+    s, alpha, f = 0.2, 0.8, 100.0
+    rgb = np.array([[0.2], [0.5], [0.9]])
+    sem = np.array([[1.5], [-0.5]])
+    sc = frontal_scene([pos], s, alpha, rgb, sem, f=f)
+    cam = sc.cams[0]
+    prm = oracle.Params.from_scene(sc)
+    out, tf, nl = oracle.render_fwd(prm, cam)
+    # camera frame: x_c = -y_w, y_c = -(z_w - 1.5), z_c = x_w
+    X, Y, Z = -np.float64(np.float32(pos[1])), -(np.float64(np.float32(pos[2])) - 1.5), np.float64(np.float32(pos[0]))
+    u, v = f * X / Z + cam.cx, f * Y / Z + cam.cy
+    sig2 = (f * np.float64(np.float32(s)) / Z) ** 2 + OPTS.eps2d
+    py, px = np.mgrid[0:cam.h, 0:cam.w]
+    r2 = (px + 0.5 - u) ** 2 + (py + 0.5 - v) ** 2
+    qv = r2 / sig2
+    a = np.float64(np.float32(alpha))
+    expect = np.where(qv <= OPTS.q_cut, a * np.exp(-0.5 * qv), 0.0).reshape(-1)
+    ok = np.abs(qv - OPTS.q_cut).reshape(-1) > 1e-4          # exclude the cut boundary itself
+    A = out[-1]
+    assert np.count_nonzero(expect) > 100
+    assert np.max(np.abs(A - expect)[ok]) < 1e-6
+    for ch in range(3):
+        assert np.max(np.abs(out[ch] - expect * rgb[ch, 0])[ok]) < 1e-6
+    for ch in range(2):
+        assert np.max(np.abs(out[3 + ch] - expect * sem[ch, 0])[ok]) < 1e-6
+    assert np.max(np.abs(out[5] - expect * Z)[ok]) < 1e-5
+
+
+# ---------------------------------------------------------------- P2
+
+def test_p2_ortho_covariance_any_rotation():
+    rng = np.random.default_rng(3)
+    n = 40
+    Rs = Rotation.random(n, random_state=4).as_matrix()
+    q = np.stack([quat_wxyz(R) for R in Rs], axis=1) * rng.uniform(0.5, 2.0, (1, n))
+    s = rng.uniform(0.02, 0.3, (2, n))
+    x, y = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    z = rng.uniform(-0.2, 0.2, n)
+    cam = synth.ortho_bev_camera((0.0, 0.0), 10.0, 64, 64, m_per_px=0.05)
+    sc = synth.custom_scene(x, y, z, q, s, np.full(n, 0.5), np.zeros((3, n)), np.zeros((1, n)), [cam])
+    prm = oracle.Params.from_scene(sc)
+    geo = oracle.geo64(prm, cam)
+    Rcw = np.float64(cam.R_cw)
+    k = np.float64(np.float32(cam.fx))
+    for i in range(n):
+        qi = prm.q[:, i] / np.linalg.norm(prm.q[:, i])
+        R = Rotation.from_quat([qi[1], qi[2], qi[3], qi[0]]).as_matrix()
+        S = np.diag([prm.s[0, i], prm.s[1, i], 0.0])
+        Sig = R @ S @ S.T @ R.T                                     # Eq. 2, s_z = 0
+        Sp = k * k * (Rcw @ Sig @ Rcw.T)[:2, :2] + OPTS.eps2d * np.eye(2)
+        inv = np.linalg.inv(Sp)
+        np.testing.assert_allclose(geo[i, 2:5], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=1e-7)
+        t = Rcw @ np.array([prm.x[i], prm.y[i], prm.z[i]]) + np.float64(cam.t_cw)
+        np.testing.assert_allclose(geo[i, :2], [k * t[0] + cam.cx, k * t[1] + cam.cy], rtol=1e-12)
+        np.testing.assert_allclose(geo[i, 5], t[2], rtol=1e-12)
+
+
+def test_p2b_pinhole_covariance_numerical_jacobian():
+    sc = synth.tiny_scene(nx=6, ny=6, n_views=2)
+    prm = oracle.Params.from_scene(sc)
+    for cam in sc.cams:
+        geo = oracle.geo64(prm, cam)
+        vis, rec, _ = oracle.contract(prm, cam)
+        Rcw, tcw = np.float64(cam.R_cw), np.float64(cam.t_cw)
+        fx, fy = np.float64(np.float32(cam.fx)), np.float64(np.float32(cam.fy))
+
+        def proj(t):
+            return np.array([fx * t[0] / t[2] + cam.cx, fy * t[1] / t[2] + cam.cy])
+
+        checked = 0
+        for i in np.nonzero(vis)[0]:
+            t = Rcw @ np.array([prm.x[i], prm.y[i], prm.z[i]]) + tcw
+            if abs(t[0] / t[2]) > 0.6 * cam.w / fx or abs(t[1] / t[2]) > 0.6 * cam.h / fy:
+                continue                    # inside the Jacobian clamp only
+            h = 1e-6 * t[2]
+            J = np.stack([(proj(t + h * e) - proj(t - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+            qi = prm.q[:, i] / np.linalg.norm(prm.q[:, i])
+            R = Rotation.from_quat([qi[1], qi[2], qi[3], qi[0]]).as_matrix()
+            S = np.diag([prm.s[0, i], prm.s[1, i], 0.0])
+            Sp = J @ Rcw @ (R @ S @ S.T @ R.T) @ Rcw.T @ J.T + OPTS.eps2d * np.eye(2)   # Eq. 5
+            inv = np.linalg.inv(Sp)
+            np.testing.assert_allclose(geo[i, 2:5], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=2e-7)
+            np.testing.assert_allclose(geo[i, :2], proj(t), rtol=1e-12)
+            # the FP32 contract is the same projection, to FP32 rounding
+            np.testing.assert_allclose(rec[i, :5], geo[i, :5], rtol=1e-4, atol=1e-5)
+            checked += 1
+        assert checked > 5
+
+
+# ---------------------------------------------------------------- P3 / P5
+
+def test_p3_telescoping_and_linearity():
+    sc = synth.config1()
+    cam = sc.cams[0]
+    prm = oracle.Params.from_scene(sc)
+    prm1 = prm.copy()
+    prm1.rgb[:] = 1.0
+    out, tf, nl = oracle.render_fwd(prm1, cam)
+    A = out[-1]
+    for ch in range(3):
+        np.testing.assert_allclose(out[ch], A, atol=1e-13)          # sum_k w_k = 1 - T
+    np.testing.assert_allclose(A, 1.0 - tf, atol=1e-15)
+    rng = np.random.default_rng(0)
+    pa, pb, pab = prm.copy(), prm.copy(), prm.copy()
+    pa.rgb[:] = rng.uniform(0, 1, pa.rgb.shape)
+    pb.rgb[:] = rng.uniform(0, 1, pb.rgb.shape)
+    pab.rgb[:] = pa.rgb + pb.rgb
+    pa.sem[:] = rng.normal(size=pa.sem.shape)
+    pb.sem[:] = rng.normal(size=pb.sem.shape)
+    pab.sem[:] = pa.sem + pb.sem
+    oa, ob, oab = (oracle.render_fwd(p, cam)[0] for p in (pa, pb, pab))
+    np.testing.assert_allclose(oab[:3 + prm.C], oa[:3 + prm.C] + ob[:3 + prm.C], atol=1e-12)
+    np.testing.assert_array_equal(oab[-2:], oa[-2:])                # depth/alpha untouched
+
+
+def test_p5_alpha_range_and_nlast():
+    sc = synth.config1()
+    cam = sc.cams[0]
+    prm = oracle.Params.from_scene(sc)
+    out, tf, nl = oracle.render_fwd(prm, cam)
+    keys, ids, ranges = oracle.tile_lists(prm, cam)
+    A = out[-1]
+    assert np.all(A >= 0.0) and np.all(A < 1.0)
+    assert np.all(tf > 0.0) and np.all(tf <= 1.0)
+    tx = (cam.w + 15) // 16
+    py, px = np.divmod(np.arange(cam.w * cam.h), cam.w)
+    tile = (py // 16) * tx + px // 16
+    lens = ranges[tile, 1] - ranges[tile, 0]
+    assert np.all(nl >= 0) and np.all(nl <= lens)
+    assert A.max() > 0.9
+    # prefix property: rendering with only the first k surfels of every list
+    # can only raise the transmittance (T is non-increasing along the list)
+    prm_f = prm.copy()
+    far = np.argsort(prm.x)[-prm.n // 2:]
+    prm_f.alpha[far] = 1e-12          # (nearly) remove the far half
+    _, tf2, _ = oracle.render_fwd(prm_f, cam)
+    assert np.all(tf2 >= tf - 1e-15)
+
+
+# ---------------------------------------------------------------- P4
+
+def test_p4_opaque_stack_occludes():
+    rng = np.random.default_rng(1)
+    front = [(3.0 + 0.01 * k, 0.0, 1.5) for k in range(4)]
+    back = [(5.0 + 0.05 * k, rng.uniform(-0.5, 0.5), 1.5 + rng.uniform(-0.3, 0.3)) for k in range(10)]
+    pos = front + back
+    n = len(pos)
+    s = np.array([1.0] * 4 + [0.3] * 10)
+    alpha = np.array([0.999] * 4 + [0.9] * 10)
+    rgb = rng.uniform(0, 1, (3, n))
+    sem = rng.normal(size=(2, n))
+    sc = frontal_scene(pos, 0.5, 0.9, rgb, sem)
+    sc.s[:] = np.float32(np.tile(s[None], (2, 1)))
+    sc.alpha[:] = np.float32(alpha)
+    cam = sc.cams[0]
+    prm = oracle.Params.from_scene(sc)
+    out1, tf1, nl1 = oracle.render_fwd(prm, cam)
+    prm2 = prm.copy()
+    prm2.rgb[:, 4:] = rng.uniform(0, 1, (3, 10))
+    prm2.sem[:, 4:] = rng.normal(size=(2, 10))
+    out2, tf2, nl2 = oracle.render_fwd(prm2, cam)
+    stopped = (tf1 < OPTS.t_eps) & (nl1 <= 4)
+    assert stopped.sum() > 150
+    np.testing.assert_array_equal(out1[:, stopped], out2[:, stopped])
+    # the stack is opaque: alpha is 1 - T with T < t_eps
+    assert np.all(out1[-1, stopped] > 1.0 - OPTS.t_eps)
+
+
+# ---------------------------------------------------------------- P6
+
+def test_p6_ties_by_id_and_ranges_partition():
+    n1 = 24
+    i, j = np.meshgrid(np.arange(n1), np.arange(n1), indexing="xy")
+    x = 0.1 * (i.reshape(-1) - 11.5)
+    y = 0.1 * (j.reshape(-1) - 11.5)
+    n = x.size
+    q = np.tile(np.array([[1.0], [0.0], [0.0], [0.0]]), (1, n))
+    cam = synth.ortho_bev_camera((0.0, 0.0), 10.0, 64, 48, m_per_px=0.05)
+    sc = synth.custom_scene(x, y, np.zeros(n), q, np.full((2, n), 0.08), np.full(n, 0.5),
+                            np.zeros((3, n)), np.zeros((1, n)), [cam])
+    prm = oracle.Params.from_scene(sc)
+    keys, ids, ranges = oracle.tile_lists(prm, cam)
+    P = len(keys)
+    assert P > 0
+    assert np.all(np.diff(keys.astype(np.uint64)) >= 0)
+    depth = (keys & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    assert np.unique(depth).size == 1                      # all depths tie
+    tile = (keys >> np.uint64(32)).astype(np.int64)
+    for t in range(ranges.shape[0]):
+        a, b = ranges[t]
+        assert np.all(tile[a:b] == t)
+        assert np.all(np.diff(ids[a:b]) > 0)              # ties ordered by surfel id
+    assert ranges[0, 0] == 0 and ranges[-1, 1] == P
+    assert np.all(ranges[1:, 0] == ranges[:-1, 1])
+
+
+@pytest.mark.parametrize("which", ["c1", "ortho"])
+def test_p6_rect_covers_every_contributing_pixel(which):
+    if which == "c1":
+        sc = synth.config1()
+        sel = np.arange(0, sc.n, 5)
+    else:
+        sc = synth.tiny_scene(nx=12, ny=12)
+        sc.cams = [synth.ortho_bev_camera((1.5, 0.0), 5.0, 40, 40, m_per_px=0.03)]
+        sel = np.arange(sc.n)
+    cam = sc.cams[0]
+    prm = oracle.Params.from_scene(sc)
+    vis, rec, rect = oracle.contract(prm, cam)
+    py, px = np.mgrid[0:cam.h, 0:cam.w]
+    pxc = (px.astype(np.float32) + np.float32(0.5)).reshape(-1)
+    pyc = (py.astype(np.float32) + np.float32(0.5)).reshape(-1)
+    tx, ty = px.reshape(-1) // 16, py.reshape(-1) // 16
+    hits = 0
+    for i in sel:
+        if not vis[i]:
+            continue
+        u, v, A, B, C = (np.float32(t) for t in rec[i, :5])
+        dx, dy = pxc - u, pyc - v
+        q = (A * (dx * dx) + C * (dy * dy)) + np.float32(2.0) * (B * (dx * dy))
+        inside = q <= np.float32(9.0)
+        x0, x1, y0, y1 = rect[i]
+        cov = (tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)
+        assert not np.any(inside & ~cov)
+        hits += inside.sum()
+    assert hits > 1000
+
+
+# ---------------------------------------------------------------- P7 / P8
+
+def _functional(prm, cams, Gs, opts):
+    tot = 0.0
+    for cam, G in zip(cams, Gs):
+        out, _, _ = oracle.render_fwd(prm, cam, opts)
+        tot += float(np.sum(G * out))
+    return tot
+
+
+@pytest.mark.parametrize("n_views", [1, 2])
+def test_p7_render_adjoint_matches_finite_differences(n_views):
+    sc = synth.tiny_scene(n_views=n_views)
+    opts = oracle.Opts(t_eps=0.0)          # no early stop: the forward is smooth in the values
+    prm = oracle.Params.from_scene(sc)
+    rng = np.random.default_rng(11)
+    Gs = [rng.normal(size=(5 + prm.C, c.w * c.h)) for c in sc.cams]
+    grads = np.zeros((11 + prm.C) * prm.n)
+    for cam, G in zip(sc.cams, Gs):
+        out, tf, nl = oracle.render_fwd(prm, cam, opts)
+        oracle.render_bwd(prm, cam, out, G, tf, nl, opts, grads=grads)
+    g = oracle.split_grads(grads, prm.n, prm.C)
+    h = 1e-6
+    worst = 0.0
+    for name in oracle.GRAD_NAMES:
+        arr = getattr(prm, name)
+        flat = arr.reshape(-1)
+        an = g[name].reshape(-1)
+        scale = max(np.abs(an).max(), 1e-12)
+        for k in range(flat.size):
+            old = flat[k]
+            flat[k] = old + h
+            lp = _functional(prm, sc.cams, Gs, opts)
+            flat[k] = old - h
+            lm = _functional(prm, sc.cams, Gs, opts)
+            flat[k] = old
+            fd = (lp - lm) / (2 * h)
+            err = abs(fd - an[k]) / scale
+            worst = max(worst, err)
+            assert err < 1e-6, (name, k, fd, an[k])
+        assert np.abs(an).max() > 0, name
+    assert worst < 1e-6
+
+
+def test_p7_loss_chain_matches_finite_differences():
+    sc = synth.tiny_scene(n_views=2, n_sem=3)
+    opts = oracle.Opts(t_eps=0.0)
+    prm = oracle.Params.from_scene(sc)
+    expo = np.array([[0.1, -0.05], [-0.2, 0.03]])
+
+    def total(p, e):
+        return oracle.loss_and_grads(p, sc.cams, sc.targets, e, opts)[0]
+
+    L0, grads, dexp, _ = oracle.loss_and_grads(prm, sc.cams, sc.targets, expo, opts)
+    g = oracle.split_grads(grads, prm.n, prm.C)
+    rng = np.random.default_rng(2)
+    h = 1e-6
+    for name in oracle.GRAD_NAMES:
+        flat = getattr(prm, name).reshape(-1)
+        an = g[name].reshape(-1)
+        for k in rng.choice(flat.size, 6, replace=False):
+            old = flat[k]
+            flat[k] = old + h
+            lp = total(prm, expo)
+            flat[k] = old - h
+            lm = total(prm, expo)
+            flat[k] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - an[k]) <= 1e-5 * max(np.abs(an).max(), 1e-9), (name, k, fd, an[k])
+    for v in range(2):
+        for j in range(2):
+            e = expo.copy()
+            e[v, j] += h
+            lp = total(prm, e)
+            e[v, j] -= 2 * h
+            lm = total(prm, e)
+            assert abs((lp - lm) / (2 * h) - dexp[v, j]) < 1e-6
+
+
+def test_p8_projection_adjoint_vs_finite_differences():
+    sc = synth.tiny_scene(nx=5, ny=5, n_views=2)
+    # one surfel far to the side so that the Jacobian clamp is active
+    sc.y[0] = np.float32(3.0)
+    prm = oracle.Params.from_scene(sc)
+    rng = np.random.default_rng(9)
+    h = 1e-7
+    for cam in sc.cams:
+        for i in range(prm.n):
+            dgeo = rng.normal(size=6)
+            an = oracle.geo64_adjoint(prm, cam, i, dgeo)
+            fields = [(prm.z, None)] + [(prm.q, k) for k in range(4)] + [(prm.s, k) for k in range(2)]
+            for f_i, (arr, row) in enumerate(fields):
+                ref = arr if row is None else arr[row]
+                old = ref[i]
+                ref[i] = old + h
+                gp = oracle.geo64(prm, cam)[i]
+                ref[i] = old - h
+                gm = oracle.geo64(prm, cam)[i]
+                ref[i] = old
+                fd = float(np.dot((gp - gm) / (2 * h), dgeo))
+                assert abs(fd - an[f_i]) <= 1e-6 * max(1.0, abs(an).max()), (i, f_i, fd, an[f_i])
+
+
+# ---------------------------------------------------------------- P9 / P10
+
+def test_p9_loss_matches_torch():
+    rng = np.random.default_rng(4)
+    C, npix = 5, 777
+    out = np.concatenate([rng.uniform(0, 1, (3, npix)), rng.normal(size=(C, npix)),
+                          rng.uniform(0, 9, (1, npix)), rng.uniform(0, 1, (1, npix))])
+    tgt = rng.uniform(0, 1, (3, npix)).astype(np.float32)
+    label = rng.integers(0, C, npix).astype(np.uint8)
+    mask = (rng.uniform(size=npix) < 0.7).astype(np.uint8)
+    mc = int(mask.sum())
+    a, b, lc, ls, scale = 0.12, -0.03, 1.0, 0.06, 1.0 / 3
+    L, G, dexp = oracle.loss(C, out, tgt, label, mask, mc, a, b, lc, ls, scale)
+    O = torch.tensor(out, dtype=torch.float64, requires_grad=True)
+    ta = torch.tensor(a, dtype=torch.float64, requires_grad=True)
+    tb = torch.tensor(b, dtype=torch.float64, requires_grad=True)
+    m = torch.tensor(mask, dtype=torch.bool)
+    cprime = torch.exp(ta) * O[:3] + tb                                   # Eq. 7
+    l1 = torch.nn.functional.l1_loss(cprime[:, m], torch.tensor(tgt, dtype=torch.float64)[:, m],
+                                     reduction="sum") / mc                 # Eq. 8
+    ce = torch.nn.functional.cross_entropy(O[3:3 + C, m].T, torch.tensor(label, dtype=torch.long)[m],
+                                           reduction="sum") / mc           # Eq. 9
+    Lt = scale * (lc * l1 + ls * ce)                                       # Eq. 12
+    Lt.backward()
+    assert abs(L - Lt.item()) < 1e-12
+    np.testing.assert_allclose(G, O.grad.numpy(), atol=1e-14)
+    np.testing.assert_allclose(dexp, [ta.grad.item(), tb.grad.item()], atol=1e-12)
+    # an empty mask contributes nothing
+    L0, G0, d0 = oracle.loss(C, out, tgt, label, np.zeros(npix, np.uint8), 0)
+    assert L0 == 0.0 and not G0.any() and not d0.any()
+
+
+def test_p10_adam_matches_torch():
+    rng = np.random.default_rng(5)
+    p0 = rng.normal(size=257)
+    p = p0.copy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    tp = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 6):
+        g = rng.normal(size=p.size)
+        oracle.adam(p, g, m, v, 3e-3, step)
+        tp.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        np.testing.assert_allclose(p, tp.detach().numpy(), rtol=0, atol=1e-13)
