@@ -1,0 +1,256 @@
+/*
+ * rogs.h -- C ABI of librogs, differentiable tile-based splatting of meshgrid
+ * Gaussian surfels (RoGs, arXiv 2405.14342) on AMD MI355X (gfx950).
+ *
+ * The library renders 2D Gaussian surfels (Sec. 3.1, Eq. 1-3: covariance
+ * R S S^T R^T with s_z = 0) into camera images with the EWA projection of
+ * Eq. 5, sorts them by view depth and alpha-composites colour, semantic
+ * logits, depth and alpha front to back (Eq. 6), evaluates the masked L1 and
+ * cross-entropy losses with per-camera exposure (Eq. 7-9, Eq. 12), runs the
+ * adjoint of all of that, and applies Adam (Sec. 4.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Memory.  Every array argument is a DEVICE pointer owned by the caller,
+ *    except the structs themselves and `rogs_camera` arrays, which live in
+ *    host memory and are read during the call.  The library allocates no
+ *    device memory in these calls: scratch space is one caller-provided
+ *    workspace whose size `rogs_workspace_size` returns.  The context owns
+ *    a small pinned host buffer and a few events.
+ *  - Streams.  `stream` is a hipStream_t (NULL = the null stream).  Calls
+ *    enqueue work and return without waiting, except where a flag asks for
+ *    a host read-back (ROGS_SYNC_COUNT).
+ *  - Errors.  Every call returns ROGS_OK (0) or a negative status; the text
+ *    of the last error is kept in the context (`rogs_last_error`).  No
+ *    exception crosses the ABI.  A context is used by one host thread at a
+ *    time.  Invalid arguments are rejected before any GPU work is enqueued.
+ *  - Parameter layout.  Surfel parameters are structure-of-arrays FP32,
+ *    component-major: q[4][N] (w, x, y, z), s[2][N], rgb[3][N], sem[C][N].
+ *  - Packed parameter block (gradients and Adam): K = 11 + C rows of N
+ *    floats each, in the row order
+ *        0 z | 1-4 q(w,x,y,z) | 5-6 s (log-scale for Adam) |
+ *        7 alpha (logit for Adam) | 8-10 rgb | 11.. 11+C-1 sem
+ *  - Image layout.  Views of a batch are packed one after another; view v
+ *    starts at pixel offset P_v = sum_{u<v} W_u H_u.  A per-pixel image with
+ *    K channels stores channel c of pixel (x, y) of view v at
+ *        K * P_v + c * W_v * H_v + y * W_v + x.
+ *    Rendered images have K = 5 + C channels: R, G, B, sem[0..C-1], D, A.
+ *
+ * FP32 key contract
+ * -----------------
+ * Everything that decides an integer (culling, tile rectangles, the depth
+ * sort key, whether a pixel is touched by a surfel) is computed in IEEE
+ * binary32, round to nearest even, without fused multiply-add, with
+ * correctly rounded division and square root, exactly in this order
+ * ("a*b + c*d" means round(round(a*b) + round(c*d))):
+ *
+ *   tx = ((R0*x + R1*y) + R2*z) + t0,  ty, tz likewise with rows 1, 2
+ *   visible needs tz >= z_near; if cull_lat > 0 also, with dx = x - o0,
+ *     dy = y - o1: |dx*ex0 + dy*ex1| <= cull_lat and
+ *     0 <= dx*ez0 + dy*ez1 <= cull_fwd     (ground rectangle, supp. Sec. 2.1)
+ *   nn = ((qw*qw + qx*qx) + qy*qy) + qz*qz > 0;  n = sqrt(nn);
+ *   w = qw/n, a = qx/n, b = qy/n, c = qz/n
+ *   r1 = (1 - 2*(b*b + c*c), 2*(a*b + w*c), 2*(a*c - w*b))
+ *   r2 = (2*(a*b - w*c), 1 - 2*(a*a + c*c), 2*(b*c + w*a))
+ *   T1 = s_x*r1, T2 = s_y*r2;  c1_k = (Rk0*T1_0 + Rk1*T1_1) + Rk2*T1_2, c2 likewise
+ *   pinhole: limx = (0.65*W)/fx, limy = (0.65*H)/fy, xr = tx/tz, yr = ty/tz,
+ *            xc = min(max(xr, -limx), limx), yc likewise,
+ *            j00 = fx/tz, j11 = fy/tz, j02 = -(j00*xc), j12 = -(j11*yc),
+ *            u = fx*xr + cx, v = fy*yr + cy
+ *   ortho:   j00 = fx, j11 = fy, j02 = j12 = 0, u = fx*tx + cx, v = fy*ty + cy
+ *   m00 = j00*c1_0 + j02*c1_2, m01 = j00*c2_0 + j02*c2_2,
+ *   m10 = j11*c1_1 + j12*c1_2, m11 = j11*c2_1 + j12*c2_2
+ *   g0 = m00*m00 + m01*m01, g1 = m10*m10 + m11*m11,
+ *   s00 = g0 + eps, s11 = g1 + eps, s01 = m00*m10 + m01*m11,
+ *   dm = m00*m11 - m01*m10, det = (dm*dm + eps*(g0 + g1)) + eps*eps > 0
+ *   conic A = s11/det, B = -(s01/det), C = s00/det
+ *   hx = sqrt(q_cut*s00) + 1, hy = sqrt(q_cut*s11) + 1
+ *   tile rect: x0 = floor((u - hx)/tile_w), x1 = floor((u + hx)/tile_w) + 1,
+ *              y0, y1 likewise; each clamped to [0, tiles]; needs x0<x1, y0<y1
+ *              (and u, v, hx, hy, A, B, C finite)
+ *   sort key  = (global tile index << 32) | bit pattern of tz, ties by id
+ *   pixel (px, py) is touched iff q32 <= q_cut, where dx = (px + 0.5) - u,
+ *   dy = (py + 0.5) - v, q32 = (A*(dx*dx) + C*(dy*dy)) + 2*(B*(dx*dy)).
+ *
+ * Values (Eq. 6): for touched pixels g = exp(-q/2), a = min(alpha*g,
+ * alpha_max), w = a*T, O += w*f for f in (rgb, sem, tz), T *= 1 - a; a pixel
+ * stops after the surfel that takes T below t_eps; A = 1 - T.
+ */
+#ifndef ROGS_H
+#define ROGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ROGS_API __attribute__((visibility("default")))
+#else
+#define ROGS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status */
+#define ROGS_OK          0
+#define ROGS_NOT_READY   1   /* serve poll: result not finished yet */
+#define ROGS_EINVAL     -1   /* invalid argument (nothing enqueued) */
+#define ROGS_ENOMEM     -2   /* workspace or arena too small */
+#define ROGS_ECAPACITY  -3   /* pair buffer too small; needed size reported */
+#define ROGS_EHIP       -4   /* a HIP runtime call failed */
+#define ROGS_EREJECT    -5   /* serve admission rejected the request */
+#define ROGS_ESTATE     -6   /* call out of order (e.g. bin_sort before project) */
+
+#define ROGS_PINHOLE 0
+#define ROGS_ORTHO   1
+
+/* flags */
+#define ROGS_SYNC_COUNT   1u  /* rogs_bin_sort: read the pair count back (host sync) */
+#define ROGS_ACCUMULATE   2u  /* rogs_render_bwd: add into grads instead of overwriting */
+
+typedef struct rogs_ctx rogs_ctx;
+
+/* Surfel parameters in the render domain (activated s and alpha), device SoA.
+ * Eq. 3: Theta = {(x, y, z), (r, g, b), (s_x, s_y), alpha, R, Sem}; x, y are
+ * the fixed grid vertices (Sec. 3.1, meshgrid layout), the rest learnable. */
+typedef struct {
+  int32_t n;            /* number of surfels N (>= 1) */
+  int32_t n_sem;        /* semantic classes C (1..8 or 16) */
+  const float* x;       /* [N] grid vertex x (m) */
+  const float* y;       /* [N] grid vertex y (m) */
+  const float* z;       /* [N] height (m) */
+  const float* q;       /* [4][N] rotation quaternion w, x, y, z (not necessarily unit) */
+  const float* s;       /* [2][N] scales s_x, s_y > 0 (m) */
+  const float* alpha;   /* [N] opacity in (0, 1) */
+  const float* rgb;     /* [3][N] colour */
+  const float* sem;     /* [C][N] semantic logits */
+} rogs_surfels;
+
+/* One view (host memory).  OpenCV camera: x right, y down, z forward;
+ * camera-space point t = R_cw * mu + t_cw.  Pinhole: fx, fy, cx, cy in
+ * pixels.  Orthographic (Sec. 3.3.1, J = identity): fx, fy in pixels per
+ * metre.  The ground cull rectangle (supp. Sec. 2.1) is given by its origin
+ * (camera centre xy), unit ground directions of the camera x and z axes, a
+ * half-width and a forward length; cull_lat <= 0 disables it. */
+typedef struct {
+  int32_t w, h;         /* image size, 1..16384 */
+  int32_t model;        /* ROGS_PINHOLE or ROGS_ORTHO */
+  int32_t reserved;     /* must be 0 */
+  float fx, fy, cx, cy;
+  float R_cw[9];        /* row-major */
+  float t_cw[3];
+  float z_near;
+  float cull_o[2], cull_ex[2], cull_ez[2];
+  float cull_lat, cull_fwd;
+} rogs_camera;
+
+typedef struct {
+  int32_t tile_w, tile_h;  /* tile shape; tile_w in {1,2,...,64} dividing 64 and
+                              tile_w*tile_h in {64, 128, 256}; default 16 x 16 */
+  float eps2d;             /* EWA low-pass added to Sigma' (px^2), default 0.3 */
+  float q_cut;             /* Mahalanobis cut, default 9 (3 sigma) */
+  float alpha_max;         /* opacity clamp, default 0.99 */
+  float t_eps;             /* termination threshold on T, default 1e-6 */
+} rogs_render_opts;
+
+/* Loss targets of a batch (Eq. 8, 9), device arrays in the image layout. */
+typedef struct {
+  const float* rgb;        /* [3 channels per view] target colour */
+  const uint8_t* label;    /* [1 channel per view] class index < C */
+  const uint8_t* mask;     /* [1 channel per view] 1 = road pixel (M), 0 = ignored */
+  const float* exposure;   /* [V][2] per-view (a, b) of Eq. 7 */
+  float lambda_c;          /* Eq. 12 weight of L_c (paper: 1) */
+  float lambda_s;          /* Eq. 12 weight of L_s (paper: 0.06) */
+  float view_scale;        /* multiplies every view's loss (1 / total views) */
+} rogs_targets;
+
+/* Per-group Adam learning rates (Sec. 4.2). */
+typedef struct {
+  float z, q, s, alpha, rgb, sem, exposure;
+} rogs_lr;
+
+/* ------------------------------------------------------ context */
+ROGS_API int rogs_create(rogs_ctx** ctx);
+ROGS_API void rogs_destroy(rogs_ctx* ctx);
+ROGS_API const char* rogs_last_error(const rogs_ctx* ctx);
+/* Fills opts with the defaults listed above. */
+ROGS_API void rogs_default_opts(rogs_render_opts* opts);
+
+/* Bytes of workspace for a batch of n_views cameras over s->n surfels with
+ * room for pair_capacity (surfel, tile) pairs.  Host-only computation. */
+ROGS_API int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
+                        const rogs_render_opts* opts, int64_t pair_capacity, size_t* bytes);
+
+/* a1-a2, Eq. 5 + supp. Sec. 2.1.  Starts a batch: uploads the view table into
+ * the workspace, culls and projects every (view, surfel) with the FP32 key
+ * contract, counts tiles per surfel and scans the counts.  The batch state
+ * (layout, views) is kept in ctx for the calls below, which must pass the
+ * same workspace. */
+ROGS_API int rogs_project(rogs_ctx* ctx, const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
+                 const rogs_render_opts* opts, void* ws, size_t ws_bytes, int64_t pair_capacity,
+                 void* stream);
+
+/* a3-a5, Sec. 3.3.1 ("ascending order of original depth").  Emits one
+ * (tile, depth) key per covered tile, radix-sorts the keys stably (ties keep
+ * surfel-id order) and writes per-tile ranges.  With ROGS_SYNC_COUNT the pair
+ * count P is read back first (host sync): if P > pair_capacity the call
+ * returns ROGS_ECAPACITY with *n_pairs_out = P and enqueues nothing more.
+ * Without it the count stays on the device; an overflow is flagged on the
+ * device and reported by rogs_overflow(). n_pairs_out may be NULL. */
+ROGS_API int rogs_bin_sort(rogs_ctx* ctx, void* ws, int64_t* n_pairs_out, uint32_t flags, void* stream);
+
+/* Reads the device pair count and overflow flag of the current batch (host sync). */
+ROGS_API int rogs_pair_count(rogs_ctx* ctx, void* ws, int64_t* n_pairs, int32_t* overflow, void* stream);
+
+/* a6, Eq. 6.  Front-to-back compositing of R, G, B, sem[C], D = sum w t_z and
+ * A = 1 - T into out_images (5 + C channels, image layout above).  Keeps
+ * T_final and the number of list entries each pixel visited in the workspace
+ * for the backward. */
+ROGS_API int rogs_render_fwd(rogs_ctx* ctx, const rogs_surfels* s, void* ws, float* out_images,
+                    void* stream);
+
+/* a7, Eq. 7, 8, 9, 12.  For every pixel of the batch: c' = e^a c + b,
+ * masked L1 over the three colour channels and masked cross-entropy of the
+ * composited logits against the label, each divided by the view's mask
+ * count |M_v|, weighted by lambda_c / lambda_s and view_scale.  Writes
+ * dL/d(out) into dL_dout (5 + C channels; D and A rows are 0), adds the loss
+ * to loss_out[0] and dL/d(a, b) to d_exposure[V][2] (device, accumulate). */
+ROGS_API int rogs_loss(rogs_ctx* ctx, void* ws, const float* out_images, const rogs_targets* t,
+              float* dL_dout, float* loss_out, float* d_exposure, void* stream);
+
+/* a8-a9, adjoint of Eq. 5-6.  Given the forward images and dL/d(out) of
+ * the current batch, writes dL/d(surfel parameters) into the packed block
+ * grads[11 + C][N] (rows: z, q, s, alpha, rgb, sem; w.r.t. the activated
+ * s and alpha), summed over the batch's views.  ROGS_ACCUMULATE adds. */
+ROGS_API int rogs_render_bwd(rogs_ctx* ctx, const rogs_surfels* s, void* ws, const float* out_images,
+                    const float* dL_dout, float* grads, uint32_t flags, void* stream);
+
+/* a10, Adam (Sec. 4.2) with torch semantics (bias correction, dense update)
+ * on the packed raw block params[11 + C][N] (rows 5-6 log-scales, row 7
+ * opacity logit) with moments m, v of the same shape; grads are w.r.t. the
+ * activated values and are chained through exp / sigmoid.  Writes the
+ * refreshed activated scales s_act[2][N] and opacity alpha_act[N].  When
+ * exposure != NULL also steps exposure[n_views][2] with d_exposure and its
+ * moments m_exp, v_exp.  step >= 1. */
+ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* params, const float* grads,
+                   float* m, float* v, float* s_act, float* alpha_act, const rogs_lr* lr,
+                   int64_t step, float beta1, float beta2, float eps, float* exposure,
+                   const float* d_exposure, float* m_exp, float* v_exp, int32_t n_views,
+                   void* stream);
+
+/* Read-back helpers for tests (host sync): copy the sorted keys, surfel ids
+ * and per-tile ranges of the current batch to host buffers of the given
+ * capacity. */
+ROGS_API int rogs_debug_pairs(rogs_ctx* ctx, void* ws, uint64_t* keys, int32_t* surfel_ids,
+                     int32_t* views, int64_t cap, uint32_t* ranges, int64_t n_tiles,
+                     void* stream);
+/* Copy the per-(view, surfel) projection records of the current batch:
+ * rec[V][N][8] = u v A B C tz alpha 0, rect[V][N][4], count[V][N]. */
+ROGS_API int rogs_debug_records(rogs_ctx* ctx, void* ws, float* rec, int32_t* rect, uint32_t* count,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROGS_H */

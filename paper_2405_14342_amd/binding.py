@@ -1,0 +1,267 @@
+"""ctypes binding of librogs (see include/rogs.h).
+
+Argument marshalling only: every step of the splatting path runs inside the
+HIP library.  Each method of :class:`Rogs` wraps the C entry point of the same
+name (``Rogs.project`` -> ``rogs_project`` ...), takes torch device tensors
+for the device pointers and raises :class:`RogsError` on a non-zero status.
+The library must have been built (``paper_2405_14342_amd.build``); there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librogs.so")
+
+OK, NOT_READY, EINVAL, ENOMEM, ECAPACITY, EHIP, EREJECT, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6
+SYNC_COUNT, ACCUMULATE = 1, 2
+PINHOLE, ORTHO = 0, 1
+STATUS_NAMES = {0: "OK", 1: "NOT_READY", -1: "EINVAL", -2: "ENOMEM", -3: "ECAPACITY",
+                -4: "EHIP", -5: "EREJECT", -6: "ESTATE"}
+
+EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts",
+            "rogs_workspace_size", "rogs_project", "rogs_bin_sort", "rogs_pair_count",
+            "rogs_render_fwd", "rogs_loss", "rogs_render_bwd", "rogs_adam_step",
+            "rogs_debug_pairs", "rogs_debug_records")
+
+
+class RogsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+
+
+class Surfels(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_sem", ctypes.c_int32), ("x", _vp), ("y", _vp),
+                ("z", _vp), ("q", _vp), ("s", _vp), ("alpha", _vp), ("rgb", _vp), ("sem", _vp)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("R_cw", ctypes.c_float * 9),
+                ("t_cw", ctypes.c_float * 3), ("z_near", ctypes.c_float),
+                ("cull_o", ctypes.c_float * 2), ("cull_ex", ctypes.c_float * 2),
+                ("cull_ez", ctypes.c_float * 2), ("cull_lat", ctypes.c_float),
+                ("cull_fwd", ctypes.c_float)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("eps2d", ctypes.c_float),
+                ("q_cut", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_eps", ctypes.c_float)]
+
+
+class Targets(ctypes.Structure):
+    _fields_ = [("rgb", _vp), ("label", _vp), ("mask", _vp), ("exposure", _vp),
+                ("lambda_c", ctypes.c_float), ("lambda_s", ctypes.c_float),
+                ("view_scale", ctypes.c_float)]
+
+
+class LR(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_float), ("q", ctypes.c_float), ("s", ctypes.c_float),
+                ("alpha", ctypes.c_float), ("rgb", ctypes.c_float), ("sem", ctypes.c_float),
+                ("exposure", ctypes.c_float)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librogs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"librogs.so not found at {path}: run paper_2405_14342_amd/build.py")
+        L = ctypes.CDLL(path)
+        P, I32, I64, U32, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float
+        sig = {
+            "rogs_create": ([ctypes.POINTER(P)], I32),
+            "rogs_destroy": ([P], None),
+            "rogs_last_error": ([P], ctypes.c_char_p),
+            "rogs_default_opts": ([ctypes.POINTER(RenderOpts)], None),
+            "rogs_workspace_size": ([ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
+                                     ctypes.POINTER(RenderOpts), I64, ctypes.POINTER(ctypes.c_size_t)], I32),
+            "rogs_project": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
+                              ctypes.POINTER(RenderOpts), P, ctypes.c_size_t, I64, P], I32),
+            "rogs_bin_sort": ([P, P, ctypes.POINTER(I64), U32, P], I32),
+            "rogs_pair_count": ([P, P, ctypes.POINTER(I64), ctypes.POINTER(I32), P], I32),
+            "rogs_render_fwd": ([P, ctypes.POINTER(Surfels), P, P, P], I32),
+            "rogs_loss": ([P, P, P, ctypes.POINTER(Targets), P, P, P, P], I32),
+            "rogs_render_bwd": ([P, ctypes.POINTER(Surfels), P, P, P, P, U32, P], I32),
+            "rogs_adam_step": ([P, I32, I32, P, P, P, P, P, P, ctypes.POINTER(LR), I64, F, F, F,
+                                P, P, P, P, I32, P], I32),
+            "rogs_debug_pairs": ([P, P, P, P, P, I64, P, I64, P], I32),
+            "rogs_debug_records": ([P, P, P, P, P, P], I32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def ptr(t) -> Optional[int]:
+    """Device (or host) address of a tensor / array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def make_camera(cam) -> Camera:
+    """rogs_camera from a camera description with the fields of synth.Camera."""
+    c = Camera()
+    c.w, c.h, c.model, c.reserved = int(cam.w), int(cam.h), int(cam.model), 0
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R_cw, np.float32).reshape(9)
+    t = np.asarray(cam.t_cw, np.float32).reshape(3)
+    for k in range(9):
+        c.R_cw[k] = float(R[k])
+    for k in range(3):
+        c.t_cw[k] = float(t[k])
+    c.z_near = float(cam.z_near)
+    for k in range(2):
+        c.cull_o[k] = float(cam.cull_o[k])
+        c.cull_ex[k] = float(cam.cull_ex[k])
+        c.cull_ez[k] = float(cam.cull_ez[k])
+    c.cull_lat, c.cull_fwd = float(cam.cull_lat), float(cam.cull_fwd)
+    return c
+
+
+def camera_array(cams: Sequence) -> ctypes.Array:
+    arr = (Camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k] = c if isinstance(c, Camera) else make_camera(c)
+    return arr
+
+
+def default_opts() -> RenderOpts:
+    o = RenderOpts()
+    load_library().rogs_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_opts(tile_w=16, tile_h=16, eps2d=0.3, q_cut=9.0, alpha_max=0.99, t_eps=1e-6) -> RenderOpts:
+    return RenderOpts(tile_w, tile_h, eps2d, q_cut, alpha_max, t_eps)
+
+
+def workspace_size(surf: Surfels, cams, opts: RenderOpts, pair_capacity: int) -> int:
+    """rogs_workspace_size (host-only)."""
+    L = load_library()
+    arr = camera_array(cams)
+    out = ctypes.c_size_t(0)
+    r = L.rogs_workspace_size(ctypes.byref(surf), arr, len(cams), ctypes.byref(opts),
+                              int(pair_capacity), ctypes.byref(out))
+    if r != OK:
+        raise RogsError(r, "rogs_workspace_size rejected its arguments")
+    return int(out.value)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream
+
+
+class Rogs:
+    """One librogs context (rogs_create / rogs_destroy)."""
+
+    def __init__(self):
+        self.L = load_library()
+        h = ctypes.c_void_p()
+        r = self.L.rogs_create(ctypes.byref(h))
+        if r != OK:
+            raise RogsError(r, "rogs_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.rogs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, r: int, what: str):
+        if r != OK:
+            msg = self.L.rogs_last_error(self.h)
+            raise RogsError(r, f"{what}: {msg.decode() if msg else ''}")
+
+    def last_error(self) -> str:
+        m = self.L.rogs_last_error(self.h)
+        return m.decode() if m else ""
+
+    # --- entry points -------------------------------------------------
+    def project(self, surf: Surfels, cams, opts: RenderOpts, ws, pair_capacity: int, stream=None):
+        arr = camera_array(cams)
+        self._check(self.L.rogs_project(self.h, ctypes.byref(surf), arr, len(cams), ctypes.byref(opts),
+                                        ptr(ws), ws.numel() * ws.element_size(), int(pair_capacity),
+                                        _stream(stream)), "rogs_project")
+
+    def bin_sort(self, ws, flags: int = SYNC_COUNT, stream=None, raise_on_capacity=True) -> int:
+        n = ctypes.c_int64(-1)
+        r = self.L.rogs_bin_sort(self.h, ptr(ws), ctypes.byref(n), flags, _stream(stream))
+        if r == ECAPACITY and not raise_on_capacity:
+            return -int(n.value) - 1
+        self._check(r, "rogs_bin_sort")
+        return int(n.value)
+
+    def pair_count(self, ws, stream=None):
+        n, o = ctypes.c_int64(0), ctypes.c_int32(0)
+        self._check(self.L.rogs_pair_count(self.h, ptr(ws), ctypes.byref(n), ctypes.byref(o),
+                                           _stream(stream)), "rogs_pair_count")
+        return int(n.value), int(o.value)
+
+    def render_fwd(self, surf: Surfels, ws, out, stream=None):
+        self._check(self.L.rogs_render_fwd(self.h, ctypes.byref(surf), ptr(ws), ptr(out),
+                                           _stream(stream)), "rogs_render_fwd")
+
+    def loss(self, ws, out, targets: Targets, dL_dout, loss_out, d_exposure, stream=None):
+        self._check(self.L.rogs_loss(self.h, ptr(ws), ptr(out), ctypes.byref(targets), ptr(dL_dout),
+                                     ptr(loss_out), ptr(d_exposure), _stream(stream)), "rogs_loss")
+
+    def render_bwd(self, surf: Surfels, ws, out, dL_dout, grads, flags: int = 0, stream=None):
+        self._check(self.L.rogs_render_bwd(self.h, ctypes.byref(surf), ptr(ws), ptr(out),
+                                           ptr(dL_dout), ptr(grads), flags, _stream(stream)),
+                    "rogs_render_bwd")
+
+    def adam_step(self, n, n_sem, params, grads, m, v, s_act, alpha_act, lr: LR, step, beta1=0.9,
+                  beta2=0.999, eps=1e-8, exposure=None, d_exposure=None, m_exp=None, v_exp=None,
+                  n_views=0, stream=None):
+        self._check(self.L.rogs_adam_step(self.h, int(n), int(n_sem), ptr(params), ptr(grads), ptr(m),
+                                          ptr(v), ptr(s_act), ptr(alpha_act), ctypes.byref(lr),
+                                          int(step), beta1, beta2, eps, ptr(exposure),
+                                          ptr(d_exposure), ptr(m_exp), ptr(v_exp), int(n_views),
+                                          _stream(stream)), "rogs_adam_step")
+
+    def debug_pairs(self, ws, cap: int, n_tiles: int, stream=None):
+        keys = np.zeros(max(cap, 1), np.uint64)
+        ids = np.zeros(max(cap, 1), np.int32)
+        views = np.zeros(max(cap, 1), np.int32)
+        ranges = np.zeros((max(n_tiles, 1), 2), np.uint32)
+        self._check(self.L.rogs_debug_pairs(self.h, ptr(ws), keys.ctypes.data, ids.ctypes.data,
+                                            views.ctypes.data, int(cap), ranges.ctypes.data,
+                                            int(n_tiles), _stream(stream)), "rogs_debug_pairs")
+        return keys, ids, views, ranges
+
+    def debug_records(self, ws, n_views: int, n: int, stream=None):
+        rec = np.zeros((n_views, n, 8), np.float32)
+        rect = np.zeros((n_views, n, 4), np.int32)
+        cnt = np.zeros((n_views, n), np.uint32)
+        self._check(self.L.rogs_debug_records(self.h, ptr(ws), rec.ctypes.data, rect.ctypes.data,
+                                              cnt.ctypes.data, _stream(stream)), "rogs_debug_records")
+        return rec, rect, cnt

@@ -1,0 +1,471 @@
+// Host side of the C ABI declared in include/rogs.h: argument validation,
+// workspace layout, view-table upload and the launch sequence of each entry
+// point.  No device memory is allocated here; the caller owns all of it.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rogs_internal.h"
+
+using rogs::Layout;
+using rogs::ViewDev;
+
+struct rogs_ctx {
+  std::string err;
+  bool have_batch = false;
+  bool sorted = false;
+  Layout L;
+  void* ws = nullptr;
+  int64_t n_pairs_host = -1;
+  void* stage = nullptr;          // pinned staging for the view table upload
+  size_t stage_bytes = 0;
+  hipEvent_t stage_evt = nullptr;
+  bool stage_pending = false;
+  uint32_t* readback = nullptr;   // pinned, for pair-count read-back
+};
+
+namespace {
+
+int fail(rogs_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(rogs_ctx* c, hipError_t e, const char* where) {
+  return fail(c, ROGS_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int check_launch(rogs_ctx* c, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, where);
+  return ROGS_OK;
+}
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+bool is_fin(float x) { return isfinite(x); }
+
+}  // namespace
+
+namespace rogs {
+
+int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
+                const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why) {
+  *why = nullptr;
+  if (!s || !cams || !opts || !L) { *why = "null argument"; return ROGS_EINVAL; }
+  if (s->n < 1) { *why = "surfel count must be >= 1"; return ROGS_EINVAL; }
+  if (!sem_supported(s->n_sem)) { *why = "n_sem must be 1..8 or 16"; return ROGS_EINVAL; }
+  if (n_views < 1 || n_views > kMaxViews) { *why = "n_views out of range"; return ROGS_EINVAL; }
+  if (cap < 0 || cap >= (int64_t(1) << 31)) { *why = "pair_capacity must be in [0, 2^31)"; return ROGS_EINVAL; }
+  const int tw = opts->tile_w, th = opts->tile_h;
+  if (tw < 1 || tw > 64 || (64 % tw) != 0 || th < 1 || tw * th < 64 || tw * th > 256 ||
+      ((tw * th) & (tw * th - 1)) != 0) {
+    *why = "tile shape: tile_w must divide 64 and tile_w*tile_h must be 64, 128 or 256";
+    return ROGS_EINVAL;
+  }
+  if (!(opts->eps2d >= 0.0f) || !is_fin(opts->eps2d) || !(opts->q_cut > 0.0f) ||
+      !is_fin(opts->q_cut) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
+      !(opts->t_eps >= 0.0f && opts->t_eps < 1.0f)) {
+    *why = "render options out of range";
+    return ROGS_EINVAL;
+  }
+  Layout l;
+  l.N = s->n;
+  l.C = s->n_sem;
+  l.V = n_views;
+  l.tw = tw;
+  l.th = th;
+  l.ppl = tw * th / 64;
+  l.FS = feat_stride(l.C);
+  l.GS = grad_stride(l.C);
+  l.nb = (l.N + kProjBlock - 1) / kProjBlock;
+  l.eps2d = opts->eps2d;
+  l.q_cut = opts->q_cut;
+  l.alpha_max = opts->alpha_max;
+  l.t_eps = opts->t_eps;
+  l.cap = cap;
+  int64_t loss_blocks = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const rogs_camera& c = cams[v];
+    if (c.w < 1 || c.h < 1 || c.w > 16384 || c.h > 16384) { *why = "camera size out of range"; return ROGS_EINVAL; }
+    if (c.model != ROGS_PINHOLE && c.model != ROGS_ORTHO) { *why = "unknown camera model"; return ROGS_EINVAL; }
+    if (c.reserved != 0) { *why = "camera.reserved must be 0"; return ROGS_EINVAL; }
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !is_fin(c.fx) || !is_fin(c.fy) || !is_fin(c.cx) ||
+        !is_fin(c.cy) || !is_fin(c.z_near)) {
+      *why = "camera intrinsics must be finite with fx, fy > 0";
+      return ROGS_EINVAL;
+    }
+    for (int k = 0; k < 9; ++k) if (!is_fin(c.R_cw[k])) { *why = "camera pose not finite"; return ROGS_EINVAL; }
+    for (int k = 0; k < 3; ++k) if (!is_fin(c.t_cw[k])) { *why = "camera pose not finite"; return ROGS_EINVAL; }
+    const int64_t np = (int64_t)c.w * c.h;
+    l.total_pix += np;
+    l.max_view_pix = std::max(l.max_view_pix, np);
+    l.total_tiles += (int64_t)((c.w + tw - 1) / tw) * ((c.h + th - 1) / th);
+    loss_blocks += (np + 255) / 256;
+  }
+  if (l.total_tiles >= (int64_t(1) << 31) || l.total_pix >= (int64_t(1) << 40)) {
+    *why = "batch too large";
+    return ROGS_EINVAL;
+  }
+  l.slots = (int64_t)l.V * l.N;
+  if (l.slots >= (int64_t(1) << 32)) { *why = "n_views * n must be < 2^32"; return ROGS_EINVAL; }
+  int tb = 1;
+  while ((int64_t(1) << tb) < l.total_tiles) ++tb;
+  l.tile_bits = tb;
+  l.sort_blocks = std::max<int64_t>(1, (cap + kSortTile - 1) / kSortTile);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
+  l.o_views = take(sizeof(ViewDev) * l.V);
+  l.o_misc = take(sizeof(uint32_t) * kMiscCount);
+  l.o_mcount = take(sizeof(uint32_t) * l.V);
+  l.o_lpart = take(sizeof(int64_t) * (l.V + 1) + sizeof(float) * 3 * loss_blocks);
+  l.o_cnt = take(4 * (size_t)l.slots);
+  l.o_off = take(4 * (size_t)l.slots);
+  l.o_rec = take(32 * (size_t)l.slots);
+  l.o_rect = take(8 * (size_t)l.slots);
+  l.o_feat = take(4 * (size_t)l.N * l.FS);
+  l.o_part = take(4 * (size_t)l.V * l.nb);
+  l.o_parttmp = take(4 * scan_tmp_words((int64_t)l.V * l.nb));
+  l.o_keys = take(8 * (size_t)cap);
+  l.o_keys2 = take(8 * (size_t)cap);
+  l.o_vals = take(4 * (size_t)cap);
+  l.o_vals2 = take(4 * (size_t)cap);
+  l.o_pslot = take(4 * (size_t)cap);
+  l.o_ranges = take(8 * (size_t)l.total_tiles);
+  l.o_tfin = take(4 * (size_t)l.total_pix);
+  l.o_nlast = take(4 * (size_t)l.total_pix);
+  l.o_gpair = take(4 * (size_t)cap * l.GS);
+  l.o_hist = take(4 * (size_t)kRadix * l.sort_blocks);
+  l.o_histtmp = take(4 * scan_tmp_words((int64_t)kRadix * l.sort_blocks));
+  l.total = o;
+  *L = l;
+  return ROGS_OK;
+}
+
+}  // namespace rogs
+
+namespace {
+
+int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws, hipStream_t st) {
+  const size_t vbytes = sizeof(ViewDev) * L.V;
+  const size_t fbytes = sizeof(int64_t) * (L.V + 1);
+  const size_t need = vbytes + fbytes;
+  if (c->stage_pending) {
+    hipError_t e = hipEventSynchronize(c->stage_evt);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    c->stage_pending = false;
+  }
+  if (c->stage_bytes < need) {
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    hipError_t e = hipHostMalloc(&c->stage, need, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+    c->stage_bytes = need;
+  }
+  ViewDev* vt = static_cast<ViewDev*>(c->stage);
+  int64_t* fb = reinterpret_cast<int64_t*>(static_cast<char*>(c->stage) + vbytes);
+  int64_t pix = 0, tiles = 0, blk = 0;
+  for (int v = 0; v < L.V; ++v) {
+    const rogs_camera& k = cams[v];
+    ViewDev d;
+    memset(&d, 0, sizeof(d));
+    d.pix_off = pix;
+    for (int j = 0; j < 9; ++j) d.R[j] = k.R_cw[j];
+    for (int j = 0; j < 3; ++j) d.t[j] = k.t_cw[j];
+    d.fx = k.fx; d.fy = k.fy; d.cx = k.cx; d.cy = k.cy;
+    d.znear = k.z_near;
+    d.o[0] = k.cull_o[0]; d.o[1] = k.cull_o[1];
+    d.ex[0] = k.cull_ex[0]; d.ex[1] = k.cull_ex[1];
+    d.ez[0] = k.cull_ez[0]; d.ez[1] = k.cull_ez[1];
+    d.lat = k.cull_lat; d.fwd = k.cull_fwd;
+    d.w = k.w; d.h = k.h; d.model = k.model;
+    d.tiles_x = (k.w + L.tw - 1) / L.tw;
+    d.tiles_y = (k.h + L.th - 1) / L.th;
+    d.tile_off = (int32_t)tiles;
+    vt[v] = d;
+    fb[v] = blk;
+    pix += (int64_t)k.w * k.h;
+    tiles += (int64_t)d.tiles_x * d.tiles_y;
+    blk += ((int64_t)k.w * k.h + 255) / 256;
+  }
+  fb[L.V] = blk;
+  hipError_t e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), vt, vbytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), fb, fbytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(c->stage_evt, st);
+  if (e != hipSuccess) return hip_fail(c, e, "view table upload");
+  c->stage_pending = true;
+  return ROGS_OK;
+}
+
+int need_batch(rogs_ctx* c, void* ws, bool sorted) {
+  if (!c) return ROGS_EINVAL;
+  if (!c->have_batch) return fail(c, ROGS_ESTATE, "no batch: call rogs_project first");
+  if (ws != c->ws) return fail(c, ROGS_EINVAL, "workspace differs from the one given to rogs_project");
+  if (sorted && !c->sorted) return fail(c, ROGS_ESTATE, "pairs not sorted: call rogs_bin_sort first");
+  return ROGS_OK;
+}
+
+int check_surfels(rogs_ctx* c, const rogs_surfels* s, const Layout& L) {
+  if (!s) return fail(c, ROGS_EINVAL, "surfels is null");
+  if (s->n != L.N || s->n_sem != L.C) return fail(c, ROGS_EINVAL, "surfels differ from the batch (n or n_sem)");
+  if (!s->x || !s->y || !s->z || !s->q || !s->s || !s->alpha || !s->rgb || !s->sem)
+    return fail(c, ROGS_EINVAL, "a surfel array pointer is null");
+  return ROGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rogs_create(rogs_ctx** ctx) {
+  if (!ctx) return ROGS_EINVAL;
+  *ctx = nullptr;
+  rogs_ctx* c = new (std::nothrow) rogs_ctx();
+  if (!c) return ROGS_ENOMEM;
+  hipError_t e = hipEventCreateWithFlags(&c->stage_evt, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->readback, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (c->stage_evt) (void)hipEventDestroy(c->stage_evt);
+    delete c;
+    return ROGS_EHIP;
+  }
+  *ctx = c;
+  return ROGS_OK;
+}
+
+void rogs_destroy(rogs_ctx* c) {
+  if (!c) return;
+  if (c->stage_pending) (void)hipEventSynchronize(c->stage_evt);
+  if (c->stage) (void)hipHostFree(c->stage);
+  if (c->readback) (void)hipHostFree(c->readback);
+  if (c->stage_evt) (void)hipEventDestroy(c->stage_evt);
+  delete c;
+}
+
+const char* rogs_last_error(const rogs_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void rogs_default_opts(rogs_render_opts* o) {
+  if (!o) return;
+  o->tile_w = 16;
+  o->tile_h = 16;
+  o->eps2d = 0.3f;
+  o->q_cut = 9.0f;
+  o->alpha_max = 0.99f;
+  o->t_eps = 1e-6f;
+}
+
+int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
+                        const rogs_render_opts* opts, int64_t pair_capacity, size_t* bytes) {
+  if (!bytes) return ROGS_EINVAL;
+  Layout L;
+  const char* why = nullptr;
+  int r = rogs::make_layout(s, cams, n_views, opts, pair_capacity, &L, &why);
+  if (r != ROGS_OK) return r;
+  *bytes = L.total;
+  return ROGS_OK;
+}
+
+int rogs_project(rogs_ctx* c, const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
+                 const rogs_render_opts* opts, void* ws, size_t ws_bytes, int64_t pair_capacity,
+                 void* stream) {
+  if (!c) return ROGS_EINVAL;
+  Layout L;
+  const char* why = nullptr;
+  int r = rogs::make_layout(s, cams, n_views, opts, pair_capacity, &L, &why);
+  if (r != ROGS_OK) return fail(c, r, why ? why : "invalid argument");
+  r = check_surfels(c, s, L);
+  if (r != ROGS_OK) return r;
+  if (!ws) return fail(c, ROGS_EINVAL, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, ROGS_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(c, ROGS_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  c->have_batch = false;
+  c->sorted = false;
+  r = upload_views(c, L, cams, ws, st);
+  if (r != ROGS_OK) return r;
+  rogs::launch_project(L, ws, s, true, st);
+  rogs::launch_scan_part(L, ws, st);
+  r = check_launch(c, "rogs_project");
+  if (r != ROGS_OK) return r;
+  c->L = L;
+  c->ws = ws;
+  c->have_batch = true;
+  c->n_pairs_host = -1;
+  return ROGS_OK;
+}
+
+int rogs_pair_count(rogs_ctx* c, void* ws, int64_t* n_pairs, int32_t* overflow, void* stream) {
+  int r = need_batch(c, ws, false);
+  if (r != ROGS_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(c->readback, rogs::at<void>(ws, c->L.o_misc), 8,
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "rogs_pair_count");
+  if (n_pairs) *n_pairs = (int64_t)c->readback[rogs::kMiscPairs];
+  if (overflow) *overflow = (int32_t)c->readback[rogs::kMiscOverflow];
+  return ROGS_OK;
+}
+
+int rogs_bin_sort(rogs_ctx* c, void* ws, int64_t* n_pairs_out, uint32_t flags, void* stream) {
+  int r = need_batch(c, ws, false);
+  if (r != ROGS_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int64_t n_host = -1;
+  if (flags & ROGS_SYNC_COUNT) {
+    int32_t ovf = 0;
+    r = rogs_pair_count(c, ws, &n_host, &ovf, stream);
+    if (r != ROGS_OK) return r;
+    if (n_pairs_out) *n_pairs_out = n_host;
+    if (n_host > c->L.cap)
+      return fail(c, ROGS_ECAPACITY, "pair capacity " + std::to_string(c->L.cap) +
+                                         " too small for " + std::to_string(n_host) + " pairs");
+  } else if (n_pairs_out) {
+    *n_pairs_out = -1;
+  }
+  Layout& L = c->L;
+  rogs::launch_emit(L, ws, st);
+  int alt = rogs::launch_sort(L, ws, n_host, st);
+  if (alt) {
+    std::swap(L.o_keys, L.o_keys2);
+    std::swap(L.o_vals, L.o_vals2);
+  }
+  rogs::launch_ranges(L, ws, n_host, st);
+  r = check_launch(c, "rogs_bin_sort");
+  if (r != ROGS_OK) return r;
+  c->sorted = true;
+  c->n_pairs_host = n_host;
+  return ROGS_OK;
+}
+
+int rogs_render_fwd(rogs_ctx* c, const rogs_surfels* s, void* ws, float* out_images, void* stream) {
+  int r = need_batch(c, ws, true);
+  if (r != ROGS_OK) return r;
+  r = check_surfels(c, s, c->L);
+  if (r != ROGS_OK) return r;
+  if (!out_images) return fail(c, ROGS_EINVAL, "out_images is null");
+  if (rogs::launch_render_fwd(c->L, ws, s, out_images, static_cast<hipStream_t>(stream)) != 0)
+    return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
+  return check_launch(c, "rogs_render_fwd");
+}
+
+int rogs_loss(rogs_ctx* c, void* ws, const float* out_images, const rogs_targets* t,
+              float* dL_dout, float* loss_out, float* d_exposure, void* stream) {
+  int r = need_batch(c, ws, true);
+  if (r != ROGS_OK) return r;
+  if (!out_images || !t || !dL_dout) return fail(c, ROGS_EINVAL, "null argument");
+  if (!t->rgb || !t->label || !t->mask || !t->exposure)
+    return fail(c, ROGS_EINVAL, "a target array pointer is null");
+  if (!is_fin(t->lambda_c) || !is_fin(t->lambda_s) || !is_fin(t->view_scale))
+    return fail(c, ROGS_EINVAL, "loss weights must be finite");
+  rogs::launch_loss(c->L, ws, out_images, t, dL_dout, loss_out, d_exposure,
+                    static_cast<hipStream_t>(stream));
+  return check_launch(c, "rogs_loss");
+}
+
+int rogs_render_bwd(rogs_ctx* c, const rogs_surfels* s, void* ws, const float* out_images,
+                    const float* dL_dout, float* grads, uint32_t flags, void* stream) {
+  int r = need_batch(c, ws, true);
+  if (r != ROGS_OK) return r;
+  r = check_surfels(c, s, c->L);
+  if (r != ROGS_OK) return r;
+  if (!out_images || !dL_dout || !grads) return fail(c, ROGS_EINVAL, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (rogs::launch_render_bwd(c->L, ws, s, out_images, dL_dout, st) != 0)
+    return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
+  rogs::launch_proj_bwd(c->L, ws, s, grads, (flags & ROGS_ACCUMULATE) != 0, st);
+  return check_launch(c, "rogs_render_bwd");
+}
+
+int rogs_adam_step(rogs_ctx* c, int32_t n, int32_t n_sem, float* params, const float* grads,
+                   float* m, float* v, float* s_act, float* alpha_act, const rogs_lr* lr,
+                   int64_t step, float beta1, float beta2, float eps, float* exposure,
+                   const float* d_exposure, float* m_exp, float* v_exp, int32_t n_views,
+                   void* stream) {
+  if (!c) return ROGS_EINVAL;
+  if (n < 1) return fail(c, ROGS_EINVAL, "n must be >= 1");
+  if (n_sem < 1 || n_sem > 64) return fail(c, ROGS_EINVAL, "n_sem out of range");
+  if (!params || !grads || !m || !v || !s_act || !alpha_act || !lr)
+    return fail(c, ROGS_EINVAL, "null argument");
+  if (step < 1) return fail(c, ROGS_EINVAL, "step must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(c, ROGS_EINVAL, "Adam hyper-parameters out of range");
+  if (exposure && (!d_exposure || !m_exp || !v_exp || n_views < 1))
+    return fail(c, ROGS_EINVAL, "exposure group needs gradients, moments and n_views >= 1");
+  rogs::launch_adam(n, n_sem, params, grads, m, v, s_act, alpha_act, lr, step, beta1, beta2, eps,
+                    exposure, d_exposure, m_exp, v_exp, n_views, static_cast<hipStream_t>(stream));
+  return check_launch(c, "rogs_adam_step");
+}
+
+int rogs_debug_pairs(rogs_ctx* c, void* ws, uint64_t* keys, int32_t* surfel_ids, int32_t* views,
+                     int64_t cap, uint32_t* ranges, int64_t n_tiles, void* stream) {
+  int r = need_batch(c, ws, true);
+  if (r != ROGS_OK) return r;
+  const Layout& L = c->L;
+  int64_t P = 0;
+  int32_t ovf = 0;
+  r = rogs_pair_count(c, ws, &P, &ovf, stream);
+  if (r != ROGS_OK) return r;
+  if (P > L.cap) P = L.cap;
+  if (cap < P || !keys || !surfel_ids || !views) return fail(c, ROGS_EINVAL, "output capacity too small");
+  if (ranges && n_tiles < L.total_tiles) return fail(c, ROGS_EINVAL, "ranges capacity too small");
+  std::vector<uint32_t> vals(P), pslot(P);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (P > 0) {
+    e = hipMemcpyAsync(keys, rogs::at<void>(ws, L.o_keys), 8 * P, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(vals.data(), rogs::at<void>(ws, L.o_vals), 4 * P, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pslot.data(), rogs::at<void>(ws, L.o_pslot), 4 * P, hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess && ranges)
+    e = hipMemcpyAsync(ranges, rogs::at<void>(ws, L.o_ranges), 8 * L.total_tiles,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "rogs_debug_pairs");
+  for (int64_t k = 0; k < P; ++k) {
+    const uint32_t sl = pslot[vals[k]];
+    surfel_ids[k] = (int32_t)(sl % (uint32_t)L.N);
+    views[k] = (int32_t)(sl / (uint32_t)L.N);
+  }
+  return ROGS_OK;
+}
+
+int rogs_debug_records(rogs_ctx* c, void* ws, float* rec, int32_t* rect, uint32_t* count,
+                       void* stream) {
+  int r = need_batch(c, ws, false);
+  if (r != ROGS_OK) return r;
+  if (!rec || !rect || !count) return fail(c, ROGS_EINVAL, "null argument");
+  const Layout& L = c->L;
+  const size_t S = (size_t)L.slots;
+  std::vector<uint32_t> rc(2 * S);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(rec, rogs::at<void>(ws, L.o_rec), 32 * S, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rc.data(), rogs::at<void>(ws, L.o_rect), 8 * S, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(count, rogs::at<void>(ws, L.o_cnt), 4 * S, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "rogs_debug_records");
+  for (size_t k = 0; k < S; ++k) {
+    if (count[k] == 0) {
+      for (int j = 0; j < 8; ++j) rec[8 * k + j] = 0.0f;
+      for (int j = 0; j < 4; ++j) rect[4 * k + j] = 0;
+      continue;
+    }
+    rect[4 * k + 0] = (int32_t)(rc[2 * k] & 0xffff);
+    rect[4 * k + 1] = (int32_t)(rc[2 * k] >> 16);
+    rect[4 * k + 2] = (int32_t)(rc[2 * k + 1] & 0xffff);
+    rect[4 * k + 3] = (int32_t)(rc[2 * k + 1] >> 16);
+  }
+  return ROGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+// Per-(view, surfel) culling and EWA projection (Eq. 5, supp. Sec. 2.1), tile
+// counts, their scan, and the emission of (tile, depth) sort keys.
+//
+// One thread owns one surfel and walks all views of the batch, so the surfel's
+// parameters are read from HBM once per batch; per-view results land in
+// "slot" arrays indexed v * N + i.
+#include "rogs_internal.h"
+
+namespace rogs {
+
+namespace {
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Block-wide exclusive scan of one value per thread (kProjBlock threads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(x, lane);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kProjBlock / 64; ++w) {
+    uint32_t t = s_w[w];
+    pre += (w < wv) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - x;
+}
+
+__global__ __launch_bounds__(kProjBlock) void k_project(
+    const ViewDev* __restrict__ views, int V, int N, int nb, float eps, float qcut, int tw, int th,
+    const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
+    const float* __restrict__ pq, const float* __restrict__ ps, const float* __restrict__ pa,
+    const float* __restrict__ prgb, const float* __restrict__ psem, int C, int FS, int pack,
+    uint32_t* __restrict__ cnt, float4* __restrict__ rec, uint2* __restrict__ rect,
+    uint32_t* __restrict__ part, float* __restrict__ feat) {
+  __shared__ uint32_t s_w[kProjBlock / 64];
+  const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  const bool valid = i < N;
+  float x = 0, y = 0, z = 0, qw = 1, qx = 0, qy = 0, qz = 0, sx = 1, sy = 1, al = 0;
+  if (valid) {
+    x = px[i]; y = py[i]; z = pz[i];
+    qw = pq[i]; qx = pq[N + i]; qy = pq[2 * (size_t)N + i]; qz = pq[3 * (size_t)N + i];
+    sx = ps[i]; sy = ps[N + i];
+    al = pa[i];
+    if (pack) {
+      float* f = feat + (size_t)i * FS;
+      f[0] = prgb[i];
+      f[1] = prgb[N + i];
+      f[2] = prgb[2 * (size_t)N + i];
+      for (int c = 0; c < C; ++c) f[3 + c] = psem[(size_t)c * N + i];
+      for (int c = 3 + C; c < FS; ++c) f[c] = 0.0f;
+    }
+  }
+  for (int v = 0; v < V; ++v) {
+    const ViewDev& vw = views[v];
+    uint32_t nt = 0;
+    if (valid) {
+      Proj p = project_contract(vw, eps, qcut, tw, th, x, y, z, qw, qx, qy, qz, sx, sy);
+      const size_t slot = (size_t)v * N + i;
+      if (p.vis) {
+        nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
+        rec[2 * slot] = make_float4(p.u, p.v, p.A, p.B);
+        rec[2 * slot + 1] = make_float4(p.C, p.tz, al, 0.0f);
+        rect[slot] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.x1 << 16),
+                                (uint32_t)p.y0 | ((uint32_t)p.y1 << 16));
+      }
+      cnt[slot] = nt;
+    }
+    uint32_t ws = wave_sum_u32(nt);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = ws;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int w = 0; w < kProjBlock / 64; ++w) t += s_w[w];
+      part[(size_t)v * nb + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_check_cap(uint32_t* misc, int64_t cap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    misc[kMiscOverflow] = ((int64_t)misc[kMiscPairs] > cap) ? 1u : 0u;
+}
+
+// Emission: pair e of surfel slot (v, i) covers tile (x0 + k % wx, y0 + k / wx);
+// pairs of one slot are consecutive and slots are in (view, surfel id) order,
+// which the stable sort turns into the id tie-break.
+__global__ __launch_bounds__(kProjBlock) void k_emit(
+    const ViewDev* __restrict__ views, int V, int N, int nb, const uint32_t* __restrict__ cnt,
+    const float4* __restrict__ rec, const uint2* __restrict__ rect,
+    const uint32_t* __restrict__ part_scan, int64_t cap, unsigned long long* __restrict__ keys,
+    uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ off) {
+  __shared__ uint32_t s_w[kProjBlock / 64];
+  const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  const bool valid = i < N;
+  for (int v = 0; v < V; ++v) {
+    const size_t slot = (size_t)v * N + i;
+    uint32_t nt = valid ? cnt[slot] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(nt, s_w, &tot);
+    uint32_t base = part_scan[(size_t)v * nb + blockIdx.x] + ex;
+    if (valid) off[slot] = base;
+    if (nt) {
+      const ViewDev& vw = views[v];
+      uint2 r = rect[slot];
+      int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
+      uint32_t db = __float_as_uint(rec[2 * slot + 1].y);
+      uint32_t e = base;
+      for (int ty = y0; ty < y1; ++ty) {
+        for (int tx = x0; tx < x1; ++tx, ++e) {
+          if ((int64_t)e < cap) {
+            uint32_t gt = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
+            keys[e] = ((unsigned long long)gt << 32) | db;
+            vals[e] = e;
+            pslot[e] = (uint32_t)slot;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ generic scan
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                     uint32_t* __restrict__ sums) {
+  __shared__ uint32_t s_w[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t acc = 0;
+  for (int k = threadIdx.x; k < kScanChunk; k += 256) {
+    int64_t j = base + k;
+    if (j < n) acc += in[j];
+  }
+  acc = wave_sum_u32(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// Exclusive scan in place of m values with one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, int64_t m,
+                                                   uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_w[16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t per = (m + 1023) / 1024;
+  const int64_t b = t * per, e = (b + per < m) ? b + per : m;
+  uint32_t loc = 0;
+  for (int64_t j = b; j < e; ++j) loc += sums[j];
+  uint32_t inc = wave_incl_scan(loc, lane);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    pre += (w < wv) ? s_w[w] : 0u;
+    tot += s_w[w];
+  }
+  uint32_t run = pre + inc - loc;
+  for (int64_t j = b; j < e; ++j) {
+    uint32_t x = sums[j];
+    sums[j] = run;
+    run += x;
+  }
+  if (t == 0 && total) *total = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in,
+                                                   uint32_t* __restrict__ out, int64_t n,
+                                                   const uint32_t* __restrict__ sums) {
+  __shared__ uint32_t s_v[kScanChunk];
+  __shared__ uint32_t s_w[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  for (int k = threadIdx.x; k < kScanChunk; k += 256) {
+    int64_t j = base + k;
+    s_v[k] = (j < n) ? in[j] : 0u;
+  }
+  __syncthreads();
+  constexpr int per = kScanChunk / 256;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  uint32_t loc = 0;
+  for (int k = 0; k < per; ++k) loc += s_v[t * per + k];
+  uint32_t inc = wave_incl_scan(loc, lane);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = sums[blockIdx.x];
+  for (int w = 0; w < 4; ++w) pre += (w < wv) ? s_w[w] : 0u;
+  uint32_t run = pre + inc - loc;
+  for (int k = 0; k < per; ++k) {
+    uint32_t x = s_v[t * per + k];
+    s_v[t * per + k] = run;
+    run += x;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kScanChunk; k += 256) {
+    int64_t j = base + k;
+    if (j < n) out[j] = s_v[k];
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = value;
+}
+
+}  // namespace
+
+size_t scan_tmp_words(int64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1; }
+
+void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
+              hipStream_t st) {
+  if (n <= 0) return;
+  int64_t m = (n + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)m), dim3(256), 0, st, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, m, total);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)m), dim3(256), 0, st, in, out, n, tmp);
+}
+
+void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, value, n);
+}
+
+void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_project, dim3(L.nb), dim3(kProjBlock), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
+                     L.th, s->x, s->y, s->z, s->q, s->s, s->alpha, s->rgb, s->sem, L.C, L.FS,
+                     pack_feat ? 1 : 0, at<uint32_t>(ws, L.o_cnt), at<float4>(ws, L.o_rec),
+                     at<uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_part), at<float>(ws, L.o_feat));
+}
+
+void launch_scan_part(const Layout& L, void* ws, hipStream_t st) {
+  uint32_t* misc = at<uint32_t>(ws, L.o_misc);
+  scan_u32(at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_part), (int64_t)L.V * L.nb,
+           misc + kMiscPairs, at<uint32_t>(ws, L.o_parttmp), st);
+  hipLaunchKernelGGL(k_check_cap, dim3(1), dim3(64), 0, st, misc, L.cap);
+}
+
+void launch_emit(const Layout& L, void* ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_emit, dim3(L.nb), dim3(kProjBlock), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb,
+                     at<const uint32_t>(ws, L.o_cnt), at<const float4>(ws, L.o_rec),
+                     at<const uint2>(ws, L.o_rect), at<const uint32_t>(ws, L.o_part), L.cap,
+                     at<unsigned long long>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
+                     at<uint32_t>(ws, L.o_pslot), at<uint32_t>(ws, L.o_off));
+}
+
+}  // namespace rogs

@@ -1,0 +1,343 @@
+// Front-to-back alpha compositing of the sorted tile lists (Eq. 6) and its
+// adjoint.
+//
+// Mapping: one 64-lane wave per tile; a tile of tile_w x tile_h = 64 * PPL
+// pixels gives every lane PPL pixels of one column, so the per-pair x
+// offset is shared and each broadcast record read from LDS feeds PPL pixels.
+// The wave stages 64 list entries at a time in LDS (projection record + the
+// surfel's colour/semantic features), then every lane walks them in order.
+// A pixel stops after the surfel that takes its transmittance below t_eps;
+// the wave leaves the list once all of its pixels have stopped.
+//
+// The backward walks the list front to back again, recomputing T exactly as
+// the forward did, and uses sum_{j>k} w_j f_j = O - prefix - w_k f_k for the
+// suffix term of dO/d(alpha_k).  Per (tile, pair) the 10 + C gradient values
+// are summed over the lane's pixels and then over the wave, and written as
+// one record at the pair's emission index; the projection adjoint later sums
+// each surfel's records.  No atomics: the result does not depend on timing.
+#include "rogs_internal.h"
+
+namespace rogs {
+
+namespace {
+
+__device__ __forceinline__ int find_view(const ViewDev* __restrict__ views, int V, int gt) {
+  int lo = 0, hi = V - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_off <= gt) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <int C, int PPL>
+__global__ __launch_bounds__(64) void k_render_fwd(
+    const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
+    float teps, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
+    const float4* __restrict__ feat, float* __restrict__ out, float* __restrict__ tfin,
+    uint32_t* __restrict__ nlast) {
+  constexpr int F = 3 + C;            // composited features besides depth
+  constexpr int FS4 = (F + 3) / 4;    // float4 per feature record
+  constexpr int NO = 5 + C;           // output channels
+  __shared__ float4 s_r0[64], s_r1[64];
+  __shared__ float4 s_f[64 * FS4];
+  const int lane = threadIdx.x;
+  const int gt = blockIdx.x;
+  const int v = find_view(views, V, gt);
+  const ViewDev& vw = views[v];
+  const int W = vw.w, H = vw.h;
+  const int lt = gt - vw.tile_off;
+  const int ty = lt / vw.tiles_x, tx = lt - ty * vw.tiles_x;
+  const int rows = 64 / tw;
+  const int px = tx * tw + (lane % tw);
+  const int py0 = ty * th + lane / tw;
+  const float pxc = (float)px + 0.5f;
+
+  float T[PPL], acc[PPL][F + 1], pyc[PPL];
+  bool done[PPL];
+  uint32_t nl[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int py = py0 + k * rows;
+    done[k] = !(px < W && py < H);
+    T[k] = 1.0f;
+    nl[k] = 0;
+    pyc[k] = (float)py + 0.5f;
+#pragma unroll
+    for (int f = 0; f <= F; ++f) acc[k][f] = 0.0f;
+  }
+  const uint2 rg = ranges[gt];
+  const uint32_t len = rg.y - rg.x;
+  const uint32_t sbase = (uint32_t)v * (uint32_t)N;
+  bool stop_all = false;
+  for (uint32_t base = rg.x; base < rg.y && !stop_all; base += 64) {
+    const int cnt = (int)min(64u, rg.y - base);
+    if (lane < cnt) {
+      const uint32_t e = vals[base + lane];
+      const uint32_t slot = pslot[e];
+      s_r0[lane] = rec[2 * (size_t)slot];
+      s_r1[lane] = rec[2 * (size_t)slot + 1];
+      const uint32_t i = slot - sbase;
+#pragma unroll
+      for (int f = 0; f < FS4; ++f) s_f[lane * FS4 + f] = feat[(size_t)i * FS4 + f];
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const float4 r0 = s_r0[j], r1 = s_r1[j];   // u v A B | C tz alpha -
+      float fv[FS4 * 4];
+#pragma unroll
+      for (int f = 0; f < FS4; ++f) {
+        const float4 t4 = s_f[j * FS4 + f];
+        fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
+      }
+      const float dx = pxc - r0.x;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (done[k]) continue;
+        const float dy = pyc[k] - r0.y;
+        const float q = pixel_q32(r0.z, r0.w, r1.x, dx, dy);
+        if (q <= qcut) {
+          const float g = __expf(-0.5f * q);
+          const float a = fminf(r1.z * g, amax);
+          const float w = a * T[k];
+#pragma unroll
+          for (int f = 0; f < F; ++f) acc[k][f] += w * fv[f];
+          acc[k][F] += w * r1.y;
+          T[k] *= (1.0f - a);
+          if (T[k] < teps) {
+            done[k] = true;
+            nl[k] = base - rg.x + (uint32_t)j + 1u;
+          }
+        }
+      }
+      bool mine = true;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) mine = mine && done[k];
+      if (__all(mine)) { stop_all = true; break; }
+    }
+    __syncthreads();
+  }
+  const size_t HW = (size_t)W * H;
+  float* o = out + (size_t)NO * vw.pix_off;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int py = py0 + k * rows;
+    if (!(px < W && py < H)) continue;
+    const size_t p = (size_t)py * W + px;
+#pragma unroll
+    for (int f = 0; f <= F; ++f) o[f * HW + p] = acc[k][f];
+    o[(F + 1) * HW + p] = 1.0f - T[k];
+    tfin[vw.pix_off + p] = T[k];
+    nlast[vw.pix_off + p] = (T[k] < teps) ? nl[k] : len;
+  }
+}
+
+template <int C, int PPL>
+__global__ __launch_bounds__(64) void k_render_bwd(
+    const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
+    const float4* __restrict__ feat, const float* __restrict__ out, const float* __restrict__ G,
+    const float* __restrict__ tfin, const uint32_t* __restrict__ nlast, float* __restrict__ gpair,
+    int GS) {
+  constexpr int F = 3 + C;
+  constexpr int FS4 = (F + 3) / 4;
+  constexpr int NO = 5 + C;
+  constexpr int NV = 10 + C;          // du dv dA dB dC dalpha dtz drgb[3] dsem[C]
+  __shared__ float4 s_r0[64], s_r1[64];
+  __shared__ float4 s_f[64 * FS4];
+  __shared__ uint32_t s_e[64];
+  const int lane = threadIdx.x;
+  const int gt = blockIdx.x;
+  const int v = find_view(views, V, gt);
+  const ViewDev& vw = views[v];
+  const int W = vw.w, H = vw.h;
+  const int lt = gt - vw.tile_off;
+  const int ty = lt / vw.tiles_x, tx = lt - ty * vw.tiles_x;
+  const int rows = 64 / tw;
+  const int px = tx * tw + (lane % tw);
+  const int py0 = ty * th + lane / tw;
+  const float pxc = (float)px + 0.5f;
+  const size_t HW = (size_t)W * H;
+
+  float Gv[PPL][F + 2], GO[PPL], Tf[PPL], T[PPL], Spre[PPL], pyc[PPL];
+  uint32_t nl[PPL];
+  uint32_t maxn = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int py = py0 + k * rows;
+    pyc[k] = (float)py + 0.5f;
+    T[k] = 1.0f;
+    Spre[k] = 0.0f;
+    GO[k] = 0.0f;
+    Tf[k] = 1.0f;
+    nl[k] = 0;
+#pragma unroll
+    for (int f = 0; f < F + 2; ++f) Gv[k][f] = 0.0f;
+    if (px < W && py < H) {
+      const size_t p = (size_t)py * W + px;
+      const float* g = G + (size_t)NO * vw.pix_off + p;
+      const float* o = out + (size_t)NO * vw.pix_off + p;
+      float go = 0.0f;
+#pragma unroll
+      for (int f = 0; f < F + 2; ++f) Gv[k][f] = g[f * HW];
+#pragma unroll
+      for (int f = 0; f <= F; ++f) go += Gv[k][f] * o[f * HW];
+      GO[k] = go;
+      Tf[k] = tfin[vw.pix_off + p];
+      nl[k] = nlast[vw.pix_off + p];
+      maxn = max(maxn, nl[k]);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, (uint32_t)__shfl_xor((int)maxn, o, 64));
+  const uint2 rg = ranges[gt];
+  const uint32_t stop = rg.x + min(maxn, rg.y - rg.x);
+  const uint32_t sbase = (uint32_t)v * (uint32_t)N;
+  for (uint32_t base = rg.x; base < stop; base += 64) {
+    const int cnt = (int)min(64u, stop - base);
+    if (lane < cnt) {
+      const uint32_t e = vals[base + lane];
+      const uint32_t slot = pslot[e];
+      s_e[lane] = e;
+      s_r0[lane] = rec[2 * (size_t)slot];
+      s_r1[lane] = rec[2 * (size_t)slot + 1];
+      const uint32_t i = slot - sbase;
+#pragma unroll
+      for (int f = 0; f < FS4; ++f) s_f[lane * FS4 + f] = feat[(size_t)i * FS4 + f];
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const uint32_t idx = base - rg.x + (uint32_t)j;
+      const float4 r0 = s_r0[j], r1 = s_r1[j];
+      const float A = r0.z, B = r0.w, Cc = r1.x, tz = r1.y, al = r1.z;
+      float fv[FS4 * 4];
+#pragma unroll
+      for (int f = 0; f < FS4; ++f) {
+        const float4 t4 = s_f[j * FS4 + f];
+        fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
+      }
+      float pv[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) pv[c] = 0.0f;
+      bool touched = false;
+      const float dx = pxc - r0.x;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (idx >= nl[k]) continue;
+        const float dy = pyc[k] - r0.y;
+        const float q = pixel_q32(A, B, Cc, dx, dy);
+        if (!(q <= qcut)) continue;
+        touched = true;
+        const float g = __expf(-0.5f * q);
+        const float araw = al * g;
+        const bool clamped = araw > amax;
+        const float a = clamped ? amax : araw;
+        const float w = a * T[k];
+        float gf = Gv[k][F] * tz;
+#pragma unroll
+        for (int f = 0; f < F; ++f) gf += Gv[k][f] * fv[f];
+#pragma unroll
+        for (int f = 0; f < F; ++f) pv[7 + f] += w * Gv[k][f];
+        pv[6] += w * Gv[k][F];
+        const float inv = 1.0f / (1.0f - a);
+        const float suffix = (GO[k] - Spre[k]) - w * gf;
+        const float da = T[k] * gf - suffix * inv + Gv[k][F + 1] * Tf[k] * inv;
+        Spre[k] += w * gf;
+        if (!clamped) {
+          pv[5] += g * da;
+          const float dq = -0.5f * g * al * da;
+          pv[2] += dx * dx * dq;
+          pv[3] += 2.0f * dx * dy * dq;
+          pv[4] += dy * dy * dq;
+          pv[0] += -(2.0f * A * dx + 2.0f * B * dy) * dq;
+          pv[1] += -(2.0f * Cc * dy + 2.0f * B * dx) * dq;
+        }
+        T[k] *= (1.0f - a);
+      }
+      const uint32_t e = s_e[j];
+      float mine = 0.0f;
+      if (__any(touched)) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          const float s = wave_sum(pv[c]);
+          mine = (lane == c) ? s : mine;
+        }
+      }
+      if (lane < NV) gpair[(size_t)e * GS + lane] = mine;
+    }
+    __syncthreads();
+  }
+  // pairs that no pixel of the tile reached contribute nothing
+  for (uint32_t p = stop + lane; p < rg.y; p += 64) {
+    const uint32_t e = vals[p];
+    for (int c = 0; c < NV; ++c) gpair[(size_t)e * GS + c] = 0.0f;
+  }
+}
+
+template <int C, int PPL>
+void fwd_launch(const Layout& L, void* ws, float* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_render_fwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
+                     L.t_eps, at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
+                     at<const float4>(ws, L.o_feat), out, at<float>(ws, L.o_tfin),
+                     at<uint32_t>(ws, L.o_nlast));
+}
+
+template <int C, int PPL>
+void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hipStream_t st) {
+  hipLaunchKernelGGL((k_render_bwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
+                     at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
+                     at<const float4>(ws, L.o_feat), out, G, at<const float>(ws, L.o_tfin),
+                     at<const uint32_t>(ws, L.o_nlast), at<float>(ws, L.o_gpair), L.GS);
+}
+
+template <int C>
+int dispatch_ppl(const Layout& L, void* ws, const float* out, const float* G, float* outw,
+                 bool bwd, hipStream_t st) {
+  switch (L.ppl) {
+    case 1: bwd ? bwd_launch<C, 1>(L, ws, out, G, st) : fwd_launch<C, 1>(L, ws, outw, st); return 0;
+    case 2: bwd ? bwd_launch<C, 2>(L, ws, out, G, st) : fwd_launch<C, 2>(L, ws, outw, st); return 0;
+    case 4: bwd ? bwd_launch<C, 4>(L, ws, out, G, st) : fwd_launch<C, 4>(L, ws, outw, st); return 0;
+    default: return -1;
+  }
+}
+
+int dispatch(const Layout& L, void* ws, const float* out, const float* G, float* outw, bool bwd,
+             hipStream_t st) {
+  switch (L.C) {
+    case 1: return dispatch_ppl<1>(L, ws, out, G, outw, bwd, st);
+    case 2: return dispatch_ppl<2>(L, ws, out, G, outw, bwd, st);
+    case 3: return dispatch_ppl<3>(L, ws, out, G, outw, bwd, st);
+    case 4: return dispatch_ppl<4>(L, ws, out, G, outw, bwd, st);
+    case 5: return dispatch_ppl<5>(L, ws, out, G, outw, bwd, st);
+    case 6: return dispatch_ppl<6>(L, ws, out, G, outw, bwd, st);
+    case 7: return dispatch_ppl<7>(L, ws, out, G, outw, bwd, st);
+    case 8: return dispatch_ppl<8>(L, ws, out, G, outw, bwd, st);
+    case 16: return dispatch_ppl<16>(L, ws, out, G, outw, bwd, st);
+    default: return -1;
+  }
+}
+
+}  // namespace
+
+int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels*, float* out, hipStream_t st) {
+  if (L.total_tiles <= 0) return 0;
+  return dispatch(L, ws, nullptr, nullptr, out, false, st);
+}
+
+int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels*, const float* out,
+                      const float* G, hipStream_t st) {
+  if (L.total_tiles <= 0) return 0;
+  return dispatch(L, ws, out, G, nullptr, true, st);
+}
+
+}  // namespace rogs

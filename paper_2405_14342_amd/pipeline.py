@@ -1,0 +1,192 @@
+"""Device-resident training state and the per-step call sequences.
+
+PyTorch provides device memory and the stream; every step of the path runs in
+librogs through :mod:`binding`.  Two sequences are provided:
+
+* :meth:`TrainState.step_plain` - one launch sequence per view (project,
+  bin/sort with a host read-back of the pair count, forward, loss, backward),
+  then one Adam step: the plain per-view path.
+* :meth:`TrainState.step_batched` - all views of the step in one batch, the
+  pair count kept on the device.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+# Sec. 4.2 hyper-parameters
+LAMBDA_C, LAMBDA_S = 1.0, 0.06
+LR_ALPHA = LR_SCALE = LR_ROT = 1e-4
+LR_RGB, LR_SEM, LR_EXPOSURE = 0.008, 0.1, 0.001
+LR_Z_START, LR_Z_END = 1.6e-4, 1.6e-6      # times the scene size
+
+
+def z_learning_rate(extent: float, step: int, total_steps: int) -> float:
+    """z learning rate: proportional to the scene size, decaying log-linearly
+    from 1.6e-4 to 1.6e-6 of it over the run (Sec. 4.2)."""
+    t = 0.0 if total_steps <= 1 else min(max((step - 1) / (total_steps - 1), 0.0), 1.0)
+    return extent * math.exp(math.log(LR_Z_START) * (1.0 - t) + math.log(LR_Z_END) * t)
+
+
+def paper_lr(extent: float, step: int = 1, total_steps: int = 1) -> B.LR:
+    return B.LR(z_learning_rate(extent, step, total_steps), LR_ROT, LR_SCALE, LR_ALPHA, LR_RGB,
+                LR_SEM, LR_EXPOSURE)
+
+
+def n_out(C: int) -> int:
+    return 5 + C
+
+
+class TrainState:
+    """Surfel parameters, Adam moments, targets and output buffers on the GPU."""
+
+    def __init__(self, scene, device="cuda", opts: Optional[B.RenderOpts] = None,
+                 pair_capacity: Optional[int] = None):
+        self.scene = scene
+        self.dev = torch.device(device)
+        N, C = scene.n, scene.n_sem
+        self.N, self.C, self.K = N, C, 11 + C
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=self.dev)
+        P = torch.empty((self.K, N), dtype=torch.float32, device=self.dev)
+        P[0] = f(scene.z)
+        P[1:5] = f(scene.q)
+        P[5:7] = f(scene.log_s)
+        P[7] = f(scene.logit_a)
+        P[8:11] = f(scene.rgb)
+        P[11:] = f(scene.sem)
+        self.params = P
+        self.s_act = f(scene.s).clone()
+        self.alpha_act = f(scene.alpha).clone()
+        self.x = f(scene.x)
+        self.y = f(scene.y)
+        self.m = torch.zeros_like(P)
+        self.v = torch.zeros_like(P)
+        self.grads = torch.zeros_like(P)
+        self.cams = list(scene.cams)
+        V = len(self.cams)
+        self.V = V
+        self.npix = [c.w * c.h for c in self.cams]
+        self.pix_off = np.concatenate([[0], np.cumsum(self.npix)]).astype(np.int64)
+        self.total_pix = int(self.pix_off[-1])
+        self.exposure = torch.zeros((V, 2), dtype=torch.float32, device=self.dev)
+        self.d_exp = torch.zeros_like(self.exposure)
+        self.m_exp = torch.zeros_like(self.exposure)
+        self.v_exp = torch.zeros_like(self.exposure)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
+        NO = n_out(C)
+        self.out = torch.zeros(NO * self.total_pix, dtype=torch.float32, device=self.dev)
+        self.G = torch.zeros_like(self.out)
+        if scene.targets:
+            self.tgt_rgb = torch.cat([f(t.rgb).reshape(-1) for t in scene.targets])
+            self.tgt_label = torch.cat([torch.as_tensor(t.label.reshape(-1), device=self.dev)
+                                        for t in scene.targets])
+            self.tgt_mask = torch.cat([torch.as_tensor(t.mask.reshape(-1), device=self.dev)
+                                       for t in scene.targets])
+        else:
+            self.tgt_rgb = self.tgt_label = self.tgt_mask = None
+        self.opts = opts or B.make_opts()
+        self.rg = B.Rogs()
+        self.cap_view = pair_capacity or 1 << 20
+        self.cap_batch = pair_capacity or 1 << 22
+        self._ws_view = None
+        self._ws_batch = None
+        self.step_count = 0
+
+    # -------------------------------------------------------------- views
+    def surfels(self) -> B.Surfels:
+        P = self.params
+        return B.Surfels(self.N, self.C, self.x.data_ptr(), self.y.data_ptr(), P[0].data_ptr(),
+                         P[1].data_ptr(), self.s_act.data_ptr(), self.alpha_act.data_ptr(),
+                         P[8].data_ptr(), P[11].data_ptr())
+
+    def out_view(self, v: int, buf=None) -> torch.Tensor:
+        buf = self.out if buf is None else buf
+        NO = n_out(self.C)
+        return buf[NO * int(self.pix_off[v]): NO * int(self.pix_off[v + 1])]
+
+    def image(self, v: int, buf=None) -> torch.Tensor:
+        """[5 + C, H, W] view of the rendered (or gradient) image of view v."""
+        c = self.cams[v]
+        return self.out_view(v, buf).view(n_out(self.C), c.h, c.w)
+
+    def targets(self, v0: int, v1: int) -> B.Targets:
+        o = int(self.pix_off[v0])
+        return B.Targets(self.tgt_rgb.data_ptr() + 4 * 3 * o, self.tgt_label.data_ptr() + o,
+                         self.tgt_mask.data_ptr() + o, self.exposure.data_ptr() + 8 * v0,
+                         LAMBDA_C, LAMBDA_S, 1.0 / self.V)
+
+    # ---------------------------------------------------------- workspace
+    def _workspace(self, cams, cap, which):
+        size = B.workspace_size(self.surfels(), cams, self.opts, cap)
+        cur = getattr(self, which)
+        if cur is None or cur.numel() < size:
+            cur = torch.empty(size, dtype=torch.uint8, device=self.dev)
+            setattr(self, which, cur)
+        return cur
+
+    def project_and_sort(self, cams, cap_attr: str, ws_attr: str, sync: bool = True):
+        """rogs_project + rogs_bin_sort, growing the pair capacity if needed."""
+        while True:
+            cap = getattr(self, cap_attr)
+            ws = self._workspace(cams, cap, ws_attr)
+            self.rg.project(self.surfels(), cams, self.opts, ws, cap)
+            if not sync:
+                self.rg.bin_sort(ws, 0)
+                return ws, -1
+            n = self.rg.bin_sort(ws, B.SYNC_COUNT, raise_on_capacity=False)
+            if n >= 0:
+                return ws, n
+            need = -n - 1
+            setattr(self, cap_attr, int(need * 1.25) + 4096)
+
+    # -------------------------------------------------------------- steps
+    def forward_view(self, v: int):
+        ws, n = self.project_and_sort([self.cams[v]], "cap_view", "_ws_view")
+        self.rg.render_fwd(self.surfels(), ws, self.out_view(v))
+        return ws, n
+
+    def step_plain(self, lr: Optional[B.LR] = None, total_steps: int = 1, adam: bool = True):
+        """One training step, one launch sequence per view (the plain path)."""
+        self.step_count += 1
+        lr = lr or paper_lr(self.scene.extent, self.step_count, total_steps)
+        self.loss.zero_()
+        self.d_exp.zero_()
+        surf = self.surfels()
+        for v in range(self.V):
+            ws, _ = self.forward_view(v)
+            ov, gv = self.out_view(v), self.out_view(v, self.G)
+            self.rg.loss(ws, ov, self.targets(v, v + 1), gv, self.loss, self.d_exp[v])
+            self.rg.render_bwd(surf, ws, ov, gv, self.grads, B.ACCUMULATE if v else 0)
+        if adam:
+            self.adam(lr)
+
+    def step_batched(self, lr: Optional[B.LR] = None, total_steps: int = 1, adam: bool = True,
+                     sync: bool = True):
+        """One training step with every view in one batch."""
+        self.step_count += 1
+        lr = lr or paper_lr(self.scene.extent, self.step_count, total_steps)
+        self.loss.zero_()
+        self.d_exp.zero_()
+        surf = self.surfels()
+        ws, _ = self.project_and_sort(self.cams, "cap_batch", "_ws_batch", sync=sync)
+        self.rg.render_fwd(surf, ws, self.out)
+        self.rg.loss(ws, self.out, self.targets(0, self.V), self.G, self.loss, self.d_exp)
+        self.rg.render_bwd(surf, ws, self.out, self.G, self.grads, 0)
+        if adam:
+            self.adam(lr)
+
+    def adam(self, lr: B.LR):
+        self.rg.adam_step(self.N, self.C, self.params, self.grads, self.m, self.v, self.s_act,
+                          self.alpha_act, lr, self.step_count, exposure=self.exposure,
+                          d_exposure=self.d_exp, m_exp=self.m_exp, v_exp=self.v_exp,
+                          n_views=self.V)
+
+    def render_all_plain(self):
+        for v in range(self.V):
+            self.forward_view(v)
