@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the surfel-splatting training step on one MI355X.
+
+A step is the whole hot path over one batch: cull + EWA projection, tile-key
+emission + radix sort + ranges, forward compositing, L1 + cross-entropy loss
+seed, backward compositing, projection adjoint, and the Adam update.
+
+Default workload: 200,000 surfels (1000 x 200 grid at 0.1 m along a curved
+trajectory, 8 semantic classes) seen by six 1600 x 900 surround cameras.
+Two paths are timed on the same workload: "batched" (all views of the step in
+one launch sequence, pair count kept on the device) and "plain" (one launch
+sequence per view with a host read-back of the pair count).
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+
+
+def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int) -> float:
+    """Compulsory HBM bytes of one launch group of one step."""
+    N, V = st.N, st.V
+    P, vis, pix, slots = stats["pairs"], stats["visible"], stats["pixels"], stats["slots"]
+    FS = ((4 + C) + 3) // 4 * 4
+    if kernel == "project":
+        return N * (40 + 4 * FS) + slots * 4 + vis * 40
+    if kernel == "emit":
+        return slots * 8 + vis * 40 + P * 16
+    if kernel == "sort":
+        return passes * P * 32
+    if kernel == "render_fwd":
+        return pix * ((5 + C) * 4 + 8) + P * 8 + vis * (32 + 4 * FS)
+    if kernel == "loss":
+        return pix * ((3 + C) * 4 + 14 + 1 + (5 + C) * 4)
+    if kernel == "render_bwd":
+        return pix * ((5 + C) * 4 + (4 + C) * 4 + 8) + P * (8 + 4 * (10 + C)) + vis * (32 + 4 * FS)
+    if kernel == "proj_bwd":
+        return slots * 4 + vis * 4 + P * 4 * (10 + C) + N * (40 + 4 * (11 + C))
+    if kernel == "adam":
+        return N * ((11 + C) * 4 * 7 + 2 * 3 * 4) + V * 2 * 4 * 7
+    return 0.0
+
+
+def cpu_baseline(scene, budget_s: float = 12.0):
+    """The FP64 oracle's full training step (all views: forward, loss,
+    backward, Adam) on the host cores; repeated until budget_s is used."""
+    import numpy as np
+    import oracle
+
+    prm = oracle.Params.from_scene(scene)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        L, g, dexp, _ = oracle.loss_and_grads(prm, scene.cams, scene.targets)
+        p = prm.z.copy()
+        oracle.adam(p, np.ascontiguousarray(g[:scene.n]), np.zeros_like(p), np.zeros_like(p), 1e-4, 1)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 20:
+            break
+    px = scene.npix * reps
+    return {"value": round(px / el / 1e6, 3), "unit": "Mpixel/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} full FP64 oracle step(s) of the same workload "
+                      f"({scene.n_views} views, {scene.npix} px each step), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, help="1..4: workload (default 2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2405_14342_amd import synth
+    from paper_2405_14342_amd.pipeline import TrainState
+
+    torch.cuda.set_device(0)
+    scene = synth.CONFIGS[args.config]()
+    C = scene.n_sem
+    total_steps = args.warmup + args.steps
+    st = TrainState(scene, device="cuda:0")
+    print(f"[bench] {scene.name}: {scene.n} surfels, {scene.n_views} views, "
+          f"{scene.npix} px/step", file=sys.stderr, flush=True)
+
+    def run(path, steps, profile=False):
+        fn = st.step_batched if path == "batched" else st.step_plain
+        torch.cuda.synchronize()
+        if profile:
+            st.rg.prof_enable(True)
+            st.rg.prof_read()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            fn(total_steps=total_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = None
+        if profile:
+            prof = st.rg.prof_read()
+            st.rg.prof_enable(False)
+        return wall * 1e3 / steps, e0.elapsed_time(e1) / steps, prof
+
+    run("batched", args.warmup)
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    ms_b, ev_b, prof = run("batched", args.steps, profile=True)
+    stats = st.rg.batch_stats(st._ws_batch)
+    print(f"[bench] batched: {ms_b:.3f} ms/step, pairs {stats['pairs']}", file=sys.stderr, flush=True)
+    plain = None
+    if not args.no_plain:
+        run("plain", max(1, args.warmup))
+        ms_p, ev_p, _ = run("plain", args.steps)
+        plain = {"ms_per_step": round(ms_p, 4),
+                 "value": round(scene.npix / (ms_p * 1e-3) / 1e6, 2)}
+        print(f"[bench] plain: {ms_p:.3f} ms/step", file=sys.stderr, flush=True)
+
+    key_bits = 32 + max(1, (stats["tiles"] - 1).bit_length())
+    passes = (key_bits + 7) // 8
+    kernels = {}
+    for name, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        per = ms / args.steps
+        b = algorithmic_bytes(name, st, stats, C, passes)
+        kernels[name] = {"ms_per_step": round(per, 4), "launches_per_step": n // args.steps,
+                         "alg_GBs": round(b / (per * 1e-3) / 1e9, 1) if per > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    dom_ms = prof[dom][0] / prof[dom][1]          # average duration of one launch group
+    dom_bytes = algorithmic_bytes(dom, st, stats, C, passes) / (prof[dom][1] / args.steps)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(dom_ms, 4),
+                "alg_bytes_per_launch": int(dom_bytes)}
+
+    value = scene.npix / (ms_b * 1e-3) / 1e6
+    line = {
+        "metric": "fwd+bwd Mpixel/s per train step (fused vs plain)",
+        "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_b, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded surfel grid, cameras and random targets)",
+        "config": {"workload": scene.name, "surfels": scene.n, "views": scene.n_views,
+                   "pixels_per_step": scene.npix, "sem_classes": C, "path": "batched",
+                   "pairs": stats["pairs"], "visible_slots": stats["visible"]},
+        "plain": plain,
+        "speedup_vs_plain": round(plain["ms_per_step"] / ms_b, 3) if plain else None,
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(scene)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

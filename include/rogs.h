@@ -36,13 +36,14 @@
  *        K * P_v + c * W_v * H_v + y * W_v + x.
  *    Rendered images have K = 5 + C channels: R, G, B, sem[0..C-1], D, A.
  *
- * FP32 key contract
- * -----------------
+ * Key contract
+ * ------------
  * Everything that decides an integer (culling, tile rectangles, the depth
- * sort key, whether a pixel is touched by a surfel) is computed in IEEE
- * binary32, round to nearest even, without fused multiply-add, with
- * correctly rounded division and square root, exactly in this order
- * ("a*b + c*d" means round(round(a*b) + round(c*d))):
+ * sort key, whether a pixel is touched by a surfel) follows this sequence on
+ * every implementation.  The projection is computed in IEEE binary64 from the
+ * binary32 inputs (promoted exactly), round to nearest even, without fused
+ * multiply-add, with correctly rounded division and square root, exactly in
+ * this order ("a*b + c*d" means round(round(a*b) + round(c*d))):
  *
  *   tx = ((R0*x + R1*y) + R2*z) + t0,  ty, tz likewise with rows 1, 2
  *   visible needs tz >= z_near; if cull_lat > 0 also, with dx = x - o0,
@@ -68,9 +69,12 @@
  *   tile rect: x0 = floor((u - hx)/tile_w), x1 = floor((u + hx)/tile_w) + 1,
  *              y0, y1 likewise; each clamped to [0, tiles]; needs x0<x1, y0<y1
  *              (and u, v, hx, hy, A, B, C finite)
- *   sort key  = (global tile index << 32) | bit pattern of tz, ties by id
- *   pixel (px, py) is touched iff q32 <= q_cut, where dx = (px + 0.5) - u,
- *   dy = (py + 0.5) - v, q32 = (A*(dx*dx) + C*(dy*dy)) + 2*(B*(dx*dy)).
+ * The record keeps binary32 roundings: u_hi = f32(u), u_lo = f32(u - u_hi),
+ * v_hi, v_lo likewise, A, B, C = f32(A), ..., t_z = f32(tz).
+ *   sort key  = (global tile index << 32) | bit pattern of f32(tz), ties by id
+ * Per pixel, in binary32: dx = ((px + 0.5) - u_hi) - u_lo, dy likewise,
+ *   q32 = (A*(dx*dx) + C*(dy*dy)) + 2*(B*(dx*dy)); the pixel is touched iff
+ *   q32 <= q_cut.
  *
  * Values (Eq. 6): for touched pixels g = exp(-q/2), a = min(alpha*g,
  * alpha_max), w = a*T, O += w*f for f in (rgb, sem, tz), T *= 1 - a; a pixel
@@ -183,7 +187,7 @@ ROGS_API int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams,
                         const rogs_render_opts* opts, int64_t pair_capacity, size_t* bytes);
 
 /* a1-a2, Eq. 5 + supp. Sec. 2.1.  Starts a batch: uploads the view table into
- * the workspace, culls and projects every (view, surfel) with the FP32 key
+ * the workspace, culls and projects every (view, surfel) with the key
  * contract, counts tiles per surfel and scans the counts.  The batch state
  * (layout, views) is kept in ctx for the calls below, which must pass the
  * same workspace. */
@@ -239,6 +243,20 @@ ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* para
                    const float* d_exposure, float* m_exp, float* v_exp, int32_t n_views,
                    void* stream);
 
+/* Batch statistics (host sync): stats[0] pairs P, [1] overflow flag,
+ * [2] visible (view, surfel) slots, [3] pixels, [4] tiles, [5] slots V*N. */
+ROGS_API int rogs_batch_stats(rogs_ctx* ctx, void* ws, int64_t* stats, void* stream);
+
+/* Kernel timing.  While enabled, every launch group of the context is
+ * bracketed by two HIP events on its stream.  rogs_prof_read waits for the
+ * recorded events, returns the summed milliseconds and launch counts per group
+ * (arrays of ROGS_PROF_GROUPS entries; n must be >= ROGS_PROF_GROUPS) since
+ * the previous read, and resets them.  Group names: rogs_prof_name. */
+#define ROGS_PROF_GROUPS 10
+ROGS_API int rogs_prof_enable(rogs_ctx* ctx, int32_t on);
+ROGS_API int rogs_prof_read(rogs_ctx* ctx, double* ms, int64_t* launches, int32_t n);
+ROGS_API const char* rogs_prof_name(int32_t group);
+
 /* Read-back helpers for tests (host sync): copy the sorted keys, surfel ids
  * and per-tile ranges of the current batch to host buffers of the given
  * capacity. */
@@ -246,7 +264,8 @@ ROGS_API int rogs_debug_pairs(rogs_ctx* ctx, void* ws, uint64_t* keys, int32_t* 
                      int32_t* views, int64_t cap, uint32_t* ranges, int64_t n_tiles,
                      void* stream);
 /* Copy the per-(view, surfel) projection records of the current batch:
- * rec[V][N][8] = u v A B C tz alpha 0, rect[V][N][4], count[V][N]. */
+ * rec[V][N][8] = u_hi v_hi u_lo v_lo A B C t_z, rect[V][N][4] = x0 x1 y0 y1,
+ * count[V][N] = tiles covered (0 = culled; then rec and rect are zero). */
 ROGS_API int rogs_debug_records(rogs_ctx* ctx, void* ws, float* rec, int32_t* rect, uint32_t* count,
                        void* stream);
 

@@ -11,8 +11,9 @@ Eq. 2 (covariance with s_z = 0), Eq. 5 (EWA projection; orthographic J),
 the ascending-depth sort and Eq. 6 (alpha compositing of RGB, semantics,
 depth and alpha), Eq. 7 (exposure), Eq. 8/9/12 (masked L1 + CE), and Adam
 (Sec. 4.2).  Discrete decisions (cull, tile rectangles, per-pixel 3-sigma
-test, depth order) are taken with the FP32 key contract that the library
-documents; every value is computed in FP64.
+test, depth order) are taken with the key contract that the library
+documents (FP64 projection rounded to an FP32 record, FP32 per-pixel test);
+every value is computed in FP64.
 
 Parity status of each function (what pins it) is listed in the test files
 ``tests/test_oracle_*.py``.
@@ -147,11 +148,12 @@ def split_grads(g: np.ndarray, n: int, C: int):
 
 
 def contract(prm: Params, cam, opts: Opts = Opts()):
-    """FP32 key contract of one view: (vis[n] bool, rec[n,6] u v A B C tz, rect[n,4])."""
+    """Key contract of one view: (vis[n] bool, rec[n,8] = u_hi v_hi u_lo v_lo A B C t_z
+    (binary32), rect[n,4] = x0 x1 y0 y1)."""
     L = _load()
     io, fo = opts.arrays()
     f64 = prm.f64()
-    rec = np.zeros((prm.n, 6), np.float32)
+    rec = np.zeros((prm.n, 8), np.float32)
     rect = np.zeros((prm.n, 4), np.int32)
     vis = np.zeros(prm.n, np.uint8)
     L.orc_contract(prm.n, prm.C, _p(prm.f32), _p(f64), _p(pack_camera(cam)), _p(io), _p(fo),

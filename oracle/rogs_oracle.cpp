@@ -18,10 +18,11 @@
 //   * Adam                                                         (Sec. 4.2)
 // Readings where the paper is silent (pixel centres, the EWA low-pass eps,
 // the 3-sigma cut, the opacity clamp, the termination threshold, the
-// Jacobian clamp) are fixed by the library's documented FP32 "key contract";
-// this file restates that contract on its own, in FP32, because it decides
-// integers (which surfels touch which tiles and pixels, and their order).
-// All values are then computed in FP64 from the same inputs.
+// Jacobian clamp) are fixed by the library's documented "key contract"; this
+// file restates that contract on its own (FP64 projection rounded to an FP32
+// record, FP32 per-pixel test) because it decides integers: which surfels
+// touch which tiles and pixels, and their order.  All values are then
+// computed in FP64 from the same inputs.
 //
 // Build: g++ -O2 -std=c++17 -fopenmp -ffp-contract=off -fno-fast-math -shared -fPIC
 #include <algorithm>
@@ -76,112 +77,126 @@ struct Surfels {
   const double *x, *y, *z, *q, *s, *alpha, *rgb, *sem;   // rgb [3][n], sem [C][n]
 };
 
-// ------------------------------------------------- FP32 decision contract
+// ------------------------------------------------------ decision contract
 //
-// Every operation below is one IEEE binary32 operation, rounded to nearest
-// even, in the order written (the file is compiled with -ffp-contract=off so
-// no multiply-add is fused).
+// The projection that decides integers is computed in IEEE binary64 from the
+// FP32 inputs (promoted exactly), one rounded operation per step in the order
+// written (the file is compiled with -ffp-contract=off so no multiply-add is
+// fused), then rounded once to the binary32 record; the per-pixel test is
+// binary32.  The library documents the same sequence.
 
 struct Rec32 {
   bool vis;
-  float u, v, A, B, C, tz;
+  float uh, vh, ul, vl;      // centre as a binary32 pair: u = uh + ul
+  float A, B, C, tz;
   int x0, x1, y0, y1;
 };
 
-int clampi_f(float f, int hi) {   // clamp a floored float into [0, hi]
-  if (!(f > 0.0f)) return 0;
-  if (f > (float)hi) return hi;
+int clampi_d(double f, int hi) {   // clamp a floored value into [0, hi]
+  if (!(f > 0.0)) return 0;
+  if (f > (double)hi) return hi;
   return (int)f;
 }
 
-Rec32 contract(const Cam& c, const Opts& o, float x, float y, float z,
-               float qw, float qx, float qy, float qz, float sx, float sy) {
+Rec32 contract(const Cam& c, const Opts& o, float xf, float yf, float zf, float qwf, float qxf,
+               float qyf, float qzf, float sxf, float syf) {
   Rec32 r;
   r.vis = false;
-  const float* R = c.R;
-  float tx = ((R[0] * x + R[1] * y) + R[2] * z) + c.t[0];
-  float ty = ((R[3] * x + R[4] * y) + R[5] * z) + c.t[1];
-  float tz = ((R[6] * x + R[7] * y) + R[8] * z) + c.t[2];
-  r.tz = tz;
-  if (!(tz >= c.znear)) return r;
+  r.uh = r.vh = r.ul = r.vl = r.A = r.B = r.C = 0.0f;
+  r.x0 = r.x1 = r.y0 = r.y1 = 0;
+  const double x = xf, y = yf, z = zf, qw = qwf, qx = qxf, qy = qyf, qz = qzf, sx = sxf, sy = syf;
+  double R[9];
+  for (int k = 0; k < 9; ++k) R[k] = c.R[k];
+  double tx = ((R[0] * x + R[1] * y) + R[2] * z) + (double)c.t[0];
+  double ty = ((R[3] * x + R[4] * y) + R[5] * z) + (double)c.t[1];
+  double tz = ((R[6] * x + R[7] * y) + R[8] * z) + (double)c.t[2];
+  r.tz = (float)tz;
+  if (!(tz >= (double)c.znear)) return r;
   if (c.lat > 0.0f) {
-    float dx = x - c.o[0];
-    float dy = y - c.o[1];
-    float a = dx * c.ex[0] + dy * c.ex[1];
-    float b = dx * c.ez[0] + dy * c.ez[1];
-    if (!(std::fabs(a) <= c.lat)) return r;
-    if (!(b >= 0.0f && b <= c.fwd)) return r;
+    double dx = x - (double)c.o[0];
+    double dy = y - (double)c.o[1];
+    double a = dx * (double)c.ex[0] + dy * (double)c.ex[1];
+    double b = dx * (double)c.ez[0] + dy * (double)c.ez[1];
+    if (!(std::fabs(a) <= (double)c.lat)) return r;
+    if (!(b >= 0.0 && b <= (double)c.fwd)) return r;
   }
-  float nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-  if (!(nn > 0.0f) || !std::isfinite(nn)) return r;
-  float nq = std::sqrt(nn);
-  float w = qw / nq, a = qx / nq, b = qy / nq, cc = qz / nq;
-  float r1x = 1.0f - 2.0f * (b * b + cc * cc);
-  float r1y = 2.0f * (a * b + w * cc);
-  float r1z = 2.0f * (a * cc - w * b);
-  float r2x = 2.0f * (a * b - w * cc);
-  float r2y = 1.0f - 2.0f * (a * a + cc * cc);
-  float r2z = 2.0f * (b * cc + w * a);
-  float T1[3] = {sx * r1x, sx * r1y, sx * r1z};
-  float T2[3] = {sy * r2x, sy * r2y, sy * r2z};
-  float c1[3], c2[3];
+  double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+  if (!(nn > 0.0) || !std::isfinite(nn)) return r;
+  double nq = std::sqrt(nn);
+  double w = qw / nq, a = qx / nq, b = qy / nq, cc = qz / nq;
+  double r1x = 1.0 - 2.0 * (b * b + cc * cc);
+  double r1y = 2.0 * (a * b + w * cc);
+  double r1z = 2.0 * (a * cc - w * b);
+  double r2x = 2.0 * (a * b - w * cc);
+  double r2y = 1.0 - 2.0 * (a * a + cc * cc);
+  double r2z = 2.0 * (b * cc + w * a);
+  double T1[3] = {sx * r1x, sx * r1y, sx * r1z};
+  double T2[3] = {sy * r2x, sy * r2y, sy * r2z};
+  double c1[3], c2[3];
   for (int k = 0; k < 3; ++k) {
     c1[k] = (R[3 * k] * T1[0] + R[3 * k + 1] * T1[1]) + R[3 * k + 2] * T1[2];
     c2[k] = (R[3 * k] * T2[0] + R[3 * k + 1] * T2[1]) + R[3 * k + 2] * T2[2];
   }
-  float j00, j11, j02, j12, u, v;
+  const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
+  double j00, j11, j02, j12, u, v;
   if (c.model == 0) {
-    float limx = (0.65f * (float)c.w) / c.fx;
-    float limy = (0.65f * (float)c.h) / c.fy;
-    float xr = tx / tz, yr = ty / tz;
-    float xc = std::min(std::max(xr, -limx), limx);
-    float yc = std::min(std::max(yr, -limy), limy);
-    j00 = c.fx / tz;
-    j11 = c.fy / tz;
+    double limx = (0.65 * (double)c.w) / fx;
+    double limy = (0.65 * (double)c.h) / fy;
+    double xr = tx / tz, yr = ty / tz;
+    double xc = std::min(std::max(xr, -limx), limx);
+    double yc = std::min(std::max(yr, -limy), limy);
+    j00 = fx / tz;
+    j11 = fy / tz;
     j02 = -(j00 * xc);
     j12 = -(j11 * yc);
-    u = c.fx * xr + c.cx;
-    v = c.fy * yr + c.cy;
+    u = fx * xr + cx;
+    v = fy * yr + cy;
   } else {
-    j00 = c.fx; j11 = c.fy; j02 = 0.0f; j12 = 0.0f;
-    u = c.fx * tx + c.cx;
-    v = c.fy * ty + c.cy;
+    j00 = fx; j11 = fy; j02 = 0.0; j12 = 0.0;
+    u = fx * tx + cx;
+    v = fy * ty + cy;
   }
-  float m00 = j00 * c1[0] + j02 * c1[2];
-  float m01 = j00 * c2[0] + j02 * c2[2];
-  float m10 = j11 * c1[1] + j12 * c1[2];
-  float m11 = j11 * c2[1] + j12 * c2[2];
-  float g0 = m00 * m00 + m01 * m01;
-  float g1 = m10 * m10 + m11 * m11;
-  float s00 = g0 + o.eps, s11 = g1 + o.eps;
-  float s01 = m00 * m10 + m01 * m11;
-  float dm = m00 * m11 - m01 * m10;
-  float det = (dm * dm + o.eps * (g0 + g1)) + o.eps * o.eps;
-  if (!(det > 0.0f) || !std::isfinite(det)) return r;
-  r.A = s11 / det;
-  r.B = -(s01 / det);
-  r.C = s00 / det;
-  float hx = std::sqrt(o.qcut * s00) + 1.0f;
-  float hy = std::sqrt(o.qcut * s11) + 1.0f;
+  const double eps = o.eps, qcut = o.qcut;
+  double m00 = j00 * c1[0] + j02 * c1[2];
+  double m01 = j00 * c2[0] + j02 * c2[2];
+  double m10 = j11 * c1[1] + j12 * c1[2];
+  double m11 = j11 * c2[1] + j12 * c2[2];
+  double g0 = m00 * m00 + m01 * m01;
+  double g1 = m10 * m10 + m11 * m11;
+  double s00 = g0 + eps, s11 = g1 + eps;
+  double s01 = m00 * m10 + m01 * m11;
+  double dm = m00 * m11 - m01 * m10;
+  double det = (dm * dm + eps * (g0 + g1)) + eps * eps;
+  if (!(det > 0.0) || !std::isfinite(det)) return r;
+  double A = s11 / det;
+  double B = -(s01 / det);
+  double C = s00 / det;
+  double hx = std::sqrt(qcut * s00) + 1.0;
+  double hy = std::sqrt(qcut * s11) + 1.0;
   if (!std::isfinite(u) || !std::isfinite(v) || !std::isfinite(hx) || !std::isfinite(hy) ||
-      !std::isfinite(r.A) || !std::isfinite(r.B) || !std::isfinite(r.C))
+      !std::isfinite(A) || !std::isfinite(B) || !std::isfinite(C))
     return r;
   int TX = (c.w + o.tw - 1) / o.tw, TY = (c.h + o.th - 1) / o.th;
-  r.x0 = clampi_f(std::floor((u - hx) / (float)o.tw), TX);
-  r.x1 = clampi_f(std::floor((u + hx) / (float)o.tw) + 1.0f, TX);
-  r.y0 = clampi_f(std::floor((v - hy) / (float)o.th), TY);
-  r.y1 = clampi_f(std::floor((v + hy) / (float)o.th) + 1.0f, TY);
+  r.x0 = clampi_d(std::floor((u - hx) / (double)o.tw), TX);
+  r.x1 = clampi_d(std::floor((u + hx) / (double)o.tw) + 1.0, TX);
+  r.y0 = clampi_d(std::floor((v - hy) / (double)o.th), TY);
+  r.y1 = clampi_d(std::floor((v + hy) / (double)o.th) + 1.0, TY);
   if (r.x0 >= r.x1 || r.y0 >= r.y1) return r;
-  r.u = u;
-  r.v = v;
+  r.uh = (float)u;
+  r.ul = (float)(u - (double)r.uh);
+  r.vh = (float)v;
+  r.vl = (float)(v - (double)r.vh);
+  r.A = (float)A;
+  r.B = (float)B;
+  r.C = (float)C;
   r.vis = true;
   return r;
 }
 
-// Per-pixel contribution test of the contract.
+// Per-pixel contribution test (binary32).
 inline float q32(const Rec32& r, int px, int py) {
-  float dx = ((float)px + 0.5f) - r.u;
-  float dy = ((float)py + 0.5f) - r.v;
+  float dx = (((float)px + 0.5f) - r.uh) - r.ul;
+  float dy = (((float)py + 0.5f) - r.vh) - r.vl;
   return (r.A * (dx * dx) + r.C * (dy * dy)) + 2.0f * (r.B * (dx * dy));
 }
 
@@ -530,8 +545,8 @@ Opts make_opts(const int* io, const float* fo) {
 
 extern "C" {
 
-// FP32 contract for every surfel of one view.
-// rec: [n][6] = u v A B C tz ; rect: [n][4] = x0 x1 y0 y1 ; vis: [n]
+// Decision contract for every surfel of one view.
+// rec: [n][8] = u_hi v_hi u_lo v_lo A B C tz ; rect: [n][4] = x0 x1 y0 y1 ; vis: [n]
 // Returns the number of visible surfels.
 int orc_contract(int n, int C, const float* f32, const double* f64, const float* cam,
                  const int* iopts, const float* fopts, float* rec, int32_t* rect, uint8_t* vis) {
@@ -543,11 +558,17 @@ int orc_contract(int n, int C, const float* f32, const double* f64, const float*
     Rec32 r = contract(c, o, S.xf[i], S.yf[i], S.zf[i], S.qf[i], S.qf[n + i], S.qf[2 * n + i],
                        S.qf[3 * n + i], S.sf[i], S.sf[n + i]);
     vis[i] = r.vis ? 1 : 0;
-    float* R = rec + 6 * (size_t)i;
-    R[0] = r.u; R[1] = r.v; R[2] = r.A; R[3] = r.B; R[4] = r.C; R[5] = r.tz;
+    float* R = rec + 8 * (size_t)i;
     int32_t* q = rect + 4 * (size_t)i;
-    q[0] = r.x0; q[1] = r.x1; q[2] = r.y0; q[3] = r.y1;
-    if (!r.vis) { R[0] = R[1] = R[2] = R[3] = R[4] = 0.0f; q[0] = q[1] = q[2] = q[3] = 0; }
+    if (r.vis) {
+      R[0] = r.uh; R[1] = r.vh; R[2] = r.ul; R[3] = r.vl;
+      R[4] = r.A; R[5] = r.B; R[6] = r.C; R[7] = r.tz;
+      q[0] = r.x0; q[1] = r.x1; q[2] = r.y0; q[3] = r.y1;
+    } else {
+      for (int k = 0; k < 8; ++k) R[k] = 0.0f;
+      R[7] = r.tz;
+      q[0] = q[1] = q[2] = q[3] = 0;
+    }
     cnt += r.vis;
   }
   return cnt;

@@ -27,7 +27,9 @@ STATUS_NAMES = {0: "OK", 1: "NOT_READY", -1: "EINVAL", -2: "ENOMEM", -3: "ECAPAC
 EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts",
             "rogs_workspace_size", "rogs_project", "rogs_bin_sort", "rogs_pair_count",
             "rogs_render_fwd", "rogs_loss", "rogs_render_bwd", "rogs_adam_step",
-            "rogs_debug_pairs", "rogs_debug_records")
+            "rogs_debug_pairs", "rogs_debug_records", "rogs_batch_stats", "rogs_prof_enable",
+            "rogs_prof_read", "rogs_prof_name")
+PROF_GROUPS = 10
 
 
 class RogsError(RuntimeError):
@@ -100,6 +102,10 @@ def load_library(path: str = LIB_PATH):
                                 P, P, P, P, I32, P], I32),
             "rogs_debug_pairs": ([P, P, P, P, P, I64, P, I64, P], I32),
             "rogs_debug_records": ([P, P, P, P, P, P], I32),
+            "rogs_batch_stats": ([P, P, P, P], I32),
+            "rogs_prof_enable": ([P, I32], I32),
+            "rogs_prof_read": ([P, P, P, I32], I32),
+            "rogs_prof_name": ([I32], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -247,6 +253,24 @@ class Rogs:
                                           int(step), beta1, beta2, eps, ptr(exposure),
                                           ptr(d_exposure), ptr(m_exp), ptr(v_exp), int(n_views),
                                           _stream(stream)), "rogs_adam_step")
+
+    def batch_stats(self, ws, stream=None) -> dict:
+        st = np.zeros(6, np.int64)
+        self._check(self.L.rogs_batch_stats(self.h, ptr(ws), st.ctypes.data, _stream(stream)),
+                    "rogs_batch_stats")
+        return dict(pairs=int(st[0]), overflow=int(st[1]), visible=int(st[2]), pixels=int(st[3]),
+                    tiles=int(st[4]), slots=int(st[5]))
+
+    def prof_enable(self, on: bool = True):
+        self._check(self.L.rogs_prof_enable(self.h, 1 if on else 0), "rogs_prof_enable")
+
+    def prof_read(self) -> dict:
+        ms = np.zeros(PROF_GROUPS, np.float64)
+        n = np.zeros(PROF_GROUPS, np.int64)
+        self._check(self.L.rogs_prof_read(self.h, ms.ctypes.data, n.ctypes.data, PROF_GROUPS),
+                    "rogs_prof_read")
+        return {self.L.rogs_prof_name(k).decode(): (float(ms[k]), int(n[k]))
+                for k in range(PROF_GROUPS)}
 
     def debug_pairs(self, ws, cap: int, n_tiles: int, stream=None):
         keys = np.zeros(max(cap, 1), np.uint64)

@@ -25,6 +25,17 @@ struct rogs_ctx {
   hipEvent_t stage_evt = nullptr;
   bool stage_pending = false;
   uint32_t* readback = nullptr;   // pinned, for pair-count read-back
+  int64_t last_visible = 0;
+  // kernel timing (rogs_prof_enable): events bracketing each launch group
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Rec { int group; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  int open_group = -1;
+  hipEvent_t open_ev = nullptr;
+  double prof_ms[ROGS_PROF_GROUPS] = {};
+  int64_t prof_n[ROGS_PROF_GROUPS] = {};
 };
 
 namespace {
@@ -202,6 +213,56 @@ int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws
   return ROGS_OK;
 }
 
+const char* kProfNames[ROGS_PROF_GROUPS] = {"project",    "scan",       "emit",
+                                            "sort",       "ranges",     "render_fwd",
+                                            "loss",       "render_bwd", "proj_bwd",
+                                            "adam"};
+
+hipEvent_t prof_event(rogs_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// Brackets the launches between prof_begin and prof_end with two events on
+// the launch stream (no-op unless timing is enabled).
+void prof_begin(rogs_ctx* c, int group, hipStream_t st) {
+  if (!c->prof) return;
+  hipEvent_t e = prof_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, st);
+  c->open_group = group;
+  c->open_ev = e;
+}
+
+void prof_end(rogs_ctx* c, hipStream_t st) {
+  if (!c->prof || c->open_group < 0) return;
+  hipEvent_t e = prof_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, st);
+  c->recs.push_back({c->open_group, c->open_ev, e});
+  c->open_group = -1;
+}
+
+// Folds finished records into the per-group totals (waits for them).
+int prof_collect(rogs_ctx* c) {
+  for (const auto& r : c->recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return hip_fail(c, e, "rogs_prof_read");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(c, e, "rogs_prof_read");
+    c->prof_ms[r.group] += ms;
+    c->prof_n[r.group] += 1;
+  }
+  c->recs.clear();
+  c->ev_used = 0;
+  return ROGS_OK;
+}
+
 int need_batch(rogs_ctx* c, void* ws, bool sorted) {
   if (!c) return ROGS_EINVAL;
   if (!c->have_batch) return fail(c, ROGS_ESTATE, "no batch: call rogs_project first");
@@ -240,6 +301,8 @@ int rogs_create(rogs_ctx** ctx) {
 
 void rogs_destroy(rogs_ctx* c) {
   if (!c) return;
+  if (!c->recs.empty()) (void)hipEventSynchronize(c->recs.back().b);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->stage_pending) (void)hipEventSynchronize(c->stage_evt);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->readback) (void)hipHostFree(c->readback);
@@ -289,8 +352,12 @@ int rogs_project(rogs_ctx* c, const rogs_surfels* s, const rogs_camera* cams, in
   c->sorted = false;
   r = upload_views(c, L, cams, ws, st);
   if (r != ROGS_OK) return r;
+  prof_begin(c, 0, st);
   rogs::launch_project(L, ws, s, true, st);
+  prof_end(c, st);
+  prof_begin(c, 1, st);
   rogs::launch_scan_part(L, ws, st);
+  prof_end(c, st);
   r = check_launch(c, "rogs_project");
   if (r != ROGS_OK) return r;
   c->L = L;
@@ -310,7 +377,50 @@ int rogs_pair_count(rogs_ctx* c, void* ws, int64_t* n_pairs, int32_t* overflow, 
   if (e != hipSuccess) return hip_fail(c, e, "rogs_pair_count");
   if (n_pairs) *n_pairs = (int64_t)c->readback[rogs::kMiscPairs];
   if (overflow) *overflow = (int32_t)c->readback[rogs::kMiscOverflow];
+  c->last_visible = (int64_t)c->readback[rogs::kMiscVisible];
   return ROGS_OK;
+}
+
+int rogs_batch_stats(rogs_ctx* c, void* ws, int64_t* stats, void* stream) {
+  if (!stats) return fail(c, ROGS_EINVAL, "stats is null");
+  int64_t n = 0;
+  int32_t ovf = 0;
+  int r = rogs_pair_count(c, ws, &n, &ovf, stream);
+  if (r != ROGS_OK) return r;
+  stats[0] = n;
+  stats[1] = ovf;
+  stats[2] = c->last_visible;
+  stats[3] = c->L.total_pix;
+  stats[4] = c->L.total_tiles;
+  stats[5] = c->L.slots;
+  return ROGS_OK;
+}
+
+int rogs_prof_enable(rogs_ctx* c, int32_t on) {
+  if (!c) return ROGS_EINVAL;
+  if (!on && c->prof) {
+    int r = prof_collect(c);
+    if (r != ROGS_OK) return r;
+  }
+  c->prof = on != 0;
+  return ROGS_OK;
+}
+
+int rogs_prof_read(rogs_ctx* c, double* ms, int64_t* launches, int32_t n) {
+  if (!c || !ms || !launches || n < ROGS_PROF_GROUPS) return c ? fail(c, ROGS_EINVAL, "bad arguments") : ROGS_EINVAL;
+  int r = prof_collect(c);
+  if (r != ROGS_OK) return r;
+  for (int k = 0; k < ROGS_PROF_GROUPS; ++k) {
+    ms[k] = c->prof_ms[k];
+    launches[k] = c->prof_n[k];
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  return ROGS_OK;
+}
+
+const char* rogs_prof_name(int32_t group) {
+  return (group >= 0 && group < ROGS_PROF_GROUPS) ? kProfNames[group] : "";
 }
 
 int rogs_bin_sort(rogs_ctx* c, void* ws, int64_t* n_pairs_out, uint32_t flags, void* stream) {
@@ -330,13 +440,19 @@ int rogs_bin_sort(rogs_ctx* c, void* ws, int64_t* n_pairs_out, uint32_t flags, v
     *n_pairs_out = -1;
   }
   Layout& L = c->L;
+  prof_begin(c, 2, st);
   rogs::launch_emit(L, ws, st);
+  prof_end(c, st);
+  prof_begin(c, 3, st);
   int alt = rogs::launch_sort(L, ws, n_host, st);
+  prof_end(c, st);
   if (alt) {
     std::swap(L.o_keys, L.o_keys2);
     std::swap(L.o_vals, L.o_vals2);
   }
+  prof_begin(c, 4, st);
   rogs::launch_ranges(L, ws, n_host, st);
+  prof_end(c, st);
   r = check_launch(c, "rogs_bin_sort");
   if (r != ROGS_OK) return r;
   c->sorted = true;
@@ -350,8 +466,11 @@ int rogs_render_fwd(rogs_ctx* c, const rogs_surfels* s, void* ws, float* out_ima
   r = check_surfels(c, s, c->L);
   if (r != ROGS_OK) return r;
   if (!out_images) return fail(c, ROGS_EINVAL, "out_images is null");
-  if (rogs::launch_render_fwd(c->L, ws, s, out_images, static_cast<hipStream_t>(stream)) != 0)
-    return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  prof_begin(c, 5, st);
+  int rr = rogs::launch_render_fwd(c->L, ws, s, out_images, st);
+  prof_end(c, st);
+  if (rr != 0) return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
   return check_launch(c, "rogs_render_fwd");
 }
 
@@ -364,8 +483,10 @@ int rogs_loss(rogs_ctx* c, void* ws, const float* out_images, const rogs_targets
     return fail(c, ROGS_EINVAL, "a target array pointer is null");
   if (!is_fin(t->lambda_c) || !is_fin(t->lambda_s) || !is_fin(t->view_scale))
     return fail(c, ROGS_EINVAL, "loss weights must be finite");
-  rogs::launch_loss(c->L, ws, out_images, t, dL_dout, loss_out, d_exposure,
-                    static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  prof_begin(c, 6, st);
+  rogs::launch_loss(c->L, ws, out_images, t, dL_dout, loss_out, d_exposure, st);
+  prof_end(c, st);
   return check_launch(c, "rogs_loss");
 }
 
@@ -377,9 +498,13 @@ int rogs_render_bwd(rogs_ctx* c, const rogs_surfels* s, void* ws, const float* o
   if (r != ROGS_OK) return r;
   if (!out_images || !dL_dout || !grads) return fail(c, ROGS_EINVAL, "null argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (rogs::launch_render_bwd(c->L, ws, s, out_images, dL_dout, st) != 0)
-    return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
+  prof_begin(c, 7, st);
+  int rr = rogs::launch_render_bwd(c->L, ws, s, out_images, dL_dout, st);
+  prof_end(c, st);
+  if (rr != 0) return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
+  prof_begin(c, 8, st);
   rogs::launch_proj_bwd(c->L, ws, s, grads, (flags & ROGS_ACCUMULATE) != 0, st);
+  prof_end(c, st);
   return check_launch(c, "rogs_render_bwd");
 }
 
@@ -398,8 +523,11 @@ int rogs_adam_step(rogs_ctx* c, int32_t n, int32_t n_sem, float* params, const f
     return fail(c, ROGS_EINVAL, "Adam hyper-parameters out of range");
   if (exposure && (!d_exposure || !m_exp || !v_exp || n_views < 1))
     return fail(c, ROGS_EINVAL, "exposure group needs gradients, moments and n_views >= 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  prof_begin(c, 9, st);
   rogs::launch_adam(n, n_sem, params, grads, m, v, s_act, alpha_act, lr, step, beta1, beta2, eps,
-                    exposure, d_exposure, m_exp, v_exp, n_views, static_cast<hipStream_t>(stream));
+                    exposure, d_exposure, m_exp, v_exp, n_views, st);
+  prof_end(c, st);
   return check_launch(c, "rogs_adam_step");
 }
 
@@ -455,7 +583,7 @@ int rogs_debug_records(rogs_ctx* c, void* ws, float* rec, int32_t* rect, uint32_
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(c, e, "rogs_debug_records");
   for (size_t k = 0; k < S; ++k) {
-    if (count[k] == 0) {
+    if (count[k] == 0) {   // culled slots keep no record
       for (int j = 0; j < 8; ++j) rec[8 * k + j] = 0.0f;
       for (int j = 0; j < 4; ++j) rect[4 * k + j] = 0;
       continue;

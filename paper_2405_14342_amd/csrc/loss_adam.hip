@@ -213,8 +213,16 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
 #pragma unroll
       for (int c = 0; c < NV; ++c) rg[c] += r[c];
     }
-    proj_adjoint(views[v], eps, x, y, z, q, sx, sy, rg[0], rg[1], rg[2], rg[3], rg[4], rg[6], dz,
-                 dq, dsx, dsy);
+    // this view's contribution first, then one add per component into the
+    // running sum, so summing views here or across calls gives the same bits
+    float dzv = 0.0f, dqv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsxv = 0.0f, dsyv = 0.0f;
+    proj_adjoint(views[v], eps, x, y, z, q, sx, sy, rg[0], rg[1], rg[2], rg[3], rg[4], rg[6], dzv,
+                 dqv, dsxv, dsyv);
+    dz += dzv;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dq[c] += dqv[c];
+    dsx += dsxv;
+    dsy += dsyv;
     dal += rg[5];
 #pragma unroll
     for (int c = 0; c < 3 + C; ++c) dft[c] += rg[7 + c];

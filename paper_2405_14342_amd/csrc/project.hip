@@ -47,9 +47,10 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
     const float* __restrict__ pq, const float* __restrict__ ps, const float* __restrict__ pa,
     const float* __restrict__ prgb, const float* __restrict__ psem, int C, int FS, int pack,
     uint32_t* __restrict__ cnt, float4* __restrict__ rec, uint2* __restrict__ rect,
-    uint32_t* __restrict__ part, float* __restrict__ feat) {
+    uint32_t* __restrict__ part, float* __restrict__ feat, uint32_t* __restrict__ misc) {
   __shared__ uint32_t s_w[kProjBlock / 64];
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  uint32_t nvis = 0;
   const bool valid = i < N;
   float x = 0, y = 0, z = 0, qw = 1, qx = 0, qy = 0, qz = 0, sx = 1, sy = 1, al = 0;
   if (valid) {
@@ -63,7 +64,8 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
       f[1] = prgb[N + i];
       f[2] = prgb[2 * (size_t)N + i];
       for (int c = 0; c < C; ++c) f[3 + c] = psem[(size_t)c * N + i];
-      for (int c = 3 + C; c < FS; ++c) f[c] = 0.0f;
+      f[3 + C] = al;
+      for (int c = 4 + C; c < FS; ++c) f[c] = 0.0f;
     }
   }
   for (int v = 0; v < V; ++v) {
@@ -73,9 +75,10 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
       Proj p = project_contract(vw, eps, qcut, tw, th, x, y, z, qw, qx, qy, qz, sx, sy);
       const size_t slot = (size_t)v * N + i;
       if (p.vis) {
+        ++nvis;
         nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
-        rec[2 * slot] = make_float4(p.u, p.v, p.A, p.B);
-        rec[2 * slot + 1] = make_float4(p.C, p.tz, al, 0.0f);
+        rec[2 * slot] = make_float4(p.uh, p.vh, p.ul, p.vl);
+        rec[2 * slot + 1] = make_float4(p.A, p.B, p.C, p.tz);
         rect[slot] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.x1 << 16),
                                 (uint32_t)p.y0 | ((uint32_t)p.y1 << 16));
       }
@@ -91,6 +94,8 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
     }
     __syncthreads();
   }
+  nvis = wave_sum_u32(nvis);
+  if ((threadIdx.x & 63) == 0 && nvis) atomicAdd(misc + kMiscVisible, nvis);
 }
 
 __global__ void k_check_cap(uint32_t* misc, int64_t cap) {
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(kProjBlock) void k_emit(
       const ViewDev& vw = views[v];
       uint2 r = rect[slot];
       int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
-      uint32_t db = __float_as_uint(rec[2 * slot + 1].y);
+      uint32_t db = __float_as_uint(rec[2 * slot + 1].w);
       uint32_t e = base;
       for (int ty = y0; ty < y1; ++ty) {
         for (int tx = x0; tx < x1; ++tx, ++e) {
@@ -179,8 +184,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, 
   if (t == 0 && total) *total = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in,
-                                                   uint32_t* __restrict__ out, int64_t n,
+// in and out may be the same array (each block reads its chunk before writing it).
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n,
                                                    const uint32_t* __restrict__ sums) {
   __shared__ uint32_t s_v[kScanChunk];
   __shared__ uint32_t s_w[4];
@@ -240,11 +245,13 @@ void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
 
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
                     hipStream_t st) {
+  fill_u32(at<uint32_t>(ws, L.o_misc), 0u, kMiscCount, st);
   hipLaunchKernelGGL(k_project, dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
                      L.th, s->x, s->y, s->z, s->q, s->s, s->alpha, s->rgb, s->sem, L.C, L.FS,
                      pack_feat ? 1 : 0, at<uint32_t>(ws, L.o_cnt), at<float4>(ws, L.o_rec),
-                     at<uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_part), at<float>(ws, L.o_feat));
+                     at<uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_part), at<float>(ws, L.o_feat),
+                     at<uint32_t>(ws, L.o_misc));
 }
 
 void launch_scan_part(const Layout& L, void* ws, hipStream_t st) {

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(
     const float4* __restrict__ feat, float* __restrict__ out, float* __restrict__ tfin,
     uint32_t* __restrict__ nlast) {
   constexpr int F = 3 + C;            // composited features besides depth
-  constexpr int FS4 = (F + 3) / 4;    // float4 per feature record
+  constexpr int FS4 = (F + 4) / 4;    // float4 per feature record (features, alpha)
   constexpr int NO = 5 + C;           // output channels
   __shared__ float4 s_r0[64], s_r1[64];
   __shared__ float4 s_f[64 * FS4];
@@ -89,26 +89,27 @@ __global__ __launch_bounds__(64) void k_render_fwd(
     }
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
-      const float4 r0 = s_r0[j], r1 = s_r1[j];   // u v A B | C tz alpha -
+      const float4 r0 = s_r0[j], r1 = s_r1[j];   // u_hi v_hi u_lo v_lo | A B C tz
       float fv[FS4 * 4];
 #pragma unroll
       for (int f = 0; f < FS4; ++f) {
         const float4 t4 = s_f[j * FS4 + f];
         fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
       }
-      const float dx = pxc - r0.x;
+      const float al = fv[F];
+      const float dx = pixel_offset(pxc, r0.x, r0.z);
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         if (done[k]) continue;
-        const float dy = pyc[k] - r0.y;
-        const float q = pixel_q32(r0.z, r0.w, r1.x, dx, dy);
+        const float dy = pixel_offset(pyc[k], r0.y, r0.w);
+        const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
         if (q <= qcut) {
           const float g = __expf(-0.5f * q);
-          const float a = fminf(r1.z * g, amax);
+          const float a = fminf(al * g, amax);
           const float w = a * T[k];
 #pragma unroll
           for (int f = 0; f < F; ++f) acc[k][f] += w * fv[f];
-          acc[k][F] += w * r1.y;
+          acc[k][F] += w * r1.w;
           T[k] *= (1.0f - a);
           if (T[k] < teps) {
             done[k] = true;
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     const float* __restrict__ tfin, const uint32_t* __restrict__ nlast, float* __restrict__ gpair,
     int GS) {
   constexpr int F = 3 + C;
-  constexpr int FS4 = (F + 3) / 4;
+  constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
   constexpr int NV = 10 + C;          // du dv dA dB dC dalpha dtz drgb[3] dsem[C]
   __shared__ float4 s_r0[64], s_r1[64];
@@ -215,22 +216,23 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     for (int j = 0; j < cnt; ++j) {
       const uint32_t idx = base - rg.x + (uint32_t)j;
       const float4 r0 = s_r0[j], r1 = s_r1[j];
-      const float A = r0.z, B = r0.w, Cc = r1.x, tz = r1.y, al = r1.z;
+      const float A = r1.x, B = r1.y, Cc = r1.z, tz = r1.w;
       float fv[FS4 * 4];
 #pragma unroll
       for (int f = 0; f < FS4; ++f) {
         const float4 t4 = s_f[j * FS4 + f];
         fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
       }
+      const float al = fv[F];
       float pv[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) pv[c] = 0.0f;
       bool touched = false;
-      const float dx = pxc - r0.x;
+      const float dx = pixel_offset(pxc, r0.x, r0.z);
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         if (idx >= nl[k]) continue;
-        const float dy = pyc[k] - r0.y;
+        const float dy = pixel_offset(pyc[k], r0.y, r0.w);
         const float q = pixel_q32(A, B, Cc, dx, dy);
         if (!(q <= qcut)) continue;
         touched = true;

@@ -1,5 +1,5 @@
 // Internal declarations of librogs: workspace layout, the device view table,
-// the FP32 key contract as device code, and kernel launchers.
+// the key contract as device code, and kernel launchers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,7 +35,7 @@ struct ViewDev {
 
 // Number of semantic classes with a compiled kernel set.
 inline bool sem_supported(int C) { return (C >= 1 && C <= 8) || C == 16; }
-inline int feat_stride(int C) { return ((3 + C) + 3) & ~3; }      // rgb + sem, padded to float4
+inline int feat_stride(int C) { return ((4 + C) + 3) & ~3; }      // rgb, sem, alpha; float4-padded
 inline int grad_stride(int C) { return ((10 + C) + 3) & ~3; }     // per-pair gradient record
 
 // Layout of one batch inside the caller's workspace (byte offsets).
@@ -56,7 +56,7 @@ struct Layout {
 };
 
 // misc counters (uint32 slots at o_misc)
-enum MiscSlot { kMiscPairs = 0, kMiscOverflow = 1, kMiscCount = 16 };
+enum MiscSlot { kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscCount = 16 };
 
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
                 const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why);
@@ -70,108 +70,121 @@ __host__ __device__ inline T* at(void* ws, size_t off) {
 
 struct Proj {
   bool vis;
-  float u, v, A, B, C, tz;
+  float uh, vh, ul, vl;   // centre as a binary32 pair (u = uh + ul)
+  float A, B, C, tz;
   int x0, x1, y0, y1;
 };
 
-__device__ __forceinline__ int clamp_tile(float f, int hi) {
-  if (!(f > 0.0f)) return 0;
-  if (f > (float)hi) return hi;
+__device__ __forceinline__ int clamp_tile(double f, int hi) {
+  if (!(f > 0.0)) return 0;
+  if (f > (double)hi) return hi;
   return (int)f;
 }
 
-// FP32 key contract (see rogs.h).  Compiled without FMA contraction; every
-// line is one rounded binary32 operation in the documented order.
-__device__ inline Proj project_contract(const ViewDev& c, float eps, float qcut, int tw, int th,
-                                        float x, float y, float z, float qw, float qx, float qy,
-                                        float qz, float sx, float sy) {
+// Key contract (see rogs.h): the projection in binary64 from the binary32
+// inputs, without FMA contraction, one rounded operation per step in the
+// documented order, rounded once into the binary32 record.
+__device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcut_f, int tw,
+                                        int th, float xf, float yf, float zf, float qwf,
+                                        float qxf, float qyf, float qzf, float sxf, float syf) {
 #pragma clang fp contract(off)
   Proj r;
   r.vis = false;
-  r.u = r.v = r.A = r.B = r.C = 0.0f;
+  r.uh = r.vh = r.ul = r.vl = r.A = r.B = r.C = 0.0f;
   r.x0 = r.x1 = r.y0 = r.y1 = 0;
-  const float* R = c.R;
-  float tx = ((R[0] * x + R[1] * y) + R[2] * z) + c.t[0];
-  float ty = ((R[3] * x + R[4] * y) + R[5] * z) + c.t[1];
-  float tz = ((R[6] * x + R[7] * y) + R[8] * z) + c.t[2];
-  r.tz = tz;
-  if (!(tz >= c.znear)) return r;
+  const double x = xf, y = yf, z = zf, qw = qwf, qx = qxf, qy = qyf, qz = qzf;
+  const double sx = sxf, sy = syf;
+  const double R0 = c.R[0], R1 = c.R[1], R2 = c.R[2], R3 = c.R[3], R4 = c.R[4], R5 = c.R[5];
+  const double R6 = c.R[6], R7 = c.R[7], R8 = c.R[8];
+  const double tx = ((R0 * x + R1 * y) + R2 * z) + (double)c.t[0];
+  const double ty = ((R3 * x + R4 * y) + R5 * z) + (double)c.t[1];
+  const double tz = ((R6 * x + R7 * y) + R8 * z) + (double)c.t[2];
+  r.tz = (float)tz;
+  if (!(tz >= (double)c.znear)) return r;
   if (c.lat > 0.0f) {
-    float dx = x - c.o[0];
-    float dy = y - c.o[1];
-    float a = dx * c.ex[0] + dy * c.ex[1];
-    float b = dx * c.ez[0] + dy * c.ez[1];
-    if (!(fabsf(a) <= c.lat)) return r;
-    if (!(b >= 0.0f && b <= c.fwd)) return r;
+    const double dx = x - (double)c.o[0];
+    const double dy = y - (double)c.o[1];
+    const double a = dx * (double)c.ex[0] + dy * (double)c.ex[1];
+    const double b = dx * (double)c.ez[0] + dy * (double)c.ez[1];
+    if (!(fabs(a) <= (double)c.lat)) return r;
+    if (!(b >= 0.0 && b <= (double)c.fwd)) return r;
   }
-  float nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-  if (!(nn > 0.0f) || !isfinite(nn)) return r;
-  float nq = sqrtf(nn);
-  float w = qw / nq, a = qx / nq, b = qy / nq, cc = qz / nq;
-  float r1x = 1.0f - 2.0f * (b * b + cc * cc);
-  float r1y = 2.0f * (a * b + w * cc);
-  float r1z = 2.0f * (a * cc - w * b);
-  float r2x = 2.0f * (a * b - w * cc);
-  float r2y = 1.0f - 2.0f * (a * a + cc * cc);
-  float r2z = 2.0f * (b * cc + w * a);
-  float T10 = sx * r1x, T11 = sx * r1y, T12 = sx * r1z;
-  float T20 = sy * r2x, T21 = sy * r2y, T22 = sy * r2z;
-  float c10 = (R[0] * T10 + R[1] * T11) + R[2] * T12;
-  float c11 = (R[3] * T10 + R[4] * T11) + R[5] * T12;
-  float c12 = (R[6] * T10 + R[7] * T11) + R[8] * T12;
-  float c20 = (R[0] * T20 + R[1] * T21) + R[2] * T22;
-  float c21 = (R[3] * T20 + R[4] * T21) + R[5] * T22;
-  float c22 = (R[6] * T20 + R[7] * T21) + R[8] * T22;
-  float j00, j11, j02, j12, u, v;
+  const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+  if (!(nn > 0.0) || !isfinite(nn)) return r;
+  const double nq = sqrt(nn);
+  const double w = qw / nq, a = qx / nq, b = qy / nq, cc = qz / nq;
+  const double r1x = 1.0 - 2.0 * (b * b + cc * cc);
+  const double r1y = 2.0 * (a * b + w * cc);
+  const double r1z = 2.0 * (a * cc - w * b);
+  const double r2x = 2.0 * (a * b - w * cc);
+  const double r2y = 1.0 - 2.0 * (a * a + cc * cc);
+  const double r2z = 2.0 * (b * cc + w * a);
+  const double T10 = sx * r1x, T11 = sx * r1y, T12 = sx * r1z;
+  const double T20 = sy * r2x, T21 = sy * r2y, T22 = sy * r2z;
+  const double c10 = (R0 * T10 + R1 * T11) + R2 * T12;
+  const double c11 = (R3 * T10 + R4 * T11) + R5 * T12;
+  const double c12 = (R6 * T10 + R7 * T11) + R8 * T12;
+  const double c20 = (R0 * T20 + R1 * T21) + R2 * T22;
+  const double c21 = (R3 * T20 + R4 * T21) + R5 * T22;
+  const double c22 = (R6 * T20 + R7 * T21) + R8 * T22;
+  const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
+  double j00, j11, j02, j12, u, v;
   if (c.model == ROGS_PINHOLE) {
-    float limx = (0.65f * (float)c.w) / c.fx;
-    float limy = (0.65f * (float)c.h) / c.fy;
-    float xr = tx / tz, yr = ty / tz;
-    float xc = (xr < -limx) ? -limx : xr;
+    const double limx = (0.65 * (double)c.w) / fx;
+    const double limy = (0.65 * (double)c.h) / fy;
+    const double xr = tx / tz, yr = ty / tz;
+    double xc = (xr < -limx) ? -limx : xr;
     xc = (limx < xc) ? limx : xc;
-    float yc = (yr < -limy) ? -limy : yr;
+    double yc = (yr < -limy) ? -limy : yr;
     yc = (limy < yc) ? limy : yc;
-    j00 = c.fx / tz;
-    j11 = c.fy / tz;
+    j00 = fx / tz;
+    j11 = fy / tz;
     j02 = -(j00 * xc);
     j12 = -(j11 * yc);
-    u = c.fx * xr + c.cx;
-    v = c.fy * yr + c.cy;
+    u = fx * xr + cx;
+    v = fy * yr + cy;
   } else {
-    j00 = c.fx; j11 = c.fy; j02 = 0.0f; j12 = 0.0f;
-    u = c.fx * tx + c.cx;
-    v = c.fy * ty + c.cy;
+    j00 = fx; j11 = fy; j02 = 0.0; j12 = 0.0;
+    u = fx * tx + cx;
+    v = fy * ty + cy;
   }
-  float m00 = j00 * c10 + j02 * c12;
-  float m01 = j00 * c20 + j02 * c22;
-  float m10 = j11 * c11 + j12 * c12;
-  float m11 = j11 * c21 + j12 * c22;
-  float g0 = m00 * m00 + m01 * m01;
-  float g1 = m10 * m10 + m11 * m11;
-  float s00 = g0 + eps, s11 = g1 + eps;
-  float s01 = m00 * m10 + m01 * m11;
-  float dm = m00 * m11 - m01 * m10;
-  float det = (dm * dm + eps * (g0 + g1)) + eps * eps;
-  if (!(det > 0.0f) || !isfinite(det)) return r;
-  float A = s11 / det;
-  float B = -(s01 / det);
-  float C = s00 / det;
-  float hx = sqrtf(qcut * s00) + 1.0f;
-  float hy = sqrtf(qcut * s11) + 1.0f;
+  const double eps = eps_f, qcut = qcut_f;
+  const double m00 = j00 * c10 + j02 * c12;
+  const double m01 = j00 * c20 + j02 * c22;
+  const double m10 = j11 * c11 + j12 * c12;
+  const double m11 = j11 * c21 + j12 * c22;
+  const double g0 = m00 * m00 + m01 * m01;
+  const double g1 = m10 * m10 + m11 * m11;
+  const double s00 = g0 + eps, s11 = g1 + eps;
+  const double s01 = m00 * m10 + m01 * m11;
+  const double dm = m00 * m11 - m01 * m10;
+  const double det = (dm * dm + eps * (g0 + g1)) + eps * eps;
+  if (!(det > 0.0) || !isfinite(det)) return r;
+  const double A = s11 / det;
+  const double B = -(s01 / det);
+  const double C = s00 / det;
+  const double hx = sqrt(qcut * s00) + 1.0;
+  const double hy = sqrt(qcut * s11) + 1.0;
   if (!isfinite(u) || !isfinite(v) || !isfinite(hx) || !isfinite(hy) || !isfinite(A) ||
       !isfinite(B) || !isfinite(C))
     return r;
-  int x0 = clamp_tile(floorf((u - hx) / (float)tw), c.tiles_x);
-  int x1 = clamp_tile(floorf((u + hx) / (float)tw) + 1.0f, c.tiles_x);
-  int y0 = clamp_tile(floorf((v - hy) / (float)th), c.tiles_y);
-  int y1 = clamp_tile(floorf((v + hy) / (float)th) + 1.0f, c.tiles_y);
+  const int x0 = clamp_tile(floor((u - hx) / (double)tw), c.tiles_x);
+  const int x1 = clamp_tile(floor((u + hx) / (double)tw) + 1.0, c.tiles_x);
+  const int y0 = clamp_tile(floor((v - hy) / (double)th), c.tiles_y);
+  const int y1 = clamp_tile(floor((v + hy) / (double)th) + 1.0, c.tiles_y);
   if (x0 >= x1 || y0 >= y1) return r;
   r.vis = true;
-  r.u = u; r.v = v; r.A = A; r.B = B; r.C = C;
+  r.uh = (float)u;
+  r.ul = (float)(u - (double)r.uh);
+  r.vh = (float)v;
+  r.vl = (float)(v - (double)r.vh);
+  r.A = (float)A; r.B = (float)B; r.C = (float)C;
   r.x0 = x0; r.x1 = x1; r.y0 = y0; r.y1 = y1;
   return r;
 }
 
+// Per-pixel contribution test of the contract (binary32, no contraction).
+// dx = ((px + 0.5) - u_hi) - u_lo and dy likewise are formed by the caller.
 __device__ __forceinline__ float pixel_q32(float A, float B, float C, float dx, float dy) {
 #pragma clang fp contract(off)
   float t0 = dx * dx;
@@ -181,6 +194,11 @@ __device__ __forceinline__ float pixel_q32(float A, float B, float C, float dx, 
   float c = C * t1;
   float b = B * t2;
   return (a + c) + 2.0f * b;
+}
+
+__device__ __forceinline__ float pixel_offset(float pc, float hi, float lo) {
+#pragma clang fp contract(off)
+  return (pc - hi) - lo;
 }
 
 // ------------------------------------------------------------------ launchers

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Bars (from the FP32 key contract and the stated tolerances):
+Bars (from the key contract and the stated tolerances):
   * projection records, culling, tile rectangles, sort keys, surfel order and
     per-tile ranges: bit-exact;
   * rendered R, G, B, semantic logits and alpha: |delta| <= 1e-5; depth:
@@ -73,14 +73,13 @@ def test_projection_records_bitexact(gpu, name):
         gvis = cnt[v] > 0
         np.testing.assert_array_equal(gvis, vis)
         assert vis.sum() > 0
-        g = rec[v][vis][:, :6].view(np.uint32)
+        g = rec[v][vis].view(np.uint32)          # u_hi v_hi u_lo v_lo A B C t_z
         o = orec[vis].view(np.uint32)
         bad = np.nonzero((g != o).any(axis=1))[0]
         assert bad.size == 0, (v, bad[:5], rec[v][vis][bad[:3]], orec[vis][bad[:3]])
         np.testing.assert_array_equal(rect[v][vis], orect[vis])
         r = orect[vis]
         np.testing.assert_array_equal(cnt[v][vis], (r[:, 1] - r[:, 0]) * (r[:, 3] - r[:, 2]))
-        np.testing.assert_array_equal(rec[v][vis][:, 6], sc.alpha[vis])
 
 
 @pytest.mark.parametrize("name", SCENES)
@@ -145,7 +144,9 @@ def grads_compare(g_gpu, ref_flat, n, C, tol=1e-4):
         a = g_gpu[sl].reshape(ref[name].shape) if ref[name].ndim > 1 else g_gpu[sl].reshape(-1)
         r = ref[name]
         mx = np.abs(r).max()
-        assert mx > 0, name
+        if mx == 0.0:            # e.g. dL/dz under a top-down orthographic camera
+            assert np.abs(a).max() == 0.0, name
+            continue
         d = np.abs(a - r)
         assert d.max() <= tol * mx, (name, d.max() / mx)
         big = np.abs(r) >= 1e-2 * mx

@@ -137,8 +137,12 @@ def test_p2b_pinhole_covariance_numerical_jacobian():
             inv = np.linalg.inv(Sp)
             np.testing.assert_allclose(geo[i, 2:5], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=2e-7)
             np.testing.assert_allclose(geo[i, :2], proj(t), rtol=1e-12)
-            # the FP32 contract is the same projection, to FP32 rounding
-            np.testing.assert_allclose(rec[i, :5], geo[i, :5], rtol=1e-4, atol=1e-5)
+            # the contract record is the same projection rounded to binary32
+            u = np.float64(rec[i, 0]) + np.float64(rec[i, 2])
+            v = np.float64(rec[i, 1]) + np.float64(rec[i, 3])
+            np.testing.assert_allclose([u, v], geo[i, :2], rtol=1e-13)
+            np.testing.assert_allclose(rec[i, 4:7], geo[i, 2:5], rtol=2e-7)
+            np.testing.assert_allclose(rec[i, 7], geo[i, 5], rtol=1e-7)
             checked += 1
         assert checked > 5
 
@@ -270,8 +274,8 @@ def test_p6_rect_covers_every_contributing_pixel(which):
     for i in sel:
         if not vis[i]:
             continue
-        u, v, A, B, C = (np.float32(t) for t in rec[i, :5])
-        dx, dy = pxc - u, pyc - v
+        uh, vh, ul, vl, A, B, C = (np.float32(t) for t in rec[i, :7])
+        dx, dy = (pxc - uh) - ul, (pyc - vh) - vl
         q = (A * (dx * dx) + C * (dy * dy)) + np.float32(2.0) * (B * (dx * dy))
         inside = q <= np.float32(9.0)
         x0, x1, y0, y1 = rect[i]
