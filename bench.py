@@ -82,6 +82,7 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="1..4: workload (default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tile", default="16x16", help="tile shape WxH (default 16x16)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -96,7 +97,9 @@ def main():
     scene = synth.CONFIGS[args.config]()
     C = scene.n_sem
     total_steps = args.warmup + args.steps
-    st = TrainState(scene, device="cuda:0")
+    from paper_2405_14342_amd import binding as B
+    tw, th = (int(t) for t in args.tile.split("x"))
+    st = TrainState(scene, device="cuda:0", opts=B.make_opts(tile_w=tw, tile_h=th))
     print(f"[bench] {scene.name}: {scene.n} surfels, {scene.n_views} views, "
           f"{scene.npix} px/step", file=sys.stderr, flush=True)
 
@@ -160,6 +163,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded surfel grid, cameras and random targets)",
         "config": {"workload": scene.name, "surfels": scene.n, "views": scene.n_views,
+                   "tile": args.tile,
                    "pixels_per_step": scene.npix, "sem_classes": C, "path": "batched",
                    "pairs": stats["pairs"], "visible_slots": stats["visible"]},
         "plain": plain,

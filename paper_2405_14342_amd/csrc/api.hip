@@ -131,7 +131,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
   l.o_views = take(sizeof(ViewDev) * l.V);
   l.o_misc = take(sizeof(uint32_t) * kMiscCount);
-  l.o_mcount = take(sizeof(uint32_t) * l.V);
+  l.o_mcount = take(sizeof(uint32_t) * 2 * l.V);   // mask counts, then per-view loss sums
   l.o_lpart = take(sizeof(int64_t) * (l.V + 1) + sizeof(float) * 3 * loss_blocks);
   l.o_cnt = take(4 * (size_t)l.slots);
   l.o_off = take(4 * (size_t)l.slots);
@@ -371,7 +371,7 @@ int rogs_pair_count(rogs_ctx* c, void* ws, int64_t* n_pairs, int32_t* overflow, 
   int r = need_batch(c, ws, false);
   if (r != ROGS_OK) return r;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = hipMemcpyAsync(c->readback, rogs::at<void>(ws, c->L.o_misc), 8,
+  hipError_t e = hipMemcpyAsync(c->readback, rogs::at<void>(ws, c->L.o_misc), 16,
                                 hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(c, e, "rogs_pair_count");

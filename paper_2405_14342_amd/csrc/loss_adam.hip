@@ -23,43 +23,75 @@ __device__ __forceinline__ int find_view_pix(const ViewDev* __restrict__ views, 
   return lo;
 }
 
-// |M_v|: number of mask pixels per view (integer atomics: exact).
+// |M_v|: number of mask pixels per view.  grid.y = view; each block counts
+// kMaskPerBlock pixels and adds its count with one integer atomic (exact).
+constexpr int kMaskPerBlock = 16 * kLossBlock;
+
 __global__ __launch_bounds__(kLossBlock) void k_mask_count(const ViewDev* __restrict__ views,
-                                                           int V, int64_t total,
                                                            const uint8_t* __restrict__ mask,
                                                            uint32_t* __restrict__ mcount) {
-  const int64_t p = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
-  if (p >= total) return;
-  if (mask[p]) {
-    const int v = find_view_pix(views, V, p);
-    atomicAdd(&mcount[v], 1u);
+  __shared__ uint32_t s_w[kLossBlock / 64];
+  const int v = blockIdx.y;
+  const ViewDev& vw = views[v];
+  const int64_t npix = (int64_t)vw.w * vw.h;
+  const int64_t base = (int64_t)blockIdx.x * kMaskPerBlock;
+  if (base >= npix) return;
+  const uint8_t* m = mask + vw.pix_off;
+  uint32_t c = 0;
+  for (int k = threadIdx.x; k < kMaskPerBlock; k += kLossBlock) {
+    const int64_t p = base + k;
+    if (p < npix) c += m[p] ? 1u : 0u;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kLossBlock / 64; ++w) t += s_w[w];
+    if (t) atomicAdd(&mcount[v], t);
   }
 }
 
-// Sums the per-block loss partials of each view in block order.
-__global__ void k_loss_final(const ViewDev* __restrict__ views, int V,
-                             const int64_t* __restrict__ first_blk, const float* __restrict__ part,
-                             float* __restrict__ loss_out, float* __restrict__ d_exp) {
-  __shared__ float s_l[64];
-  float lsum = 0.0f;
-  for (int v = threadIdx.x; v < V; v += blockDim.x) {
-    float l = 0.0f, a = 0.0f, b = 0.0f;
-    for (int64_t k = first_blk[v]; k < first_blk[v + 1]; ++k) {
-      l += part[3 * k];
-      a += part[3 * k + 1];
-      b += part[3 * k + 2];
+// Sums the per-block loss partials of each view: one block per view, a fixed
+// assignment of partials to threads and a fixed tree, so the result does not
+// depend on scheduling.  Then block 0 of a second launch adds the views.
+__global__ __launch_bounds__(256) void k_loss_views(const int64_t* __restrict__ first_blk,
+                                                    const float* __restrict__ part,
+                                                    float* __restrict__ per_view,
+                                                    float* __restrict__ d_exp) {
+  __shared__ float s[3][256];
+  const int v = blockIdx.x;
+  float l = 0.0f, a = 0.0f, b = 0.0f;
+  for (int64_t k = first_blk[v] + threadIdx.x; k < first_blk[v + 1]; k += 256) {
+    l += part[3 * k];
+    a += part[3 * k + 1];
+    b += part[3 * k + 2];
+  }
+  s[0][threadIdx.x] = l;
+  s[1][threadIdx.x] = a;
+  s[2][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + w];
+      s[1][threadIdx.x] += s[1][threadIdx.x + w];
+      s[2][threadIdx.x] += s[2][threadIdx.x + w];
     }
-    lsum += l;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    per_view[v] = s[0][0];
     if (d_exp) {
-      d_exp[2 * v] += a;
-      d_exp[2 * v + 1] += b;
+      d_exp[2 * v] += s[1][0];
+      d_exp[2 * v + 1] += s[2][0];
     }
   }
-  s_l[threadIdx.x] = lsum;
-  __syncthreads();
-  if (threadIdx.x == 0 && loss_out) {
+}
+
+__global__ void k_loss_total(int V, const float* __restrict__ per_view, float* __restrict__ loss_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && loss_out) {
     float t = 0.0f;
-    for (int k = 0; k < (int)blockDim.x; ++k) t += s_l[k];
+    for (int v = 0; v < V; ++v) t += per_view[v];
     loss_out[0] += t;
   }
 }
@@ -395,9 +427,10 @@ void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets
                  float* loss_out, float* d_exp, hipStream_t st) {
   uint32_t* mcount = at<uint32_t>(ws, L.o_mcount);
   fill_u32(mcount, 0u, L.V, st);
-  hipLaunchKernelGGL(k_mask_count, dim3((unsigned)((L.total_pix + kLossBlock - 1) / kLossBlock)),
-                     dim3(kLossBlock), 0, st, at<const ViewDev>(ws, L.o_views), L.V, L.total_pix,
-                     t->mask, mcount);
+  hipLaunchKernelGGL(k_mask_count,
+                     dim3((unsigned)((L.max_view_pix + kMaskPerBlock - 1) / kMaskPerBlock),
+                          (unsigned)L.V),
+                     dim3(kLossBlock), 0, st, at<const ViewDev>(ws, L.o_views), t->mask, mcount);
   switch (L.C) {
     case 1: loss_launch<1>(L, ws, out, t, G, st); break;
     case 2: loss_launch<2>(L, ws, out, t, G, st); break;
@@ -410,9 +443,11 @@ void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets
     case 16: loss_launch<16>(L, ws, out, t, G, st); break;
     default: return;
   }
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, at<const ViewDev>(ws, L.o_views),
-                     L.V, at<const int64_t>(ws, L.o_lpart), at<const float>(ws, L.o_lpart) + 2 * (L.V + 1),
-                     loss_out, d_exp);
+  float* per_view = reinterpret_cast<float*>(at<uint32_t>(ws, L.o_mcount) + L.V);
+  hipLaunchKernelGGL(k_loss_views, dim3((unsigned)L.V), dim3(256), 0, st,
+                     at<const int64_t>(ws, L.o_lpart), at<const float>(ws, L.o_lpart) + 2 * (L.V + 1),
+                     per_view, d_exp);
+  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, st, L.V, per_view, loss_out);
 }
 
 void launch_proj_bwd(const Layout& L, void* ws, const rogs_surfels* s, float* grads,
