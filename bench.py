@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tile", default="16x16", help="tile shape WxH (default 16x16)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a 256 MiB device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -94,6 +96,13 @@ def main():
     from paper_2405_14342_amd.pipeline import TrainState
 
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     scene = synth.CONFIGS[args.config]()
     C = scene.n_sem
     total_steps = args.warmup + args.steps
