@@ -243,6 +243,63 @@ ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* para
                    const float* d_exposure, float* m_exp, float* v_exp, int32_t n_views,
                    void* stream);
 
+/* ------------------------------------------------------ fused step
+ * The whole training step (a1-a10) over all views of a batch in one graph:
+ * cull + projection, emission, radix sort and ranges with the pair count kept
+ * on the device, forward compositing with the loss seed fused into its
+ * epilogue (per-pixel dL/dO, G.O, T and n_last kept in a tile-major
+ * workspace record; the images themselves are not written), backward
+ * compositing, and the projection adjoint fused with Adam.  The step number
+ * lives on the device (step_state), so no host value changes between steps.
+ *
+ * The sequence is captured into a hipGraph on the first call and replayed by
+ * later calls with the same arguments (same pointers, sizes, options and
+ * view resolutions; camera poses may change: they are copied from a pinned
+ * buffer by the graph).  Each call first waits for the previous step, then
+ * launches.  If the previous step overflowed pair_capacity it made no update
+ * (parameters, moments and step count untouched) and this call returns
+ * ROGS_ECAPACITY without launching; read the needed count with
+ * rogs_fused_status, grow the workspace and call again. */
+typedef struct {
+  int32_t n, n_sem;
+  const float* x;        /* [N] fixed grid vertices */
+  const float* y;
+  float* params;         /* [11 + C][N] raw block (row layout above) */
+  float* m;              /* Adam moments, same shape */
+  float* v;
+  float* s_act;          /* [2][N] activated scales; refreshed by every step */
+  float* alpha_act;      /* [N] activated opacity; refreshed by every step */
+  float* exposure;       /* [V][2] per-view (a, b) of Eq. 7; updated by Adam */
+  float* m_exp;          /* its moments */
+  float* v_exp;
+  float* d_exposure;     /* [V][2] output: dL/d(a, b) of the last step */
+  float* grads;          /* optional [11 + C][N] output of the step's gradients, or NULL */
+  void* step_state;      /* 64 bytes of device memory, zeroed before the first step:
+                            step count, skipped steps, last loss (16-byte aligned) */
+} rogs_train_state;
+
+typedef struct {
+  rogs_lr lr;            /* per-group rates (lr.z used only when total_steps == 0) */
+  float z_start, z_end;  /* z rate at the first and at the last step, log-linear between
+                            (Sec. 4.2: proportional to the scene size) */
+  int64_t total_steps;   /* length of the z schedule; 0 = constant lr.z */
+  float beta1, beta2, eps;
+} rogs_optim;
+
+#define ROGS_FUSED_EAGER 4u   /* run the same kernels without graph capture */
+
+ROGS_API int rogs_fused_workspace_size(const rogs_train_state* t, const rogs_camera* cams,
+                                       int32_t n_views, const rogs_render_opts* opts,
+                                       int64_t pair_capacity, size_t* bytes);
+ROGS_API int rogs_step_fused(rogs_ctx* ctx, const rogs_train_state* t, const rogs_camera* cams,
+                             int32_t n_views, const rogs_render_opts* opts,
+                             const rogs_targets* targets, const rogs_optim* optim, void* ws,
+                             size_t ws_bytes, int64_t pair_capacity, uint32_t flags, void* stream);
+/* Waits for the last fused step and reports stats[0] pairs P, [1] overflow,
+ * [2] visible slots, [3] steps applied, [4] steps skipped, [5] pixels,
+ * [6] tiles, [7] slots; *loss = loss of the last applied step (nullable). */
+ROGS_API int rogs_fused_status(rogs_ctx* ctx, int64_t* stats, float* loss);
+
 /* Batch statistics (host sync): stats[0] pairs P, [1] overflow flag,
  * [2] visible (view, surfel) slots, [3] pixels, [4] tiles, [5] slots V*N. */
 ROGS_API int rogs_batch_stats(rogs_ctx* ctx, void* ws, int64_t* stats, void* stream);
@@ -251,8 +308,10 @@ ROGS_API int rogs_batch_stats(rogs_ctx* ctx, void* ws, int64_t* stats, void* str
  * bracketed by two HIP events on its stream.  rogs_prof_read waits for the
  * recorded events, returns the summed milliseconds and launch counts per group
  * (arrays of ROGS_PROF_GROUPS entries; n must be >= ROGS_PROF_GROUPS) since
- * the previous read, and resets them.  Group names: rogs_prof_name. */
-#define ROGS_PROF_GROUPS 10
+ * the previous read, and resets them.  Group names: rogs_prof_name.  In
+ * the fused step, group "fused_graph" times the whole graph launch (the
+ * kernels inside a graph carry no events; ROGS_FUSED_EAGER times them). */
+#define ROGS_PROF_GROUPS 11
 ROGS_API int rogs_prof_enable(rogs_ctx* ctx, int32_t on);
 ROGS_API int rogs_prof_read(rogs_ctx* ctx, double* ms, int64_t* launches, int32_t n);
 ROGS_API const char* rogs_prof_name(int32_t group);

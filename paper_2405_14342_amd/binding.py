@@ -28,8 +28,10 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_workspace_size", "rogs_project", "rogs_bin_sort", "rogs_pair_count",
             "rogs_render_fwd", "rogs_loss", "rogs_render_bwd", "rogs_adam_step",
             "rogs_debug_pairs", "rogs_debug_records", "rogs_batch_stats", "rogs_prof_enable",
-            "rogs_prof_read", "rogs_prof_name")
-PROF_GROUPS = 10
+            "rogs_prof_read", "rogs_prof_name", "rogs_fused_workspace_size", "rogs_step_fused",
+            "rogs_fused_status")
+PROF_GROUPS = 11
+FUSED_EAGER = 4
 
 
 class RogsError(RuntimeError):
@@ -73,6 +75,19 @@ class LR(ctypes.Structure):
                 ("exposure", ctypes.c_float)]
 
 
+class TrainStateC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_sem", ctypes.c_int32), ("x", _vp), ("y", _vp),
+                ("params", _vp), ("m", _vp), ("v", _vp), ("s_act", _vp), ("alpha_act", _vp),
+                ("exposure", _vp), ("m_exp", _vp), ("v_exp", _vp), ("d_exposure", _vp),
+                ("grads", _vp), ("step_state", _vp)]
+
+
+class Optim(ctypes.Structure):
+    _fields_ = [("lr", LR), ("z_start", ctypes.c_float), ("z_end", ctypes.c_float),
+                ("total_steps", ctypes.c_int64), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -106,6 +121,13 @@ def load_library(path: str = LIB_PATH):
             "rogs_prof_enable": ([P, I32], I32),
             "rogs_prof_read": ([P, P, P, I32], I32),
             "rogs_prof_name": ([I32], ctypes.c_char_p),
+            "rogs_fused_workspace_size": ([ctypes.POINTER(TrainStateC), ctypes.POINTER(Camera), I32,
+                                           ctypes.POINTER(RenderOpts), I64,
+                                           ctypes.POINTER(ctypes.c_size_t)], I32),
+            "rogs_step_fused": ([P, ctypes.POINTER(TrainStateC), ctypes.POINTER(Camera), I32,
+                                 ctypes.POINTER(RenderOpts), ctypes.POINTER(Targets),
+                                 ctypes.POINTER(Optim), P, ctypes.c_size_t, I64, U32, P], I32),
+            "rogs_fused_status": ([P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -159,6 +181,18 @@ def default_opts() -> RenderOpts:
 
 def make_opts(tile_w=16, tile_h=16, eps2d=0.3, q_cut=9.0, alpha_max=0.99, t_eps=1e-6) -> RenderOpts:
     return RenderOpts(tile_w, tile_h, eps2d, q_cut, alpha_max, t_eps)
+
+
+def fused_workspace_size(ts: TrainStateC, cams, opts: RenderOpts, pair_capacity: int) -> int:
+    """rogs_fused_workspace_size (host-only)."""
+    L = load_library()
+    arr = camera_array(cams)
+    out = ctypes.c_size_t(0)
+    r = L.rogs_fused_workspace_size(ctypes.byref(ts), arr, len(cams), ctypes.byref(opts),
+                                    int(pair_capacity), ctypes.byref(out))
+    if r != OK:
+        raise RogsError(r, "rogs_fused_workspace_size rejected its arguments")
+    return int(out.value)
 
 
 def workspace_size(surf: Surfels, cams, opts: RenderOpts, pair_capacity: int) -> int:
@@ -271,6 +305,28 @@ class Rogs:
                     "rogs_prof_read")
         return {self.L.rogs_prof_name(k).decode(): (float(ms[k]), int(n[k]))
                 for k in range(PROF_GROUPS)}
+
+    def step_fused(self, ts: "TrainStateC", cams, opts: RenderOpts, targets: Targets,
+                   optim: Optim, ws, pair_capacity: int, flags: int = 0, stream=None,
+                   raise_on_capacity=True) -> int:
+        arr = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
+        r = self.L.rogs_step_fused(self.h, ctypes.byref(ts), arr, len(arr), ctypes.byref(opts),
+                                   ctypes.byref(targets), ctypes.byref(optim), ptr(ws),
+                                   ws.numel() * ws.element_size(), int(pair_capacity), flags,
+                                   _stream(stream))
+        if r == ECAPACITY and not raise_on_capacity:
+            return r
+        self._check(r, "rogs_step_fused")
+        return r
+
+    def fused_status(self) -> dict:
+        st = np.zeros(8, np.int64)
+        loss = ctypes.c_float(0.0)
+        self._check(self.L.rogs_fused_status(self.h, st.ctypes.data, ctypes.byref(loss)),
+                    "rogs_fused_status")
+        return dict(pairs=int(st[0]), overflow=int(st[1]), visible=int(st[2]), step=int(st[3]),
+                    skipped=int(st[4]), pixels=int(st[5]), tiles=int(st[6]), slots=int(st[7]),
+                    loss=float(loss.value))
 
     def debug_pairs(self, ws, cap: int, n_tiles: int, stream=None):
         keys = np.zeros(max(cap, 1), np.uint64)

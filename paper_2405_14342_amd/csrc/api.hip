@@ -36,6 +36,27 @@ struct rogs_ctx {
   hipEvent_t open_ev = nullptr;
   double prof_ms[ROGS_PROF_GROUPS] = {};
   int64_t prof_n[ROGS_PROF_GROUPS] = {};
+  // fused step: the captured graph and what it was captured for
+  struct Fused {
+    bool valid = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Layout L;
+    int alt = 0;
+    void* ws = nullptr;
+    hipStream_t st = nullptr;
+    uint32_t flags = 0;
+    rogs_train_state ts{};
+    rogs_targets tg{};
+    rogs_optim opt{};
+    rogs_render_opts opts{};
+    std::vector<int32_t> sizes;         // w, h, model of every view
+    void* stage = nullptr;               // pinned: view table + first-block table
+    size_t stage_bytes = 0;
+    uint32_t* status = nullptr;          // pinned: misc[4] + StepState
+    hipEvent_t done = nullptr;
+    bool pending = false;
+  } fz;
 };
 
 namespace {
@@ -64,7 +85,8 @@ bool is_fin(float x) { return isfinite(x); }
 namespace rogs {
 
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
-                const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why) {
+                const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why,
+                bool fused) {
   *why = nullptr;
   if (!s || !cams || !opts || !L) { *why = "null argument"; return ROGS_EINVAL; }
   if (s->n < 1) { *why = "surfel count must be >= 1"; return ROGS_EINVAL; }
@@ -151,6 +173,11 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_gpair = take(4 * (size_t)cap * l.GS);
   l.o_hist = take(4 * (size_t)kRadix * l.sort_blocks);
   l.o_histtmp = take(4 * scan_tmp_words((int64_t)kRadix * l.sort_blocks));
+  if (fused) {
+    const size_t nch = (size_t)(6 + l.C), tp = (size_t)tw * th;
+    l.o_tm = take(4 * (size_t)l.total_tiles * nch * tp);
+    l.o_tpart = take(4 * 3 * (size_t)l.total_tiles);
+  }
   l.total = o;
   *L = l;
   return ROGS_OK;
@@ -160,25 +187,12 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
 
 namespace {
 
-int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws, hipStream_t st) {
+// Writes the device view table and the per-view first loss-block table of a
+// batch into host memory at dst (sizeof(ViewDev) * V + 8 * (V + 1) bytes).
+void fill_view_table(const Layout& L, const rogs_camera* cams, void* dst) {
   const size_t vbytes = sizeof(ViewDev) * L.V;
-  const size_t fbytes = sizeof(int64_t) * (L.V + 1);
-  const size_t need = vbytes + fbytes;
-  if (c->stage_pending) {
-    hipError_t e = hipEventSynchronize(c->stage_evt);
-    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-    c->stage_pending = false;
-  }
-  if (c->stage_bytes < need) {
-    if (c->stage) (void)hipHostFree(c->stage);
-    c->stage = nullptr;
-    c->stage_bytes = 0;
-    hipError_t e = hipHostMalloc(&c->stage, need, hipHostMallocDefault);
-    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
-    c->stage_bytes = need;
-  }
-  ViewDev* vt = static_cast<ViewDev*>(c->stage);
-  int64_t* fb = reinterpret_cast<int64_t*>(static_cast<char*>(c->stage) + vbytes);
+  ViewDev* vt = static_cast<ViewDev*>(dst);
+  int64_t* fb = reinterpret_cast<int64_t*>(static_cast<char*>(dst) + vbytes);
   int64_t pix = 0, tiles = 0, blk = 0;
   for (int v = 0; v < L.V; ++v) {
     const rogs_camera& k = cams[v];
@@ -204,9 +218,30 @@ int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws
     blk += ((int64_t)k.w * k.h + 255) / 256;
   }
   fb[L.V] = blk;
-  hipError_t e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), vt, vbytes, hipMemcpyHostToDevice, st);
+}
+
+int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws, hipStream_t st) {
+  const size_t vbytes = sizeof(ViewDev) * L.V;
+  const size_t fbytes = sizeof(int64_t) * (L.V + 1);
+  const size_t need = vbytes + fbytes;
+  if (c->stage_pending) {
+    hipError_t e = hipEventSynchronize(c->stage_evt);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    c->stage_pending = false;
+  }
+  if (c->stage_bytes < need) {
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    hipError_t e = hipHostMalloc(&c->stage, need, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+    c->stage_bytes = need;
+  }
+  fill_view_table(L, cams, c->stage);
+  const char* base = static_cast<const char*>(c->stage);
+  hipError_t e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), base, vbytes, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), fb, fbytes, hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), base + vbytes, fbytes, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventRecord(c->stage_evt, st);
   if (e != hipSuccess) return hip_fail(c, e, "view table upload");
   c->stage_pending = true;
@@ -216,7 +251,7 @@ int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws
 const char* kProfNames[ROGS_PROF_GROUPS] = {"project",    "scan",       "emit",
                                             "sort",       "ranges",     "render_fwd",
                                             "loss",       "render_bwd", "proj_bwd",
-                                            "adam"};
+                                            "adam",       "fused_graph"};
 
 hipEvent_t prof_event(rogs_ctx* c) {
   if (c->ev_used == c->ev_pool.size()) {
@@ -301,6 +336,12 @@ int rogs_create(rogs_ctx** ctx) {
 
 void rogs_destroy(rogs_ctx* c) {
   if (!c) return;
+  if (c->fz.pending) (void)hipEventSynchronize(c->fz.done);
+  if (c->fz.exec) (void)hipGraphExecDestroy(c->fz.exec);
+  if (c->fz.graph) (void)hipGraphDestroy(c->fz.graph);
+  if (c->fz.stage) (void)hipHostFree(c->fz.stage);
+  if (c->fz.status) (void)hipHostFree(c->fz.status);
+  if (c->fz.done) (void)hipEventDestroy(c->fz.done);
   if (!c->recs.empty()) (void)hipEventSynchronize(c->recs.back().b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->stage_pending) (void)hipEventSynchronize(c->stage_evt);
@@ -593,6 +634,282 @@ int rogs_debug_records(rogs_ctx* c, void* ws, float* rec, int32_t* rect, uint32_
     rect[4 * k + 2] = (int32_t)(rc[2 * k + 1] & 0xffff);
     rect[4 * k + 3] = (int32_t)(rc[2 * k + 1] >> 16);
   }
+  return ROGS_OK;
+}
+
+// ------------------------------------------------------------ fused step
+
+namespace {
+
+bool same_bytes(const void* a, const void* b, size_t n) { return memcmp(a, b, n) == 0; }
+
+rogs_surfels fused_surfels(const rogs_train_state* t) {
+  rogs_surfels s;
+  const size_t N = (size_t)t->n;
+  s.n = t->n;
+  s.n_sem = t->n_sem;
+  s.x = t->x;
+  s.y = t->y;
+  s.z = t->params;
+  s.q = t->params + N;
+  s.s = t->s_act;
+  s.alpha = t->alpha_act;
+  s.rgb = t->params + 8 * N;
+  s.sem = t->params + 11 * N;
+  return s;
+}
+
+int check_fused_args(rogs_ctx* c, const rogs_train_state* t, const rogs_targets* tg,
+                     const rogs_optim* o) {
+  if (!t || !tg || !o) return fail(c, ROGS_EINVAL, "null argument");
+  if (!t->x || !t->y || !t->params || !t->m || !t->v || !t->s_act || !t->alpha_act ||
+      !t->exposure || !t->m_exp || !t->v_exp || !t->d_exposure || !t->step_state)
+    return fail(c, ROGS_EINVAL, "a training-state pointer is null");
+  if (reinterpret_cast<uintptr_t>(t->step_state) % 16 != 0)
+    return fail(c, ROGS_EINVAL, "step_state must be 16-byte aligned");
+  if (!tg->rgb || !tg->label || !tg->mask || tg->exposure != t->exposure)
+    return fail(c, ROGS_EINVAL, "targets incomplete, or targets.exposure differs from the state's");
+  if (!(o->beta1 >= 0.0f && o->beta1 < 1.0f) || !(o->beta2 >= 0.0f && o->beta2 < 1.0f) ||
+      !(o->eps > 0.0f) || o->total_steps < 0 || !is_fin(o->z_start) || !is_fin(o->z_end) ||
+      (o->total_steps > 1 && !(o->z_start > 0.0f && o->z_end > 0.0f)))
+    return fail(c, ROGS_EINVAL, "optimizer settings out of range");
+  return ROGS_OK;
+}
+
+rogs::AdamArgs fused_adam_args(const rogs_optim* o, const Layout& L, void* ws, const void* state) {
+  rogs::AdamArgs aa{};
+  aa.lr = o->lr;
+  aa.b1 = o->beta1;
+  aa.b2 = o->beta2;
+  aa.eps = o->eps;
+  aa.z_start = o->z_start;
+  aa.z_end = o->z_end;
+  aa.total_steps = o->total_steps;
+  aa.step = 0;
+  aa.state = static_cast<const rogs::StepState*>(state);
+  aa.misc = rogs::at<const uint32_t>(ws, L.o_misc);
+  return aa;
+}
+
+// The whole step on one stream; captured once into a graph or run eagerly.
+// Returns the sort's buffer parity.
+int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs_targets* tg,
+                   const rogs_optim* o, void* ws, hipStream_t st) {
+  auto& F = c->fz;
+  const size_t vbytes = sizeof(ViewDev) * L.V, fbytes = sizeof(int64_t) * (L.V + 1);
+  const char* stage = static_cast<const char*>(F.stage);
+  (void)hipMemcpyAsync(rogs::at<void>(ws, L.o_views), stage, vbytes, hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), stage + vbytes, fbytes, hipMemcpyHostToDevice, st);
+  rogs_surfels s = fused_surfels(t);
+  prof_begin(c, 0, st);
+  rogs::launch_project(L, ws, &s, true, st);
+  prof_end(c, st);
+  prof_begin(c, 1, st);
+  rogs::launch_scan_part(L, ws, st);
+  prof_end(c, st);
+  prof_begin(c, 2, st);
+  rogs::launch_emit(L, ws, st);
+  prof_end(c, st);
+  prof_begin(c, 3, st);
+  int alt = rogs::launch_sort(L, ws, -1, st);
+  prof_end(c, st);
+  if (alt) {
+    std::swap(L.o_keys, L.o_keys2);
+    std::swap(L.o_vals, L.o_vals2);
+  }
+  prof_begin(c, 4, st);
+  rogs::launch_ranges(L, ws, -1, st);
+  prof_end(c, st);
+  prof_begin(c, 6, st);
+  rogs::launch_mask_count(L, ws, tg->mask, st);
+  prof_end(c, st);
+  rogs::FusedLoss fl;
+  fl.tgt = tg->rgb;
+  fl.label = tg->label;
+  fl.mask = tg->mask;
+  fl.expo = tg->exposure;
+  fl.mcount = rogs::at<const uint32_t>(ws, L.o_mcount);
+  fl.lam_c = tg->lambda_c;
+  fl.lam_s = tg->lambda_s;
+  fl.scale = tg->view_scale;
+  fl.tm = rogs::at<float>(ws, L.o_tm);
+  fl.part = rogs::at<float>(ws, L.o_tpart);
+  prof_begin(c, 5, st);
+  int r = rogs::launch_render_fwd_fused(L, ws, fl, st);
+  prof_end(c, st);
+  if (r != 0) return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
+  prof_begin(c, 7, st);
+  rogs::launch_render_bwd_fused(L, ws, st);
+  prof_end(c, st);
+  prof_begin(c, 6, st);
+  rogs::launch_loss_tiles(L, ws, t->d_exposure, st);
+  prof_end(c, st);
+  rogs::AdamArgs aa = fused_adam_args(o, L, ws, t->step_state);
+  prof_begin(c, 8, st);
+  rogs::launch_proj_bwd_adam(L, ws, t->x, t->y, t->params, t->m, t->v, t->s_act, t->alpha_act,
+                             t->grads, aa, t->exposure, t->d_exposure, t->m_exp, t->v_exp, st);
+  prof_end(c, st);
+  rogs::launch_step_end(L, ws, static_cast<rogs::StepState*>(t->step_state), aa, st);
+  (void)hipMemcpyAsync(F.status, rogs::at<void>(ws, L.o_misc), 16, hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(reinterpret_cast<char*>(F.status) + 16, t->step_state,
+                       sizeof(rogs::StepState), hipMemcpyDeviceToHost, st);
+  return ROGS_OK;
+}
+
+}  // namespace
+
+int rogs_fused_workspace_size(const rogs_train_state* t, const rogs_camera* cams, int32_t n_views,
+                              const rogs_render_opts* opts, int64_t pair_capacity, size_t* bytes) {
+  if (!t || !bytes) return ROGS_EINVAL;
+  rogs_surfels s = fused_surfels(t);
+  Layout L;
+  const char* why = nullptr;
+  int r = rogs::make_layout(&s, cams, n_views, opts, pair_capacity, &L, &why, true);
+  if (r != ROGS_OK) return r;
+  *bytes = L.total;
+  return ROGS_OK;
+}
+
+int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* cams,
+                    int32_t n_views, const rogs_render_opts* opts, const rogs_targets* tg,
+                    const rogs_optim* o, void* ws, size_t ws_bytes, int64_t pair_capacity,
+                    uint32_t flags, void* stream) {
+  if (!c) return ROGS_EINVAL;
+  int r = check_fused_args(c, t, tg, o);
+  if (r != ROGS_OK) return r;
+  rogs_surfels s = fused_surfels(t);
+  Layout L;
+  const char* why = nullptr;
+  r = rogs::make_layout(&s, cams, n_views, opts, pair_capacity, &L, &why, true);
+  if (r != ROGS_OK) return fail(c, r, why ? why : "invalid argument");
+  if (!ws) return fail(c, ROGS_EINVAL, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, ROGS_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(c, ROGS_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto& F = c->fz;
+  hipError_t e = hipSuccess;
+  if (!F.done) {
+    e = hipEventCreateWithFlags(&F.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&F.status, 128, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused setup");
+    memset(F.status, 0, 128);
+  }
+  // the previous step must have finished before its status is read and the
+  // pinned camera table is rewritten
+  if (F.pending) {
+    e = hipEventSynchronize(F.done);
+    if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused");
+    F.pending = false;
+    if (F.status[rogs::kMiscOverflow])
+      return fail(c, ROGS_ECAPACITY, "the previous fused step overflowed the pair capacity (" +
+                                         std::to_string(F.status[rogs::kMiscPairs]) +
+                                         " pairs) and was skipped");
+  }
+  std::vector<int32_t> sizes;
+  for (int v = 0; v < n_views; ++v) {
+    sizes.push_back(cams[v].w);
+    sizes.push_back(cams[v].h);
+    sizes.push_back(cams[v].model);
+  }
+  const bool eager = (flags & ROGS_FUSED_EAGER) != 0;
+  const bool same = F.valid && F.ws == ws && F.st == st && F.flags == flags &&
+                    same_bytes(&F.ts, t, sizeof(*t)) && same_bytes(&F.tg, tg, sizeof(*tg)) &&
+                    same_bytes(&F.opt, o, sizeof(*o)) && same_bytes(&F.opts, opts, sizeof(*opts)) &&
+                    F.sizes == sizes && F.L.total == L.total && F.L.cap == L.cap;
+  const size_t need = sizeof(ViewDev) * L.V + sizeof(int64_t) * (L.V + 1);
+  if (!same) {
+    if (F.exec) (void)hipGraphExecDestroy(F.exec);
+    if (F.graph) (void)hipGraphDestroy(F.graph);
+    F.exec = nullptr;
+    F.graph = nullptr;
+    F.valid = false;
+    if (F.stage_bytes < need) {
+      if (F.stage) (void)hipHostFree(F.stage);
+      F.stage = nullptr;
+      F.stage_bytes = 0;
+      e = hipHostMalloc(&F.stage, need, hipHostMallocDefault);
+      if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+      F.stage_bytes = need;
+    }
+  }
+  fill_view_table(L, cams, F.stage);
+  if (eager) {
+    Layout Lr = L;
+    r = fused_sequence(c, Lr, t, tg, o, ws, st);
+    if (r != ROGS_OK) return r;
+    r = check_launch(c, "rogs_step_fused");
+    if (r != ROGS_OK) return r;
+    F.L = Lr;
+  } else {
+    if (!same) {
+      Layout Lr = L;
+      e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+      const bool prof = c->prof;
+      c->prof = false;                 // no timing events inside the graph
+      r = fused_sequence(c, Lr, t, tg, o, ws, st);
+      c->prof = prof;
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(st, &g);
+      if (r != ROGS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+      }
+      if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&F.exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(c, e, "hipGraphInstantiate");
+      }
+      F.graph = g;
+      F.L = Lr;
+    }
+    prof_begin(c, 10, st);
+    e = hipGraphLaunch(F.exec, st);
+    prof_end(c, st);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+  }
+  F.valid = true;
+  F.ws = ws;
+  F.st = st;
+  F.flags = flags;
+  F.ts = *t;
+  F.tg = *tg;
+  F.opt = *o;
+  F.opts = *opts;
+  F.sizes = sizes;
+  e = hipEventRecord(F.done, st);
+  if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+  F.pending = true;
+  // the batch state of the plain entry points no longer describes the workspace
+  if (c->ws == ws) {
+    c->have_batch = false;
+    c->sorted = false;
+  }
+  return ROGS_OK;
+}
+
+int rogs_fused_status(rogs_ctx* c, int64_t* stats, float* loss) {
+  if (!c) return ROGS_EINVAL;
+  if (!stats) return fail(c, ROGS_EINVAL, "stats is null");
+  auto& F = c->fz;
+  if (!F.status) return fail(c, ROGS_ESTATE, "no fused step has run");
+  if (F.pending) {
+    hipError_t e = hipEventSynchronize(F.done);
+    if (e != hipSuccess) return hip_fail(c, e, "rogs_fused_status");
+  }
+  const rogs::StepState* ss = reinterpret_cast<const rogs::StepState*>(
+      reinterpret_cast<const char*>(F.status) + 16);
+  stats[0] = F.status[rogs::kMiscPairs];
+  stats[1] = F.status[rogs::kMiscOverflow];
+  stats[2] = F.status[rogs::kMiscVisible];
+  stats[3] = ss->step;
+  stats[4] = ss->skipped;
+  stats[5] = F.L.total_pix;
+  stats[6] = F.L.total_tiles;
+  stats[7] = F.L.slots;
+  if (loss) *loss = ss->loss;
   return ROGS_OK;
 }
 

@@ -213,19 +213,67 @@ __device__ __forceinline__ void proj_adjoint(const ViewDev& c, float eps, float 
   dq[3] += (dc - cc * dot) * iq;
 }
 
+// Bias corrections of Adam for a step (same arithmetic on every path).
+__device__ __forceinline__ void adam_bias(float b1, float b2, int64_t step, float& bc1,
+                                          float& bc2s) {
+  bc1 = (float)(1.0 - pow((double)b1, (double)step));
+  bc2s = (float)sqrt(1.0 - pow((double)b2, (double)step));
+}
+
+// z learning rate of a step: z_start (z_end / z_start)^t, t = (step-1)/(total-1).
+__device__ __forceinline__ float z_rate(const AdamArgs& aa, int64_t step) {
+  if (aa.total_steps <= 1) return aa.total_steps == 1 ? aa.z_start : aa.lr.z;
+  double t = (double)(step - 1) / (double)(aa.total_steps - 1);
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  return (float)((double)aa.z_start * pow((double)aa.z_end / (double)aa.z_start, t));
+}
+
+// Adam (torch semantics) on the 11 + C rows of surfel i, with the chain rule
+// through s = exp(log s) and alpha = sigmoid(logit); refreshes s and alpha.
 template <int C>
-__global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
-    const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
-    const float* __restrict__ py, const float* __restrict__ pz, const float* __restrict__ pq,
-    const float* __restrict__ ps, const uint32_t* __restrict__ cnt,
-    const uint32_t* __restrict__ off, const float* __restrict__ gpair, int GS, int64_t cap,
-    float* __restrict__ grads, int accumulate) {
+__device__ __forceinline__ void adam_surfel(int i, size_t N, float* __restrict__ P,
+                                            float* __restrict__ M, float* __restrict__ Vv,
+                                            float* __restrict__ s_act, float* __restrict__ a_act,
+                                            const float* g, const rogs_lr& lr, float lr_z,
+                                            float b1, float b2, float eps, float bc1,
+                                            float bc2s) {
+  const float sx = s_act[i], sy = s_act[N + i], al = a_act[i];
+#pragma unroll
+  for (int r = 0; r < 11 + C; ++r) {
+    const size_t j = r * N + i;
+    float gr = g[r];
+    float lrr;
+    if (r == 0) lrr = lr_z;
+    else if (r <= 4) lrr = lr.q;
+    else if (r <= 6) { lrr = lr.s; gr *= (r == 5) ? sx : sy; }      // d/d log s = s d/ds
+    else if (r == 7) { lrr = lr.alpha; gr *= al * (1.0f - al); }   // d/d logit = a(1-a) d/da
+    else if (r <= 10) lrr = lr.rgb;
+    else lrr = lr.sem;
+    const float m = b1 * M[j] + (1.0f - b1) * gr;
+    const float v = b2 * Vv[j] + (1.0f - b2) * gr * gr;
+    M[j] = m;
+    Vv[j] = v;
+    const float denom = sqrtf(v) / bc2s + eps;
+    P[j] -= (lrr / bc1) * (m / denom);
+  }
+  s_act[i] = expf(P[5 * N + i]);
+  s_act[N + i] = expf(P[6 * N + i]);
+  a_act[i] = 1.0f / (1.0f + expf(-P[7 * N + i]));
+}
+
+// Projection adjoint of surfel i summed over the batch's views: the per-pair
+// gradient records of each visible (view, surfel) slot are summed, chained
+// through the projection of that view and accumulated.  vals[11 + C]: dL/d
+// (z, q, s, alpha, rgb, sem) w.r.t. the activated values.
+template <int C>
+__device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ views, int V,
+                                             int N, float eps, float x, float y, float z,
+                                             const float q[4], float sx, float sy,
+                                             const uint32_t* __restrict__ cnt,
+                                             const uint32_t* __restrict__ off,
+                                             const float* __restrict__ gpair, int GS, int64_t cap,
+                                             float* vals) {
   constexpr int NV = 10 + C;
-  const int i = blockIdx.x * kProjBlock + threadIdx.x;
-  if (i >= N) return;
-  const float x = px[i], y = py[i], z = pz[i];
-  const float q[4] = {pq[i], pq[N + i], pq[2 * (size_t)N + i], pq[3 * (size_t)N + i]};
-  const float sx = ps[i], sy = ps[N + i];
   float dz = 0.0f, dq[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsx = 0.0f, dsy = 0.0f, dal = 0.0f;
   float dft[3 + C];
 #pragma unroll
@@ -259,18 +307,62 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
 #pragma unroll
     for (int c = 0; c < 3 + C; ++c) dft[c] += rg[7 + c];
   }
-  const size_t Nn = (size_t)N;
-  float vals[11 + C];
   vals[0] = dz;
   vals[1] = dq[0]; vals[2] = dq[1]; vals[3] = dq[2]; vals[4] = dq[3];
   vals[5] = dsx; vals[6] = dsy; vals[7] = dal;
 #pragma unroll
   for (int c = 0; c < 3 + C; ++c) vals[8 + c] = dft[c];
+}
+
+template <int C>
+__global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
+    const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
+    const float* __restrict__ py, const float* __restrict__ pz, const float* __restrict__ pq,
+    const float* __restrict__ ps, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ off, const float* __restrict__ gpair, int GS, int64_t cap,
+    float* __restrict__ grads, int accumulate) {
+  const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  if (i >= N) return;
+  const float q[4] = {pq[i], pq[N + i], pq[2 * (size_t)N + i], pq[3 * (size_t)N + i]};
+  float vals[11 + C];
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], cnt, off, gpair,
+                  GS, cap, vals);
+  const size_t Nn = (size_t)N;
 #pragma unroll
   for (int r = 0; r < 11 + C; ++r) {
     float* g = grads + r * Nn + i;
     *g = accumulate ? (*g + vals[r]) : vals[r];
   }
+}
+
+// Fused: projection adjoint + Adam of each surfel (the parameters read for
+// the adjoint are the ones the forward used; each thread updates only its own
+// surfel after reading it).
+template <int C>
+__global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
+    const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
+    const float* __restrict__ py, float* __restrict__ P, float* __restrict__ M,
+    float* __restrict__ Vv, float* __restrict__ s_act, float* __restrict__ a_act,
+    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ off,
+    const float* __restrict__ gpair, int GS, int64_t cap, float* __restrict__ grads_out,
+    AdamArgs aa) {
+  const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  if (i >= N) return;
+  if (aa.misc[kMiscOverflow]) return;
+  const size_t Nn = (size_t)N;
+  const float q[4] = {P[Nn + i], P[2 * Nn + i], P[3 * Nn + i], P[4 * Nn + i]};
+  float vals[11 + C];
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], cnt, off,
+                  gpair, GS, cap, vals);
+  if (grads_out) {
+#pragma unroll
+    for (int r = 0; r < 11 + C; ++r) grads_out[r * Nn + i] = vals[r];
+  }
+  const int64_t step = aa.state->step + 1;
+  float bc1, bc2s;
+  adam_bias(aa.b1, aa.b2, step, bc1, bc2s);
+  adam_surfel<C>(i, Nn, P, M, Vv, s_act, a_act, vals, aa.lr, z_rate(aa, step), aa.b1, aa.b2,
+                 aa.eps, bc1, bc2s);
 }
 
 template <int C>
@@ -306,47 +398,18 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_v(
     const float* o = out + (size_t)NO * vw.pix_off + q;
     float* g = G + (size_t)NO * vw.pix_off + q;
     const int64_t p = vw.pix_off + q;
-    const uint32_t mc = mcount[v];
     float gv[NO];
 #pragma unroll
     for (int c = 0; c < NO; ++c) gv[c] = 0.0f;
-    if (mask[p] && mc > 0) {
-      const float wc = lam_c * scale / (float)mc;
-      const float ws = lam_s * scale / (float)mc;
-      const float a = expo[2 * v], b = expo[2 * v + 1];
-      const float ea = expf(a);
+    const LossView lv = loss_view(expo, mcount, v, lam_c, lam_s, scale);
+    if (mask[p] && lv.any) {
+      float ov[3 + C], tv[3];
+#pragma unroll
+      for (int c = 0; c < 3 + C; ++c) ov[c] = o[c * HW];
       const float* t = tgt + 3 * (size_t)vw.pix_off + q;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float cc = o[c * HW];
-        const float r = (ea * cc + b) - t[c * HW];
-        const float sg = (r > 0.0f) ? 1.0f : ((r < 0.0f) ? -1.0f : 0.0f);
-        l += wc * fabsf(r);
-        gv[c] = wc * sg * ea;
-        da += wc * sg * ea * cc;
-        db += wc * sg;
-      }
-      float sv[C], ov[C];
-      float mx = -INFINITY;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        ov[c] = o[(3 + c) * HW];
-        mx = fmaxf(mx, ov[c]);
-      }
-      float se = 0.0f;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        sv[c] = expf(ov[c] - mx);
-        se += sv[c];
-      }
-      const int lb = label[p];
-      float olb = 0.0f;
-#pragma unroll
-      for (int c = 0; c < C; ++c) olb = (c == lb) ? ov[c] : olb;
-      l += ws * ((mx + logf(se)) - olb);
-      const float inv = 1.0f / se;
-#pragma unroll
-      for (int c = 0; c < C; ++c) gv[3 + c] = ws * (sv[c] * inv - ((c == lb) ? 1.0f : 0.0f));
+      for (int c = 0; c < 3; ++c) tv[c] = t[c * HW];
+      pixel_loss<C>(ov, tv, label[p], lv.wc, lv.ws, lv.ea, lv.b, gv, l, da, db);
     }
 #pragma unroll
     for (int c = 0; c < NO; ++c) g[c * HW] = gv[c];
@@ -377,60 +440,101 @@ void loss_launch(const Layout& L, void* ws, const float* out, const rogs_targets
 
 // ------------------------------------------------------------ Adam
 
-__global__ __launch_bounds__(256) void k_adam(int N, int K, float* __restrict__ P,
+template <int C>
+__global__ __launch_bounds__(256) void k_adam(int N, float* __restrict__ P,
                                               const float* __restrict__ Gd, float* __restrict__ M,
                                               float* __restrict__ Vv, float* __restrict__ s_act,
-                                              float* __restrict__ a_act, rogs_lr lr, float b1,
-                                              float b2, float eps, float bc1, float bc2s) {
+                                              float* __restrict__ a_act, AdamArgs aa) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
   const size_t Nn = (size_t)N;
-  const float sx = s_act[i], sy = s_act[Nn + i], al = a_act[i];
-  for (int r = 0; r < K; ++r) {
-    const size_t j = r * Nn + i;
-    float g = Gd[j];
-    float lrr;
-    if (r == 0) lrr = lr.z;
-    else if (r <= 4) lrr = lr.q;
-    else if (r <= 6) { lrr = lr.s; g *= (r == 5) ? sx : sy; }        // d/d log s = s d/ds
-    else if (r == 7) { lrr = lr.alpha; g *= al * (1.0f - al); }     // d/d logit = a(1-a) d/da
-    else if (r <= 10) lrr = lr.rgb;
-    else lrr = lr.sem;
-    const float m = b1 * M[j] + (1.0f - b1) * g;
-    const float v = b2 * Vv[j] + (1.0f - b2) * g * g;
-    M[j] = m;
-    Vv[j] = v;
-    const float denom = sqrtf(v) / bc2s + eps;
-    P[j] -= (lrr / bc1) * (m / denom);
-  }
-  s_act[i] = expf(P[5 * Nn + i]);
-  s_act[Nn + i] = expf(P[6 * Nn + i]);
-  a_act[i] = 1.0f / (1.0f + expf(-P[7 * Nn + i]));
+  float g[11 + C];
+#pragma unroll
+  for (int r = 0; r < 11 + C; ++r) g[r] = Gd[r * Nn + i];
+  float bc1, bc2s;
+  adam_bias(aa.b1, aa.b2, aa.step, bc1, bc2s);
+  adam_surfel<C>(i, Nn, P, M, Vv, s_act, a_act, g, aa.lr, z_rate(aa, aa.step), aa.b1, aa.b2,
+                 aa.eps, bc1, bc2s);
 }
 
+// Adam on a plain array (the per-view exposure (a, b)).  With a step state
+// the step comes from the device and an overflow skips the update.
 __global__ void k_adam_plain(int n, float* __restrict__ P, const float* __restrict__ Gd,
-                             float* __restrict__ M, float* __restrict__ Vv, float lr, float b1,
-                             float b2, float eps, float bc1, float bc2s) {
+                             float* __restrict__ M, float* __restrict__ Vv, AdamArgs aa) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (aa.misc && aa.misc[kMiscOverflow]) return;
+  const int64_t step = aa.state ? aa.state->step + 1 : aa.step;
+  float bc1, bc2s;
+  adam_bias(aa.b1, aa.b2, step, bc1, bc2s);
   const float g = Gd[i];
-  const float m = b1 * M[i] + (1.0f - b1) * g;
-  const float v = b2 * Vv[i] + (1.0f - b2) * g * g;
+  const float m = aa.b1 * M[i] + (1.0f - aa.b1) * g;
+  const float v = aa.b2 * Vv[i] + (1.0f - aa.b2) * g * g;
   M[i] = m;
   Vv[i] = v;
-  P[i] -= (lr / bc1) * (m / (sqrtf(v) / bc2s + eps));
+  P[i] -= (aa.lr.exposure / bc1) * (m / (sqrtf(v) / bc2s + aa.eps));
+}
+
+// Per-view sums of the per-tile loss partials of the fused forward: fixed
+// assignment of tiles to threads and a fixed tree (deterministic).  dL/d(a,b)
+// are overwritten.
+__global__ __launch_bounds__(256) void k_loss_tiles(const ViewDev* __restrict__ views, int V,
+                                                    int64_t total_tiles,
+                                                    const float* __restrict__ part,
+                                                    float* __restrict__ per_view,
+                                                    float* __restrict__ d_exp) {
+  __shared__ float s[3][256];
+  const int v = blockIdx.x;
+  const int64_t t0 = views[v].tile_off;
+  const int64_t t1 = (v + 1 < V) ? views[v + 1].tile_off : total_tiles;
+  float l = 0.0f, a = 0.0f, b = 0.0f;
+  for (int64_t k = t0 + threadIdx.x; k < t1; k += 256) {
+    l += part[3 * k];
+    a += part[3 * k + 1];
+    b += part[3 * k + 2];
+  }
+  s[0][threadIdx.x] = l;
+  s[1][threadIdx.x] = a;
+  s[2][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + w];
+      s[1][threadIdx.x] += s[1][threadIdx.x + w];
+      s[2][threadIdx.x] += s[2][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    per_view[v] = s[0][0];
+    if (d_exp) {
+      d_exp[2 * v] = s[1][0];
+      d_exp[2 * v + 1] = s[2][0];
+    }
+  }
+}
+
+// Closes a fused step: counts it (or its skip on overflow) and keeps its loss.
+__global__ void k_step_end(StepState* __restrict__ st, const uint32_t* __restrict__ misc,
+                           const float* __restrict__ per_view, int V, AdamArgs aa) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (misc[kMiscOverflow]) {
+    st->skipped += 1;
+    return;
+  }
+  float t = 0.0f;
+  for (int v = 0; v < V; ++v) t += per_view[v];
+  const int64_t step = st->step + 1;
+  st->lr_z = z_rate(aa, step);
+  st->loss = t;
+  st->step = step;
 }
 
 }  // namespace
 
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,
                  float* loss_out, float* d_exp, hipStream_t st) {
-  uint32_t* mcount = at<uint32_t>(ws, L.o_mcount);
-  fill_u32(mcount, 0u, L.V, st);
-  hipLaunchKernelGGL(k_mask_count,
-                     dim3((unsigned)((L.max_view_pix + kMaskPerBlock - 1) / kMaskPerBlock),
-                          (unsigned)L.V),
-                     dim3(kLossBlock), 0, st, at<const ViewDev>(ws, L.o_views), t->mask, mcount);
+  launch_mask_count(L, ws, t->mask, st);
   switch (L.C) {
     case 1: loss_launch<1>(L, ws, out, t, G, st); break;
     case 2: loss_launch<2>(L, ws, out, t, G, st); break;
@@ -466,18 +570,90 @@ void launch_proj_bwd(const Layout& L, void* ws, const rogs_surfels* s, float* gr
   }
 }
 
+namespace {
+template <int C>
+void adam_launch(int n, float* params, const float* grads, float* m, float* v, float* s_act,
+                 float* a_act, const AdamArgs& aa, hipStream_t st) {
+  hipLaunchKernelGGL((k_adam<C>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, params,
+                     grads, m, v, s_act, a_act, aa);
+}
+
+template <int C>
+void proj_bwd_adam_launch(const Layout& L, void* ws, const float* x, const float* y,
+                          float* params, float* m, float* v, float* s_act, float* a_act,
+                          float* grads_out, const AdamArgs& aa, hipStream_t st) {
+  hipLaunchKernelGGL((k_proj_bwd_adam<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, x, y, params, m, v,
+                     s_act, a_act, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_off),
+                     at<const float>(ws, L.o_gpair), L.GS, L.cap, grads_out, aa);
+}
+}  // namespace
+
+#define ROGS_SEM_SWITCH(C_, CALL)      \
+  switch (C_) {                        \
+    case 1: { constexpr int KC = 1; CALL; } break;   \
+    case 2: { constexpr int KC = 2; CALL; } break;   \
+    case 3: { constexpr int KC = 3; CALL; } break;   \
+    case 4: { constexpr int KC = 4; CALL; } break;   \
+    case 5: { constexpr int KC = 5; CALL; } break;   \
+    case 6: { constexpr int KC = 6; CALL; } break;   \
+    case 7: { constexpr int KC = 7; CALL; } break;   \
+    case 8: { constexpr int KC = 8; CALL; } break;   \
+    case 16: { constexpr int KC = 16; CALL; } break; \
+    default: break;                    \
+  }
+
 void launch_adam(int n, int C, float* params, const float* grads, float* m, float* v,
                  float* s_act, float* a_act, const rogs_lr* lr, int64_t step, float b1, float b2,
                  float eps, float* expo, const float* dexpo, float* me, float* ve, int nv,
                  hipStream_t st) {
-  const double bc1 = 1.0 - pow((double)b1, (double)step);
-  const double bc2 = 1.0 - pow((double)b2, (double)step);
-  const float bc2s = (float)sqrt(bc2);
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, 11 + C,
-                     params, grads, m, v, s_act, a_act, *lr, b1, b2, eps, (float)bc1, bc2s);
+  AdamArgs aa{};
+  aa.lr = *lr;
+  aa.b1 = b1;
+  aa.b2 = b2;
+  aa.eps = eps;
+  aa.total_steps = 0;
+  aa.step = step;
+  aa.state = nullptr;
+  aa.misc = nullptr;
+  ROGS_SEM_SWITCH(C, (adam_launch<KC>(n, params, grads, m, v, s_act, a_act, aa, st)));
   if (expo && nv > 0)
     hipLaunchKernelGGL(k_adam_plain, dim3((unsigned)((2 * nv + 63) / 64)), dim3(64), 0, st, 2 * nv,
-                       expo, dexpo, me, ve, lr->exposure, b1, b2, eps, (float)bc1, bc2s);
+                       expo, dexpo, me, ve, aa);
+}
+
+void launch_proj_bwd_adam(const Layout& L, void* ws, const float* x, const float* y, float* params,
+                          float* m, float* v, float* s_act, float* a_act, float* grads_out,
+                          const AdamArgs& aa, float* expo, const float* dexpo, float* me,
+                          float* ve, hipStream_t st) {
+  ROGS_SEM_SWITCH(L.C, (proj_bwd_adam_launch<KC>(L, ws, x, y, params, m, v, s_act, a_act,
+                                                  grads_out, aa, st)));
+  if (expo)
+    hipLaunchKernelGGL(k_adam_plain, dim3((unsigned)((2 * L.V + 63) / 64)), dim3(64), 0, st,
+                       2 * L.V, expo, dexpo, me, ve, aa);
+}
+
+void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st) {
+  float* per_view = reinterpret_cast<float*>(at<uint32_t>(ws, L.o_mcount) + L.V);
+  hipLaunchKernelGGL(k_loss_tiles, dim3((unsigned)L.V), dim3(256), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.total_tiles,
+                     at<const float>(ws, L.o_tpart), per_view, d_exp);
+}
+
+void launch_mask_count(const Layout& L, void* ws, const uint8_t* mask, hipStream_t st) {
+  uint32_t* mcount = at<uint32_t>(ws, L.o_mcount);
+  fill_u32(mcount, 0u, L.V, st);
+  hipLaunchKernelGGL(k_mask_count,
+                     dim3((unsigned)((L.max_view_pix + kMaskPerBlock - 1) / kMaskPerBlock),
+                          (unsigned)L.V),
+                     dim3(kLossBlock), 0, st, at<const ViewDev>(ws, L.o_views), mask, mcount);
+}
+
+void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs& aa,
+                     hipStream_t st) {
+  const float* per_view = reinterpret_cast<const float*>(at<uint32_t>(ws, L.o_mcount) + L.V);
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, state, at<const uint32_t>(ws, L.o_misc),
+                     per_view, L.V, aa);
 }
 
 }  // namespace rogs

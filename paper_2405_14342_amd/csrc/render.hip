@@ -118,13 +118,19 @@ __device__ __forceinline__ float wave_reduce_scatter(const float* v, int lane) {
 }
 static_assert(rs_comp(0, 18) == 0 && rs_comp(63, 18) == -1, "reduce-scatter map");
 
-template <int C, int PPL>
+// Tile-major per-pixel record of the fused path: channel ch of in-tile pixel
+// p of global tile gt is at tm[(gt * NCH + ch) * (64 * PPL) + p], with NCH =
+// 3 + C gradients, then G.O, T_final and n_last (as bits).
+template <int C>
+__host__ __device__ constexpr int fused_channels() { return 3 + C + 3; }
+
+template <int C, int PPL, bool FUSED>
 __global__ __launch_bounds__(64) void k_render_fwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
     float teps, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
     const float4* __restrict__ feat, float* __restrict__ out, float* __restrict__ tfin,
-    uint32_t* __restrict__ nlast) {
+    uint32_t* __restrict__ nlast, FusedLoss fl) {
   constexpr int F = 3 + C;            // composited features besides depth
   constexpr int FS4 = (F + 4) / 4;    // float4 per feature record (features, alpha)
   constexpr int NO = 5 + C;           // output channels
@@ -207,29 +213,81 @@ __global__ __launch_bounds__(64) void k_render_fwd(
     }
     __syncthreads();
   }
-  const size_t HW = (size_t)W * H;
-  float* o = out + (size_t)NO * vw.pix_off;
+  if constexpr (!FUSED) {
+    const size_t HW = (size_t)W * H;
+    float* o = out + (size_t)NO * vw.pix_off;
 #pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const int py = py0 + k * rows;
-    if (!(px < W && py < H)) continue;
-    const size_t p = (size_t)py * W + px;
+    for (int k = 0; k < PPL; ++k) {
+      const int py = py0 + k * rows;
+      if (!(px < W && py < H)) continue;
+      const size_t p = (size_t)py * W + px;
 #pragma unroll
-    for (int f = 0; f <= F; ++f) o[f * HW + p] = acc[k][f];
-    o[(F + 1) * HW + p] = 1.0f - T[k];
-    tfin[vw.pix_off + p] = T[k];
-    nlast[vw.pix_off + p] = (T[k] < teps) ? nl[k] : len;
+      for (int f = 0; f <= F; ++f) o[f * HW + p] = acc[k][f];
+      o[(F + 1) * HW + p] = 1.0f - T[k];
+      tfin[vw.pix_off + p] = T[k];
+      nlast[vw.pix_off + p] = (T[k] < teps) ? nl[k] : len;
+    }
+  } else {
+    // loss epilogue: dL/dO, G.O, T and n_last per pixel in the tile-major
+    // record, and this tile's share of the loss and of dL/d(a, b)
+    constexpr int NCH = fused_channels<C>();
+    constexpr int TP = 64 * PPL;
+    const LossView lv = loss_view(fl.expo, fl.mcount, v, fl.lam_c, fl.lam_s, fl.scale);
+    float* tm = fl.tm + (size_t)gt * NCH * TP;
+    float l = 0.0f, dal = 0.0f, dbl = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      const int py = py0 + k * rows;
+      const int pt = lane + 64 * k;
+      float g[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) g[f] = 0.0f;
+      float go = 0.0f, tf = 1.0f;
+      uint32_t nlk = 0;
+      if (px < W && py < H) {
+        const size_t p = (size_t)py * W + px;
+        if (fl.mask[vw.pix_off + p] && lv.any) {
+          const float* t = fl.tgt + 3 * (size_t)vw.pix_off + p;
+          const size_t HW = (size_t)W * H;
+          const float tv[3] = {t[0], t[HW], t[2 * HW]};
+          pixel_loss<C>(acc[k], tv, fl.label[vw.pix_off + p], lv.wc, lv.ws, lv.ea, lv.b, g, l,
+                        dal, dbl);
+        }
+        // G.O over the composited channels; the depth row of G is zero
+        const float gd = 0.0f;
+#pragma unroll
+        for (int f = 0; f < F; ++f) go += g[f] * acc[k][f];
+        go += gd * acc[k][F];
+        tf = T[k];
+        nlk = (T[k] < teps) ? nl[k] : len;
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f) tm[f * TP + pt] = g[f];
+      tm[F * TP + pt] = go;
+      tm[(F + 1) * TP + pt] = tf;
+      tm[(F + 2) * TP + pt] = __uint_as_float(nlk);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      l += __shfl_xor(l, o, 64);
+      dal += __shfl_xor(dal, o, 64);
+      dbl += __shfl_xor(dbl, o, 64);
+    }
+    if (lane == 0) {
+      fl.part[3 * (size_t)gt] = l;
+      fl.part[3 * (size_t)gt + 1] = dal;
+      fl.part[3 * (size_t)gt + 2] = dbl;
+    }
   }
 }
 
-template <int C, int PPL>
+template <int C, int PPL, bool FUSED>
 __global__ __launch_bounds__(64) void k_render_bwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
     const float4* __restrict__ feat, const float* __restrict__ out, const float* __restrict__ G,
     const float* __restrict__ tfin, const uint32_t* __restrict__ nlast, float* __restrict__ gpair,
-    int GS) {
+    int GS, const float* __restrict__ tm_in) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
@@ -266,7 +324,18 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     nl[k] = 0;
 #pragma unroll
     for (int f = 0; f < F + 2; ++f) Gv[k][f] = 0.0f;
-    if (px < W && py < H) {
+    if constexpr (FUSED) {
+      // tile-major record written by the fused forward (zeros off-image)
+      constexpr int NCH = fused_channels<C>();
+      constexpr int TP = 64 * PPL;
+      const float* tm = tm_in + (size_t)gt * NCH * TP + lane + 64 * k;
+#pragma unroll
+      for (int f = 0; f < F; ++f) Gv[k][f] = tm[f * TP];
+      GO[k] = tm[F * TP];
+      Tf[k] = tm[(F + 1) * TP];
+      nl[k] = __float_as_uint(tm[(F + 2) * TP]);
+      maxn = max(maxn, nl[k]);
+    } else if (px < W && py < H) {
       const size_t p = (size_t)py * W + px;
       const float* g = G + (size_t)NO * vw.pix_off + p;
       const float* o = out + (size_t)NO * vw.pix_off + p;
@@ -360,49 +429,62 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   }
 }
 
-template <int C, int PPL>
-void fwd_launch(const Layout& L, void* ws, float* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_render_fwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+template <int C, int PPL, bool FUSED>
+void fwd_launch(const Layout& L, void* ws, float* out, const FusedLoss& fl, hipStream_t st) {
+  hipLaunchKernelGGL((k_render_fwd<C, PPL, FUSED>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
                      L.t_eps, at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
                      at<const float4>(ws, L.o_feat), out, at<float>(ws, L.o_tfin),
-                     at<uint32_t>(ws, L.o_nlast));
+                     at<uint32_t>(ws, L.o_nlast), fl);
 }
 
-template <int C, int PPL>
+template <int C, int PPL, bool FUSED>
 void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hipStream_t st) {
-  hipLaunchKernelGGL((k_render_bwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+  hipLaunchKernelGGL((k_render_bwd<C, PPL, FUSED>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
                      at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
                      at<const float4>(ws, L.o_feat), out, G, at<const float>(ws, L.o_tfin),
-                     at<const uint32_t>(ws, L.o_nlast), at<float>(ws, L.o_gpair), L.GS);
+                     at<const uint32_t>(ws, L.o_nlast), at<float>(ws, L.o_gpair), L.GS,
+                     FUSED ? at<const float>(ws, L.o_tm) : nullptr);
+}
+
+template <int C, int PPL>
+void launch_one(const Layout& L, void* ws, const float* out, const float* G, float* outw,
+                const FusedLoss* fl, bool bwd, hipStream_t st) {
+  if (bwd) {
+    if (fl) bwd_launch<C, PPL, true>(L, ws, out, G, st);
+    else bwd_launch<C, PPL, false>(L, ws, out, G, st);
+  } else {
+    if (fl) fwd_launch<C, PPL, true>(L, ws, outw, *fl, st);
+    else fwd_launch<C, PPL, false>(L, ws, outw, FusedLoss{}, st);
+  }
 }
 
 template <int C>
 int dispatch_ppl(const Layout& L, void* ws, const float* out, const float* G, float* outw,
-                 bool bwd, hipStream_t st) {
+                 const FusedLoss* fl, bool bwd, hipStream_t st) {
   switch (L.ppl) {
-    case 1: bwd ? bwd_launch<C, 1>(L, ws, out, G, st) : fwd_launch<C, 1>(L, ws, outw, st); return 0;
-    case 2: bwd ? bwd_launch<C, 2>(L, ws, out, G, st) : fwd_launch<C, 2>(L, ws, outw, st); return 0;
-    case 4: bwd ? bwd_launch<C, 4>(L, ws, out, G, st) : fwd_launch<C, 4>(L, ws, outw, st); return 0;
+    case 1: launch_one<C, 1>(L, ws, out, G, outw, fl, bwd, st); return 0;
+    case 2: launch_one<C, 2>(L, ws, out, G, outw, fl, bwd, st); return 0;
+    case 4: launch_one<C, 4>(L, ws, out, G, outw, fl, bwd, st); return 0;
     default: return -1;
   }
 }
 
-int dispatch(const Layout& L, void* ws, const float* out, const float* G, float* outw, bool bwd,
-             hipStream_t st) {
+int dispatch(const Layout& L, void* ws, const float* out, const float* G, float* outw,
+             const FusedLoss* fl, bool bwd, hipStream_t st) {
   switch (L.C) {
-    case 1: return dispatch_ppl<1>(L, ws, out, G, outw, bwd, st);
-    case 2: return dispatch_ppl<2>(L, ws, out, G, outw, bwd, st);
-    case 3: return dispatch_ppl<3>(L, ws, out, G, outw, bwd, st);
-    case 4: return dispatch_ppl<4>(L, ws, out, G, outw, bwd, st);
-    case 5: return dispatch_ppl<5>(L, ws, out, G, outw, bwd, st);
-    case 6: return dispatch_ppl<6>(L, ws, out, G, outw, bwd, st);
-    case 7: return dispatch_ppl<7>(L, ws, out, G, outw, bwd, st);
-    case 8: return dispatch_ppl<8>(L, ws, out, G, outw, bwd, st);
-    case 16: return dispatch_ppl<16>(L, ws, out, G, outw, bwd, st);
+    case 1: return dispatch_ppl<1>(L, ws, out, G, outw, fl, bwd, st);
+    case 2: return dispatch_ppl<2>(L, ws, out, G, outw, fl, bwd, st);
+    case 3: return dispatch_ppl<3>(L, ws, out, G, outw, fl, bwd, st);
+    case 4: return dispatch_ppl<4>(L, ws, out, G, outw, fl, bwd, st);
+    case 5: return dispatch_ppl<5>(L, ws, out, G, outw, fl, bwd, st);
+    case 6: return dispatch_ppl<6>(L, ws, out, G, outw, fl, bwd, st);
+    case 7: return dispatch_ppl<7>(L, ws, out, G, outw, fl, bwd, st);
+    case 8: return dispatch_ppl<8>(L, ws, out, G, outw, fl, bwd, st);
+    case 16: return dispatch_ppl<16>(L, ws, out, G, outw, fl, bwd, st);
     default: return -1;
   }
 }
@@ -411,13 +493,24 @@ int dispatch(const Layout& L, void* ws, const float* out, const float* G, float*
 
 int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels*, float* out, hipStream_t st) {
   if (L.total_tiles <= 0) return 0;
-  return dispatch(L, ws, nullptr, nullptr, out, false, st);
+  return dispatch(L, ws, nullptr, nullptr, out, nullptr, false, st);
 }
 
 int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels*, const float* out,
                       const float* G, hipStream_t st) {
   if (L.total_tiles <= 0) return 0;
-  return dispatch(L, ws, out, G, nullptr, true, st);
+  return dispatch(L, ws, out, G, nullptr, nullptr, true, st);
+}
+
+int launch_render_fwd_fused(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st) {
+  if (L.total_tiles <= 0) return 0;
+  return dispatch(L, ws, nullptr, nullptr, nullptr, &fl, false, st);
+}
+
+int launch_render_bwd_fused(const Layout& L, void* ws, hipStream_t st) {
+  if (L.total_tiles <= 0) return 0;
+  FusedLoss dummy{};
+  return dispatch(L, ws, nullptr, nullptr, nullptr, &dummy, true, st);
 }
 
 }  // namespace rogs

@@ -52,6 +52,7 @@ struct Layout {
   size_t o_views, o_cnt, o_off, o_rec, o_rect, o_feat, o_part, o_parttmp;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_hist, o_histtmp, o_misc, o_lpart, o_mcount;
+  size_t o_tm = 0, o_tpart = 0, o_state = 0;    // fused path only (0 = absent)
   size_t total = 0;
 };
 
@@ -59,7 +60,8 @@ struct Layout {
 enum MiscSlot { kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscCount = 16 };
 
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
-                const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why);
+                const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why,
+                bool fused = false);
 
 template <typename T>
 __host__ __device__ inline T* at(void* ws, size_t off) {
@@ -201,6 +203,98 @@ __device__ __forceinline__ float pixel_offset(float pc, float hi, float lo) {
   return (pc - hi) - lo;
 }
 
+// ------------------------------------------------------------------ loss seed
+
+// Per-pixel loss of Eq. 7-9 and 12 for one masked pixel.  o: the composited
+// R, G, B and C semantic logits; t: the target colour.  wc, ws: lambda_c and
+// lambda_s times the view scale over |M_v|; ea = e^a, b: the view's exposure.
+// Writes dL/d(o) into g (3 + C values) and adds the pixel's loss and its
+// dL/da, dL/db to l, da, db.  Shared by the stand-alone loss kernel and the
+// fused forward epilogue so that both produce identical bits.
+template <int C>
+__device__ __forceinline__ void pixel_loss(const float* o, const float* t, int label, float wc,
+                                           float ws, float ea, float b, float* g, float& l,
+                                           float& da, float& db) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float cc = o[c];
+    const float r = (ea * cc + b) - t[c];
+    const float sg = (r > 0.0f) ? 1.0f : ((r < 0.0f) ? -1.0f : 0.0f);
+    l += wc * fabsf(r);
+    g[c] = wc * sg * ea;
+    da += wc * sg * ea * cc;
+    db += wc * sg;
+  }
+  float sv[C];
+  float mx = -INFINITY;
+#pragma unroll
+  for (int c = 0; c < C; ++c) mx = fmaxf(mx, o[3 + c]);
+  float se = 0.0f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    sv[c] = expf(o[3 + c] - mx);
+    se += sv[c];
+  }
+  float olb = 0.0f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) olb = (c == label) ? o[3 + c] : olb;
+  l += ws * ((mx + logf(se)) - olb);
+  const float inv = 1.0f / se;
+#pragma unroll
+  for (int c = 0; c < C; ++c) g[3 + c] = ws * (sv[c] * inv - ((c == label) ? 1.0f : 0.0f));
+}
+
+// Per-view loss constants (uniform over a view).
+struct LossView {
+  float wc, ws, ea, b;
+  bool any;
+};
+
+__device__ __forceinline__ LossView loss_view(const float* expo, const uint32_t* mcount, int v,
+                                              float lam_c, float lam_s, float scale) {
+  LossView r;
+  const uint32_t mc = mcount[v];
+  r.any = mc > 0;
+  r.wc = r.any ? lam_c * scale / (float)mc : 0.0f;
+  r.ws = r.any ? lam_s * scale / (float)mc : 0.0f;
+  r.ea = expf(expo[2 * v]);
+  r.b = expo[2 * v + 1];
+  return r;
+}
+
+// Inputs of the loss fused into the forward epilogue.
+struct FusedLoss {
+  const float* tgt;        // target colour, 3 planes per view
+  const uint8_t* label;
+  const uint8_t* mask;
+  const float* expo;       // [V][2]
+  const uint32_t* mcount;  // |M_v|
+  float lam_c, lam_s, scale;
+  float* tm;               // tile-major per-pixel records: dL/dO (3 + C), G.O, T, n_last
+  float* part;             // per-tile (loss, dL/da, dL/db)
+};
+
+// Device-resident state of the fused step (caller-owned, 64 bytes, zeroed by
+// the caller before the first step).
+struct StepState {
+  int64_t step;      // Adam steps applied
+  int64_t skipped;   // steps skipped because the pair capacity overflowed
+  float loss;        // loss of the last applied step
+  float lr_z;        // z learning rate of the last applied step
+  float pad[10];
+};
+static_assert(sizeof(StepState) == 64, "step state is 64 bytes");
+
+struct AdamArgs {
+  rogs_lr lr;                 // lr.z used as is unless a schedule is given
+  float b1, b2, eps;
+  float z_start, z_end;       // log-linear z schedule (fused path)
+  int64_t total_steps;        // 0: no schedule, use lr.z
+  int64_t step;               // step number of this update (>= 1); ignored with state
+  const StepState* state;     // fused path: step = state->step + 1
+  const uint32_t* misc;       // fused path: skip the update on overflow
+};
+
 // ------------------------------------------------------------------ launchers
 
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
@@ -214,12 +308,25 @@ void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets
                  float* loss_out, float* d_exp, hipStream_t st);
 int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels* s, const float* out,
                       const float* G, hipStream_t st);
+int launch_render_fwd_fused(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st);
+int launch_render_bwd_fused(const Layout& L, void* ws, hipStream_t st);
 void launch_proj_bwd(const Layout& L, void* ws, const rogs_surfels* s, float* grads,
                      bool accumulate, hipStream_t st);
 void launch_adam(int n, int C, float* params, const float* grads, float* m, float* v,
                  float* s_act, float* a_act, const rogs_lr* lr, int64_t step, float b1, float b2,
                  float eps, float* expo, const float* dexpo, float* me, float* ve, int nv,
                  hipStream_t st);
+// Fused: projection adjoint of every surfel followed by its Adam update (and
+// the exposure update); optional gradient output.  Skipped on overflow.
+void launch_proj_bwd_adam(const Layout& L, void* ws, const float* x, const float* y, float* params,
+                          float* m, float* v, float* s_act, float* a_act, float* grads_out,
+                          const AdamArgs& aa, float* expo, const float* dexpo, float* me,
+                          float* ve, hipStream_t st);
+// Fused: per-view loss and dL/d(a, b) (overwritten) from the per-tile partials.
+void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st);
+void launch_mask_count(const Layout& L, void* ws, const uint8_t* mask, hipStream_t st);
+void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs& aa,
+                     hipStream_t st);
 // Exclusive scan of n uint32 values; total written to *total (device) if non-null.
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
               hipStream_t st);

@@ -8,6 +8,9 @@ librogs through :mod:`binding`.  Two sequences are provided:
   then one Adam step: the plain per-view path.
 * :meth:`TrainState.step_batched` - all views of the step in one batch, the
   pair count kept on the device.
+* :meth:`TrainState.step_fused` - the batched step with the loss fused into
+  the forward and Adam into the projection adjoint, captured once as a
+  hipGraph and replayed.
 """
 from __future__ import annotations
 
@@ -29,14 +32,25 @@ LR_Z_START, LR_Z_END = 1.6e-4, 1.6e-6      # times the scene size
 
 def z_learning_rate(extent: float, step: int, total_steps: int) -> float:
     """z learning rate: proportional to the scene size, decaying log-linearly
-    from 1.6e-4 to 1.6e-6 of it over the run (Sec. 4.2)."""
-    t = 0.0 if total_steps <= 1 else min(max((step - 1) / (total_steps - 1), 0.0), 1.0)
-    return extent * math.exp(math.log(LR_Z_START) * (1.0 - t) + math.log(LR_Z_END) * t)
+    from 1.6e-4 to 1.6e-6 of it over the run (Sec. 4.2).  Same expression as
+    the fused step's device schedule: z_start (z_end / z_start)^t."""
+    z0 = float(np.float32(extent * LR_Z_START))
+    z1 = float(np.float32(extent * LR_Z_END))
+    if total_steps <= 1:
+        return z0
+    t = min(max((step - 1) / (total_steps - 1), 0.0), 1.0)
+    return z0 * (z1 / z0) ** t
 
 
 def paper_lr(extent: float, step: int = 1, total_steps: int = 1) -> B.LR:
     return B.LR(z_learning_rate(extent, step, total_steps), LR_ROT, LR_SCALE, LR_ALPHA, LR_RGB,
                 LR_SEM, LR_EXPOSURE)
+
+
+def paper_optim(extent: float, total_steps: int) -> B.Optim:
+    """Optimizer settings of Sec. 4.2 with the device-side z schedule."""
+    return B.Optim(paper_lr(extent), float(np.float32(extent * LR_Z_START)),
+                   float(np.float32(extent * LR_Z_END)), int(total_steps), 0.9, 0.999, 1e-8)
 
 
 def n_out(C: int) -> int:
@@ -186,6 +200,53 @@ class TrainState:
                           self.alpha_act, lr, self.step_count, exposure=self.exposure,
                           d_exposure=self.d_exp, m_exp=self.m_exp, v_exp=self.v_exp,
                           n_views=self.V)
+
+    # ------------------------------------------------------------ fused
+    def train_state(self, grads_out: bool = False) -> B.TrainStateC:
+        if not hasattr(self, "step_state"):
+            self.step_state = torch.zeros(16, dtype=torch.int32, device=self.dev)
+        P = self.params
+        return B.TrainStateC(self.N, self.C, self.x.data_ptr(), self.y.data_ptr(), P.data_ptr(),
+                             self.m.data_ptr(), self.v.data_ptr(), self.s_act.data_ptr(),
+                             self.alpha_act.data_ptr(), self.exposure.data_ptr(),
+                             self.m_exp.data_ptr(), self.v_exp.data_ptr(), self.d_exp.data_ptr(),
+                             self.grads.data_ptr() if grads_out else None,
+                             self.step_state.data_ptr())
+
+    def step_fused(self, total_steps: int = 1, eager: bool = False, grads_out: bool = False,
+                   check: bool = True):
+        """One training step as one captured graph (or the same kernels eagerly).
+
+        With check=True the call waits for the step and, if it overflowed the
+        pair capacity (the device then skips the update), grows the capacity
+        and runs the step again.  With check=False the call returns right
+        after the launch; an overflow is then reported by the next call, which
+        grows the capacity before launching its own step."""
+        ts = self.train_state(grads_out)
+        optim = paper_optim(self.scene.extent, total_steps)
+        flags = B.FUSED_EAGER if eager else 0
+        if not hasattr(self, "cap_fused"):
+            self.cap_fused = self.cap_batch
+        for _ in range(8):
+            size = B.fused_workspace_size(ts, self.cams, self.opts, self.cap_fused)
+            if getattr(self, "_ws_fused", None) is None or self._ws_fused.numel() < size:
+                self._ws_fused = torch.empty(size, dtype=torch.uint8, device=self.dev)
+            r = self.rg.step_fused(ts, self.cams, self.opts, self.targets(0, self.V), optim,
+                                   self._ws_fused, self.cap_fused, flags, raise_on_capacity=False)
+            if r == B.ECAPACITY:
+                self.cap_fused = int(self.rg.fused_status()["pairs"] * 1.25) + 4096
+                continue
+            if not check:
+                return
+            st = self.rg.fused_status()
+            if not st["overflow"]:
+                return
+            self.cap_fused = int(st["pairs"] * 1.25) + 4096
+        raise RuntimeError("pair capacity did not converge")
+
+    def fused_status(self) -> dict:
+        """Waits for the last fused step and returns its statistics."""
+        return self.rg.fused_status()
 
     def render_all_plain(self):
         for v in range(self.V):

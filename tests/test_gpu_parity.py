@@ -285,3 +285,73 @@ def test_invalid_calls_raise(gpu):
     with pytest.raises(B.RogsError) as e:
         st.rg.project(bad, st.cams, st.opts, ws, 1000)
     assert e.value.code == B.EINVAL
+
+
+# ------------------------------------------------------------------ fused step
+
+def _snapshot(st):
+    return {k: getattr(st, k).detach().cpu().clone() for k in
+            ("params", "m", "v", "s_act", "alpha_act", "exposure", "m_exp", "v_exp")}
+
+
+@pytest.mark.parametrize("name,eager", [("c1", True), ("c1", False), ("mini", False),
+                                        ("mini16", False)])
+def test_fused_step_equals_batched_plus_adam(gpu, name, eager):
+    sc = make_scene(name)
+    a = TrainState(sc)
+    a.step_batched(total_steps=5)
+    b = TrainState(sc)
+    b.step_fused(total_steps=5, eager=eager, grads_out=True)
+    torch.cuda.synchronize()
+    sa, sb = _snapshot(a), _snapshot(b)
+    # surfel parameters and moments: same per-pixel loss seed and the same
+    # gradient records, so the same bits
+    for k in ("params", "m", "v", "s_act", "alpha_act"):
+        assert torch.equal(sa[k], sb[k]), k
+    assert torch.equal(a.grads.cpu(), b.grads.cpu())
+    # the per-view sums of dL/d(a, b) and of the loss group pixels differently
+    np.testing.assert_allclose(b.d_exp.cpu().numpy(), a.d_exp.cpu().numpy(), rtol=1e-5, atol=1e-7)
+    for k in ("exposure", "m_exp", "v_exp"):
+        np.testing.assert_allclose(sb[k].numpy(), sa[k].numpy(), rtol=1e-4, atol=1e-9)
+    stf = b.fused_status()
+    assert stf["step"] == 1 and stf["skipped"] == 0 and stf["overflow"] == 0
+    assert abs(stf["loss"] - a.loss.item()) <= 1e-5 * abs(a.loss.item())
+
+
+def test_fused_graph_replays_match_eager(gpu):
+    sc = make_scene("mini")
+    a = TrainState(sc)
+    b = TrainState(sc)
+    for _ in range(3):
+        a.step_fused(total_steps=3, eager=True)
+        b.step_fused(total_steps=3, eager=False, check=False)
+        torch.cuda.synchronize()          # eager work between the replays
+        assert torch.equal(a.params, b.params)
+    sa, sb = a.fused_status(), b.fused_status()
+    assert sa["step"] == sb["step"] == 3
+    for k in ("params", "m", "v", "s_act", "alpha_act"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+
+
+def test_fused_overflow_skips_update_and_recovers(gpu):
+    sc = make_scene("c1")
+    st = TrainState(sc, pair_capacity=256)
+    before = st.params.clone()
+    ts = st.train_state()
+    from paper_2405_14342_amd.pipeline import paper_optim
+    optim = paper_optim(sc.extent, 1)
+    size = B.fused_workspace_size(ts, st.cams, st.opts, 256)
+    ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+    st.rg.step_fused(ts, st.cams, st.opts, st.targets(0, st.V), optim, ws, 256)
+    s1 = st.rg.fused_status()
+    assert s1["overflow"] == 1 and s1["step"] == 0 and s1["skipped"] == 1
+    assert s1["pairs"] > 256
+    assert torch.equal(st.params, before)             # no update on overflow
+    r = st.rg.step_fused(ts, st.cams, st.opts, st.targets(0, st.V), optim, ws, 256,
+                         raise_on_capacity=False)
+    assert r == B.ECAPACITY
+    st.cap_fused = 256
+    st.step_fused(total_steps=1)                      # grows and runs the step
+    s2 = st.fused_status()
+    assert s2["step"] == 1 and s2["overflow"] == 0
+    assert not torch.equal(st.params, before)
