@@ -7,9 +7,12 @@ seed, backward compositing, projection adjoint, and the Adam update.
 
 Default workload: 200,000 surfels (1000 x 200 grid at 0.1 m along a curved
 trajectory, 8 semantic classes) seen by six 1600 x 900 surround cameras.
-Two paths are timed on the same workload: "batched" (all views of the step in
-one launch sequence, pair count kept on the device) and "plain" (one launch
-sequence per view with a host read-back of the pair count).
+The headline is the fused step (loss fused into the forward, Adam into the
+projection adjoint, the whole step one replayed hipGraph).  On the same
+workload it also times the same kernels launched one by one (each bracketed
+by HIP events: the per-kernel breakdown), the batched path (all views in one
+launch sequence) and the plain path (one launch sequence per view with a host
+read-back of the pair count).
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -26,27 +29,41 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 
 
-def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int) -> float:
-    """Compulsory HBM bytes of one launch group of one step."""
+def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) -> float:
+    """Compulsory HBM bytes of one launch group of one step.
+    P pairs, S visible (view, surfel) slots, X pixels, N surfels, V views."""
     N, V = st.N, st.V
-    P, vis, pix, slots = stats["pairs"], stats["visible"], stats["pixels"], stats["slots"]
+    P, S, X, slots = stats["pairs"], stats["visible"], stats["pixels"], stats["slots"]
     FS = ((4 + C) + 3) // 4 * 4
+    NCH = 6 + C                       # fused per-pixel record: dL/dO (3+C), G.O, T, n_last
+    K = 11 + C
     if kernel == "project":
-        return N * (40 + 4 * FS) + slots * 4 + vis * 40
+        return N * (40 + 4 * FS) + slots * 4 + S * 40
     if kernel == "emit":
-        return slots * 8 + vis * 40 + P * 16
+        return slots * 8 + S * 40 + P * 16
     if kernel == "sort":
         return passes * P * 32
+    if kernel == "ranges":
+        return P * 8 + stats["tiles"] * 8
     if kernel == "render_fwd":
-        return pix * ((5 + C) * 4 + 8) + P * 8 + vis * (32 + 4 * FS)
+        if fused:   # + targets (12 B colour, label, mask) in, the record out
+            return X * (14 + NCH * 4) + P * 8 + S * (32 + 4 * FS)
+        return X * ((5 + C) * 4 + 8) + P * 8 + S * (32 + 4 * FS)
     if kernel == "loss":
-        return pix * ((3 + C) * 4 + 14 + 1 + (5 + C) * 4)
+        if fused:   # mask count + per-view sums of the per-tile partials
+            return X * 1 + stats["tiles"] * 12
+        return X * ((3 + C) * 4 + 14 + 1 + (5 + C) * 4)
     if kernel == "render_bwd":
-        return pix * ((5 + C) * 4 + (4 + C) * 4 + 8) + P * (8 + 4 * (10 + C)) + vis * (32 + 4 * FS)
+        if fused:
+            return X * NCH * 4 + P * (8 + 4 * (10 + C)) + S * (32 + 4 * FS)
+        return X * ((5 + C) * 4 + (4 + C) * 4 + 8) + P * (8 + 4 * (10 + C)) + S * (32 + 4 * FS)
     if kernel == "proj_bwd":
-        return slots * 4 + vis * 4 + P * 4 * (10 + C) + N * (40 + 4 * (11 + C))
+        base = slots * 4 + S * 4 + P * 4 * (10 + C) + N * (40 + 4 * K)
+        if fused:   # + Adam: p, m, v read and written, s and alpha refreshed
+            return base - N * 4 * K + N * (K * 4 * 6 + 2 * 3 * 4)
+        return base
     if kernel == "adam":
-        return N * ((11 + C) * 4 * 7 + 2 * 3 * 4) + V * 2 * 4 * 7
+        return N * (K * 4 * 7 + 2 * 3 * 4) + V * 2 * 4 * 7
     return 0.0
 
 
@@ -82,6 +99,7 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="1..4: workload (default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", default="16x16", help="tile shape WxH (default 16x16)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a 256 MiB device copy (known bytes) to calibrate HBM counters")
@@ -113,7 +131,12 @@ def main():
           f"{scene.npix} px/step", file=sys.stderr, flush=True)
 
     def run(path, steps, profile=False):
-        fn = st.step_batched if path == "batched" else st.step_plain
+        if path == "fused":
+            fn = lambda total_steps: st.step_fused(total_steps=total_steps, check=False)
+        elif path == "fused_eager":
+            fn = lambda total_steps: st.step_fused(total_steps=total_steps, eager=True, check=False)
+        else:
+            fn = st.step_batched if path == "batched" else st.step_plain
         torch.cuda.synchronize()
         if profile:
             st.rg.prof_enable(True)
@@ -132,14 +155,28 @@ def main():
             st.rg.prof_enable(False)
         return wall * 1e3 / steps, e0.elapsed_time(e1) / steps, prof
 
-    run("batched", args.warmup)
+    # headline: the fused step, captured once as a graph and replayed
+    run("fused", args.warmup)
     print("[bench] warmup done", file=sys.stderr, flush=True)
-    ms_b, ev_b, prof = run("batched", args.steps, profile=True)
-    stats = st.rg.batch_stats(st._ws_batch)
-    print(f"[bench] batched: {ms_b:.3f} ms/step, pairs {stats['pairs']}", file=sys.stderr, flush=True)
+    ms_f, ev_f, _ = run("fused", args.steps)
+    fst = st.fused_status()
+    if fst["overflow"]:
+        raise RuntimeError("pair capacity overflow during the timed steps")
+    stats = {k: fst[k] for k in ("pairs", "visible", "pixels", "tiles", "slots")}
+    print(f"[bench] fused (graph): {ms_f:.3f} ms/step, pairs {stats['pairs']}", file=sys.stderr,
+          flush=True)
+    # the same kernels launched one by one, each bracketed by HIP events
+    run("fused_eager", 1)
+    ms_fe, _, prof = run("fused_eager", args.steps, profile=True)
+    print(f"[bench] fused (eager, timed kernels): {ms_fe:.3f} ms/step", file=sys.stderr, flush=True)
+    ms_b = None
+    if not args.no_batched:
+        run("batched", 1)
+        ms_b, _, _ = run("batched", args.steps)
+        print(f"[bench] batched: {ms_b:.3f} ms/step", file=sys.stderr, flush=True)
     plain = None
     if not args.no_plain:
-        run("plain", max(1, args.warmup))
+        run("plain", 1)
         ms_p, ev_p, _ = run("plain", args.steps)
         plain = {"ms_per_step": round(ms_p, 4),
                  "value": round(scene.npix / (ms_p * 1e-3) / 1e6, 2)}
@@ -149,34 +186,37 @@ def main():
     passes = (key_bits + 7) // 8
     kernels = {}
     for name, (ms, n) in prof.items():
-        if n == 0:
+        if n == 0 or name == "fused_graph":
             continue
         per = ms / args.steps
-        b = algorithmic_bytes(name, st, stats, C, passes)
+        b = algorithmic_bytes(name, st, stats, C, passes, fused=True)
         kernels[name] = {"ms_per_step": round(per, 4), "launches_per_step": n // args.steps,
                          "alg_GBs": round(b / (per * 1e-3) / 1e9, 1) if per > 0 else None}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     dom_ms = prof[dom][0] / prof[dom][1]          # average duration of one launch group
-    dom_bytes = algorithmic_bytes(dom, st, stats, C, passes) / (prof[dom][1] / args.steps)
+    dom_bytes = algorithmic_bytes(dom, st, stats, C, passes, True) / (prof[dom][1] / args.steps)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "avg_launch_ms": round(dom_ms, 4),
                 "alg_bytes_per_launch": int(dom_bytes)}
 
-    value = scene.npix / (ms_b * 1e-3) / 1e6
+    value = scene.npix / (ms_f * 1e-3) / 1e6
     line = {
         "metric": "fwd+bwd Mpixel/s per train step (fused vs plain)",
         "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_b, 4), "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": round(ms_f, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded surfel grid, cameras and random targets)",
         "config": {"workload": scene.name, "surfels": scene.n, "views": scene.n_views,
-                   "tile": args.tile,
-                   "pixels_per_step": scene.npix, "sem_classes": C, "path": "batched",
-                   "pairs": stats["pairs"], "visible_slots": stats["visible"]},
+                   "tile": args.tile, "pixels_per_step": scene.npix, "sem_classes": C,
+                   "path": "fused (hipGraph)", "pairs": stats["pairs"],
+                   "visible_slots": stats["visible"]},
+        "fused_eager_ms_per_step": round(ms_fe, 4),
+        "batched": ({"ms_per_step": round(ms_b, 4),
+                     "value": round(scene.npix / (ms_b * 1e-3) / 1e6, 2)} if ms_b else None),
         "plain": plain,
-        "speedup_vs_plain": round(plain["ms_per_step"] / ms_b, 3) if plain else None,
+        "speedup_vs_plain": round(plain["ms_per_step"] / ms_f, 3) if plain else None,
         "kernels": kernels,
         "roofline": roofline,
     }

@@ -257,9 +257,10 @@ ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* para
  * view resolutions; camera poses may change: they are copied from a pinned
  * buffer by the graph).  Each call first waits for the previous step, then
  * launches.  If the previous step overflowed pair_capacity it made no update
- * (parameters, moments and step count untouched) and this call returns
- * ROGS_ECAPACITY without launching; read the needed count with
- * rogs_fused_status, grow the workspace and call again. */
+ * (parameters, moments and step count untouched); unless that was already
+ * seen through rogs_fused_status, this call then returns ROGS_ECAPACITY
+ * without launching.  Read the needed count with rogs_fused_status, grow
+ * the workspace and call again. */
 typedef struct {
   int32_t n, n_sem;
   const float* x;        /* [N] fixed grid vertices */

@@ -56,6 +56,7 @@ struct rogs_ctx {
     uint32_t* status = nullptr;          // pinned: misc[4] + StepState
     hipEvent_t done = nullptr;
     bool pending = false;
+    hipStream_t cap_stream = nullptr;    // capture happens here (the null stream cannot be captured)
   } fz;
 };
 
@@ -342,6 +343,7 @@ void rogs_destroy(rogs_ctx* c) {
   if (c->fz.stage) (void)hipHostFree(c->fz.stage);
   if (c->fz.status) (void)hipHostFree(c->fz.status);
   if (c->fz.done) (void)hipEventDestroy(c->fz.done);
+  if (c->fz.cap_stream) (void)hipStreamDestroy(c->fz.cap_stream);
   if (!c->recs.empty()) (void)hipEventSynchronize(c->recs.back().b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->stage_pending) (void)hipEventSynchronize(c->stage_evt);
@@ -844,14 +846,21 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
   } else {
     if (!same) {
       Layout Lr = L;
-      e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (!F.cap_stream) {
+        e = hipStreamCreateWithFlags(&F.cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreateWithFlags");
+      }
+      // captured work touches the workspace: let earlier work on st finish first
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+      e = hipStreamBeginCapture(F.cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
       const bool prof = c->prof;
       c->prof = false;                 // no timing events inside the graph
-      r = fused_sequence(c, Lr, t, tg, o, ws, st);
+      r = fused_sequence(c, Lr, t, tg, o, ws, F.cap_stream);
       c->prof = prof;
       hipGraph_t g = nullptr;
-      hipError_t e2 = hipStreamEndCapture(st, &g);
+      hipError_t e2 = hipStreamEndCapture(F.cap_stream, &g);
       if (r != ROGS_OK) {
         if (g) (void)hipGraphDestroy(g);
         return r;
@@ -898,6 +907,7 @@ int rogs_fused_status(rogs_ctx* c, int64_t* stats, float* loss) {
   if (F.pending) {
     hipError_t e = hipEventSynchronize(F.done);
     if (e != hipSuccess) return hip_fail(c, e, "rogs_fused_status");
+    F.pending = false;     // seen: the next step call does not report it again
   }
   const rogs::StepState* ss = reinterpret_cast<const rogs::StepState*>(
       reinterpret_cast<const char*>(F.status) + 16);

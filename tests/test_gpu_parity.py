@@ -343,13 +343,14 @@ def test_fused_overflow_skips_update_and_recovers(gpu):
     size = B.fused_workspace_size(ts, st.cams, st.opts, 256)
     ws = torch.empty(size, dtype=torch.uint8, device="cuda")
     st.rg.step_fused(ts, st.cams, st.opts, st.targets(0, st.V), optim, ws, 256)
+    # the next call sees the overflow of the previous step and launches nothing
+    r = st.rg.step_fused(ts, st.cams, st.opts, st.targets(0, st.V), optim, ws, 256,
+                         raise_on_capacity=False)
+    assert r == B.ECAPACITY
     s1 = st.rg.fused_status()
     assert s1["overflow"] == 1 and s1["step"] == 0 and s1["skipped"] == 1
     assert s1["pairs"] > 256
     assert torch.equal(st.params, before)             # no update on overflow
-    r = st.rg.step_fused(ts, st.cams, st.opts, st.targets(0, st.V), optim, ws, 256,
-                         raise_on_capacity=False)
-    assert r == B.ECAPACITY
     st.cap_fused = 256
     st.step_fused(total_steps=1)                      # grows and runs the step
     s2 = st.fused_status()
