@@ -39,10 +39,13 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) 
     K = 11 + C
     if kernel == "project":
         return N * (40 + 4 * FS) + slots * 4 + S * 40
-    if kernel == "emit":
-        return slots * 8 + S * 40 + P * 16
     if kernel == "sort":
-        return passes * P * 32
+        # compaction (counts, depth keys) + depth sort of the S visible slots
+        # (64-bit keys, 8-bit digits) + emission offsets + one tile key,
+        # value and slot per pair + tile sort of the pairs (32-bit keys)
+        view_bits = max(0, (V - 1).bit_length())
+        s_passes = (32 + view_bits + 7) // 8
+        return slots * 4 + S * 16 + s_passes * S * 32 + S * 24 + P * 12 + passes * P * 20
     if kernel == "ranges":
         return P * 8 + stats["tiles"] * 8
     if kernel == "render_fwd":
@@ -155,7 +158,10 @@ def main():
             st.rg.prof_enable(False)
         return wall * 1e3 / steps, e0.elapsed_time(e1) / steps, prof
 
-    # headline: the fused step, captured once as a graph and replayed
+    # headline: the fused step, captured once as a graph and replayed; after
+    # the first step the capacities are fitted to the measured counts (+10 %)
+    run("fused", 1)
+    st.fit_fused_capacity()
     run("fused", args.warmup)
     print("[bench] warmup done", file=sys.stderr, flush=True)
     ms_f, ev_f, _ = run("fused", args.steps)
@@ -182,8 +188,8 @@ def main():
                  "value": round(scene.npix / (ms_p * 1e-3) / 1e6, 2)}
         print(f"[bench] plain: {ms_p:.3f} ms/step", file=sys.stderr, flush=True)
 
-    key_bits = 32 + max(1, (stats["tiles"] - 1).bit_length())
-    passes = (key_bits + 7) // 8
+    tile_bits = max(1, (stats["tiles"] - 1).bit_length())
+    passes = (tile_bits + 8) // 9          # pair sort: 32-bit tile keys, up to 9-bit digits
     kernels = {}
     for name, (ms, n) in prof.items():
         if n == 0 or name == "fused_graph":

@@ -182,9 +182,14 @@ ROGS_API const char* rogs_last_error(const rogs_ctx* ctx);
 ROGS_API void rogs_default_opts(rogs_render_opts* opts);
 
 /* Bytes of workspace for a batch of n_views cameras over s->n surfels with
- * room for pair_capacity (surfel, tile) pairs.  Host-only computation. */
+ * room for pair_capacity (surfel, tile) pairs and slot_capacity visible
+ * (view, surfel) slots (0 = pair_capacity; at most pair_capacity, since
+ * every visible slot has at least one pair).  Host-only computation.  Kernels
+ * that wait for a count kept on the device are sized by these capacities, so
+ * capacities close to the real counts launch fewer idle blocks. */
 ROGS_API int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
-                        const rogs_render_opts* opts, int64_t pair_capacity, size_t* bytes);
+                        const rogs_render_opts* opts, int64_t pair_capacity,
+                        int64_t slot_capacity, size_t* bytes);
 
 /* a1-a2, Eq. 5 + supp. Sec. 2.1.  Starts a batch: uploads the view table into
  * the workspace, culls and projects every (view, surfel) with the key
@@ -193,13 +198,15 @@ ROGS_API int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams,
  * same workspace. */
 ROGS_API int rogs_project(rogs_ctx* ctx, const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
                  const rogs_render_opts* opts, void* ws, size_t ws_bytes, int64_t pair_capacity,
-                 void* stream);
+                 int64_t slot_capacity, void* stream);
 
 /* a3-a5, Sec. 3.3.1 ("ascending order of original depth").  Emits one
  * (tile, depth) key per covered tile, radix-sorts the keys stably (ties keep
  * surfel-id order) and writes per-tile ranges.  With ROGS_SYNC_COUNT the pair
- * count P is read back first (host sync): if P > pair_capacity the call
- * returns ROGS_ECAPACITY with *n_pairs_out = P and enqueues nothing more.
+ * count P is read back first (host sync): if P > pair_capacity or the
+ * visible-slot count exceeds slot_capacity the call returns ROGS_ECAPACITY
+ * with *n_pairs_out = P and enqueues nothing more (rogs_batch_stats gives
+ * both counts).
  * Without it the count stays on the device; an overflow is flagged on the
  * device and reported by rogs_overflow(). n_pairs_out may be NULL. */
 ROGS_API int rogs_bin_sort(rogs_ctx* ctx, void* ws, int64_t* n_pairs_out, uint32_t flags, void* stream);
@@ -291,11 +298,13 @@ typedef struct {
 
 ROGS_API int rogs_fused_workspace_size(const rogs_train_state* t, const rogs_camera* cams,
                                        int32_t n_views, const rogs_render_opts* opts,
-                                       int64_t pair_capacity, size_t* bytes);
+                                       int64_t pair_capacity, int64_t slot_capacity,
+                                       size_t* bytes);
 ROGS_API int rogs_step_fused(rogs_ctx* ctx, const rogs_train_state* t, const rogs_camera* cams,
                              int32_t n_views, const rogs_render_opts* opts,
                              const rogs_targets* targets, const rogs_optim* optim, void* ws,
-                             size_t ws_bytes, int64_t pair_capacity, uint32_t flags, void* stream);
+                             size_t ws_bytes, int64_t pair_capacity, int64_t slot_capacity,
+                             uint32_t flags, void* stream);
 /* Waits for the last fused step and reports stats[0] pairs P, [1] overflow,
  * [2] visible slots, [3] steps applied, [4] steps skipped, [5] pixels,
  * [6] tiles, [7] slots; *loss = loss of the last applied step (nullable). */

@@ -105,9 +105,10 @@ def load_library(path: str = LIB_PATH):
             "rogs_last_error": ([P], ctypes.c_char_p),
             "rogs_default_opts": ([ctypes.POINTER(RenderOpts)], None),
             "rogs_workspace_size": ([ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
-                                     ctypes.POINTER(RenderOpts), I64, ctypes.POINTER(ctypes.c_size_t)], I32),
+                                     ctypes.POINTER(RenderOpts), I64, I64,
+                                     ctypes.POINTER(ctypes.c_size_t)], I32),
             "rogs_project": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
-                              ctypes.POINTER(RenderOpts), P, ctypes.c_size_t, I64, P], I32),
+                              ctypes.POINTER(RenderOpts), P, ctypes.c_size_t, I64, I64, P], I32),
             "rogs_bin_sort": ([P, P, ctypes.POINTER(I64), U32, P], I32),
             "rogs_pair_count": ([P, P, ctypes.POINTER(I64), ctypes.POINTER(I32), P], I32),
             "rogs_render_fwd": ([P, ctypes.POINTER(Surfels), P, P, P], I32),
@@ -122,11 +123,11 @@ def load_library(path: str = LIB_PATH):
             "rogs_prof_read": ([P, P, P, I32], I32),
             "rogs_prof_name": ([I32], ctypes.c_char_p),
             "rogs_fused_workspace_size": ([ctypes.POINTER(TrainStateC), ctypes.POINTER(Camera), I32,
-                                           ctypes.POINTER(RenderOpts), I64,
+                                           ctypes.POINTER(RenderOpts), I64, I64,
                                            ctypes.POINTER(ctypes.c_size_t)], I32),
             "rogs_step_fused": ([P, ctypes.POINTER(TrainStateC), ctypes.POINTER(Camera), I32,
                                  ctypes.POINTER(RenderOpts), ctypes.POINTER(Targets),
-                                 ctypes.POINTER(Optim), P, ctypes.c_size_t, I64, U32, P], I32),
+                                 ctypes.POINTER(Optim), P, ctypes.c_size_t, I64, I64, U32, P], I32),
             "rogs_fused_status": ([P, P, P], I32),
         }
         for name, (args, res) in sig.items():
@@ -183,25 +184,27 @@ def make_opts(tile_w=16, tile_h=16, eps2d=0.3, q_cut=9.0, alpha_max=0.99, t_eps=
     return RenderOpts(tile_w, tile_h, eps2d, q_cut, alpha_max, t_eps)
 
 
-def fused_workspace_size(ts: TrainStateC, cams, opts: RenderOpts, pair_capacity: int) -> int:
+def fused_workspace_size(ts: TrainStateC, cams, opts: RenderOpts, pair_capacity: int,
+                         slot_capacity: int = 0) -> int:
     """rogs_fused_workspace_size (host-only)."""
     L = load_library()
     arr = camera_array(cams)
     out = ctypes.c_size_t(0)
     r = L.rogs_fused_workspace_size(ctypes.byref(ts), arr, len(cams), ctypes.byref(opts),
-                                    int(pair_capacity), ctypes.byref(out))
+                                    int(pair_capacity), int(slot_capacity), ctypes.byref(out))
     if r != OK:
         raise RogsError(r, "rogs_fused_workspace_size rejected its arguments")
     return int(out.value)
 
 
-def workspace_size(surf: Surfels, cams, opts: RenderOpts, pair_capacity: int) -> int:
+def workspace_size(surf: Surfels, cams, opts: RenderOpts, pair_capacity: int,
+                   slot_capacity: int = 0) -> int:
     """rogs_workspace_size (host-only)."""
     L = load_library()
     arr = camera_array(cams)
     out = ctypes.c_size_t(0)
     r = L.rogs_workspace_size(ctypes.byref(surf), arr, len(cams), ctypes.byref(opts),
-                              int(pair_capacity), ctypes.byref(out))
+                              int(pair_capacity), int(slot_capacity), ctypes.byref(out))
     if r != OK:
         raise RogsError(r, "rogs_workspace_size rejected its arguments")
     return int(out.value)
@@ -246,11 +249,12 @@ class Rogs:
         return m.decode() if m else ""
 
     # --- entry points -------------------------------------------------
-    def project(self, surf: Surfels, cams, opts: RenderOpts, ws, pair_capacity: int, stream=None):
+    def project(self, surf: Surfels, cams, opts: RenderOpts, ws, pair_capacity: int,
+                slot_capacity: int = 0, stream=None):
         arr = camera_array(cams)
         self._check(self.L.rogs_project(self.h, ctypes.byref(surf), arr, len(cams), ctypes.byref(opts),
                                         ptr(ws), ws.numel() * ws.element_size(), int(pair_capacity),
-                                        _stream(stream)), "rogs_project")
+                                        int(slot_capacity), _stream(stream)), "rogs_project")
 
     def bin_sort(self, ws, flags: int = SYNC_COUNT, stream=None, raise_on_capacity=True) -> int:
         n = ctypes.c_int64(-1)
@@ -308,12 +312,12 @@ class Rogs:
 
     def step_fused(self, ts: "TrainStateC", cams, opts: RenderOpts, targets: Targets,
                    optim: Optim, ws, pair_capacity: int, flags: int = 0, stream=None,
-                   raise_on_capacity=True) -> int:
+                   raise_on_capacity=True, slot_capacity: int = 0) -> int:
         arr = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         r = self.L.rogs_step_fused(self.h, ctypes.byref(ts), arr, len(arr), ctypes.byref(opts),
                                    ctypes.byref(targets), ctypes.byref(optim), ptr(ws),
-                                   ws.numel() * ws.element_size(), int(pair_capacity), flags,
-                                   _stream(stream))
+                                   ws.numel() * ws.element_size(), int(pair_capacity),
+                                   int(slot_capacity), flags, _stream(stream))
         if r == ECAPACITY and not raise_on_capacity:
             return r
         self._check(r, "rogs_step_fused")

@@ -86,14 +86,16 @@ bool is_fin(float x) { return isfinite(x); }
 namespace rogs {
 
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
-                const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why,
-                bool fused) {
+                const rogs_render_opts* opts, int64_t cap, int64_t scap, Layout* L,
+                const char** why, bool fused) {
   *why = nullptr;
   if (!s || !cams || !opts || !L) { *why = "null argument"; return ROGS_EINVAL; }
   if (s->n < 1) { *why = "surfel count must be >= 1"; return ROGS_EINVAL; }
   if (!sem_supported(s->n_sem)) { *why = "n_sem must be 1..8 or 16"; return ROGS_EINVAL; }
   if (n_views < 1 || n_views > kMaxViews) { *why = "n_views out of range"; return ROGS_EINVAL; }
   if (cap < 0 || cap >= (int64_t(1) << 31)) { *why = "pair_capacity must be in [0, 2^31)"; return ROGS_EINVAL; }
+  if (scap < 0) { *why = "slot_capacity must be >= 0"; return ROGS_EINVAL; }
+  if (scap == 0 || scap > cap) scap = cap;
   const int tw = opts->tile_w, th = opts->tile_h;
   if (tw < 1 || tw > 64 || (64 % tw) != 0 || th < 1 || tw * th < 64 || tw * th > 256 ||
       ((tw * th) & (tw * th - 1)) != 0) {
@@ -121,6 +123,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.alpha_max = opts->alpha_max;
   l.t_eps = opts->t_eps;
   l.cap = cap;
+  l.scap = scap;
   int64_t loss_blocks = 0;
   for (int v = 0; v < n_views; ++v) {
     const rogs_camera& c = cams[v];
@@ -157,23 +160,31 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_mcount = take(sizeof(uint32_t) * 2 * l.V);   // mask counts, then per-view loss sums
   l.o_lpart = take(sizeof(int64_t) * (l.V + 1) + sizeof(float) * 3 * loss_blocks);
   l.o_cnt = take(4 * (size_t)l.slots);
-  l.o_off = take(4 * (size_t)l.slots);
   l.o_rec = take(32 * (size_t)l.slots);
   l.o_rect = take(8 * (size_t)l.slots);
   l.o_feat = take(4 * (size_t)l.N * l.FS);
   l.o_part = take(4 * (size_t)l.V * l.nb);
+  l.o_partv = take(4 * (size_t)l.V * l.nb);
   l.o_parttmp = take(4 * scan_tmp_words((int64_t)l.V * l.nb));
-  l.o_keys = take(8 * (size_t)cap);
-  l.o_keys2 = take(8 * (size_t)cap);
+  l.o_parttmp2 = take(4 * scan_tmp_words(scap));
+  l.o_keys = take(4 * (size_t)cap);          // tile of each pair
+  l.o_keys2 = take(8 * (size_t)cap);         // also scratch of the 64-bit slot sort
   l.o_vals = take(4 * (size_t)cap);
   l.o_vals2 = take(4 * (size_t)cap);
   l.o_pslot = take(4 * (size_t)cap);
+  l.o_skey = take(8 * (size_t)scap);         // visible slots (at most one per pair)
+  l.o_sval = take(4 * (size_t)scap);
+  l.o_scnt = take(4 * (size_t)scap);
+  l.o_soff = take(4 * (size_t)scap);
+  l.o_ssum = take(4 * (size_t)l.GS * scap);
+  l.o_long = take(4 * (size_t)scap);
+  l.o_pos = take(4 * (size_t)l.slots);
   l.o_ranges = take(8 * (size_t)l.total_tiles);
   l.o_tfin = take(4 * (size_t)l.total_pix);
   l.o_nlast = take(4 * (size_t)l.total_pix);
   l.o_gpair = take(4 * (size_t)cap * l.GS);
-  l.o_hist = take(4 * (size_t)kRadix * l.sort_blocks);
-  l.o_histtmp = take(4 * scan_tmp_words((int64_t)kRadix * l.sort_blocks));
+  l.o_hist = take(4 * (size_t)kRadixMax * l.sort_blocks);
+  l.o_histtmp = take(4 * scan_tmp_words((int64_t)kRadixMax * l.sort_blocks));
   if (fused) {
     const size_t nch = (size_t)(6 + l.C), tp = (size_t)tw * th;
     l.o_tm = take(4 * (size_t)l.total_tiles * nch * tp);
@@ -366,11 +377,12 @@ void rogs_default_opts(rogs_render_opts* o) {
 }
 
 int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
-                        const rogs_render_opts* opts, int64_t pair_capacity, size_t* bytes) {
+                        const rogs_render_opts* opts, int64_t pair_capacity, int64_t slot_capacity,
+                        size_t* bytes) {
   if (!bytes) return ROGS_EINVAL;
   Layout L;
   const char* why = nullptr;
-  int r = rogs::make_layout(s, cams, n_views, opts, pair_capacity, &L, &why);
+  int r = rogs::make_layout(s, cams, n_views, opts, pair_capacity, slot_capacity, &L, &why);
   if (r != ROGS_OK) return r;
   *bytes = L.total;
   return ROGS_OK;
@@ -378,11 +390,11 @@ int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams, int32_t 
 
 int rogs_project(rogs_ctx* c, const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
                  const rogs_render_opts* opts, void* ws, size_t ws_bytes, int64_t pair_capacity,
-                 void* stream) {
+                 int64_t slot_capacity, void* stream) {
   if (!c) return ROGS_EINVAL;
   Layout L;
   const char* why = nullptr;
-  int r = rogs::make_layout(s, cams, n_views, opts, pair_capacity, &L, &why);
+  int r = rogs::make_layout(s, cams, n_views, opts, pair_capacity, slot_capacity, &L, &why);
   if (r != ROGS_OK) return fail(c, r, why ? why : "invalid argument");
   r = check_surfels(c, s, L);
   if (r != ROGS_OK) return r;
@@ -470,24 +482,24 @@ int rogs_bin_sort(rogs_ctx* c, void* ws, int64_t* n_pairs_out, uint32_t flags, v
   int r = need_batch(c, ws, false);
   if (r != ROGS_OK) return r;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int64_t n_host = -1;
+  int64_t n_host = -1, n_vis = -1;
   if (flags & ROGS_SYNC_COUNT) {
     int32_t ovf = 0;
     r = rogs_pair_count(c, ws, &n_host, &ovf, stream);
     if (r != ROGS_OK) return r;
+    n_vis = c->last_visible;
     if (n_pairs_out) *n_pairs_out = n_host;
-    if (n_host > c->L.cap)
-      return fail(c, ROGS_ECAPACITY, "pair capacity " + std::to_string(c->L.cap) +
-                                         " too small for " + std::to_string(n_host) + " pairs");
+    if (n_host > c->L.cap || n_vis > c->L.scap)
+      return fail(c, ROGS_ECAPACITY, "capacity (" + std::to_string(c->L.cap) + " pairs, " +
+                                         std::to_string(c->L.scap) + " slots) too small for " +
+                                         std::to_string(n_host) + " pairs, " +
+                                         std::to_string(n_vis) + " slots");
   } else if (n_pairs_out) {
     *n_pairs_out = -1;
   }
   Layout& L = c->L;
-  prof_begin(c, 2, st);
-  rogs::launch_emit(L, ws, st);
-  prof_end(c, st);
   prof_begin(c, 3, st);
-  int alt = rogs::launch_sort(L, ws, n_host, st);
+  int alt = rogs::launch_binning(L, ws, n_host, n_vis, st);
   prof_end(c, st);
   if (alt) {
     std::swap(L.o_keys, L.o_keys2);
@@ -546,6 +558,7 @@ int rogs_render_bwd(rogs_ctx* c, const rogs_surfels* s, void* ws, const float* o
   prof_end(c, st);
   if (rr != 0) return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
   prof_begin(c, 8, st);
+  rogs::launch_slot_sums(c->L, ws, st);
   rogs::launch_proj_bwd(c->L, ws, s, grads, (flags & ROGS_ACCUMULATE) != 0, st);
   prof_end(c, st);
   return check_launch(c, "rogs_render_bwd");
@@ -586,15 +599,19 @@ int rogs_debug_pairs(rogs_ctx* c, void* ws, uint64_t* keys, int32_t* surfel_ids,
   if (P > L.cap) P = L.cap;
   if (cap < P || !keys || !surfel_ids || !views) return fail(c, ROGS_EINVAL, "output capacity too small");
   if (ranges && n_tiles < L.total_tiles) return fail(c, ROGS_EINVAL, "ranges capacity too small");
-  std::vector<uint32_t> vals(P), pslot(P);
+  std::vector<uint32_t> tiles(P), vals(P), pslot(P);
+  std::vector<float> rec(8 * (size_t)L.slots);
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (P > 0) {
-    e = hipMemcpyAsync(keys, rogs::at<void>(ws, L.o_keys), 8 * P, hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(tiles.data(), rogs::at<void>(ws, L.o_keys), 4 * P, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(vals.data(), rogs::at<void>(ws, L.o_vals), 4 * P, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(pslot.data(), rogs::at<void>(ws, L.o_pslot), 4 * P, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(rec.data(), rogs::at<void>(ws, L.o_rec), 32 * (size_t)L.slots,
+                         hipMemcpyDeviceToHost, st);
   }
   if (e == hipSuccess && ranges)
     e = hipMemcpyAsync(ranges, rogs::at<void>(ws, L.o_ranges), 8 * L.total_tiles,
@@ -605,6 +622,9 @@ int rogs_debug_pairs(rogs_ctx* c, void* ws, uint64_t* keys, int32_t* surfel_ids,
     const uint32_t sl = pslot[vals[k]];
     surfel_ids[k] = (int32_t)(sl % (uint32_t)L.N);
     views[k] = (int32_t)(sl / (uint32_t)L.N);
+    uint32_t db;
+    memcpy(&db, &rec[8 * (size_t)sl + 7], 4);
+    keys[k] = ((uint64_t)tiles[k] << 32) | db;
   }
   return ROGS_OK;
 }
@@ -709,11 +729,8 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
   prof_begin(c, 1, st);
   rogs::launch_scan_part(L, ws, st);
   prof_end(c, st);
-  prof_begin(c, 2, st);
-  rogs::launch_emit(L, ws, st);
-  prof_end(c, st);
   prof_begin(c, 3, st);
-  int alt = rogs::launch_sort(L, ws, -1, st);
+  int alt = rogs::launch_binning(L, ws, -1, -1, st);
   prof_end(c, st);
   if (alt) {
     std::swap(L.o_keys, L.o_keys2);
@@ -748,6 +765,7 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
   prof_end(c, st);
   rogs::AdamArgs aa = fused_adam_args(o, L, ws, t->step_state);
   prof_begin(c, 8, st);
+  rogs::launch_slot_sums(L, ws, st);
   rogs::launch_proj_bwd_adam(L, ws, t->x, t->y, t->params, t->m, t->v, t->s_act, t->alpha_act,
                              t->grads, aa, t->exposure, t->d_exposure, t->m_exp, t->v_exp, st);
   prof_end(c, st);
@@ -761,12 +779,13 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
 }  // namespace
 
 int rogs_fused_workspace_size(const rogs_train_state* t, const rogs_camera* cams, int32_t n_views,
-                              const rogs_render_opts* opts, int64_t pair_capacity, size_t* bytes) {
+                              const rogs_render_opts* opts, int64_t pair_capacity,
+                              int64_t slot_capacity, size_t* bytes) {
   if (!t || !bytes) return ROGS_EINVAL;
   rogs_surfels s = fused_surfels(t);
   Layout L;
   const char* why = nullptr;
-  int r = rogs::make_layout(&s, cams, n_views, opts, pair_capacity, &L, &why, true);
+  int r = rogs::make_layout(&s, cams, n_views, opts, pair_capacity, slot_capacity, &L, &why, true);
   if (r != ROGS_OK) return r;
   *bytes = L.total;
   return ROGS_OK;
@@ -775,14 +794,14 @@ int rogs_fused_workspace_size(const rogs_train_state* t, const rogs_camera* cams
 int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* cams,
                     int32_t n_views, const rogs_render_opts* opts, const rogs_targets* tg,
                     const rogs_optim* o, void* ws, size_t ws_bytes, int64_t pair_capacity,
-                    uint32_t flags, void* stream) {
+                    int64_t slot_capacity, uint32_t flags, void* stream) {
   if (!c) return ROGS_EINVAL;
   int r = check_fused_args(c, t, tg, o);
   if (r != ROGS_OK) return r;
   rogs_surfels s = fused_surfels(t);
   Layout L;
   const char* why = nullptr;
-  r = rogs::make_layout(&s, cams, n_views, opts, pair_capacity, &L, &why, true);
+  r = rogs::make_layout(&s, cams, n_views, opts, pair_capacity, slot_capacity, &L, &why, true);
   if (r != ROGS_OK) return fail(c, r, why ? why : "invalid argument");
   if (!ws) return fail(c, ROGS_EINVAL, "workspace is null");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(c, ROGS_EINVAL, "workspace must be 256-byte aligned");
@@ -818,7 +837,8 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
   const bool same = F.valid && F.ws == ws && F.st == st && F.flags == flags &&
                     same_bytes(&F.ts, t, sizeof(*t)) && same_bytes(&F.tg, tg, sizeof(*tg)) &&
                     same_bytes(&F.opt, o, sizeof(*o)) && same_bytes(&F.opts, opts, sizeof(*opts)) &&
-                    F.sizes == sizes && F.L.total == L.total && F.L.cap == L.cap;
+                    F.sizes == sizes && F.L.total == L.total && F.L.cap == L.cap &&
+                    F.L.scap == L.scap;
   const size_t need = sizeof(ViewDev) * L.V + sizeof(int64_t) * (L.V + 1);
   if (!same) {
     if (F.exec) (void)hipGraphExecDestroy(F.exec);

@@ -261,37 +261,126 @@ __device__ __forceinline__ void adam_surfel(int i, size_t N, float* __restrict__
   a_act[i] = 1.0f / (1.0f + expf(-P[7 * N + i]));
 }
 
-// Projection adjoint of surfel i summed over the batch's views: the per-pair
-// gradient records of each visible (view, surfel) slot are summed, chained
-// through the projection of that view and accumulated.  vals[11 + C]: dL/d
-// (z, q, s, alpha, rgb, sem) w.r.t. the activated values.
+// Per-slot sums of the per-pair gradient records.  The records of a visible
+// slot are contiguous in emission order; a slot with at most kLongRows records
+// is summed by one thread in record order, a longer one by one wave (lane l
+// takes records l, l + 64, ... in order, then the wave reduce-scatter).  Each
+// slot's sum depends only on its own records, not on how a batch is laid out.
+constexpr uint32_t kLongRows = 32;
+
+template <int C>
+__global__ __launch_bounds__(256) void k_slot_sums(const uint32_t* __restrict__ misc,
+                                                   int64_t scap, int64_t cap,
+                                                   const uint32_t* __restrict__ scnt,
+                                                   const uint32_t* __restrict__ soff,
+                                                   const float* __restrict__ gpair,
+                                                   float* __restrict__ ssum,
+                                                   uint32_t* __restrict__ long_list,
+                                                   uint32_t* __restrict__ long_count) {
+  constexpr int GSC = ((10 + C) + 3) & ~3;
+  constexpr int Q = GSC / 4;
+  const int64_t S = min((int64_t)misc[kMiscVisible], scap);
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= S) return;
+  const uint32_t n = scnt[k], o = soff[k];
+  if (n > kLongRows) {
+    long_list[atomicAdd(long_count, 1u)] = (uint32_t)k;
+    return;
+  }
+  // after a pair-capacity overflow the records past the capacity were never written
+  const uint32_t m = ((int64_t)o + n <= cap) ? n : (((int64_t)o < cap) ? (uint32_t)(cap - o) : 0u);
+  const float4* r4 = reinterpret_cast<const float4*>(gpair) + (size_t)o * Q;
+  float4 acc[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) acc[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  uint32_t r = 0;
+  for (; r + 1 < m; r += 2) {
+    float4 a[Q], b[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      a[j] = r4[(size_t)r * Q + j];
+      b[j] = r4[(size_t)(r + 1) * Q + j];
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      acc[j].x += a[j].x; acc[j].y += a[j].y; acc[j].z += a[j].z; acc[j].w += a[j].w;
+      acc[j].x += b[j].x; acc[j].y += b[j].y; acc[j].z += b[j].z; acc[j].w += b[j].w;
+    }
+  }
+  if (r < m) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const float4 a = r4[(size_t)r * Q + j];
+      acc[j].x += a.x; acc[j].y += a.y; acc[j].z += a.z; acc[j].w += a.w;
+    }
+  }
+  float4* out = reinterpret_cast<float4*>(ssum) + (size_t)k * Q;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) out[j] = acc[j];
+}
+
+// Long slots: one wave each; the grid loops over the list (every wave exits).
+template <int C>
+__global__ __launch_bounds__(64) void k_slot_sums_long(const uint32_t* __restrict__ long_list,
+                                                       const uint32_t* __restrict__ long_count,
+                                                       int64_t cap,
+                                                       const uint32_t* __restrict__ scnt,
+                                                       const uint32_t* __restrict__ soff,
+                                                       const float* __restrict__ gpair,
+                                                       float* __restrict__ ssum) {
+  constexpr int NV = 10 + C;
+  constexpr int GSC = ((10 + C) + 3) & ~3;
+  const int lane = threadIdx.x;
+  const uint32_t nl = *long_count;
+  const int my_comp = rs_comp(lane, NV);
+  const bool writer = my_comp >= 0 && (lane & rs_dup_bits(NV)) == 0;
+  for (uint32_t it = blockIdx.x; it < nl; it += gridDim.x) {
+    const uint32_t k = long_list[it];
+    const uint32_t n = scnt[k], o = soff[k];
+    const uint32_t m = ((int64_t)o + n <= cap) ? n : (((int64_t)o < cap) ? (uint32_t)(cap - o) : 0u);
+    float acc[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[c] = 0.0f;
+    for (uint32_t r = lane; r < m; r += 64) {
+      const float* row = gpair + (size_t)(o + r) * GSC;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) acc[c] += row[c];
+    }
+    const float tot = wave_reduce_scatter<NV>(acc, lane);
+    if (writer) ssum[(size_t)k * GSC + my_comp] = tot;
+  }
+}
+
+// Projection adjoint of surfel i summed over the batch's views: each visible
+// (view, surfel) slot's gradient sum is chained through the projection of
+// that view and accumulated.  vals[11 + C]: dL/d(z, q, s, alpha, rgb, sem)
+// w.r.t. the activated values.
 template <int C>
 __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ views, int V,
                                              int N, float eps, float x, float y, float z,
                                              const float q[4], float sx, float sy,
                                              const uint32_t* __restrict__ cnt,
-                                             const uint32_t* __restrict__ off,
-                                             const float* __restrict__ gpair, int GS, int64_t cap,
-                                             float* vals) {
-  constexpr int NV = 10 + C;
+                                             const uint32_t* __restrict__ pos, int64_t scap,
+                                             const float* __restrict__ ssum, float* vals) {
+  constexpr int GSC = ((10 + C) + 3) & ~3;
+  constexpr int Q = GSC / 4;
   float dz = 0.0f, dq[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsx = 0.0f, dsy = 0.0f, dal = 0.0f;
   float dft[3 + C];
 #pragma unroll
   for (int c = 0; c < 3 + C; ++c) dft[c] = 0.0f;
   for (int v = 0; v < V; ++v) {
     const size_t slot = (size_t)v * N + i;
-    const uint32_t n = cnt[slot];
-    if (!n) continue;
-    const uint32_t o = off[slot];
-    // after a pair-capacity overflow the records past the capacity were never written
-    const uint32_t m = ((int64_t)o + n <= cap) ? n : (((int64_t)o < cap) ? (uint32_t)(cap - o) : 0u);
-    float rg[NV];
+    if (!cnt[slot]) continue;
+    // after a slot-capacity overflow a visible slot may have no sum (results
+    // are flagged invalid; the read stays inside the table)
+    const uint32_t p = pos[slot];
+    if ((int64_t)p >= scap) continue;
+    const float4* r4 = reinterpret_cast<const float4*>(ssum) + (size_t)p * Q;
+    float rg[4 * Q];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) rg[c] = 0.0f;
-    for (uint32_t k = 0; k < m; ++k) {
-      const float* r = gpair + (size_t)(o + k) * GS;
-#pragma unroll
-      for (int c = 0; c < NV; ++c) rg[c] += r[c];
+    for (int j = 0; j < Q; ++j) {
+      const float4 a = r4[j];
+      rg[4 * j] = a.x; rg[4 * j + 1] = a.y; rg[4 * j + 2] = a.z; rg[4 * j + 3] = a.w;
     }
     // this view's contribution first, then one add per component into the
     // running sum, so summing views here or across calls gives the same bits
@@ -319,14 +408,14 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
     const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
     const float* __restrict__ py, const float* __restrict__ pz, const float* __restrict__ pq,
     const float* __restrict__ ps, const uint32_t* __restrict__ cnt,
-    const uint32_t* __restrict__ off, const float* __restrict__ gpair, int GS, int64_t cap,
+    const uint32_t* __restrict__ pos, int64_t scap, const float* __restrict__ ssum,
     float* __restrict__ grads, int accumulate) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   const float q[4] = {pq[i], pq[N + i], pq[2 * (size_t)N + i], pq[3 * (size_t)N + i]};
   float vals[11 + C];
-  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], cnt, off, gpair,
-                  GS, cap, vals);
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], cnt, pos, scap,
+                  ssum, vals);
   const size_t Nn = (size_t)N;
 #pragma unroll
   for (int r = 0; r < 11 + C; ++r) {
@@ -343,17 +432,16 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
     const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
     const float* __restrict__ py, float* __restrict__ P, float* __restrict__ M,
     float* __restrict__ Vv, float* __restrict__ s_act, float* __restrict__ a_act,
-    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ off,
-    const float* __restrict__ gpair, int GS, int64_t cap, float* __restrict__ grads_out,
-    AdamArgs aa) {
+    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ pos, int64_t scap,
+    const float* __restrict__ ssum, float* __restrict__ grads_out, AdamArgs aa) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   if (aa.misc[kMiscOverflow]) return;
   const size_t Nn = (size_t)N;
   const float q[4] = {P[Nn + i], P[2 * Nn + i], P[3 * Nn + i], P[4 * Nn + i]};
   float vals[11 + C];
-  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], cnt, off,
-                  gpair, GS, cap, vals);
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], cnt, pos,
+                  scap, ssum, vals);
   if (grads_out) {
 #pragma unroll
     for (int r = 0; r < 11 + C; ++r) grads_out[r * Nn + i] = vals[r];
@@ -370,8 +458,8 @@ void proj_bwd_launch(const Layout& L, void* ws, const rogs_surfels* s, float* gr
                      hipStream_t st) {
   hipLaunchKernelGGL((k_proj_bwd<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, s->x, s->y, s->z, s->q,
-                     s->s, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_off),
-                     at<const float>(ws, L.o_gpair), L.GS, L.cap, grads, acc ? 1 : 0);
+                     s->s, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_pos),
+                     L.scap, at<const float>(ws, L.o_ssum), grads, acc ? 1 : 0);
 }
 
 // One thread per pixel; grid.y = view, so a block never straddles views.
@@ -584,8 +672,8 @@ void proj_bwd_adam_launch(const Layout& L, void* ws, const float* x, const float
                           float* grads_out, const AdamArgs& aa, hipStream_t st) {
   hipLaunchKernelGGL((k_proj_bwd_adam<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, x, y, params, m, v,
-                     s_act, a_act, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_off),
-                     at<const float>(ws, L.o_gpair), L.GS, L.cap, grads_out, aa);
+                     s_act, a_act, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_pos),
+                     L.scap, at<const float>(ws, L.o_ssum), grads_out, aa);
 }
 }  // namespace
 
@@ -631,6 +719,28 @@ void launch_proj_bwd_adam(const Layout& L, void* ws, const float* x, const float
   if (expo)
     hipLaunchKernelGGL(k_adam_plain, dim3((unsigned)((2 * L.V + 63) / 64)), dim3(64), 0, st,
                        2 * L.V, expo, dexpo, me, ve, aa);
+}
+
+namespace {
+template <int C>
+void slot_sums_launch(const Layout& L, void* ws, hipStream_t st) {
+  uint32_t* misc = at<uint32_t>(ws, L.o_misc);
+  const int64_t s_grid = L.scap;
+  if (s_grid <= 0) return;
+  fill_u32(misc + kMiscLong, 0u, 1, st);
+  hipLaunchKernelGGL((k_slot_sums<C>), dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0, st,
+                     misc, L.scap, L.cap, at<const uint32_t>(ws, L.o_scnt),
+                     at<const uint32_t>(ws, L.o_soff), at<const float>(ws, L.o_gpair),
+                     at<float>(ws, L.o_ssum), at<uint32_t>(ws, L.o_long), misc + kMiscLong);
+  hipLaunchKernelGGL((k_slot_sums_long<C>), dim3(1024), dim3(64), 0, st,
+                     at<const uint32_t>(ws, L.o_long), misc + kMiscLong, L.cap,
+                     at<const uint32_t>(ws, L.o_scnt), at<const uint32_t>(ws, L.o_soff),
+                     at<const float>(ws, L.o_gpair), at<float>(ws, L.o_ssum));
+}
+}  // namespace
+
+void launch_slot_sums(const Layout& L, void* ws, hipStream_t st) {
+  ROGS_SEM_SWITCH(L.C, (slot_sums_launch<KC>(L, ws, st)));
 }
 
 void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st) {

@@ -1,5 +1,5 @@
 // Per-(view, surfel) culling and EWA projection (Eq. 5, supp. Sec. 2.1), tile
-// counts, their scan, and the emission of (tile, depth) sort keys.
+// counts and visible counts per block, their scans, and the generic scan.
 //
 // One thread owns one surfel and walks all views of the batch, so the surfel's
 // parameters are read from HBM once per batch; per-view results land in
@@ -47,10 +47,10 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
     const float* __restrict__ pq, const float* __restrict__ ps, const float* __restrict__ pa,
     const float* __restrict__ prgb, const float* __restrict__ psem, int C, int FS, int pack,
     uint32_t* __restrict__ cnt, float4* __restrict__ rec, uint2* __restrict__ rect,
-    uint32_t* __restrict__ part, float* __restrict__ feat, uint32_t* __restrict__ misc) {
+    uint32_t* __restrict__ part, uint32_t* __restrict__ partv, float* __restrict__ feat) {
   __shared__ uint32_t s_w[kProjBlock / 64];
+  __shared__ uint32_t s_v[kProjBlock / 64];
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
-  uint32_t nvis = 0;
   const bool valid = i < N;
   float x = 0, y = 0, z = 0, qw = 1, qx = 0, qy = 0, qz = 0, sx = 1, sy = 1, al = 0;
   if (valid) {
@@ -75,7 +75,6 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
       Proj p = project_contract(vw, eps, qcut, tw, th, x, y, z, qw, qx, qy, qz, sx, sy);
       const size_t slot = (size_t)v * N + i;
       if (p.vis) {
-        ++nvis;
         nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
         rec[2 * slot] = make_float4(p.uh, p.vh, p.ul, p.vl);
         rec[2 * slot + 1] = make_float4(p.A, p.B, p.C, p.tz);
@@ -85,67 +84,44 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
       cnt[slot] = nt;
     }
     uint32_t ws = wave_sum_u32(nt);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = ws;
+    const uint32_t wvis = (uint32_t)__popcll(__ballot(nt != 0));
+    if ((threadIdx.x & 63) == 0) {
+      s_w[threadIdx.x >> 6] = ws;
+      s_v[threadIdx.x >> 6] = wvis;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      uint32_t t = 0;
-      for (int w = 0; w < kProjBlock / 64; ++w) t += s_w[w];
+      uint32_t t = 0, tv = 0;
+      for (int w = 0; w < kProjBlock / 64; ++w) {
+        t += s_w[w];
+        tv += s_v[w];
+      }
       part[(size_t)v * nb + blockIdx.x] = t;
+      partv[(size_t)v * nb + blockIdx.x] = tv;
     }
     __syncthreads();
   }
-  nvis = wave_sum_u32(nvis);
-  if ((threadIdx.x & 63) == 0 && nvis) atomicAdd(misc + kMiscVisible, nvis);
 }
 
-__global__ void k_check_cap(uint32_t* misc, int64_t cap) {
+__global__ void k_check_cap(uint32_t* misc, int64_t cap, int64_t scap) {
   if (threadIdx.x == 0 && blockIdx.x == 0)
-    misc[kMiscOverflow] = ((int64_t)misc[kMiscPairs] > cap) ? 1u : 0u;
-}
-
-// Emission: pair e of surfel slot (v, i) covers tile (x0 + k % wx, y0 + k / wx);
-// pairs of one slot are consecutive and slots are in (view, surfel id) order,
-// which the stable sort turns into the id tie-break.
-__global__ __launch_bounds__(kProjBlock) void k_emit(
-    const ViewDev* __restrict__ views, int V, int N, int nb, const uint32_t* __restrict__ cnt,
-    const float4* __restrict__ rec, const uint2* __restrict__ rect,
-    const uint32_t* __restrict__ part_scan, int64_t cap, unsigned long long* __restrict__ keys,
-    uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ off) {
-  __shared__ uint32_t s_w[kProjBlock / 64];
-  const int i = blockIdx.x * kProjBlock + threadIdx.x;
-  const bool valid = i < N;
-  for (int v = 0; v < V; ++v) {
-    const size_t slot = (size_t)v * N + i;
-    uint32_t nt = valid ? cnt[slot] : 0u;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(nt, s_w, &tot);
-    uint32_t base = part_scan[(size_t)v * nb + blockIdx.x] + ex;
-    if (valid) off[slot] = base;
-    if (nt) {
-      const ViewDev& vw = views[v];
-      uint2 r = rect[slot];
-      int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
-      uint32_t db = __float_as_uint(rec[2 * slot + 1].w);
-      uint32_t e = base;
-      for (int ty = y0; ty < y1; ++ty) {
-        for (int tx = x0; tx < x1; ++tx, ++e) {
-          if ((int64_t)e < cap) {
-            uint32_t gt = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
-            keys[e] = ((unsigned long long)gt << 32) | db;
-            vals[e] = e;
-            pslot[e] = (uint32_t)slot;
-          }
-        }
-      }
-    }
-  }
+    misc[kMiscOverflow] =
+        ((int64_t)misc[kMiscPairs] > cap || (int64_t)misc[kMiscVisible] > scap) ? 1u : 0u;
 }
 
 // ------------------------------------------------------------ generic scan
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+__device__ __forceinline__ int64_t scan_count(const uint32_t* n_dev, int64_t n) {
+  if (!n_dev) return n;
+  const int64_t d = (int64_t)(*n_dev);
+  return d < n ? d : n;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n_cap,
+                                                     const uint32_t* __restrict__ n_dev,
                                                      uint32_t* __restrict__ sums) {
   __shared__ uint32_t s_w[4];
+  const int64_t n = scan_count(n_dev, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   uint32_t acc = 0;
   for (int k = threadIdx.x; k < kScanChunk; k += 256) {
@@ -185,11 +161,14 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, 
 }
 
 // in and out may be the same array (each block reads its chunk before writing it).
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n,
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n_cap,
+                                                   const uint32_t* __restrict__ n_dev,
                                                    const uint32_t* __restrict__ sums) {
   __shared__ uint32_t s_v[kScanChunk];
   __shared__ uint32_t s_w[4];
+  const int64_t n = scan_count(n_dev, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  if (base >= n) return;
   for (int k = threadIdx.x; k < kScanChunk; k += 256) {
     int64_t j = base + k;
     s_v[k] = (j < n) ? in[j] : 0u;
@@ -217,6 +196,43 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t*
   }
 }
 
+// Exclusive scan of at most kSmallScan values in one block of 1024 threads
+// (one launch instead of three for the small tables).
+constexpr int kSmallScan = 1024 * 32;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_t* out,
+                                                     int64_t n_cap,
+                                                     const uint32_t* __restrict__ n_dev,
+                                                     uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_w[16];
+  const int64_t n = scan_count(n_dev, n_cap);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = t * per, e = (b + per < n) ? b + per : n;
+  uint32_t v[32];
+  uint32_t loc = 0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    v[k] = (b + k < e) ? in[b + k] : 0u;
+    loc += v[k];
+  }
+  const uint32_t inc = wave_incl_scan(loc, lane);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    pre += (w < wv) ? s_w[w] : 0u;
+    tot += s_w[w];
+  }
+  uint32_t run = pre + inc - loc;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    if (b + k < e) out[b + k] = run;
+    run += v[k];
+  }
+  if (t == 0 && total) *total = tot;
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -230,10 +246,31 @@ size_t scan_tmp_words(int64_t n) { return (size_t)((n + kScanChunk - 1) / kScanC
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
               hipStream_t st) {
   if (n <= 0) return;
+  if (n <= kSmallScan) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, out, n,
+                       (const uint32_t*)nullptr, total);
+    return;
+  }
   int64_t m = (n + kScanChunk - 1) / kScanChunk;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)m), dim3(256), 0, st, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)m), dim3(256), 0, st, in, n,
+                     (const uint32_t*)nullptr, tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, m, total);
-  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)m), dim3(256), 0, st, in, out, n, tmp);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)m), dim3(256), 0, st, in, out, n,
+                     (const uint32_t*)nullptr, tmp);
+}
+
+void scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
+                  uint32_t* tmp, hipStream_t st) {
+  if (n_cap <= 0) return;
+  if (n_cap <= kSmallScan) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, out, n_cap, n_dev,
+                       (uint32_t*)nullptr);
+    return;
+  }
+  int64_t m = (n_cap + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)m), dim3(256), 0, st, in, n_cap, n_dev, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, m, (uint32_t*)nullptr);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)m), dim3(256), 0, st, in, out, n_cap, n_dev, tmp);
 }
 
 void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
@@ -250,24 +287,17 @@ void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
                      L.th, s->x, s->y, s->z, s->q, s->s, s->alpha, s->rgb, s->sem, L.C, L.FS,
                      pack_feat ? 1 : 0, at<uint32_t>(ws, L.o_cnt), at<float4>(ws, L.o_rec),
-                     at<uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_part), at<float>(ws, L.o_feat),
-                     at<uint32_t>(ws, L.o_misc));
+                     at<uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
+                     at<float>(ws, L.o_feat));
 }
 
 void launch_scan_part(const Layout& L, void* ws, hipStream_t st) {
   uint32_t* misc = at<uint32_t>(ws, L.o_misc);
   scan_u32(at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_part), (int64_t)L.V * L.nb,
            misc + kMiscPairs, at<uint32_t>(ws, L.o_parttmp), st);
-  hipLaunchKernelGGL(k_check_cap, dim3(1), dim3(64), 0, st, misc, L.cap);
-}
-
-void launch_emit(const Layout& L, void* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_emit, dim3(L.nb), dim3(kProjBlock), 0, st,
-                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb,
-                     at<const uint32_t>(ws, L.o_cnt), at<const float4>(ws, L.o_rec),
-                     at<const uint2>(ws, L.o_rect), at<const uint32_t>(ws, L.o_part), L.cap,
-                     at<unsigned long long>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
-                     at<uint32_t>(ws, L.o_pslot), at<uint32_t>(ws, L.o_off));
+  scan_u32(at<uint32_t>(ws, L.o_partv), at<uint32_t>(ws, L.o_partv), (int64_t)L.V * L.nb,
+           misc + kMiscVisible, at<uint32_t>(ws, L.o_parttmp), st);
+  hipLaunchKernelGGL(k_check_cap, dim3(1), dim3(64), 0, st, misc, L.cap, L.scap);
 }
 
 }  // namespace rogs

@@ -30,93 +30,6 @@ __device__ __forceinline__ int find_view(const ViewDev* __restrict__ views, int 
   return lo;
 }
 
-// ---------------------------------------------------------------------------
-// Wave reduce-scatter of N per-lane values (gfx950).  Six exchange stages pair
-// every lane with its partner across lane bit 32, 16, 8, 4, 2, 1.  While a lane
-// still holds more than one value, each stage halves the list: the lane with
-// the bit clear keeps the first half and the partner the second half, and each
-// adds what the other sends (so the lane sends the half it gives away).  The
-// stages use v_permlane32_swap, v_permlane16_swap (both swap whole half-waves
-// between two registers, so one swap serves both directions) and DPP
-// row_mirror (bit 8), row_half_mirror (bit 4) and quad_perm (bits 2, 1).  After
-// the six stages lane l holds the wave total of component rs_comp(l, N); lanes
-// that differ only in bits where a single value was left hold identical bits.
-
-__host__ __device__ constexpr int rs_half(int n) { return (n + 1) / 2; }
-
-// Component held by lane l after reducing N values (-1: padding).
-__host__ __device__ constexpr int rs_comp(int lane, int N) {
-  int arr = N, valid = N, off = 0;
-  for (int s = 0; s < 6; ++s) {
-    const int bit = 32 >> s;
-    if (arr > 1) {
-      const int h = rs_half(arr);
-      if (lane & bit) {
-        off += h;
-        valid = valid - h > 0 ? valid - h : 0;
-      } else {
-        valid = valid < h ? valid : h;
-      }
-      arr = h;
-    }
-  }
-  return valid >= 1 ? off : -1;
-}
-
-// Lane bits of the stages where only one value was left (its holders agree).
-__host__ __device__ constexpr int rs_dup_bits(int N) {
-  int arr = N, m = 0;
-  for (int s = 0; s < 6; ++s) {
-    if (arr > 1) arr = rs_half(arr); else m |= 32 >> s;
-  }
-  return m;
-}
-
-template <int STAGE>
-__device__ __forceinline__ float rs_dpp(float x) {
-  constexpr int ctrl = STAGE == 2 ? 0x140 : STAGE == 3 ? 0x141 : STAGE == 4 ? 0x4E : 0xB1;
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false));
-}
-
-template <int N, int STAGE>
-__device__ __forceinline__ void rs_stage(const float* in, float* out, int lane) {
-  constexpr int H = N > 1 ? rs_half(N) : 1;
-#pragma unroll
-  for (int k = 0; k < H; ++k) {
-    const float a = in[k];
-    const float b = (N == 1) ? in[0] : ((k + H < N) ? in[k + H] : 0.0f);
-    if constexpr (STAGE == 0) {
-      const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-      out[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    } else if constexpr (STAGE == 1) {
-      const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-      out[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    } else {
-      const bool hi = (lane & (32 >> STAGE)) != 0;
-      const float mine = hi ? b : a;
-      const float other = hi ? a : b;
-      out[k] = mine + rs_dpp<STAGE>(other);
-    }
-  }
-}
-
-template <int N>
-__device__ __forceinline__ float wave_reduce_scatter(const float* v, int lane) {
-  constexpr int N1 = N > 1 ? rs_half(N) : 1;
-  constexpr int N2 = N1 > 1 ? rs_half(N1) : 1;
-  constexpr int N3 = N2 > 1 ? rs_half(N2) : 1;
-  constexpr int N4 = N3 > 1 ? rs_half(N3) : 1;
-  constexpr int N5 = N4 > 1 ? rs_half(N4) : 1;
-  float t1[N1], t2[N2], t3[N3], t4[N4], t5[N5], t6[1];
-  rs_stage<N, 0>(v, t1, lane);
-  rs_stage<N1, 1>(t1, t2, lane);
-  rs_stage<N2, 2>(t2, t3, lane);
-  rs_stage<N3, 3>(t3, t4, lane);
-  rs_stage<N4, 4>(t4, t5, lane);
-  rs_stage<N5, 5>(t5, t6, lane);
-  return t6[0];
-}
-static_assert(rs_comp(0, 18) == 0 && rs_comp(63, 18) == -1, "reduce-scatter map");
 
 // Tile-major per-pixel record of the fused path: channel ch of in-tile pixel
 // p of global tile gt is at tm[(gt * NCH + ch) * (64 * PPL) + p], with NCH =

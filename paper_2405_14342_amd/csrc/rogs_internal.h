@@ -13,8 +13,7 @@ constexpr int kProjBlock = 256;     // threads per block of the per-surfel kerne
 constexpr int kSortBlock = 256;     // threads per radix-sort block
 constexpr int kSortIPT = 16;        // keys per thread per radix-sort block
 constexpr int kSortTile = kSortBlock * kSortIPT;
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixMax = 512;     // largest radix of the sorts (9-bit digits)
 constexpr int kScanChunk = 4096;    // elements per block of the generic scan
 constexpr int kMaxViews = 4096;
 
@@ -46,22 +45,25 @@ struct Layout {
   int32_t nb = 0;              // blocks of kProjBlock surfels
   int32_t tile_bits = 1;
   int64_t total_pix = 0, total_tiles = 0, max_view_pix = 0, cap = 0;
+  int64_t scap = 0;            // visible-slot capacity (<= cap)
   int64_t slots = 0;           // V * N
   int64_t sort_blocks = 0;     // ceil(cap / kSortTile)
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
-  size_t o_views, o_cnt, o_off, o_rec, o_rect, o_feat, o_part, o_parttmp;
+  size_t o_views, o_cnt, o_rec, o_rect, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
+  size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
+  size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
   size_t o_hist, o_histtmp, o_misc, o_lpart, o_mcount;
   size_t o_tm = 0, o_tpart = 0, o_state = 0;    // fused path only (0 = absent)
   size_t total = 0;
 };
 
 // misc counters (uint32 slots at o_misc)
-enum MiscSlot { kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscCount = 16 };
+enum MiscSlot { kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscLong = 3, kMiscCount = 16 };
 
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
-                const rogs_render_opts* opts, int64_t cap, Layout* L, const char** why,
-                bool fused = false);
+                const rogs_render_opts* opts, int64_t cap, int64_t scap, Layout* L,
+                const char** why, bool fused = false);
 
 template <typename T>
 __host__ __device__ inline T* at(void* ws, size_t off) {
@@ -203,6 +205,94 @@ __device__ __forceinline__ float pixel_offset(float pc, float hi, float lo) {
   return (pc - hi) - lo;
 }
 
+// ---------------------------------------------------------------------------
+// Wave reduce-scatter of N per-lane values (gfx950).  Six exchange stages pair
+// every lane with its partner across lane bit 32, 16, 8, 4, 2, 1.  While a lane
+// still holds more than one value, each stage halves the list: the lane with
+// the bit clear keeps the first half and the partner the second half, and each
+// adds what the other sends (so the lane sends the half it gives away).  The
+// stages use v_permlane32_swap, v_permlane16_swap (both swap whole half-waves
+// between two registers, so one swap serves both directions) and DPP
+// row_mirror (bit 8), row_half_mirror (bit 4) and quad_perm (bits 2, 1).  After
+// the six stages lane l holds the wave total of component rs_comp(l, N); lanes
+// that differ only in bits where a single value was left hold identical bits.
+
+__host__ __device__ constexpr int rs_half(int n) { return (n + 1) / 2; }
+
+// Component held by lane l after reducing N values (-1: padding).
+__host__ __device__ constexpr int rs_comp(int lane, int N) {
+  int arr = N, valid = N, off = 0;
+  for (int s = 0; s < 6; ++s) {
+    const int bit = 32 >> s;
+    if (arr > 1) {
+      const int h = rs_half(arr);
+      if (lane & bit) {
+        off += h;
+        valid = valid - h > 0 ? valid - h : 0;
+      } else {
+        valid = valid < h ? valid : h;
+      }
+      arr = h;
+    }
+  }
+  return valid >= 1 ? off : -1;
+}
+
+// Lane bits of the stages where only one value was left (its holders agree).
+__host__ __device__ constexpr int rs_dup_bits(int N) {
+  int arr = N, m = 0;
+  for (int s = 0; s < 6; ++s) {
+    if (arr > 1) arr = rs_half(arr); else m |= 32 >> s;
+  }
+  return m;
+}
+
+template <int STAGE>
+__device__ __forceinline__ float rs_dpp(float x) {
+  constexpr int ctrl = STAGE == 2 ? 0x140 : STAGE == 3 ? 0x141 : STAGE == 4 ? 0x4E : 0xB1;
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false));
+}
+
+template <int N, int STAGE>
+__device__ __forceinline__ void rs_stage(const float* in, float* out, int lane) {
+  constexpr int H = N > 1 ? rs_half(N) : 1;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const float a = in[k];
+    const float b = (N == 1) ? in[0] : ((k + H < N) ? in[k + H] : 0.0f);
+    if constexpr (STAGE == 0) {
+      const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+      out[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else if constexpr (STAGE == 1) {
+      const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+      out[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+      const bool hi = (lane & (32 >> STAGE)) != 0;
+      const float mine = hi ? b : a;
+      const float other = hi ? a : b;
+      out[k] = mine + rs_dpp<STAGE>(other);
+    }
+  }
+}
+
+template <int N>
+__device__ __forceinline__ float wave_reduce_scatter(const float* v, int lane) {
+  constexpr int N1 = N > 1 ? rs_half(N) : 1;
+  constexpr int N2 = N1 > 1 ? rs_half(N1) : 1;
+  constexpr int N3 = N2 > 1 ? rs_half(N2) : 1;
+  constexpr int N4 = N3 > 1 ? rs_half(N3) : 1;
+  constexpr int N5 = N4 > 1 ? rs_half(N4) : 1;
+  float t1[N1], t2[N2], t3[N3], t4[N4], t5[N5], t6[1];
+  rs_stage<N, 0>(v, t1, lane);
+  rs_stage<N1, 1>(t1, t2, lane);
+  rs_stage<N2, 2>(t2, t3, lane);
+  rs_stage<N3, 3>(t3, t4, lane);
+  rs_stage<N4, 4>(t4, t5, lane);
+  rs_stage<N5, 5>(t5, t6, lane);
+  return t6[0];
+}
+static_assert(rs_comp(0, 18) == 0 && rs_comp(63, 18) == -1, "reduce-scatter map");
+
 // ------------------------------------------------------------------ loss seed
 
 // Per-pixel loss of Eq. 7-9 and 12 for one masked pixel.  o: the composited
@@ -300,8 +390,9 @@ struct AdamArgs {
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
                     hipStream_t st);
 void launch_scan_part(const Layout& L, void* ws, hipStream_t st);
-void launch_emit(const Layout& L, void* ws, hipStream_t st);
-int launch_sort(const Layout& L, void* ws, int64_t n_host, hipStream_t st);
+// Compaction and depth sort of the visible slots, emission, sort of the pairs
+// by tile.  Counts < 0 are read on the device.  Returns the buffer parity.
+int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st);
 void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st);
 int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* out, hipStream_t st);
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,
@@ -310,6 +401,8 @@ int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels* s, const fl
                       const float* G, hipStream_t st);
 int launch_render_fwd_fused(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st);
 int launch_render_bwd_fused(const Layout& L, void* ws, hipStream_t st);
+// Per-slot sums of the per-pair gradient records (before the projection adjoint).
+void launch_slot_sums(const Layout& L, void* ws, hipStream_t st);
 void launch_proj_bwd(const Layout& L, void* ws, const rogs_surfels* s, float* grads,
                      bool accumulate, hipStream_t st);
 void launch_adam(int n, int C, float* params, const float* grads, float* m, float* v,
@@ -330,6 +423,9 @@ void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs
 // Exclusive scan of n uint32 values; total written to *total (device) if non-null.
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
               hipStream_t st);
+// Same with the count read on the device (at most n_cap).
+void scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
+                  uint32_t* tmp, hipStream_t st);
 size_t scan_tmp_words(int64_t n);
 void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st);
 

@@ -1,13 +1,13 @@
-// Stable LSD radix sort of the (tile, depth) keys with their pair values, and
-// per-tile ranges of the sorted list ("ascending order of original depth",
-// Sec. 3.3.1; ties keep the emission order, i.e. surfel id).
+// Binning: depth order of the visible (view, surfel) slots, emission of one
+// (tile) key per covered tile in that order, a stable radix sort of the pairs
+// by tile, and per-tile ranges.  The result is every tile's list in ascending
+// order of original depth with ties by surfel id (Sec. 3.3.1).
 //
-// Each pass: per-block digit histograms (LDS atomics) -> one exclusive scan
-// over the digit-major histogram table -> stable scatter.  In the scatter a
-// block owns kSortTile consecutive keys; each of its four waves ranks a
-// contiguous quarter, 64 keys at a time, finding lanes with equal digits by
-// eight ballots (one per digit bit), so the rank inside the block follows the
-// input order exactly.
+// Stable LSD radix sort: per pass, per-block digit histograms (LDS atomics),
+// one exclusive scan over the digit-major histogram table, then a stable
+// scatter.  In the scatter a block owns kSortTile consecutive keys; each of its
+// four waves ranks a contiguous quarter, 64 keys at a time, finding lanes with
+// equal digits with one ballot per digit bit, so ranks follow the input order.
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -20,13 +20,15 @@ __device__ __forceinline__ uint32_t count_n(const uint32_t* n_dev, int64_t n_hos
   return (uint32_t)(n < cap ? n : cap);
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_hist(const unsigned long long* __restrict__ keys,
+template <typename K, int RB>
+__global__ __launch_bounds__(kSortBlock) void k_hist(const K* __restrict__ keys,
                                                      const uint32_t* __restrict__ n_dev,
                                                      int64_t n_host, int64_t cap, int shift,
                                                      uint32_t mask, uint32_t* __restrict__ hist,
                                                      int64_t nblk) {
-  __shared__ uint32_t h[kRadix];
-  h[threadIdx.x] = 0;
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t h[R];
+  for (int d = threadIdx.x; d < R; d += kSortBlock) h[d] = 0;
   __syncthreads();
   const uint32_t n = count_n(n_dev, n_host, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -38,23 +40,24 @@ __global__ __launch_bounds__(kSortBlock) void k_hist(const unsigned long long* _
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < R; d += kSortBlock) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
 }
 
+template <typename K, int RB>
 __global__ __launch_bounds__(kSortBlock) void k_scatter(
-    const unsigned long long* __restrict__ kin, const uint32_t* __restrict__ vin,
-    unsigned long long* __restrict__ kout, uint32_t* __restrict__ vout,
-    const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap, int shift, uint32_t mask,
-    int nbits, const uint32_t* __restrict__ hist_scan, int64_t nblk) {
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
+    int shift, uint32_t mask, int nbits, const uint32_t* __restrict__ hist_scan, int64_t nblk) {
+  constexpr int R = 1 << RB;
   constexpr int kWaves = kSortBlock / 64;
   constexpr int kPerWave = kSortTile / kWaves;
   constexpr int kIters = kPerWave / 64;
-  __shared__ uint32_t wcnt[kWaves][kRadix];
+  __shared__ uint32_t wcnt[kWaves][R];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t n = count_n(n_dev, n_host, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= (int64_t)n) return;
-  for (int k = threadIdx.x; k < kWaves * kRadix; k += kSortBlock) (&wcnt[0][0])[k] = 0;
+  for (int k = threadIdx.x; k < kWaves * R; k += kSortBlock) (&wcnt[0][0])[k] = 0;
   __syncthreads();
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t rank[kIters];
@@ -80,8 +83,7 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
   }
   __syncthreads();
   // per digit: global start of this block, then the waves one after another
-  {
-    const int d = threadIdx.x;   // kSortBlock == kRadix
+  for (int d = threadIdx.x; d < R; d += kSortBlock) {
     uint32_t run = hist_scan[(int64_t)d * nblk + blockIdx.x];
     for (int w = 0; w < kWaves; ++w) {
       uint32_t c = wcnt[w][d];
@@ -100,46 +102,178 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
   }
 }
 
-__global__ void k_ranges(const unsigned long long* __restrict__ keys,
-                         const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
-                         uint2* __restrict__ ranges) {
+// Stable LSD sort of (keys, vals) over the low key_bits bits in as few passes
+// of at most RB bits as possible.  Returns 1 when the result is in the
+// alternate buffers, 0 when it is back in keys / vals.
+template <typename K, int RB>
+int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, int64_t n_host,
+               int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st) {
+  const int passes = (key_bits + RB - 1) / RB;
+  const int width = (key_bits + passes - 1) / passes;
+  const int64_t n_grid = n_dev ? cap : n_host;
+  if (n_grid <= 0 || passes == 0) return passes & 1;
+  const int64_t nblk = (n_grid + kSortTile - 1) / kSortTile;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * width;
+    const int nbits = (key_bits - shift) < width ? (key_bits - shift) : width;
+    const uint32_t mask = (1u << nbits) - 1u;
+    hipLaunchKernelGGL((k_hist<K, RB>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
+                       n_grid, cap, shift, mask, hist, nblk);
+    scan_u32(hist, hist, (int64_t)(1 << RB) * nblk, nullptr, histtmp, st);
+    hipLaunchKernelGGL((k_scatter<K, RB>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
+                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk);
+    K* tk = k0; k0 = k1; k1 = tk;
+    uint32_t* tv = v0; v0 = v1; v1 = tv;
+  }
+  return passes & 1;
+}
+
+// Visible slots in (view, surfel) order with their (view, depth bits) keys.
+__global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
+                                                        const uint32_t* __restrict__ cnt,
+                                                        const float4* __restrict__ rec,
+                                                        const uint32_t* __restrict__ partv,
+                                                        int64_t scap,
+                                                        unsigned long long* __restrict__ skey,
+                                                        uint32_t* __restrict__ sval) {
+  __shared__ uint32_t s_w[kProjBlock / 64];
+  const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  const bool valid = i < N;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int v = 0; v < V; ++v) {
+    const size_t slot = (size_t)v * N + i;
+    const bool vis = valid && cnt[slot] != 0;
+    const unsigned long long b = __ballot(vis);
+    if (lane == 0) s_w[wv] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t pre = partv[(size_t)v * nb + blockIdx.x];
+    for (int w = 0; w < wv; ++w) pre += s_w[w];
+    __syncthreads();
+    if (vis) {
+      const uint32_t pos = pre + (uint32_t)__popcll(b & lt_mask);
+      if ((int64_t)pos < scap) {
+        skey[pos] = ((unsigned long long)v << 32) | __float_as_uint(rec[2 * slot + 1].w);
+        sval[pos] = (uint32_t)slot;
+      }
+    }
+  }
+}
+
+__global__ void k_gather_cnt(const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
+                             const uint32_t* __restrict__ sval, const uint32_t* __restrict__ cnt,
+                             uint32_t* __restrict__ scnt) {
+  const uint32_t n = count_n(n_dev, n_host, cap);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < (int64_t)n) scnt[k] = cnt[sval[k]];
+}
+
+// Emission in depth-sorted slot order, one block per 256 sorted slots: the
+// block's pairs e in [soff[first], soff[last + 1]) are spread over its
+// threads; each finds its slot by binary search over the block's offsets and
+// writes key = global tile, value = e, pslot[e] = slot.
+__global__ __launch_bounds__(kProjBlock) void k_emit(
+    const ViewDev* __restrict__ views, int N, const uint32_t* __restrict__ n_dev, int64_t n_host,
+    int64_t scap, int64_t cap, const uint32_t* __restrict__ sval,
+    const uint32_t* __restrict__ soff, const uint32_t* __restrict__ scnt,
+    const uint2* __restrict__ rect, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    uint32_t* __restrict__ pslot, uint32_t* __restrict__ pos) {
+  __shared__ uint32_t s_off[kProjBlock + 1];
+  __shared__ uint32_t s_slot[kProjBlock];
+  __shared__ uint2 s_rect[kProjBlock];
+  const uint32_t S = count_n(n_dev, n_host, scap);
+  const int64_t k0 = (int64_t)blockIdx.x * kProjBlock;
+  if (k0 >= (int64_t)S) return;
+  const int nloc = (int)min<int64_t>(kProjBlock, (int64_t)S - k0);
+  const int t = threadIdx.x;
+  if (t < nloc) {
+    const uint32_t slot = sval[k0 + t];
+    const uint32_t o = soff[k0 + t];
+    s_slot[t] = slot;
+    s_off[t] = o;
+    s_rect[t] = rect[slot];
+    pos[slot] = (uint32_t)(k0 + t);
+    if (t == nloc - 1) s_off[nloc] = o + scnt[k0 + t];
+  }
+  __syncthreads();
+  const uint32_t e0 = s_off[0], e1 = s_off[nloc];
+  for (uint32_t e = e0 + t; e < e1; e += kProjBlock) {
+    if ((int64_t)e >= cap) break;
+    int lo = 0, hi = nloc - 1;            // last j with s_off[j] <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t slot = s_slot[lo];
+    const uint2 r = s_rect[lo];
+    const int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff;
+    const int wx = x1 - x0;
+    const int kk = (int)(e - s_off[lo]);
+    const int ty = y0 + kk / wx, tx = x0 + kk % wx;
+    const ViewDev& vw = views[slot / (uint32_t)N];
+    keys[e] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
+    vals[e] = e;
+    pslot[e] = slot;
+  }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                         int64_t n_host, int64_t cap, uint2* __restrict__ ranges) {
   const uint32_t n = count_n(n_dev, n_host, cap);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (uint32_t)i;
-  if (i == (int64_t)n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (uint32_t)(i + 1);
+  const uint32_t t = keys[i];
+  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
+  if (i == (int64_t)n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
 }  // namespace
 
-// Sort the batch's keys/vals.  n_host >= 0: the pair count is known on the
-// host; < 0: it is read on the device.  Returns 1 when the sorted result is in
-// the alternate buffers (o_keys2 / o_vals2), 0 when it is in o_keys / o_vals.
-int launch_sort(const Layout& L, void* ws, int64_t n_host, hipStream_t st) {
-  const uint32_t* n_dev = n_host < 0 ? at<uint32_t>(ws, L.o_misc) + kMiscPairs : nullptr;
-  const int64_t n_grid = n_host < 0 ? L.cap : n_host;
-  const int key_bits = 32 + L.tile_bits;
-  const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
-  if (n_grid <= 0) return passes & 1;
-  const int64_t nblk = (n_grid + kSortTile - 1) / kSortTile;
-  unsigned long long* k0 = at<unsigned long long>(ws, L.o_keys);
-  unsigned long long* k1 = at<unsigned long long>(ws, L.o_keys2);
-  uint32_t* v0 = at<uint32_t>(ws, L.o_vals);
-  uint32_t* v1 = at<uint32_t>(ws, L.o_vals2);
+// Binning of the current batch.  n_pairs / n_vis >= 0: counts known on the
+// host (exact grids); < 0: read on the device (grids sized by the capacity).
+// Returns 1 when the sorted pairs are in the alternate buffers.
+int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st) {
+  uint32_t* misc = at<uint32_t>(ws, L.o_misc);
+  const uint32_t* p_dev = n_pairs < 0 ? misc + kMiscPairs : nullptr;
+  const uint32_t* s_dev = n_vis < 0 ? misc + kMiscVisible : nullptr;
+  const int64_t s_grid = n_vis < 0 ? L.scap : n_vis;
+  const int64_t p_grid = n_pairs < 0 ? L.cap : n_pairs;
   uint32_t* hist = at<uint32_t>(ws, L.o_hist);
-  for (int shift = 0; shift < key_bits; shift += kRadixBits) {
-    const int nbits = (key_bits - shift) < kRadixBits ? (key_bits - shift) : kRadixBits;
-    const uint32_t mask = (1u << nbits) - 1u;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
-                       n_grid, L.cap, shift, mask, hist, nblk);
-    scan_u32(hist, hist, (int64_t)kRadix * nblk, nullptr, at<uint32_t>(ws, L.o_histtmp), st);
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0, k1, v1,
-                       n_dev, n_grid, L.cap, shift, mask, nbits, hist, nblk);
-    unsigned long long* tk = k0; k0 = k1; k1 = tk;
-    uint32_t* tv = v0; v0 = v1; v1 = tv;
+  uint32_t* histtmp = at<uint32_t>(ws, L.o_histtmp);
+  // 1. visible slots with (view, depth) keys, in (view, surfel id) order
+  hipLaunchKernelGGL(k_compact, dim3(L.nb), dim3(kProjBlock), 0, st, L.V, L.N, L.nb,
+                     at<const uint32_t>(ws, L.o_cnt), at<const float4>(ws, L.o_rec),
+                     at<const uint32_t>(ws, L.o_partv), L.scap,
+                     at<unsigned long long>(ws, L.o_skey), at<uint32_t>(ws, L.o_sval));
+  // 2. stable sort by (view, depth): ties keep surfel-id order
+  int view_bits = 0;
+  while ((1 << view_bits) < L.V) ++view_bits;
+  unsigned long long* sk = at<unsigned long long>(ws, L.o_skey);
+  unsigned long long* sk2 = at<unsigned long long>(ws, L.o_keys2);   // free until emission
+  uint32_t* sv = at<uint32_t>(ws, L.o_sval);
+  uint32_t* sv2 = at<uint32_t>(ws, L.o_vals2);
+  if (radix_sort<unsigned long long, 8>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
+                                        hist, histtmp, st)) {
+    sv = sv2;
   }
-  return passes & 1;
+  // 3. emission offsets in depth order
+  uint32_t* scnt = at<uint32_t>(ws, L.o_scnt);
+  uint32_t* soff = at<uint32_t>(ws, L.o_soff);
+  if (s_grid > 0) {
+    hipLaunchKernelGGL(k_gather_cnt, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0, st,
+                       s_dev, s_grid, L.scap, sv, at<const uint32_t>(ws, L.o_cnt), scnt);
+    scan_u32_dev(scnt, soff, s_dev, s_grid, at<uint32_t>(ws, L.o_parttmp2), st);
+    // 4. one key per covered tile
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((s_grid + kProjBlock - 1) / kProjBlock)),
+                       dim3(kProjBlock), 0, st, at<const ViewDev>(ws, L.o_views), L.N, s_dev,
+                       s_grid, L.scap, L.cap, sv, soff, scnt, at<const uint2>(ws, L.o_rect),
+                       at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
+                       at<uint32_t>(ws, L.o_pslot), at<uint32_t>(ws, L.o_pos));
+  }
+  // 5. stable sort of the pairs by tile
+  return radix_sort<uint32_t, 9>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
+                                 at<uint32_t>(ws, L.o_keys2), at<uint32_t>(ws, L.o_vals2), p_dev,
+                                 p_grid, L.cap, L.tile_bits, hist, histtmp, st);
 }
 
 void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st) {
@@ -149,7 +283,7 @@ void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st) {
   const int64_t n_grid = n_host < 0 ? L.cap : n_host;
   if (n_grid <= 0) return;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_grid + 255) / 256)), dim3(256), 0, st,
-                     at<const unsigned long long>(ws, L.o_keys), n_dev, n_grid, L.cap, ranges);
+                     at<const uint32_t>(ws, L.o_keys), n_dev, n_grid, L.cap, ranges);
 }
 
 }  // namespace rogs

@@ -108,6 +108,8 @@ class TrainState:
         self.rg = B.Rogs()
         self.cap_view = pair_capacity or 1 << 20
         self.cap_batch = pair_capacity or 1 << 22
+        self.cap_fused = self.cap_batch
+        self.scap_fused = 0          # visible-slot capacity; 0 = the pair capacity
         self._ws_view = None
         self._ws_batch = None
         self.step_count = 0
@@ -136,8 +138,8 @@ class TrainState:
                          LAMBDA_C, LAMBDA_S, 1.0 / self.V)
 
     # ---------------------------------------------------------- workspace
-    def _workspace(self, cams, cap, which):
-        size = B.workspace_size(self.surfels(), cams, self.opts, cap)
+    def _workspace(self, cams, cap, which, scap=0):
+        size = B.workspace_size(self.surfels(), cams, self.opts, cap, scap)
         cur = getattr(self, which)
         if cur is None or cur.numel() < size:
             cur = torch.empty(size, dtype=torch.uint8, device=self.dev)
@@ -156,8 +158,8 @@ class TrainState:
             n = self.rg.bin_sort(ws, B.SYNC_COUNT, raise_on_capacity=False)
             if n >= 0:
                 return ws, n
-            need = -n - 1
-            setattr(self, cap_attr, int(need * 1.25) + 4096)
+            st = self.rg.batch_stats(ws)
+            setattr(self, cap_attr, int(max(st["pairs"], st["visible"]) * 1.25) + 4096)
 
     # -------------------------------------------------------------- steps
     def forward_view(self, v: int):
@@ -225,24 +227,34 @@ class TrainState:
         ts = self.train_state(grads_out)
         optim = paper_optim(self.scene.extent, total_steps)
         flags = B.FUSED_EAGER if eager else 0
-        if not hasattr(self, "cap_fused"):
-            self.cap_fused = self.cap_batch
         for _ in range(8):
-            size = B.fused_workspace_size(ts, self.cams, self.opts, self.cap_fused)
+            size = B.fused_workspace_size(ts, self.cams, self.opts, self.cap_fused, self.scap_fused)
             if getattr(self, "_ws_fused", None) is None or self._ws_fused.numel() < size:
                 self._ws_fused = torch.empty(size, dtype=torch.uint8, device=self.dev)
             r = self.rg.step_fused(ts, self.cams, self.opts, self.targets(0, self.V), optim,
-                                   self._ws_fused, self.cap_fused, flags, raise_on_capacity=False)
+                                   self._ws_fused, self.cap_fused, flags, raise_on_capacity=False,
+                                   slot_capacity=self.scap_fused)
             if r == B.ECAPACITY:
-                self.cap_fused = int(self.rg.fused_status()["pairs"] * 1.25) + 4096
+                self._grow_fused(self.rg.fused_status())
                 continue
             if not check:
                 return
             st = self.rg.fused_status()
             if not st["overflow"]:
                 return
-            self.cap_fused = int(st["pairs"] * 1.25) + 4096
+            self._grow_fused(st)
         raise RuntimeError("pair capacity did not converge")
+
+    def _grow_fused(self, st, slack: float = 1.25):
+        self.cap_fused = max(self.cap_fused, int(st["pairs"] * slack) + 4096)
+        self.scap_fused = max(self.scap_fused, int(st["visible"] * slack) + 4096)
+
+    def fit_fused_capacity(self, slack: float = 1.1):
+        """Shrinks the fused step's capacities to the last step's counts plus a
+        margin (kernels waiting for device-side counts are sized by them)."""
+        st = self.rg.fused_status()
+        self.cap_fused = int(st["pairs"] * slack) + 4096
+        self.scap_fused = int(st["visible"] * slack) + 4096
 
     def fused_status(self) -> dict:
         """Waits for the last fused step and returns its statistics."""

@@ -61,9 +61,10 @@ def test_workspace_size_grows_with_capacity_and_views():
     a = B.workspace_size(s, sc.cams, o, 1000)
     b = B.workspace_size(s, sc.cams, o, 100000)
     c = B.workspace_size(s, sc.cams * 3, o, 100000)
-    assert 0 < a < b < c
-    # per pair: keys x2, vals x2, emission slot, gradient record (C = 8 -> 20 floats)
-    assert b - a >= (100000 - 1000) * (8 * 2 + 4 * 3 + 4 * 20)
+    d = B.workspace_size(s, sc.cams, o, 100000, 2000)
+    assert 0 < a < d < b < c
+    # per pair: keys (4 + 8), vals x2, emission slot, gradient record (C = 8 -> 20 floats)
+    assert d - a >= (100000 - 1000) * (4 + 8 + 4 * 3 + 4 * 20)
 
 
 @pytest.mark.parametrize("bad", ["n", "sem", "views", "cap", "tile", "tile2", "eps", "amax",
@@ -103,7 +104,7 @@ def test_workspace_size_rejects_invalid(bad):
     L = B.load_library()
     arr = B.camera_array(cams)
     out = ctypes.c_size_t(0)
-    r = L.rogs_workspace_size(ctypes.byref(s), arr, nv, ctypes.byref(o), cap, ctypes.byref(out))
+    r = L.rogs_workspace_size(ctypes.byref(s), arr, nv, ctypes.byref(o), cap, 0, ctypes.byref(out))
     assert r == B.EINVAL
 
 
@@ -111,9 +112,11 @@ def test_workspace_size_null_arguments():
     L = B.load_library()
     out = ctypes.c_size_t(0)
     o = B.make_opts()
-    assert L.rogs_workspace_size(None, None, 1, ctypes.byref(o), 10, ctypes.byref(out)) == B.EINVAL
+    assert L.rogs_workspace_size(None, None, 1, ctypes.byref(o), 10, 0, ctypes.byref(out)) == B.EINVAL
     assert L.rogs_workspace_size(ctypes.byref(_surf()), B.camera_array(synth.config1().cams), 1,
-                                 ctypes.byref(o), 10, None) == B.EINVAL
+                                 ctypes.byref(o), 10, 0, None) == B.EINVAL
+    assert L.rogs_workspace_size(ctypes.byref(_surf()), B.camera_array(synth.config1().cams), 1,
+                                 ctypes.byref(o), 10, -1, ctypes.byref(out)) == B.EINVAL
 
 
 def test_null_context_is_rejected():

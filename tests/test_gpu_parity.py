@@ -36,6 +36,13 @@ def make_scene(name):
         return synth.mini_strip()
     if name == "mini16":
         return synth.mini_strip(n_along=160, n_across=40, n_sem=16, w=200, h=120, cfg_index=8)
+    if name == "big":
+        # large footprints: 76 of the 100 slots cover more than 32 tiles of
+        # 16 x 16 (summed by a wave), 28 more than 64, up to all 120
+        sc = synth.tiny_scene(nx=10, ny=10, n_sem=3, w=192, h=160, f=140.0, seed=21)
+        sc.s[:] = sc.s * np.float32(5.0)
+        sc.log_s[:] = np.log(sc.s.astype(np.float64)).astype(np.float32)
+        return sc
     if name == "ortho":
         sc = synth.mini_strip(n_along=120, n_across=50, n_sem=4, cfg_index=9)
         c = sc.cams[0]
@@ -46,7 +53,7 @@ def make_scene(name):
     raise KeyError(name)
 
 
-SCENES = ["c1", "tiny2", "mini", "mini16", "ortho"]
+SCENES = ["c1", "tiny2", "mini", "mini16", "ortho", "big"]
 
 
 @pytest.fixture(scope="module")
