@@ -152,7 +152,8 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   int tb = 1;
   while ((int64_t(1) << tb) < l.total_tiles) ++tb;
   l.tile_bits = tb;
-  l.sort_blocks = std::max<int64_t>(1, (cap + kSortTile - 1) / kSortTile);
+  l.sort_blocks = std::max<int64_t>(1, (std::max<int64_t>(cap, l.total_tiles) + kSortTile - 1) /
+                                            kSortTile);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
   l.o_views = take(sizeof(ViewDev) * l.V);
@@ -180,6 +181,8 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_long = take(4 * (size_t)scap);
   l.o_pos = take(4 * (size_t)l.slots);
   l.o_ranges = take(8 * (size_t)l.total_tiles);
+  l.o_order = take(4 * (size_t)l.total_tiles);      // tile launch order (longest lists first)
+  l.o_tkey = take(4 * 3 * (size_t)l.total_tiles);   // its sort keys / values / keys out
   l.o_tfin = take(4 * (size_t)l.total_pix);
   l.o_nlast = take(4 * (size_t)l.total_pix);
   l.o_gpair = take(4 * (size_t)cap * l.GS);

@@ -1,7 +1,7 @@
 // Front-to-back alpha compositing of the sorted tile lists (Eq. 6) and its
 // adjoint.
 //
-// Mapping: one 64-lane wave per tile; a tile of tile_w x tile_h = 64 * PPL
+// Mapping: one 64-lane wave per tile, tiles launched longest list first; a tile of tile_w x tile_h = 64 * PPL
 // pixels gives every lane PPL pixels of one column, so the per-pair x
 // offset is shared and each broadcast record read from LDS feeds PPL pixels.
 // The wave stages 64 list entries at a time in LDS (projection record + the
@@ -40,7 +40,8 @@ __host__ __device__ constexpr int fused_channels() { return 3 + C + 3; }
 template <int C, int PPL, bool FUSED>
 __global__ __launch_bounds__(64) void k_render_fwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
-    float teps, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    float teps, const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
     const float4* __restrict__ feat, float* __restrict__ out, float* __restrict__ tfin,
     uint32_t* __restrict__ nlast, FusedLoss fl) {
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   __shared__ float4 s_r0[64], s_r1[64];
   __shared__ float4 s_f[64 * FS4];
   const int lane = threadIdx.x;
-  const int gt = blockIdx.x;
+  const int gt = (int)order[blockIdx.x];
   const int v = find_view(views, V, gt);
   const ViewDev& vw = views[v];
   const int W = vw.w, H = vw.h;
@@ -196,7 +197,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 template <int C, int PPL, bool FUSED>
 __global__ __launch_bounds__(64) void k_render_bwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
     const float4* __restrict__ feat, const float* __restrict__ out, const float* __restrict__ G,
     const float* __restrict__ tfin, const uint32_t* __restrict__ nlast, float* __restrict__ gpair,
@@ -205,11 +207,12 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
   constexpr int NV = 10 + C;          // du dv dA dB dC dalpha dtz drgb[3] dsem[C]
+  // the fused loss has no depth or alpha term: their gradient rows are zero
+  constexpr bool kDA = !FUSED;
   __shared__ float4 s_r0[64], s_r1[64];
   __shared__ float4 s_f[64 * FS4];
-  __shared__ uint32_t s_e[64];
   const int lane = threadIdx.x;
-  const int gt = blockIdx.x;
+  const int gt = (int)order[blockIdx.x];
   const int v = find_view(views, V, gt);
   const ViewDev& vw = views[v];
   const int W = vw.w, H = vw.h;
@@ -269,10 +272,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   const uint32_t sbase = (uint32_t)v * (uint32_t)N;
   for (uint32_t base = rg.x; base < stop; base += 64) {
     const int cnt = (int)min(64u, stop - base);
+    uint32_t e_mine = 0;
     if (lane < cnt) {
-      const uint32_t e = vals[base + lane];
-      const uint32_t slot = pslot[e];
-      s_e[lane] = e;
+      e_mine = vals[base + lane];
+      const uint32_t slot = pslot[e_mine];
       s_r0[lane] = rec[2 * (size_t)slot];
       s_r1[lane] = rec[2 * (size_t)slot + 1];
       const uint32_t i = slot - sbase;
@@ -282,8 +285,24 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
       const uint32_t idx = base - rg.x + (uint32_t)j;
+      const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)e_mine, j);
       const float4 r0 = s_r0[j], r1 = s_r1[j];
       const float A = r1.x, B = r1.y, Cc = r1.z, tz = r1.w;
+      const float dx = pixel_offset(pxc, r0.x, r0.z);
+      float dy[PPL], q[PPL];
+      bool hit[PPL];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        dy[k] = pixel_offset(pyc[k], r0.y, r0.w);
+        q[k] = pixel_q32(A, B, Cc, dx, dy[k]);
+        hit[k] = idx < nl[k] && q[k] <= qcut;
+        any = any || hit[k];
+      }
+      if (!__any(any)) {            // no pixel of the tile reached by this pair
+        if (writer) gpair[(size_t)e * GS + my_comp] = 0.0f;
+        continue;
+      }
       float fv[FS4 * 4];
 #pragma unroll
       for (int f = 0; f < FS4; ++f) {
@@ -291,46 +310,42 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
       }
       const float al = fv[F];
+      // Lanes whose pixel the pair does not reach run the same arithmetic with
+      // g = 0: alpha = w = 0, T and the prefix unchanged, every term +-0.
       float pv[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) pv[c] = 0.0f;
-      bool touched = false;
-      const float dx = pixel_offset(pxc, r0.x, r0.z);
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        if (idx >= nl[k]) continue;
-        const float dy = pixel_offset(pyc[k], r0.y, r0.w);
-        const float q = pixel_q32(A, B, Cc, dx, dy);
-        if (!(q <= qcut)) continue;
-        touched = true;
-        const float g = __expf(-0.5f * q);
+        const float g = hit[k] ? __expf(-0.5f * q[k]) : 0.0f;
         const float araw = al * g;
         const bool clamped = araw > amax;
         const float a = clamped ? amax : araw;
         const float w = a * T[k];
-        float gf = Gv[k][F] * tz;
+        float gf = kDA ? Gv[k][F] * tz : 0.0f;
 #pragma unroll
         for (int f = 0; f < F; ++f) gf += Gv[k][f] * fv[f];
 #pragma unroll
         for (int f = 0; f < F; ++f) pv[7 + f] += w * Gv[k][f];
-        pv[6] += w * Gv[k][F];
-        const float inv = 1.0f / (1.0f - a);
+        if (kDA) pv[6] += w * Gv[k][F];
+        const float om = 1.0f - a;
+        const float inv = __builtin_amdgcn_rcpf(om);
         const float suffix = (GO[k] - Spre[k]) - w * gf;
-        const float da = T[k] * gf - suffix * inv + Gv[k][F + 1] * Tf[k] * inv;
+        float da = T[k] * gf - suffix * inv;
+        if (kDA) da += Gv[k][F + 1] * Tf[k] * inv;
         Spre[k] += w * gf;
-        if (!clamped) {
-          pv[5] += g * da;
-          const float dq = -0.5f * g * al * da;
-          pv[2] += dx * dx * dq;
-          pv[3] += 2.0f * dx * dy * dq;
-          pv[4] += dy * dy * dq;
-          pv[0] += -(2.0f * A * dx + 2.0f * B * dy) * dq;
-          pv[1] += -(2.0f * Cc * dy + 2.0f * B * dx) * dq;
-        }
-        T[k] *= (1.0f - a);
+        const float gd = clamped ? 0.0f : g;      // the clamp cuts alpha's dependence on g
+        pv[5] += gd * da;
+        const float dq = -0.5f * gd * al * da;
+        const float dyk = dy[k];
+        pv[2] += dx * dx * dq;
+        pv[3] += 2.0f * dx * dyk * dq;
+        pv[4] += dyk * dyk * dq;
+        pv[0] += -(2.0f * A * dx + 2.0f * B * dyk) * dq;
+        pv[1] += -(2.0f * Cc * dyk + 2.0f * B * dx) * dq;
+        T[k] *= om;
       }
-      const uint32_t e = s_e[j];
-      const float tot = __any(touched) ? wave_reduce_scatter<NV>(pv, lane) : 0.0f;
+      const float tot = wave_reduce_scatter<NV>(pv, lane);
       if (writer) gpair[(size_t)e * GS + my_comp] = tot;
     }
     __syncthreads();
@@ -346,7 +361,8 @@ template <int C, int PPL, bool FUSED>
 void fwd_launch(const Layout& L, void* ws, float* out, const FusedLoss& fl, hipStream_t st) {
   hipLaunchKernelGGL((k_render_fwd<C, PPL, FUSED>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
-                     L.t_eps, at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
+                     L.t_eps, at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
+                     at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
                      at<const float4>(ws, L.o_feat), out, at<float>(ws, L.o_tfin),
                      at<uint32_t>(ws, L.o_nlast), fl);
@@ -356,9 +372,9 @@ template <int C, int PPL, bool FUSED>
 void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hipStream_t st) {
   hipLaunchKernelGGL((k_render_bwd<C, PPL, FUSED>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
-                     at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
-                     at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
-                     at<const float4>(ws, L.o_feat), out, G, at<const float>(ws, L.o_tfin),
+                     at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
+                     at<const uint32_t>(ws, L.o_vals), at<const uint32_t>(ws, L.o_pslot),
+                     at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out, G, at<const float>(ws, L.o_tfin),
                      at<const uint32_t>(ws, L.o_nlast), at<float>(ws, L.o_gpair), L.GS,
                      FUSED ? at<const float>(ws, L.o_tm) : nullptr);
 }

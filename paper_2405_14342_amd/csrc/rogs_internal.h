@@ -49,7 +49,7 @@ struct Layout {
   int64_t slots = 0;           // V * N
   int64_t sort_blocks = 0;     // ceil(cap / kSortTile)
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
-  size_t o_views, o_cnt, o_rec, o_rect, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
+  size_t o_views, o_order, o_tkey, o_cnt, o_rec, o_rect, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
@@ -394,6 +394,7 @@ void launch_scan_part(const Layout& L, void* ws, hipStream_t st);
 // by tile.  Counts < 0 are read on the device.  Returns the buffer parity.
 int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st);
 void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st);
+void launch_tile_order(const Layout& L, void* ws, hipStream_t st);
 int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* out, hipStream_t st);
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,
                  float* loss_out, float* d_exp, hipStream_t st);

@@ -227,6 +227,22 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __re
   if (i == (int64_t)n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
+// Launch order of the tiles for compositing: the longest lists first (keys =
+// bucket of the list length's bit length, descending), tile index order inside
+// a bucket.  A tile's results do not depend on when it runs; the order keeps
+// the few very long lists (far field) from starting last and setting the
+// kernel's end.
+__global__ void k_tile_keys(const uint2* __restrict__ ranges, int64_t T, uint32_t* __restrict__ key,
+                            uint32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  const uint2 r = ranges[i];
+  const uint32_t len = r.y - r.x;             // empty tiles hold (0, 0)
+  const int bl = len ? 32 - __clz((int)len) : 0;
+  key[i] = 15u - (uint32_t)min(bl, 15);
+  val[i] = (uint32_t)i;
+}
+
 }  // namespace
 
 // Binning of the current batch.  n_pairs / n_vis >= 0: counts known on the
@@ -281,9 +297,22 @@ void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st) {
   fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.total_tiles, st);
   const uint32_t* n_dev = n_host < 0 ? at<uint32_t>(ws, L.o_misc) + kMiscPairs : nullptr;
   const int64_t n_grid = n_host < 0 ? L.cap : n_host;
-  if (n_grid <= 0) return;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_grid + 255) / 256)), dim3(256), 0, st,
-                     at<const uint32_t>(ws, L.o_keys), n_dev, n_grid, L.cap, ranges);
+  if (n_grid > 0)
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_grid + 255) / 256)), dim3(256), 0, st,
+                       at<const uint32_t>(ws, L.o_keys), n_dev, n_grid, L.cap, ranges);
+  launch_tile_order(L, ws, st);
+}
+
+void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {
+  const int64_t T = L.total_tiles;
+  uint32_t* key = at<uint32_t>(ws, L.o_tkey);
+  uint32_t* val = key + T;
+  uint32_t* key2 = val + T;
+  hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
+                     at<const uint2>(ws, L.o_ranges), T, key, val);
+  // one 4-bit pass: the result lands in the alternate buffers (key2, order)
+  radix_sort<uint32_t, 4>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
+                          at<uint32_t>(ws, L.o_hist), at<uint32_t>(ws, L.o_histtmp), st);
 }
 
 }  // namespace rogs
