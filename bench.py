@@ -41,10 +41,11 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) 
         return N * (40 + 4 * FS) + slots * 4 + S * 40
     if kernel == "sort":
         # compaction (counts, depth keys) + depth sort of the S visible slots
-        # (64-bit keys, 8-bit digits) + emission offsets + one tile key,
-        # value and slot per pair + tile sort of the pairs (32-bit keys)
+        # (64-bit keys, digits of at most 9 bits) + emission offsets + one
+        # tile key, value and slot per pair + tile sort of the pairs (32-bit
+        # keys)
         view_bits = max(0, (V - 1).bit_length())
-        s_passes = (32 + view_bits + 7) // 8
+        s_passes = (32 + view_bits + 8) // 9
         return slots * 4 + S * 16 + s_passes * S * 32 + S * 24 + P * 12 + passes * P * 20
     if kernel == "ranges":
         return P * 8 + stats["tiles"] * 8

@@ -140,7 +140,9 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
     const int64_t np = (int64_t)c.w * c.h;
     l.total_pix += np;
     l.max_view_pix = std::max(l.max_view_pix, np);
-    l.total_tiles += (int64_t)((c.w + tw - 1) / tw) * ((c.h + th - 1) / th);
+    const int64_t vt = (int64_t)((c.w + tw - 1) / tw) * ((c.h + th - 1) / th);
+    l.total_tiles += vt;
+    l.max_view_tiles = std::max(l.max_view_tiles, vt);
     loss_blocks += (np + 255) / 256;
   }
   if (l.total_tiles >= (int64_t(1) << 31) || l.total_pix >= (int64_t(1) << 40)) {

@@ -24,8 +24,17 @@ __device__ __forceinline__ int find_view_pix(const ViewDev* __restrict__ views, 
 }
 
 // |M_v|: number of mask pixels per view.  grid.y = view; each block counts
-// kMaskPerBlock pixels and adds its count with one integer atomic (exact).
-constexpr int kMaskPerBlock = 16 * kLossBlock;
+// kMaskPerBlock bytes of the view's mask, 16 per thread and iteration (one
+// 16-byte load where the group is aligned and whole), and adds its count with
+// one integer atomic (exact, order-free).
+constexpr int kMaskIters = 2;
+constexpr int kMaskPerBlock = 16 * kLossBlock * kMaskIters;
+
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t x) {
+  // bit 7 of each byte of t is set iff that byte of x is nonzero
+  const uint32_t t = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
+  return (uint32_t)__popc(t & 0x80808080u);
+}
 
 __global__ __launch_bounds__(kLossBlock) void k_mask_count(const ViewDev* __restrict__ views,
                                                            const uint8_t* __restrict__ mask,
@@ -38,9 +47,18 @@ __global__ __launch_bounds__(kLossBlock) void k_mask_count(const ViewDev* __rest
   if (base >= npix) return;
   const uint8_t* m = mask + vw.pix_off;
   uint32_t c = 0;
-  for (int k = threadIdx.x; k < kMaskPerBlock; k += kLossBlock) {
-    const int64_t p = base + k;
-    if (p < npix) c += m[p] ? 1u : 0u;
+#pragma unroll
+  for (int it = 0; it < kMaskIters; ++it) {
+    const int64_t p = base + 16 * ((int64_t)it * kLossBlock + threadIdx.x);
+    if (p >= npix) continue;
+    const uint8_t* g = m + p;
+    if (p + 16 <= npix && (reinterpret_cast<uintptr_t>(g) & 15u) == 0) {
+      const uint4 x = *reinterpret_cast<const uint4*>(g);
+      c += nonzero_bytes(x.x) + nonzero_bytes(x.y) + nonzero_bytes(x.z) + nonzero_bytes(x.w);
+    } else {
+      const int n = (int)min<int64_t>(16, npix - p);
+      for (int k = 0; k < n; ++k) c += g[k] ? 1u : 0u;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
@@ -263,9 +281,11 @@ __device__ __forceinline__ void adam_surfel(int i, size_t N, float* __restrict__
 
 // Per-slot sums of the per-pair gradient records.  The records of a visible
 // slot are contiguous in emission order; a slot with at most kLongRows records
-// is summed by one thread in record order, a longer one by one wave (lane l
-// takes records l, l + 64, ... in order, then the wave reduce-scatter).  Each
-// slot's sum depends only on its own records, not on how a batch is laid out.
+// is summed in record order by Q threads, one per float4 column of the record
+// (so a wave's loads cover runs of whole records), a longer one by one wave
+// (lane l takes records l, l + 64, ... in order, then the wave reduce-scatter).
+// Each slot's sum depends only on its own records, not on how a batch is laid
+// out.
 constexpr uint32_t kLongRows = 32;
 
 template <int C>
@@ -280,43 +300,34 @@ __global__ __launch_bounds__(256) void k_slot_sums(const uint32_t* __restrict__ 
   constexpr int GSC = ((10 + C) + 3) & ~3;
   constexpr int Q = GSC / 4;
   const int64_t S = min((int64_t)misc[kMiscVisible], scap);
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t k = t / Q;
+  const int q = (int)(t - k * Q);
   if (k >= S) return;
   const uint32_t n = scnt[k], o = soff[k];
   if (n > kLongRows) {
-    long_list[atomicAdd(long_count, 1u)] = (uint32_t)k;
+    if (q == 0) long_list[atomicAdd(long_count, 1u)] = (uint32_t)k;
     return;
   }
   // after a pair-capacity overflow the records past the capacity were never written
   const uint32_t m = ((int64_t)o + n <= cap) ? n : (((int64_t)o < cap) ? (uint32_t)(cap - o) : 0u);
-  const float4* r4 = reinterpret_cast<const float4*>(gpair) + (size_t)o * Q;
-  float4 acc[Q];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) acc[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const float4* col = reinterpret_cast<const float4*>(gpair) + (size_t)o * Q + q;
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   uint32_t r = 0;
-  for (; r + 1 < m; r += 2) {
-    float4 a[Q], b[Q];
+  for (; r + 4 <= m; r += 4) {
+    float4 a[4];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      a[j] = r4[(size_t)r * Q + j];
-      b[j] = r4[(size_t)(r + 1) * Q + j];
-    }
+    for (int u = 0; u < 4; ++u) a[u] = col[(size_t)(r + u) * Q];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      acc[j].x += a[j].x; acc[j].y += a[j].y; acc[j].z += a[j].z; acc[j].w += a[j].w;
-      acc[j].x += b[j].x; acc[j].y += b[j].y; acc[j].z += b[j].z; acc[j].w += b[j].w;
+    for (int u = 0; u < 4; ++u) {
+      acc.x += a[u].x; acc.y += a[u].y; acc.z += a[u].z; acc.w += a[u].w;
     }
   }
-  if (r < m) {
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const float4 a = r4[(size_t)r * Q + j];
-      acc[j].x += a.x; acc[j].y += a.y; acc[j].z += a.z; acc[j].w += a.w;
-    }
+  for (; r < m; ++r) {
+    const float4 a = col[(size_t)r * Q];
+    acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
   }
-  float4* out = reinterpret_cast<float4*>(ssum) + (size_t)k * Q;
-#pragma unroll
-  for (int j = 0; j < Q; ++j) out[j] = acc[j];
+  reinterpret_cast<float4*>(ssum)[(size_t)k * Q + q] = acc;
 }
 
 // Long slots: one wave each; the grid loops over the list (every wave exits).
@@ -566,20 +577,30 @@ __global__ void k_adam_plain(int n, float* __restrict__ P, const float* __restri
 // Per-view sums of the per-tile loss partials of the fused forward: fixed
 // assignment of tiles to threads and a fixed tree (deterministic).  dL/d(a,b)
 // are overwritten.
+// Per-view sums of the fused forward's per-tile partials (loss, dL/da,
+// dL/db) in two fixed-order stages: block (c, v) adds tiles c * kTileChunk ...
+// of view v (8 per thread, then a fixed tree), and one wave per view adds the
+// chunks in order.  The result does not depend on scheduling.
+constexpr int kTileChunk = 8 * 256;
+
 __global__ __launch_bounds__(256) void k_loss_tiles(const ViewDev* __restrict__ views, int V,
                                                     int64_t total_tiles,
-                                                    const float* __restrict__ part,
-                                                    float* __restrict__ per_view,
-                                                    float* __restrict__ d_exp) {
+                                                    const float* __restrict__ part, int nchunk,
+                                                    float* __restrict__ cpart) {
   __shared__ float s[3][256];
-  const int v = blockIdx.x;
+  const int v = blockIdx.y, c = blockIdx.x;
   const int64_t t0 = views[v].tile_off;
   const int64_t t1 = (v + 1 < V) ? views[v + 1].tile_off : total_tiles;
+  const int64_t k0 = t0 + (int64_t)c * kTileChunk;
   float l = 0.0f, a = 0.0f, b = 0.0f;
-  for (int64_t k = t0 + threadIdx.x; k < t1; k += 256) {
-    l += part[3 * k];
-    a += part[3 * k + 1];
-    b += part[3 * k + 2];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t k = k0 + threadIdx.x + 256 * i;
+    if (k < t1) {
+      l += part[3 * k];
+      a += part[3 * k + 1];
+      b += part[3 * k + 2];
+    }
   }
   s[0][threadIdx.x] = l;
   s[1][threadIdx.x] = a;
@@ -593,11 +614,28 @@ __global__ __launch_bounds__(256) void k_loss_tiles(const ViewDev* __restrict__ 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    per_view[v] = s[0][0];
+  if (threadIdx.x < 3) cpart[((size_t)v * nchunk + c) * 3 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_loss_chunks(const float* __restrict__ cpart, int nchunk,
+                                                    float* __restrict__ per_view,
+                                                    float* __restrict__ d_exp) {
+  const int v = blockIdx.x, lane = threadIdx.x;
+  float l = 0.0f, a = 0.0f, b = 0.0f;
+  for (int c = lane; c < nchunk; c += 64) {
+    const float* q = cpart + ((size_t)v * nchunk + c) * 3;
+    l += q[0];
+    a += q[1];
+    b += q[2];
+  }
+  l = wave_sum_f(l);
+  a = wave_sum_f(a);
+  b = wave_sum_f(b);
+  if (lane == 0) {
+    per_view[v] = l;
     if (d_exp) {
-      d_exp[2 * v] = s[1][0];
-      d_exp[2 * v + 1] = s[2][0];
+      d_exp[2 * v] = a;
+      d_exp[2 * v + 1] = b;
     }
   }
 }
@@ -728,7 +766,8 @@ void slot_sums_launch(const Layout& L, void* ws, hipStream_t st) {
   const int64_t s_grid = L.scap;
   if (s_grid <= 0) return;
   fill_u32(misc + kMiscLong, 0u, 1, st);
-  hipLaunchKernelGGL((k_slot_sums<C>), dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0, st,
+  constexpr int Q = (((10 + C) + 3) & ~3) / 4;
+  hipLaunchKernelGGL((k_slot_sums<C>), dim3((unsigned)((s_grid * Q + 255) / 256)), dim3(256), 0, st,
                      misc, L.scap, L.cap, at<const uint32_t>(ws, L.o_scnt),
                      at<const uint32_t>(ws, L.o_soff), at<const float>(ws, L.o_gpair),
                      at<float>(ws, L.o_ssum), at<uint32_t>(ws, L.o_long), misc + kMiscLong);
@@ -745,9 +784,14 @@ void launch_slot_sums(const Layout& L, void* ws, hipStream_t st) {
 
 void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st) {
   float* per_view = reinterpret_cast<float*>(at<uint32_t>(ws, L.o_mcount) + L.V);
-  hipLaunchKernelGGL(k_loss_tiles, dim3((unsigned)L.V), dim3(256), 0, st,
+  // the plain loss's block partials are unused on the fused path: chunk sums go there
+  float* cpart = at<float>(ws, L.o_lpart) + 2 * (L.V + 1);
+  const int nchunk = (int)((L.max_view_tiles + kTileChunk - 1) / kTileChunk);
+  hipLaunchKernelGGL(k_loss_tiles, dim3((unsigned)nchunk, (unsigned)L.V), dim3(256), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.total_tiles,
-                     at<const float>(ws, L.o_tpart), per_view, d_exp);
+                     at<const float>(ws, L.o_tpart), nchunk, cpart);
+  hipLaunchKernelGGL(k_loss_chunks, dim3((unsigned)L.V), dim3(64), 0, st, cpart, nchunk, per_view,
+                     d_exp);
 }
 
 void launch_mask_count(const Layout& L, void* ws, const uint8_t* mask, hipStream_t st) {

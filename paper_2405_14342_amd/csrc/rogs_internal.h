@@ -44,7 +44,7 @@ struct Layout {
   int32_t FS = 0, GS = 0;
   int32_t nb = 0;              // blocks of kProjBlock surfels
   int32_t tile_bits = 1;
-  int64_t total_pix = 0, total_tiles = 0, max_view_pix = 0, cap = 0;
+  int64_t total_pix = 0, total_tiles = 0, max_view_pix = 0, max_view_tiles = 0, cap = 0;
   int64_t scap = 0;            // visible-slot capacity (<= cap)
   int64_t slots = 0;           // V * N
   int64_t sort_blocks = 0;     // ceil(cap / kSortTile)
@@ -59,7 +59,13 @@ struct Layout {
 };
 
 // misc counters (uint32 slots at o_misc)
-enum MiscSlot { kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscLong = 3, kMiscCount = 16 };
+// misc words: pair count, overflow flag, visible-slot count, long-slot count,
+// pairs actually emitted (min of the pair count, the capacity and the pairs of
+// the slots that fit the slot capacity)
+enum MiscSlot {
+  kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscLong = 3, kMiscEmit = 4,
+  kMiscCount = 16
+};
 
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
                 const rogs_render_opts* opts, int64_t cap, int64_t scap, Layout* L,

@@ -160,46 +160,70 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
   }
 }
 
+// Emission counts in depth order; pos[slot] = the slot's sorted position.
 __global__ void k_gather_cnt(const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
                              const uint32_t* __restrict__ sval, const uint32_t* __restrict__ cnt,
-                             uint32_t* __restrict__ scnt) {
+                             uint32_t* __restrict__ scnt, uint32_t* __restrict__ pos) {
   const uint32_t n = count_n(n_dev, n_host, cap);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < (int64_t)n) scnt[k] = cnt[sval[k]];
+  if (k >= (int64_t)n) return;
+  const uint32_t slot = sval[k];
+  scnt[k] = cnt[slot];
+  pos[slot] = (uint32_t)k;
 }
 
-// Emission in depth-sorted slot order, one block per 256 sorted slots: the
-// block's pairs e in [soff[first], soff[last + 1]) are spread over its
-// threads; each finds its slot by binary search over the block's offsets and
-// writes key = global tile, value = e, pslot[e] = slot.
-__global__ __launch_bounds__(kProjBlock) void k_emit(
-    const ViewDev* __restrict__ views, int N, const uint32_t* __restrict__ n_dev, int64_t n_host,
-    int64_t scap, int64_t cap, const uint32_t* __restrict__ sval,
-    const uint32_t* __restrict__ soff, const uint32_t* __restrict__ scnt,
-    const uint2* __restrict__ rect, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    uint32_t* __restrict__ pslot, uint32_t* __restrict__ pos) {
-  __shared__ uint32_t s_off[kProjBlock + 1];
-  __shared__ uint32_t s_slot[kProjBlock];
-  __shared__ uint2 s_rect[kProjBlock];
-  const uint32_t S = count_n(n_dev, n_host, scap);
-  const int64_t k0 = (int64_t)blockIdx.x * kProjBlock;
-  if (k0 >= (int64_t)S) return;
-  const int nloc = (int)min<int64_t>(kProjBlock, (int64_t)S - k0);
-  const int t = threadIdx.x;
-  if (t < nloc) {
-    const uint32_t slot = sval[k0 + t];
-    const uint32_t o = soff[k0 + t];
-    s_slot[t] = slot;
-    s_off[t] = o;
-    s_rect[t] = rect[slot];
-    pos[slot] = (uint32_t)(k0 + t);
-    if (t == nloc - 1) s_off[nloc] = o + scnt[k0 + t];
+// Emission in depth-sorted slot order, balanced by pairs: block b writes the
+// pairs e in [b * kEmitPairs, (b + 1) * kEmitPairs).  Two threads find the
+// first and last slot of the block's range by binary search over the slot
+// offsets (each visible slot has at least one pair, so the offsets are
+// strictly increasing and the range holds at most kEmitPairs slots); the
+// block stages those slots in LDS, and each pair finds its slot there.  Per
+// pair: key = global tile, value = e, pslot[e] = slot.  The number of pairs
+// written (the pair count, clipped to the capacity and to the pairs of the
+// slots within the slot capacity) goes to *n_emit for the sort.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitPairs = 2048;
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit(
+    const ViewDev* __restrict__ views, int N, const uint32_t* __restrict__ p_dev, int64_t p_host,
+    const uint32_t* __restrict__ s_dev, int64_t s_host, int64_t scap, int64_t cap,
+    const uint32_t* __restrict__ sval, const uint32_t* __restrict__ soff,
+    const uint32_t* __restrict__ scnt, const uint2* __restrict__ rect, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ n_emit) {
+  __shared__ uint32_t s_off[kEmitPairs + 1];
+  __shared__ uint32_t s_slot[kEmitPairs];
+  __shared__ uint2 s_rect[kEmitPairs];
+  __shared__ uint32_t s_k[2];
+  const uint32_t S = count_n(s_dev, s_host, scap);
+  const uint32_t P = count_n(p_dev, p_host, cap);
+  const uint32_t pend = S ? soff[S - 1] + scnt[S - 1] : 0u;
+  const uint32_t E = min(P, pend);
+  if (n_emit && blockIdx.x == 0 && threadIdx.x == 0) *n_emit = E;
+  const uint32_t e0 = blockIdx.x * (uint32_t)kEmitPairs;
+  if (e0 >= E) return;
+  const uint32_t e1 = min(E, e0 + (uint32_t)kEmitPairs);
+  if (threadIdx.x < 2) {
+    const uint32_t target = threadIdx.x == 0 ? e0 : e1 - 1u;
+    uint32_t lo = 0, hi = S - 1u;                  // last k with soff[k] <= target
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1u) >> 1;
+      if (soff[mid] <= target) lo = mid; else hi = mid - 1u;
+    }
+    s_k[threadIdx.x] = lo;
   }
   __syncthreads();
-  const uint32_t e0 = s_off[0], e1 = s_off[nloc];
-  for (uint32_t e = e0 + t; e < e1; e += kProjBlock) {
-    if ((int64_t)e >= cap) break;
-    int lo = 0, hi = nloc - 1;            // last j with s_off[j] <= e
+  const uint32_t ka = s_k[0];
+  const int ns = (int)min<uint32_t>(s_k[1] - ka + 1u, (uint32_t)kEmitPairs);
+  for (int t = threadIdx.x; t < ns; t += kEmitThreads) {
+    const uint32_t slot = sval[ka + t];
+    s_off[t] = soff[ka + t];
+    s_slot[t] = slot;
+    s_rect[t] = rect[slot];
+  }
+  if (threadIdx.x == 0) s_off[ns] = soff[ka + ns - 1] + scnt[ka + ns - 1];
+  __syncthreads();
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += kEmitThreads) {
+    int lo = 0, hi = ns - 1;                       // last j with s_off[j] <= e
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
@@ -268,34 +292,42 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
   unsigned long long* sk2 = at<unsigned long long>(ws, L.o_keys2);   // free until emission
   uint32_t* sv = at<uint32_t>(ws, L.o_sval);
   uint32_t* sv2 = at<uint32_t>(ws, L.o_vals2);
-  if (radix_sort<unsigned long long, 8>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
+  if (radix_sort<unsigned long long, 9>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
                                         hist, histtmp, st)) {
     sv = sv2;
   }
   // 3. emission offsets in depth order
   uint32_t* scnt = at<uint32_t>(ws, L.o_scnt);
   uint32_t* soff = at<uint32_t>(ws, L.o_soff);
+  uint32_t* n_emit = p_dev ? misc + kMiscEmit : nullptr;
   if (s_grid > 0) {
     hipLaunchKernelGGL(k_gather_cnt, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0, st,
-                       s_dev, s_grid, L.scap, sv, at<const uint32_t>(ws, L.o_cnt), scnt);
+                       s_dev, s_grid, L.scap, sv, at<const uint32_t>(ws, L.o_cnt), scnt,
+                       at<uint32_t>(ws, L.o_pos));
     scan_u32_dev(scnt, soff, s_dev, s_grid, at<uint32_t>(ws, L.o_parttmp2), st);
-    // 4. one key per covered tile
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((s_grid + kProjBlock - 1) / kProjBlock)),
-                       dim3(kProjBlock), 0, st, at<const ViewDev>(ws, L.o_views), L.N, s_dev,
-                       s_grid, L.scap, L.cap, sv, soff, scnt, at<const uint2>(ws, L.o_rect),
-                       at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
-                       at<uint32_t>(ws, L.o_pslot), at<uint32_t>(ws, L.o_pos));
+  }
+  // 4. one key per covered tile
+  if (p_grid > 0) {
+    if (s_grid > 0) {
+      hipLaunchKernelGGL(k_emit, dim3((unsigned)((p_grid + kEmitPairs - 1) / kEmitPairs)),
+                         dim3(kEmitThreads), 0, st, at<const ViewDev>(ws, L.o_views), L.N, p_dev,
+                         p_grid, s_dev, s_grid, L.scap, L.cap, sv, soff, scnt,
+                         at<const uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_keys),
+                         at<uint32_t>(ws, L.o_vals), at<uint32_t>(ws, L.o_pslot), n_emit);
+    } else if (n_emit) {
+      fill_u32(n_emit, 0u, 1, st);
+    }
   }
   // 5. stable sort of the pairs by tile
   return radix_sort<uint32_t, 9>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
-                                 at<uint32_t>(ws, L.o_keys2), at<uint32_t>(ws, L.o_vals2), p_dev,
+                                 at<uint32_t>(ws, L.o_keys2), at<uint32_t>(ws, L.o_vals2), n_emit,
                                  p_grid, L.cap, L.tile_bits, hist, histtmp, st);
 }
 
 void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st) {
   uint2* ranges = at<uint2>(ws, L.o_ranges);
   fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.total_tiles, st);
-  const uint32_t* n_dev = n_host < 0 ? at<uint32_t>(ws, L.o_misc) + kMiscPairs : nullptr;
+  const uint32_t* n_dev = n_host < 0 ? at<uint32_t>(ws, L.o_misc) + kMiscEmit : nullptr;
   const int64_t n_grid = n_host < 0 ? L.cap : n_host;
   if (n_grid > 0)
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_grid + 255) / 256)), dim3(256), 0, st,
