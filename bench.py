@@ -104,7 +104,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--tile", default="16x16", help="tile shape WxH (default 16x16)")
+    ap.add_argument("--tile", default="16x4",
+                    help="tile shape WxH, or 'auto' (rogs_autotune; default 16x4)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a 256 MiB device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
@@ -129,8 +130,15 @@ def main():
     C = scene.n_sem
     total_steps = args.warmup + args.steps
     from paper_2405_14342_amd import binding as B
-    tw, th = (int(t) for t in args.tile.split("x"))
-    st = TrainState(scene, device="cuda:0", opts=B.make_opts(tile_w=tw, tile_h=th))
+    if args.tile == "auto":
+        # rogs_autotune times every supported tile shape on this workload first
+        st = TrainState(scene, device="cuda:0", opts="auto")
+        print(f"[bench] autotuned tile {st.opts.tile_w}x{st.opts.tile_h} "
+              f"({st.autotune_ms:.3f} ms per project+sort+fwd+bwd)", file=sys.stderr, flush=True)
+    else:
+        tw, th = (int(t) for t in args.tile.split("x"))
+        st = TrainState(scene, device="cuda:0", opts=B.make_opts(tile_w=tw, tile_h=th))
+    tile = f"{st.opts.tile_w}x{st.opts.tile_h}"
     print(f"[bench] {scene.name}: {scene.n} surfels, {scene.n_views} views, "
           f"{scene.npix} px/step", file=sys.stderr, flush=True)
 
@@ -216,7 +224,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded surfel grid, cameras and random targets)",
         "config": {"workload": scene.name, "surfels": scene.n, "views": scene.n_views,
-                   "tile": args.tile, "pixels_per_step": scene.npix, "sem_classes": C,
+                   "tile": tile, "pixels_per_step": scene.npix, "sem_classes": C,
                    "path": "fused (hipGraph)", "pairs": stats["pairs"],
                    "visible_slots": stats["visible"]},
         "fused_eager_ms_per_step": round(ms_fe, 4),

@@ -310,6 +310,30 @@ ROGS_API int rogs_step_fused(rogs_ctx* ctx, const rogs_train_state* t, const rog
  * [6] tiles, [7] slots; *loss = loss of the last applied step (nullable). */
 ROGS_API int rogs_fused_status(rogs_ctx* ctx, int64_t* stats, float* loss);
 
+/* ------------------------------------------------------ autotuner
+ * Chooses the tile shape for a workload.  Every supported shape (tile_w in
+ * {4, 8, 16, 32, 64}, tile_w * tile_h in {64, 128, 256}) renders the same
+ * values, since the per-pixel rule does not depend on it (Sec. 3.3.1 with
+ * the 3-sigma cut); shapes differ in the number of (surfel, tile) pairs and in
+ * the work each wave rejects.  For each shape the call sizes the capacities
+ * with one counted run, then times `reps` runs (after one warm-up) of
+ * rogs_project + rogs_bin_sort (device count) + rogs_render_fwd +
+ * rogs_render_bwd with dL/d(out) = 1 over the given surfels and views, and
+ * writes the fastest shape into opts->tile_w / tile_h (other fields kept);
+ * *ms_out (nullable) receives its time per run.
+ * cache_json (nullable): path of a JSON cache keyed by the workload (n,
+ * n_sem, every view's size, model and fx).  A cached entry is returned
+ * without timing; a new result is added to the file, which this call
+ * rewrites whole.  A file not written by this call is rejected (ROGS_EINVAL)
+ * and left untouched.
+ * Unlike the calls above this one allocates (hipMalloc: workspace, images,
+ * gradients) and frees before returning, synchronises the stream, and leaves
+ * the context's batch state at the last shape timed (call rogs_project
+ * again before rogs_bin_sort / render). */
+ROGS_API int rogs_autotune(rogs_ctx* ctx, const rogs_surfels* s, const rogs_camera* cams,
+                           int32_t n_views, rogs_render_opts* opts, const char* cache_json,
+                           int32_t reps, float* ms_out, void* stream);
+
 /* Batch statistics (host sync): stats[0] pairs P, [1] overflow flag,
  * [2] visible (view, surfel) slots, [3] pixels, [4] tiles, [5] slots V*N. */
 ROGS_API int rogs_batch_stats(rogs_ctx* ctx, void* ws, int64_t* stats, void* stream);

@@ -29,7 +29,7 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_render_fwd", "rogs_loss", "rogs_render_bwd", "rogs_adam_step",
             "rogs_debug_pairs", "rogs_debug_records", "rogs_batch_stats", "rogs_prof_enable",
             "rogs_prof_read", "rogs_prof_name", "rogs_fused_workspace_size", "rogs_step_fused",
-            "rogs_fused_status")
+            "rogs_fused_status", "rogs_autotune")
 PROF_GROUPS = 11
 FUSED_EAGER = 4
 
@@ -129,6 +129,9 @@ def load_library(path: str = LIB_PATH):
                                  ctypes.POINTER(RenderOpts), ctypes.POINTER(Targets),
                                  ctypes.POINTER(Optim), P, ctypes.c_size_t, I64, I64, U32, P], I32),
             "rogs_fused_status": ([P, P, P], I32),
+            "rogs_autotune": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
+                               ctypes.POINTER(RenderOpts), ctypes.c_char_p, I32,
+                               ctypes.POINTER(ctypes.c_float), P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -322,6 +325,18 @@ class Rogs:
             return r
         self._check(r, "rogs_step_fused")
         return r
+
+    def autotune(self, surf: Surfels, cams, opts: Optional[RenderOpts] = None,
+                 cache_json: Optional[str] = None, reps: int = 3, stream=None):
+        """rogs_autotune: returns (opts with the fastest tile shape, ms per run)."""
+        o = RenderOpts.from_buffer_copy(opts if opts is not None else default_opts())
+        arr = camera_array(cams)
+        ms = ctypes.c_float(0.0)
+        path = cache_json.encode() if cache_json else None
+        self._check(self.L.rogs_autotune(self.h, ctypes.byref(surf), arr, len(arr), ctypes.byref(o),
+                                         path, int(reps), ctypes.byref(ms), _stream(stream)),
+                    "rogs_autotune")
+        return o, float(ms.value)
 
     def fused_status(self) -> dict:
         st = np.zeros(8, np.int64)

@@ -85,6 +85,8 @@ bool is_fin(float x) { return isfinite(x); }
 
 namespace rogs {
 
+int ctx_fail(rogs_ctx* c, int code, const std::string& msg) { return fail(c, code, msg); }
+
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
                 const rogs_render_opts* opts, int64_t cap, int64_t scap, Layout* L,
                 const char** why, bool fused) {

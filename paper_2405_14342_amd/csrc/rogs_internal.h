@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/rogs.h"
 
 namespace rogs {
@@ -434,6 +436,8 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uin
 void scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
                   uint32_t* tmp, hipStream_t st);
 size_t scan_tmp_words(int64_t n);
+// Stores msg as the context's last error and returns code.
+int ctx_fail(rogs_ctx* c, int code, const std::string& msg);
 void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st);
 
 }  // namespace rogs

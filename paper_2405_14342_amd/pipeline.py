@@ -60,8 +60,11 @@ def n_out(C: int) -> int:
 class TrainState:
     """Surfel parameters, Adam moments, targets and output buffers on the GPU."""
 
-    def __init__(self, scene, device="cuda", opts: Optional[B.RenderOpts] = None,
-                 pair_capacity: Optional[int] = None):
+    def __init__(self, scene, device="cuda", opts=None, pair_capacity: Optional[int] = None,
+                 autotune_cache: Optional[str] = None):
+        """opts: RenderOpts, None (defaults) or "auto" (rogs_autotune picks the
+        tile shape for these surfels and views, optionally through a JSON
+        cache file)."""
         self.scene = scene
         self.dev = torch.device(device)
         N, C = scene.n, scene.n_sem
@@ -104,8 +107,13 @@ class TrainState:
                                        for t in scene.targets])
         else:
             self.tgt_rgb = self.tgt_label = self.tgt_mask = None
-        self.opts = opts or B.make_opts()
         self.rg = B.Rogs()
+        if isinstance(opts, str):
+            if opts != "auto":
+                raise ValueError("opts must be RenderOpts, None or 'auto'")
+            opts, self.autotune_ms = self.rg.autotune(self.surfels(), self.cams,
+                                                      cache_json=autotune_cache)
+        self.opts = opts or B.make_opts()
         self.cap_view = pair_capacity or 1 << 20
         self.cap_batch = pair_capacity or 1 << 22
         self.cap_fused = self.cap_batch
