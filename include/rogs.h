@@ -334,6 +334,72 @@ ROGS_API int rogs_autotune(rogs_ctx* ctx, const rogs_surfels* s, const rogs_came
                            int32_t n_views, rogs_render_opts* opts, const char* cache_json,
                            int32_t reps, float* ms_out, void* stream);
 
+/* ------------------------------------------------------ serving
+ * Render server over a resident map (the served form of a6: forward only).
+ * Requests are single views with a channel set; a worker thread owned by the
+ * server batches whatever is queued whenever it is idle (continuous
+ * batching, up to max_views views per batch and what the arena holds),
+ * renders the batch with rogs_project + rogs_bin_sort (pair count on the
+ * device) + rogs_render_fwd, and copies each request's channels into its
+ * buffer.  A batch that overflows the pair capacity the arena leaves is split
+ * in two and rerun; a single view that still does not fit completes with
+ * status ROGS_ECAPACITY.  Every view is rendered independently of the rest
+ * of its batch, so a request's output is bitwise the same alone or batched.
+ *
+ * Output planes (each W x H floats, row-major), in this order for the bits
+ * set: RGB (3 planes), SEM (C), D, A, ELEV.  ELEV = elev_ref - D / A (for an
+ * orthographic camera looking straight down from height elev_ref this is the
+ * surface height: D / A is the opacity-weighted depth); NaN where A = 0. */
+#define ROGS_CH_RGB  1u
+#define ROGS_CH_SEM  2u
+#define ROGS_CH_D    4u
+#define ROGS_CH_A    8u
+#define ROGS_CH_ELEV 16u
+#define ROGS_CH_ALL  31u
+
+typedef struct rogs_server rogs_server;
+
+typedef struct {
+  rogs_camera cam;       /* the view (host copy taken at submit) */
+  uint32_t channels;     /* OR of ROGS_CH_* (non-zero) */
+  float elev_ref;        /* reference height for ROGS_CH_ELEV */
+  float* out;            /* DEVICE buffer of (planes * w * h) floats, caller-owned; must
+                            stay valid until the request's poll returns ROGS_OK */
+} rogs_request;
+
+typedef struct {
+  int32_t status;        /* ROGS_OK or the request's error (ROGS_ECAPACITY, ROGS_EHIP) */
+  int32_t batch_views;   /* views in the batch that rendered it */
+  int64_t t_arrive_ns;   /* steady-clock time of submit */
+  int64_t t_start_ns;    /* its batch started */
+  int64_t t_done_ns;     /* its output was complete on the device */
+} rogs_result;
+
+/* map: device surfel arrays that stay valid and unchanged while the server
+ * lives.  arena: caller-owned device memory (256-byte aligned) holding the
+ * batch workspace and images; the server allocates no device memory.
+ * device: HIP device ordinal the worker renders on.  Returns ROGS_EINVAL for
+ * bad arguments. */
+ROGS_API int rogs_server_create(rogs_server** srv, const rogs_surfels* map,
+                                const rogs_render_opts* opts, void* arena, size_t arena_bytes,
+                                int32_t max_views, int32_t device);
+/* Thread-safe.  Queues one request and returns its ticket.  ROGS_EINVAL: bad
+ * camera, channels or buffer; ROGS_EREJECT: the view alone cannot fit the
+ * arena, or the queue is full (65536 requests); ROGS_ESTATE: the server is
+ * shutting down. */
+ROGS_API int rogs_serve_submit(rogs_server* srv, const rogs_request* req, uint64_t* ticket);
+/* Thread-safe, non-blocking.  ROGS_NOT_READY while the request is queued or
+ * rendering (res gets t_arrive_ns); ROGS_OK once done: res filled, the ticket
+ * is released (a second poll returns ROGS_EINVAL).  res->status carries the
+ * request's own outcome. */
+ROGS_API int rogs_serve_poll(rogs_server* srv, uint64_t ticket, rogs_result* res);
+/* stats[6]: batches, views rendered, batch splits, largest batch, views that
+ * failed with ROGS_ECAPACITY, requests queued now. */
+ROGS_API int rogs_server_stats(rogs_server* srv, int64_t* stats);
+/* Stops accepting requests, renders everything still queued, joins the
+ * worker and frees the server (not the arena). */
+ROGS_API void rogs_server_destroy(rogs_server* srv);
+
 /* Batch statistics (host sync): stats[0] pairs P, [1] overflow flag,
  * [2] visible (view, surfel) slots, [3] pixels, [4] tiles, [5] slots V*N. */
 ROGS_API int rogs_batch_stats(rogs_ctx* ctx, void* ws, int64_t* stats, void* stream);

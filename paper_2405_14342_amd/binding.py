@@ -29,7 +29,8 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_render_fwd", "rogs_loss", "rogs_render_bwd", "rogs_adam_step",
             "rogs_debug_pairs", "rogs_debug_records", "rogs_batch_stats", "rogs_prof_enable",
             "rogs_prof_read", "rogs_prof_name", "rogs_fused_workspace_size", "rogs_step_fused",
-            "rogs_fused_status", "rogs_autotune")
+            "rogs_fused_status", "rogs_autotune", "rogs_server_create", "rogs_serve_submit",
+            "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy")
 PROF_GROUPS = 11
 FUSED_EAGER = 4
 
@@ -56,6 +57,25 @@ class Camera(ctypes.Structure):
                 ("cull_o", ctypes.c_float * 2), ("cull_ex", ctypes.c_float * 2),
                 ("cull_ez", ctypes.c_float * 2), ("cull_lat", ctypes.c_float),
                 ("cull_fwd", ctypes.c_float)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("cam", Camera), ("channels", ctypes.c_uint32), ("elev_ref", ctypes.c_float),
+                ("out", _vp)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_views", ctypes.c_int32),
+                ("t_arrive_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+CH_RGB, CH_SEM, CH_D, CH_A, CH_ELEV = 1, 2, 4, 8, 16
+
+
+def channel_planes(channels: int, C: int) -> int:
+    return (3 * bool(channels & CH_RGB) + C * bool(channels & CH_SEM) + bool(channels & CH_D)
+            + bool(channels & CH_A) + bool(channels & CH_ELEV))
 
 
 class RenderOpts(ctypes.Structure):
@@ -129,6 +149,13 @@ def load_library(path: str = LIB_PATH):
                                  ctypes.POINTER(RenderOpts), ctypes.POINTER(Targets),
                                  ctypes.POINTER(Optim), P, ctypes.c_size_t, I64, I64, U32, P], I32),
             "rogs_fused_status": ([P, P, P], I32),
+            "rogs_server_create": ([ctypes.POINTER(P), ctypes.POINTER(Surfels),
+                                    ctypes.POINTER(RenderOpts), P, ctypes.c_size_t, I32, I32], I32),
+            "rogs_serve_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
+                                  I32),
+            "rogs_serve_poll": ([P, ctypes.c_uint64, ctypes.POINTER(Result)], I32),
+            "rogs_server_stats": ([P, P], I32),
+            "rogs_server_destroy": ([P], None),
             "rogs_autotune": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
                                ctypes.POINTER(RenderOpts), ctypes.c_char_p, I32,
                                ctypes.POINTER(ctypes.c_float), P], I32),
@@ -364,3 +391,71 @@ class Rogs:
         self._check(self.L.rogs_debug_records(self.h, ptr(ws), rec.ctypes.data, rect.ctypes.data,
                                               cnt.ctypes.data, _stream(stream)), "rogs_debug_records")
         return rec, rect, cnt
+
+
+class Server:
+    """Continuous-batching render server (rogs_server_*) over a resident map.
+
+    ``keep`` holds the tensors behind the map's pointers and the arena so they
+    outlive the server."""
+
+    def __init__(self, surf: Surfels, opts: Optional[RenderOpts], arena, max_views: int = 16,
+                 device: int = 0, keep=()):
+        self.L = load_library()
+        self.h = ctypes.c_void_p()
+        self._keep = (surf, arena, tuple(keep))
+        self.C = int(surf.n_sem)
+        o = opts if opts is not None else default_opts()
+        r = self.L.rogs_server_create(ctypes.byref(self.h), ctypes.byref(surf), ctypes.byref(o),
+                                      ptr(arena), arena.numel() * arena.element_size(),
+                                      int(max_views), int(device))
+        if r != OK:
+            raise RogsError(r, "rogs_server_create")
+
+    def submit(self, cam, channels: int, out, elev_ref: float = 0.0,
+               raise_on_reject: bool = True) -> int:
+        req = Request(cam if isinstance(cam, Camera) else make_camera(cam), int(channels),
+                      float(elev_ref), ptr(out))
+        t = ctypes.c_uint64(0)
+        r = self.L.rogs_serve_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        if r != OK:
+            if not raise_on_reject and r == EREJECT:
+                return 0
+            raise RogsError(r, "rogs_serve_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int) -> Optional[dict]:
+        """None while pending; the result dict once done (the ticket is released)."""
+        res = Result()
+        r = self.L.rogs_serve_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(res))
+        if r == NOT_READY:
+            return None
+        if r != OK:
+            raise RogsError(r, "rogs_serve_poll")
+        return dict(status=res.status, batch_views=res.batch_views, t_arrive_ns=res.t_arrive_ns,
+                    t_start_ns=res.t_start_ns, t_done_ns=res.t_done_ns)
+
+    def wait(self, ticket: int, sleep_s: float = 0.0002) -> dict:
+        import time
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            time.sleep(sleep_s)
+
+    def stats(self) -> dict:
+        st = np.zeros(6, np.int64)
+        self.L.rogs_server_stats(self.h, st.ctypes.data)
+        return dict(batches=int(st[0]), views=int(st[1]), splits=int(st[2]),
+                    max_batch=int(st[3]), capacity_failures=int(st[4]), queued=int(st[5]))
+
+    def close(self):
+        if self.h:
+            self.L.rogs_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librogs.so")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "loss_adam.hip", "autotune.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "loss_adam.hip", "autotune.hip",
+           "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

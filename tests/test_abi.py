@@ -41,6 +41,9 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(B.Surfels) == 8 + 8 * 8
     assert ctypes.sizeof(B.Targets) == 4 * 8 + 3 * 4 + 4
     assert ctypes.sizeof(B.LR) == 7 * 4
+    # rogs_request: camera, channels, elev_ref, then the 8-byte-aligned pointer
+    assert ctypes.sizeof(B.Request) == 136 and B.Request.out.offset == 128
+    assert ctypes.sizeof(B.Result) == 32
 
 
 def _surf(n=100, C=8):
