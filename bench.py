@@ -95,6 +95,87 @@ def cpu_baseline(scene, budget_s: float = 12.0):
                       f"({scene.n_views} views, {scene.npix} px each step), {el:.1f} s"}
 
 
+def serve_bench(seconds: float, warmup_s: float = 1.0, rate: float = 200.0,
+                max_views: int = 16, lanes: int = 2):
+    """Serving workload: the 3M-surfel, C = 16 map resident on the GPU,
+    Poisson arrivals at `rate`/s of single-view requests (four pinhole sizes
+    and a 512 x 512 top-down orthographic view; channel sets RGB / RGB+SEM /
+    RGB+SEM+D+A, ELEV+SEM for the top-down view), served by the library's
+    continuous-batching server.  Latency = completion - submit, measured by
+    the server on the steady clock; requests arriving during the first
+    warmup_s seconds are not counted."""
+    import numpy as np
+    import torch
+    from paper_2405_14342_amd import binding as B
+    from paper_2405_14342_amd import synth
+
+    sc = synth.config4(with_targets=False)
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device="cuda:0")
+    dev = dict(x=f(sc.x), y=f(sc.y), z=f(sc.z), q=f(sc.q), s=f(sc.s), alpha=f(sc.alpha),
+               rgb=f(sc.rgb), sem=f(sc.sem))
+    surf = B.Surfels(sc.n, sc.n_sem, *(dev[k].data_ptr() for k in
+                                       ("x", "y", "z", "q", "s", "alpha", "rgb", "sem")))
+    C = sc.n_sem
+    kinds = {"rgb": B.CH_RGB, "rgb_sem": B.CH_RGB | B.CH_SEM,
+             "rgb_sem_d_a": B.CH_RGB | B.CH_SEM | B.CH_D | B.CH_A,
+             "elev_sem": B.CH_ELEV | B.CH_SEM}
+    sched = synth.serve_schedule(sc.trajectory, rate, warmup_s + seconds)
+    max_floats = max(B.channel_planes(ch, C) for ch in kinds.values()) * 1920 * 1080
+    pool = [torch.empty(max_floats, dtype=torch.float32, device="cuda:0") for _ in range(48)]
+    arena = torch.empty(8 << 30, dtype=torch.uint8, device="cuda:0")
+    opts = B.make_opts(tile_w=16, tile_h=4)
+    srv = B.Server(surf, opts, arena, max_views=max_views, lanes=lanes, keep=(dev, sc))
+    # one request of every class first, so the timed run starts warm
+    for cls_req in sched[:8]:
+        srv.wait(srv.submit(cls_req.cam, kinds[cls_req.kind], pool[0], cls_req.elev_ref))
+    free = list(range(len(pool)))
+    live = {}                      # ticket -> (buffer index, request)
+    done = []
+    dropped = 0
+
+    def collect(block: bool):
+        for tk in list(live):
+            r = srv.wait(tk) if block else srv.poll(tk)
+            if r is not None:
+                b, rq = live.pop(tk)
+                free.append(b)
+                done.append((rq, r))
+
+    t0 = time.perf_counter()
+    for rq in sched:
+        while True:
+            collect(False)
+            now = time.perf_counter() - t0
+            if now >= rq.t:
+                break
+            if rq.t - now > 0.0005:
+                time.sleep(0.0002)
+        if not free:
+            dropped += 1
+            continue
+        b = free.pop()
+        live[srv.submit(rq.cam, kinds[rq.kind], pool[b], rq.elev_ref)] = (b, rq)
+    collect(True)
+    stats = srv.stats()
+    srv.close()
+    ok = [(rq, r) for rq, r in done if r["status"] == B.OK and rq.t >= warmup_s]
+    lat = np.array([(r["t_done_ns"] - r["t_arrive_ns"]) * 1e-6 for _, r in ok])
+    t_first = min(r["t_arrive_ns"] for _, r in ok)
+    t_last = max(r["t_done_ns"] for _, r in ok)
+    span = (t_last - t_first) * 1e-9
+    px = sum(rq.cam.w * rq.cam.h for rq, _ in ok)
+    return {"workload": "C5: 3M-surfel C=16 map, Poisson %.0f req/s, %.0f s (+%.0f s warm-up)"
+                        % (rate, seconds, warmup_s),
+            "renders_per_s": round(len(ok) / span, 2), "Mpixel_per_s": round(px / span / 1e6, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "requests": len(ok), "failed": sum(1 for _, r in done if r["status"] != B.OK),
+            "dropped_no_buffer": dropped, "batches": stats["batches"],
+            "mean_batch_views": round(stats["views"] / max(1, stats["batches"]), 2),
+            "max_batch_views": stats["max_batch"], "lanes": lanes,
+            "max_batches_in_flight": stats["max_in_flight"], "tile": "16x4"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +187,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", default="16x4",
                     help="tile shape WxH, or 'auto' (rogs_autotune; default 16x4)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the timed serving run (0 = skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a 256 MiB device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
@@ -218,7 +301,7 @@ def main():
 
     value = scene.npix / (ms_f * 1e-3) / 1e6
     line = {
-        "metric": "fwd+bwd Mpixel/s per train step (fused vs plain)",
+        "metric": "fwd+bwd Mpixel/s per train step (fused vs plain); serve renders/s + p50/p99",
         "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_f, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -235,6 +318,15 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if args.serve_seconds > 0:
+        print("[bench] serving (3M-surfel map, Poisson 200 req/s)...", file=sys.stderr, flush=True)
+        del st
+        torch.cuda.empty_cache()
+        line["serve"] = serve_bench(args.serve_seconds)
+        sv = line["serve"]
+        print(f"[bench] serve: {sv['renders_per_s']} renders/s, p50 {sv['p50_ms']} ms, "
+              f"p99 {sv['p99_ms']} ms, mean batch {sv['mean_batch_views']}", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene)

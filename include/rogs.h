@@ -336,9 +336,9 @@ ROGS_API int rogs_autotune(rogs_ctx* ctx, const rogs_surfels* s, const rogs_came
 
 /* ------------------------------------------------------ serving
  * Render server over a resident map (the served form of a6: forward only).
- * Requests are single views with a channel set; a worker thread owned by the
- * server batches whatever is queued whenever it is idle (continuous
- * batching, up to max_views views per batch and what the arena holds),
+ * Requests are single views with a channel set; worker lanes owned by the
+ * server batch whatever is queued whenever one is idle (continuous
+ * batching, up to max_views views per batch and what a lane's arena holds),
  * renders the batch with rogs_project + rogs_bin_sort (pair count on the
  * device) + rogs_render_fwd, and copies each request's channels into its
  * buffer.  A batch that overflows the pair capacity the arena leaves is split
@@ -377,24 +377,27 @@ typedef struct {
 
 /* map: device surfel arrays that stay valid and unchanged while the server
  * lives.  arena: caller-owned device memory (256-byte aligned) holding the
- * batch workspace and images; the server allocates no device memory.
- * device: HIP device ordinal the worker renders on.  Returns ROGS_EINVAL for
- * bad arguments. */
+ * batch workspaces and images; the server allocates no device memory.
+ * lanes (1..8): worker threads, each with its own stream and an equal share
+ * of the arena; an idle lane takes the queued requests, so batches on
+ * different lanes overlap on the device.  device: HIP device ordinal.
+ * Returns ROGS_EINVAL for bad arguments. */
 ROGS_API int rogs_server_create(rogs_server** srv, const rogs_surfels* map,
                                 const rogs_render_opts* opts, void* arena, size_t arena_bytes,
-                                int32_t max_views, int32_t device);
+                                int32_t max_views, int32_t lanes, int32_t device);
 /* Thread-safe.  Queues one request and returns its ticket.  ROGS_EINVAL: bad
- * camera, channels or buffer; ROGS_EREJECT: the view alone cannot fit the
- * arena, or the queue is full (65536 requests); ROGS_ESTATE: the server is
- * shutting down. */
+ * camera, channels or buffer; ROGS_EREJECT: the view alone cannot fit a
+ * lane's arena share, or the queue is full (65536 requests); ROGS_ESTATE:
+ * the server is shutting down. */
 ROGS_API int rogs_serve_submit(rogs_server* srv, const rogs_request* req, uint64_t* ticket);
 /* Thread-safe, non-blocking.  ROGS_NOT_READY while the request is queued or
  * rendering (res gets t_arrive_ns); ROGS_OK once done: res filled, the ticket
  * is released (a second poll returns ROGS_EINVAL).  res->status carries the
  * request's own outcome. */
 ROGS_API int rogs_serve_poll(rogs_server* srv, uint64_t ticket, rogs_result* res);
-/* stats[6]: batches, views rendered, batch splits, largest batch, views that
- * failed with ROGS_ECAPACITY, requests queued now. */
+/* stats[7]: batches, views rendered, batch splits, largest batch, views that
+ * failed with ROGS_ECAPACITY, requests queued now, most batches in flight at
+ * once (over all lanes). */
 ROGS_API int rogs_server_stats(rogs_server* srv, int64_t* stats);
 /* Stops accepting requests, renders everything still queued, joins the
  * worker and frees the server (not the arena). */

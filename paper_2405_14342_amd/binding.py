@@ -150,7 +150,8 @@ def load_library(path: str = LIB_PATH):
                                  ctypes.POINTER(Optim), P, ctypes.c_size_t, I64, I64, U32, P], I32),
             "rogs_fused_status": ([P, P, P], I32),
             "rogs_server_create": ([ctypes.POINTER(P), ctypes.POINTER(Surfels),
-                                    ctypes.POINTER(RenderOpts), P, ctypes.c_size_t, I32, I32], I32),
+                                    ctypes.POINTER(RenderOpts), P, ctypes.c_size_t, I32, I32, I32],
+                                   I32),
             "rogs_serve_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
                                   I32),
             "rogs_serve_poll": ([P, ctypes.c_uint64, ctypes.POINTER(Result)], I32),
@@ -400,7 +401,7 @@ class Server:
     outlive the server."""
 
     def __init__(self, surf: Surfels, opts: Optional[RenderOpts], arena, max_views: int = 16,
-                 device: int = 0, keep=()):
+                 lanes: int = 2, device: int = 0, keep=()):
         self.L = load_library()
         self.h = ctypes.c_void_p()
         self._keep = (surf, arena, tuple(keep))
@@ -408,7 +409,7 @@ class Server:
         o = opts if opts is not None else default_opts()
         r = self.L.rogs_server_create(ctypes.byref(self.h), ctypes.byref(surf), ctypes.byref(o),
                                       ptr(arena), arena.numel() * arena.element_size(),
-                                      int(max_views), int(device))
+                                      int(max_views), int(lanes), int(device))
         if r != OK:
             raise RogsError(r, "rogs_server_create")
 
@@ -444,10 +445,11 @@ class Server:
             time.sleep(sleep_s)
 
     def stats(self) -> dict:
-        st = np.zeros(6, np.int64)
+        st = np.zeros(7, np.int64)
         self.L.rogs_server_stats(self.h, st.ctypes.data)
         return dict(batches=int(st[0]), views=int(st[1]), splits=int(st[2]),
-                    max_batch=int(st[3]), capacity_failures=int(st[4]), queued=int(st[5]))
+                    max_batch=int(st[3]), capacity_failures=int(st[4]), queued=int(st[5]),
+                    max_in_flight=int(st[6]))
 
     def close(self):
         if self.h:

@@ -1,12 +1,15 @@
 // Continuous-batching render server over a resident surfel map.
 //
 // Requests (one view each, a channel set and a caller-owned device output
-// buffer) are queued by rogs_serve_submit from any thread.  One worker thread
-// owns a library context and a stream: whenever it is idle it takes every
-// queued request that fits (up to max_views views and the arena), renders
-// them as one batch (rogs_project + rogs_bin_sort with the pair count on the
-// device + rogs_render_fwd into the arena), copies each request's channels
-// into its buffer, and waits for the batch.  If the batch overflowed the pair
+// buffer) are queued by rogs_serve_submit from any thread.  The server runs
+// `lanes` worker threads; each owns a library context, a stream and an equal
+// share of the arena.  Whenever a lane is idle it takes every queued request
+// that fits (up to max_views views and its arena share), so requests that
+// arrive while other batches are on the GPU start on a free lane and their
+// work overlaps on the device.  A lane renders its requests as one batch
+// (rogs_project + rogs_bin_sort with the pair count on the device +
+// rogs_render_fwd into its arena share), copies each request's channels into
+// its buffer, and waits for the batch.  If the batch overflowed the pair
 // capacity that the arena allows, it is split in two and both halves run
 // again; a single view that does not fit fails with ROGS_ECAPACITY.  Each
 // view is rendered independently of the others in its batch (per-view tile
@@ -31,11 +34,6 @@ int64_t now_ns() {
       .count();
 }
 
-int planes_of(uint32_t ch, int C) {
-  return ((ch & ROGS_CH_RGB) ? 3 : 0) + ((ch & ROGS_CH_SEM) ? C : 0) + ((ch & ROGS_CH_D) ? 1 : 0) +
-         ((ch & ROGS_CH_A) ? 1 : 0) + ((ch & ROGS_CH_ELEV) ? 1 : 0);
-}
-
 // Copies the requested planes of one rendered view (5 + C planes: R G B,
 // sem, D, A) into the request's buffer, in the order RGB, SEM, D, A, ELEV.
 // ELEV = elev_ref - D / A where A > 0, NaN where nothing was composited.
@@ -52,7 +50,8 @@ __global__ __launch_bounds__(256) void k_serve_extract(const float* __restrict__
   const float D = img[(3 + C) * npix + p], A = img[(4 + C) * npix + p];
   if (ch & ROGS_CH_D) out[(o++) * npix + p] = D;
   if (ch & ROGS_CH_A) out[(o++) * npix + p] = A;
-  if (ch & ROGS_CH_ELEV) out[(o++) * npix + p] = (A > 0.0f) ? elev_ref - D / A : __int_as_float(0x7fc00000);
+  if (ch & ROGS_CH_ELEV)
+    out[(o++) * npix + p] = (A > 0.0f) ? elev_ref - D / A : __int_as_float(0x7fc00000);
 }
 
 struct Item {
@@ -63,12 +62,21 @@ struct Item {
 
 }  // namespace
 
+struct ServeLane {
+  uint8_t* arena = nullptr;       // this lane's share of the arena
+  size_t arena_bytes = 0;
+  rogs_ctx* ctx = nullptr;        // owned by the lane's thread
+  hipStream_t st = nullptr;
+  std::thread thread;
+  int init_status = ROGS_OK;
+  bool ready = false;
+};
+
 struct rogs_server {
   int device = 0;
   rogs_surfels map{};
   rogs_render_opts opts{};
-  uint8_t* arena = nullptr;
-  size_t arena_bytes = 0;
+  size_t lane_bytes = 0;
   int max_views = 1;
   std::mutex mu;
   std::condition_variable cv;
@@ -76,13 +84,10 @@ struct rogs_server {
   std::unordered_map<uint64_t, rogs_result> results;   // pending (status NOT_READY) or done
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread worker;
-  int64_t stats[8] = {};          // batches, views, splits, max batch, capacity failures
-  // worker-owned
-  rogs_ctx* ctx = nullptr;
-  hipStream_t st = nullptr;
-  int init_status = ROGS_OK;
-  bool ready = false;
+  std::vector<ServeLane> lanes;
+  int64_t stats[8] = {};          // batches, views, splits, max batch, capacity failures,
+                                  // -, -, most batches on the GPU at once
+  int64_t busy = 0;
 };
 
 namespace {
@@ -113,8 +118,8 @@ int64_t fit_capacity(const rogs_server* s, const std::vector<rogs_camera>& cams,
   return lo;
 }
 
-// Renders one batch; returns false if it overflowed and must be split.
-bool run_batch(rogs_server* s, std::vector<Item>& batch) {
+// Renders one batch on a lane; returns false if it overflowed and must be split.
+bool run_batch(rogs_server* s, ServeLane& ln, std::vector<Item>& batch) {
   std::vector<rogs_camera> cams;
   int64_t pix = 0;
   for (const Item& it : batch) {
@@ -135,33 +140,37 @@ bool run_batch(rogs_server* s, std::vector<Item>& batch) {
       r.t_done_ns = t;
     }
   };
-  const int64_t cap = img < s->arena_bytes ? fit_capacity(s, cams, s->arena_bytes - img) : 0;
+  const int64_t cap = img < ln.arena_bytes ? fit_capacity(s, cams, ln.arena_bytes - img) : 0;
   if (cap <= 0) {
-    if (batch.size() > 1) return false;
+    if (batch.size() > 1) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stats[2] += 1;
+      return false;
+    }
     finish(ROGS_ECAPACITY);
     return true;
   }
   size_t wsb = 0;
   (void)rogs_workspace_size(&s->map, cams.data(), (int)cams.size(), &s->opts, cap, 0, &wsb);
-  void* ws = s->arena;
-  float* images = reinterpret_cast<float*>(s->arena + wsb);
-  int r = rogs_project(s->ctx, &s->map, cams.data(), (int)cams.size(), &s->opts, ws, wsb, cap, 0,
-                       s->st);
-  if (r == ROGS_OK) r = rogs_bin_sort(s->ctx, ws, nullptr, 0u, s->st);
-  if (r == ROGS_OK) r = rogs_render_fwd(s->ctx, &s->map, ws, images, s->st);
+  void* ws = ln.arena;
+  float* images = reinterpret_cast<float*>(ln.arena + wsb);
+  int r = rogs_project(ln.ctx, &s->map, cams.data(), (int)cams.size(), &s->opts, ws, wsb, cap, 0,
+                       ln.st);
+  if (r == ROGS_OK) r = rogs_bin_sort(ln.ctx, ws, nullptr, 0u, ln.st);
+  if (r == ROGS_OK) r = rogs_render_fwd(ln.ctx, &s->map, ws, images, ln.st);
   int64_t off = 0;
   const int C = s->map.n_sem;
   for (size_t k = 0; k < batch.size() && r == ROGS_OK; ++k) {
     const rogs_request& q = batch[k].req;
     const int64_t np = (int64_t)q.cam.w * q.cam.h;
-    hipLaunchKernelGGL(k_serve_extract, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s->st,
+    hipLaunchKernelGGL(k_serve_extract, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ln.st,
                        images + (5 + C) * off, np, C, q.channels, q.elev_ref, q.out);
     off += np;
   }
   if (r == ROGS_OK && hipGetLastError() != hipSuccess) r = ROGS_EHIP;
   int64_t n = 0;
   int32_t ovf = 0;
-  if (r == ROGS_OK) r = rogs_pair_count(s->ctx, ws, &n, &ovf, s->st);   // waits for the batch
+  if (r == ROGS_OK) r = rogs_pair_count(ln.ctx, ws, &n, &ovf, ln.st);   // waits for the batch
   if (r == ROGS_OK && ovf) {
     if (batch.size() > 1) {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -182,36 +191,39 @@ bool run_batch(rogs_server* s, std::vector<Item>& batch) {
   return true;
 }
 
-void worker_main(rogs_server* s) {
+void worker_main(rogs_server* s, int lane) {
+  ServeLane& ln = s->lanes[lane];
   int r = hipSetDevice(s->device) == hipSuccess ? ROGS_OK : ROGS_EHIP;
-  if (r == ROGS_OK) r = rogs_create(&s->ctx);
-  if (r == ROGS_OK && hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess)
+  if (r == ROGS_OK) r = rogs_create(&ln.ctx);
+  if (r == ROGS_OK && hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess)
     r = ROGS_EHIP;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    s->init_status = r;
-    s->ready = true;
+    ln.init_status = r;
+    ln.ready = true;
   }
   s->cv.notify_all();
   if (r != ROGS_OK) return;
-  std::vector<Item> batch, rest;
+  std::vector<Item> batch;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
       if (s->queue.empty()) break;                 // stop requested and drained
       // continuous batching: everything queued now, up to max_views views
-      // whose images leave room for a workspace in the arena
+      // whose images leave room for a workspace in this lane's arena share
       int64_t pix = 0;
       batch.clear();
       while (!s->queue.empty() && (int)batch.size() < s->max_views) {
         const Item& it = s->queue.front();
         const int64_t np = (int64_t)it.req.cam.w * it.req.cam.h;
-        if (!batch.empty() && image_bytes(s, pix + np) * 2 > s->arena_bytes) break;
+        if (!batch.empty() && image_bytes(s, pix + np) * 2 > ln.arena_bytes) break;
         pix += np;
         batch.push_back(it);
         s->queue.pop_front();
       }
+      s->busy += 1;
+      if (s->busy > s->stats[7]) s->stats[7] = s->busy;
     }
     // split until every part fits; parts keep the arrival order
     std::deque<std::vector<Item>> work;
@@ -219,11 +231,28 @@ void worker_main(rogs_server* s) {
     while (!work.empty()) {
       std::vector<Item> b = std::move(work.front());
       work.pop_front();
-      if (run_batch(s, b)) continue;
+      if (run_batch(s, ln, b)) continue;
       const size_t h = b.size() / 2;
       work.push_front(std::vector<Item>(b.begin() + h, b.end()));
       work.push_front(std::vector<Item>(b.begin(), b.begin() + h));
     }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->busy -= 1;
+  }
+}
+
+void stop_lanes(rogs_server* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (ServeLane& ln : s->lanes) {
+    if (ln.thread.joinable()) ln.thread.join();
+    if (ln.st) (void)hipStreamDestroy(ln.st);
+    rogs_destroy(ln.ctx);
+    ln.st = nullptr;
+    ln.ctx = nullptr;
   }
 }
 
@@ -232,10 +261,13 @@ void worker_main(rogs_server* s) {
 extern "C" {
 
 int rogs_server_create(rogs_server** out, const rogs_surfels* map, const rogs_render_opts* opts,
-                       void* arena, size_t arena_bytes, int32_t max_views, int32_t device) {
+                       void* arena, size_t arena_bytes, int32_t max_views, int32_t lanes,
+                       int32_t device) {
   if (!out) return ROGS_EINVAL;
   *out = nullptr;
-  if (!map || !opts || !arena || max_views < 1 || max_views > 256 || device < 0) return ROGS_EINVAL;
+  if (!map || !opts || !arena || max_views < 1 || max_views > 256 || lanes < 1 || lanes > 8 ||
+      device < 0)
+    return ROGS_EINVAL;
   if (reinterpret_cast<uintptr_t>(arena) % 256 != 0) return ROGS_EINVAL;
   if (!map->x || !map->y || !map->z || !map->q || !map->s || !map->alpha || !map->rgb || !map->sem)
     return ROGS_EINVAL;
@@ -250,20 +282,25 @@ int rogs_server_create(rogs_server** out, const rogs_surfels* map, const rogs_re
   s->device = device;
   s->map = *map;
   s->opts = *opts;
-  s->arena = static_cast<uint8_t*>(arena);
-  s->arena_bytes = arena_bytes;
   s->max_views = max_views;
-  s->worker = std::thread(worker_main, s);
-  int r;
+  s->lane_bytes = arena_bytes / (size_t)lanes / 256 * 256;
+  s->lanes.resize((size_t)lanes);
+  for (int k = 0; k < lanes; ++k) {
+    s->lanes[k].arena = static_cast<uint8_t*>(arena) + (size_t)k * s->lane_bytes;
+    s->lanes[k].arena_bytes = s->lane_bytes;
+  }
+  int r = ROGS_OK;
+  for (int k = 0; k < lanes; ++k) s->lanes[k].thread = std::thread(worker_main, s, k);
   {
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv.wait(lk, [&] { return s->ready; });
-    r = s->init_status;
+    s->cv.wait(lk, [&] {
+      for (const ServeLane& ln : s->lanes) if (!ln.ready) return false;
+      return true;
+    });
+    for (const ServeLane& ln : s->lanes) if (ln.init_status != ROGS_OK) r = ln.init_status;
   }
   if (r != ROGS_OK) {
-    s->worker.join();
-    if (s->st) (void)hipStreamDestroy(s->st);
-    rogs_destroy(s->ctx);
+    stop_lanes(s);
     delete s;
     return r;
   }
@@ -278,7 +315,7 @@ int rogs_serve_submit(rogs_server* s, const rogs_request* req, uint64_t* ticket)
   size_t b = 0;
   if (rogs_workspace_size(&s->map, &req->cam, 1, &s->opts, 0, 0, &b) != ROGS_OK) return ROGS_EINVAL;
   // admission: the view's images and a minimal workspace must fit the arena
-  if (image_bytes(s, (int64_t)req->cam.w * req->cam.h) + b > s->arena_bytes) return ROGS_EREJECT;
+  if (image_bytes(s, (int64_t)req->cam.w * req->cam.h) + b > s->lane_bytes) return ROGS_EREJECT;
   const int64_t t = now_ns();
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -312,19 +349,13 @@ int rogs_server_stats(rogs_server* s, int64_t* stats) {
   std::lock_guard<std::mutex> lk(s->mu);
   for (int k = 0; k < 5; ++k) stats[k] = s->stats[k];
   stats[5] = (int64_t)s->queue.size();
+  stats[6] = s->stats[7];
   return ROGS_OK;
 }
 
 void rogs_server_destroy(rogs_server* s) {
   if (!s) return;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-  }
-  s->cv.notify_all();
-  s->worker.join();
-  if (s->st) (void)hipStreamDestroy(s->st);
-  rogs_destroy(s->ctx);
+  stop_lanes(s);
   delete s;
 }
 

@@ -332,6 +332,48 @@ def mini_strip(n_along=240, n_across=60, n_sem=8, w=320, h=180, n_frames=1,
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
 
+# serving request classes over the 3M-surfel map (pinhole sizes with HFOV 70
+# degrees, and a 512 x 512 top-down orthographic view at 0.05 m/px)
+SERVE_CLASSES = [(640, 360), (1280, 720), (1600, 900), (1920, 1080), "bev"]
+SERVE_KINDS_PINHOLE = ["rgb", "rgb_sem", "rgb_sem_d_a"]
+BEV_HEIGHT = 50.0
+
+
+@dataclass
+class ServeRequest:
+    t: float             # arrival time (s) from the start of the schedule
+    cam: Camera
+    kind: str            # "rgb", "rgb_sem", "rgb_sem_d_a" (pinhole) or "elev_sem" (BEV)
+    elev_ref: float      # camera height for the elevation channel
+
+
+def serve_schedule(traj: Trajectory, rate: float, duration: float, seed: int = 5000,
+                   length_m: float = 1000.0) -> List[ServeRequest]:
+    """Poisson arrivals at ``rate`` per second over ``duration`` seconds; pose
+    s ~ U[0, length_m], rig camera ~ U{0..5}; class uniform over
+    SERVE_CLASSES; pinhole channel set uniform over SERVE_KINDS_PINHOLE."""
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return out
+        s = rng.uniform(0.0, length_m)
+        k = int(rng.integers(0, 6))
+        cls = SERVE_CLASSES[int(rng.integers(0, len(SERVE_CLASSES)))]
+        p, th = traj.at(s)
+        if cls == "bev":
+            zc = float(surface_height(p[0], p[1])) + BEV_HEIGHT
+            out.append(ServeRequest(t, ortho_bev_camera((p[0], p[1]), zc, 512, 512, 0.05),
+                                    "elev_sem", zc))
+            continue
+        w, h = cls
+        zc = float(surface_height(p[0], p[1])) + CAM_HEIGHT
+        cam = pinhole_camera((p[0], p[1], zc), th + math.radians(60.0 * k),
+                             math.radians(CAM_PITCH_DEG), w, h, focal_from_hfov(w))
+        kind = SERVE_KINDS_PINHOLE[int(rng.integers(0, 3))]
+        out.append(ServeRequest(t, cam, kind, zc))
+
 
 def custom_scene(x, y, z, q, s, alpha, rgb, sem, cams, targets=None, name="custom",
                  seed: int = 99) -> Scene:

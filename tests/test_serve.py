@@ -28,10 +28,10 @@ def _scene():
     return sc
 
 
-def _server(st, arena_bytes=256 << 20, max_views=16):
+def _server(st, arena_bytes=512 << 20, max_views=16, lanes=2):
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     keep = (st.params, st.s_act, st.alpha_act, st.x, st.y)
-    return B.Server(st.surfels(), st.opts, arena, max_views=max_views, keep=keep)
+    return B.Server(st.surfels(), st.opts, arena, max_views=max_views, lanes=lanes, keep=keep)
 
 
 def _direct(st):
@@ -97,14 +97,11 @@ def test_request_renders_the_same_alone_and_batched():
         r = srv.wait(srv.submit(cam, ALL, alone, elev_ref=1.0))
         assert r["status"] == B.OK and r["batch_views"] == 1
         seen_batched = False
-        for _ in range(5):
-            # a large first request keeps the worker busy while the rest queue up
-            big = synth.pinhole_camera((0.0, 0.0, 1.5), 0.0, math.radians(-10.0), 1600, 900,
-                                       1142.52)
-            ob = _out(big, ALL, sc.n_sem)
+        for _ in range(8):
+            # a burst: whatever is queued when a lane frees up is one batch
             others = [(c, _out(c, ALL, sc.n_sem)) for c in sc.cams]
             mixed = _out(cam, ALL, sc.n_sem)
-            ts = [srv.submit(big, ALL, ob)] + [srv.submit(c, ALL, o) for c, o in others]
+            ts = [srv.submit(c, ALL, o) for c, o in others]
             tr = srv.submit(cam, ALL, mixed, elev_ref=1.0)
             res = [srv.wait(t) for t in ts]
             rr = srv.wait(tr)
@@ -113,8 +110,34 @@ def test_request_renders_the_same_alone_and_batched():
             if rr["batch_views"] > 1:
                 seen_batched = True
                 break
-        assert seen_batched
-        assert srv.stats()["max_batch"] > 1
+        assert seen_batched and srv.stats()["max_batch"] > 1
+    finally:
+        srv.close()
+
+
+def test_batches_overlap_on_two_lanes():
+    sc = _scene()
+    st = TrainState(sc)
+    srv = _server(st, arena_bytes=4 << 30, lanes=2)
+    try:
+        cam = sc.cams[1]
+        alone = _out(cam, ALL, sc.n_sem)
+        srv.wait(srv.submit(cam, ALL, alone))
+        big = synth.pinhole_camera((0.0, 0.0, 1.5), 0.0, math.radians(-10.0), 4096, 2048, 2900.0)
+        ob = _out(big, B.CH_RGB, sc.n_sem)
+        seen = False
+        for k in range(10):
+            tb = srv.submit(big, B.CH_RGB, ob)
+            time.sleep(0.0002 * (k + 1))
+            mixed = _out(cam, ALL, sc.n_sem)
+            tr = srv.submit(cam, ALL, mixed)
+            rb, rr = srv.wait(tb), srv.wait(tr)
+            assert rb["status"] == B.OK and rr["status"] == B.OK
+            assert torch.equal(torch.nan_to_num(mixed, nan=-1.0), torch.nan_to_num(alone, nan=-1.0))
+            if rr["t_start_ns"] < rb["t_done_ns"] and rb["t_start_ns"] < rr["t_done_ns"]:
+                seen = True
+                break
+        assert seen and srv.stats()["max_in_flight"] == 2
     finally:
         srv.close()
 
@@ -124,7 +147,7 @@ def test_overflowing_batch_is_split():
     st = TrainState(sc)
     ref = _direct(st)
     # room for one view's pairs at a time but not for two views together
-    srv = _server(st, arena_bytes=12 << 20)
+    srv = _server(st, arena_bytes=12 << 20, lanes=1)
     try:
         outs = [_out(c, B.CH_RGB, sc.n_sem) for c in sc.cams]
         ts = [srv.submit(c, B.CH_RGB, o) for c, o in zip(sc.cams, outs)]
@@ -141,7 +164,7 @@ def test_overflowing_batch_is_split():
 def test_admission_and_argument_errors():
     sc = _scene()
     st = TrainState(sc)
-    srv = _server(st, arena_bytes=1 << 20)
+    srv = _server(st, arena_bytes=2 << 20)
     try:
         big = synth.pinhole_camera((0.0, 0.0, 1.5), 0.0, 0.0, 1920, 1080, 1371.02)
         with pytest.raises(B.RogsError, match="EREJECT"):
