@@ -425,6 +425,13 @@ ROGS_API const char* rogs_prof_name(int32_t group);
 ROGS_API int rogs_debug_pairs(rogs_ctx* ctx, void* ws, uint64_t* keys, int32_t* surfel_ids,
                      int32_t* views, int64_t cap, uint32_t* ranges, int64_t n_tiles,
                      void* stream);
+/* Work counts of the current batch after rogs_render_fwd (host sync): over
+ * all pixels, *evaluated = list entries visited front to back up to each
+ * pixel's termination, *contributing = those whose 3-sigma test passed
+ * (q32 <= q_cut).  The compositing kernels' arithmetic is proportional to
+ * these counts. */
+ROGS_API int rogs_debug_work(rogs_ctx* ctx, void* ws, int64_t* evaluated, int64_t* contributing,
+                             void* stream);
 /* Copy the per-(view, surfel) projection records of the current batch:
  * rec[V][N][8] = u_hi v_hi u_lo v_lo A B C t_z, rect[V][N][4] = x0 x1 y0 y1,
  * count[V][N] = tiles covered (0 = culled; then rec and rect are zero). */

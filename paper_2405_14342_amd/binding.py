@@ -30,7 +30,7 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_debug_pairs", "rogs_debug_records", "rogs_batch_stats", "rogs_prof_enable",
             "rogs_prof_read", "rogs_prof_name", "rogs_fused_workspace_size", "rogs_step_fused",
             "rogs_fused_status", "rogs_autotune", "rogs_server_create", "rogs_serve_submit",
-            "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy")
+            "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy", "rogs_debug_work")
 PROF_GROUPS = 11
 FUSED_EAGER = 4
 
@@ -156,6 +156,7 @@ def load_library(path: str = LIB_PATH):
                                   I32),
             "rogs_serve_poll": ([P, ctypes.c_uint64, ctypes.POINTER(Result)], I32),
             "rogs_server_stats": ([P, P], I32),
+            "rogs_debug_work": ([P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], I32),
             "rogs_server_destroy": ([P], None),
             "rogs_autotune": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
                                ctypes.POINTER(RenderOpts), ctypes.c_char_p, I32,
@@ -365,6 +366,13 @@ class Rogs:
                                          path, int(reps), ctypes.byref(ms), _stream(stream)),
                     "rogs_autotune")
         return o, float(ms.value)
+
+    def debug_work(self, ws, stream=None):
+        """(evaluated, contributing) list entries over all pixels of the batch."""
+        e, k = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.L.rogs_debug_work(self.h, ptr(ws), ctypes.byref(e), ctypes.byref(k),
+                                           _stream(stream)), "rogs_debug_work")
+        return int(e.value), int(k.value)
 
     def fused_status(self) -> dict:
         st = np.zeros(8, np.int64)

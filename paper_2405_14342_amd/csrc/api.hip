@@ -536,6 +536,26 @@ int rogs_render_fwd(rogs_ctx* c, const rogs_surfels* s, void* ws, float* out_ima
   return check_launch(c, "rogs_render_fwd");
 }
 
+int rogs_debug_work(rogs_ctx* c, void* ws, int64_t* evaluated, int64_t* contributing,
+                    void* stream) {
+  int r = need_batch(c, ws, true);
+  if (r != ROGS_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* misc = rogs::at<uint32_t>(ws, c->L.o_misc);
+  rogs::fill_u32(misc + rogs::kMiscWork, 0u, 4, st);
+  rogs::launch_count_work(c->L, ws, reinterpret_cast<unsigned long long*>(misc + rogs::kMiscWork),
+                          st);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->readback, misc + rogs::kMiscWork, 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "rogs_debug_work");
+  const unsigned long long* w = reinterpret_cast<const unsigned long long*>(c->readback);
+  if (evaluated) *evaluated = (int64_t)w[0];
+  if (contributing) *contributing = (int64_t)w[1];
+  return ROGS_OK;
+}
+
 int rogs_loss(rogs_ctx* c, void* ws, const float* out_images, const rogs_targets* t,
               float* dL_dout, float* loss_out, float* d_exposure, void* stream) {
   int r = need_batch(c, ws, true);

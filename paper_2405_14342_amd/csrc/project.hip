@@ -197,40 +197,57 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t*
 }
 
 // Exclusive scan of at most kSmallScan values in one block of 1024 threads
-// (one launch instead of three for the small tables).
+// (one launch instead of three for the small tables).  Rounds of kSmallChunk
+// values: a coalesced load into LDS (padded by one word per 32 against bank
+// conflicts), 8 consecutive values per thread, a block scan of the thread
+// sums, the results back through LDS and a coalesced store; a carry links
+// the rounds.  Every round reads its values before it writes them, so
+// in == out is allowed.
 constexpr int kSmallScan = 1024 * 32;
+constexpr int kSmallChunk = 1024 * 8;
+
+__device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
 
 __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_t* out,
                                                      int64_t n_cap,
                                                      const uint32_t* __restrict__ n_dev,
                                                      uint32_t* __restrict__ total) {
+  __shared__ uint32_t s[kSmallChunk + kSmallChunk / 32];
   __shared__ uint32_t s_w[16];
   const int64_t n = scan_count(n_dev, n_cap);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = t * per, e = (b + per < n) ? b + per : n;
-  uint32_t v[32];
-  uint32_t loc = 0;
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += kSmallChunk) {
+    const int m = (int)((n - c0) < kSmallChunk ? (n - c0) : kSmallChunk);
+    for (int i = t; i < kSmallChunk; i += 1024) s[pad32(i)] = (i < m) ? in[c0 + i] : 0u;
+    __syncthreads();
+    uint32_t v[8];
+    uint32_t loc = 0;
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    v[k] = (b + k < e) ? in[b + k] : 0u;
-    loc += v[k];
-  }
-  const uint32_t inc = wave_incl_scan(loc, lane);
-  if (lane == 63) s_w[wv] = inc;
-  __syncthreads();
-  uint32_t pre = 0, tot = 0;
-  for (int w = 0; w < 16; ++w) {
-    pre += (w < wv) ? s_w[w] : 0u;
-    tot += s_w[w];
-  }
-  uint32_t run = pre + inc - loc;
+    for (int j = 0; j < 8; ++j) {
+      v[j] = s[pad32(8 * t + j)];
+      loc += v[j];
+    }
+    const uint32_t inc = wave_incl_scan(loc, lane);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      pre += (w < wv) ? s_w[w] : 0u;
+      tot += s_w[w];
+    }
+    uint32_t run = carry + pre + inc - loc;
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    if (b + k < e) out[b + k] = run;
-    run += v[k];
+    for (int j = 0; j < 8; ++j) {
+      s[pad32(8 * t + j)] = run;
+      run += v[j];
+    }
+    __syncthreads();
+    for (int i = t; i < m; i += 1024) out[c0 + i] = s[pad32(i)];
+    carry += tot;
+    __syncthreads();
   }
-  if (t == 0 && total) *total = tot;
+  if (t == 0 && total) *total = carry;
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {

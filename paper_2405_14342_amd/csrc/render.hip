@@ -357,6 +357,59 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   }
 }
 
+// Work counts of a rendered batch (diagnostics): per pixel, the list entries
+// it visits in front-to-back order up to its termination (n_last) and, of
+// those, the ones whose 3-sigma test passes.  Summed over the batch into
+// counts[0] (evaluated) and counts[1] (contributing) with 64-bit atomics.
+__global__ __launch_bounds__(64) void k_count_work(
+    const ViewDev* __restrict__ views, int V, int tw, int th, int ppl, float qcut,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
+    const uint32_t* __restrict__ nlast, unsigned long long* __restrict__ counts) {
+  const int lane = threadIdx.x;
+  const int gt = blockIdx.x;
+  const int v = find_view(views, V, gt);
+  const ViewDev& vw = views[v];
+  const int lt = gt - vw.tile_off;
+  const int ty = lt / vw.tiles_x, tx = lt - ty * vw.tiles_x;
+  const int rows = 64 / tw;
+  const int px = tx * tw + (lane % tw);
+  const float pxc = (float)px + 0.5f;
+  uint32_t nl[4];
+  float pyc[4];
+  uint32_t maxn = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int py = ty * th + lane / tw + k * rows;
+    pyc[k] = (float)py + 0.5f;
+    nl[k] = (k < ppl && px < vw.w && py < vw.h) ? nlast[vw.pix_off + (size_t)py * vw.w + px] : 0u;
+    maxn = max(maxn, nl[k]);
+  }
+  for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, (uint32_t)__shfl_xor((int)maxn, o, 64));
+  const uint2 rg = ranges[gt];
+  const uint32_t stop = rg.x + min(maxn, rg.y - rg.x);
+  unsigned long long ev = 0, co = 0;
+  for (uint32_t p = rg.x; p < stop; ++p) {
+    const uint32_t slot = pslot[vals[p]];
+    const float4 r0 = rec[2 * (size_t)slot], r1 = rec[2 * (size_t)slot + 1];
+    const float dx = pixel_offset(pxc, r0.x, r0.z);
+    const uint32_t idx = p - rg.x;
+    for (int k = 0; k < 4; ++k) {
+      if (idx >= nl[k]) continue;
+      ev += 1;
+      const float dy = pixel_offset(pyc[k], r0.y, r0.w);
+      if (pixel_q32(r1.x, r1.y, r1.z, dx, dy) <= qcut) co += 1;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    ev += (unsigned long long)__shfl_xor((long long)ev, o, 64);
+    co += (unsigned long long)__shfl_xor((long long)co, o, 64);
+  }
+  if (lane == 0) {
+    atomicAdd(&counts[0], ev);
+    atomicAdd(&counts[1], co);
+  }
+}
+
 template <int C, int PPL, bool FUSED>
 void fwd_launch(const Layout& L, void* ws, float* out, const FusedLoss& fl, hipStream_t st) {
   hipLaunchKernelGGL((k_render_fwd<C, PPL, FUSED>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
@@ -429,6 +482,15 @@ int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels*, const floa
                       const float* G, hipStream_t st) {
   if (L.total_tiles <= 0) return 0;
   return dispatch(L, ws, out, G, nullptr, nullptr, true, st);
+}
+
+void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st) {
+  if (L.total_tiles <= 0) return;
+  hipLaunchKernelGGL(k_count_work, dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.tw, L.th, L.ppl, L.q_cut,
+                     at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
+                     at<const uint32_t>(ws, L.o_nlast), counts);
 }
 
 int launch_render_fwd_fused(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st) {

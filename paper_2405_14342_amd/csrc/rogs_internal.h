@@ -66,6 +66,7 @@ struct Layout {
 // the slots that fit the slot capacity)
 enum MiscSlot {
   kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscLong = 3, kMiscEmit = 4,
+  kMiscWork = 8,   // two 64-bit work counters (words 8-11)
   kMiscCount = 16
 };
 
@@ -402,6 +403,7 @@ void launch_scan_part(const Layout& L, void* ws, hipStream_t st);
 // by tile.  Counts < 0 are read on the device.  Returns the buffer parity.
 int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st);
 void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st);
+void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st);
 void launch_tile_order(const Layout& L, void* ws, hipStream_t st);
 int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* out, hipStream_t st);
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,

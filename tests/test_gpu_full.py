@@ -1,0 +1,268 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark uses (tile 16 x 4, all views in one batch), on outputs the FP64
+oracle can compute one by one:
+
+* 800k surfels x 24 views at mixed resolutions (1600x900 and 1280x720), C = 8;
+* 3M surfels x 6 views of 1920x1080, C = 16 (per-view culling).
+
+Keys, surfel order and per-tile ranges are compared bit-exactly on whole
+views; rendered channels at sampled pixels; gradients with dL/d(image) set at
+sampled pixels only.  On the 3M-surfel map a central finite-difference check
+of the oracle's adjoint (FP64) runs on a 32 x 32-surfel patch centred where
+the front camera's principal ray meets the ground, and the autograd wrapper's
+gradient is compared with the oracle's on that patch."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2405_14342_amd import binding as B
+from paper_2405_14342_amd import synth
+from paper_2405_14342_amd.autograd import render
+from paper_2405_14342_amd.pipeline import TrainState, n_out
+
+pytestmark = pytest.mark.gpu
+TILE = (16, 4)
+ROWS = {"z": slice(0, 1), "q": slice(1, 5), "s": slice(5, 7), "alpha": slice(7, 8),
+        "rgb": slice(8, 11), "sem": slice(11, None)}
+KEY_VIEWS = {"C3": [0, 13], "C4": [0]}
+_CACHE = {}
+
+
+def oopts():
+    return oracle.Opts(TILE[0], TILE[1], 0.3, 9.0, 0.99, 1e-6)
+
+
+def scene(name):
+    if name not in _CACHE:
+        sc = synth.config3() if name == "C3" else synth.config4()
+        _CACHE[name] = (sc, oracle.Params.from_scene(sc))
+    return _CACHE[name]
+
+
+def batched(sc):
+    st = TrainState(sc, opts=B.make_opts(tile_w=TILE[0], tile_h=TILE[1]), pair_capacity=1 << 24)
+    ws, n = st.project_and_sort(st.cams, "cap_batch", "_ws_batch")
+    return st, ws, n
+
+
+def sample_pixels(sc, n, seed):
+    rng = np.random.default_rng(seed)
+    npix = np.array([c.w * c.h for c in sc.cams])
+    v = rng.integers(0, len(sc.cams), n)
+    p = (rng.uniform(0.0, 1.0, n) * npix[v]).astype(np.int64)
+    pairs = sorted(set(zip(v.tolist(), p.tolist())))
+    return [(vv, np.array([pp for w, pp in pairs if w == vv], np.int32))
+            for vv in range(len(sc.cams))]
+
+
+@pytest.mark.parametrize("name", ["C3", "C4"])
+def test_full_size_keys_order_ranges_bitexact(name):
+    sc, prm = scene(name)
+    st, ws, n = batched(sc)
+    T = sum(((c.w + TILE[0] - 1) // TILE[0]) * ((c.h + TILE[1] - 1) // TILE[1]) for c in sc.cams)
+    keys, ids, views, ranges = st.rg.debug_pairs(ws, n, T)
+    tile_off = 0
+    for v, cam in enumerate(sc.cams):
+        nt = ((cam.w + TILE[0] - 1) // TILE[0]) * ((cam.h + TILE[1] - 1) // TILE[1])
+        if v in KEY_VIEWS[name]:
+            k, i, r = oracle.tile_lists(prm, cam, oopts())
+            sel = views[:n] == v
+            assert sel.sum() == len(k) > 0
+            np.testing.assert_array_equal(keys[:n][sel], k + (np.uint64(tile_off) << np.uint64(32)))
+            np.testing.assert_array_equal(ids[:n][sel], i)
+            first = int(np.argmax(sel))
+            rv = ranges[tile_off:tile_off + nt].astype(np.int64)
+            empty = r[:, 0] == r[:, 1]
+            np.testing.assert_array_equal(rv[~empty], r[~empty] + first)
+        tile_off += nt
+
+
+@pytest.mark.parametrize("name", ["C3", "C4"])
+def test_full_size_forward_at_sampled_pixels(name):
+    sc, prm = scene(name)
+    st, ws, n = batched(sc)
+    st.rg.render_fwd(st.surfels(), ws, st.out)
+    out = st.out.cpu().numpy()
+    NO = n_out(sc.n_sem)
+    checked = 0
+    for v, pix in sample_pixels(sc, 3000, 11):
+        if len(pix) == 0:
+            continue
+        ref, _, _ = oracle.render_fwd(prm, sc.cams[v], oopts(), pix=pix)
+        g = out[NO * st.pix_off[v]: NO * st.pix_off[v + 1]].reshape(NO, -1)[:, pix]
+        d = np.abs(g - ref)
+        col = np.r_[0:NO - 2, NO - 1]
+        assert d[col].max() <= 1e-5, (v, d[col].max())
+        assert np.all(d[NO - 2] <= 1e-5 * np.maximum(1.0, np.abs(ref[NO - 2])))
+        checked += len(pix)
+    assert checked > 2500
+
+
+@pytest.mark.parametrize("name", ["C3", "C4"])
+def test_full_size_gradients_from_sampled_pixels(name):
+    sc, prm = scene(name)
+    st, ws, n = batched(sc)
+    surf = st.surfels()
+    st.rg.render_fwd(surf, ws, st.out)
+    NO = n_out(sc.n_sem)
+    rng = np.random.default_rng(12)
+    G = np.zeros(st.out.numel(), np.float32)
+    ref = np.zeros((11 + sc.n_sem) * sc.n, np.float64)
+    for v, pix in sample_pixels(sc, 1500, 13):
+        if len(pix) == 0:
+            continue
+        cam = sc.cams[v]
+        npx = cam.w * cam.h
+        gv = rng.normal(0.0, 1.0, (NO, len(pix)))
+        o, tf, nl = oracle.render_fwd(prm, cam, oopts(), pix=pix)
+        # the depth channel is in metres (up to ~45 m): its weight is scaled to
+        # unit size, as a loss on D / max(1, D) would be, so that every
+        # channel's term has the same magnitude (the FP32 suffix term of the
+        # alpha adjoint cancels in proportion to |dL/dD| * D)
+        gv[NO - 2] /= np.maximum(1.0, o[NO - 2])
+        gv = gv.astype(np.float32)
+        block = G[NO * st.pix_off[v]: NO * st.pix_off[v + 1]].reshape(NO, npx)
+        block[:, pix] = gv
+        oracle.render_bwd(prm, cam, o, gv.astype(np.float64), tf, nl, oopts(), pix=pix, grads=ref)
+    Gd = torch.as_tensor(G, device="cuda")
+    grads = torch.empty((11 + sc.n_sem, sc.n), dtype=torch.float32, device="cuda")
+    st.rg.render_bwd(surf, ws, st.out, Gd, grads, 0)
+    got = grads.cpu().numpy()
+    r = oracle.split_grads(ref, sc.n, sc.n_sem)
+    for nm, sl in ROWS.items():
+        a = got[sl].reshape(r[nm].shape) if r[nm].ndim > 1 else got[sl].reshape(-1)
+        mx = np.abs(r[nm]).max()
+        assert mx > 0.0, nm
+        d = np.abs(a - r[nm])
+        assert d.max() <= 1e-4 * mx, (nm, d.max() / mx)
+        big = np.abs(r[nm]) >= 1e-2 * mx
+        assert (d[big] / np.abs(r[nm][big])).max() <= 1e-4, nm
+
+
+def test_full_size_fused_step_equals_batched_step():
+    sc, _ = scene("C3")
+    opts = B.make_opts(tile_w=TILE[0], tile_h=TILE[1])
+    a = TrainState(sc, opts=opts, pair_capacity=1 << 24)
+    a.step_batched(total_steps=3)
+    b = TrainState(sc, opts=opts, pair_capacity=1 << 24)
+    b.step_fused(total_steps=3)
+    torch.cuda.synchronize()
+    for k in ("params", "m", "v", "s_act", "alpha_act"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    stf = b.fused_status()
+    assert stf["step"] == 1 and stf["overflow"] == 0
+    assert abs(stf["loss"] - a.loss.item()) <= 1e-5 * abs(a.loss.item())
+
+
+# ------------------------------------------------ 3M-surfel patch checks
+
+def _patch(sc):
+    """32 x 32 grid vertices centred on the ground point of the front
+    camera's principal ray, and the pixel window they project into."""
+    cam = sc.cams[0]
+    R = np.asarray(cam.R_cw, np.float64).reshape(3, 3)
+    c = -R.T @ np.asarray(cam.t_cw, np.float64)
+    f = R[2]
+    t = (c[2] - 0.0) / -f[2]
+    for _ in range(20):                       # ray / height-field intersection
+        p = c + t * f
+        t = (c[2] - synth.surface_height(p[0], p[1])) / -f[2]
+    p = c + t * f
+    n_across = 300
+    d2 = (sc.x.astype(np.float64) - p[0]) ** 2 + (sc.y.astype(np.float64) - p[1]) ** 2
+    k0 = int(np.argmin(d2))
+    i0, j0 = divmod(k0, n_across)
+    ii, jj = np.meshgrid(np.arange(i0 - 16, i0 + 16), np.arange(j0 - 16, j0 + 16), indexing="ij")
+    return (ii * n_across + jj).reshape(-1), cam
+
+
+def _window(prm, cam, ids, pad=8):
+    """Pixels around the patch's projection, and the surfels whose tile
+    rectangles reach the window's tiles (every surfel that can touch a window
+    pixel), in ascending id order."""
+    vis, rec, rect = oracle.contract(prm, cam, oopts())
+    pv = ids[vis[ids]]
+    u, v = rec[pv, 0], rec[pv, 1]
+    x0, x1 = max(0, int(u.min()) - pad), min(cam.w, int(u.max()) + pad)
+    y0, y1 = max(0, int(v.min()) - pad), min(cam.h, int(v.max()) + pad)
+    xs, ys = np.meshgrid(np.arange(x0, x1), np.arange(y0, y1))
+    pix = (ys * cam.w + xs).reshape(-1).astype(np.int32)
+    tx0, tx1 = x0 // TILE[0], (x1 - 1) // TILE[0] + 1
+    ty0, ty1 = y0 // TILE[1], (y1 - 1) // TILE[1] + 1
+    near = vis & (rect[:, 0] < tx1) & (rect[:, 1] > tx0) & (rect[:, 2] < ty1) & (rect[:, 3] > ty0)
+    return pix, np.nonzero(near)[0]
+
+
+def _subset(prm, sel):
+    c = lambda a: np.ascontiguousarray(a[..., sel])
+    return oracle.Params(len(sel), prm.C, c(prm.x), c(prm.y), c(prm.z), c(prm.q), c(prm.s),
+                         c(prm.alpha), c(prm.rgb), c(prm.sem))
+
+
+def test_c4_patch_finite_differences_and_autograd():
+    sc, prm = scene("C4")
+    ids, cam = _patch(sc)
+    pix, near = _window(prm, cam, ids)
+    assert 1000 < len(pix) < 400000 and np.isin(ids, near).sum() > 900
+    # the window's pixels see only the surfels in `near`: the oracle runs on
+    # that subset (same relative order, so the same lists)
+    sub = _subset(prm, near)
+    loc = np.searchsorted(near, ids)
+    in_sub = (loc < len(near)) & (near[np.minimum(loc, len(near) - 1)] == ids)
+    NO = n_out(sc.n_sem)
+    rng = np.random.default_rng(21)
+    G = rng.normal(0.0, 1.0, (NO, len(pix)))
+    # oracle adjoint on the window, then central differences of the oracle's
+    # forward for a sample of the patch's parameters (FP64, decisions frozen;
+    # a sample whose +-h runs change any pixel's stop index is skipped)
+    o, tf, nl = oracle.render_fwd(sub, cam, oopts(), pix=pix)
+    full = oracle.render_fwd(prm, cam, oopts(), pix=pix[::97])[0]
+    np.testing.assert_array_equal(o[:, ::97], full)
+    ref = oracle.render_bwd(sub, cam, o, G, tf, nl, oopts(), pix=pix)
+    r = oracle.split_grads(ref, sub.n, sc.n_sem)
+    fields = [("z", None), ("q", 1), ("s", 0), ("alpha", None), ("rgb", 2), ("sem", 5)]
+    checked = 0
+    for field, row in fields:
+        for i in rng.choice(loc[in_sub], 4, replace=False):
+            vals = []
+            for sgn in (1.0, -1.0):
+                q = sub.copy()
+                arr = getattr(q, field)
+                h = 1e-6 * max(1.0, abs(float(arr[i] if row is None else arr[row, i])))
+                if row is None:
+                    arr[i] += sgn * h
+                else:
+                    arr[row, i] += sgn * h
+                oo, _, nn = oracle.render_fwd(q, cam, oopts(), pix=pix)
+                vals.append((float((G * oo).sum()), nn))
+            if not np.array_equal(vals[0][1], nl) or not np.array_equal(vals[1][1], nl):
+                continue
+            fd = (vals[0][0] - vals[1][0]) / (2 * h)
+            an = r[field][i] if row is None else r[field][row, i]
+            scale = max(abs(fd), abs(an), 1e-3 * np.abs(r[field]).max())
+            assert abs(fd - an) <= 1e-4 * scale, (field, row, i, fd, an)
+            checked += 1
+    assert checked >= 16
+    # the autograd wrapper on the 3M-surfel map, dL/d(image) on the window
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device="cuda")
+    t = dict(z=f(sc.z), q=f(sc.q), s=f(sc.s), alpha=f(sc.alpha), rgb=f(sc.rgb), sem=f(sc.sem))
+    for k in t:
+        t[k].requires_grad_(True)
+    out = render(t["z"], t["q"], t["s"], t["alpha"], t["rgb"], t["sem"], f(sc.x), f(sc.y), [cam],
+                 B.make_opts(tile_w=TILE[0], tile_h=TILE[1]))
+    W = torch.zeros(NO, cam.w * cam.h, device="cuda")
+    W[:, torch.as_tensor(pix, device="cuda", dtype=torch.long)] = torch.as_tensor(
+        G, dtype=torch.float32, device="cuda")
+    (out * W.reshape(-1)).sum().backward()
+    got = {"z": t["z"].grad, "q": t["q"].grad, "s": t["s"].grad, "alpha": t["alpha"].grad,
+           "rgb": t["rgb"].grad, "sem": t["sem"].grad}
+    for nm, g in got.items():
+        a = g.cpu().numpy()
+        a = a[..., ids[in_sub]]
+        rr = r[nm][..., loc[in_sub]]
+        mx = np.abs(rr).max()
+        assert mx > 0.0, nm
+        assert np.abs(a - rr).max() <= 1e-4 * mx, (nm, np.abs(a - rr).max() / mx)

@@ -363,3 +363,37 @@ def test_fused_overflow_skips_update_and_recovers(gpu):
     s2 = st.fused_status()
     assert s2["step"] == 1 and s2["overflow"] == 0
     assert not torch.equal(st.params, before)
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny2"])
+def test_work_counts_match_oracle_lists(gpu, name):
+    """rogs_debug_work against a count over the oracle's tile lists: per pixel,
+    the entries up to its termination (n_last of the oracle's forward) and
+    those passing the binary32 3-sigma test."""
+    sc = make_scene(name)
+    st = TrainState(sc)
+    ws, _ = st.project_and_sort(st.cams, "cap_batch", "_ws_batch")
+    st.rg.render_fwd(st.surfels(), ws, st.out)
+    ev, co = st.rg.debug_work(ws)
+    prm = oracle.Params.from_scene(sc)
+    o = oopts(st.opts)
+    e_ref = k_ref = 0
+    for cam in sc.cams:
+        _, rec, _ = oracle.contract(prm, cam, o)
+        keys, ids, ranges = oracle.tile_lists(prm, cam, o)
+        _, _, nl = oracle.render_fwd(prm, cam, o)
+        tx = (cam.w + o.tile_w - 1) // o.tile_w
+        for py in range(cam.h):
+            for px in range(cam.w):
+                t = (py // o.tile_h) * tx + px // o.tile_w
+                a, b = ranges[t]
+                n = int(nl[py * cam.w + px])
+                lst = ids[a:a + n]
+                e_ref += len(lst)
+                r = rec[lst]
+                f = np.float32
+                dx = (f(px + 0.5) - r[:, 0]) - r[:, 2]
+                dy = (f(py + 0.5) - r[:, 1]) - r[:, 3]
+                q = (r[:, 4] * (dx * dx) + r[:, 6] * (dy * dy)) + f(2.0) * (r[:, 5] * (dx * dy))
+                k_ref += int((q <= f(o.q_cut)).sum())
+    assert (ev, co) == (e_ref, k_ref)
