@@ -30,16 +30,22 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rogs_oracle.cpp")
+_SRC_GRID = os.path.join(_HERE, "rogs_oracle_grid.cpp")
 _LIB = os.path.join(_HERE, "_rogs_oracle.so")
 _lib = None
 
 CMD = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-       "-fPIC", "-shared", _SRC, "-o", _LIB]
+       "-fPIC", "-shared", _SRC, _SRC_GRID, "-o", _LIB]
+
+
+def _stale() -> bool:
+    return not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
+                                           for f in (_SRC, _SRC_GRID))
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle shared library with g++ (always, when force)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or _stale():
         tmp = _LIB + ".tmp"
         cmd = CMD[:-1] + [tmp]
         subprocess.run(cmd, check=True)
@@ -50,7 +56,7 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         _lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
@@ -67,6 +73,16 @@ def _load():
         _lib.orc_loss.restype = D
         _lib.orc_adam.argtypes = [I64, P, P, P, P, D, D, D, D, I64]
         _lib.orc_num_threads.restype = I
+        _lib.orc_smooth.argtypes = [I64, P, P, D, P]
+        _lib.orc_smooth.restype = D
+        _lib.orc_lidar_loss.argtypes = [I64, P, P, D, P]
+        _lib.orc_lidar_loss.restype = D
+        _lib.orc_lidar_nn.argtypes = [I64, P, P, I64, P, P, P]
+        _lib.orc_pose_pixels.argtypes = [I, P, D, D, ctypes.c_float, P]
+        _lib.orc_layout_mask.argtypes = [I, I, I, P, I, P]
+        _lib.orc_layout_mask.restype = I64
+        _lib.orc_layout_build.argtypes = [I, I, P, D, D, ctypes.c_float, I, P, I64, P, P, P, P,
+                                          P, P]
     return _lib
 
 
@@ -284,3 +300,55 @@ def loss_and_grads(prm: Params, cams: Sequence, targets: Sequence, exposure=None
         dexp[v] = de
         render_bwd(prm, c, out, G, tf, nl, opts, grads=grads)
     return total, grads, dexp, fwd
+
+
+# ------------------------------------------------------ grid-side terms
+
+def smooth_loss(z, nbr, lam: float = 1.0):
+    """Eq. 10 (K = 4 neighbours from the table nbr[4][n]): (lambda * L, dL/dz)."""
+    z = np.ascontiguousarray(z, np.float64)
+    nbr = np.ascontiguousarray(nbr, np.int32)
+    dz = np.zeros_like(z)
+    val = _load().orc_smooth(z.size, _p(z), _p(nbr), float(lam), _p(dz))
+    return float(val), dz
+
+
+def lidar_loss(z, zbar, lam: float = 1.0):
+    """Eq. 11: (lambda * L_z, dL/dz)."""
+    z = np.ascontiguousarray(z, np.float64)
+    zbar = np.ascontiguousarray(zbar, np.float64)
+    dz = np.zeros_like(z)
+    val = _load().orc_lidar_loss(z.size, _p(z), _p(zbar), float(lam), _p(dz))
+    return float(val), dz
+
+
+def lidar_nn(x, y, px, py) -> np.ndarray:
+    """Index of the nearest point in the xy-plane (brute force, ties to the lower index)."""
+    c = lambda a: np.ascontiguousarray(a, np.float32)
+    x, y, px, py = c(x), c(y), c(px), c(py)
+    idx = np.zeros(x.size, np.int32)
+    _load().orc_lidar_nn(x.size, _p(x), _p(y), px.size, _p(px), _p(py), _p(idx))
+    return idx
+
+
+def meshgrid_layout(poses, x0: float, y0: float, h: float, W: int, H: int, radius_px: int):
+    """Road mask, surfel grid, neighbour table and pose-based initialisation.
+
+    poses: float32 [P, 12] = x, y, z, R row-major.  Returns a dict with mask
+    [H, W], idx [H, W], x, y, z (float32), q [4, n] (float64), nbr [4, n]."""
+    L = _load()
+    poses = np.ascontiguousarray(poses, np.float32)
+    P = poses.shape[0]
+    pix = np.zeros((P, 2), np.int32)
+    L.orc_pose_pixels(P, _p(poses), float(x0), float(y0), float(h), _p(pix))
+    mask = np.zeros((H, W), np.uint8)
+    n = L.orc_layout_mask(W, H, P, _p(pix), int(radius_px), _p(mask))
+    idx = np.zeros((H, W), np.int32)
+    x = np.zeros(n, np.float32)
+    y = np.zeros(n, np.float32)
+    z = np.zeros(n, np.float32)
+    q = np.zeros((4, n), np.float64)
+    nbr = np.zeros((4, n), np.int32)
+    L.orc_layout_build(W, H, _p(mask), float(x0), float(y0), float(h), P, _p(poses), n, _p(idx),
+                       _p(x), _p(y), _p(z), _p(q), _p(nbr))
+    return dict(mask=mask, idx=idx, x=x, y=y, z=z, q=q, nbr=nbr, pose_pixels=pix)

@@ -267,6 +267,60 @@ def surround_rig(traj: Trajectory, s: float, sizes: Sequence[tuple]) -> List[Cam
     return cams
 
 
+def vehicle_poses(traj: Trajectory, step_m: float = 0.5, s0: float = 0.0,
+                  s1: Optional[float] = None) -> np.ndarray:
+    """Vehicle poses along the trajectory every ``step_m`` metres: the rear
+    axle's ground point on the road surface, rotation with columns forward,
+    left, up, where up is the surface normal and forward the heading projected
+    onto the surface.  float32 [P, 12] = x, y, z, R (row-major)."""
+    s1 = traj.s[-1] if s1 is None else s1
+    out = []
+    for s in np.arange(s0, s1 + 1e-9, step_m):
+        p, th = traj.at(float(s))
+        z = float(surface_height(p[0], p[1]))
+        zx, zy = surface_slope(p[0], p[1])
+        up = np.array([-zx, -zy, 1.0])
+        up /= np.linalg.norm(up)
+        f = np.array([math.cos(th), math.sin(th), 0.0])
+        f = f - (f @ up) * up
+        f /= np.linalg.norm(f)
+        left = np.cross(up, f)
+        R = np.stack([f, left, up], axis=-1)
+        out.append(np.concatenate([[p[0], p[1], z], R.reshape(-1)]))
+    return np.ascontiguousarray(np.array(out), np.float32)
+
+
+def lidar_points(traj: Trajectory, n: int, seed: int, half_width: float = 8.0,
+                 noise_std: float = 0.02, s0: float = 0.0, s1: Optional[float] = None) -> np.ndarray:
+    """Synthetic LiDAR returns on the road surface near the trajectory (the
+    paper's nuScenes sweeps are not available): xy uniform in a band of
+    +-half_width metres around the path, z = surface height + N(0, noise_std).
+    float32 [3, n]."""
+    rng = np.random.default_rng(seed)
+    s1 = traj.s[-1] if s1 is None else s1
+    s = rng.uniform(s0, s1, n)
+    lat = rng.uniform(-half_width, half_width, n)
+    k = np.clip(np.round(s / SPACING).astype(np.int64), 0, len(traj.s) - 1)
+    th = traj.heading(traj.s[k])
+    x = traj.p[k, 0] - lat * np.sin(th)
+    y = traj.p[k, 1] + lat * np.cos(th)
+    z = surface_height(x, y) + rng.normal(0.0, noise_std, n)
+    return np.ascontiguousarray(np.stack([x, y, z]), np.float32)
+
+
+def grid_neighbours(n_along: int, n_across: int) -> np.ndarray:
+    """Four-neighbour table [4, n] (up, down, left, right; own index at the
+    border) of the curvilinear lattice, whose vertex (k, j) has index
+    k * n_across + j: up/down step along the path, left/right across."""
+    k, j = np.meshgrid(np.arange(n_along), np.arange(n_across), indexing="ij")
+    idx = k * n_across + j
+    up = np.where(k > 0, idx - n_across, idx)
+    down = np.where(k < n_along - 1, idx + n_across, idx)
+    left = np.where(j > 0, idx - 1, idx)
+    right = np.where(j < n_across - 1, idx + 1, idx)
+    return np.ascontiguousarray(np.stack([up, down, left, right]).reshape(4, -1), np.int32)
+
+
 # ---------------------------------------------------------------- configs
 
 def _assemble(x, y, n_sem, cams, seed0, name, mask_keep=1.0, with_targets=True):
