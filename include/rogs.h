@@ -167,6 +167,13 @@ typedef struct {
   float lambda_c;          /* Eq. 12 weight of L_c (paper: 1) */
   float lambda_s;          /* Eq. 12 weight of L_s (paper: 0.06) */
   float view_scale;        /* multiplies every view's loss (1 / total views) */
+  /* Grid-side terms of Eq. 12, applied by rogs_step_fused (the plain path
+   * calls rogs_elev_loss); rogs_loss ignores them. */
+  const int32_t* nbr;      /* [4][N] neighbour table of Eq. 10 (up, down, left, right;
+                              own index where there is none; symmetric), or NULL */
+  const float* zbar;       /* [N] LiDAR elevation targets of Eq. 11, or NULL */
+  float lambda_smooth;     /* Eq. 12 weight of L_smooth (paper: 0.003; 1 with LiDAR) */
+  float lambda_z;          /* Eq. 12 weight of L_z (paper: 0.02) */
 } rogs_targets;
 
 /* Per-group Adam learning rates (Sec. 4.2). */
@@ -309,6 +316,58 @@ ROGS_API int rogs_step_fused(rogs_ctx* ctx, const rogs_train_state* t, const rog
  * [2] visible slots, [3] steps applied, [4] steps skipped, [5] pixels,
  * [6] tiles, [7] slots; *loss = loss of the last applied step (nullable). */
 ROGS_API int rogs_fused_status(rogs_ctx* ctx, int64_t* stats, float* loss);
+
+/* ------------------------------------------------------ grid-side terms
+ * Elevation smoothness (Eq. 10) over the four grid neighbours and the LiDAR
+ * elevation loss (Eq. 11), per surfel:
+ *   L = lambda_smooth / 4 * sum_i sum_{j in N(i)} (z_i - z_j)^2
+ *     + lambda_z * sum_i (z_i - zbar_i)^2
+ * nbr[4][n] must be symmetric (j = up(i) implies i = down(j), likewise
+ * left/right; a surfel is its own neighbour where it has none), which makes
+ * dL/dz_i = lambda_smooth * sum_d (z_i - z_{nbr[d][i]}) + 2 lambda_z (z_i - zbar_i).
+ * Adds the gradient into dz[n] and the loss into loss_out[0] (device).  Either
+ * term may be off (nbr or zbar NULL).  scratch: device memory of
+ * rogs_elev_scratch_bytes(n) bytes (block partial sums, summed in a fixed
+ * order). */
+ROGS_API size_t rogs_elev_scratch_bytes(int32_t n);
+ROGS_API int rogs_elev_loss(rogs_ctx* ctx, int32_t n, const float* z, const int32_t* nbr,
+                            float lambda_smooth, const float* zbar, float lambda_z, float* dz,
+                            float* loss_out, void* scratch, size_t scratch_bytes, void* stream);
+
+/* LiDAR targets of Eq. 11: zbar[i] = pz of the point nearest to (x_i, y_i) in
+ * the xy-plane (squared distance in binary64 of the binary32 inputs, ties to
+ * the lower point index; brute force over the points), idx[i] its index
+ * (nullable).  Device arrays; m >= 1. */
+ROGS_API int rogs_lidar_targets(rogs_ctx* ctx, int32_t n, const float* x, const float* y,
+                                int32_t m, const float* px, const float* py, const float* pz,
+                                float* zbar, int32_t* idx, void* stream);
+
+/* Meshgrid layout and pose-based initialisation (Sec. 3.1, Eq. 4; supp.
+ * Sec. 1 and 3.3).  A raster of W x H cells of `spacing` metres with cell
+ * (col, row) centred at (x0 + col * spacing, y0 + row * spacing); each pose's
+ * position falls in cell (floor((x - x0)/spacing + 1/2), likewise for y);
+ * the road mask is the disk dilation of those cells by radius_px cells
+ * (dx^2 + dy^2 <= r^2).  Surfels sit at the road cells, indexed by a running
+ * count in row-major order (idx[H][W], -1 off the road); per surfel: x, y
+ * (binary32 of the binary64 cell position), neighbours nbr[4][cap] (cells
+ * above, below, left, right; own index off the road), and from the pose
+ * nearest in the xy-plane (binary64 squared distance, ties to the lower
+ * index): z = z_v - (n31 (x - x_v) + n32 (y - y_v)) / n33 with n3 the third
+ * column of R_v (Eq. 4, binary64), and q = R_v as a unit quaternion (w >= 0).
+ * Writes the count to *n_out (host sync).  If it exceeds capacity the
+ * per-surfel arrays are not written and the call returns ROGS_ECAPACITY
+ * (capacity 0 with NULL arrays is a size query and returns ROGS_OK).
+ * poses: device array; scratch: rogs_meshgrid_scratch_bytes(W, H, n_poses). */
+typedef struct {
+  float x, y, z;           /* rear-axle ground point (m) */
+  float R[9];              /* row-major world-from-vehicle rotation: columns forward, left, up */
+} rogs_pose;
+ROGS_API size_t rogs_meshgrid_scratch_bytes(int32_t W, int32_t H, int32_t n_poses);
+ROGS_API int rogs_meshgrid_layout(rogs_ctx* ctx, const rogs_pose* poses, int32_t n_poses,
+                                  double x0, double y0, float spacing, int32_t W, int32_t H,
+                                  int32_t radius_px, int32_t* idx, int64_t capacity, float* x,
+                                  float* y, float* z, float* q, int32_t* nbr, int64_t* n_out,
+                                  void* scratch, size_t scratch_bytes, void* stream);
 
 /* ------------------------------------------------------ autotuner
  * Chooses the tile shape for a workload.  Every supported shape (tile_w in

@@ -30,7 +30,9 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_debug_pairs", "rogs_debug_records", "rogs_batch_stats", "rogs_prof_enable",
             "rogs_prof_read", "rogs_prof_name", "rogs_fused_workspace_size", "rogs_step_fused",
             "rogs_fused_status", "rogs_autotune", "rogs_server_create", "rogs_serve_submit",
-            "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy", "rogs_debug_work")
+            "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy", "rogs_debug_work",
+            "rogs_elev_scratch_bytes", "rogs_elev_loss", "rogs_lidar_targets",
+            "rogs_meshgrid_scratch_bytes", "rogs_meshgrid_layout")
 PROF_GROUPS = 11
 FUSED_EAGER = 4
 
@@ -86,7 +88,13 @@ class RenderOpts(ctypes.Structure):
 class Targets(ctypes.Structure):
     _fields_ = [("rgb", _vp), ("label", _vp), ("mask", _vp), ("exposure", _vp),
                 ("lambda_c", ctypes.c_float), ("lambda_s", ctypes.c_float),
-                ("view_scale", ctypes.c_float)]
+                ("view_scale", ctypes.c_float), ("nbr", _vp), ("zbar", _vp),
+                ("lambda_smooth", ctypes.c_float), ("lambda_z", ctypes.c_float)]
+
+
+class Pose(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_float), ("y", ctypes.c_float), ("z", ctypes.c_float),
+                ("R", ctypes.c_float * 9)]
 
 
 class LR(ctypes.Structure):
@@ -157,6 +165,13 @@ def load_library(path: str = LIB_PATH):
             "rogs_serve_poll": ([P, ctypes.c_uint64, ctypes.POINTER(Result)], I32),
             "rogs_server_stats": ([P, P], I32),
             "rogs_debug_work": ([P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], I32),
+            "rogs_elev_scratch_bytes": ([I32], ctypes.c_size_t),
+            "rogs_elev_loss": ([P, I32, P, P, F, P, F, P, P, P, ctypes.c_size_t, P], I32),
+            "rogs_lidar_targets": ([P, I32, P, P, I32, P, P, P, P, P, P], I32),
+            "rogs_meshgrid_scratch_bytes": ([I32, I32, I32], ctypes.c_size_t),
+            "rogs_meshgrid_layout": ([P, P, I32, ctypes.c_double, ctypes.c_double, F, I32, I32, I32,
+                                      P, I64, P, P, P, P, P, ctypes.POINTER(I64), P,
+                                      ctypes.c_size_t, P], I32),
             "rogs_server_destroy": ([P], None),
             "rogs_autotune": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
                                ctypes.POINTER(RenderOpts), ctypes.c_char_p, I32,
@@ -227,6 +242,10 @@ def fused_workspace_size(ts: TrainStateC, cams, opts: RenderOpts, pair_capacity:
     if r != OK:
         raise RogsError(r, "rogs_fused_workspace_size rejected its arguments")
     return int(out.value)
+
+
+def elev_scratch_bytes(n: int) -> int:
+    return int(load_library().rogs_elev_scratch_bytes(int(n)))
 
 
 def workspace_size(surf: Surfels, cams, opts: RenderOpts, pair_capacity: int,
@@ -366,6 +385,48 @@ class Rogs:
                                          path, int(reps), ctypes.byref(ms), _stream(stream)),
                     "rogs_autotune")
         return o, float(ms.value)
+
+    def elev_loss(self, n, z, nbr, lambda_smooth, zbar, lambda_z, dz, loss_out, scratch,
+                  stream=None):
+        """rogs_elev_loss: adds Eq. 10 / 11 terms into dz and loss_out."""
+        self._check(self.L.rogs_elev_loss(self.h, int(n), ptr(z), ptr(nbr), float(lambda_smooth),
+                                          ptr(zbar), float(lambda_z), ptr(dz), ptr(loss_out),
+                                          ptr(scratch), scratch.numel() * scratch.element_size(),
+                                          _stream(stream)), "rogs_elev_loss")
+
+    def lidar_targets(self, x, y, px, py, pz, zbar, idx=None, stream=None):
+        """rogs_lidar_targets: zbar (and idx) of the nearest point in xy."""
+        self._check(self.L.rogs_lidar_targets(self.h, x.numel(), ptr(x), ptr(y), px.numel(), ptr(px),
+                                              ptr(py), ptr(pz), ptr(zbar), ptr(idx),
+                                              _stream(stream)), "rogs_lidar_targets")
+
+    def meshgrid_layout(self, poses, x0, y0, spacing, W, H, radius_px, stream=None):
+        """rogs_meshgrid_layout on device poses (uint8 view of rogs_pose
+        records or a float32 [P, 12] tensor): returns a dict of device
+        tensors idx [H, W], x, y, z, q [4, n], nbr [4, n]."""
+        import torch
+        n_poses = poses.numel() * poses.element_size() // ctypes.sizeof(Pose)
+        dev = poses.device
+        scratch = torch.empty(self.L.rogs_meshgrid_scratch_bytes(W, H, n_poses), dtype=torch.uint8,
+                              device=dev)
+        n = ctypes.c_int64(0)
+        args = (float(x0), float(y0), float(spacing), int(W), int(H), int(radius_px))
+        self._check(self.L.rogs_meshgrid_layout(self.h, ptr(poses), n_poses, *args, None, 0, None, None,
+                                                None, None, None, ctypes.byref(n), ptr(scratch),
+                                                scratch.numel(), _stream(stream)),
+                    "rogs_meshgrid_layout")
+        N = int(n.value)
+        idx = torch.empty((H, W), dtype=torch.int32, device=dev)
+        x = torch.empty(N, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        z = torch.empty_like(x)
+        q = torch.empty((4, N), dtype=torch.float32, device=dev)
+        nbr = torch.empty((4, N), dtype=torch.int32, device=dev)
+        self._check(self.L.rogs_meshgrid_layout(self.h, ptr(poses), n_poses, *args, ptr(idx), N,
+                                                ptr(x), ptr(y), ptr(z), ptr(q), ptr(nbr),
+                                                ctypes.byref(n), ptr(scratch), scratch.numel(),
+                                                _stream(stream)), "rogs_meshgrid_layout")
+        return dict(idx=idx, x=x, y=y, z=z, q=q, nbr=nbr, n=N)
 
     def debug_work(self, ws, stream=None):
         """(evaluated, contributing) list entries over all pixels of the batch."""

@@ -196,6 +196,9 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
     const size_t nch = (size_t)(6 + l.C), tp = (size_t)tw * th;
     l.o_tm = take(4 * (size_t)l.total_tiles * nch * tp);
     l.o_tpart = take(4 * 3 * (size_t)l.total_tiles);
+    l.o_dzr = take(4 * (size_t)l.N);                          // grid-side dL/dz
+    l.o_regpart = take(4 * (size_t)rogs::elev_reg_blocks(l.N));
+    l.o_regtot = take(4);
   }
   l.total = o;
   *L = l;
@@ -718,6 +721,8 @@ int check_fused_args(rogs_ctx* c, const rogs_train_state* t, const rogs_targets*
     return fail(c, ROGS_EINVAL, "step_state must be 16-byte aligned");
   if (!tg->rgb || !tg->label || !tg->mask || tg->exposure != t->exposure)
     return fail(c, ROGS_EINVAL, "targets incomplete, or targets.exposure differs from the state's");
+  if ((tg->nbr && !is_fin(tg->lambda_smooth)) || (tg->zbar && !is_fin(tg->lambda_z)))
+    return fail(c, ROGS_EINVAL, "grid-side loss weights must be finite");
   if (!(o->beta1 >= 0.0f && o->beta1 < 1.0f) || !(o->beta2 >= 0.0f && o->beta2 < 1.0f) ||
       !(o->eps > 0.0f) || o->total_steps < 0 || !is_fin(o->z_start) || !is_fin(o->z_end) ||
       (o->total_steps > 1 && !(o->z_start > 0.0f && o->z_end > 0.0f)))
@@ -792,11 +797,19 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
   prof_end(c, st);
   rogs::AdamArgs aa = fused_adam_args(o, L, ws, t->step_state);
   prof_begin(c, 8, st);
+  // grid-side terms (Eq. 10, 11) from the heights before the update
+  const bool reg = tg->nbr || tg->zbar;
+  if (reg)
+    rogs::launch_elev_reg(L.N, t->params, tg->nbr, tg->lambda_smooth, tg->zbar, tg->lambda_z,
+                          rogs::at<float>(ws, L.o_dzr), nullptr, rogs::at<float>(ws, L.o_regpart),
+                          rogs::at<float>(ws, L.o_regtot), false, st);
   rogs::launch_slot_sums(L, ws, st);
   rogs::launch_proj_bwd_adam(L, ws, t->x, t->y, t->params, t->m, t->v, t->s_act, t->alpha_act,
-                             t->grads, aa, t->exposure, t->d_exposure, t->m_exp, t->v_exp, st);
+                             t->grads, aa, t->exposure, t->d_exposure, t->m_exp, t->v_exp,
+                             reg ? rogs::at<const float>(ws, L.o_dzr) : nullptr, st);
   prof_end(c, st);
-  rogs::launch_step_end(L, ws, static_cast<rogs::StepState*>(t->step_state), aa, st);
+  rogs::launch_step_end(L, ws, static_cast<rogs::StepState*>(t->step_state), aa,
+                        reg ? rogs::at<const float>(ws, L.o_regtot) : nullptr, st);
   (void)hipMemcpyAsync(F.status, rogs::at<void>(ws, L.o_misc), 16, hipMemcpyDeviceToHost, st);
   (void)hipMemcpyAsync(reinterpret_cast<char*>(F.status) + 16, t->step_state,
                        sizeof(rogs::StepState), hipMemcpyDeviceToHost, st);

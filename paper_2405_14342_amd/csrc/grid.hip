@@ -1,0 +1,364 @@
+// Grid-side terms of the training loss and the surfel grid itself:
+//   * elevation smoothness over the four grid neighbours (Eq. 10; the
+//     neighbours come from the pixel index of the meshgrid, supp. Sec. 3.3)
+//     and the LiDAR elevation loss (Eq. 11), both per surfel;
+//   * the LiDAR targets: height of the point nearest to each surfel in the
+//     xy-plane (Eq. 11);
+//   * the meshgrid layout (Sec. 3.1): vehicle positions on a raster, a disk
+//     dilation into the road mask, surfels at its pixels indexed by a running
+//     count, neighbour indices from adjacent pixels, and the pose-based
+//     initial height and rotation (Eq. 4; supp. Sec. 1).
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "rogs_internal.h"
+
+namespace rogs {
+
+namespace {
+
+constexpr int kRegBlock = 256;
+
+// Per surfel i, with r_d = z_i - z_{nbr[d][i]} and a symmetric table (a
+// neighbour's opposite neighbour is the surfel itself):
+//   loss_i = lambda_s / 4 * sum_d r_d^2 + lambda_z * (z_i - zbar_i)^2
+//   dL/dz_i = lambda_s * sum_d r_d + 2 lambda_z (z_i - zbar_i)
+// (each edge enters the loss from both ends, hence 2 * 2 / K = 1 for K = 4).
+// The gradient goes to out_dz (overwritten) or is added to acc_dz; block sums
+// of the loss go to part[blockIdx.x] in a fixed order.
+__global__ __launch_bounds__(kRegBlock) void k_elev_reg(int n, const float* __restrict__ z,
+                                                        const int32_t* __restrict__ nbr,
+                                                        float lam_s, const float* __restrict__ zbar,
+                                                        float lam_z, float* __restrict__ out_dz,
+                                                        float* __restrict__ acc_dz,
+                                                        float* __restrict__ part) {
+  __shared__ float s_w[kRegBlock / 64];
+  const int i = blockIdx.x * kRegBlock + threadIdx.x;
+  float l = 0.0f;
+  if (i < n) {
+    const float zi = z[i];
+    float g = 0.0f;
+    if (nbr) {
+      float s = 0.0f, t = 0.0f;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const float r = zi - z[nbr[(size_t)d * n + i]];
+        s += r * r;
+        t += r;
+      }
+      l = (lam_s * 0.25f) * s;
+      g = lam_s * t;
+    }
+    if (zbar) {
+      const float r = zi - zbar[i];
+      l += lam_z * (r * r);
+      g += (2.0f * lam_z) * r;
+    }
+    if (out_dz) out_dz[i] = g;
+    if (acc_dz) acc_dz[i] += g;
+  }
+  for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < kRegBlock / 64; ++w) t += s_w[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+// Sums the block partials in order (one wave, lane-strided then a fixed tree).
+__global__ __launch_bounds__(64) void k_reg_total(const float* __restrict__ part, int nb,
+                                                  float* __restrict__ total, int accumulate) {
+  float t = 0.0f;
+  for (int k = threadIdx.x; k < nb; k += 64) t += part[k];
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (threadIdx.x == 0) *total = accumulate ? (*total + t) : t;
+}
+
+// Nearest point in the xy-plane: squared distance in binary64 of the binary32
+// inputs, ties to the lower point index.  Points are staged in LDS tiles.
+constexpr int kNNBlock = 256;
+constexpr int kNNTile = 1024;
+
+__global__ __launch_bounds__(kNNBlock) void k_lidar_nn(int n, const float* __restrict__ x,
+                                                       const float* __restrict__ y, int m,
+                                                       const float* __restrict__ px,
+                                                       const float* __restrict__ py,
+                                                       const float* __restrict__ pz,
+                                                       float* __restrict__ zbar,
+                                                       int32_t* __restrict__ idx) {
+#pragma clang fp contract(off)
+  __shared__ float s_x[kNNTile], s_y[kNNTile];
+  const int i = blockIdx.x * kNNBlock + threadIdx.x;
+  const double xi = i < n ? (double)x[i] : 0.0, yi = i < n ? (double)y[i] : 0.0;
+  double best = __longlong_as_double(0x7ff0000000000000ll);
+  int bi = -1;
+  for (int k0 = 0; k0 < m; k0 += kNNTile) {
+    const int cnt = min(kNNTile, m - k0);
+    for (int t = threadIdx.x; t < cnt; t += kNNBlock) {
+      s_x[t] = px[k0 + t];
+      s_y[t] = py[k0 + t];
+    }
+    __syncthreads();
+    for (int t = 0; t < cnt; ++t) {
+      const double dx = xi - (double)s_x[t];
+      const double dy = yi - (double)s_y[t];
+      const double d2 = dx * dx + dy * dy;
+      if (d2 < best) {
+        best = d2;
+        bi = k0 + t;
+      }
+    }
+    __syncthreads();
+  }
+  if (i < n) {
+    zbar[i] = bi >= 0 ? pz[bi] : 0.0f;
+    if (idx) idx[i] = bi;
+  }
+}
+
+// ------------------------------------------------------------ meshgrid layout
+
+__global__ void k_pose_pixels(int np, const rogs_pose* __restrict__ poses, double x0, double y0,
+                              float h, int2* __restrict__ pix) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  pix[k] = make_int2((int)floor(((double)poses[k].x - x0) / (double)h + 0.5),
+                     (int)floor(((double)poses[k].y - y0) / (double)h + 0.5));
+}
+
+// Disk dilation by stamping: every pose marks the pixels within radius r of
+// its cell (all writers store the same value 1).
+__global__ void k_stamp(int np, const int2* __restrict__ pix, int r, int W, int H,
+                        uint32_t* __restrict__ mask) {
+  const int k = blockIdx.x;
+  if (k >= np) return;
+  const int2 c = pix[k];
+  const int side = 2 * r + 1;
+  for (int t = threadIdx.x; t < side * side; t += blockDim.x) {
+    const int dy = t / side - r, dx = t % side - r;
+    if ((int64_t)dx * dx + (int64_t)dy * dy > (int64_t)r * r) continue;
+    const int col = c.x + dx, row = c.y + dy;
+    if (col < 0 || col >= W || row < 0 || row >= H) continue;
+    mask[(size_t)row * W + col] = 1u;
+  }
+}
+
+__device__ __forceinline__ void quat_of(const float* R, float q[4]) {
+#pragma clang fp contract(off)
+  const double m00 = R[0], m01 = R[1], m02 = R[2], m10 = R[3], m11 = R[4], m12 = R[5],
+               m20 = R[6], m21 = R[7], m22 = R[8];
+  double w, a, b, d;
+  const double tr = m00 + m11 + m22;
+  if (tr > 0.0) {
+    const double s = sqrt(tr + 1.0) * 2.0;
+    w = 0.25 * s; a = (m21 - m12) / s; b = (m02 - m20) / s; d = (m10 - m01) / s;
+  } else if (m00 > m11 && m00 > m22) {
+    const double s = sqrt(1.0 + m00 - m11 - m22) * 2.0;
+    w = (m21 - m12) / s; a = 0.25 * s; b = (m01 + m10) / s; d = (m02 + m20) / s;
+  } else if (m11 > m22) {
+    const double s = sqrt(1.0 + m11 - m00 - m22) * 2.0;
+    w = (m02 - m20) / s; a = (m01 + m10) / s; b = 0.25 * s; d = (m12 + m21) / s;
+  } else {
+    const double s = sqrt(1.0 + m22 - m00 - m11) * 2.0;
+    w = (m10 - m01) / s; a = (m02 + m20) / s; b = (m12 + m21) / s; d = 0.25 * s;
+  }
+  if (w < 0.0) { w = -w; a = -a; b = -b; d = -d; }
+  q[0] = (float)w; q[1] = (float)a; q[2] = (float)b; q[3] = (float)d;
+}
+
+// One thread per raster pixel: road pixels get their surfel (position,
+// neighbours, Eq. 4 height, rotation of the nearest pose); idx = -1 off the
+// road.  mask holds 0/1, sidx the running count (exclusive scan of mask).
+__global__ void k_layout_fill(int W, int H, const uint32_t* __restrict__ mask,
+                              const uint32_t* __restrict__ sidx, double x0, double y0, float h,
+                              int np, const rogs_pose* __restrict__ poses, int64_t n,
+                              int32_t* __restrict__ idx, float* __restrict__ x,
+                              float* __restrict__ y, float* __restrict__ z, float* __restrict__ q,
+                              int32_t* __restrict__ nbr) {
+#pragma clang fp contract(off)
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)W * H) return;
+  if (!mask[p]) {
+    idx[p] = -1;
+    return;
+  }
+  const int row = (int)(p / W), col = (int)(p - (int64_t)row * W);
+  const int32_t i = (int32_t)sidx[p];
+  idx[p] = i;
+  const float xi = (float)(x0 + (double)col * (double)h);
+  const float yi = (float)(y0 + (double)row * (double)h);
+  x[i] = xi;
+  y[i] = yi;
+  auto at = [&](int rr, int cc) -> int32_t {
+    if (rr < 0 || rr >= H || cc < 0 || cc >= W) return i;
+    const int64_t o = (int64_t)rr * W + cc;
+    return mask[o] ? (int32_t)sidx[o] : i;
+  };
+  nbr[0 * n + i] = at(row - 1, col);
+  nbr[1 * n + i] = at(row + 1, col);
+  nbr[2 * n + i] = at(row, col - 1);
+  nbr[3 * n + i] = at(row, col + 1);
+  double best = __longlong_as_double(0x7ff0000000000000ll);
+  int bk = 0;
+  for (int k = 0; k < np; ++k) {
+    const double dx = (double)xi - (double)poses[k].x;
+    const double dy = (double)yi - (double)poses[k].y;
+    const double d2 = dx * dx + dy * dy;
+    if (d2 < best) {
+      best = d2;
+      bk = k;
+    }
+  }
+  const rogs_pose& P = poses[bk];
+  const double n31 = P.R[2], n32 = P.R[5], n33 = P.R[8];
+  const double t = (n31 * ((double)xi - (double)P.x) + n32 * ((double)yi - (double)P.y)) / n33;
+  z[i] = (float)((double)P.z - t);
+  float qq[4];
+  quat_of(P.R, qq);
+  for (int c = 0; c < 4; ++c) q[(size_t)c * n + i] = qq[c];
+}
+
+}  // namespace
+
+int64_t elev_reg_blocks(int n) { return (n + kRegBlock - 1) / kRegBlock; }
+
+void launch_elev_reg(int n, const float* z, const int32_t* nbr, float lam_s, const float* zbar,
+                     float lam_z, float* out_dz, float* acc_dz, float* part, float* total,
+                     bool accumulate_total, hipStream_t st) {
+  const int nb = (int)elev_reg_blocks(n);
+  hipLaunchKernelGGL(k_elev_reg, dim3((unsigned)nb), dim3(kRegBlock), 0, st, n, z, nbr, lam_s,
+                     zbar, lam_z, out_dz, acc_dz, part);
+  hipLaunchKernelGGL(k_reg_total, dim3(1), dim3(64), 0, st, part, nb, total,
+                     accumulate_total ? 1 : 0);
+}
+
+void launch_lidar_nn(int n, const float* x, const float* y, int m, const float* px,
+                     const float* py, const float* pz, float* zbar, int32_t* idx, hipStream_t st) {
+  hipLaunchKernelGGL(k_lidar_nn, dim3((unsigned)((n + kNNBlock - 1) / kNNBlock)), dim3(kNNBlock),
+                     0, st, n, x, y, m, px, py, pz, zbar, idx);
+}
+
+size_t layout_scratch_bytes(int W, int H, int np) {
+  const int64_t cells = (int64_t)W * H;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  return up(8 * (size_t)np) + 2 * up(4 * (size_t)cells) + up(4 * scan_tmp_words(cells)) + 256;
+}
+
+void launch_layout_mask(const rogs_pose* poses, int np, double x0, double y0, float h, int W,
+                        int H, int r, void* scratch, uint32_t* n_dev, hipStream_t st) {
+  const int64_t cells = (int64_t)W * H;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  uint8_t* s = static_cast<uint8_t*>(scratch);
+  int2* pix = reinterpret_cast<int2*>(s);
+  uint32_t* mask = reinterpret_cast<uint32_t*>(s + up(8 * (size_t)np));
+  uint32_t* sidx = mask + up(4 * (size_t)cells) / 4;
+  uint32_t* tmp = sidx + up(4 * (size_t)cells) / 4;
+  hipLaunchKernelGGL(k_pose_pixels, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np, poses,
+                     x0, y0, h, pix);
+  fill_u32(mask, 0u, cells, st);
+  hipLaunchKernelGGL(k_stamp, dim3((unsigned)np), dim3(256), 0, st, np, pix, r, W, H, mask);
+  scan_u32(mask, sidx, cells, n_dev, tmp, st);
+}
+
+void launch_layout_fill(const rogs_pose* poses, int np, double x0, double y0, float h, int W,
+                        int H, void* scratch, int64_t n, int32_t* idx, float* x, float* y,
+                        float* z, float* q, int32_t* nbr, hipStream_t st) {
+  const int64_t cells = (int64_t)W * H;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  uint8_t* s = static_cast<uint8_t*>(scratch);
+  const uint32_t* mask = reinterpret_cast<const uint32_t*>(s + up(8 * (size_t)np));
+  const uint32_t* sidx = mask + up(4 * (size_t)cells) / 4;
+  hipLaunchKernelGGL(k_layout_fill, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, W, H,
+                     mask, sidx, x0, y0, h, np, poses, n, idx, x, y, z, q, nbr);
+}
+
+}  // namespace rogs
+
+extern "C" {
+
+size_t rogs_elev_scratch_bytes(int32_t n) {
+  return n < 1 ? 0 : (size_t)(rogs::elev_reg_blocks(n) + 1) * 4;
+}
+
+int rogs_elev_loss(rogs_ctx* c, int32_t n, const float* z, const int32_t* nbr, float lambda_smooth,
+                   const float* zbar, float lambda_z, float* dz, float* loss_out, void* scratch,
+                   size_t scratch_bytes, void* stream) {
+  if (!c) return ROGS_EINVAL;
+  if (n < 1 || !z || !dz || !loss_out || !scratch)
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_elev_loss: null argument or n < 1");
+  if (scratch_bytes < rogs_elev_scratch_bytes(n))
+    return rogs::ctx_fail(c, ROGS_ENOMEM, "rogs_elev_loss: scratch too small");
+  if ((nbr && !std::isfinite(lambda_smooth)) || (zbar && !std::isfinite(lambda_z)))
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_elev_loss: weights must be finite");
+  if (!nbr && !zbar) return ROGS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* part = static_cast<float*>(scratch);
+  rogs::launch_elev_reg(n, z, nbr, lambda_smooth, zbar, lambda_z, nullptr, dz, part, loss_out,
+                        true, st);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ROGS_OK
+                         : rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_elev_loss: ") +
+                                                            hipGetErrorString(e));
+}
+
+int rogs_lidar_targets(rogs_ctx* c, int32_t n, const float* x, const float* y, int32_t m,
+                       const float* px, const float* py, const float* pz, float* zbar,
+                       int32_t* idx, void* stream) {
+  if (!c) return ROGS_EINVAL;
+  if (n < 1 || m < 1 || !x || !y || !px || !py || !pz || !zbar)
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_lidar_targets: null argument or empty set");
+  rogs::launch_lidar_nn(n, x, y, m, px, py, pz, zbar, idx, static_cast<hipStream_t>(stream));
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ROGS_OK
+                         : rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_lidar_targets: ") +
+                                                            hipGetErrorString(e));
+}
+
+size_t rogs_meshgrid_scratch_bytes(int32_t W, int32_t H, int32_t n_poses) {
+  if (W < 1 || H < 1 || n_poses < 1) return 0;
+  return rogs::layout_scratch_bytes(W, H, n_poses);
+}
+
+int rogs_meshgrid_layout(rogs_ctx* c, const rogs_pose* poses, int32_t n_poses, double x0,
+                         double y0, float spacing, int32_t W, int32_t H, int32_t radius_px,
+                         int32_t* idx, int64_t capacity, float* x, float* y, float* z, float* q,
+                         int32_t* nbr, int64_t* n_out, void* scratch, size_t scratch_bytes,
+                         void* stream) {
+  if (!c) return ROGS_EINVAL;
+  if (!poses || n_poses < 1 || W < 1 || H < 1 || (int64_t)W * H >= (int64_t(1) << 31) ||
+      radius_px < 0 || radius_px > 4096 || !(spacing > 0.0f) || !std::isfinite(x0) ||
+      !std::isfinite(y0) || !n_out || !scratch || capacity < 0)
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_meshgrid_layout: invalid argument");
+  const size_t need = rogs::layout_scratch_bytes(W, H, n_poses);
+  if (scratch_bytes < need) return rogs::ctx_fail(c, ROGS_ENOMEM, "rogs_meshgrid_layout: scratch too small");
+  const bool query = capacity == 0 && !idx && !x && !y && !z && !q && !nbr;
+  if (!query && (!idx || !x || !y || !z || !q || !nbr))
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_meshgrid_layout: null output array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* n_dev = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(scratch) + need - 256);
+  rogs::launch_layout_mask(poses, n_poses, x0, y0, spacing, W, H, radius_px, scratch, n_dev, st);
+  uint32_t n_host = 0;
+  hipError_t e = hipMemcpyAsync(&n_host, n_dev, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess)
+    return rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_meshgrid_layout: ") + hipGetErrorString(e));
+  *n_out = (int64_t)n_host;
+  if (query) return ROGS_OK;
+  if ((int64_t)n_host > capacity)
+    return rogs::ctx_fail(c, ROGS_ECAPACITY, "rogs_meshgrid_layout: " + std::to_string(n_host) +
+                                                 " road cells exceed the capacity");
+  rogs::launch_layout_fill(poses, n_poses, x0, y0, spacing, W, H, scratch, capacity, idx, x, y, z,
+                           q, nbr, st);
+  e = hipGetLastError();
+  return e == hipSuccess ? ROGS_OK
+                         : rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_meshgrid_layout: ") +
+                                                            hipGetErrorString(e));
+}
+
+}  // extern "C"

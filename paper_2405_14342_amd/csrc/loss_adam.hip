@@ -444,7 +444,8 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
     const float* __restrict__ py, float* __restrict__ P, float* __restrict__ M,
     float* __restrict__ Vv, float* __restrict__ s_act, float* __restrict__ a_act,
     const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ pos, int64_t scap,
-    const float* __restrict__ ssum, float* __restrict__ grads_out, AdamArgs aa) {
+    const float* __restrict__ ssum, const float* __restrict__ dzr, float* __restrict__ grads_out,
+    AdamArgs aa) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   if (aa.misc[kMiscOverflow]) return;
@@ -453,6 +454,7 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
   float vals[11 + C];
   surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], cnt, pos,
                   scap, ssum, vals);
+  if (dzr) vals[0] += dzr[i];
   if (grads_out) {
 #pragma unroll
     for (int r = 0; r < 11 + C; ++r) grads_out[r * Nn + i] = vals[r];
@@ -642,7 +644,8 @@ __global__ __launch_bounds__(64) void k_loss_chunks(const float* __restrict__ cp
 
 // Closes a fused step: counts it (or its skip on overflow) and keeps its loss.
 __global__ void k_step_end(StepState* __restrict__ st, const uint32_t* __restrict__ misc,
-                           const float* __restrict__ per_view, int V, AdamArgs aa) {
+                           const float* __restrict__ per_view, int V,
+                           const float* __restrict__ reg_total, AdamArgs aa) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (misc[kMiscOverflow]) {
     st->skipped += 1;
@@ -650,6 +653,7 @@ __global__ void k_step_end(StepState* __restrict__ st, const uint32_t* __restric
   }
   float t = 0.0f;
   for (int v = 0; v < V; ++v) t += per_view[v];
+  if (reg_total) t += *reg_total;
   const int64_t step = st->step + 1;
   st->lr_z = z_rate(aa, step);
   st->loss = t;
@@ -707,11 +711,11 @@ void adam_launch(int n, float* params, const float* grads, float* m, float* v, f
 template <int C>
 void proj_bwd_adam_launch(const Layout& L, void* ws, const float* x, const float* y,
                           float* params, float* m, float* v, float* s_act, float* a_act,
-                          float* grads_out, const AdamArgs& aa, hipStream_t st) {
+                          float* grads_out, const AdamArgs& aa, const float* dzr, hipStream_t st) {
   hipLaunchKernelGGL((k_proj_bwd_adam<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, x, y, params, m, v,
                      s_act, a_act, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_pos),
-                     L.scap, at<const float>(ws, L.o_ssum), grads_out, aa);
+                     L.scap, at<const float>(ws, L.o_ssum), dzr, grads_out, aa);
 }
 }  // namespace
 
@@ -751,9 +755,9 @@ void launch_adam(int n, int C, float* params, const float* grads, float* m, floa
 void launch_proj_bwd_adam(const Layout& L, void* ws, const float* x, const float* y, float* params,
                           float* m, float* v, float* s_act, float* a_act, float* grads_out,
                           const AdamArgs& aa, float* expo, const float* dexpo, float* me,
-                          float* ve, hipStream_t st) {
+                          float* ve, const float* dzr, hipStream_t st) {
   ROGS_SEM_SWITCH(L.C, (proj_bwd_adam_launch<KC>(L, ws, x, y, params, m, v, s_act, a_act,
-                                                  grads_out, aa, st)));
+                                                  grads_out, aa, dzr, st)));
   if (expo)
     hipLaunchKernelGGL(k_adam_plain, dim3((unsigned)((2 * L.V + 63) / 64)), dim3(64), 0, st,
                        2 * L.V, expo, dexpo, me, ve, aa);
@@ -804,10 +808,10 @@ void launch_mask_count(const Layout& L, void* ws, const uint8_t* mask, hipStream
 }
 
 void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs& aa,
-                     hipStream_t st) {
+                     const float* reg_total, hipStream_t st) {
   const float* per_view = reinterpret_cast<const float*>(at<uint32_t>(ws, L.o_mcount) + L.V);
   hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, state, at<const uint32_t>(ws, L.o_misc),
-                     per_view, L.V, aa);
+                     per_view, L.V, reg_total, aa);
 }
 
 }  // namespace rogs

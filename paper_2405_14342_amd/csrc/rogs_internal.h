@@ -51,7 +51,7 @@ struct Layout {
   int64_t slots = 0;           // V * N
   int64_t sort_blocks = 0;     // ceil(cap / kSortTile)
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
-  size_t o_views, o_order, o_tkey, o_cnt, o_rec, o_rect, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
+  size_t o_views, o_order, o_tkey, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
@@ -404,6 +404,18 @@ void launch_scan_part(const Layout& L, void* ws, hipStream_t st);
 int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st);
 void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st);
 void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st);
+int64_t elev_reg_blocks(int n);
+void launch_elev_reg(int n, const float* z, const int32_t* nbr, float lam_s, const float* zbar,
+                     float lam_z, float* out_dz, float* acc_dz, float* part, float* total,
+                     bool accumulate_total, hipStream_t st);
+void launch_lidar_nn(int n, const float* x, const float* y, int m, const float* px,
+                     const float* py, const float* pz, float* zbar, int32_t* idx, hipStream_t st);
+size_t layout_scratch_bytes(int W, int H, int np);
+void launch_layout_mask(const rogs_pose* poses, int np, double x0, double y0, float h, int W,
+                        int H, int r, void* scratch, uint32_t* n_dev, hipStream_t st);
+void launch_layout_fill(const rogs_pose* poses, int np, double x0, double y0, float h, int W,
+                        int H, void* scratch, int64_t n, int32_t* idx, float* x, float* y,
+                        float* z, float* q, int32_t* nbr, hipStream_t st);
 void launch_tile_order(const Layout& L, void* ws, hipStream_t st);
 int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* out, hipStream_t st);
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,
@@ -422,15 +434,17 @@ void launch_adam(int n, int C, float* params, const float* grads, float* m, floa
                  hipStream_t st);
 // Fused: projection adjoint of every surfel followed by its Adam update (and
 // the exposure update); optional gradient output.  Skipped on overflow.
+// dzr (nullable): per-surfel dL/dz of the grid-side terms, added to the
+// height gradient before the update.
 void launch_proj_bwd_adam(const Layout& L, void* ws, const float* x, const float* y, float* params,
                           float* m, float* v, float* s_act, float* a_act, float* grads_out,
                           const AdamArgs& aa, float* expo, const float* dexpo, float* me,
-                          float* ve, hipStream_t st);
+                          float* ve, const float* dzr, hipStream_t st);
 // Fused: per-view loss and dL/d(a, b) (overwritten) from the per-tile partials.
 void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st);
 void launch_mask_count(const Layout& L, void* ws, const uint8_t* mask, hipStream_t st);
 void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs& aa,
-                     hipStream_t st);
+                     const float* reg_total, hipStream_t st);
 // Exclusive scan of n uint32 values; total written to *total (device) if non-null.
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
               hipStream_t st);

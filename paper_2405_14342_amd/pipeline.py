@@ -25,6 +25,7 @@ from . import binding as B
 
 # Sec. 4.2 hyper-parameters
 LAMBDA_C, LAMBDA_S = 1.0, 0.06
+LAMBDA_SMOOTH, LAMBDA_Z = 0.003, 0.02   # Eq. 12 (lambda_smooth = 1 when LiDAR supervises z)
 LR_ALPHA = LR_SCALE = LR_ROT = 1e-4
 LR_RGB, LR_SEM, LR_EXPOSURE = 0.008, 0.1, 0.001
 LR_Z_START, LR_Z_END = 1.6e-4, 1.6e-6      # times the scene size
@@ -121,6 +122,8 @@ class TrainState:
         self._ws_view = None
         self._ws_batch = None
         self.step_count = 0
+        self.nbr = self.zbar = None
+        self.lambda_smooth = self.lambda_z = 0.0
 
     # -------------------------------------------------------------- views
     def surfels(self) -> B.Surfels:
@@ -143,7 +146,39 @@ class TrainState:
         o = int(self.pix_off[v0])
         return B.Targets(self.tgt_rgb.data_ptr() + 4 * 3 * o, self.tgt_label.data_ptr() + o,
                          self.tgt_mask.data_ptr() + o, self.exposure.data_ptr() + 8 * v0,
-                         LAMBDA_C, LAMBDA_S, 1.0 / self.V)
+                         LAMBDA_C, LAMBDA_S, 1.0 / self.V, B.ptr(self.nbr), B.ptr(self.zbar),
+                         self.lambda_smooth, self.lambda_z)
+
+    # ------------------------------------------------------ grid-side terms
+    def set_grid_terms(self, nbr=None, zbar=None, lambda_smooth: float = LAMBDA_SMOOTH,
+                       lambda_z: float = LAMBDA_Z):
+        """Enables the elevation smoothness (Eq. 10, neighbour table nbr[4][N])
+        and/or the LiDAR elevation loss (Eq. 11, targets zbar[N]) in every
+        training step (plain, batched and fused)."""
+        dev = self.dev
+        self.nbr = None if nbr is None else torch.as_tensor(np.ascontiguousarray(nbr, np.int32),
+                                                            device=dev)
+        self.zbar = None if zbar is None else torch.as_tensor(
+            np.ascontiguousarray(zbar, np.float32), device=dev) if not torch.is_tensor(zbar) \
+            else zbar.to(dev, torch.float32).contiguous()
+        self.lambda_smooth = float(lambda_smooth) if nbr is not None else 0.0
+        self.lambda_z = float(lambda_z) if zbar is not None else 0.0
+        self._reg_scratch = torch.empty(max(4, B.elev_scratch_bytes(self.N)), dtype=torch.uint8,
+                                        device=dev)
+
+    def lidar_targets(self, points) -> torch.Tensor:
+        """zbar[N]: height of the LiDAR point nearest to each surfel in the
+        xy-plane (rogs_lidar_targets); points: float32 [3, M]."""
+        pts = torch.as_tensor(np.ascontiguousarray(points, np.float32), device=self.dev)
+        zbar = torch.empty(self.N, dtype=torch.float32, device=self.dev)
+        self.rg.lidar_targets(self.x, self.y, pts[0], pts[1], pts[2], zbar)
+        return zbar
+
+    def _grid_terms(self):
+        if self.nbr is None and self.zbar is None:
+            return
+        self.rg.elev_loss(self.N, self.params[0], self.nbr, self.lambda_smooth, self.zbar,
+                          self.lambda_z, self.grads[0], self.loss, self._reg_scratch)
 
     # ---------------------------------------------------------- workspace
     def _workspace(self, cams, cap, which, scap=0):
@@ -187,6 +222,7 @@ class TrainState:
             ov, gv = self.out_view(v), self.out_view(v, self.G)
             self.rg.loss(ws, ov, self.targets(v, v + 1), gv, self.loss, self.d_exp[v])
             self.rg.render_bwd(surf, ws, ov, gv, self.grads, B.ACCUMULATE if v else 0)
+        self._grid_terms()
         if adam:
             self.adam(lr)
 
@@ -202,6 +238,7 @@ class TrainState:
         self.rg.render_fwd(surf, ws, self.out)
         self.rg.loss(ws, self.out, self.targets(0, self.V), self.G, self.loss, self.d_exp)
         self.rg.render_bwd(surf, ws, self.out, self.G, self.grads, 0)
+        self._grid_terms()
         if adam:
             self.adam(lr)
 

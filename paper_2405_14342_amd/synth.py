@@ -340,7 +340,9 @@ def config1(n_sem: int = 8, mask_keep: float = 1.0) -> Scene:
     i = np.arange(64)
     gx, gy = np.meshgrid(SPACING * i, SPACING * (i - 31.5), indexing="xy")
     cam = pinhole_camera((-1.0, 0.0, 1.5), 0.0, math.radians(CAM_PITCH_DEG), 160, 90, 120.0)
-    return _assemble(gx.reshape(-1), gy.reshape(-1), n_sem, [cam], seed0, "C1-4096", mask_keep)
+    sc = _assemble(gx.reshape(-1), gy.reshape(-1), n_sem, [cam], seed0, "C1-4096", mask_keep)
+    sc.grid_shape = (64, 64)       # vertex (row j, column i) has index 64 j + i
+    return sc
 
 
 def strip_scene(cfg_index: int, n_along: int, n_across: int, n_sem: int,
@@ -354,6 +356,7 @@ def strip_scene(cfg_index: int, n_along: int, n_across: int, n_sem: int,
         cams += surround_rig(traj, s, sizes)
     sc = _assemble(x, y, n_sem, cams, seed0, name, mask_keep, with_targets)
     sc.trajectory = traj
+    sc.grid_shape = (n_along, n_across)
     return sc
 
 

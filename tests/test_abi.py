@@ -39,7 +39,9 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(B.Camera) == 4 * (4 + 4 + 9 + 3 + 1 + 6 + 2)
     assert ctypes.sizeof(B.RenderOpts) == 24
     assert ctypes.sizeof(B.Surfels) == 8 + 8 * 8
-    assert ctypes.sizeof(B.Targets) == 4 * 8 + 3 * 4 + 4
+    # 4 pointers, 3 floats (+4 padding), 2 pointers, 2 floats
+    assert ctypes.sizeof(B.Targets) == 4 * 8 + 3 * 4 + 4 + 2 * 8 + 2 * 4
+    assert ctypes.sizeof(B.Pose) == 12 * 4
     assert ctypes.sizeof(B.LR) == 7 * 4
     # rogs_request: camera, channels, elev_ref, then the 8-byte-aligned pointer
     assert ctypes.sizeof(B.Request) == 136 and B.Request.out.offset == 128

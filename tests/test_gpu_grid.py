@@ -1,0 +1,161 @@
+"""Grid-side terms on the GPU against the oracle: elevation smoothness and
+LiDAR loss (values and gradients), LiDAR nearest-neighbour targets
+(bit-exact), the meshgrid layout with pose-based initialisation
+(bit-exact), and the training step with these terms (plain = batched,
+fused = batched + Adam bit for bit, loss and gradients against the oracle)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2405_14342_amd import binding as B
+from paper_2405_14342_amd import synth
+from paper_2405_14342_amd.pipeline import TrainState
+
+pytestmark = pytest.mark.gpu
+
+
+def _grads_close(got, ref, tol=1e-4):
+    mx = np.abs(ref).max()
+    assert mx > 0
+    d = np.abs(got - ref)
+    assert d.max() <= tol * mx, d.max() / mx
+    big = np.abs(ref) >= 1e-2 * mx
+    assert (d[big] / np.abs(ref[big])).max() <= tol
+
+
+def test_elev_loss_matches_oracle():
+    sc = synth.mini_strip()
+    nbr = synth.grid_neighbours(*sc.grid_shape)
+    rng = np.random.default_rng(8)
+    z = (sc.z + rng.normal(0, 0.05, sc.n)).astype(np.float32)
+    zbar = (sc.z + rng.normal(0, 0.05, sc.n)).astype(np.float32)
+    rg = B.Rogs()
+    d = lambda a: torch.as_tensor(a, device="cuda")
+    dz = d(np.zeros(sc.n, np.float32))
+    loss = d(np.array([1.5], np.float32))
+    scratch = torch.empty(B.elev_scratch_bytes(sc.n), dtype=torch.uint8, device="cuda")
+    rg.elev_loss(sc.n, d(z), d(nbr), 0.003, d(zbar), 0.02, dz, loss, scratch)
+    torch.cuda.synchronize()
+    ls, gs = oracle.smooth_loss(z, nbr, 0.003)
+    lz, gz = oracle.lidar_loss(z, zbar, 0.02)
+    assert loss.item() == pytest.approx(1.5 + ls + lz, rel=1e-5)
+    _grads_close(dz.cpu().numpy(), gs + gz)
+    # the gradient is added to what dz holds
+    dz_acc = d(np.full(sc.n, 0.25, np.float32))
+    rg.elev_loss(sc.n, d(z), d(nbr), 0.003, d(zbar), 0.02, dz_acc, loss, scratch)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dz_acc.cpu().numpy(), np.float32(0.25) + dz.cpu().numpy())
+    # one term alone
+    dz2 = torch.zeros(sc.n, device="cuda")
+    loss2 = torch.zeros(1, device="cuda")
+    rg.elev_loss(sc.n, d(z), d(nbr), 1.0, None, 0.0, dz2, loss2, scratch)
+    torch.cuda.synchronize()
+    ls1, gs1 = oracle.smooth_loss(z, nbr, 1.0)
+    assert loss2.item() == pytest.approx(ls1, rel=1e-5)
+    _grads_close(dz2.cpu().numpy(), gs1)
+
+
+def test_lidar_targets_bitexact():
+    sc = synth.mini_strip()
+    pts = synth.lidar_points(sc.trajectory, 20000, 77)
+    st = TrainState(sc)
+    zbar = st.lidar_targets(pts)
+    idx = torch.empty(sc.n, dtype=torch.int32, device="cuda")
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    zb2 = torch.empty_like(zbar)
+    st.rg.lidar_targets(st.x, st.y, d(pts[0]), d(pts[1]), d(pts[2]), zb2, idx)
+    torch.cuda.synchronize()
+    ref = oracle.lidar_nn(sc.x, sc.y, pts[0], pts[1])
+    np.testing.assert_array_equal(idx.cpu().numpy(), ref)
+    np.testing.assert_array_equal(zbar.cpu().numpy(), pts[2][ref])
+    np.testing.assert_array_equal(zb2.cpu().numpy(), pts[2][ref])
+
+
+@pytest.mark.parametrize("radius", [0, 7, 25])
+def test_meshgrid_layout_bitexact(radius):
+    traj = synth.Trajectory(40.0, 31)
+    poses = synth.vehicle_poses(traj, 0.5)
+    h = np.float32(0.1)
+    xy = poses[:, :2].astype(np.float64)
+    x0 = float(np.floor(xy[:, 0].min()) - 3.0)
+    y0 = float(np.floor(xy[:, 1].min()) - 3.0)
+    W = int(math.ceil((xy[:, 0].max() + 3.0 - x0) / h)) + 1
+    H = int(math.ceil((xy[:, 1].max() + 3.0 - y0) / h)) + 1
+    ref = oracle.meshgrid_layout(poses, x0, y0, h, W, H, radius)
+    rg = B.Rogs()
+    out = rg.meshgrid_layout(torch.as_tensor(poses, device="cuda"), x0, y0, h, W, H, radius)
+    torch.cuda.synchronize()
+    assert out["n"] == ref["x"].size > 0
+    np.testing.assert_array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    for k in ("x", "y", "z"):
+        np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k], err_msg=k)
+    np.testing.assert_array_equal(out["q"].cpu().numpy(), ref["q"].astype(np.float32))
+    np.testing.assert_array_equal(out["nbr"].cpu().numpy(), ref["nbr"])
+
+
+def test_meshgrid_layout_capacity_and_query():
+    traj = synth.Trajectory(20.0, 32)
+    poses = torch.as_tensor(synth.vehicle_poses(traj, 1.0), device="cuda")
+    rg = B.Rogs()
+    out = rg.meshgrid_layout(poses, -30.0, -30.0, np.float32(0.1), 600, 600, 10)
+    assert out["n"] > 0
+    L = B.load_library()
+    scratch = torch.empty(L.rogs_meshgrid_scratch_bytes(600, 600, poses.shape[0]), dtype=torch.uint8,
+                          device="cuda")
+    import ctypes
+    n = ctypes.c_int64(0)
+    small = torch.empty(16, device="cuda")
+    small_i = torch.empty((600, 600), dtype=torch.int32, device="cuda")
+    nb = torch.empty((4, 4), dtype=torch.int32, device="cuda")
+    r = L.rogs_meshgrid_layout(rg.h, B.ptr(poses), poses.shape[0], -30.0, -30.0, 0.1, 600, 600, 10,
+                               B.ptr(small_i), 4, B.ptr(small), B.ptr(small), B.ptr(small),
+                               B.ptr(small), B.ptr(nb), ctypes.byref(n), B.ptr(scratch),
+                               scratch.numel(), None)
+    assert r == B.ECAPACITY and n.value == out["n"]
+
+
+def _with_terms(sc, lidar=True):
+    st = TrainState(sc)
+    nbr = synth.grid_neighbours(*sc.grid_shape)
+    zbar = st.lidar_targets(synth.lidar_points(sc.trajectory, 20000, 78)) if lidar else None
+    st.set_grid_terms(nbr, zbar, lambda_smooth=1.0 if lidar else 0.003, lambda_z=0.02)
+    return st, nbr, zbar
+
+
+def test_step_with_grid_terms_matches_oracle():
+    sc = synth.mini_strip()
+    st, nbr, zbar = _with_terms(sc)
+    st.step_batched(adam=False)
+    torch.cuda.synchronize()
+    prm = oracle.Params.from_scene(sc)
+    L, g, _, _ = oracle.loss_and_grads(prm, sc.cams, sc.targets,
+                                       opts=oracle.Opts(st.opts.tile_w, st.opts.tile_h))
+    ls, gs = oracle.smooth_loss(sc.z, nbr, 1.0)
+    zb = zbar.cpu().numpy()
+    lz, gz = oracle.lidar_loss(sc.z, zb, 0.02)
+    assert st.loss.item() == pytest.approx(L + ls + lz, rel=1e-5)
+    ref = oracle.split_grads(g, sc.n, sc.n_sem)
+    _grads_close(st.grads[0].cpu().numpy(), ref["z"] + gs + gz)
+
+
+def test_grid_terms_plain_batched_fused_agree():
+    sc = synth.mini_strip()
+    a, _, _ = _with_terms(sc)
+    a.step_plain(adam=False)
+    b, _, _ = _with_terms(sc)
+    b.step_batched(adam=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a.grads, b.grads)
+    c, _, _ = _with_terms(sc)
+    c.step_batched(total_steps=4)
+    d, _, _ = _with_terms(sc)
+    d.step_fused(total_steps=4, grads_out=True)
+    torch.cuda.synchronize()
+    for k in ("params", "m", "v", "s_act", "alpha_act"):
+        assert torch.equal(getattr(c, k), getattr(d, k)), k
+    assert torch.equal(c.grads, d.grads)
+    stf = d.fused_status()
+    assert stf["loss"] == pytest.approx(c.loss.item(), rel=1e-5)
