@@ -128,6 +128,48 @@ def cpu_baseline(scene, budget_s: float = 12.0):
                       f"({scene.n_views} views, {scene.npix} px each step), {el:.1f} s"}
 
 
+def grid_terms_bench(st, scene, run, steps: int, n_points: int = 1_000_000):
+    """The fused step with the grid-side terms of Eq. 12 switched on
+    (elevation smoothness over the four grid neighbours, lambda 1, and the
+    LiDAR elevation loss, lambda 0.02, on synthetic road returns), the
+    one-off LiDAR target lookup, and the meshgrid layout + pose-based
+    initialisation of the 3M-surfel road (1 km of poses every 0.5 m)."""
+    import torch
+    from paper_2405_14342_amd import synth
+
+    pts = synth.lidar_points(scene.trajectory, n_points, 4242)
+    st.lidar_targets(pts)                      # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    zbar = st.lidar_targets(pts)
+    torch.cuda.synchronize()
+    t_nn = (time.perf_counter() - t0) * 1e3
+    st.set_grid_terms(synth.grid_neighbours(*scene.grid_shape), zbar, lambda_smooth=1.0,
+                      lambda_z=0.02)
+    run("fused", 2)
+    ms, _, _ = run("fused", steps)
+    st.set_grid_terms(None, None)
+    # meshgrid layout of the 1 km road: raster bounding box of the poses + 16 m
+    traj = synth.Trajectory(1000.0, 3000)
+    poses = synth.vehicle_poses(traj, 0.5)
+    h = 0.1
+    lo = poses[:, :2].min(0) - 16.0
+    hi = poses[:, :2].max(0) + 16.0
+    W, H = int((hi[0] - lo[0]) / h) + 1, int((hi[1] - lo[1]) / h) + 1
+    pd = torch.as_tensor(poses, device=st.dev)
+    st.rg.meshgrid_layout(pd, float(lo[0]), float(lo[1]), h, W, H, 150)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = st.rg.meshgrid_layout(pd, float(lo[0]), float(lo[1]), h, W, H, 150)
+    torch.cuda.synchronize()
+    t_lay = (time.perf_counter() - t0) * 1e3
+    return {"ms_per_step": round(ms, 4), "value": round(scene.npix / (ms * 1e-3) / 1e6, 2),
+            "unit": "Mpixel/s", "lambda_smooth": 1.0, "lambda_z": 0.02,
+            "lidar_points": n_points, "lidar_targets_ms": round(t_nn, 3),
+            "layout": {"poses": int(poses.shape[0]), "raster": f"{W}x{H}", "radius_px": 150,
+                       "surfels": out["n"], "ms": round(t_lay, 3)}}
+
+
 def serve_bench(seconds: float, warmup_s: float = 1.0, rate: float = 200.0,
                 max_views: int = 16, lanes: int = 2):
     """Serving workload: the 3M-surfel, C = 16 map resident on the GPU,
@@ -220,6 +262,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", default="16x4",
                     help="tile shape WxH, or 'auto' (rogs_autotune; default 16x4)")
+    ap.add_argument("--no-grid-terms", action="store_true",
+                    help="skip the step with the smoothness and LiDAR losses")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the timed serving run (0 = skip)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -370,6 +414,12 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if not args.no_grid_terms:
+        line["grid_terms"] = grid_terms_bench(st, scene, run, args.steps)
+        g = line["grid_terms"]
+        print(f"[bench] fused step with smoothness + LiDAR loss: {g['ms_per_step']} ms/step; "
+              f"LiDAR targets {g['lidar_targets_ms']} ms; meshgrid layout {g['layout']['ms']} ms",
+              file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         print("[bench] serving (3M-surfel map, Poisson 200 req/s)...", file=sys.stderr, flush=True)
         del st
