@@ -369,6 +369,32 @@ ROGS_API int rogs_meshgrid_layout(rogs_ctx* ctx, const rogs_pose* poses, int32_t
                                   float* y, float* z, float* q, int32_t* nbr, int64_t* n_out,
                                   void* scratch, size_t scratch_bytes, void* stream);
 
+/* ------------------------------------------------------ BEV export
+ * Chunked orthographic top-down export (the paper renders its BEV maps in
+ * chunks of 2000 x 2000 pixels at 0.05 m/px and stitches them).  The stitched
+ * image has W x H pixels of m_per_px metres; pixel (col, row) is centred at
+ * (x0 + (col + 1/2) m, y0 + (H - row - 1/2) m), so row 0 is the image's
+ * northern edge.  Every chunk of chunk_px x chunk_px pixels (smaller at the
+ * right and bottom edges) is one orthographic camera looking straight down
+ * from `height` (rogs_bev_camera), rendered with rogs_project + rogs_bin_sort
+ * (host count, one sync per chunk) + rogs_render_fwd and copied into `out`:
+ * the planes selected by `channels` (ROGS_CH_* as for serving, in the order
+ * RGB, SEM, D, A, ELEV, each W x H floats; ELEV = height - D / A, NaN where
+ * A = 0).  ws: device workspace of rogs_bev_workspace_size bytes for the
+ * given pair capacity; a chunk with more pairs stops the export with
+ * ROGS_ECAPACITY and *n_pairs_max (nullable) = the largest pair count seen. */
+ROGS_API void rogs_bev_camera(double x0, double y0, int32_t W, int32_t H, float m_per_px,
+                              int32_t ox, int32_t oy, int32_t cw, int32_t ch, float height,
+                              rogs_camera* cam);
+ROGS_API int rogs_bev_workspace_size(const rogs_surfels* s, int32_t chunk_px,
+                                     const rogs_render_opts* opts, int64_t pair_capacity,
+                                     size_t* bytes);
+ROGS_API int rogs_bev_export(rogs_ctx* ctx, const rogs_surfels* s, const rogs_render_opts* opts,
+                             double x0, double y0, int32_t W, int32_t H, float m_per_px,
+                             int32_t chunk_px, float height, uint32_t channels, float* out,
+                             void* ws, size_t ws_bytes, int64_t pair_capacity,
+                             int64_t* n_pairs_max, void* stream);
+
 /* ------------------------------------------------------ autotuner
  * Chooses the tile shape for a workload.  Every supported shape (tile_w in
  * {4, 8, 16, 32, 64}, tile_w * tile_h in {64, 128, 256}) renders the same

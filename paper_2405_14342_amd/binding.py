@@ -32,7 +32,8 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_fused_status", "rogs_autotune", "rogs_server_create", "rogs_serve_submit",
             "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy", "rogs_debug_work",
             "rogs_elev_scratch_bytes", "rogs_elev_loss", "rogs_lidar_targets",
-            "rogs_meshgrid_scratch_bytes", "rogs_meshgrid_layout")
+            "rogs_meshgrid_scratch_bytes", "rogs_meshgrid_layout", "rogs_bev_camera",
+            "rogs_bev_workspace_size", "rogs_bev_export")
 PROF_GROUPS = 11
 FUSED_EAGER = 4
 
@@ -165,6 +166,13 @@ def load_library(path: str = LIB_PATH):
             "rogs_serve_poll": ([P, ctypes.c_uint64, ctypes.POINTER(Result)], I32),
             "rogs_server_stats": ([P, P], I32),
             "rogs_debug_work": ([P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], I32),
+            "rogs_bev_camera": ([ctypes.c_double, ctypes.c_double, I32, I32, F, I32, I32, I32, I32,
+                                 F, ctypes.POINTER(Camera)], None),
+            "rogs_bev_workspace_size": ([ctypes.POINTER(Surfels), I32, ctypes.POINTER(RenderOpts),
+                                         I64, ctypes.POINTER(ctypes.c_size_t)], I32),
+            "rogs_bev_export": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(RenderOpts),
+                                 ctypes.c_double, ctypes.c_double, I32, I32, F, I32, F, U32, P, P,
+                                 ctypes.c_size_t, I64, ctypes.POINTER(I64), P], I32),
             "rogs_elev_scratch_bytes": ([I32], ctypes.c_size_t),
             "rogs_elev_loss": ([P, I32, P, P, F, P, F, P, P, P, ctypes.c_size_t, P], I32),
             "rogs_lidar_targets": ([P, I32, P, P, I32, P, P, P, P, P, P], I32),
@@ -242,6 +250,13 @@ def fused_workspace_size(ts: TrainStateC, cams, opts: RenderOpts, pair_capacity:
     if r != OK:
         raise RogsError(r, "rogs_fused_workspace_size rejected its arguments")
     return int(out.value)
+
+
+def bev_camera(x0, y0, W, H, m_per_px, ox, oy, cw, ch, height) -> Camera:
+    cam = Camera()
+    load_library().rogs_bev_camera(float(x0), float(y0), int(W), int(H), float(m_per_px), int(ox),
+                                   int(oy), int(cw), int(ch), float(height), ctypes.byref(cam))
+    return cam
 
 
 def elev_scratch_bytes(n: int) -> int:
@@ -427,6 +442,30 @@ class Rogs:
                                                 ctypes.byref(n), ptr(scratch), scratch.numel(),
                                                 _stream(stream)), "rogs_meshgrid_layout")
         return dict(idx=idx, x=x, y=y, z=z, q=q, nbr=nbr, n=N)
+
+    def bev_export(self, surf: Surfels, opts: Optional[RenderOpts], x0, y0, W, H, m_per_px,
+                   chunk_px, height, channels, out, pair_capacity=1 << 22, stream=None):
+        """rogs_bev_export into `out` (planes x H x W); grows the pair capacity
+        and retries if a chunk overflows.  Returns the largest chunk pair count."""
+        import torch
+        o = opts if opts is not None else default_opts()
+        cap = int(pair_capacity)
+        while True:
+            size = ctypes.c_size_t(0)
+            self._check(self.L.rogs_bev_workspace_size(ctypes.byref(surf), int(chunk_px),
+                                                       ctypes.byref(o), cap, ctypes.byref(size)),
+                        "rogs_bev_workspace_size")
+            ws = torch.empty(size.value, dtype=torch.uint8, device=out.device)
+            worst = ctypes.c_int64(0)
+            r = self.L.rogs_bev_export(self.h, ctypes.byref(surf), ctypes.byref(o), float(x0),
+                                       float(y0), int(W), int(H), float(m_per_px), int(chunk_px),
+                                       float(height), int(channels), ptr(out), ptr(ws), size.value,
+                                       cap, ctypes.byref(worst), _stream(stream))
+            if r == ECAPACITY:
+                cap = int(worst.value * 1.25) + 4096
+                continue
+            self._check(r, "rogs_bev_export")
+            return int(worst.value)
 
     def debug_work(self, ws, stream=None):
         """(evaluated, contributing) list entries over all pixels of the batch."""

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librogs.so")
 SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "loss_adam.hip", "autotune.hip",
-           "serve.hip", "grid.hip"]
+           "serve.hip", "grid.hip", "bev.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
