@@ -107,8 +107,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(
         const float dy = pixel_offset(pyc[k], r0.y, r0.w);
         const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
         if (q <= qcut) {
-          const float g = __expf(-0.5f * q);
-          const float a = fminf(al * g, amax);
+          const float g = gauss_weight(q);
+          const float a = clamp_alpha(al * g, amax);
           const float w = a * T[k];
 #pragma unroll
           for (int f = 0; f < F; ++f) acc[k][f] += w * fv[f];
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       for (int c = 0; c < NV; ++c) pv[c] = 0.0f;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        const float g = hit[k] ? __expf(-0.5f * q[k]) : 0.0f;
+        const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
         const float araw = al * g;
         const bool clamped = araw > amax;
         const float a = clamped ? amax : araw;

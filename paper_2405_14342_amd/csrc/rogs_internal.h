@@ -209,6 +209,16 @@ __device__ __forceinline__ float pixel_q32(float A, float B, float C, float dx, 
   return (a + c) + 2.0f * b;
 }
 
+// Footprint weight g = exp(-q/2) = 2^(q * (-log2(e)/2)): one multiply and the
+// hardware base-2 exponential.  The forward and the backward both use this
+// function, so the backward recomputes the forward's transmittance exactly.
+__device__ __forceinline__ float gauss_weight(float q) {
+  return __builtin_amdgcn_exp2f(q * -0.72134752044448170f);
+}
+
+// Opacity clamp alpha' = min(alpha g, alpha_max) as a compare and select.
+__device__ __forceinline__ float clamp_alpha(float ag, float amax) { return ag > amax ? amax : ag; }
+
 __device__ __forceinline__ float pixel_offset(float pc, float hi, float lo) {
 #pragma clang fp contract(off)
   return (pc - hi) - lo;
