@@ -268,11 +268,13 @@ ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* para
  *
  * The sequence is captured into a hipGraph on the first call and replayed by
  * later calls with the same arguments (same pointers, sizes, options and
- * view resolutions; camera poses may change: they are copied from a pinned
- * buffer by the graph).  Each call first waits for the previous step, then
- * launches.  If the previous step overflowed pair_capacity it made no update
- * (parameters, moments and step count untouched); unless that was already
- * seen through rogs_fused_status, this call then returns ROGS_ECAPACITY
+ * view resolutions; camera poses may change: each call copies the camera
+ * table from one of two pinned buffers ahead of the graph).  Two steps stay
+ * in flight: each call first waits for the step launched two calls before,
+ * then launches, so the device runs the previous step meanwhile.  A step
+ * that overflowed pair_capacity made no update (parameters, moments and
+ * step count untouched); unless that was already seen through
+ * rogs_fused_status, the call that waits for it returns ROGS_ECAPACITY
  * without launching.  Read the needed count with rogs_fused_status, grow
  * the workspace and call again. */
 typedef struct {
@@ -312,7 +314,8 @@ ROGS_API int rogs_step_fused(rogs_ctx* ctx, const rogs_train_state* t, const rog
                              const rogs_targets* targets, const rogs_optim* optim, void* ws,
                              size_t ws_bytes, int64_t pair_capacity, int64_t slot_capacity,
                              uint32_t flags, void* stream);
-/* Waits for the last fused step and reports stats[0] pairs P, [1] overflow,
+/* Waits for the fused steps in flight and reports, for the last one,
+ * stats[0] pairs P, [1] overflow,
  * [2] visible slots, [3] steps applied, [4] steps skipped, [5] pixels,
  * [6] tiles, [7] slots; *loss = loss of the last applied step (nullable). */
 ROGS_API int rogs_fused_status(rogs_ctx* ctx, int64_t* stats, float* loss);
@@ -519,7 +522,8 @@ ROGS_API int rogs_debug_work(rogs_ctx* ctx, void* ws, int64_t* evaluated, int64_
                              void* stream);
 /* Copy the per-(view, surfel) projection records of the current batch:
  * rec[V][N][8] = u_hi v_hi u_lo v_lo A B C t_z, rect[V][N][4] = x0 x1 y0 y1,
- * count[V][N] = tiles covered (0 = culled; then rec and rect are zero). */
+ * count[V][N] = tiles reached (the row spans; 0 = culled or no tile reached, then
+ * rec and rect read as zero). */
 ROGS_API int rogs_debug_records(rogs_ctx* ctx, void* ws, float* rec, int32_t* rect, uint32_t* count,
                        void* stream);
 

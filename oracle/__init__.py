@@ -73,6 +73,7 @@ def _load():
         _lib.orc_loss.restype = D
         _lib.orc_adam.argtypes = [I64, P, P, P, P, D, D, D, D, I64]
         _lib.orc_num_threads.restype = I
+        _lib.orc_row_spans.argtypes = [P, I, I, I, I, ctypes.c_float, I, I, I, I, P, P]
         _lib.orc_smooth.argtypes = [I64, P, P, D, P]
         _lib.orc_smooth.restype = D
         _lib.orc_lidar_loss.argtypes = [I64, P, P, D, P]
@@ -352,3 +353,15 @@ def meshgrid_layout(poses, x0: float, y0: float, h: float, W: int, H: int, radiu
     L.orc_layout_build(W, H, _p(mask), float(x0), float(y0), float(h), P, _p(poses), n, _p(idx),
                        _p(x), _p(y), _p(z), _p(q), _p(nbr))
     return dict(mask=mask, idx=idx, x=x, y=y, z=z, q=q, nbr=nbr, pose_pixels=pix)
+
+
+def row_spans(rec7, rect, q_cut: float, tw: int, th: int, W: int, H: int):
+    """Tight per-row tile spans of one binary32 record (u_hi v_hi u_lo v_lo A B
+    C) inside its rectangle (x0, x1, y0, y1): arrays lo, hi per row."""
+    rec7 = np.ascontiguousarray(rec7, np.float32)
+    x0, x1, y0, y1 = (int(t) for t in rect)
+    lo = np.zeros(max(y1 - y0, 1), np.int32)
+    hi = np.zeros(max(y1 - y0, 1), np.int32)
+    _load().orc_row_spans(_p(rec7), x0, x1, y0, y1, float(q_cut), int(tw), int(th), int(W), int(H),
+                          _p(lo), _p(hi))
+    return lo[:y1 - y0], hi[:y1 - y0]

@@ -98,6 +98,62 @@ int clampi_d(double f, int hi) {   // clamp a floored value into [0, hi]
   return (int)f;
 }
 
+// Tiles of rectangle row ty that the 3-sigma ellipse of a record can reach
+// (the contract's tight culling).  The conic of the record is tested per pixel
+// in binary32; its rounding error is below 2^-19.8 q / (1 - rho) with
+// rho = |B| / sqrt(AC), so the ellipse is inflated to
+// q <= q_cut (1 + 2^-18 / (1 - rho)) and its x-extent over the tile row's
+// pixel-centre rows gives the pixel columns, hence the tiles, clipped to the
+// image and to the rectangle.  A conic with 1 - rho < 2^-16 (axis ratio above
+// about 360) or no positive determinant keeps the whole rectangle row.  In
+// binary64 from the binary32 record, one rounding per step, no contraction.
+void row_span(const Rec32& r, double qcut, int tw, int th, int W, int H, int ty, int* lo,
+              int* hi) {
+  *lo = r.x0;
+  *hi = r.x1;
+  const double A = r.A, B = r.B, C = r.C;
+  if (!(A > 0.0) || !(C > 0.0)) return;
+  const double det = A * C - B * B;
+  const double gap = 1.0 - std::fabs(B) / std::sqrt(A * C);
+  if (!(det > 0.0) || !(gap >= 0x1p-16)) return;
+  *hi = r.x0;                                    // empty unless a column is reached
+  const double qe = qcut * (1.0 + 0x1p-18 / gap);
+  const double u = (double)r.uh + (double)r.ul;
+  const double v = (double)r.vh + (double)r.vl;
+  // vertical half-extent, then the tile row's pixel-centre rows inside it
+  const double dym = std::sqrt((A * qe) / det);
+  const int r0 = ty * th;
+  const int r1 = std::min(r0 + th, H);
+  double a = ((double)r0 + 0.5) - v;
+  double b = ((double)r1 - 0.5) - v;
+  if (b < -dym || a > dym) return;
+  if (a < -dym) a = -dym;
+  if (b > dym) b = dym;
+  // the left boundary x(dy) = u + (-B dy - sqrt(A qe - det dy^2)) / A is convex
+  // with its minimum at dy = B sqrt(qe / (C det)); the right one is its mirror
+  const double dys = B * std::sqrt(qe / (C * det));
+  const double tl = dys < a ? a : (dys > b ? b : dys);
+  const double tr = -dys < a ? a : (-dys > b ? b : -dys);
+  double dl = A * qe - det * (tl * tl);
+  double dr = A * qe - det * (tr * tr);
+  if (dl < 0.0) dl = 0.0;
+  if (dr < 0.0) dr = 0.0;
+  const double xl = u + (-(B * tl) - std::sqrt(dl)) / A;
+  const double xr = u + (-(B * tr) + std::sqrt(dr)) / A;
+  // pixel p is reached iff its centre p + 1/2 lies in [xl, xr]
+  const double pl = std::ceil(xl - 0.5);
+  const double pr = std::floor(xr - 0.5);
+  if (!(pl <= pr) || pl > (double)(W - 1) || pr < 0.0) return;
+  const int cl = pl < 0.0 ? 0 : (int)pl;
+  const int cr = pr > (double)(W - 1) ? W - 1 : (int)pr;
+  const int l = std::max(cl / tw, r.x0);
+  const int h = std::min(cr / tw + 1, r.x1);
+  if (l < h) {
+    *lo = l;
+    *hi = h;
+  }
+}
+
 Rec32 contract(const Cam& c, const Opts& o, float xf, float yf, float zf, float qwf, float qxf,
                float qyf, float qzf, float sxf, float syf) {
   Rec32 r;
@@ -404,14 +460,18 @@ void build_view(const Surfels& S, const Cam& cam, const Opts& o, ViewData& V) {
     double q[4] = {S.q[i], S.q[n + i], S.q[2 * n + i], S.q[3 * n + i]};
     V.geo[k] = geo64(cam, o, S.x[i], S.y[i], S.z[i], q, S.s[i], S.s[n + i]);
   }
-  // Brute-force tile lists: every surfel is appended to every tile its
-  // rectangle covers, then each list is ordered by (depth bits, id)
-  // ("ascending order of original depth", Sec. 3.3.1; ties by surfel id).
+  // Brute-force tile lists: every surfel is appended to every tile of its
+  // rectangle that its ellipse reaches (row spans), then each list is ordered
+  // by (depth bits, id) ("ascending order of original depth", Sec. 3.3.1;
+  // ties by surfel id).
   V.lists.assign((size_t)V.TX * V.TY, std::vector<int>());
   for (int i : V.vis_ids) {
     const Rec32& r = V.rec[i];
-    for (int ty = r.y0; ty < r.y1; ++ty)
-      for (int tx = r.x0; tx < r.x1; ++tx) V.lists[(size_t)ty * V.TX + tx].push_back(i);
+    for (int ty = r.y0; ty < r.y1; ++ty) {
+      int lo, hi;
+      row_span(r, o.qcut, o.tw, o.th, cam.w, cam.h, ty, &lo, &hi);
+      for (int tx = lo; tx < hi; ++tx) V.lists[(size_t)ty * V.TX + tx].push_back(i);
+    }
   }
   for (auto& L : V.lists) {
     std::sort(L.begin(), L.end(), [&](int a, int b) {
@@ -544,6 +604,23 @@ Opts make_opts(const int* io, const float* fo) {
 }  // namespace
 
 extern "C" {
+
+// Row spans of one binary32 record (u_hi v_hi u_lo v_lo A B C) over the
+// rectangle rows y0..y1-1: lo[k], hi[k] for row y0 + k.
+void orc_row_spans(const float* rec7, int x0, int x1, int y0, int y1, float qcut, int tw, int th,
+                   int W, int H, int32_t* lo, int32_t* hi) {
+  Rec32 r{};
+  r.vis = true;
+  r.uh = rec7[0]; r.vh = rec7[1]; r.ul = rec7[2]; r.vl = rec7[3];
+  r.A = rec7[4]; r.B = rec7[5]; r.C = rec7[6];
+  r.x0 = x0; r.x1 = x1; r.y0 = y0; r.y1 = y1;
+  for (int ty = y0; ty < y1; ++ty) {
+    int l, h;
+    row_span(r, (double)qcut, tw, th, W, H, ty, &l, &h);
+    lo[ty - y0] = l;
+    hi[ty - y0] = h;
+  }
+}
 
 // Decision contract for every surfel of one view.
 // rec: [n][8] = u_hi v_hi u_lo v_lo A B C tz ; rect: [n][4] = x0 x1 y0 y1 ; vis: [n]

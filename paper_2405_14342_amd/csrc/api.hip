@@ -51,11 +51,14 @@ struct rogs_ctx {
     rogs_optim opt{};
     rogs_render_opts opts{};
     std::vector<int32_t> sizes;         // w, h, model of every view
-    void* stage = nullptr;               // pinned: view table + first-block table
+    // two steps in flight: step k uses buffer k & 1, and step k + 2 waits for it
+    void* stage[2] = {nullptr, nullptr}; // pinned: view table + first-block table
     size_t stage_bytes = 0;
-    uint32_t* status = nullptr;          // pinned: misc[4] + StepState
-    hipEvent_t done = nullptr;
-    bool pending = false;
+    uint32_t* status[2] = {nullptr, nullptr};   // pinned: misc[4] + StepState
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
+    int64_t launched = 0;                // steps launched so far
+    int last = 0;                        // buffer of the last launched step
     hipStream_t cap_stream = nullptr;    // capture happens here (the null stream cannot be captured)
   } fz;
 };
@@ -191,7 +194,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_nlast = take(4 * (size_t)l.total_pix);
   l.o_gpair = take(4 * (size_t)cap * l.GS);
   l.o_hist = take(4 * (size_t)kRadixMax * l.sort_blocks);
-  l.o_histtmp = take(4 * scan_tmp_words((int64_t)kRadixMax * l.sort_blocks));
+  l.o_histtmp = take(4 * (size_t)kRadixMax);  // digit totals of a sort pass
   if (fused) {
     const size_t nch = (size_t)(6 + l.C), tp = (size_t)tw * th;
     l.o_tm = take(4 * (size_t)l.total_tiles * nch * tp);
@@ -358,12 +361,15 @@ int rogs_create(rogs_ctx** ctx) {
 
 void rogs_destroy(rogs_ctx* c) {
   if (!c) return;
-  if (c->fz.pending) (void)hipEventSynchronize(c->fz.done);
+  for (int k = 0; k < 2; ++k)
+    if (c->fz.pending[k]) (void)hipEventSynchronize(c->fz.done[k]);
   if (c->fz.exec) (void)hipGraphExecDestroy(c->fz.exec);
   if (c->fz.graph) (void)hipGraphDestroy(c->fz.graph);
-  if (c->fz.stage) (void)hipHostFree(c->fz.stage);
-  if (c->fz.status) (void)hipHostFree(c->fz.status);
-  if (c->fz.done) (void)hipEventDestroy(c->fz.done);
+  for (int k = 0; k < 2; ++k) {
+    if (c->fz.stage[k]) (void)hipHostFree(c->fz.stage[k]);
+    if (c->fz.status[k]) (void)hipHostFree(c->fz.status[k]);
+    if (c->fz.done[k]) (void)hipEventDestroy(c->fz.done[k]);
+  }
   if (c->fz.cap_stream) (void)hipStreamDestroy(c->fz.cap_stream);
   if (!c->recs.empty()) (void)hipEventSynchronize(c->recs.back().b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -749,11 +755,6 @@ rogs::AdamArgs fused_adam_args(const rogs_optim* o, const Layout& L, void* ws, c
 // Returns the sort's buffer parity.
 int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs_targets* tg,
                    const rogs_optim* o, void* ws, hipStream_t st) {
-  auto& F = c->fz;
-  const size_t vbytes = sizeof(ViewDev) * L.V, fbytes = sizeof(int64_t) * (L.V + 1);
-  const char* stage = static_cast<const char*>(F.stage);
-  (void)hipMemcpyAsync(rogs::at<void>(ws, L.o_views), stage, vbytes, hipMemcpyHostToDevice, st);
-  (void)hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), stage + vbytes, fbytes, hipMemcpyHostToDevice, st);
   rogs_surfels s = fused_surfels(t);
   prof_begin(c, 0, st);
   rogs::launch_project(L, ws, &s, true, st);
@@ -810,9 +811,6 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
   prof_end(c, st);
   rogs::launch_step_end(L, ws, static_cast<rogs::StepState*>(t->step_state), aa,
                         reg ? rogs::at<const float>(ws, L.o_regtot) : nullptr, st);
-  (void)hipMemcpyAsync(F.status, rogs::at<void>(ws, L.o_misc), 16, hipMemcpyDeviceToHost, st);
-  (void)hipMemcpyAsync(reinterpret_cast<char*>(F.status) + 16, t->step_state,
-                       sizeof(rogs::StepState), hipMemcpyDeviceToHost, st);
   return ROGS_OK;
 }
 
@@ -850,21 +848,24 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto& F = c->fz;
   hipError_t e = hipSuccess;
-  if (!F.done) {
-    e = hipEventCreateWithFlags(&F.done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&F.status, 128, hipHostMallocDefault);
-    if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused setup");
-    memset(F.status, 0, 128);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    if (F.done[k]) continue;
+    e = hipEventCreateWithFlags(&F.done[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&F.status[k], 128, hipHostMallocDefault);
+    if (e == hipSuccess) memset(F.status[k], 0, 128);
   }
-  // the previous step must have finished before its status is read and the
-  // pinned camera table is rewritten
-  if (F.pending) {
-    e = hipEventSynchronize(F.done);
+  if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused setup");
+  // this step's buffers were last used two steps ago: that step must have
+  // finished before its status is read and its pinned camera table is
+  // rewritten (the step launched last may still be queued)
+  const int p = (int)(F.launched & 1);
+  if (F.pending[p]) {
+    e = hipEventSynchronize(F.done[p]);
     if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused");
-    F.pending = false;
-    if (F.status[rogs::kMiscOverflow])
-      return fail(c, ROGS_ECAPACITY, "the previous fused step overflowed the pair capacity (" +
-                                         std::to_string(F.status[rogs::kMiscPairs]) +
+    F.pending[p] = false;
+    if (F.status[p][rogs::kMiscOverflow])
+      return fail(c, ROGS_ECAPACITY, "an earlier fused step overflowed the pair capacity (" +
+                                         std::to_string(F.status[p][rogs::kMiscPairs]) +
                                          " pairs) and was skipped");
   }
   std::vector<int32_t> sizes;
@@ -887,15 +888,35 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
     F.graph = nullptr;
     F.valid = false;
     if (F.stage_bytes < need) {
-      if (F.stage) (void)hipHostFree(F.stage);
-      F.stage = nullptr;
+      // both stages may be read by queued copies
+      for (int k = 0; k < 2; ++k) {
+        if (F.pending[k]) {
+          e = hipEventSynchronize(F.done[k]);
+          if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused");
+        }
+      }
+      for (int k = 0; k < 2; ++k) {
+        if (F.stage[k]) (void)hipHostFree(F.stage[k]);
+        F.stage[k] = nullptr;
+      }
       F.stage_bytes = 0;
-      e = hipHostMalloc(&F.stage, need, hipHostMallocDefault);
-      if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+      for (int k = 0; k < 2; ++k) {
+        e = hipHostMalloc(&F.stage[k], need, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+      }
       F.stage_bytes = need;
     }
   }
-  fill_view_table(L, cams, F.stage);
+  fill_view_table(L, cams, F.stage[p]);
+  {
+    const size_t vbytes = sizeof(ViewDev) * L.V, fbytes = sizeof(int64_t) * (L.V + 1);
+    const char* stage = static_cast<const char*>(F.stage[p]);
+    e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), stage, vbytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), stage + vbytes, fbytes,
+                         hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused: camera table");
+  }
   if (eager) {
     Layout Lr = L;
     r = fused_sequence(c, Lr, t, tg, o, ws, st);
@@ -948,9 +969,15 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
   F.opt = *o;
   F.opts = *opts;
   F.sizes = sizes;
-  e = hipEventRecord(F.done, st);
-  if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord");
-  F.pending = true;
+  e = hipMemcpyAsync(F.status[p], rogs::at<void>(ws, F.L.o_misc), 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(reinterpret_cast<char*>(F.status[p]) + 16, t->step_state,
+                       sizeof(rogs::StepState), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(F.done[p], st);
+  if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused: status");
+  F.pending[p] = true;
+  F.last = p;
+  F.launched += 1;
   // the batch state of the plain entry points no longer describes the workspace
   if (c->ws == ws) {
     c->have_batch = false;
@@ -963,17 +990,21 @@ int rogs_fused_status(rogs_ctx* c, int64_t* stats, float* loss) {
   if (!c) return ROGS_EINVAL;
   if (!stats) return fail(c, ROGS_EINVAL, "stats is null");
   auto& F = c->fz;
-  if (!F.status) return fail(c, ROGS_ESTATE, "no fused step has run");
-  if (F.pending) {
-    hipError_t e = hipEventSynchronize(F.done);
+  if (F.launched == 0) return fail(c, ROGS_ESTATE, "no fused step has run");
+  // both steps in flight are waited for and seen: the next step call does
+  // not report them again
+  for (int k = 0; k < 2; ++k) {
+    if (!F.pending[k]) continue;
+    hipError_t e = hipEventSynchronize(F.done[k]);
     if (e != hipSuccess) return hip_fail(c, e, "rogs_fused_status");
-    F.pending = false;     // seen: the next step call does not report it again
+    F.pending[k] = false;
   }
+  const uint32_t* stt = F.status[F.last];
   const rogs::StepState* ss = reinterpret_cast<const rogs::StepState*>(
-      reinterpret_cast<const char*>(F.status) + 16);
-  stats[0] = F.status[rogs::kMiscPairs];
-  stats[1] = F.status[rogs::kMiscOverflow];
-  stats[2] = F.status[rogs::kMiscVisible];
+      reinterpret_cast<const char*>(stt) + 16);
+  stats[0] = stt[rogs::kMiscPairs];
+  stats[1] = stt[rogs::kMiscOverflow];
+  stats[2] = stt[rogs::kMiscVisible];
   stats[3] = ss->step;
   stats[4] = ss->skipped;
   stats[5] = F.L.total_pix;

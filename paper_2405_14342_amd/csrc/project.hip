@@ -10,37 +10,6 @@ namespace rogs {
 
 namespace {
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
-// Block-wide exclusive scan of one value per thread (kProjBlock threads).
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, uint32_t* total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t inc = wave_incl_scan(x, lane);
-  if (lane == 63) s_w[wv] = inc;
-  __syncthreads();
-  uint32_t pre = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kProjBlock / 64; ++w) {
-    uint32_t t = s_w[w];
-    pre += (w < wv) ? t : 0u;
-    tot += t;
-  }
-  __syncthreads();
-  *total = tot;
-  return pre + inc - x;
-}
-
 __global__ __launch_bounds__(kProjBlock) void k_project(
     const ViewDev* __restrict__ views, int V, int N, int nb, float eps, float qcut, int tw, int th,
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
@@ -50,7 +19,12 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
     uint32_t* __restrict__ part, uint32_t* __restrict__ partv, float* __restrict__ feat) {
   __shared__ uint32_t s_w[kProjBlock / 64];
   __shared__ uint32_t s_v[kProjBlock / 64];
+  __shared__ Span s_sp[kProjBlock];           // per-record span set-up
+  __shared__ uint32_t s_roff[kProjBlock];     // first row item of each lane in its wave
+  __shared__ uint32_t s_y0[kProjBlock];
+  __shared__ uint32_t s_cnt[kProjBlock];
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
   const bool valid = i < N;
   float x = 0, y = 0, z = 0, qw = 1, qx = 0, qy = 0, qz = 0, sx = 1, sy = 1, al = 0;
   if (valid) {
@@ -70,19 +44,43 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
   }
   for (int v = 0; v < V; ++v) {
     const ViewDev& vw = views[v];
-    uint32_t nt = 0;
+    uint32_t nt = 0, rows = 0;
+    Proj p;
+    p.vis = false;
+    p.y0 = 0;
+    const size_t slot = (size_t)v * N + i;
     if (valid) {
-      Proj p = project_contract(vw, eps, qcut, tw, th, x, y, z, qw, qx, qy, qz, sx, sy);
-      const size_t slot = (size_t)v * N + i;
+      p = project_contract(vw, eps, qcut, tw, th, x, y, z, qw, qx, qy, qz, sx, sy);
       if (p.vis) {
-        nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
+        const Span sp = span_setup(p.uh, p.vh, p.ul, p.vl, p.A, p.B, p.C, qcut, p.x0, p.x1);
+        if (sp.full)
+          nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
+        else
+          rows = (uint32_t)(p.y1 - p.y0);
+        s_sp[threadIdx.x] = sp;
         rec[2 * slot] = make_float4(p.uh, p.vh, p.ul, p.vl);
         rec[2 * slot + 1] = make_float4(p.A, p.B, p.C, p.tz);
         rect[slot] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.x1 << 16),
                                 (uint32_t)p.y0 | ((uint32_t)p.y1 << 16));
       }
-      cnt[slot] = nt;
     }
+    // the wave's rectangle rows, spread evenly over its lanes: the row spans
+    // of one record are summed into its lane's counter (integer adds)
+    const uint32_t incl = wave_incl_scan(rows, lane);
+    const uint32_t R = __shfl(incl, 63, 64);
+    s_roff[threadIdx.x] = incl - rows;
+    s_y0[threadIdx.x] = (uint32_t)p.y0;
+    s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t k = (uint32_t)lane; k < R; k += 64) {
+      const int j = wbase + last_le(s_roff + wbase, 64, k);
+      int lo, hi;
+      span_row(s_sp[j], tw, th, vw.w, vw.h, (int)(s_y0[j] + (k - s_roff[j])), lo, hi);
+      if (hi > lo) atomicAdd(&s_cnt[j], (uint32_t)(hi - lo));
+    }
+    __syncthreads();
+    nt += s_cnt[threadIdx.x];
+    if (valid) cnt[slot] = nt;
     uint32_t ws = wave_sum_u32(nt);
     const uint32_t wvis = (uint32_t)__popcll(__ballot(nt != 0));
     if ((threadIdx.x & 63) == 0) {

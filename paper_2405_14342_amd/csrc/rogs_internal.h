@@ -196,6 +196,82 @@ __device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcu
   return r;
 }
 
+// Tight tile culling of the key contract: the tiles of one rectangle row that
+// the record's 3-sigma ellipse can reach.  The per-pixel binary32 test below
+// rounds q by less than 2^-19.8 q / (1 - rho), rho = |B| / sqrt(AC), so the
+// ellipse is inflated to q <= q_cut (1 + 2^-18 / (1 - rho)); its x-extent over
+// the tile row's pixel-centre rows bounds the reached pixel columns.  A conic
+// with 1 - rho < 2^-16 or without a positive determinant keeps the whole
+// rectangle row.  Binary64 from the binary32 record, one rounding per step,
+// no contraction; span_setup holds the per-record part, span_row one row.
+struct Span {
+  double A, B, det, qe, u, v, dym, dys;
+  int x0, x1;
+  bool full;
+};
+
+__device__ inline Span span_setup(float uh, float vh, float ul, float vl, float Af, float Bf,
+                                  float Cf, float qcut_f, int x0, int x1) {
+#pragma clang fp contract(off)
+  Span s;
+  s.x0 = x0;
+  s.x1 = x1;
+  s.full = true;
+  s.A = s.B = s.det = s.qe = s.u = s.v = s.dym = s.dys = 0.0;
+  const double A = Af, B = Bf, C = Cf;
+  if (!(A > 0.0) || !(C > 0.0)) return s;
+  const double det = A * C - B * B;
+  const double gap = 1.0 - fabs(B) / sqrt(A * C);
+  if (!(det > 0.0) || !(gap >= 0x1p-16)) return s;
+  s.full = false;
+  s.A = A;
+  s.B = B;
+  s.det = det;
+  s.qe = (double)qcut_f * (1.0 + 0x1p-18 / gap);
+  s.u = (double)uh + (double)ul;
+  s.v = (double)vh + (double)vl;
+  s.dym = sqrt((A * s.qe) / det);
+  s.dys = B * sqrt(s.qe / (C * det));
+  return s;
+}
+
+// Tiles [lo, hi) of tile row ty (inside the rectangle) for an image W x H.
+__device__ inline void span_row(const Span& s, int tw, int th, int W, int H, int ty, int& lo,
+                                int& hi) {
+#pragma clang fp contract(off)
+  lo = s.x0;
+  hi = s.x1;
+  if (s.full) return;
+  hi = s.x0;
+  const int r0 = ty * th;
+  const int r1 = min(r0 + th, H);
+  double a = ((double)r0 + 0.5) - s.v;
+  double b = ((double)r1 - 0.5) - s.v;
+  if (b < -s.dym || a > s.dym) return;
+  if (a < -s.dym) a = -s.dym;
+  if (b > s.dym) b = s.dym;
+  // left boundary convex in dy, minimum at dys; right boundary its mirror
+  const double tl = s.dys < a ? a : (s.dys > b ? b : s.dys);
+  const double tr = -s.dys < a ? a : (-s.dys > b ? b : -s.dys);
+  double dl = s.A * s.qe - s.det * (tl * tl);
+  double dr = s.A * s.qe - s.det * (tr * tr);
+  if (dl < 0.0) dl = 0.0;
+  if (dr < 0.0) dr = 0.0;
+  const double xl = s.u + (-(s.B * tl) - sqrt(dl)) / s.A;
+  const double xr = s.u + (-(s.B * tr) + sqrt(dr)) / s.A;
+  const double pl = ceil(xl - 0.5);
+  const double pr = floor(xr - 0.5);
+  if (!(pl <= pr) || pl > (double)(W - 1) || pr < 0.0) return;
+  const int cl = pl < 0.0 ? 0 : (int)pl;
+  const int cr = pr > (double)(W - 1) ? W - 1 : (int)pr;
+  const int l = max(cl / tw, s.x0);
+  const int h = min(cr / tw + 1, s.x1);
+  if (l < h) {
+    lo = l;
+    hi = h;
+  }
+}
+
 // Per-pixel contribution test of the contract (binary32, no contraction).
 // dx = ((px + 0.5) - u_hi) - u_lo and dy likewise are formed by the caller.
 __device__ __forceinline__ float pixel_q32(float A, float B, float C, float dx, float dy) {
@@ -222,6 +298,47 @@ __device__ __forceinline__ float clamp_alpha(float ag, float amax) { return ag >
 __device__ __forceinline__ float pixel_offset(float pc, float hi, float lo) {
 #pragma clang fp contract(off)
   return (pc - hi) - lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Block-wide exclusive scan of one value per thread (kProjBlock threads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(x, lane);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kProjBlock / 64; ++w) {
+    uint32_t t = s_w[w];
+    pre += (w < wv) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - x;
+}
+
+// Last index j in [0, n) with off[j] <= k, for non-decreasing off with off[0] <= k.
+__device__ __forceinline__ int last_le(const uint32_t* off, int n, uint32_t k) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 // ---------------------------------------------------------------------------

@@ -4,10 +4,12 @@
 // order of original depth with ties by surfel id (Sec. 3.3.1).
 //
 // Stable LSD radix sort: per pass, per-block digit histograms (LDS atomics),
-// one exclusive scan over the digit-major histogram table, then a stable
-// scatter.  In the scatter a block owns kSortTile consecutive keys; each of its
-// four waves ranks a contiguous quarter, 64 keys at a time, finding lanes with
-// equal digits with one ballot per digit bit, so ranks follow the input order.
+// an exclusive scan of each digit's column of that table with the digit
+// totals (one block per digit), then a stable scatter.  In the scatter a block
+// owns kSortTile consecutive keys and starts each digit at the scan of the
+// totals plus its column entry; each of its four waves ranks a contiguous
+// quarter, 64 keys at a time, finding lanes with equal digits with one ballot
+// per digit bit, so ranks follow the input order.
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -43,21 +45,72 @@ __global__ __launch_bounds__(kSortBlock) void k_hist(const K* __restrict__ keys,
   for (int d = threadIdx.x; d < R; d += kSortBlock) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
 }
 
+// Exclusive scan of each digit's column of the block histogram table (one
+// block per digit, the column in rounds of 1024 with a carry) and the digit
+// totals.
+__global__ __launch_bounds__(kProjBlock) void k_colscan(uint32_t* __restrict__ hist, int64_t nblk,
+                                                        uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_w[kProjBlock / 64];
+  uint32_t* col = hist + (int64_t)blockIdx.x * nblk;
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < nblk; c0 += 4 * kProjBlock) {
+    const int64_t b = c0 + 4 * (int64_t)threadIdx.x;
+    uint32_t v[4], loc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = (b + k < nblk) ? col[b + k] : 0u;
+      loc += v[k];
+    }
+    uint32_t total;
+    uint32_t run = carry + block_excl_scan(loc, s_w, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (b + k < nblk) col[b + k] = run;
+      run += v[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
 template <typename K, int RB>
 __global__ __launch_bounds__(kSortBlock) void k_scatter(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
-    int shift, uint32_t mask, int nbits, const uint32_t* __restrict__ hist_scan, int64_t nblk) {
+    int shift, uint32_t mask, int nbits, const uint32_t* __restrict__ hist_scan, int64_t nblk,
+    const uint32_t* __restrict__ tot) {
+  static_assert(kSortBlock == kProjBlock, "block scan width");
   constexpr int R = 1 << RB;
   constexpr int kWaves = kSortBlock / 64;
   constexpr int kPerWave = kSortTile / kWaves;
   constexpr int kIters = kPerWave / 64;
+  constexpr int kDig = (R + kSortBlock - 1) / kSortBlock;
   __shared__ uint32_t wcnt[kWaves][R];
+  __shared__ uint32_t s_base[R];
+  __shared__ uint32_t s_w[kSortBlock / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t n = count_n(n_dev, n_host, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= (int64_t)n) return;
   for (int k = threadIdx.x; k < kWaves * R; k += kSortBlock) (&wcnt[0][0])[k] = 0;
+  {
+    // first output position of each digit: exclusive scan of the totals
+    uint32_t v[kDig], loc = 0;
+#pragma unroll
+    for (int k = 0; k < kDig; ++k) {
+      const int d = threadIdx.x * kDig + k;
+      v[k] = d < R ? tot[d] : 0u;
+      loc += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(loc, s_w, &total);
+#pragma unroll
+    for (int k = 0; k < kDig; ++k) {
+      const int d = threadIdx.x * kDig + k;
+      if (d < R) s_base[d] = run;
+      run += v[k];
+    }
+  }
   __syncthreads();
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t rank[kIters];
@@ -84,7 +137,7 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
   __syncthreads();
   // per digit: global start of this block, then the waves one after another
   for (int d = threadIdx.x; d < R; d += kSortBlock) {
-    uint32_t run = hist_scan[(int64_t)d * nblk + blockIdx.x];
+    uint32_t run = s_base[d] + hist_scan[(int64_t)d * nblk + blockIdx.x];
     for (int w = 0; w < kWaves; ++w) {
       uint32_t c = wcnt[w][d];
       wcnt[w][d] = run;
@@ -119,9 +172,9 @@ int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, 
     const uint32_t mask = (1u << nbits) - 1u;
     hipLaunchKernelGGL((k_hist<K, RB>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
                        n_grid, cap, shift, mask, hist, nblk);
-    scan_u32(hist, hist, (int64_t)(1 << RB) * nblk, nullptr, histtmp, st);
+    hipLaunchKernelGGL(k_colscan, dim3(1u << RB), dim3(kProjBlock), 0, st, hist, nblk, histtmp);
     hipLaunchKernelGGL((k_scatter<K, RB>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
-                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk);
+                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp);
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;
   }
@@ -176,24 +229,62 @@ __global__ void k_gather_cnt(const uint32_t* __restrict__ n_dev, int64_t n_host,
 // pairs e in [b * kEmitPairs, (b + 1) * kEmitPairs).  Two threads find the
 // first and last slot of the block's range by binary search over the slot
 // offsets (each visible slot has at least one pair, so the offsets are
-// strictly increasing and the range holds at most kEmitPairs slots); the
-// block stages those slots in LDS, and each pair finds its slot there.  Per
-// pair: key = global tile, value = e, pslot[e] = slot.  The number of pairs
-// written (the pair count, clipped to the capacity and to the pairs of the
-// slots within the slot capacity) goes to *n_emit for the sort.
+// strictly increasing and the range holds at most kEmitPairs slots), and the
+// block stages those slots in LDS.  The rectangle rows of the staged slots
+// become row items: each gets its tile span (the same row spans that gave the
+// counts), an exclusive scan turns the span lengths into pair offsets, and
+// each pair finds its row by binary search.  A block whose slots hold more
+// than kEmitRows rows walks each pair's rows instead.  Per pair: key = global
+// tile, value = e, pslot[e] = slot.  The number of pairs written (the pair
+// count, clipped to the capacity and to the pairs of the slots within the
+// slot capacity) goes to *n_emit for the sort.
 constexpr int kEmitThreads = 256;
-constexpr int kEmitPairs = 2048;
+constexpr int kEmitPairs = 1024;
+constexpr int kEmitRows = 2048;
+
+__device__ __forceinline__ Span emit_span(const float4* __restrict__ rec, uint32_t slot, float qcut,
+                                          int x0, int x1) {
+  const float4 r0 = rec[2 * (size_t)slot], r1 = rec[2 * (size_t)slot + 1];
+  return span_setup(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, qcut, x0, x1);
+}
+
+// In-place exclusive scan of n <= kEmitRows values in LDS; returns the total.
+__device__ uint32_t emit_scan(uint32_t* a, int n, uint32_t* s_w) {
+  constexpr int kPer = kEmitRows / kEmitThreads;
+  const int b = threadIdx.x * kPer;
+  uint32_t v[kPer], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    v[k] = (b + k < n) ? a[b + k] : 0u;
+    sum += v[k];
+  }
+  uint32_t total;
+  uint32_t pre = block_excl_scan(sum, s_w, &total);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (b + k < n) a[b + k] = pre;
+    pre += v[k];
+  }
+  __syncthreads();
+  return total;
+}
 
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const ViewDev* __restrict__ views, int N, const uint32_t* __restrict__ p_dev, int64_t p_host,
     const uint32_t* __restrict__ s_dev, int64_t s_host, int64_t scap, int64_t cap,
     const uint32_t* __restrict__ sval, const uint32_t* __restrict__ soff,
-    const uint32_t* __restrict__ scnt, const uint2* __restrict__ rect, uint32_t* __restrict__ keys,
+    const uint32_t* __restrict__ scnt, const uint2* __restrict__ rect,
+    const float4* __restrict__ rec, float qcut, int tw, int th, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ n_emit) {
+  static_assert(kEmitThreads == kProjBlock, "block scan width");
   __shared__ uint32_t s_off[kEmitPairs + 1];
   __shared__ uint32_t s_slot[kEmitPairs];
-  __shared__ uint2 s_rect[kEmitPairs];
+  __shared__ uint32_t s_roff[kEmitPairs + 1];   // first row item of each slot
+  __shared__ uint32_t s_rx[kEmitRows];          // row span length, then its first pair
+  __shared__ uint32_t s_rinfo[kEmitRows];       // span start tile | tile row << 16
+  __shared__ uint16_t s_rslot[kEmitRows];
   __shared__ uint32_t s_k[2];
+  __shared__ uint32_t s_w[kEmitThreads / 64];
   const uint32_t S = count_n(s_dev, s_host, scap);
   const uint32_t P = count_n(p_dev, p_host, cap);
   const uint32_t pend = S ? soff[S - 1] + scnt[S - 1] : 0u;
@@ -204,37 +295,88 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
   const uint32_t e1 = min(E, e0 + (uint32_t)kEmitPairs);
   if (threadIdx.x < 2) {
     const uint32_t target = threadIdx.x == 0 ? e0 : e1 - 1u;
-    uint32_t lo = 0, hi = S - 1u;                  // last k with soff[k] <= target
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1u) >> 1;
-      if (soff[mid] <= target) lo = mid; else hi = mid - 1u;
-    }
-    s_k[threadIdx.x] = lo;
+    s_k[threadIdx.x] = (uint32_t)last_le(soff, (int)S, target);
   }
   __syncthreads();
   const uint32_t ka = s_k[0];
   const int ns = (int)min<uint32_t>(s_k[1] - ka + 1u, (uint32_t)kEmitPairs);
-  for (int t = threadIdx.x; t < ns; t += kEmitThreads) {
-    const uint32_t slot = sval[ka + t];
-    s_off[t] = soff[ka + t];
-    s_slot[t] = slot;
-    s_rect[t] = rect[slot];
+  // stage the slots and count their rectangle rows (ns <= kEmitThreads * 4)
+  constexpr int kPer = kEmitPairs / kEmitThreads;
+  uint32_t nrow[kPer], rsum = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int t = threadIdx.x * kPer + k;
+    nrow[k] = 0;
+    if (t < ns) {
+      const uint32_t slot = sval[ka + t];
+      s_off[t] = soff[ka + t];
+      s_slot[t] = slot;
+      const uint2 r = rect[slot];
+      nrow[k] = (r.y >> 16) - (r.y & 0xffff);
+    }
+    rsum += nrow[k];
   }
   if (threadIdx.x == 0) s_off[ns] = soff[ka + ns - 1] + scnt[ka + ns - 1];
+  uint32_t R;
+  uint32_t pre = block_excl_scan(rsum, s_w, &R);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int t = threadIdx.x * kPer + k;
+    if (t < ns) s_roff[t] = pre;
+    pre += nrow[k];
+  }
   __syncthreads();
-  for (uint32_t e = e0 + threadIdx.x; e < e1; e += kEmitThreads) {
-    int lo = 0, hi = ns - 1;                       // last j with s_off[j] <= e
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+  if (R <= (uint32_t)kEmitRows) {
+    // row items: span of each rectangle row of the staged slots
+    for (int k = threadIdx.x; k < (int)R; k += kEmitThreads) {
+      const int j = last_le(s_roff, ns, (uint32_t)k);
+      const uint32_t slot = s_slot[j];
+      const uint2 r = rect[slot];
+      const ViewDev& vw = views[slot / (uint32_t)N];
+      const Span sp = emit_span(rec, slot, qcut, r.x & 0xffff, r.x >> 16);
+      const int ty = (int)(r.y & 0xffff) + (k - (int)s_roff[j]);
+      int lo, hi;
+      span_row(sp, tw, th, vw.w, vw.h, ty, lo, hi);
+      s_rx[k] = (uint32_t)(hi - lo);
+      s_rinfo[k] = (uint32_t)lo | ((uint32_t)ty << 16);
+      s_rslot[k] = (uint16_t)j;
     }
-    const uint32_t slot = s_slot[lo];
-    const uint2 r = s_rect[lo];
-    const int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff;
-    const int wx = x1 - x0;
-    const int kk = (int)(e - s_off[lo]);
-    const int ty = y0 + kk / wx, tx = x0 + kk % wx;
+    __syncthreads();
+    emit_scan(s_rx, (int)R, s_w);                 // pair offsets from the first slot's first pair
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kEmitThreads) {
+      const uint32_t t = e - s_off[0];
+      const int rr = last_le(s_rx, (int)R, t);
+      const uint32_t info = s_rinfo[rr];
+      const uint32_t slot = s_slot[s_rslot[rr]];
+      const int tx = (int)(info & 0xffff) + (int)(t - s_rx[rr]);
+      const int ty = (int)(info >> 16);
+      const ViewDev& vw = views[slot / (uint32_t)N];
+      keys[e] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
+      vals[e] = e;
+      pslot[e] = slot;
+    }
+    return;
+  }
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += kEmitThreads) {
+    const int j = last_le(s_off, ns, e);
+    const uint32_t slot = s_slot[j];
+    const uint2 r = rect[slot];
+    const int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
     const ViewDev& vw = views[slot / (uint32_t)N];
+    const Span sp = emit_span(rec, slot, qcut, x0, x1);
+    // walk the rectangle's rows to the one holding the kk-th reached tile
+    int kk = (int)(e - s_off[j]);
+    int ty = y0, tx = x0;
+    for (; ty < y1; ++ty) {
+      int a, b;
+      span_row(sp, tw, th, vw.w, vw.h, ty, a, b);
+      if (kk < b - a) {
+        tx = a + kk;
+        break;
+      }
+      kk -= b - a;
+    }
+    if (ty >= y1) ty = y1 - 1;   // unreachable: the counts come from the same spans
     keys[e] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
     vals[e] = e;
     pslot[e] = slot;
@@ -312,7 +454,8 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
       hipLaunchKernelGGL(k_emit, dim3((unsigned)((p_grid + kEmitPairs - 1) / kEmitPairs)),
                          dim3(kEmitThreads), 0, st, at<const ViewDev>(ws, L.o_views), L.N, p_dev,
                          p_grid, s_dev, s_grid, L.scap, L.cap, sv, soff, scnt,
-                         at<const uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_keys),
+                         at<const uint2>(ws, L.o_rect), at<const float4>(ws, L.o_rec), L.q_cut,
+                         L.tw, L.th, at<uint32_t>(ws, L.o_keys),
                          at<uint32_t>(ws, L.o_vals), at<uint32_t>(ws, L.o_pslot), n_emit);
     } else if (n_emit) {
       fill_u32(n_emit, 0u, 1, st);

@@ -267,8 +267,9 @@ class TrainState:
         With check=True the call waits for the step and, if it overflowed the
         pair capacity (the device then skips the update), grows the capacity
         and runs the step again.  With check=False the call returns right
-        after the launch; an overflow is then reported by the next call, which
-        grows the capacity before launching its own step."""
+        after the launch (two steps stay in flight); an overflow is then
+        reported by the call that waits for that step, which grows the
+        capacity before launching its own step."""
         ts = self.train_state(grads_out)
         optim = paper_optim(self.scene.extent, total_steps)
         flags = B.FUSED_EAGER if eager else 0

@@ -254,8 +254,12 @@ def test_p6_ties_by_id_and_ranges_partition():
     assert np.all(ranges[1:, 0] == ranges[:-1, 1])
 
 
-@pytest.mark.parametrize("which", ["c1", "ortho"])
-def test_p6_rect_covers_every_contributing_pixel(which):
+@pytest.mark.parametrize("which,tw,th", [("c1", 16, 16), ("c1", 16, 4), ("ortho", 16, 16),
+                                         ("ortho", 8, 8)])
+def test_p6_lists_cover_every_contributing_pixel(which, tw, th):
+    """Every pixel whose binary32 test q <= 9 passes lies in a tile of the
+    surfel's rectangle and of its list: the row spans drop only tiles that no
+    such pixel reaches."""
     if which == "c1":
         sc = synth.config1()
         sel = np.arange(0, sc.n, 5)
@@ -264,13 +268,18 @@ def test_p6_rect_covers_every_contributing_pixel(which):
         sc.cams = [synth.ortho_bev_camera((1.5, 0.0), 5.0, 40, 40, m_per_px=0.03)]
         sel = np.arange(sc.n)
     cam = sc.cams[0]
+    opts = oracle.Opts(tile_w=tw, tile_h=th)
     prm = oracle.Params.from_scene(sc)
-    vis, rec, rect = oracle.contract(prm, cam)
+    vis, rec, rect = oracle.contract(prm, cam, opts)
+    keys, ids, ranges = oracle.tile_lists(prm, cam, opts)
+    TX = (cam.w + tw - 1) // tw
+    member = set(zip(((keys >> np.uint64(32)).astype(np.int64)).tolist(), ids.tolist()))
     py, px = np.mgrid[0:cam.h, 0:cam.w]
     pxc = (px.astype(np.float32) + np.float32(0.5)).reshape(-1)
     pyc = (py.astype(np.float32) + np.float32(0.5)).reshape(-1)
-    tx, ty = px.reshape(-1) // 16, py.reshape(-1) // 16
+    tx, ty = px.reshape(-1) // tw, py.reshape(-1) // th
     hits = 0
+    reached = set()
     for i in sel:
         if not vis[i]:
             continue
@@ -281,8 +290,93 @@ def test_p6_rect_covers_every_contributing_pixel(which):
         x0, x1, y0, y1 = rect[i]
         cov = (tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)
         assert not np.any(inside & ~cov)
+        for t in set((ty[inside] * TX + tx[inside]).tolist()):
+            assert (t, int(i)) in member
+            reached.add((t, int(i)))
         hits += inside.sum()
     assert hits > 1000
+    # and the lists are tight: few listed pairs reach no pixel
+    listed = [m for m in member if m[1] in set(sel.tolist())]
+    assert len(listed) <= 1.35 * len(reached)
+
+
+def _random_conic(rng, ratio):
+    smin = rng.uniform(0.55, 3.0)
+    ang = rng.uniform(0.0, math.pi)
+    c, s = math.cos(ang), math.sin(ang)
+    R = np.array([[c, -s], [s, c]])
+    Ci = np.linalg.inv(R @ np.diag([(smin * ratio) ** 2, smin ** 2]) @ R.T)
+    return np.float32(Ci[0, 0]), np.float32(Ci[0, 1]), np.float32(Ci[1, 1])
+
+
+@pytest.mark.parametrize("tw,th", [(16, 4), (8, 8), (32, 2)])
+def test_p6_row_spans_cover_extreme_ellipses(tw, th):
+    """Row spans against the brute-force binary32 test over a whole image for
+    random conics with axis ratios 1..1000 at any angle, centres inside and
+    outside the image and far from the origin (the hi/lo split): no pixel that
+    passes is left out; a conic with an axis ratio far beyond the inflation's
+    range keeps its whole rectangle row."""
+    rng = np.random.default_rng(17 + tw)
+    W, H = 200, 120
+    TX, TY = (W + tw - 1) // tw, (H + th - 1) // th
+    py, px = np.mgrid[0:H, 0:W]
+    pxc = (px.astype(np.float32) + np.float32(0.5)).reshape(-1)
+    pyc = (py.astype(np.float32) + np.float32(0.5)).reshape(-1)
+    tx, ty = px.reshape(-1) // tw, py.reshape(-1) // th
+    span = exact = 0
+    for k in range(300):
+        ratio = math.exp(rng.uniform(0.0, math.log(1000.0)))
+        A, B, C = _random_conic(rng, ratio)
+        u = rng.uniform(-40.0, W + 40.0)
+        v = rng.uniform(-40.0, H + 40.0)
+        uh, vh = np.float32(u), np.float32(v)
+        ul, vl = np.float32(u - float(uh)), np.float32(v - float(vh))
+        if k % 5 == 0:           # large coordinates: the low word carries the fraction
+            uh, ul = np.float32(4096.0 + u), np.float32(0.0)
+            pxs = pxc + np.float32(4096.0)
+        else:
+            pxs = pxc
+        rec = np.array([uh, vh, ul, vl, A, B, C], np.float32)
+        x0 = 4096 // tw if k % 5 == 0 else 0
+        lo, hi = oracle.row_spans(rec, (x0, x0 + TX, 0, TY), 9.0, tw, th,
+                                  W + (4096 if k % 5 == 0 else 0), H)
+        dx, dy = (pxs - uh) - ul, (pyc - vh) - vl
+        q = (A * (dx * dx) + C * (dy * dy)) + np.float32(2.0) * (B * (dx * dy))
+        inside = q <= np.float32(9.0)
+        txs = tx + x0
+        assert not np.any(inside & ~((txs >= lo[ty]) & (txs < hi[ty]))), (k, ratio)
+        assert np.all(lo >= x0) and np.all(hi <= x0 + TX) and np.all(lo <= hi)
+        rho = abs(float(B)) / math.sqrt(float(A) * float(C))
+        if 1.0 - rho < 2.0 ** -16:
+            assert np.all(lo == x0) and np.all(hi == x0 + TX)
+        else:
+            hit = np.zeros((TY, TX), bool)
+            hit[ty[inside], tx[inside]] = True
+            exact += int(hit.sum())
+            span += int((hi - lo).sum())
+    assert exact > 500 and span <= 1.5 * exact
+
+
+def test_p6_row_span_circle_closed_form():
+    """A circle of radius 3 sigma: each row's columns are those with
+    |x - u| <= sqrt(9 s^2 (1 + 2^-18) - dy^2) for the nearest pixel-centre row."""
+    s2 = 4.0
+    A = C = np.float32(1.0 / s2)
+    u, v = 50.25, 30.75
+    tw, th, W, H = 4, 2, 128, 64
+    rec = np.array([u, v, 0.0, 0.0, A, 0.0, C], np.float32)
+    lo, hi = oracle.row_spans(rec, (0, W // tw, 0, H // th), 9.0, tw, th, W, H)
+    qe = 9.0 * (1.0 + 2.0 ** -18)
+    for t in range(H // th):
+        rows = np.arange(t * th, (t + 1) * th) + 0.5 - v
+        if np.all(np.abs(rows) > math.sqrt(qe * s2)) and (rows.min() > 0 or rows.max() < 0):
+            assert lo[t] == hi[t]
+            continue
+        dy = 0.0 if rows.min() <= 0.0 <= rows.max() else np.min(np.abs(rows))
+        half = math.sqrt(qe * s2 - dy * dy)
+        pl = math.ceil(u - half - 0.5)
+        pr = math.floor(u + half - 0.5)
+        assert (lo[t], hi[t]) == (max(pl, 0) // tw, min(pr, W - 1) // tw + 1), t
 
 
 # ---------------------------------------------------------------- P7 / P8

@@ -142,12 +142,30 @@ def test_batches_overlap_on_two_lanes():
         srv.close()
 
 
+def _image_bytes(pix, C):
+    return ((5 + C) * pix * 4 + 255) // 256 * 256
+
+
 def test_overflowing_batch_is_split():
+    # large footprints: many pairs per pixel, so the workspace rather than the
+    # images decides what fits
     sc = _scene()
+    sc.s = sc.s * np.float32(8.0)
+    sc.log_s = sc.log_s + np.float32(math.log(8.0))
     st = TrainState(sc)
     ref = _direct(st)
-    # room for one view's pairs at a time but not for two views together
-    srv = _server(st, arena_bytes=12 << 20, lanes=1)
+    surf = st.surfels()
+    n_all = st.project_and_sort(st.cams, "cap_batch", "_ws_batch")[1]
+    pix = sum(c.w * c.h for c in sc.cams)
+    img_all = _image_bytes(pix, sc.n_sem)
+    # room for half of the batch's pairs: the whole batch is admitted (its
+    # images take at most half the arena) but overflows, every view alone fits
+    arena = (img_all + B.workspace_size(surf, sc.cams, st.opts, n_all // 2)) // 256 * 256
+    assert 2 * img_all <= arena
+    for c in sc.cams:
+        n_v = st.project_and_sort([c], "cap_view", "_ws_view")[1]
+        assert _image_bytes(c.w * c.h, sc.n_sem) + B.workspace_size(surf, [c], st.opts, n_v) <= arena
+    srv = _server(st, arena_bytes=arena, lanes=1)
     try:
         outs = [_out(c, B.CH_RGB, sc.n_sem) for c in sc.cams]
         ts = [srv.submit(c, B.CH_RGB, o) for c, o in zip(sc.cams, outs)]
