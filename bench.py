@@ -355,7 +355,8 @@ def main():
         if profile:
             prof = st.rg.prof_read()
             st.rg.prof_enable(False)
-        return wall * 1e3 / steps, e0.elapsed_time(e1) / steps, prof
+        n = max(steps, 1)
+        return wall * 1e3 / n, e0.elapsed_time(e1) / n, prof
 
     # headline: the fused step, captured once as a graph and replayed; after
     # the first step the capacities are fitted to the measured counts (+10 %)

@@ -159,8 +159,8 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   int tb = 1;
   while ((int64_t(1) << tb) < l.total_tiles) ++tb;
   l.tile_bits = tb;
-  l.sort_blocks = std::max<int64_t>(1, (std::max<int64_t>(cap, l.total_tiles) + kSortTile - 1) /
-                                            kSortTile);
+  l.sort_blocks = std::max<int64_t>(1, (std::max<int64_t>(cap, l.total_tiles) + kSortTileMin - 1) /
+                                            kSortTileMin);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
   l.o_views = take(sizeof(ViewDev) * l.V);

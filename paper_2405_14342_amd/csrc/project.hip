@@ -1,9 +1,10 @@
 // Per-(view, surfel) culling and EWA projection (Eq. 5, supp. Sec. 2.1), tile
 // counts and visible counts per block, their scans, and the generic scan.
 //
-// One thread owns one surfel and walks all views of the batch, so the surfel's
-// parameters are read from HBM once per batch; per-view results land in
-// "slot" arrays indexed v * N + i.
+// One block per (range of 256 surfels, view): a thread projects one surfel
+// into one view (the other views' blocks of a surfel range find its
+// parameters in the cache); per-view results land in "slot" arrays indexed
+// v * N + i.
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -24,80 +25,73 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
   __shared__ uint32_t s_y0[kProjBlock];
   __shared__ uint32_t s_cnt[kProjBlock];
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  const int v = blockIdx.y;
   const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
   const bool valid = i < N;
-  float x = 0, y = 0, z = 0, qw = 1, qx = 0, qy = 0, qz = 0, sx = 1, sy = 1, al = 0;
+  (void)V;
+  if (valid && pack && v == 0) {
+    float* f = feat + (size_t)i * FS;
+    f[0] = prgb[i];
+    f[1] = prgb[N + i];
+    f[2] = prgb[2 * (size_t)N + i];
+    for (int c = 0; c < C; ++c) f[3 + c] = psem[(size_t)c * N + i];
+    f[3 + C] = pa[i];
+    for (int c = 4 + C; c < FS; ++c) f[c] = 0.0f;
+  }
+  const ViewDev& vw = views[v];
+  uint32_t nt = 0, rows = 0;
+  Proj p;
+  p.vis = false;
+  p.y0 = 0;
+  const size_t slot = (size_t)v * N + i;
   if (valid) {
-    x = px[i]; y = py[i]; z = pz[i];
-    qw = pq[i]; qx = pq[N + i]; qy = pq[2 * (size_t)N + i]; qz = pq[3 * (size_t)N + i];
-    sx = ps[i]; sy = ps[N + i];
-    al = pa[i];
-    if (pack) {
-      float* f = feat + (size_t)i * FS;
-      f[0] = prgb[i];
-      f[1] = prgb[N + i];
-      f[2] = prgb[2 * (size_t)N + i];
-      for (int c = 0; c < C; ++c) f[3 + c] = psem[(size_t)c * N + i];
-      f[3 + C] = al;
-      for (int c = 4 + C; c < FS; ++c) f[c] = 0.0f;
+    p = project_contract(vw, eps, qcut, tw, th, px[i], py[i], pz[i], pq[i], pq[N + i],
+                         pq[2 * (size_t)N + i], pq[3 * (size_t)N + i], ps[i], ps[N + i]);
+    if (p.vis) {
+      const Span sp = span_setup(p.uh, p.vh, p.ul, p.vl, p.A, p.B, p.C, qcut, p.x0, p.x1);
+      if (sp.full)
+        nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
+      else
+        rows = (uint32_t)(p.y1 - p.y0);
+      s_sp[threadIdx.x] = sp;
+      rec[2 * slot] = make_float4(p.uh, p.vh, p.ul, p.vl);
+      rec[2 * slot + 1] = make_float4(p.A, p.B, p.C, p.tz);
+      rect[slot] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.x1 << 16),
+                              (uint32_t)p.y0 | ((uint32_t)p.y1 << 16));
     }
   }
-  for (int v = 0; v < V; ++v) {
-    const ViewDev& vw = views[v];
-    uint32_t nt = 0, rows = 0;
-    Proj p;
-    p.vis = false;
-    p.y0 = 0;
-    const size_t slot = (size_t)v * N + i;
-    if (valid) {
-      p = project_contract(vw, eps, qcut, tw, th, x, y, z, qw, qx, qy, qz, sx, sy);
-      if (p.vis) {
-        const Span sp = span_setup(p.uh, p.vh, p.ul, p.vl, p.A, p.B, p.C, qcut, p.x0, p.x1);
-        if (sp.full)
-          nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
-        else
-          rows = (uint32_t)(p.y1 - p.y0);
-        s_sp[threadIdx.x] = sp;
-        rec[2 * slot] = make_float4(p.uh, p.vh, p.ul, p.vl);
-        rec[2 * slot + 1] = make_float4(p.A, p.B, p.C, p.tz);
-        rect[slot] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.x1 << 16),
-                                (uint32_t)p.y0 | ((uint32_t)p.y1 << 16));
-      }
+  // the wave's rectangle rows, spread evenly over its lanes: the row spans
+  // of one record are summed into its lane's counter (integer adds)
+  const uint32_t incl = wave_incl_scan(rows, lane);
+  const uint32_t R = __shfl(incl, 63, 64);
+  s_roff[threadIdx.x] = incl - rows;
+  s_y0[threadIdx.x] = (uint32_t)p.y0;
+  s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t k = (uint32_t)lane; k < R; k += 64) {
+    const int j = wbase + last_le(s_roff + wbase, 64, k);
+    int lo, hi;
+    span_row(s_sp[j], tw, th, vw.w, vw.h, (int)(s_y0[j] + (k - s_roff[j])), lo, hi);
+    if (hi > lo) atomicAdd(&s_cnt[j], (uint32_t)(hi - lo));
+  }
+  __syncthreads();
+  nt += s_cnt[threadIdx.x];
+  if (valid) cnt[slot] = nt;
+  uint32_t ws = wave_sum_u32(nt);
+  const uint32_t wvis = (uint32_t)__popcll(__ballot(nt != 0));
+  if (lane == 0) {
+    s_w[threadIdx.x >> 6] = ws;
+    s_v[threadIdx.x >> 6] = wvis;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0, tv = 0;
+    for (int w = 0; w < kProjBlock / 64; ++w) {
+      t += s_w[w];
+      tv += s_v[w];
     }
-    // the wave's rectangle rows, spread evenly over its lanes: the row spans
-    // of one record are summed into its lane's counter (integer adds)
-    const uint32_t incl = wave_incl_scan(rows, lane);
-    const uint32_t R = __shfl(incl, 63, 64);
-    s_roff[threadIdx.x] = incl - rows;
-    s_y0[threadIdx.x] = (uint32_t)p.y0;
-    s_cnt[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t k = (uint32_t)lane; k < R; k += 64) {
-      const int j = wbase + last_le(s_roff + wbase, 64, k);
-      int lo, hi;
-      span_row(s_sp[j], tw, th, vw.w, vw.h, (int)(s_y0[j] + (k - s_roff[j])), lo, hi);
-      if (hi > lo) atomicAdd(&s_cnt[j], (uint32_t)(hi - lo));
-    }
-    __syncthreads();
-    nt += s_cnt[threadIdx.x];
-    if (valid) cnt[slot] = nt;
-    uint32_t ws = wave_sum_u32(nt);
-    const uint32_t wvis = (uint32_t)__popcll(__ballot(nt != 0));
-    if ((threadIdx.x & 63) == 0) {
-      s_w[threadIdx.x >> 6] = ws;
-      s_v[threadIdx.x >> 6] = wvis;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t t = 0, tv = 0;
-      for (int w = 0; w < kProjBlock / 64; ++w) {
-        t += s_w[w];
-        tv += s_v[w];
-      }
-      part[(size_t)v * nb + blockIdx.x] = t;
-      partv[(size_t)v * nb + blockIdx.x] = tv;
-    }
-    __syncthreads();
+    part[(size_t)v * nb + blockIdx.x] = t;
+    partv[(size_t)v * nb + blockIdx.x] = tv;
   }
 }
 
@@ -298,7 +292,7 @@ void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
                     hipStream_t st) {
   fill_u32(at<uint32_t>(ws, L.o_misc), 0u, kMiscCount, st);
-  hipLaunchKernelGGL(k_project, dim3(L.nb), dim3(kProjBlock), 0, st,
+  hipLaunchKernelGGL(k_project, dim3(L.nb, L.V), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
                      L.th, s->x, s->y, s->z, s->q, s->s, s->alpha, s->rgb, s->sem, L.C, L.FS,
                      pack_feat ? 1 : 0, at<uint32_t>(ws, L.o_cnt), at<float4>(ws, L.o_rec),

@@ -13,8 +13,7 @@ namespace rogs {
 
 constexpr int kProjBlock = 256;     // threads per block of the per-surfel kernels
 constexpr int kSortBlock = 256;     // threads per radix-sort block
-constexpr int kSortIPT = 16;        // keys per thread per radix-sort block
-constexpr int kSortTile = kSortBlock * kSortIPT;
+constexpr int kSortTileMin = kSortBlock * 4;   // fewest keys per radix-sort block (sizes the tables)
 constexpr int kRadixMax = 512;     // largest radix of the sorts (9-bit digits)
 constexpr int kScanChunk = 4096;    // elements per block of the generic scan
 constexpr int kMaxViews = 4096;
@@ -49,7 +48,7 @@ struct Layout {
   int64_t total_pix = 0, total_tiles = 0, max_view_pix = 0, max_view_tiles = 0, cap = 0;
   int64_t scap = 0;            // visible-slot capacity (<= cap)
   int64_t slots = 0;           // V * N
-  int64_t sort_blocks = 0;     // ceil(cap / kSortTile)
+  int64_t sort_blocks = 0;     // ceil(max(cap, tiles) / kSortTileMin)
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
   size_t o_views, o_order, o_tkey, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;

@@ -5,11 +5,12 @@
 //
 // Stable LSD radix sort: per pass, per-block digit histograms (LDS atomics),
 // an exclusive scan of each digit's column of that table with the digit
-// totals (one block per digit), then a stable scatter.  In the scatter a block
-// owns kSortTile consecutive keys and starts each digit at the scan of the
-// totals plus its column entry; each of its four waves ranks a contiguous
-// quarter, 64 keys at a time, finding lanes with equal digits with one ballot
-// per digit bit, so ranks follow the input order.
+// totals (one block per digit), then a stable scatter.  A block owns
+// 256 * IPT consecutive keys (IPT = 4 for the slot sort, 8 for the pair sort,
+// so that even the slot sort fills the chip); the scatter starts each digit
+// at the scan of the totals plus its column entry, and each of its four waves
+// ranks a contiguous quarter, 64 keys at a time, finding lanes with equal
+// digits with one ballot per digit bit, so ranks follow the input order.
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -22,7 +23,7 @@ __device__ __forceinline__ uint32_t count_n(const uint32_t* n_dev, int64_t n_hos
   return (uint32_t)(n < cap ? n : cap);
 }
 
-template <typename K, int RB>
+template <typename K, int RB, int IPT>
 __global__ __launch_bounds__(kSortBlock) void k_hist(const K* __restrict__ keys,
                                                      const uint32_t* __restrict__ n_dev,
                                                      int64_t n_host, int64_t cap, int shift,
@@ -33,8 +34,8 @@ __global__ __launch_bounds__(kSortBlock) void k_hist(const K* __restrict__ keys,
   for (int d = threadIdx.x; d < R; d += kSortBlock) h[d] = 0;
   __syncthreads();
   const uint32_t n = count_n(n_dev, n_host, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int it = 0; it < kSortIPT; ++it) {
+  const int64_t base = (int64_t)blockIdx.x * (kSortBlock * IPT);
+  for (int it = 0; it < IPT; ++it) {
     int64_t idx = base + it * kSortBlock + threadIdx.x;
     if (idx < (int64_t)n) {
       uint32_t d = (uint32_t)(keys[idx] >> shift) & mask;
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kProjBlock) void k_colscan(uint32_t* __restrict__ h
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-template <typename K, int RB>
+template <typename K, int RB, int IPT>
 __global__ __launch_bounds__(kSortBlock) void k_scatter(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
   static_assert(kSortBlock == kProjBlock, "block scan width");
   constexpr int R = 1 << RB;
   constexpr int kWaves = kSortBlock / 64;
-  constexpr int kPerWave = kSortTile / kWaves;
+  constexpr int kPerWave = kSortBlock * IPT / kWaves;
   constexpr int kIters = kPerWave / 64;
   constexpr int kDig = (R + kSortBlock - 1) / kSortBlock;
   __shared__ uint32_t wcnt[kWaves][R];
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
   __shared__ uint32_t s_w[kSortBlock / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t n = count_n(n_dev, n_host, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * (kSortBlock * IPT);
   if (base >= (int64_t)n) return;
   for (int k = threadIdx.x; k < kWaves * R; k += kSortBlock) (&wcnt[0][0])[k] = 0;
   {
@@ -158,22 +159,24 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
 // Stable LSD sort of (keys, vals) over the low key_bits bits in as few passes
 // of at most RB bits as possible.  Returns 1 when the result is in the
 // alternate buffers, 0 when it is back in keys / vals.
-template <typename K, int RB>
+template <typename K, int RB, int IPT>
 int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, int64_t n_host,
                int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st) {
   const int passes = (key_bits + RB - 1) / RB;
   const int width = (key_bits + passes - 1) / passes;
   const int64_t n_grid = n_dev ? cap : n_host;
   if (n_grid <= 0 || passes == 0) return passes & 1;
-  const int64_t nblk = (n_grid + kSortTile - 1) / kSortTile;
+  static_assert(IPT >= 4 && kSortBlock * IPT >= kSortTileMin, "histogram table sizing");
+  constexpr int64_t kTile = kSortBlock * IPT;
+  const int64_t nblk = (n_grid + kTile - 1) / kTile;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * width;
     const int nbits = (key_bits - shift) < width ? (key_bits - shift) : width;
     const uint32_t mask = (1u << nbits) - 1u;
-    hipLaunchKernelGGL((k_hist<K, RB>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
+    hipLaunchKernelGGL((k_hist<K, RB, IPT>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
                        n_grid, cap, shift, mask, hist, nblk);
     hipLaunchKernelGGL(k_colscan, dim3(1u << RB), dim3(kProjBlock), 0, st, hist, nblk, histtmp);
-    hipLaunchKernelGGL((k_scatter<K, RB>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
+    hipLaunchKernelGGL((k_scatter<K, RB, IPT>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
                        k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp);
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;
@@ -434,7 +437,7 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
   unsigned long long* sk2 = at<unsigned long long>(ws, L.o_keys2);   // free until emission
   uint32_t* sv = at<uint32_t>(ws, L.o_sval);
   uint32_t* sv2 = at<uint32_t>(ws, L.o_vals2);
-  if (radix_sort<unsigned long long, 9>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
+  if (radix_sort<unsigned long long, 9, 4>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
                                         hist, histtmp, st)) {
     sv = sv2;
   }
@@ -462,7 +465,7 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
     }
   }
   // 5. stable sort of the pairs by tile
-  return radix_sort<uint32_t, 9>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
+  return radix_sort<uint32_t, 9, 8>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
                                  at<uint32_t>(ws, L.o_keys2), at<uint32_t>(ws, L.o_vals2), n_emit,
                                  p_grid, L.cap, L.tile_bits, hist, histtmp, st);
 }
@@ -486,7 +489,7 @@ void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {
   hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
                      at<const uint2>(ws, L.o_ranges), T, key, val);
   // one 4-bit pass: the result lands in the alternate buffers (key2, order)
-  radix_sort<uint32_t, 4>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
+  radix_sort<uint32_t, 4, 4>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
                           at<uint32_t>(ws, L.o_hist), at<uint32_t>(ws, L.o_histtmp), st);
 }
 
