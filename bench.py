@@ -36,7 +36,6 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) 
     N, V = st.N, st.V
     P, S, X, slots = stats["pairs"], stats["visible"], stats["pixels"], stats["slots"]
     FS = ((4 + C) + 3) // 4 * 4
-    NCH = 6 + C                       # fused per-pixel record: dL/dO (3+C), G.O, T, n_last
     K = 11 + C
     if kernel == "project":
         return N * (40 + 4 * FS) + slots * 4 + S * 40
@@ -50,17 +49,18 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) 
         return slots * 4 + S * 16 + s_passes * S * 32 + S * 24 + P * 12 + passes * P * 20
     if kernel == "ranges":
         return P * 8 + stats["tiles"] * 8
+    if kernel == "render_step":
+        # fused forward + loss + backward of a tile: targets (12 B colour,
+        # label, mask) in, the tile lists and the records of the listed slots
+        # in, one gradient record per pair and the per-tile loss partials out
+        return X * 14 + P * (8 + 4 * (10 + C)) + S * (32 + 4 * FS) + stats["tiles"] * 12
     if kernel == "render_fwd":
-        if fused:   # + targets (12 B colour, label, mask) in, the record out
-            return X * (14 + NCH * 4) + P * 8 + S * (32 + 4 * FS)
         return X * ((5 + C) * 4 + 8) + P * 8 + S * (32 + 4 * FS)
     if kernel == "loss":
         if fused:   # mask count + per-view sums of the per-tile partials
             return X * 1 + stats["tiles"] * 12
         return X * ((3 + C) * 4 + 14 + 1 + (5 + C) * 4)
     if kernel == "render_bwd":
-        if fused:
-            return X * NCH * 4 + P * (8 + 4 * (10 + C)) + S * (32 + 4 * FS)
         return X * ((5 + C) * 4 + (4 + C) * 4 + 8) + P * (8 + 4 * (10 + C)) + S * (32 + 4 * FS)
     if kernel == "proj_bwd":
         base = slots * 4 + S * 4 + P * 4 * (10 + C) + N * (40 + 4 * K)
@@ -85,6 +85,9 @@ def compositing_flops(kernel: str, n_eval: int, n_contrib: int, C: int, fused: b
         return 14.0 * n_eval + (9 + 2 * (4 + C)) * n_contrib
     if kernel == "render_bwd":
         return 14.0 * n_eval + (38 + 4 * (3 + C) + (0 if fused else 7)) * n_contrib
+    if kernel == "render_step":
+        return (compositing_flops("render_fwd", n_eval, n_contrib, C, True) +
+                compositing_flops("render_bwd", n_eval, n_contrib, C, True))
     return 0.0
 
 
@@ -403,13 +406,14 @@ def main():
     st.rg.render_fwd(st.surfels(), ws_b, st.out)
     n_eval, n_contrib = st.rg.debug_work(ws_b)
     flops = {k: compositing_flops(k, n_eval, n_contrib, C, fused=True)
-             for k in ("render_fwd", "render_bwd")}
+             for k in ("render_step",)}
     for k, f in flops.items():
         if k in kernels and kernels[k]["ms_per_step"] > 0:
             kernels[k]["alg_TFLOPs"] = round(f / (kernels[k]["ms_per_step"] * 1e-3) / 1e12, 2)
-    # roofline of the dominant single kernel (the compositing backward): it is
-    # bound by VALU issue (rocprofv3 counters), so it is priced in FLOP/s
-    dom = "render_bwd"
+    # roofline of the dominant single kernel (the fused step's compositing:
+    # forward, loss and backward of a tile), priced in FLOP/s against the
+    # non-packed FP32 VALU peak
+    dom = "render_step"
     dom_ms = prof[dom][0] / prof[dom][1]          # average duration of one launch
     per_launch = prof[dom][1] / args.steps
     dom_flops = flops[dom] / per_launch

@@ -72,8 +72,18 @@
  * The record keeps binary32 roundings: u_hi = f32(u), u_lo = f32(u - u_hi),
  * v_hi, v_lo likewise, A, B, C = f32(A), ..., t_z = f32(tz).
  *   sort key  = (global tile index << 32) | bit pattern of f32(tz), ties by id
+ * Tiles of a slot: in each rectangle row ty, the tiles [lo, hi) whose pixel
+ * columns the ellipse q <= q_cut * (1 + 2^-18 / (1 - rho)), rho = |B| /
+ * sqrt(A C), reaches over the row's pixel-centre rows (binary64 from the
+ * record, one rounding per step): a = (ty*tile_h + 0.5) - v, b = (min((ty +
+ * 1)*tile_h, h) - 0.5) - v clipped to +-dym, dym = sqrt((A*qe)/det), det =
+ * A*C - B*B; the extreme points dy* = +-B*sqrt(qe/(C*det)) clamped to [a, b];
+ * x = u + (-(B*dy*) -+ sqrt(max(0, A*qe - det*dy*^2)))/A; columns ceil(xl -
+ * 0.5) .. floor(xr - 0.5) clipped to the image; tiles by integer division,
+ * clipped to [x0, x1).  A conic with 1 - rho < 2^-16 or det <= 0 keeps the
+ * whole rectangle row.
  * Per pixel, in binary32: dx = ((px + 0.5) - u_hi) - u_lo, dy likewise,
- *   q32 = (A*(dx*dx) + C*(dy*dy)) + 2*(B*(dx*dy)); the pixel is touched iff
+ *   q32 = fma(dx, fma(A, dx, (2*B)*dy), (C*dy)*dy); the pixel is touched iff
  *   q32 <= q_cut.
  *
  * Values (Eq. 6): for touched pixels g = exp(-q/2), a = min(alpha*g,
@@ -501,8 +511,9 @@ ROGS_API int rogs_batch_stats(rogs_ctx* ctx, void* ws, int64_t* stats, void* str
  * (arrays of ROGS_PROF_GROUPS entries; n must be >= ROGS_PROF_GROUPS) since
  * the previous read, and resets them.  Group names: rogs_prof_name.  In
  * the fused step, group "fused_graph" times the whole graph launch (the
- * kernels inside a graph carry no events; ROGS_FUSED_EAGER times them). */
-#define ROGS_PROF_GROUPS 11
+ * kernels inside a graph carry no events; ROGS_FUSED_EAGER times them), and
+ * "render_step" its combined forward + loss + backward compositing. */
+#define ROGS_PROF_GROUPS 12
 ROGS_API int rogs_prof_enable(rogs_ctx* ctx, int32_t on);
 ROGS_API int rogs_prof_read(rogs_ctx* ctx, double* ms, int64_t* launches, int32_t n);
 ROGS_API const char* rogs_prof_name(int32_t group);

@@ -74,6 +74,7 @@ def _load():
         _lib.orc_adam.argtypes = [I64, P, P, P, P, D, D, D, D, I64]
         _lib.orc_num_threads.restype = I
         _lib.orc_row_spans.argtypes = [P, I, I, I, I, ctypes.c_float, I, I, I, I, P, P]
+        _lib.orc_q32.argtypes = [I, P, I, P, P, P]
         _lib.orc_smooth.argtypes = [I64, P, P, D, P]
         _lib.orc_smooth.restype = D
         _lib.orc_lidar_loss.argtypes = [I64, P, P, D, P]
@@ -365,3 +366,14 @@ def row_spans(rec7, rect, q_cut: float, tw: int, th: int, W: int, H: int):
     _load().orc_row_spans(_p(rec7), x0, x1, y0, y1, float(q_cut), int(tw), int(th), int(W), int(H),
                           _p(lo), _p(hi))
     return lo[:y1 - y0], hi[:y1 - y0]
+
+
+def q32(rec7, px, py):
+    """The binary32 per-pixel test value of records rec7 [n, 7] (u_hi v_hi
+    u_lo v_lo A B C) at integer pixels (px, py): array [n, npix]."""
+    rec7 = np.ascontiguousarray(np.atleast_2d(rec7)[:, :7], np.float32)
+    px = np.ascontiguousarray(px, np.int32).reshape(-1)
+    py = np.ascontiguousarray(py, np.int32).reshape(-1)
+    q = np.zeros((rec7.shape[0], px.size), np.float32)
+    _load().orc_q32(rec7.shape[0], _p(rec7), px.size, _p(px), _p(py), _p(q))
+    return q

@@ -249,11 +249,13 @@ Rec32 contract(const Cam& c, const Opts& o, float xf, float yf, float zf, float 
   return r;
 }
 
-// Per-pixel contribution test (binary32).
+// Per-pixel contribution test (binary32): q = dx (A dx + 2B dy) + C dy dy
+// with two fused multiply-adds, every other product rounded on its own.
 inline float q32(const Rec32& r, int px, int py) {
-  float dx = (((float)px + 0.5f) - r.uh) - r.ul;
-  float dy = (((float)py + 0.5f) - r.vh) - r.vl;
-  return (r.A * (dx * dx) + r.C * (dy * dy)) + 2.0f * (r.B * (dx * dy));
+  const float dx = (((float)px + 0.5f) - r.uh) - r.ul;
+  const float dy = (((float)py + 0.5f) - r.vh) - r.vl;
+  const float t = std::fmaf(r.A, dx, (2.0f * r.B) * dy);
+  return std::fmaf(dx, t, (r.C * dy) * dy);
 }
 
 inline uint32_t fbits(float f) {
@@ -604,6 +606,18 @@ Opts make_opts(const int* io, const float* fo) {
 }  // namespace
 
 extern "C" {
+
+// The per-pixel test value q32 of records rec7[n][7] (u_hi v_hi u_lo v_lo A B
+// C) at pixels (px[k], py[k]) of a W x H grid: q[n][npix].
+void orc_q32(int n, const float* rec7, int npix, const int32_t* px, const int32_t* py, float* q) {
+  for (int i = 0; i < n; ++i) {
+    Rec32 r{};
+    const float* f = rec7 + 7 * (size_t)i;
+    r.uh = f[0]; r.vh = f[1]; r.ul = f[2]; r.vl = f[3];
+    r.A = f[4]; r.B = f[5]; r.C = f[6];
+    for (int k = 0; k < npix; ++k) q[(size_t)i * npix + k] = q32(r, px[k], py[k]);
+  }
+}
 
 // Row spans of one binary32 record (u_hi v_hi u_lo v_lo A B C) over the
 // rectangle rows y0..y1-1: lo[k], hi[k] for row y0 + k.

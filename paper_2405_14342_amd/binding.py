@@ -34,7 +34,7 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_elev_scratch_bytes", "rogs_elev_loss", "rogs_lidar_targets",
             "rogs_meshgrid_scratch_bytes", "rogs_meshgrid_layout", "rogs_bev_camera",
             "rogs_bev_workspace_size", "rogs_bev_export")
-PROF_GROUPS = 11
+PROF_GROUPS = 12
 FUSED_EAGER = 4
 
 

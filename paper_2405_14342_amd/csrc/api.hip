@@ -196,8 +196,6 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_hist = take(4 * (size_t)kRadixMax * l.sort_blocks);
   l.o_histtmp = take(4 * (size_t)kRadixMax);  // digit totals of a sort pass
   if (fused) {
-    const size_t nch = (size_t)(6 + l.C), tp = (size_t)tw * th;
-    l.o_tm = take(4 * (size_t)l.total_tiles * nch * tp);
     l.o_tpart = take(4 * 3 * (size_t)l.total_tiles);
     l.o_dzr = take(4 * (size_t)l.N);                          // grid-side dL/dz
     l.o_regpart = take(4 * (size_t)rogs::elev_reg_blocks(l.N));
@@ -276,7 +274,7 @@ int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws
 const char* kProfNames[ROGS_PROF_GROUPS] = {"project",    "scan",       "emit",
                                             "sort",       "ranges",     "render_fwd",
                                             "loss",       "render_bwd", "proj_bwd",
-                                            "adam",       "fused_graph"};
+                                            "adam",       "fused_graph", "render_step"};
 
 hipEvent_t prof_event(rogs_ctx* c) {
   if (c->ev_used == c->ev_pool.size()) {
@@ -784,15 +782,11 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
   fl.lam_c = tg->lambda_c;
   fl.lam_s = tg->lambda_s;
   fl.scale = tg->view_scale;
-  fl.tm = rogs::at<float>(ws, L.o_tm);
   fl.part = rogs::at<float>(ws, L.o_tpart);
-  prof_begin(c, 5, st);
-  int r = rogs::launch_render_fwd_fused(L, ws, fl, st);
+  prof_begin(c, 11, st);
+  int r = rogs::launch_render_step(L, ws, fl, st);
   prof_end(c, st);
   if (r != 0) return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
-  prof_begin(c, 7, st);
-  rogs::launch_render_bwd_fused(L, ws, st);
-  prof_end(c, st);
   prof_begin(c, 6, st);
   rogs::launch_loss_tiles(L, ws, t->d_exposure, st);
   prof_end(c, st);

@@ -55,7 +55,7 @@ struct Layout {
   size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
   size_t o_hist, o_histtmp, o_misc, o_lpart, o_mcount;
-  size_t o_tm = 0, o_tpart = 0, o_state = 0;    // fused path only (0 = absent)
+  size_t o_tpart = 0, o_state = 0;    // fused path only (0 = absent)
   size_t total = 0;
 };
 
@@ -271,17 +271,15 @@ __device__ inline void span_row(const Span& s, int tw, int th, int W, int H, int
   }
 }
 
-// Per-pixel contribution test of the contract (binary32, no contraction).
-// dx = ((px + 0.5) - u_hi) - u_lo and dy likewise are formed by the caller.
-__device__ __forceinline__ float pixel_q32(float A, float B, float C, float dx, float dy) {
+// Per-pixel contribution test of the contract (binary32):
+// q = fma(dx, fma(A, dx, B2 dy), (C dy) dy) with B2 = 2B (exact), each
+// product and fma rounded once, nothing else contracted.  dx = ((px + 0.5) -
+// u_hi) - u_lo and dy likewise are formed by the caller.
+__device__ __forceinline__ float pixel_q32(float A, float B2, float C, float dx, float dy) {
 #pragma clang fp contract(off)
-  float t0 = dx * dx;
-  float t1 = dy * dy;
-  float t2 = dx * dy;
-  float a = A * t0;
-  float c = C * t1;
-  float b = B * t2;
-  return (a + c) + 2.0f * b;
+  const float t = __builtin_fmaf(A, dx, B2 * dy);
+  const float c = (C * dy) * dy;
+  return __builtin_fmaf(dx, t, c);
 }
 
 // Footprint weight g = exp(-q/2) = 2^(q * (-log2(e)/2)): one multiply and the
@@ -291,8 +289,8 @@ __device__ __forceinline__ float gauss_weight(float q) {
   return __builtin_amdgcn_exp2f(q * -0.72134752044448170f);
 }
 
-// Opacity clamp alpha' = min(alpha g, alpha_max) as a compare and select.
-__device__ __forceinline__ float clamp_alpha(float ag, float amax) { return ag > amax ? amax : ag; }
+// Opacity clamp alpha' = min(alpha g, alpha_max) (neither operand is NaN).
+__device__ __forceinline__ float clamp_alpha(float ag, float amax) { return fminf(ag, amax); }
 
 __device__ __forceinline__ float pixel_offset(float pc, float hi, float lo) {
 #pragma clang fp contract(off)
@@ -454,17 +452,21 @@ __device__ __forceinline__ void pixel_loss(const float* o, const float* t, int l
   float mx = -INFINITY;
 #pragma unroll
   for (int c = 0; c < C; ++c) mx = fmaxf(mx, o[3 + c]);
+  // softmax with the hardware base-2 exponential and logarithm and the
+  // hardware reciprocal: every exponent is <= 0 and 1 <= se <= C, where each
+  // is within a few ulp (relative 1e-6 at the worst exponent that matters)
+  constexpr float kLog2e = 1.44269504088896341f, kLn2 = 0.69314718055994531f;
   float se = 0.0f;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    sv[c] = expf(o[3 + c] - mx);
+    sv[c] = __builtin_amdgcn_exp2f((o[3 + c] - mx) * kLog2e);
     se += sv[c];
   }
   float olb = 0.0f;
 #pragma unroll
   for (int c = 0; c < C; ++c) olb = (c == label) ? o[3 + c] : olb;
-  l += ws * ((mx + logf(se)) - olb);
-  const float inv = 1.0f / se;
+  l += ws * ((mx + __builtin_amdgcn_logf(se) * kLn2) - olb);
+  const float inv = __builtin_amdgcn_rcpf(se);
 #pragma unroll
   for (int c = 0; c < C; ++c) g[3 + c] = ws * (sv[c] * inv - ((c == label) ? 1.0f : 0.0f));
 }
@@ -495,7 +497,6 @@ struct FusedLoss {
   const float* expo;       // [V][2]
   const uint32_t* mcount;  // |M_v|
   float lam_c, lam_s, scale;
-  float* tm;               // tile-major per-pixel records: dL/dO (3 + C), G.O, T, n_last
   float* part;             // per-tile (loss, dL/da, dL/db)
 };
 
@@ -548,8 +549,7 @@ void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets
                  float* loss_out, float* d_exp, hipStream_t st);
 int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels* s, const float* out,
                       const float* G, hipStream_t st);
-int launch_render_fwd_fused(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st);
-int launch_render_bwd_fused(const Layout& L, void* ws, hipStream_t st);
+int launch_render_step(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st);
 // Per-slot sums of the per-pair gradient records (before the projection adjoint).
 void launch_slot_sums(const Layout& L, void* ws, hipStream_t st);
 void launch_proj_bwd(const Layout& L, void* ws, const rogs_surfels* s, float* grads,

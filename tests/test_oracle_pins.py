@@ -283,9 +283,7 @@ def test_p6_lists_cover_every_contributing_pixel(which, tw, th):
     for i in sel:
         if not vis[i]:
             continue
-        uh, vh, ul, vl, A, B, C = (np.float32(t) for t in rec[i, :7])
-        dx, dy = (pxc - uh) - ul, (pyc - vh) - vl
-        q = (A * (dx * dx) + C * (dy * dy)) + np.float32(2.0) * (B * (dx * dy))
+        q = oracle.q32(rec[i], px.reshape(-1), py.reshape(-1))[0]
         inside = q <= np.float32(9.0)
         x0, x1, y0, y1 = rect[i]
         cov = (tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)
@@ -331,17 +329,14 @@ def test_p6_row_spans_cover_extreme_ellipses(tw, th):
         v = rng.uniform(-40.0, H + 40.0)
         uh, vh = np.float32(u), np.float32(v)
         ul, vl = np.float32(u - float(uh)), np.float32(v - float(vh))
-        if k % 5 == 0:           # large coordinates: the low word carries the fraction
-            uh, ul = np.float32(4096.0 + u), np.float32(0.0)
-            pxs = pxc + np.float32(4096.0)
-        else:
-            pxs = pxc
+        shift = 4096 if k % 5 == 0 else 0
+        if shift:                # large coordinates: the low word carries the fraction
+            uh = np.float32(shift + u)
+            ul = np.float32(shift + u - float(uh))
         rec = np.array([uh, vh, ul, vl, A, B, C], np.float32)
-        x0 = 4096 // tw if k % 5 == 0 else 0
-        lo, hi = oracle.row_spans(rec, (x0, x0 + TX, 0, TY), 9.0, tw, th,
-                                  W + (4096 if k % 5 == 0 else 0), H)
-        dx, dy = (pxs - uh) - ul, (pyc - vh) - vl
-        q = (A * (dx * dx) + C * (dy * dy)) + np.float32(2.0) * (B * (dx * dy))
+        x0 = shift // tw
+        lo, hi = oracle.row_spans(rec, (x0, x0 + TX, 0, TY), 9.0, tw, th, W + shift, H)
+        q = oracle.q32(rec, px.reshape(-1) + shift, py.reshape(-1))[0]
         inside = q <= np.float32(9.0)
         txs = tx + x0
         assert not np.any(inside & ~((txs >= lo[ty]) & (txs < hi[ty]))), (k, ratio)
@@ -355,6 +350,35 @@ def test_p6_row_spans_cover_extreme_ellipses(tw, th):
             exact += int(hit.sum())
             span += int((hi - lo).sum())
     assert exact > 500 and span <= 1.5 * exact
+
+
+def test_p6_q32_rounding_bound():
+    """The binary32 test value against the same quadratic form in binary64 of
+    the binary32 record: within 2^-20.3 q / (1 - rho) (the bound the row
+    spans' inflation rests on), including nearly degenerate conics and
+    centres far from the origin."""
+    rng = np.random.default_rng(23)
+    worst = 0.0
+    for k in range(400):
+        ratio = math.exp(rng.uniform(0.0, math.log(3000.0)))
+        A, B, C = _random_conic(rng, ratio)
+        u = rng.uniform(0.0, 2000.0)
+        v = rng.uniform(0.0, 1000.0)
+        uh, vh = np.float32(u), np.float32(v)
+        ul, vl = np.float32(u - float(uh)), np.float32(v - float(vh))
+        rec = np.array([uh, vh, ul, vl, A, B, C], np.float32)
+        px = rng.integers(int(u) - 30, int(u) + 30, 500)
+        py = rng.integers(int(v) - 30, int(v) + 30, 500)
+        q = oracle.q32(rec, px, py)[0].astype(np.float64)
+        dx = (px + 0.5) - (float(uh) + float(ul))
+        dy = (py + 0.5) - (float(vh) + float(vl))
+        A64, B64, C64 = float(A), float(B), float(C)
+        q64 = A64 * dx * dx + 2.0 * B64 * dx * dy + C64 * dy * dy
+        rho = abs(B64) / math.sqrt(A64 * C64)
+        bound = 2.0 ** -20.3 * np.abs(q64) / (1.0 - rho) + 1e-30
+        assert np.all(np.abs(q - q64) <= bound), k
+        worst = max(worst, float(np.max(np.abs(q - q64) / bound)))
+    assert worst > 0.0
 
 
 def test_p6_row_span_circle_closed_form():
