@@ -163,10 +163,13 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
                                             kSortTileMin);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
-  l.o_views = take(sizeof(ViewDev) * l.V);
+  // the view table and the loss first-block table are contiguous, as in the
+  // host stage, so one copy uploads both
+  l.o_views = take(sizeof(ViewDev) * l.V + sizeof(int64_t) * (l.V + 1) +
+                   sizeof(float) * 3 * loss_blocks);
+  l.o_lpart = l.o_views + sizeof(ViewDev) * l.V;
   l.o_misc = take(sizeof(uint32_t) * kMiscCount);
   l.o_mcount = take(sizeof(uint32_t) * 2 * l.V);   // mask counts, then per-view loss sums
-  l.o_lpart = take(sizeof(int64_t) * (l.V + 1) + sizeof(float) * 3 * loss_blocks);
   l.o_cnt = take(4 * (size_t)l.slots);
   l.o_rec = take(32 * (size_t)l.slots);
   l.o_rect = take(8 * (size_t)l.slots);
@@ -200,6 +203,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
     l.o_dzr = take(4 * (size_t)l.N);                          // grid-side dL/dz
     l.o_regpart = take(4 * (size_t)rogs::elev_reg_blocks(l.N));
     l.o_regtot = take(4);
+    l.o_status = take(sizeof(uint32_t) * 4 + sizeof(StepState));   // misc[0..3] + step state
   }
   l.total = o;
   *L = l;
@@ -261,10 +265,8 @@ int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws
     c->stage_bytes = need;
   }
   fill_view_table(L, cams, c->stage);
-  const char* base = static_cast<const char*>(c->stage);
-  hipError_t e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), base, vbytes, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), base + vbytes, fbytes, hipMemcpyHostToDevice, st);
+  hipError_t e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), c->stage, vbytes + fbytes,
+                                hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventRecord(c->stage_evt, st);
   if (e != hipSuccess) return hip_fail(c, e, "view table upload");
   c->stage_pending = true;
@@ -787,10 +789,11 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
   int r = rogs::launch_render_step(L, ws, fl, st);
   prof_end(c, st);
   if (r != 0) return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
-  prof_begin(c, 6, st);
-  rogs::launch_loss_tiles(L, ws, t->d_exposure, st);
-  prof_end(c, st);
   rogs::AdamArgs aa = fused_adam_args(o, L, ws, t->step_state);
+  prof_begin(c, 6, st);
+  // per-view loss sums, dL/d(a, b) and the exposure's Adam step
+  rogs::launch_loss_tiles(L, ws, t->d_exposure, t->exposure, t->m_exp, t->v_exp, aa, st);
+  prof_end(c, st);
   prof_begin(c, 8, st);
   // grid-side terms (Eq. 10, 11) from the heights before the update
   const bool reg = tg->nbr || tg->zbar;
@@ -798,9 +801,9 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
     rogs::launch_elev_reg(L.N, t->params, tg->nbr, tg->lambda_smooth, tg->zbar, tg->lambda_z,
                           rogs::at<float>(ws, L.o_dzr), nullptr, rogs::at<float>(ws, L.o_regpart),
                           rogs::at<float>(ws, L.o_regtot), false, st);
-  rogs::launch_slot_sums(L, ws, st);
+  rogs::launch_slot_sums(L, ws, st, false);      // misc's long-slot count is still zero
   rogs::launch_proj_bwd_adam(L, ws, t->x, t->y, t->params, t->m, t->v, t->s_act, t->alpha_act,
-                             t->grads, aa, t->exposure, t->d_exposure, t->m_exp, t->v_exp,
+                             t->grads, aa, nullptr, nullptr, nullptr, nullptr,
                              reg ? rogs::at<const float>(ws, L.o_dzr) : nullptr, st);
   prof_end(c, st);
   rogs::launch_step_end(L, ws, static_cast<rogs::StepState*>(t->step_state), aa,
@@ -904,11 +907,8 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
   fill_view_table(L, cams, F.stage[p]);
   {
     const size_t vbytes = sizeof(ViewDev) * L.V, fbytes = sizeof(int64_t) * (L.V + 1);
-    const char* stage = static_cast<const char*>(F.stage[p]);
-    e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), stage, vbytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(rogs::at<void>(ws, L.o_lpart), stage + vbytes, fbytes,
-                         hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), F.stage[p], vbytes + fbytes,
+                       hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused: camera table");
   }
   if (eager) {
@@ -963,10 +963,9 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
   F.opt = *o;
   F.opts = *opts;
   F.sizes = sizes;
-  e = hipMemcpyAsync(F.status[p], rogs::at<void>(ws, F.L.o_misc), 16, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(reinterpret_cast<char*>(F.status[p]) + 16, t->step_state,
-                       sizeof(rogs::StepState), hipMemcpyDeviceToHost, st);
+  // the step's last kernel left misc[0..3] and the step state side by side
+  e = hipMemcpyAsync(F.status[p], rogs::at<void>(ws, F.L.o_status),
+                     16 + sizeof(rogs::StepState), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipEventRecord(F.done[p], st);
   if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused: status");
   F.pending[p] = true;

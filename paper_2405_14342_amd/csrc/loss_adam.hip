@@ -560,15 +560,13 @@ __global__ __launch_bounds__(256) void k_adam(int N, float* __restrict__ P,
 
 // Adam on a plain array (the per-view exposure (a, b)).  With a step state
 // the step comes from the device and an overflow skips the update.
-__global__ void k_adam_plain(int n, float* __restrict__ P, const float* __restrict__ Gd,
-                             float* __restrict__ M, float* __restrict__ Vv, AdamArgs aa) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void adam_plain_elem(int i, float g, float* __restrict__ P,
+                                                float* __restrict__ M, float* __restrict__ Vv,
+                                                const AdamArgs& aa) {
   if (aa.misc && aa.misc[kMiscOverflow]) return;
   const int64_t step = aa.state ? aa.state->step + 1 : aa.step;
   float bc1, bc2s;
   adam_bias(aa.b1, aa.b2, step, bc1, bc2s);
-  const float g = Gd[i];
   const float m = aa.b1 * M[i] + (1.0f - aa.b1) * g;
   const float v = aa.b2 * Vv[i] + (1.0f - aa.b2) * g * g;
   M[i] = m;
@@ -576,13 +574,19 @@ __global__ void k_adam_plain(int n, float* __restrict__ P, const float* __restri
   P[i] -= (aa.lr.exposure / bc1) * (m / (sqrtf(v) / bc2s + aa.eps));
 }
 
-// Per-view sums of the per-tile loss partials of the fused forward: fixed
-// assignment of tiles to threads and a fixed tree (deterministic).  dL/d(a,b)
-// are overwritten.
-// Per-view sums of the fused forward's per-tile partials (loss, dL/da,
-// dL/db) in two fixed-order stages: block (c, v) adds tiles c * kTileChunk ...
-// of view v (8 per thread, then a fixed tree), and one wave per view adds the
-// chunks in order.  The result does not depend on scheduling.
+__global__ void k_adam_plain(int n, float* __restrict__ P, const float* __restrict__ Gd,
+                             float* __restrict__ M, float* __restrict__ Vv, AdamArgs aa) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  adam_plain_elem(i, Gd[i], P, M, Vv, aa);
+}
+
+// Per-view sums of the fused step's per-tile partials (loss, dL/da, dL/db)
+// in two fixed-order stages: block (c, v) adds tiles c * kTileChunk ... of
+// view v (8 per thread, then a fixed tree), and one wave per view adds the
+// chunks in order (lane-strided, then a fixed tree), overwrites dL/d(a, b)
+// and applies Adam to the view's exposure (a, b).  The result does not
+// depend on scheduling.
 constexpr int kTileChunk = 8 * 256;
 
 __global__ __launch_bounds__(256) void k_loss_tiles(const ViewDev* __restrict__ views, int V,
@@ -621,7 +625,10 @@ __global__ __launch_bounds__(256) void k_loss_tiles(const ViewDev* __restrict__ 
 
 __global__ __launch_bounds__(64) void k_loss_chunks(const float* __restrict__ cpart, int nchunk,
                                                     float* __restrict__ per_view,
-                                                    float* __restrict__ d_exp) {
+                                                    float* __restrict__ d_exp,
+                                                    float* __restrict__ expo,
+                                                    float* __restrict__ m_exp,
+                                                    float* __restrict__ v_exp, AdamArgs aa) {
   const int v = blockIdx.x, lane = threadIdx.x;
   float l = 0.0f, a = 0.0f, b = 0.0f;
   for (int c = lane; c < nchunk; c += 64) {
@@ -640,24 +647,32 @@ __global__ __launch_bounds__(64) void k_loss_chunks(const float* __restrict__ cp
       d_exp[2 * v + 1] = b;
     }
   }
+  if (expo && lane < 2) adam_plain_elem(2 * v + lane, lane == 0 ? a : b, expo, m_exp, v_exp, aa);
 }
 
-// Closes a fused step: counts it (or its skip on overflow) and keeps its loss.
+// Closes a fused step: counts it (or its skip on overflow) and keeps its loss;
+// then copies misc[0..3] and the step state side by side into status (for
+// one read-back).
 __global__ void k_step_end(StepState* __restrict__ st, const uint32_t* __restrict__ misc,
                            const float* __restrict__ per_view, int V,
-                           const float* __restrict__ reg_total, AdamArgs aa) {
+                           const float* __restrict__ reg_total, AdamArgs aa,
+                           uint32_t* __restrict__ status) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (misc[kMiscOverflow]) {
     st->skipped += 1;
-    return;
+  } else {
+    float t = 0.0f;
+    for (int v = 0; v < V; ++v) t += per_view[v];
+    if (reg_total) t += *reg_total;
+    const int64_t step = st->step + 1;
+    st->lr_z = z_rate(aa, step);
+    st->loss = t;
+    st->step = step;
   }
-  float t = 0.0f;
-  for (int v = 0; v < V; ++v) t += per_view[v];
-  if (reg_total) t += *reg_total;
-  const int64_t step = st->step + 1;
-  st->lr_z = z_rate(aa, step);
-  st->loss = t;
-  st->step = step;
+  if (status) {
+    for (int k = 0; k < 4; ++k) status[k] = misc[k];
+    *reinterpret_cast<StepState*>(status + 4) = *st;
+  }
 }
 
 }  // namespace
@@ -765,11 +780,11 @@ void launch_proj_bwd_adam(const Layout& L, void* ws, const float* x, const float
 
 namespace {
 template <int C>
-void slot_sums_launch(const Layout& L, void* ws, hipStream_t st) {
+void slot_sums_launch(const Layout& L, void* ws, hipStream_t st, bool clear) {
   uint32_t* misc = at<uint32_t>(ws, L.o_misc);
   const int64_t s_grid = L.scap;
   if (s_grid <= 0) return;
-  fill_u32(misc + kMiscLong, 0u, 1, st);
+  if (clear) fill_u32(misc + kMiscLong, 0u, 1, st);
   constexpr int Q = (((10 + C) + 3) & ~3) / 4;
   hipLaunchKernelGGL((k_slot_sums<C>), dim3((unsigned)((s_grid * Q + 255) / 256)), dim3(256), 0, st,
                      misc, L.scap, L.cap, at<const uint32_t>(ws, L.o_scnt),
@@ -782,11 +797,12 @@ void slot_sums_launch(const Layout& L, void* ws, hipStream_t st) {
 }
 }  // namespace
 
-void launch_slot_sums(const Layout& L, void* ws, hipStream_t st) {
-  ROGS_SEM_SWITCH(L.C, (slot_sums_launch<KC>(L, ws, st)));
+void launch_slot_sums(const Layout& L, void* ws, hipStream_t st, bool clear) {
+  ROGS_SEM_SWITCH(L.C, (slot_sums_launch<KC>(L, ws, st, clear)));
 }
 
-void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st) {
+void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, float* expo, float* m_exp,
+                       float* v_exp, const AdamArgs& aa, hipStream_t st) {
   float* per_view = reinterpret_cast<float*>(at<uint32_t>(ws, L.o_mcount) + L.V);
   // the plain loss's block partials are unused on the fused path: chunk sums go there
   float* cpart = at<float>(ws, L.o_lpart) + 2 * (L.V + 1);
@@ -795,7 +811,7 @@ void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st) 
                      at<const ViewDev>(ws, L.o_views), L.V, L.total_tiles,
                      at<const float>(ws, L.o_tpart), nchunk, cpart);
   hipLaunchKernelGGL(k_loss_chunks, dim3((unsigned)L.V), dim3(64), 0, st, cpart, nchunk, per_view,
-                     d_exp);
+                     d_exp, expo, m_exp, v_exp, aa);
 }
 
 void launch_mask_count(const Layout& L, void* ws, const uint8_t* mask, hipStream_t st) {
@@ -811,7 +827,7 @@ void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs
                      const float* reg_total, hipStream_t st) {
   const float* per_view = reinterpret_cast<const float*>(at<uint32_t>(ws, L.o_mcount) + L.V);
   hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, state, at<const uint32_t>(ws, L.o_misc),
-                     per_view, L.V, reg_total, aa);
+                     per_view, L.V, reg_total, aa, L.o_status ? at<uint32_t>(ws, L.o_status) : nullptr);
 }
 
 }  // namespace rogs

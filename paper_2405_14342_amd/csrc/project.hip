@@ -200,13 +200,10 @@ constexpr int kSmallChunk = 1024 * 8;
 
 __device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
 
-__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_t* out,
-                                                     int64_t n_cap,
-                                                     const uint32_t* __restrict__ n_dev,
-                                                     uint32_t* __restrict__ total) {
+__device__ __forceinline__ void block_scan_small(const uint32_t* in, uint32_t* out, int64_t n,
+                                                 uint32_t* __restrict__ total) {
   __shared__ uint32_t s[kSmallChunk + kSmallChunk / 32];
   __shared__ uint32_t s_w[16];
-  const int64_t n = scan_count(n_dev, n_cap);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   uint32_t carry = 0;
   for (int64_t c0 = 0; c0 < n; c0 += kSmallChunk) {
@@ -240,6 +237,27 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_
     __syncthreads();
   }
   if (t == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_t* out,
+                                                     int64_t n_cap,
+                                                     const uint32_t* __restrict__ n_dev,
+                                                     uint32_t* __restrict__ total) {
+  block_scan_small(in, out, scan_count(n_dev, n_cap), total);
+}
+
+// Both per-block count tables of the projection (pairs, visible slots) in one
+// launch, one block each; the last block sets the overflow flag.
+__global__ __launch_bounds__(1024) void k_scan_part(uint32_t* part, uint32_t* partv, int64_t n,
+                                                    uint32_t* __restrict__ misc, int64_t cap,
+                                                    int64_t scap) {
+  uint32_t* a = blockIdx.x == 0 ? part : partv;
+  block_scan_small(a, a, n, misc + (blockIdx.x == 0 ? kMiscPairs : kMiscVisible));
+  if (last_block(misc + kMiscTicketScan) && threadIdx.x == 0) {
+    const uint32_t pairs = __atomic_load_n(misc + kMiscPairs, __ATOMIC_RELAXED);
+    const uint32_t vis = __atomic_load_n(misc + kMiscVisible, __ATOMIC_RELAXED);
+    misc[kMiscOverflow] = ((int64_t)pairs > cap || (int64_t)vis > scap) ? 1u : 0u;
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
@@ -302,6 +320,11 @@ void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_
 
 void launch_scan_part(const Layout& L, void* ws, hipStream_t st) {
   uint32_t* misc = at<uint32_t>(ws, L.o_misc);
+  if ((int64_t)L.V * L.nb <= kSmallScan) {
+    hipLaunchKernelGGL(k_scan_part, dim3(2), dim3(1024), 0, st, at<uint32_t>(ws, L.o_part),
+                       at<uint32_t>(ws, L.o_partv), (int64_t)L.V * L.nb, misc, L.cap, L.scap);
+    return;
+  }
   scan_u32(at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_part), (int64_t)L.V * L.nb,
            misc + kMiscPairs, at<uint32_t>(ws, L.o_parttmp), st);
   scan_u32(at<uint32_t>(ws, L.o_partv), at<uint32_t>(ws, L.o_partv), (int64_t)L.V * L.nb,

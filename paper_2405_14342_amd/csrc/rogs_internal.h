@@ -55,7 +55,7 @@ struct Layout {
   size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
   size_t o_hist, o_histtmp, o_misc, o_lpart, o_mcount;
-  size_t o_tpart = 0, o_state = 0;    // fused path only (0 = absent)
+  size_t o_tpart = 0, o_status = 0;   // fused path only (0 = absent)
   size_t total = 0;
 };
 
@@ -65,9 +65,30 @@ struct Layout {
 // the slots that fit the slot capacity)
 enum MiscSlot {
   kMiscPairs = 0, kMiscOverflow = 1, kMiscVisible = 2, kMiscLong = 3, kMiscEmit = 4,
+  kMiscTicketScan = 5,   // last-block ticket of the count-table scan
   kMiscWork = 8,   // two 64-bit work counters (words 8-11)
   kMiscCount = 16
 };
+
+// Last-block election for a grid-wide tail: each block calls it once, after
+// writing its partial results, from every thread; it returns true in exactly
+// one block, the last to arrive, which then sees every block's writes.  The
+// ticket word must be zero before the launch and is zero again afterwards.
+__device__ __forceinline__ bool last_block(uint32_t* ticket) {
+  __shared__ uint32_t s_last;
+  __threadfence();                     // this block's results, visible device-wide
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const uint32_t n = gridDim.x * gridDim.y;
+    const uint32_t t = atomicAdd(ticket, 1u);
+    s_last = (t == n - 1u) ? 1u : 0u;
+    if (t == n - 1u) atomicExch(ticket, 0u);
+  }
+  __syncthreads();
+  const bool last = s_last != 0u;
+  if (last) __threadfence();           // acquire the other blocks' results
+  return last;
+}
 
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
                 const rogs_render_opts* opts, int64_t cap, int64_t scap, Layout* L,
@@ -551,7 +572,10 @@ int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels* s, const fl
                       const float* G, hipStream_t st);
 int launch_render_step(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st);
 // Per-slot sums of the per-pair gradient records (before the projection adjoint).
-void launch_slot_sums(const Layout& L, void* ws, hipStream_t st);
+// Sums each visible slot's per-pair gradient records.  clear = reset the
+// long-slot count first (false only where the projection's counter reset is
+// known to be the last write to it).
+void launch_slot_sums(const Layout& L, void* ws, hipStream_t st, bool clear = true);
 void launch_proj_bwd(const Layout& L, void* ws, const rogs_surfels* s, float* grads,
                      bool accumulate, hipStream_t st);
 void launch_adam(int n, int C, float* params, const float* grads, float* m, float* v,
@@ -567,7 +591,8 @@ void launch_proj_bwd_adam(const Layout& L, void* ws, const float* x, const float
                           const AdamArgs& aa, float* expo, const float* dexpo, float* me,
                           float* ve, const float* dzr, hipStream_t st);
 // Fused: per-view loss and dL/d(a, b) (overwritten) from the per-tile partials.
-void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, hipStream_t st);
+void launch_loss_tiles(const Layout& L, void* ws, float* d_exp, float* expo, float* m_exp,
+                       float* v_exp, const AdamArgs& aa, hipStream_t st);
 void launch_mask_count(const Layout& L, void* ws, const uint8_t* mask, hipStream_t st);
 void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs& aa,
                      const float* reg_total, hipStream_t st);
@@ -577,6 +602,7 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uin
 // Same with the count read on the device (at most n_cap).
 void scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
                   uint32_t* tmp, hipStream_t st);
+
 size_t scan_tmp_words(int64_t n);
 // Stores msg as the context's last error and returns code.
 int ctx_fail(rogs_ctx* c, int code, const std::string& msg);
