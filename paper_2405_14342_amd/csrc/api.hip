@@ -173,6 +173,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_cnt = take(4 * (size_t)l.slots);
   l.o_rec = take(32 * (size_t)l.slots);
   l.o_rect = take(8 * (size_t)l.slots);
+  l.o_rspan = take(2 * kSpanRows * (size_t)l.slots);
   l.o_feat = take(4 * (size_t)l.N * l.FS);
   l.o_part = take(4 * (size_t)l.V * l.nb);
   l.o_partv = take(4 * (size_t)l.V * l.nb);
@@ -183,6 +184,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_vals = take(4 * (size_t)cap);
   l.o_vals2 = take(4 * (size_t)cap);
   l.o_pslot = take(4 * (size_t)cap);
+  l.o_bstart = take(4 * ((size_t)cap / 1024 + 2));   // first slot of each emission block
   l.o_skey = take(8 * (size_t)scap);         // visible slots (at most one per pair)
   l.o_sval = take(4 * (size_t)scap);
   l.o_scnt = take(4 * (size_t)scap);

@@ -17,12 +17,14 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
     const float* __restrict__ pq, const float* __restrict__ ps, const float* __restrict__ pa,
     const float* __restrict__ prgb, const float* __restrict__ psem, int C, int FS, int pack,
     uint32_t* __restrict__ cnt, float4* __restrict__ rec, uint2* __restrict__ rect,
-    uint32_t* __restrict__ part, uint32_t* __restrict__ partv, float* __restrict__ feat) {
+    uint16_t* __restrict__ rspan, uint32_t* __restrict__ part, uint32_t* __restrict__ partv,
+    float* __restrict__ feat) {
   __shared__ uint32_t s_w[kProjBlock / 64];
   __shared__ uint32_t s_v[kProjBlock / 64];
   __shared__ Span s_sp[kProjBlock];           // per-record span set-up
   __shared__ uint32_t s_roff[kProjBlock];     // first row item of each lane in its wave
   __shared__ uint32_t s_y0[kProjBlock];
+  __shared__ uint32_t s_y1[kProjBlock];
   __shared__ uint32_t s_cnt[kProjBlock];
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   const int v = blockIdx.y;
@@ -49,10 +51,14 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
                          pq[2 * (size_t)N + i], pq[3 * (size_t)N + i], ps[i], ps[N + i]);
     if (p.vis) {
       const Span sp = span_setup(p.uh, p.vh, p.ul, p.vl, p.A, p.B, p.C, qcut, p.x0, p.x1);
-      if (sp.full)
+      if (sp.full) {
         nt = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
-      else
+        if (span_desc_ok(p.x0, p.x1, p.y0, p.y1))
+          for (int r = 0; r < p.y1 - p.y0; ++r)
+            rspan[slot * kSpanRows + r] = (uint16_t)((p.x1 - p.x0) << 8);
+      } else {
         rows = (uint32_t)(p.y1 - p.y0);
+      }
       s_sp[threadIdx.x] = sp;
       rec[2 * slot] = make_float4(p.uh, p.vh, p.ul, p.vl);
       rec[2 * slot + 1] = make_float4(p.A, p.B, p.C, p.tz);
@@ -66,13 +72,19 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
   const uint32_t R = __shfl(incl, 63, 64);
   s_roff[threadIdx.x] = incl - rows;
   s_y0[threadIdx.x] = (uint32_t)p.y0;
+  s_y1[threadIdx.x] = (uint32_t)p.y1;
   s_cnt[threadIdx.x] = 0;
   __syncthreads();
   for (uint32_t k = (uint32_t)lane; k < R; k += 64) {
     const int j = wbase + last_le(s_roff + wbase, 64, k);
+    const int r = (int)(k - s_roff[j]);
+    const Span& sj = s_sp[j];
     int lo, hi;
-    span_row(s_sp[j], tw, th, vw.w, vw.h, (int)(s_y0[j] + (k - s_roff[j])), lo, hi);
+    span_row(sj, tw, th, vw.w, vw.h, (int)s_y0[j] + r, lo, hi);
     if (hi > lo) atomicAdd(&s_cnt[j], (uint32_t)(hi - lo));
+    if (span_desc_ok(sj.x0, sj.x1, (int)s_y0[j], (int)s_y1[j]))
+      rspan[((size_t)v * N + blockIdx.x * kProjBlock + (j & (kProjBlock - 1))) * kSpanRows + r] =
+          (uint16_t)((lo - sj.x0) | ((hi - sj.x0) << 8));
   }
   __syncthreads();
   nt += s_cnt[threadIdx.x];
@@ -314,7 +326,8 @@ void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
                      L.th, s->x, s->y, s->z, s->q, s->s, s->alpha, s->rgb, s->sem, L.C, L.FS,
                      pack_feat ? 1 : 0, at<uint32_t>(ws, L.o_cnt), at<float4>(ws, L.o_rec),
-                     at<uint2>(ws, L.o_rect), at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
+                     at<uint2>(ws, L.o_rect), at<uint16_t>(ws, L.o_rspan),
+                     at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
                      at<float>(ws, L.o_feat));
 }
 

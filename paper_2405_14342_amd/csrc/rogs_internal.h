@@ -50,7 +50,7 @@ struct Layout {
   int64_t slots = 0;           // V * N
   int64_t sort_blocks = 0;     // ceil(max(cap, tiles) / kSortTileMin)
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
-  size_t o_views, o_order, o_tkey, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
+  size_t o_views, o_order, o_tkey, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_rspan, o_bstart, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
@@ -224,6 +224,14 @@ __device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcu
 // with 1 - rho < 2^-16 or without a positive determinant keeps the whole
 // rectangle row.  Binary64 from the binary32 record, one rounding per step,
 // no contraction; span_setup holds the per-record part, span_row one row.
+// Row-span descriptor of a slot, written by the projection for the emission:
+// up to kSpanRows rectangle rows of at most 255 tiles, one 16-bit word per row
+// (lo - x0 | (hi - x0) << 8).  Slots beyond those limits are recomputed.
+constexpr int kSpanRows = 8;
+__host__ __device__ inline bool span_desc_ok(int x0, int x1, int y0, int y1) {
+  return y1 - y0 <= kSpanRows && x1 - x0 <= 255;
+}
+
 struct Span {
   double A, B, det, qe, u, v, dym, dys;
   int x0, x1;

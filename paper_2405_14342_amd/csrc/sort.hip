@@ -229,14 +229,15 @@ __global__ void k_gather_cnt(const uint32_t* __restrict__ n_dev, int64_t n_host,
 }
 
 // Emission in depth-sorted slot order, balanced by pairs: block b writes the
-// pairs e in [b * kEmitPairs, (b + 1) * kEmitPairs).  Two threads find the
-// first and last slot of the block's range by binary search over the slot
-// offsets (each visible slot has at least one pair, so the offsets are
-// strictly increasing and the range holds at most kEmitPairs slots), and the
-// block stages those slots in LDS.  The rectangle rows of the staged slots
+// pairs e in [b * kEmitPairs, (b + 1) * kEmitPairs).  Its first slot comes from
+// k_emit_starts; the following slots that start before the block's end (each
+// visible slot has at least one pair, so the offsets are strictly increasing
+// and the range holds at most kEmitPairs slots) are staged in LDS.  The rectangle rows of the staged slots
 // become row items: each gets its tile span (the same row spans that gave the
-// counts), an exclusive scan turns the span lengths into pair offsets, and
-// each pair finds its row by binary search.  A block whose slots hold more
+// counts: from the projection's row-span descriptor, or recomputed where the
+// slot has more rows or a wider rectangle than a descriptor holds), an
+// exclusive scan turns the span lengths into pair offsets, and each pair
+// finds its row by binary search.  A block whose slots hold more
 // than kEmitRows rows walks each pair's rows instead.  Per pair: key = global
 // tile, value = e, pslot[e] = slot.  The number of pairs written (the pair
 // count, clipped to the capacity and to the pairs of the slots within the
@@ -272,12 +273,31 @@ __device__ uint32_t emit_scan(uint32_t* a, int n, uint32_t* s_w) {
   return total;
 }
 
+// First slot of every emission block: the slot whose pair range holds the
+// block's first emission index (one thread per slot; each block start lies in
+// exactly one slot).
+__global__ __launch_bounds__(256) void k_emit_starts(const uint32_t* __restrict__ s_dev,
+                                                     int64_t s_host, int64_t scap,
+                                                     const uint32_t* __restrict__ soff,
+                                                     const uint32_t* __restrict__ scnt,
+                                                     uint32_t nblk, uint32_t* __restrict__ bstart) {
+  const uint32_t S = count_n(s_dev, s_host, scap);
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= (int64_t)S) return;
+  const uint32_t a = soff[k], c = scnt[k];
+  if (c == 0) return;
+  const uint32_t b0 = (a + (uint32_t)kEmitPairs - 1u) / (uint32_t)kEmitPairs;
+  const uint32_t b1 = min((a + c - 1u) / (uint32_t)kEmitPairs, nblk - 1u);   // launched blocks only
+  for (uint32_t b = b0; b <= b1; ++b) bstart[b] = (uint32_t)k;
+}
+
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const ViewDev* __restrict__ views, int N, const uint32_t* __restrict__ p_dev, int64_t p_host,
     const uint32_t* __restrict__ s_dev, int64_t s_host, int64_t scap, int64_t cap,
     const uint32_t* __restrict__ sval, const uint32_t* __restrict__ soff,
     const uint32_t* __restrict__ scnt, const uint2* __restrict__ rect,
-    const float4* __restrict__ rec, float qcut, int tw, int th, uint32_t* __restrict__ keys,
+    const uint16_t* __restrict__ rspan, const float4* __restrict__ rec, float qcut, int tw,
+    int th, const uint32_t* __restrict__ bstart, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ n_emit) {
   static_assert(kEmitThreads == kProjBlock, "block scan width");
   __shared__ uint32_t s_off[kEmitPairs + 1];
@@ -286,7 +306,6 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
   __shared__ uint32_t s_rx[kEmitRows];          // row span length, then its first pair
   __shared__ uint32_t s_rinfo[kEmitRows];       // span start tile | tile row << 16
   __shared__ uint16_t s_rslot[kEmitRows];
-  __shared__ uint32_t s_k[2];
   __shared__ uint32_t s_w[kEmitThreads / 64];
   const uint32_t S = count_n(s_dev, s_host, scap);
   const uint32_t P = count_n(p_dev, p_host, cap);
@@ -296,30 +315,33 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
   const uint32_t e0 = blockIdx.x * (uint32_t)kEmitPairs;
   if (e0 >= E) return;
   const uint32_t e1 = min(E, e0 + (uint32_t)kEmitPairs);
-  if (threadIdx.x < 2) {
-    const uint32_t target = threadIdx.x == 0 ? e0 : e1 - 1u;
-    s_k[threadIdx.x] = (uint32_t)last_le(soff, (int)S, target);
-  }
-  __syncthreads();
-  const uint32_t ka = s_k[0];
-  const int ns = (int)min<uint32_t>(s_k[1] - ka + 1u, (uint32_t)kEmitPairs);
-  // stage the slots and count their rectangle rows (ns <= kEmitThreads * 4)
+  // the block's slots are ka (holding e0) and the following ones that start
+  // before e1: at most kEmitPairs, since every listed slot has a pair
+  const uint32_t ka = bstart[blockIdx.x];
+  const uint32_t avail = min(S - ka, (uint32_t)kEmitPairs);
   constexpr int kPer = kEmitPairs / kEmitThreads;
-  uint32_t nrow[kPer], rsum = 0;
+  uint32_t nrow[kPer], rsum = 0, mine = 0;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int t = threadIdx.x * kPer + k;
     nrow[k] = 0;
-    if (t < ns) {
-      const uint32_t slot = sval[ka + t];
-      s_off[t] = soff[ka + t];
-      s_slot[t] = slot;
-      const uint2 r = rect[slot];
-      nrow[k] = (r.y >> 16) - (r.y & 0xffff);
+    if ((uint32_t)t < avail) {
+      const uint32_t o = soff[ka + t];
+      if (o < e1) {
+        const uint32_t slot = sval[ka + t];
+        s_off[t] = o;
+        s_slot[t] = slot;
+        const uint2 r = rect[slot];
+        nrow[k] = (r.y >> 16) - (r.y & 0xffff);
+        mine += 1;
+      }
     }
     rsum += nrow[k];
   }
-  if (threadIdx.x == 0) s_off[ns] = soff[ka + ns - 1] + scnt[ka + ns - 1];
+  // the staged slots are a prefix of the candidates; their count is ns
+  uint32_t ns_u;
+  (void)block_excl_scan(mine, s_w, &ns_u);
+  const int ns = (int)ns_u;
   uint32_t R;
   uint32_t pre = block_excl_scan(rsum, s_w, &R);
 #pragma unroll
@@ -335,11 +357,18 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
       const int j = last_le(s_roff, ns, (uint32_t)k);
       const uint32_t slot = s_slot[j];
       const uint2 r = rect[slot];
-      const ViewDev& vw = views[slot / (uint32_t)N];
-      const Span sp = emit_span(rec, slot, qcut, r.x & 0xffff, r.x >> 16);
-      const int ty = (int)(r.y & 0xffff) + (k - (int)s_roff[j]);
+      const int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
+      const int row = k - (int)s_roff[j];
+      const int ty = y0 + row;
       int lo, hi;
-      span_row(sp, tw, th, vw.w, vw.h, ty, lo, hi);
+      if (span_desc_ok(x0, x1, y0, y1)) {
+        const uint32_t d = rspan[(size_t)slot * kSpanRows + row];
+        lo = x0 + (int)(d & 0xffu);
+        hi = x0 + (int)(d >> 8);
+      } else {
+        const ViewDev& vw = views[slot / (uint32_t)N];
+        span_row(emit_span(rec, slot, qcut, x0, x1), tw, th, vw.w, vw.h, ty, lo, hi);
+      }
       s_rx[k] = (uint32_t)(hi - lo);
       s_rinfo[k] = (uint32_t)lo | ((uint32_t)ty << 16);
       s_rslot[k] = (uint16_t)j;
@@ -366,13 +395,20 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const uint2 r = rect[slot];
     const int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
     const ViewDev& vw = views[slot / (uint32_t)N];
-    const Span sp = emit_span(rec, slot, qcut, x0, x1);
+    const bool desc = span_desc_ok(x0, x1, y0, y1);
+    const Span sp = desc ? Span{} : emit_span(rec, slot, qcut, x0, x1);
     // walk the rectangle's rows to the one holding the kk-th reached tile
     int kk = (int)(e - s_off[j]);
     int ty = y0, tx = x0;
     for (; ty < y1; ++ty) {
       int a, b;
-      span_row(sp, tw, th, vw.w, vw.h, ty, a, b);
+      if (desc) {
+        const uint32_t d = rspan[(size_t)slot * kSpanRows + (ty - y0)];
+        a = x0 + (int)(d & 0xffu);
+        b = x0 + (int)(d >> 8);
+      } else {
+        span_row(sp, tw, th, vw.w, vw.h, ty, a, b);
+      }
       if (kk < b - a) {
         tx = a + kk;
         break;
@@ -454,11 +490,15 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
   // 4. one key per covered tile
   if (p_grid > 0) {
     if (s_grid > 0) {
+      const uint32_t nblk = (uint32_t)((p_grid + kEmitPairs - 1) / kEmitPairs);
+      hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0, st,
+                         s_dev, s_grid, L.scap, soff, scnt, nblk, at<uint32_t>(ws, L.o_bstart));
       hipLaunchKernelGGL(k_emit, dim3((unsigned)((p_grid + kEmitPairs - 1) / kEmitPairs)),
                          dim3(kEmitThreads), 0, st, at<const ViewDev>(ws, L.o_views), L.N, p_dev,
                          p_grid, s_dev, s_grid, L.scap, L.cap, sv, soff, scnt,
-                         at<const uint2>(ws, L.o_rect), at<const float4>(ws, L.o_rec), L.q_cut,
-                         L.tw, L.th, at<uint32_t>(ws, L.o_keys),
+                         at<const uint2>(ws, L.o_rect), at<const uint16_t>(ws, L.o_rspan),
+                         at<const float4>(ws, L.o_rec), L.q_cut,
+                         L.tw, L.th, at<const uint32_t>(ws, L.o_bstart), at<uint32_t>(ws, L.o_keys),
                          at<uint32_t>(ws, L.o_vals), at<uint32_t>(ws, L.o_pslot), n_emit);
     } else if (n_emit) {
       fill_u32(n_emit, 0u, 1, st);
