@@ -10,7 +10,11 @@
 // so that even the slot sort fills the chip); the scatter starts each digit
 // at the scan of the totals plus its column entry, and each of its four waves
 // ranks a contiguous quarter, 64 keys at a time, finding lanes with equal
-// digits with one ballot per digit bit, so ranks follow the input order.
+// digits with one ballot per digit bit, so ranks follow the input order.  In
+// the pair sort (STAGE) the block first reorders its keys by digit in LDS and
+// then writes them out in that order, so neighbouring lanes store to
+// neighbouring addresses (the emission order spreads a block's keys over all
+// digits; this halved the first pass).
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(kProjBlock) void k_colscan(uint32_t* __restrict__ h
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-template <typename K, int RB, int IPT>
+template <typename K, int RB, int IPT, bool STAGE>
 __global__ __launch_bounds__(kSortBlock) void k_scatter(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
@@ -88,6 +92,9 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
   constexpr int kDig = (R + kSortBlock - 1) / kSortBlock;
   __shared__ uint32_t wcnt[kWaves][R];
   __shared__ uint32_t s_base[R];
+  __shared__ uint32_t s_loc[R];
+  __shared__ K s_key[STAGE ? kSortBlock * IPT : 1];
+  __shared__ uint32_t s_val[STAGE ? kSortBlock * IPT : 1];
   __shared__ uint32_t s_w[kSortBlock / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t n = count_n(n_dev, n_host, cap);
@@ -136,30 +143,80 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
     dig[it] = d;
   }
   __syncthreads();
-  // per digit: global start of this block, then the waves one after another
-  for (int d = threadIdx.x; d < R; d += kSortBlock) {
-    uint32_t run = s_base[d] + hist_scan[(int64_t)d * nblk + blockIdx.x];
-    for (int w = 0; w < kWaves; ++w) {
-      uint32_t c = wcnt[w][d];
-      wcnt[w][d] = run;
-      run += c;
+  if constexpr (!STAGE) {
+    // per digit: global start of this block, then the waves one after another
+    for (int d = threadIdx.x; d < R; d += kSortBlock) {
+      uint32_t run = s_base[d] + hist_scan[(int64_t)d * nblk + blockIdx.x];
+      for (int w = 0; w < kWaves; ++w) {
+        uint32_t c = wcnt[w][d];
+        wcnt[w][d] = run;
+        run += c;
+      }
     }
+    __syncthreads();
+    for (int it = 0; it < kIters; ++it) {
+      const int64_t idx = base + (int64_t)wv * kPerWave + it * 64 + lane;
+      if (idx < (int64_t)n) {
+        uint32_t dst = wcnt[wv][dig[it]] + rank[it];
+        kout[dst] = kin[idx];
+        vout[dst] = vin[idx];
+      }
+    }
+    return;
+  }
+  // per digit: the waves one after another inside the block, the block's
+  // count, and the digit's first output position for this block
+  uint32_t v[kDig], cloc = 0;
+#pragma unroll
+  for (int k = 0; k < kDig; ++k) {
+    const int d = threadIdx.x * kDig + k;
+    v[k] = 0;
+    if (d < R) {
+      s_base[d] += hist_scan[(int64_t)d * nblk + blockIdx.x];
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wcnt[w][d];
+        wcnt[w][d] = v[k];
+        v[k] += c;
+      }
+    }
+    cloc += v[k];
+  }
+  // block-local order: keys grouped by digit (exclusive scan of the counts)
+  uint32_t total;
+  uint32_t run = block_excl_scan(cloc, s_w, &total);
+#pragma unroll
+  for (int k = 0; k < kDig; ++k) {
+    const int d = threadIdx.x * kDig + k;
+    if (d < R) s_loc[d] = run;
+    run += v[k];
   }
   __syncthreads();
   for (int it = 0; it < kIters; ++it) {
     const int64_t idx = base + (int64_t)wv * kPerWave + it * 64 + lane;
     if (idx < (int64_t)n) {
-      uint32_t dst = wcnt[wv][dig[it]] + rank[it];
-      kout[dst] = kin[idx];
-      vout[dst] = vin[idx];
+      const uint32_t lp = s_loc[dig[it]] + wcnt[wv][dig[it]] + rank[it];
+      s_key[lp] = kin[idx];
+      s_val[lp] = vin[idx];
     }
+  }
+  __syncthreads();
+  // write out in block order: each digit's keys are consecutive in LDS and
+  // land on consecutive output positions, so neighbouring lanes store
+  // neighbouring addresses
+  const int nk = (int)min<int64_t>((int64_t)n - base, (int64_t)kSortBlock * IPT);
+  for (int i = threadIdx.x; i < nk; i += kSortBlock) {
+    const K key = s_key[i];
+    const uint32_t d = (uint32_t)(key >> shift) & mask;
+    const uint32_t dst = s_base[d] + (uint32_t)i - s_loc[d];
+    kout[dst] = key;
+    vout[dst] = s_val[i];
   }
 }
 
 // Stable LSD sort of (keys, vals) over the low key_bits bits in as few passes
 // of at most RB bits as possible.  Returns 1 when the result is in the
 // alternate buffers, 0 when it is back in keys / vals.
-template <typename K, int RB, int IPT>
+template <typename K, int RB, int IPT, bool STAGE>
 int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, int64_t n_host,
                int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st) {
   const int passes = (key_bits + RB - 1) / RB;
@@ -176,7 +233,7 @@ int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, 
     hipLaunchKernelGGL((k_hist<K, RB, IPT>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
                        n_grid, cap, shift, mask, hist, nblk);
     hipLaunchKernelGGL(k_colscan, dim3(1u << RB), dim3(kProjBlock), 0, st, hist, nblk, histtmp);
-    hipLaunchKernelGGL((k_scatter<K, RB, IPT>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
+    hipLaunchKernelGGL((k_scatter<K, RB, IPT, STAGE>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
                        k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp);
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;
@@ -473,7 +530,7 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
   unsigned long long* sk2 = at<unsigned long long>(ws, L.o_keys2);   // free until emission
   uint32_t* sv = at<uint32_t>(ws, L.o_sval);
   uint32_t* sv2 = at<uint32_t>(ws, L.o_vals2);
-  if (radix_sort<unsigned long long, 9, 4>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
+  if (radix_sort<unsigned long long, 9, 4, false>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
                                         hist, histtmp, st)) {
     sv = sv2;
   }
@@ -505,7 +562,7 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
     }
   }
   // 5. stable sort of the pairs by tile
-  return radix_sort<uint32_t, 9, 8>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
+  return radix_sort<uint32_t, 9, 8, true>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
                                  at<uint32_t>(ws, L.o_keys2), at<uint32_t>(ws, L.o_vals2), n_emit,
                                  p_grid, L.cap, L.tile_bits, hist, histtmp, st);
 }
@@ -529,7 +586,7 @@ void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {
   hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
                      at<const uint2>(ws, L.o_ranges), T, key, val);
   // one 4-bit pass: the result lands in the alternate buffers (key2, order)
-  radix_sort<uint32_t, 4, 4>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
+  radix_sort<uint32_t, 4, 4, false>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
                           at<uint32_t>(ws, L.o_hist), at<uint32_t>(ws, L.o_histtmp), st);
 }
 
