@@ -349,13 +349,17 @@ __global__ __launch_bounds__(64) void k_slot_sums_long(const uint32_t* __restric
     const uint32_t k = long_list[it];
     const uint32_t n = scnt[k], o = soff[k];
     const uint32_t m = ((int64_t)o + n <= cap) ? n : (((int64_t)o < cap) ? (uint32_t)(cap - o) : 0u);
-    float acc[NV];
+    constexpr int Q = GSC / 4;
+    float acc[GSC];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) acc[c] = 0.0f;
+    for (int c = 0; c < GSC; ++c) acc[c] = 0.0f;
     for (uint32_t r = lane; r < m; r += 64) {
-      const float* row = gpair + (size_t)(o + r) * GSC;
+      const float4* row = reinterpret_cast<const float4*>(gpair) + (size_t)(o + r) * Q;
 #pragma unroll
-      for (int c = 0; c < NV; ++c) acc[c] += row[c];
+      for (int j = 0; j < Q; ++j) {
+        const float4 a = row[j];
+        acc[4 * j] += a.x; acc[4 * j + 1] += a.y; acc[4 * j + 2] += a.z; acc[4 * j + 3] += a.w;
+      }
     }
     const float tot = wave_reduce_scatter<NV>(acc, lane);
     if (writer) ssum[(size_t)k * GSC + my_comp] = tot;
@@ -790,7 +794,7 @@ void slot_sums_launch(const Layout& L, void* ws, hipStream_t st, bool clear) {
                      misc, L.scap, L.cap, at<const uint32_t>(ws, L.o_scnt),
                      at<const uint32_t>(ws, L.o_soff), at<const float>(ws, L.o_gpair),
                      at<float>(ws, L.o_ssum), at<uint32_t>(ws, L.o_long), misc + kMiscLong);
-  hipLaunchKernelGGL((k_slot_sums_long<C>), dim3(1024), dim3(64), 0, st,
+  hipLaunchKernelGGL((k_slot_sums_long<C>), dim3(4096), dim3(64), 0, st,
                      at<const uint32_t>(ws, L.o_long), misc + kMiscLong, L.cap,
                      at<const uint32_t>(ws, L.o_scnt), at<const uint32_t>(ws, L.o_soff),
                      at<const float>(ws, L.o_gpair), at<float>(ws, L.o_ssum));
