@@ -78,13 +78,13 @@ def compositing_flops(kernel: str, n_eval: int, n_contrib: int, C: int, fused: b
     Per contributing entry, forward: exp, clamp, weight, 4 + C accumulations,
     transmittance update and test, 9 + 2 (4 + C).  Backward: the same alpha
     and weight plus the (3 + C)-channel dot product, the (3 + C) feature
-    gradients, the suffix/alpha adjoint and the conic/centre terms,
-    38 + 4 (3 + C) without the depth and alpha loss terms (fused loss), +7
-    with them."""
+    gradients, the suffix/alpha adjoint and the five moments of dL/dq over
+    the pixel offsets, 31 + 4 (3 + C) without the depth and alpha loss terms
+    (fused loss), +7 with them."""
     if kernel == "render_fwd":
         return 14.0 * n_eval + (9 + 2 * (4 + C)) * n_contrib
     if kernel == "render_bwd":
-        return 14.0 * n_eval + (38 + 4 * (3 + C) + (0 if fused else 7)) * n_contrib
+        return 14.0 * n_eval + (31 + 4 * (3 + C) + (0 if fused else 7)) * n_contrib
     if kernel == "render_step":
         return (compositing_flops("render_fwd", n_eval, n_contrib, C, True) +
                 compositing_flops("render_bwd", n_eval, n_contrib, C, True))

@@ -376,7 +376,8 @@ __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ 
                                              const float q[4], float sx, float sy,
                                              const uint32_t* __restrict__ cnt,
                                              const uint32_t* __restrict__ pos, int64_t scap,
-                                             const float* __restrict__ ssum, float* vals) {
+                                             const float* __restrict__ ssum,
+                                             const float4* __restrict__ rec, float* vals) {
   constexpr int GSC = ((10 + C) + 3) & ~3;
   constexpr int Q = GSC / 4;
   float dz = 0.0f, dq[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsx = 0.0f, dsy = 0.0f, dal = 0.0f;
@@ -399,8 +400,15 @@ __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ 
     }
     // this view's contribution first, then one add per component into the
     // running sum, so summing views here or across calls gives the same bits
+    // the records hold moments of dL/dq over the pixel offsets (dx, dy):
+    // with the conic the forward used, du = -(2A m_x + 2B m_y),
+    // dv = -(2C m_y + 2B m_x), dA = m_xx, dB = 2 m_xy, dC = m_yy
+    const float4 cn = rec[2 * slot + 1];
+    const float A2 = 2.0f * cn.x, B2 = 2.0f * cn.y, C2 = 2.0f * cn.z;
+    const float du = -(A2 * rg[0] + B2 * rg[1]);
+    const float dv = -(C2 * rg[1] + B2 * rg[0]);
     float dzv = 0.0f, dqv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsxv = 0.0f, dsyv = 0.0f;
-    proj_adjoint(views[v], eps, x, y, z, q, sx, sy, rg[0], rg[1], rg[2], rg[3], rg[4], rg[6], dzv,
+    proj_adjoint(views[v], eps, x, y, z, q, sx, sy, du, dv, rg[2], 2.0f * rg[3], rg[4], rg[6], dzv,
                  dqv, dsxv, dsyv);
     dz += dzv;
 #pragma unroll
@@ -424,13 +432,13 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
     const float* __restrict__ py, const float* __restrict__ pz, const float* __restrict__ pq,
     const float* __restrict__ ps, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ pos, int64_t scap, const float* __restrict__ ssum,
-    float* __restrict__ grads, int accumulate) {
+    const float4* __restrict__ rec, float* __restrict__ grads, int accumulate) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   const float q[4] = {pq[i], pq[N + i], pq[2 * (size_t)N + i], pq[3 * (size_t)N + i]};
   float vals[11 + C];
   surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], cnt, pos, scap,
-                  ssum, vals);
+                  ssum, rec, vals);
   const size_t Nn = (size_t)N;
 #pragma unroll
   for (int r = 0; r < 11 + C; ++r) {
@@ -448,8 +456,8 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
     const float* __restrict__ py, float* __restrict__ P, float* __restrict__ M,
     float* __restrict__ Vv, float* __restrict__ s_act, float* __restrict__ a_act,
     const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ pos, int64_t scap,
-    const float* __restrict__ ssum, const float* __restrict__ dzr, float* __restrict__ grads_out,
-    AdamArgs aa) {
+    const float* __restrict__ ssum, const float4* __restrict__ rec, const float* __restrict__ dzr,
+    float* __restrict__ grads_out, AdamArgs aa) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   if (aa.misc[kMiscOverflow]) return;
@@ -457,7 +465,7 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
   const float q[4] = {P[Nn + i], P[2 * Nn + i], P[3 * Nn + i], P[4 * Nn + i]};
   float vals[11 + C];
   surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], cnt, pos,
-                  scap, ssum, vals);
+                  scap, ssum, rec, vals);
   if (dzr) vals[0] += dzr[i];
   if (grads_out) {
 #pragma unroll
@@ -476,7 +484,8 @@ void proj_bwd_launch(const Layout& L, void* ws, const rogs_surfels* s, float* gr
   hipLaunchKernelGGL((k_proj_bwd<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, s->x, s->y, s->z, s->q,
                      s->s, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_pos),
-                     L.scap, at<const float>(ws, L.o_ssum), grads, acc ? 1 : 0);
+                     L.scap, at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), grads,
+                     acc ? 1 : 0);
 }
 
 // One thread per pixel; grid.y = view, so a block never straddles views.
@@ -734,7 +743,8 @@ void proj_bwd_adam_launch(const Layout& L, void* ws, const float* x, const float
   hipLaunchKernelGGL((k_proj_bwd_adam<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, x, y, params, m, v,
                      s_act, a_act, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_pos),
-                     L.scap, at<const float>(ws, L.o_ssum), dzr, grads_out, aa);
+                     L.scap, at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), dzr,
+                     grads_out, aa);
 }
 }  // namespace
 

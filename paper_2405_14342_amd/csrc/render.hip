@@ -13,9 +13,10 @@
 // The backward walks the list front to back again, recomputing T exactly as
 // the forward did, and uses sum_{j>k} w_j f_j = O - prefix - w_k f_k for the
 // suffix term of dO/d(alpha_k).  Per (tile, pair) the 10 + C gradient values
-// are summed over the lane's pixels and then over the wave, and written as
-// one record at the pair's emission index; the projection adjoint later sums
-// each surfel's records.  No atomics: the result does not depend on timing.
+// (the conic and centre terms as moments of dL/dq over the pixel offsets) are
+// summed over the lane's pixels and then over the wave, and written as one
+// record at the pair's emission index; the projection adjoint later sums each
+// surfel's records and applies the conic.  No atomics: the result does not depend on timing.
 //
 // The fused training step runs forward, loss and backward of a tile in one
 // kernel (k_render_step): the per-pixel loss gradient, G.O, T_final and n_last
@@ -172,7 +173,9 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
                                               float* __restrict__ gpair, int GS) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
-  constexpr int NV = 10 + C;          // du dv dA dB dC dalpha dtz drgb[3] dsem[C]
+  // per pair: sum dq dx, sum dq dy, sum dq dx^2, sum dq dx dy, sum dq dy^2
+  // (dq = dL/dq of the quadratic form), dalpha, dtz, drgb[3], dsem[C]
+  constexpr int NV = 10 + C;
   const int lane = threadIdx.x;
   const int my_comp = rs_comp(lane, NV);
   const bool writer = my_comp >= 0 && (lane & rs_dup_bits(NV)) == 0;
@@ -245,12 +248,15 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
         const float gd = clamped ? 0.0f : g;      // the clamp cuts alpha's dependence on g
         pv[5] += gd * da;
         const float dq = -0.5f * gd * al * da;
+        // moments of dq over the pixel offsets; the projection adjoint turns
+        // them into dL/d(u, v, A, B, C) with the pair's conic
         const float dyk = dy[k];
-        pv[2] += dx * dx * dq;
-        pv[3] += 2.0f * dx * dyk * dq;
-        pv[4] += dyk * dyk * dq;
-        pv[0] += -(2.0f * A * dx + B2 * dyk) * dq;
-        pv[1] += -(2.0f * Cc * dyk + B2 * dx) * dq;
+        const float dqx = dq * dx, dqy = dq * dyk;
+        pv[0] += dqx;
+        pv[1] += dqy;
+        pv[2] += dqx * dx;
+        pv[3] += dqx * dyk;
+        pv[4] += dqy * dyk;
         T[k] *= om;
       }
       const float tot = wave_reduce_scatter<NV>(pv, lane);
