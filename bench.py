@@ -48,12 +48,16 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) 
         s_passes = (32 + view_bits + 8) // 9
         return slots * 4 + S * 16 + s_passes * S * 32 + S * 24 + P * 12 + passes * P * 20
     if kernel == "ranges":
-        return P * 8 + stats["tiles"] * 8
+        # tile ranges from the sorted keys, each sorted pair's slot (emission
+        # index and slot read, slot written), the launch order and the
+        # per-tile work items
+        return P * 20 + stats["tiles"] * 36
     if kernel == "render_step":
         # fused forward + loss + backward of a tile: targets (12 B colour,
-        # label, mask) in, the tile lists and the records of the listed slots
-        # in, one gradient record per pair and the per-tile loss partials out
-        return X * 14 + P * (8 + 4 * (10 + C)) + S * (32 + 4 * FS) + stats["tiles"] * 12
+        # label, mask) in, the work item of each tile (16 B), the slot and
+        # emission index of each pair and the records of the listed slots in,
+        # one gradient record per pair and the per-tile loss partials out
+        return X * 14 + P * (8 + 4 * (10 + C)) + S * (32 + 4 * FS) + stats["tiles"] * 28
     if kernel == "render_fwd":
         return X * ((5 + C) * 4 + 8) + P * 8 + S * (32 + 4 * FS)
     if kernel == "loss":

@@ -184,6 +184,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_vals = take(4 * (size_t)cap);
   l.o_vals2 = take(4 * (size_t)cap);
   l.o_pslot = take(4 * (size_t)cap);
+  l.o_spair = take(4 * (size_t)cap);
   l.o_bstart = take(4 * ((size_t)cap / 1024 + 2));   // first slot of each emission block
   l.o_skey = take(8 * (size_t)scap);         // visible slots (at most one per pair)
   l.o_sval = take(4 * (size_t)scap);
@@ -194,6 +195,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_pos = take(4 * (size_t)l.slots);
   l.o_ranges = take(8 * (size_t)l.total_tiles);
   l.o_order = take(4 * (size_t)l.total_tiles);      // tile launch order (longest lists first)
+  l.o_tinfo = take(16 * (size_t)l.total_tiles);
   l.o_tkey = take(4 * 3 * (size_t)l.total_tiles);   // its sort keys / values / keys out
   l.o_tfin = take(4 * (size_t)l.total_pix);
   l.o_nlast = take(4 * (size_t)l.total_pix);

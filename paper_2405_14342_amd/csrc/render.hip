@@ -4,23 +4,28 @@
 // Mapping: one 64-lane wave per tile, tiles launched longest list first; a
 // tile of tile_w x tile_h = 64 * PPL pixels gives every lane PPL pixels of one
 // column, so the per-pair x offset is shared and each broadcast record read
-// from LDS feeds PPL pixels.
-// The wave stages 64 list entries at a time in LDS (projection record + the
-// surfel's colour/semantic features), then every lane walks them in order.
-// A pixel stops after the surfel that takes its transmittance below t_eps;
-// the wave leaves the list once all of its pixels have stopped.
+// from LDS feeds PPL pixels.  A wave starts from one precomputed record
+// (tile, list range, view) and reads each entry's slot directly, so the
+// prologue is two dependent global loads before the records arrive.
+// The wave stages kStage list entries at a time in LDS (projection record +
+// the surfel's colour/semantic features), then every lane walks them in
+// order.  A pixel stops after the surfel that takes its transmittance below
+// t_eps; the wave leaves the list once all of its pixels have stopped.
 //
 // The backward walks the list front to back again, recomputing T exactly as
 // the forward did, and uses sum_{j>k} w_j f_j = O - prefix - w_k f_k for the
-// suffix term of dO/d(alpha_k).  Per (tile, pair) the 10 + C gradient values
-// (the conic and centre terms as moments of dL/dq over the pixel offsets) are
-// summed over the lane's pixels and then over the wave, and written as one
-// record at the pair's emission index; the projection adjoint later sums each
-// surfel's records and applies the conic.  No atomics: the result does not depend on timing.
+// suffix term of dO/d(alpha_k).  Per (tile, pair) it writes one record of
+// 10 + C gradient values at the pair's emission index: the five moments of
+// dL/dq over the pixel offsets and dalpha are summed across the wave with a
+// reduce-scatter; the colour, semantic and depth gradients sum_p w_p G_p are
+// a small matrix product per 16 entries on the matrix cores.  The projection
+// adjoint later sums each surfel's records and applies the conic.  No
+// atomics: the result does not depend on timing.
 //
 // The fused training step runs forward, loss and backward of a tile in one
 // kernel (k_render_step): the per-pixel loss gradient, G.O, T_final and n_last
-// stay in registers between the two passes instead of going through HBM.
+// stay in registers between the two passes instead of going through HBM, and
+// a list the forward staged whole is not staged again.
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -37,6 +42,9 @@ __device__ __forceinline__ int find_view(const ViewDev* __restrict__ views, int 
 }
 
 
+// List entries staged in LDS at a time (a multiple of 16, at most 64).
+constexpr int kStage = 32;
+
 // Per-tile constants of the compositing kernels.
 struct TileGeom {
   int gt, v, W, H, px, py0, rows;
@@ -45,13 +53,13 @@ struct TileGeom {
   const ViewDev* vw;
 };
 
-__device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views, int V, int N,
-                                              int tw, int th, const uint32_t* __restrict__ order,
-                                              const uint2* __restrict__ ranges) {
+__device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views, int N, int tw,
+                                              int th, const uint4* __restrict__ tinfo) {
   TileGeom t;
   const int lane = threadIdx.x;
-  t.gt = (int)order[blockIdx.x];
-  t.v = find_view(views, V, t.gt);
+  const uint4 ti = tinfo[blockIdx.x];      // tile, list begin, list end, view
+  t.gt = (int)ti.x;
+  t.v = (int)ti.w;
   t.vw = &views[t.v];
   t.W = t.vw->w;
   t.H = t.vw->h;
@@ -61,28 +69,27 @@ __device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views,
   t.px = tx * tw + (lane % tw);
   t.py0 = ty * th + lane / tw;
   t.pxc = (float)t.px + 0.5f;
-  const uint2 rg = ranges[t.gt];
-  t.rbeg = rg.x;
-  t.rend = rg.y;
+  t.rbeg = ti.y;
+  t.rend = ti.z;
   t.sbase = (uint32_t)t.v * (uint32_t)N;
   return t;
 }
 
 // Stages list entries [base, base + cnt) of the tile in LDS: the projection
-// record (with 2B in place of B) and the surfel's feature record.  Returns
-// this lane's emission index (lane < cnt).
-template <int FS4>
+// record (with 2B in place of B) and the surfel's feature record.  With kE,
+// returns this lane's emission index (lane < cnt).
+template <int FS4, bool kE>
 __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32_t sbase,
                                                   const uint32_t* __restrict__ vals,
-                                                  const uint32_t* __restrict__ pslot,
+                                                  const uint32_t* __restrict__ spair,
                                                   const float4* __restrict__ rec,
                                                   const float4* __restrict__ feat, float4* s_r0,
                                                   float4* s_r1, float4* s_f) {
   const int lane = threadIdx.x;
   uint32_t e = 0;
   if (lane < cnt) {
-    e = vals[base + lane];
-    const uint32_t slot = pslot[e];
+    if (kE) e = vals[base + lane];
+    const uint32_t slot = spair[base + lane];
     s_r0[lane] = rec[2 * (size_t)slot];
     const float4 r1 = rec[2 * (size_t)slot + 1];
     s_r1[lane] = make_float4(r1.x, 2.0f * r1.y, r1.z, r1.w);     // A, 2B, C, t_z
@@ -94,15 +101,17 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 }
 
 // Forward pass over the tile's list (Eq. 6): acc = sum w f (features, then
-// depth), T, and nl = entries up to the one that stopped the pixel.
-template <int C, int PPL>
+// depth), T, and nl = entries up to the one that stopped the pixel.  With kE,
+// e_first = this lane's emission index in the first staged batch.
+template <int C, int PPL, bool kE>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
-                                             const uint32_t* __restrict__ pslot,
+                                             const uint32_t* __restrict__ spair,
                                              const float4* __restrict__ rec,
                                              const float4* __restrict__ feat, float4* s_r0,
                                              float4* s_r1, float4* s_f, const float* pyc,
-                                             float (*acc)[3 + C + 1], float* T, uint32_t* nl) {
+                                             float (*acc)[3 + C + 1], float* T, uint32_t* nl,
+                                             uint32_t& e_first) {
   constexpr int F = 3 + C;            // composited features besides depth
   constexpr int FS4 = (F + 4) / 4;    // float4 per feature record (features, alpha)
   bool done[PPL];
@@ -116,9 +125,11 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
     for (int f = 0; f <= F; ++f) acc[k][f] = 0.0f;
   }
   bool stop_all = false;
-  for (uint32_t base = tg.rbeg; base < tg.rend && !stop_all; base += 64) {
-    const int cnt = (int)min(64u, tg.rend - base);
-    (void)stage_entries<FS4>(base, cnt, tg.sbase, vals, pslot, rec, feat, s_r0, s_r1, s_f);
+  for (uint32_t base = tg.rbeg; base < tg.rend && !stop_all; base += kStage) {
+    const int cnt = (int)min((uint32_t)kStage, tg.rend - base);
+    const uint32_t e =
+        stage_entries<FS4, kE>(base, cnt, tg.sbase, vals, spair, rec, feat, s_r0, s_r1, s_f);
+    if (base == tg.rbeg) e_first = e;
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
       const float4 r0 = s_r0[j], r1 = s_r1[j];   // u_hi v_hi u_lo v_lo | A 2B C tz
@@ -158,27 +169,99 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
   }
 }
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// Floats of the backward's LDS block for one block of 16 list entries: the
+// per-pixel weights w of 16 entries (rows of 64 * PPL + 4 floats), also used
+// once per tile to transpose the per-pixel gradient vectors.
+template <int C, int PPL>
+__host__ __device__ constexpr int bwd_lds_floats() {
+  constexpr int NFB = (3 + C + 1 + 15) / 16;
+  constexpr int a = 16 * (64 * PPL + 4), b = 64 * PPL * (16 * NFB + 1);
+  return a > b ? a : b;
+}
+
+// Feature and depth gradients of up to 16 list entries as one matrix product
+// on the matrix cores: D[m][n] = sum over the tile's pixels p of
+// w[m][p] * gamma[p][n], where gamma[p] = (dL/dfeatures, dL/dD) of pixel p.
+// v_mfma_f32_16x16x4_f32 takes A[m][k] from lane m + 16k, B[k][n] from lane
+// n + 16k and returns D[4g + i][n] in lane n + 16g, element i.  The k-th
+// step of 4 covers pixels kk * 64 + kgrp * 16 + c, so a lane reads its A
+// operands as 16 contiguous floats of its entry's row.
+template <int C, int PPL>
+__device__ __forceinline__ void feature_gemm(const float* s_w, const uint32_t* s_e, int nrows,
+                                             const float (&bG)[(3 + C + 1 + 15) / 16][PPL][16],
+                                             float* __restrict__ gpair, int GS) {
+  constexpr int F = 3 + C;
+  constexpr int NG = F + 1;
+  constexpr int NFB = (NG + 15) / 16;
+  constexpr int WS = 64 * PPL + 4;
+  const int lane = threadIdx.x;
+  const int mrow = lane & 15, kgrp = lane >> 4;
+  float a[PPL][16];
+#pragma unroll
+  for (int kk = 0; kk < PPL; ++kk) {
+    const float4* ap = reinterpret_cast<const float4*>(s_w + mrow * WS + kk * 64 + kgrp * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = ap[q];
+      a[kk][4 * q] = t.x; a[kk][4 * q + 1] = t.y; a[kk][4 * q + 2] = t.z; a[kk][4 * q + 3] = t.w;
+    }
+  }
+  uint32_t e4[4];
+  bool ok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = 4 * kgrp + i;
+    ok[i] = m < nrows;
+    e4[i] = s_e[m];
+  }
+#pragma unroll
+  for (int nb = 0; nb < NFB; ++nb) {
+    mfma_f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < PPL; ++kk)
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk][c], bG[nb][kk][c], acc, 0, 0, 0);
+    const int n = nb * 16 + mrow;
+    if (n < NG) {
+      const int col = n < F ? 7 + n : 6;       // record: ..., dt_z (6), features (7 ...)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (ok[i]) gpair[(size_t)e4[i] * GS + col] = acc[i];
+    }
+  }
+}
+
 // Backward pass over the tile's list, given per pixel the output gradient
 // Gv (features, depth, alpha), G.O, T_final and n_last.  Writes one record of
-// NV gradient values per pair at its emission index.
+// NV gradient values per pair at its emission index: the five moments and
+// dalpha are summed across the wave with a reduce-scatter, the feature and
+// depth gradients come from feature_gemm once per 16 entries.
 template <int C, int PPL, bool kDA>
 __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, float amax,
                                               const uint32_t* __restrict__ vals,
-                                              const uint32_t* __restrict__ pslot,
+                                              const uint32_t* __restrict__ spair,
                                               const float4* __restrict__ rec,
                                               const float4* __restrict__ feat, float4* s_r0,
-                                              float4* s_r1, float4* s_f, const float* pyc,
+                                              float4* s_r1, float4* s_f, float* s_w,
+                                              uint32_t* s_e, const float* pyc,
                                               const float (*Gv)[3 + C + 2], const float* GO,
                                               const float* Tf, const uint32_t* nl,
-                                              float* __restrict__ gpair, int GS) {
+                                              float* __restrict__ gpair, int GS, bool staged,
+                                              uint32_t e_pre) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   // per pair: sum dq dx, sum dq dy, sum dq dx^2, sum dq dx dy, sum dq dy^2
   // (dq = dL/dq of the quadratic form), dalpha, dtz, drgb[3], dsem[C]
   constexpr int NV = 10 + C;
+  constexpr int NR = 6;                       // reduced across the wave
+  constexpr int NFB = (F + 1 + 15) / 16;
+  constexpr int WS = 64 * PPL + 4;
   const int lane = threadIdx.x;
-  const int my_comp = rs_comp(lane, NV);
-  const bool writer = my_comp >= 0 && (lane & rs_dup_bits(NV)) == 0;
+  const int my_comp = rs_comp(lane, NR);
+  const bool writer = my_comp >= 0 && (lane & rs_dup_bits(NR)) == 0;
   float T[PPL], Spre[PPL];
   uint32_t maxn = 0;
 #pragma unroll
@@ -189,10 +272,37 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
   }
   for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, (uint32_t)__shfl_xor((int)maxn, o, 64));
   const uint32_t stop = tg.rbeg + min(maxn, tg.rend - tg.rbeg);
-  for (uint32_t base = tg.rbeg; base < stop; base += 64) {
-    const int cnt = (int)min(64u, stop - base);
+  // B operand of feature_gemm: gamma[pixel][n] for pixel kk * 64 + kgrp * 16
+  // + c, transposed through LDS (pixel-major rows of 16 * NFB + 1 floats);
+  // not needed when no entry is visited
+  float bG[NFB][PPL][16];
+  if (stop > tg.rbeg) {
+    constexpr int GR = 16 * NFB + 1;
+    const int mrow = lane & 15, kgrp = lane >> 4;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      float* row = s_w + (k * 64 + lane) * GR;
+#pragma unroll
+      for (int n = 0; n < 16 * NFB; ++n) row[n] = n <= F ? Gv[k][n] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < NFB; ++nb)
+#pragma unroll
+      for (int kk = 0; kk < PPL; ++kk)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          bG[nb][kk][c] = s_w[(kk * 64 + kgrp * 16 + c) * GR + nb * 16 + mrow];
+    __syncthreads();
+  }
+  for (uint32_t base = tg.rbeg; base < stop; base += kStage) {
+    const int cnt = (int)min((uint32_t)kStage, stop - base);
+    // a list the forward staged whole is still in LDS
     const uint32_t e_mine =
-        stage_entries<FS4>(base, cnt, tg.sbase, vals, pslot, rec, feat, s_r0, s_r1, s_f);
+        staged ? e_pre
+               : stage_entries<FS4, true>(base, cnt, tg.sbase, vals, spair, rec, feat, s_r0,
+                                          s_r1, s_f);
+    if (lane < kStage) s_e[lane] = e_mine;
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
       const uint32_t idx = base - tg.rbeg + (uint32_t)j;
@@ -200,6 +310,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
       const float4 r0 = s_r0[j], r1 = s_r1[j];
       const float A = r1.x, B2 = r1.y, Cc = r1.z, tz = r1.w;
       const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
+      float* wrow = s_w + (j & 15) * WS + lane;
       float dy[PPL], q[PPL];
       bool hit[PPL];
       bool any = false;
@@ -212,55 +323,60 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
       }
       if (!__any(any)) {            // no pixel of the tile reached by this pair
         if (writer) gpair[(size_t)e * GS + my_comp] = 0.0f;
-        continue;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) wrow[k * 64] = 0.0f;
+      } else {
+        float fv[FS4 * 4];
+#pragma unroll
+        for (int f = 0; f < FS4; ++f) {
+          const float4 t4 = s_f[j * FS4 + f];
+          fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
+        }
+        const float al = fv[F];
+        // Lanes whose pixel the pair does not reach run the same arithmetic
+        // with g = 0: alpha = w = 0, T and the prefix unchanged, terms +-0.
+        float pv[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) pv[c] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
+          const float araw = al * g;
+          const bool clamped = araw > amax;
+          const float a = clamped ? amax : araw;
+          const float w = a * T[k];
+          wrow[k * 64] = w;
+          float gf = kDA ? Gv[k][F] * tz : 0.0f;
+#pragma unroll
+          for (int f = 0; f < F; ++f) gf += Gv[k][f] * fv[f];
+          const float om = 1.0f - a;
+          const float inv = __builtin_amdgcn_rcpf(om);
+          const float suffix = (GO[k] - Spre[k]) - w * gf;
+          float da = T[k] * gf - suffix * inv;
+          if (kDA) da += Gv[k][F + 1] * Tf[k] * inv;
+          Spre[k] += w * gf;
+          const float gd = clamped ? 0.0f : g;    // the clamp cuts alpha's dependence on g
+          pv[5] += gd * da;
+          const float dq = -0.5f * gd * al * da;
+          // moments of dq over the pixel offsets; the projection adjoint
+          // turns them into dL/d(u, v, A, B, C) with the pair's conic
+          const float dyk = dy[k];
+          const float dqx = dq * dx, dqy = dq * dyk;
+          pv[0] += dqx;
+          pv[1] += dqy;
+          pv[2] += dqx * dx;
+          pv[3] += dqx * dyk;
+          pv[4] += dqy * dyk;
+          T[k] *= om;
+        }
+        const float tot = wave_reduce_scatter<NR>(pv, lane);
+        if (writer) gpair[(size_t)e * GS + my_comp] = tot;
       }
-      float fv[FS4 * 4];
-#pragma unroll
-      for (int f = 0; f < FS4; ++f) {
-        const float4 t4 = s_f[j * FS4 + f];
-        fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
+      if ((j & 15) == 15 || j == cnt - 1) {
+        __syncthreads();
+        feature_gemm<C, PPL>(s_w, s_e + (j & ~15), (j & 15) + 1, bG, gpair, GS);
+        __syncthreads();
       }
-      const float al = fv[F];
-      // Lanes whose pixel the pair does not reach run the same arithmetic with
-      // g = 0: alpha = w = 0, T and the prefix unchanged, every term +-0.
-      float pv[NV];
-#pragma unroll
-      for (int c = 0; c < NV; ++c) pv[c] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
-        const float araw = al * g;
-        const bool clamped = araw > amax;
-        const float a = clamped ? amax : araw;
-        const float w = a * T[k];
-        float gf = kDA ? Gv[k][F] * tz : 0.0f;
-#pragma unroll
-        for (int f = 0; f < F; ++f) gf += Gv[k][f] * fv[f];
-#pragma unroll
-        for (int f = 0; f < F; ++f) pv[7 + f] += w * Gv[k][f];
-        if (kDA) pv[6] += w * Gv[k][F];
-        const float om = 1.0f - a;
-        const float inv = __builtin_amdgcn_rcpf(om);
-        const float suffix = (GO[k] - Spre[k]) - w * gf;
-        float da = T[k] * gf - suffix * inv;
-        if (kDA) da += Gv[k][F + 1] * Tf[k] * inv;
-        Spre[k] += w * gf;
-        const float gd = clamped ? 0.0f : g;      // the clamp cuts alpha's dependence on g
-        pv[5] += gd * da;
-        const float dq = -0.5f * gd * al * da;
-        // moments of dq over the pixel offsets; the projection adjoint turns
-        // them into dL/d(u, v, A, B, C) with the pair's conic
-        const float dyk = dy[k];
-        const float dqx = dq * dx, dqy = dq * dyk;
-        pv[0] += dqx;
-        pv[1] += dqy;
-        pv[2] += dqx * dx;
-        pv[3] += dqx * dyk;
-        pv[4] += dqy * dyk;
-        T[k] *= om;
-      }
-      const float tot = wave_reduce_scatter<NV>(pv, lane);
-      if (writer) gpair[(size_t)e * GS + my_comp] = tot;
     }
     __syncthreads();
   }
@@ -276,22 +392,23 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
 template <int C, int PPL>
 __global__ __launch_bounds__(64) void k_render_fwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
-    float teps, const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ vals, const uint32_t* __restrict__ pslot,
+    float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, float* __restrict__ out,
     float* __restrict__ tfin, uint32_t* __restrict__ nlast) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;           // output channels
-  __shared__ float4 s_r0[64], s_r1[64];
-  __shared__ float4 s_f[64 * FS4];
-  const TileGeom tg = tile_geom(views, V, N, tw, th, order, ranges);
+  __shared__ float4 s_r0[kStage], s_r1[kStage];
+  __shared__ float4 s_f[kStage * FS4];
+  const TileGeom tg = tile_geom(views, N, tw, th, tinfo);
   float T[PPL], acc[PPL][F + 1], pyc[PPL];
   uint32_t nl[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) pyc[k] = (float)(tg.py0 + k * tg.rows) + 0.5f;
-  forward_tile<C, PPL>(tg, qcut, amax, teps, vals, pslot, rec, feat, s_r0, s_r1, s_f, pyc, acc, T,
-                       nl);
+  uint32_t e_first;
+  forward_tile<C, PPL, false>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1, s_f, pyc,
+                              acc, T, nl, e_first);
   const uint32_t len = tg.rend - tg.rbeg;
   const size_t HW = (size_t)tg.W * tg.H;
   float* o = out + (size_t)NO * tg.vw->pix_off;
@@ -313,17 +430,19 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 template <int C, int PPL>
 __global__ __launch_bounds__(64) void k_render_bwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
-    const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ vals, const uint32_t* __restrict__ pslot,
+    const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, const float* __restrict__ out,
     const float* __restrict__ G, const float* __restrict__ tfin,
     const uint32_t* __restrict__ nlast, float* __restrict__ gpair, int GS) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
-  __shared__ float4 s_r0[64], s_r1[64];
-  __shared__ float4 s_f[64 * FS4];
-  const TileGeom tg = tile_geom(views, V, N, tw, th, order, ranges);
+  __shared__ float4 s_r0[kStage], s_r1[kStage];
+  __shared__ float4 s_f[kStage * FS4];
+  __shared__ float4 s_w4[bwd_lds_floats<C, PPL>() / 4];
+  __shared__ uint32_t s_e[kStage];
+  const TileGeom tg = tile_geom(views, N, tw, th, tinfo);
   const size_t HW = (size_t)tg.W * tg.H;
   float Gv[PPL][F + 2], GO[PPL], Tf[PPL], pyc[PPL];
   uint32_t nl[PPL];
@@ -350,8 +469,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       nl[k] = nlast[tg.vw->pix_off + p];
     }
   }
-  backward_tile<C, PPL, true>(tg, qcut, amax, vals, pslot, rec, feat, s_r0, s_r1, s_f, pyc, Gv,
-                              GO, Tf, nl, gpair, GS);
+  backward_tile<C, PPL, true>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
+                              reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair, GS,
+                              false, 0u);
 }
 
 // The fused step's compositing: forward, the loss of Eq. 7-9 and 12 per pixel
@@ -360,29 +480,56 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 template <int C, int PPL>
 __global__ __launch_bounds__(64) void k_render_step(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
-    float teps, const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ vals, const uint32_t* __restrict__ pslot,
+    float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, float* __restrict__ gpair,
     int GS, FusedLoss fl) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
-  __shared__ float4 s_r0[64], s_r1[64];
-  __shared__ float4 s_f[64 * FS4];
+  __shared__ float4 s_r0[kStage], s_r1[kStage];
+  __shared__ float4 s_f[kStage * FS4];
+  __shared__ float4 s_w4[bwd_lds_floats<C, PPL>() / 4];
+  __shared__ uint32_t s_e[kStage];
   const int lane = threadIdx.x;
-  const TileGeom tg = tile_geom(views, V, N, tw, th, order, ranges);
+  const TileGeom tg = tile_geom(views, N, tw, th, tinfo);
   float pyc[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) pyc[k] = (float)(tg.py0 + k * tg.rows) + 0.5f;
   float Gv[PPL][F + 2], GO[PPL], Tf[PPL];
   uint32_t nl[PPL];
+  // the loss inputs of this lane's pixels (mask, target colour and label, in
+  // parallel), requested before the forward so that their latency overlaps it
+  const LossView lv = loss_view(fl.expo, fl.mcount, tg.v, fl.lam_c, fl.lam_s, fl.scale);
+  bool lmask[PPL];
+  uint32_t lab[PPL];
+  float tv[PPL][3];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int py = tg.py0 + k * tg.rows;
+    uint32_t m = 0;
+    lab[k] = 0;
+    tv[k][0] = tv[k][1] = tv[k][2] = 0.0f;
+    if (tg.px < tg.W && py < tg.H && lv.any) {
+      const size_t p = (size_t)py * tg.W + tg.px;
+      const size_t pix = tg.vw->pix_off + p;
+      const float* t = fl.tgt + 3 * (size_t)tg.vw->pix_off + p;
+      const size_t HW = (size_t)tg.W * tg.H;
+      m = fl.mask[pix];
+      lab[k] = fl.label[pix];
+      tv[k][0] = t[0];
+      tv[k][1] = t[HW];
+      tv[k][2] = t[2 * HW];
+    }
+    lmask[k] = m != 0;
+  }
   {
     float T[PPL], acc[PPL][F + 1];
     uint32_t nlf[PPL];
-    forward_tile<C, PPL>(tg, qcut, amax, teps, vals, pslot, rec, feat, s_r0, s_r1, s_f, pyc, acc,
-                         T, nlf);
+    uint32_t e_first = 0;
+    forward_tile<C, PPL, true>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1, s_f,
+                               pyc, acc, T, nlf, e_first);
     // loss epilogue: dL/dO and G.O per pixel, this tile's loss partials
     const uint32_t len = tg.rend - tg.rbeg;
-    const LossView lv = loss_view(fl.expo, fl.mcount, tg.v, fl.lam_c, fl.lam_s, fl.scale);
     float l = 0.0f, dal = 0.0f, dbl = 0.0f;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -393,14 +540,8 @@ __global__ __launch_bounds__(64) void k_render_step(
       float go = 0.0f, tf = 1.0f;
       uint32_t nlk = 0;
       if (tg.px < tg.W && py < tg.H) {
-        const size_t p = (size_t)py * tg.W + tg.px;
-        const size_t pix = tg.vw->pix_off + p;
-        if (fl.mask[pix] && lv.any) {
-          const float* t = fl.tgt + 3 * (size_t)tg.vw->pix_off + p;
-          const size_t HW = (size_t)tg.W * tg.H;
-          const float tv[3] = {t[0], t[HW], t[2 * HW]};
-          pixel_loss<C>(acc[k], tv, fl.label[pix], lv.wc, lv.ws, lv.ea, lv.b, g, l, dal, dbl);
-        }
+        if (lmask[k])
+          pixel_loss<C>(acc[k], tv[k], lab[k], lv.wc, lv.ws, lv.ea, lv.b, g, l, dal, dbl);
         // G.O over the composited channels; the depth row of G is zero
         const float gd = 0.0f;
 #pragma unroll
@@ -427,10 +568,11 @@ __global__ __launch_bounds__(64) void k_render_step(
       fl.part[3 * (size_t)tg.gt + 1] = dal;
       fl.part[3 * (size_t)tg.gt + 2] = dbl;
     }
+    // the fused loss has no depth or alpha term: their gradient rows are zero
+    backward_tile<C, PPL, false>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
+                                 reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair,
+                                 GS, len <= (uint32_t)kStage, e_first);
   }
-  // the fused loss has no depth or alpha term: their gradient rows are zero
-  backward_tile<C, PPL, false>(tg, qcut, amax, vals, pslot, rec, feat, s_r0, s_r1, s_f, pyc, Gv,
-                               GO, Tf, nl, gpair, GS);
 }
 
 // Work counts of a rendered batch (diagnostics): per pixel, the list entries
@@ -490,8 +632,8 @@ template <int C, int PPL>
 void fwd_launch(const Layout& L, void* ws, float* out, hipStream_t st) {
   hipLaunchKernelGGL((k_render_fwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
-                     L.t_eps, at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
-                     at<const uint32_t>(ws, L.o_vals), at<const uint32_t>(ws, L.o_pslot),
+                     L.t_eps, at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out,
                      at<float>(ws, L.o_tfin), at<uint32_t>(ws, L.o_nlast));
 }
@@ -500,8 +642,8 @@ template <int C, int PPL>
 void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hipStream_t st) {
   hipLaunchKernelGGL((k_render_bwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
-                     at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
-                     at<const uint32_t>(ws, L.o_vals), at<const uint32_t>(ws, L.o_pslot),
+                     at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out, G,
                      at<const float>(ws, L.o_tfin), at<const uint32_t>(ws, L.o_nlast),
                      at<float>(ws, L.o_gpair), L.GS);
@@ -511,8 +653,8 @@ template <int C, int PPL>
 void step_launch(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st) {
   hipLaunchKernelGGL((k_render_step<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
-                     L.t_eps, at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
-                     at<const uint32_t>(ws, L.o_vals), at<const uint32_t>(ws, L.o_pslot),
+                     L.t_eps, at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat),
                      at<float>(ws, L.o_gpair), L.GS, fl);
 }

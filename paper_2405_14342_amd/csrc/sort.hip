@@ -479,14 +479,36 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
   }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-                         int64_t n_host, int64_t cap, uint2* __restrict__ ranges) {
+// Per-tile list ranges of the sorted pairs, and the slot of each sorted pair
+// (so the compositing reads it without going through the emission index).
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                         const uint32_t* __restrict__ pslot, const uint32_t* __restrict__ n_dev,
+                         int64_t n_host, int64_t cap, uint2* __restrict__ ranges,
+                         uint32_t* __restrict__ spair) {
   const uint32_t n = count_n(n_dev, n_host, cap);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n) return;
   const uint32_t t = keys[i];
   if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
   if (i == (int64_t)n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  spair[i] = pslot[vals[i]];
+}
+
+// Compositing work item of each launch position b: (tile, list begin, list
+// end, view) of the tile order[b], so a compositing wave starts from one load.
+__global__ void k_tile_info(const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
+                            const ViewDev* __restrict__ views, int V, int64_t T,
+                            uint4* __restrict__ tinfo) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= T) return;
+  const uint32_t gt = order[b];
+  const uint2 r = ranges[gt];
+  int lo = 0, hi = V - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_off <= (int32_t)gt) lo = mid; else hi = mid - 1;
+  }
+  tinfo[b] = make_uint4(gt, r.x, r.y, (uint32_t)lo);
 }
 
 // Launch order of the tiles for compositing: the longest lists first (keys =
@@ -574,7 +596,9 @@ void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st) {
   const int64_t n_grid = n_host < 0 ? L.cap : n_host;
   if (n_grid > 0)
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_grid + 255) / 256)), dim3(256), 0, st,
-                       at<const uint32_t>(ws, L.o_keys), n_dev, n_grid, L.cap, ranges);
+                       at<const uint32_t>(ws, L.o_keys), at<const uint32_t>(ws, L.o_vals),
+                       at<const uint32_t>(ws, L.o_pslot), n_dev, n_grid, L.cap, ranges,
+                       at<uint32_t>(ws, L.o_spair));
   launch_tile_order(L, ws, st);
 }
 
@@ -588,6 +612,9 @@ void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {
   // one 4-bit pass: the result lands in the alternate buffers (key2, order)
   radix_sort<uint32_t, 4, 4, false>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
                           at<uint32_t>(ws, L.o_hist), at<uint32_t>(ws, L.o_histtmp), st);
+  hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
+                     at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
+                     at<const ViewDev>(ws, L.o_views), L.V, T, at<uint4>(ws, L.o_tinfo));
 }
 
 }  // namespace rogs
