@@ -516,15 +516,17 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_v(
 #pragma unroll
     for (int c = 0; c < NO; ++c) gv[c] = 0.0f;
     const LossView lv = loss_view(expo, mcount, v, lam_c, lam_s, scale);
-    if (mask[p] && lv.any) {
-      float ov[3 + C], tv[3];
+    // a pixel outside the mask is evaluated with zero weights: its gradient
+    // and loss terms are +-0, as in the fused forward epilogue
+    const bool in = mask[p] != 0;
+    float ov[3 + C], tv[3];
 #pragma unroll
-      for (int c = 0; c < 3 + C; ++c) ov[c] = o[c * HW];
-      const float* t = tgt + 3 * (size_t)vw.pix_off + q;
+    for (int c = 0; c < 3 + C; ++c) ov[c] = o[c * HW];
+    const float* t = tgt + 3 * (size_t)vw.pix_off + q;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) tv[c] = t[c * HW];
-      pixel_loss<C>(ov, tv, label[p], lv.wc, lv.ws, lv.ea, lv.b, gv, l, da, db);
-    }
+    for (int c = 0; c < 3; ++c) tv[c] = t[c * HW];
+    pixel_loss<C>(ov, tv, label[p], in ? lv.wc : 0.0f, in ? lv.ws : 0.0f, lv.ea, lv.b, gv, l, da,
+                  db);
 #pragma unroll
     for (int c = 0; c < NO; ++c) g[c * HW] = gv[c];
   }

@@ -65,9 +65,10 @@ __device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views,
   t.H = t.vw->h;
   const int lt = t.gt - t.vw->tile_off;
   const int ty = lt / t.vw->tiles_x, tx = lt - ty * t.vw->tiles_x;
-  t.rows = 64 / tw;
-  t.px = tx * tw + (lane % tw);
-  t.py0 = ty * th + lane / tw;
+  const int sh = __builtin_ctz((unsigned)tw);      // tile_w divides 64: a power of two
+  t.rows = 64 >> sh;
+  t.px = tx * tw + (lane & (tw - 1));
+  t.py0 = ty * th + (lane >> sh);
   t.pxc = (float)t.px + 0.5f;
   t.rbeg = ti.y;
   t.rend = ti.z;
@@ -112,6 +113,9 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
                                              float4* s_r1, float4* s_f, const float* pyc,
                                              float (*acc)[3 + C + 1], float* T, uint32_t* nl,
                                              uint32_t& e_first) {
+  // every multiply-add is written out: the forward rounds the same in every
+  // kernel it is inlined into
+#pragma clang fp contract(off)
   constexpr int F = 3 + C;            // composited features besides depth
   constexpr int FS4 = (F + 4) / 4;    // float4 per feature record (features, alpha)
   bool done[PPL];
@@ -151,8 +155,8 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
           const float a = clamp_alpha(al * g, amax);
           const float w = a * T[k];
 #pragma unroll
-          for (int f = 0; f < F; ++f) acc[k][f] += w * fv[f];
-          acc[k][F] += w * r1.w;
+          for (int f = 0; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+          acc[k][F] = __builtin_fmaf(w, r1.w, acc[k][F]);
           T[k] *= (1.0f - a);
           if (T[k] < teps) {
             done[k] = true;
@@ -251,6 +255,9 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
                                               const float* Tf, const uint32_t* nl,
                                               float* __restrict__ gpair, int GS, bool staged,
                                               uint32_t e_pre) {
+  // every multiply-add is written out: the backward rounds the same in the
+  // fused step and in the stand-alone backward
+#pragma clang fp contract(off)
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   // per pair: sum dq dx, sum dq dy, sum dq dx^2, sum dq dx dy, sum dq dy^2
@@ -348,25 +355,25 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           wrow[k * 64] = w;
           float gf = kDA ? Gv[k][F] * tz : 0.0f;
 #pragma unroll
-          for (int f = 0; f < F; ++f) gf += Gv[k][f] * fv[f];
+          for (int f = 0; f < F; ++f) gf = __builtin_fmaf(Gv[k][f], fv[f], gf);
           const float om = 1.0f - a;
           const float inv = __builtin_amdgcn_rcpf(om);
-          const float suffix = (GO[k] - Spre[k]) - w * gf;
-          float da = T[k] * gf - suffix * inv;
-          if (kDA) da += Gv[k][F + 1] * Tf[k] * inv;
-          Spre[k] += w * gf;
+          const float suffix = __builtin_fmaf(-w, gf, GO[k] - Spre[k]);
+          float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
+          if (kDA) da = __builtin_fmaf(Gv[k][F + 1] * Tf[k], inv, da);
+          Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
           const float gd = clamped ? 0.0f : g;    // the clamp cuts alpha's dependence on g
-          pv[5] += gd * da;
-          const float dq = -0.5f * gd * al * da;
+          pv[5] = __builtin_fmaf(gd, da, pv[5]);
+          const float dq = ((-0.5f * gd) * al) * da;
           // moments of dq over the pixel offsets; the projection adjoint
           // turns them into dL/d(u, v, A, B, C) with the pair's conic
           const float dyk = dy[k];
           const float dqx = dq * dx, dqy = dq * dyk;
           pv[0] += dqx;
           pv[1] += dqy;
-          pv[2] += dqx * dx;
-          pv[3] += dqx * dyk;
-          pv[4] += dqy * dyk;
+          pv[2] = __builtin_fmaf(dqx, dx, pv[2]);
+          pv[3] = __builtin_fmaf(dqx, dyk, pv[3]);
+          pv[4] = __builtin_fmaf(dqy, dyk, pv[4]);
           T[k] *= om;
         }
         const float tot = wave_reduce_scatter<NR>(pv, lane);
@@ -463,7 +470,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 #pragma unroll
       for (int f = 0; f < F + 2; ++f) Gv[k][f] = g[f * HW];
 #pragma unroll
-      for (int f = 0; f <= F; ++f) go += Gv[k][f] * o[f * HW];
+      for (int f = 0; f <= F; ++f) go = __builtin_fmaf(Gv[k][f], o[f * HW], go);
       GO[k] = go;
       Tf[k] = tfin[tg.vw->pix_off + p];
       nl[k] = nlast[tg.vw->pix_off + p];
@@ -535,38 +542,31 @@ __global__ __launch_bounds__(64) void k_render_step(
     for (int k = 0; k < PPL; ++k) {
       const int py = tg.py0 + k * tg.rows;
       float g[F];
-#pragma unroll
-      for (int f = 0; f < F; ++f) g[f] = 0.0f;
-      float go = 0.0f, tf = 1.0f;
-      uint32_t nlk = 0;
-      if (tg.px < tg.W && py < tg.H) {
-        if (lmask[k])
-          pixel_loss<C>(acc[k], tv[k], lab[k], lv.wc, lv.ws, lv.ea, lv.b, g, l, dal, dbl);
-        // G.O over the composited channels; the depth row of G is zero
-        const float gd = 0.0f;
-#pragma unroll
-        for (int f = 0; f < F; ++f) go += g[f] * acc[k][f];
-        go += gd * acc[k][F];
-        tf = T[k];
-        nlk = (T[k] < teps) ? nlf[k] : len;
-      }
+      // every lane evaluates the loss; a pixel outside the mask or the image
+      // has zero weights, so its gradient and loss terms are +-0
+      pixel_loss<C>(acc[k], tv[k], lab[k], lmask[k] ? lv.wc : 0.0f, lmask[k] ? lv.ws : 0.0f,
+                    lv.ea, lv.b, g, l, dal, dbl);
 #pragma unroll
       for (int f = 0; f < F; ++f) Gv[k][f] = g[f];
-      Gv[k][F] = 0.0f;
+      Gv[k][F] = 0.0f;         // the fused loss has no depth or alpha term
       Gv[k][F + 1] = 0.0f;
+      // G.O over the composited channels and depth, in the same form as the
+      // stand-alone backward so that both round alike
+      float go = 0.0f;
+#pragma unroll
+      for (int f = 0; f <= F; ++f) go = __builtin_fmaf(Gv[k][f], acc[k][f], go);
+      const bool in_img = tg.px < tg.W && py < tg.H;
+      const float tf = in_img ? T[k] : 1.0f;
+      const uint32_t nlk = in_img ? ((T[k] < teps) ? nlf[k] : len) : 0u;
       GO[k] = go;
       Tf[k] = tf;
       nl[k] = nlk;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      l += __shfl_xor(l, o, 64);
-      dal += __shfl_xor(dal, o, 64);
-      dbl += __shfl_xor(dbl, o, 64);
-    }
-    if (lane == 0) {
-      fl.part[3 * (size_t)tg.gt] = l;
-      fl.part[3 * (size_t)tg.gt + 1] = dal;
-      fl.part[3 * (size_t)tg.gt + 2] = dbl;
+    {
+      const float lp[3] = {l, dal, dbl};
+      const float tot = wave_reduce_scatter<3>(lp, lane);
+      const int c = rs_comp(lane, 3);
+      if (c >= 0 && (lane & rs_dup_bits(3)) == 0) fl.part[3 * (size_t)tg.gt + c] = tot;
     }
     // the fused loss has no depth or alpha term: their gradient rows are zero
     backward_tile<C, PPL, false>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,

@@ -469,6 +469,9 @@ template <int C>
 __device__ __forceinline__ void pixel_loss(const float* o, const float* t, int label, float wc,
                                            float ws, float ea, float b, float* g, float& l,
                                            float& da, float& db) {
+  // no multiply-add contraction: each inlined copy rounds every step the
+  // same way, whatever the surrounding code lets the compiler fuse
+#pragma clang fp contract(off)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float cc = o[c];
@@ -513,8 +516,11 @@ __device__ __forceinline__ LossView loss_view(const float* expo, const uint32_t*
   LossView r;
   const uint32_t mc = mcount[v];
   r.any = mc > 0;
-  r.wc = r.any ? lam_c * scale / (float)mc : 0.0f;
-  r.ws = r.any ? lam_s * scale / (float)mc : 0.0f;
+  // 1/|M_v| with the hardware reciprocal (within 1 ulp): evaluated once per
+  // wave by every loss kernel
+  const float inv = __builtin_amdgcn_rcpf((float)mc);
+  r.wc = r.any ? (lam_c * scale) * inv : 0.0f;
+  r.ws = r.any ? (lam_s * scale) * inv : 0.0f;
   r.ea = expf(expo[2 * v]);
   r.b = expo[2 * v + 1];
   return r;
