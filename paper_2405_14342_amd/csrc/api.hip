@@ -208,6 +208,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
     l.o_regpart = take(4 * (size_t)rogs::elev_reg_blocks(l.N));
     l.o_regtot = take(4);
     l.o_status = take(sizeof(uint32_t) * 4 + sizeof(StepState));   // misc[0..3] + step state
+    l.o_mpart = take(4 * (size_t)l.V * rogs::mask_chunks(l));        // mask counts per chunk
   }
   l.total = o;
   *L = l;
@@ -761,10 +762,11 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
                    const rogs_optim* o, void* ws, hipStream_t st) {
   rogs_surfels s = fused_surfels(t);
   prof_begin(c, 0, st);
-  rogs::launch_project(L, ws, &s, true, st);
+  // the same launch counts the loss mask per view and clears the tile ranges
+  rogs::launch_project(L, ws, &s, true, st, tg->mask);
   prof_end(c, st);
   prof_begin(c, 1, st);
-  rogs::launch_scan_part(L, ws, st);
+  rogs::launch_scan_part(L, ws, st, true);
   prof_end(c, st);
   prof_begin(c, 3, st);
   int alt = rogs::launch_binning(L, ws, -1, -1, st);
@@ -774,10 +776,7 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
     std::swap(L.o_vals, L.o_vals2);
   }
   prof_begin(c, 4, st);
-  rogs::launch_ranges(L, ws, -1, st);
-  prof_end(c, st);
-  prof_begin(c, 6, st);
-  rogs::launch_mask_count(L, ws, tg->mask, st);
+  rogs::launch_ranges(L, ws, -1, st, true);
   prof_end(c, st);
   rogs::FusedLoss fl;
   fl.tgt = tg->rgb;

@@ -11,6 +11,52 @@ namespace rogs {
 
 namespace {
 
+__device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t x) {
+  return ((x & 0xffu) != 0u) + ((x & 0xff00u) != 0u) + ((x & 0xff0000u) != 0u) +
+         ((x & 0xff000000u) != 0u);
+}
+
+// Extra blocks of the fused step's projection launch, block (nb + c, v):
+// the nonzero bytes of chunk c (kMaskChunk bytes) of view v's loss mask into
+// mpart[v * nmb + c] (summed per view by the count-table scan), and a share
+// of clearing the n_zero words of the tile-range table.  Work the step needs
+// anyway, done here instead of in two launches of its own.
+__device__ void project_side_block(const ViewDev* __restrict__ views, int V, int nb,
+                                   const uint8_t* __restrict__ mask, int nmb,
+                                   uint32_t* __restrict__ mpart, uint32_t* __restrict__ zero_words,
+                                   int64_t n_zero, uint32_t* s_w) {
+  const int c = blockIdx.x - nb, v = blockIdx.y;
+  const ViewDev& vw = views[v];
+  const int64_t npix = (int64_t)vw.w * vw.h;
+  const uint8_t* m = mask + vw.pix_off;
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int it = 0; it < kMaskChunk / (16 * kProjBlock); ++it) {
+    const int64_t p = (int64_t)c * kMaskChunk + 16 * ((int64_t)it * kProjBlock + threadIdx.x);
+    if (p >= npix) continue;
+    const uint8_t* g = m + p;
+    if (p + 16 <= npix && (reinterpret_cast<uintptr_t>(g) & 15u) == 0) {
+      const uint4 x = *reinterpret_cast<const uint4*>(g);
+      cnt += nonzero_bytes4(x.x) + nonzero_bytes4(x.y) + nonzero_bytes4(x.z) + nonzero_bytes4(x.w);
+    } else {
+      const int n = (int)min<int64_t>(16, npix - p);
+      for (int k = 0; k < n; ++k) cnt += g[k] ? 1u : 0u;
+    }
+  }
+  cnt = wave_sum_u32(cnt);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kProjBlock / 64; ++w) t += s_w[w];
+    mpart[(size_t)v * nmb + c] = t;
+  }
+  const int64_t nside = (int64_t)V * nmb;
+  for (int64_t k = ((int64_t)v * nmb + c) * kProjBlock + threadIdx.x; k < n_zero;
+       k += nside * kProjBlock)
+    zero_words[k] = 0u;
+}
+
 __global__ __launch_bounds__(kProjBlock) void k_project(
     const ViewDev* __restrict__ views, int V, int N, int nb, float eps, float qcut, int tw, int th,
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
@@ -18,8 +64,13 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
     const float* __restrict__ prgb, const float* __restrict__ psem, int C, int FS, int pack,
     uint32_t* __restrict__ cnt, float4* __restrict__ rec, uint2* __restrict__ rect,
     uint16_t* __restrict__ rspan, uint32_t* __restrict__ part, uint32_t* __restrict__ partv,
-    float* __restrict__ feat) {
+    float* __restrict__ feat, const uint8_t* __restrict__ mask, int nmb,
+    uint32_t* __restrict__ mpart, uint32_t* __restrict__ zero_words, int64_t n_zero) {
   __shared__ uint32_t s_w[kProjBlock / 64];
+  if (blockIdx.x >= (unsigned)nb) {
+    project_side_block(views, V, nb, mask, nmb, mpart, zero_words, n_zero, s_w);
+    return;
+  }
   __shared__ uint32_t s_v[kProjBlock / 64];
   __shared__ Span s_sp[kProjBlock];           // per-record span set-up
   __shared__ uint32_t s_roff[kProjBlock];     // first row item of each lane in its wave
@@ -107,10 +158,34 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
   }
 }
 
-__global__ void k_check_cap(uint32_t* misc, int64_t cap, int64_t scap) {
+// Per-view mask counts from the projection's side blocks (exact integer
+// sums): per view, the block's threads stride over the chunks, then a wave
+// sum and the waves' totals.  blockDim.x is a multiple of 64, at most 1024.
+__device__ __forceinline__ void sum_mask_parts(const uint32_t* __restrict__ mpart, int nmb, int V,
+                                               uint32_t* __restrict__ mcount) {
+  __shared__ uint32_t s_t[16];
+  for (int v = 0; v < V; ++v) {
+    uint32_t t = 0;
+    for (int c = threadIdx.x; c < nmb; c += blockDim.x) t += mpart[(size_t)v * nmb + c];
+    t = wave_sum_u32(t);
+    if ((threadIdx.x & 63) == 0) s_t[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t a = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += s_t[w];
+      mcount[v] = a;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_check_cap(uint32_t* misc, int64_t cap, int64_t scap,
+                            const uint32_t* __restrict__ mpart, int nmb, int V,
+                            uint32_t* __restrict__ mcount) {
   if (threadIdx.x == 0 && blockIdx.x == 0)
     misc[kMiscOverflow] =
         ((int64_t)misc[kMiscPairs] > cap || (int64_t)misc[kMiscVisible] > scap) ? 1u : 0u;
+  if (mpart) sum_mask_parts(mpart, nmb, V, mcount);
 }
 
 // ------------------------------------------------------------ generic scan
@@ -259,12 +334,19 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_
 }
 
 // Both per-block count tables of the projection (pairs, visible slots) in one
-// launch, one block each; the last block sets the overflow flag.
+// launch, one block each, and with mpart a third block for the per-view mask
+// counts; the last block sets the overflow flag.
 __global__ __launch_bounds__(1024) void k_scan_part(uint32_t* part, uint32_t* partv, int64_t n,
                                                     uint32_t* __restrict__ misc, int64_t cap,
-                                                    int64_t scap) {
-  uint32_t* a = blockIdx.x == 0 ? part : partv;
-  block_scan_small(a, a, n, misc + (blockIdx.x == 0 ? kMiscPairs : kMiscVisible));
+                                                    int64_t scap,
+                                                    const uint32_t* __restrict__ mpart, int nmb,
+                                                    int V, uint32_t* __restrict__ mcount) {
+  if (blockIdx.x == 2) {
+    sum_mask_parts(mpart, nmb, V, mcount);
+  } else {
+    uint32_t* a = blockIdx.x == 0 ? part : partv;
+    block_scan_small(a, a, n, misc + (blockIdx.x == 0 ? kMiscPairs : kMiscVisible));
+  }
   if (last_block(misc + kMiscTicketScan) && threadIdx.x == 0) {
     const uint32_t pairs = __atomic_load_n(misc + kMiscPairs, __ATOMIC_RELAXED);
     const uint32_t vis = __atomic_load_n(misc + kMiscVisible, __ATOMIC_RELAXED);
@@ -320,29 +402,38 @@ void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
 }
 
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
-                    hipStream_t st) {
+                    hipStream_t st, const uint8_t* mask) {
   fill_u32(at<uint32_t>(ws, L.o_misc), 0u, kMiscCount, st);
-  hipLaunchKernelGGL(k_project, dim3(L.nb, L.V), dim3(kProjBlock), 0, st,
+  const int nmb = mask ? mask_chunks(L) : 0;
+  hipLaunchKernelGGL(k_project, dim3(L.nb + nmb, L.V), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
                      L.th, s->x, s->y, s->z, s->q, s->s, s->alpha, s->rgb, s->sem, L.C, L.FS,
                      pack_feat ? 1 : 0, at<uint32_t>(ws, L.o_cnt), at<float4>(ws, L.o_rec),
                      at<uint2>(ws, L.o_rect), at<uint16_t>(ws, L.o_rspan),
                      at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
-                     at<float>(ws, L.o_feat));
+                     at<float>(ws, L.o_feat), mask, nmb,
+                     mask ? at<uint32_t>(ws, L.o_mpart) : nullptr,
+                     mask ? at<uint32_t>(ws, L.o_ranges) : nullptr,
+                     mask ? 2 * L.total_tiles : (int64_t)0);
 }
 
-void launch_scan_part(const Layout& L, void* ws, hipStream_t st) {
+void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts) {
   uint32_t* misc = at<uint32_t>(ws, L.o_misc);
+  const uint32_t* mpart = mask_parts ? at<const uint32_t>(ws, L.o_mpart) : nullptr;
+  const int nmb = mask_parts ? mask_chunks(L) : 0;
+  uint32_t* mcount = at<uint32_t>(ws, L.o_mcount);
   if ((int64_t)L.V * L.nb <= kSmallScan) {
-    hipLaunchKernelGGL(k_scan_part, dim3(2), dim3(1024), 0, st, at<uint32_t>(ws, L.o_part),
-                       at<uint32_t>(ws, L.o_partv), (int64_t)L.V * L.nb, misc, L.cap, L.scap);
+    hipLaunchKernelGGL(k_scan_part, dim3(mask_parts ? 3 : 2), dim3(1024), 0, st,
+                       at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
+                       (int64_t)L.V * L.nb, misc, L.cap, L.scap, mpart, nmb, L.V, mcount);
     return;
   }
   scan_u32(at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_part), (int64_t)L.V * L.nb,
            misc + kMiscPairs, at<uint32_t>(ws, L.o_parttmp), st);
   scan_u32(at<uint32_t>(ws, L.o_partv), at<uint32_t>(ws, L.o_partv), (int64_t)L.V * L.nb,
            misc + kMiscVisible, at<uint32_t>(ws, L.o_parttmp), st);
-  hipLaunchKernelGGL(k_check_cap, dim3(1), dim3(64), 0, st, misc, L.cap, L.scap);
+  hipLaunchKernelGGL(k_check_cap, dim3(1), dim3(64), 0, st, misc, L.cap, L.scap, mpart, nmb, L.V,
+                     mcount);
 }
 
 }  // namespace rogs

@@ -15,6 +15,7 @@ constexpr int kProjBlock = 256;     // threads per block of the per-surfel kerne
 constexpr int kSortBlock = 256;     // threads per radix-sort block
 constexpr int kSortTileMin = kSortBlock * 4;   // fewest keys per radix-sort block (sizes the tables)
 constexpr int kRadixMax = 512;     // largest radix of the sorts (9-bit digits)
+constexpr int kMaskChunk = 8192;   // mask bytes per side block of the projection launch
 constexpr int kScanChunk = 4096;    // elements per block of the generic scan
 constexpr int kMaxViews = 4096;
 
@@ -54,12 +55,18 @@ struct Layout {
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_spair;              // slot of each tile-sorted pair
   size_t o_tinfo;              // per launch position: tile, list begin, list end, view
+  size_t o_mpart = 0;          // fused path: per-view mask counts of the projection's side blocks
   size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
   size_t o_hist, o_histtmp, o_misc, o_lpart, o_mcount;
   size_t o_tpart = 0, o_status = 0;   // fused path only (0 = absent)
   size_t total = 0;
 };
+
+// Side blocks per view of the fused projection launch that count mask bytes.
+inline int mask_chunks(const Layout& L) {
+  return (int)((L.max_view_pix + kMaskChunk - 1) / kMaskChunk);
+}
 
 // misc counters (uint32 slots at o_misc)
 // misc words: pair count, overflow flag, visible-slot count, long-slot count,
@@ -561,12 +568,13 @@ struct AdamArgs {
 // ------------------------------------------------------------------ launchers
 
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
-                    hipStream_t st);
-void launch_scan_part(const Layout& L, void* ws, hipStream_t st);
+                    hipStream_t st, const uint8_t* mask = nullptr);
+void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts = false);
 // Compaction and depth sort of the visible slots, emission, sort of the pairs
 // by tile.  Counts < 0 are read on the device.  Returns the buffer parity.
 int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st);
-void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st);
+void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st,
+                   bool ranges_cleared = false);
 void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st);
 int64_t elev_reg_blocks(int n);
 void launch_elev_reg(int n, const float* z, const int32_t* nbr, float lam_s, const float* zbar,

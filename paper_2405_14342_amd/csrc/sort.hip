@@ -589,9 +589,10 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
                                  p_grid, L.cap, L.tile_bits, hist, histtmp, st);
 }
 
-void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st) {
+void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st,
+                   bool ranges_cleared) {
   uint2* ranges = at<uint2>(ws, L.o_ranges);
-  fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.total_tiles, st);
+  if (!ranges_cleared) fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.total_tiles, st);
   const uint32_t* n_dev = n_host < 0 ? at<uint32_t>(ws, L.o_misc) + kMiscEmit : nullptr;
   const int64_t n_grid = n_host < 0 ? L.cap : n_host;
   if (n_grid > 0)
