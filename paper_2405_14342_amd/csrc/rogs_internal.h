@@ -624,8 +624,12 @@ void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
               hipStream_t st);
 // Same with the count read on the device (at most n_cap).
-void scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
-                  uint32_t* tmp, hipStream_t st);
+// Exclusive scan of the first min(*n_dev, n_cap) values.  With bstart, also
+// the element holding each block start b * bpairs (b < nblk); returns whether
+// it wrote them (small tables take a one-block scan that does not).
+bool scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
+                  uint32_t* tmp, hipStream_t st, uint32_t* bstart = nullptr, uint32_t nblk = 0,
+                  uint32_t bpairs = 1);
 
 size_t scan_tmp_words(int64_t n);
 // Stores msg as the context's last error and returns code.

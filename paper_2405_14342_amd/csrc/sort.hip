@@ -83,7 +83,8 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
     int shift, uint32_t mask, int nbits, const uint32_t* __restrict__ hist_scan, int64_t nblk,
-    const uint32_t* __restrict__ tot) {
+    const uint32_t* __restrict__ tot, const uint32_t* __restrict__ gcnt,
+    uint32_t* __restrict__ gscnt, uint32_t* __restrict__ gpos) {
   static_assert(kSortBlock == kProjBlock, "block scan width");
   constexpr int R = 1 << RB;
   constexpr int kWaves = kSortBlock / 64;
@@ -158,8 +159,13 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
       const int64_t idx = base + (int64_t)wv * kPerWave + it * 64 + lane;
       if (idx < (int64_t)n) {
         uint32_t dst = wcnt[wv][dig[it]] + rank[it];
+        const uint32_t val = vin[idx];
         kout[dst] = kin[idx];
-        vout[dst] = vin[idx];
+        vout[dst] = val;
+        if (gcnt) {          // last pass of the slot sort: counts in sorted order
+          gscnt[dst] = gcnt[val];
+          gpos[val] = dst;
+        }
       }
     }
     return;
@@ -208,8 +214,13 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
     const K key = s_key[i];
     const uint32_t d = (uint32_t)(key >> shift) & mask;
     const uint32_t dst = s_base[d] + (uint32_t)i - s_loc[d];
+    const uint32_t val = s_val[i];
     kout[dst] = key;
-    vout[dst] = s_val[i];
+    vout[dst] = val;
+    if (gcnt) {
+      gscnt[dst] = gcnt[val];
+      gpos[val] = dst;
+    }
   }
 }
 
@@ -218,7 +229,9 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
 // alternate buffers, 0 when it is back in keys / vals.
 template <typename K, int RB, int IPT, bool STAGE>
 int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, int64_t n_host,
-               int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st) {
+               int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st,
+               const uint32_t* gcnt = nullptr, uint32_t* gscnt = nullptr,
+               uint32_t* gpos = nullptr) {
   const int passes = (key_bits + RB - 1) / RB;
   const int width = (key_bits + passes - 1) / passes;
   const int64_t n_grid = n_dev ? cap : n_host;
@@ -233,8 +246,10 @@ int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, 
     hipLaunchKernelGGL((k_hist<K, RB, IPT>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
                        n_grid, cap, shift, mask, hist, nblk);
     hipLaunchKernelGGL(k_colscan, dim3(1u << RB), dim3(kProjBlock), 0, st, hist, nblk, histtmp);
+    const bool last = p == passes - 1;
     hipLaunchKernelGGL((k_scatter<K, RB, IPT, STAGE>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
-                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp);
+                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp,
+                       last ? gcnt : nullptr, last ? gscnt : nullptr, last ? gpos : nullptr);
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;
   }
@@ -271,18 +286,6 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
       }
     }
   }
-}
-
-// Emission counts in depth order; pos[slot] = the slot's sorted position.
-__global__ void k_gather_cnt(const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
-                             const uint32_t* __restrict__ sval, const uint32_t* __restrict__ cnt,
-                             uint32_t* __restrict__ scnt, uint32_t* __restrict__ pos) {
-  const uint32_t n = count_n(n_dev, n_host, cap);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (int64_t)n) return;
-  const uint32_t slot = sval[k];
-  scnt[k] = cnt[slot];
-  pos[slot] = (uint32_t)k;
 }
 
 // Emission in depth-sorted slot order, balanced by pairs: block b writes the
@@ -552,26 +555,31 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
   unsigned long long* sk2 = at<unsigned long long>(ws, L.o_keys2);   // free until emission
   uint32_t* sv = at<uint32_t>(ws, L.o_sval);
   uint32_t* sv2 = at<uint32_t>(ws, L.o_vals2);
+  // the last pass also writes each sorted slot's emission count and the
+  // slot's sorted position
+  uint32_t* scnt = at<uint32_t>(ws, L.o_scnt);
+  uint32_t* soff = at<uint32_t>(ws, L.o_soff);
   if (radix_sort<unsigned long long, 9, 4, false>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
-                                        hist, histtmp, st)) {
+                                        hist, histtmp, st, at<const uint32_t>(ws, L.o_cnt), scnt,
+                                        at<uint32_t>(ws, L.o_pos))) {
     sv = sv2;
   }
   // 3. emission offsets in depth order
-  uint32_t* scnt = at<uint32_t>(ws, L.o_scnt);
-  uint32_t* soff = at<uint32_t>(ws, L.o_soff);
   uint32_t* n_emit = p_dev ? misc + kMiscEmit : nullptr;
-  if (s_grid > 0) {
-    hipLaunchKernelGGL(k_gather_cnt, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0, st,
-                       s_dev, s_grid, L.scap, sv, at<const uint32_t>(ws, L.o_cnt), scnt,
-                       at<uint32_t>(ws, L.o_pos));
-    scan_u32_dev(scnt, soff, s_dev, s_grid, at<uint32_t>(ws, L.o_parttmp2), st);
-  }
   // 4. one key per covered tile
+  const uint32_t nblk_emit = (uint32_t)((p_grid + kEmitPairs - 1) / kEmitPairs);
+  bool starts = false;
+  if (s_grid > 0)
+    starts = scan_u32_dev(scnt, soff, s_dev, s_grid, at<uint32_t>(ws, L.o_parttmp2), st,
+                          p_grid > 0 ? at<uint32_t>(ws, L.o_bstart) : nullptr, nblk_emit,
+                          (uint32_t)kEmitPairs);
   if (p_grid > 0) {
     if (s_grid > 0) {
-      const uint32_t nblk = (uint32_t)((p_grid + kEmitPairs - 1) / kEmitPairs);
-      hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0, st,
-                         s_dev, s_grid, L.scap, soff, scnt, nblk, at<uint32_t>(ws, L.o_bstart));
+      const uint32_t nblk = nblk_emit;
+      if (!starts)
+        hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0,
+                           st, s_dev, s_grid, L.scap, soff, scnt, nblk,
+                           at<uint32_t>(ws, L.o_bstart));
       hipLaunchKernelGGL(k_emit, dim3((unsigned)((p_grid + kEmitPairs - 1) / kEmitPairs)),
                          dim3(kEmitThreads), 0, st, at<const ViewDev>(ws, L.o_views), L.N, p_dev,
                          p_grid, s_dev, s_grid, L.scap, L.cap, sv, soff, scnt,
