@@ -499,12 +499,27 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __re
 
 // Compositing work item of each launch position b: (tile, list begin, list
 // end, view) of the tile order[b], so a compositing wave starts from one load.
+// Inside each length bucket the launch positions are permuted in blocks of 64
+// (an 8 x 8 transpose), so that runs of 8 consecutive tiles of the order (one
+// tile row, mostly the same surfels) take launch positions 8 apart.  The
+// workgroups of one launch go to the 8 XCDs in turn, so such a run is
+// composited by one XCD and its surfels' records stay in that XCD's L2.
 __global__ void k_tile_info(const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
                             const ViewDev* __restrict__ views, int V, int64_t T,
+                            const uint32_t* __restrict__ bucket_tot, int nbucket,
                             uint4* __restrict__ tinfo) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= T) return;
-  const uint32_t gt = order[b];
+  int64_t start = 0, size = 0;
+  for (int d = 0; d < nbucket; ++d) {
+    const int64_t n = bucket_tot[d];
+    if (b < start + n) { size = n; break; }
+    start += n;
+  }
+  const int64_t q = b - start;
+  int64_t src = q;
+  if (q < (size & ~(int64_t)63)) src = (q & ~(int64_t)63) + 8 * (q & 7) + ((q >> 3) & 7);
+  const uint32_t gt = order[start + src];
   const uint2 r = ranges[gt];
   int lo = 0, hi = V - 1;
   while (lo < hi) {
@@ -623,7 +638,8 @@ void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {
                           at<uint32_t>(ws, L.o_hist), at<uint32_t>(ws, L.o_histtmp), st);
   hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
                      at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
-                     at<const ViewDev>(ws, L.o_views), L.V, T, at<uint4>(ws, L.o_tinfo));
+                     at<const ViewDev>(ws, L.o_views), L.V, T,
+                     at<const uint32_t>(ws, L.o_histtmp), 16, at<uint4>(ws, L.o_tinfo));
 }
 
 }  // namespace rogs
