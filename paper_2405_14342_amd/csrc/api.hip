@@ -180,13 +180,13 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_parttmp = take(4 * scan_tmp_words((int64_t)l.V * l.nb));
   l.o_parttmp2 = take(4 * scan_tmp_words(scap));
   l.o_keys = take(4 * (size_t)cap);          // tile of each pair
-  l.o_keys2 = take(8 * (size_t)cap);         // also scratch of the 64-bit slot sort
+  l.o_keys2 = take(4 * (size_t)cap);         // alternate keys of the pair sort
   l.o_vals = take(4 * (size_t)cap);
   l.o_vals2 = take(4 * (size_t)cap);
   l.o_pslot = take(4 * (size_t)cap);
   l.o_spair = take(4 * (size_t)cap);
+  l.o_pdep = take(4 * (size_t)cap);
   l.o_bstart = take(4 * ((size_t)cap / 1024 + 2));   // first slot of each emission block
-  l.o_skey = take(8 * (size_t)scap);         // visible slots (at most one per pair)
   l.o_sval = take(4 * (size_t)scap);
   l.o_scnt = take(4 * (size_t)scap);
   l.o_soff = take(4 * (size_t)scap);

@@ -54,9 +54,10 @@ struct Layout {
   size_t o_views, o_order, o_tkey, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_rspan, o_bstart, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_spair;              // slot of each tile-sorted pair
+  size_t o_pdep;               // t_z bits of each emitted pair (the tile sort's key)
   size_t o_tinfo;              // per launch position: tile, list begin, list end, view
   size_t o_mpart = 0;          // fused path: per-view mask counts of the projection's side blocks
-  size_t o_skey, o_sval, o_scnt, o_soff;       // visible slots in depth order
+  size_t o_sval, o_scnt, o_soff;               // visible slots in (view, surfel id) order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
   size_t o_hist, o_histtmp, o_misc, o_lpart, o_mcount;
   size_t o_tpart = 0, o_status = 0;   // fused path only (0 = absent)

@@ -1,13 +1,14 @@
-// Binning: depth order of the visible (view, surfel) slots, emission of one
-// (tile) key per covered tile in that order, a stable radix sort of the pairs
-// by tile, and per-tile ranges.  The result is every tile's list in ascending
-// order of original depth with ties by surfel id (Sec. 3.3.1).
+// Binning: the visible (view, surfel) slots in (view, surfel id) order,
+// emission of one (tile) key per covered tile in that order, a stable radix
+// sort of the pairs by tile, per-tile ranges, then each tile's list ordered by
+// depth inside the tile.  The result is every tile's list in ascending order
+// of original depth with ties by surfel id (Sec. 3.3.1).
 //
 // Stable LSD radix sort: per pass, per-block digit histograms (LDS atomics),
 // an exclusive scan of each digit's column of that table with the digit
 // totals (one block per digit), then a stable scatter.  A block owns
-// 256 * IPT consecutive keys (IPT = 4 for the slot sort, 8 for the pair sort,
-// so that even the slot sort fills the chip); the scatter starts each digit
+// 256 * IPT consecutive keys (IPT = 8 for the pair sort, 4 for the launch
+// order); the scatter starts each digit
 // at the scan of the totals plus its column entry, and each of its four waves
 // ranks a contiguous quarter, 64 keys at a time, finding lanes with equal
 // digits with one ballot per digit bit, so ranks follow the input order.  In
@@ -83,8 +84,7 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
     int shift, uint32_t mask, int nbits, const uint32_t* __restrict__ hist_scan, int64_t nblk,
-    const uint32_t* __restrict__ tot, const uint32_t* __restrict__ gcnt,
-    uint32_t* __restrict__ gscnt, uint32_t* __restrict__ gpos) {
+    const uint32_t* __restrict__ tot) {
   static_assert(kSortBlock == kProjBlock, "block scan width");
   constexpr int R = 1 << RB;
   constexpr int kWaves = kSortBlock / 64;
@@ -159,13 +159,8 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
       const int64_t idx = base + (int64_t)wv * kPerWave + it * 64 + lane;
       if (idx < (int64_t)n) {
         uint32_t dst = wcnt[wv][dig[it]] + rank[it];
-        const uint32_t val = vin[idx];
         kout[dst] = kin[idx];
-        vout[dst] = val;
-        if (gcnt) {          // last pass of the slot sort: counts in sorted order
-          gscnt[dst] = gcnt[val];
-          gpos[val] = dst;
-        }
+        vout[dst] = vin[idx];
       }
     }
     return;
@@ -214,13 +209,8 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
     const K key = s_key[i];
     const uint32_t d = (uint32_t)(key >> shift) & mask;
     const uint32_t dst = s_base[d] + (uint32_t)i - s_loc[d];
-    const uint32_t val = s_val[i];
     kout[dst] = key;
-    vout[dst] = val;
-    if (gcnt) {
-      gscnt[dst] = gcnt[val];
-      gpos[val] = dst;
-    }
+    vout[dst] = s_val[i];
   }
 }
 
@@ -229,9 +219,7 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(
 // alternate buffers, 0 when it is back in keys / vals.
 template <typename K, int RB, int IPT, bool STAGE>
 int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, int64_t n_host,
-               int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st,
-               const uint32_t* gcnt = nullptr, uint32_t* gscnt = nullptr,
-               uint32_t* gpos = nullptr) {
+               int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st) {
   const int passes = (key_bits + RB - 1) / RB;
   const int width = (key_bits + passes - 1) / passes;
   const int64_t n_grid = n_dev ? cap : n_host;
@@ -246,24 +234,23 @@ int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, 
     hipLaunchKernelGGL((k_hist<K, RB, IPT>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
                        n_grid, cap, shift, mask, hist, nblk);
     hipLaunchKernelGGL(k_colscan, dim3(1u << RB), dim3(kProjBlock), 0, st, hist, nblk, histtmp);
-    const bool last = p == passes - 1;
     hipLaunchKernelGGL((k_scatter<K, RB, IPT, STAGE>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
-                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp,
-                       last ? gcnt : nullptr, last ? gscnt : nullptr, last ? gpos : nullptr);
+                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp);
     K* tk = k0; k0 = k1; k1 = tk;
     uint32_t* tv = v0; v0 = v1; v1 = tv;
   }
   return passes & 1;
 }
 
-// Visible slots in (view, surfel) order with their (view, depth bits) keys.
+// Visible slots in (view, surfel) order, their emission counts, and each
+// slot's position in that order.
 __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
                                                         const uint32_t* __restrict__ cnt,
-                                                        const float4* __restrict__ rec,
                                                         const uint32_t* __restrict__ partv,
                                                         int64_t scap,
-                                                        unsigned long long* __restrict__ skey,
-                                                        uint32_t* __restrict__ sval) {
+                                                        uint32_t* __restrict__ sval,
+                                                        uint32_t* __restrict__ scnt,
+                                                        uint32_t* __restrict__ spos) {
   __shared__ uint32_t s_w[kProjBlock / 64];
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   const bool valid = i < N;
@@ -271,7 +258,8 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int v = 0; v < V; ++v) {
     const size_t slot = (size_t)v * N + i;
-    const bool vis = valid && cnt[slot] != 0;
+    const uint32_t c = valid ? cnt[slot] : 0u;
+    const bool vis = c != 0;
     const unsigned long long b = __ballot(vis);
     if (lane == 0) s_w[wv] = (uint32_t)__popcll(b);
     __syncthreads();
@@ -281,14 +269,15 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
     if (vis) {
       const uint32_t pos = pre + (uint32_t)__popcll(b & lt_mask);
       if ((int64_t)pos < scap) {
-        skey[pos] = ((unsigned long long)v << 32) | __float_as_uint(rec[2 * slot + 1].w);
         sval[pos] = (uint32_t)slot;
+        scnt[pos] = c;
+        spos[slot] = pos;
       }
     }
   }
 }
 
-// Emission in depth-sorted slot order, balanced by pairs: block b writes the
+// Emission in (view, surfel id) slot order, balanced by pairs: block b writes the
 // pairs e in [b * kEmitPairs, (b + 1) * kEmitPairs).  Its first slot comes from
 // k_emit_starts; the following slots that start before the block's end (each
 // visible slot has at least one pair, so the offsets are strictly increasing
@@ -358,10 +347,12 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const uint32_t* __restrict__ scnt, const uint2* __restrict__ rect,
     const uint16_t* __restrict__ rspan, const float4* __restrict__ rec, float qcut, int tw,
     int th, const uint32_t* __restrict__ bstart, uint32_t* __restrict__ keys,
-    uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ n_emit) {
+    uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ pdep,
+    uint32_t* __restrict__ n_emit) {
   static_assert(kEmitThreads == kProjBlock, "block scan width");
   __shared__ uint32_t s_off[kEmitPairs + 1];
   __shared__ uint32_t s_slot[kEmitPairs];
+  __shared__ uint32_t s_dep[kEmitPairs];        // t_z bits of each staged slot
   __shared__ uint32_t s_roff[kEmitPairs + 1];   // first row item of each slot
   __shared__ uint32_t s_rx[kEmitRows];          // row span length, then its first pair
   __shared__ uint32_t s_rinfo[kEmitRows];       // span start tile | tile row << 16
@@ -391,6 +382,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         const uint32_t slot = sval[ka + t];
         s_off[t] = o;
         s_slot[t] = slot;
+        s_dep[t] = __float_as_uint(rec[2 * (size_t)slot + 1].w);
         const uint2 r = rect[slot];
         nrow[k] = (r.y >> 16) - (r.y & 0xffff);
         mine += 1;
@@ -439,13 +431,15 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
       const uint32_t t = e - s_off[0];
       const int rr = last_le(s_rx, (int)R, t);
       const uint32_t info = s_rinfo[rr];
-      const uint32_t slot = s_slot[s_rslot[rr]];
+      const uint32_t js = s_rslot[rr];
+      const uint32_t slot = s_slot[js];
       const int tx = (int)(info & 0xffff) + (int)(t - s_rx[rr]);
       const int ty = (int)(info >> 16);
       const ViewDev& vw = views[slot / (uint32_t)N];
       keys[e] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
       vals[e] = e;
       pslot[e] = slot;
+      pdep[e] = s_dep[js];
     }
     return;
   }
@@ -479,26 +473,192 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     keys[e] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
     vals[e] = e;
     pslot[e] = slot;
+    pdep[e] = s_dep[j];
   }
 }
 
-// Per-tile list ranges of the sorted pairs, and the slot of each sorted pair
-// (so the compositing reads it without going through the emission index).
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                         const uint32_t* __restrict__ pslot, const uint32_t* __restrict__ n_dev,
-                         int64_t n_host, int64_t cap, uint2* __restrict__ ranges,
-                         uint32_t* __restrict__ spair) {
+// Per-tile list ranges of the sorted pairs.
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                         int64_t n_host, int64_t cap, uint2* __restrict__ ranges) {
   const uint32_t n = count_n(n_dev, n_host, cap);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n) return;
   const uint32_t t = keys[i];
   if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
   if (i == (int64_t)n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
-  spair[i] = pslot[vals[i]];
 }
 
 // Compositing work item of each launch position b: (tile, list begin, list
 // end, view) of the tile order[b], so a compositing wave starts from one load.
+// Depth order inside each tile.  The pair sort leaves a tile's list in
+// emission order, i.e. by surfel id (a tile belongs to one view); these
+// kernels reorder it by (t_z bits, list position), which is the binary32
+// depth with ties by id, and write each sorted pair's slot.  t_z > 0 for a
+// visible slot, so its bits order like its value.
+__device__ __forceinline__ bool key_less(uint32_t ka, uint32_t ia, uint32_t kb, uint32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+// Lists of 1 to 64 entries, packed by length: the launch order groups the
+// tiles by the bit length bl of their list length, so a wave takes 64 / 2^bl
+// consecutive tiles of one group, each on a segment of 2^bl lanes, and sorts
+// every segment with one bitonic network over (key, lane) (lanes are
+// distinct, so the order is strict; a segment's padding sorts last).  Work
+// items (waves) of a group: ceil(tiles / (64 / 2^bl)); the blocks stride
+// over all groups' items.  Lists of 65 or more entries (bl = 7 holds 64 to
+// 127) are left to k_tile_sort_long.
+__global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict__ tinfo,
+                                                        const uint32_t* __restrict__ bucket_tot,
+                                                        uint32_t* __restrict__ vals,
+                                                        const uint32_t* __restrict__ pslot,
+                                                        const uint32_t* __restrict__ pdep,
+                                                        uint32_t* __restrict__ spair) {
+  // launch-order buckets: key 15 - bl, so bucket d holds bit length 15 - d
+  __shared__ uint32_t s_start[16], s_cnt[16], s_items[16];
+  const int lane = threadIdx.x;
+  if (lane < 16) s_cnt[lane] = bucket_tot[lane];
+  __syncthreads();
+  if (lane == 0) {
+    uint32_t st = 0;
+    for (int d = 0; d < 16; ++d) {
+      const int bl = 15 - d;
+      s_start[d] = st;
+      st += s_cnt[d];
+      s_items[d] = 0u;
+      if (bl >= 1 && bl <= 7) {
+        const uint32_t per = 64u >> (bl == 7 ? 6 : bl);       // tiles per wave
+        s_items[d] = (s_cnt[d] + per - 1u) / per;
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t total = 0;
+  for (int d = 0; d < 16; ++d) total += s_items[d];
+  for (uint32_t w = blockIdx.x; w < total; w += gridDim.x) {
+    int d = 0;
+    uint32_t wi = w;
+    while (wi >= s_items[d]) { wi -= s_items[d]; ++d; }
+    const int bl = 15 - d;
+    const int S = bl == 7 ? 64 : (1 << bl);                    // segment lanes
+    const uint32_t per = 64u / (uint32_t)S;
+    const uint32_t pos = s_start[d] + wi * per + (uint32_t)(lane / S);
+    const uint32_t seg_lane = (uint32_t)(lane & (S - 1));
+    uint32_t beg = 0u, len = 0u;
+    if (pos < s_start[d] + s_cnt[d]) {
+      const uint4 ti = tinfo[pos];
+      beg = ti.y;
+      len = ti.z - ti.y;
+      if (len > 64u) len = 0u;                                 // k_tile_sort_long's
+    }
+    uint32_t e = 0u, slot = 0u, key = 0xffffffffu;
+    if (seg_lane < len) {
+      e = vals[beg + seg_lane];
+      slot = pslot[e];
+      key = pdep[e];
+    }
+    uint32_t idx = (uint32_t)lane;
+    for (int k = 2; k <= S; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const uint32_t ok = (uint32_t)__shfl_xor((int)key, j, 64);
+        const uint32_t oi = (uint32_t)__shfl_xor((int)idx, j, 64);
+        const bool keep_min = ((lane & j) == 0) == ((seg_lane & (uint32_t)k) == 0u);
+        const bool other_less = key_less(ok, oi, key, idx);
+        if (keep_min == other_less) {
+          key = ok;
+          idx = oi;
+        }
+      }
+    }
+    const uint32_t se = (uint32_t)__shfl((int)e, (int)idx, 64);
+    const uint32_t ss = (uint32_t)__shfl((int)slot, (int)idx, 64);
+    if (seg_lane < len) {
+      vals[beg + seg_lane] = se;
+      spair[beg + seg_lane] = ss;
+    }
+  }
+}
+
+// Lists of more than 64 entries, taken in launch order (longest first, so a
+// block stops at the first list shorter than 64): up to kLongSort entries in
+// an LDS bitonic network; longer lists by ranking every entry against all
+// others through the free sort buffers (quadratic, for rare extreme lists).
+constexpr int kLongSort = 4096;
+constexpr int kLongBlocks = 4096;
+constexpr int kShortBlocks = 16384;
+
+__global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict__ tinfo, int64_t T,
+                                                        uint32_t* __restrict__ vals,
+                                                        const uint32_t* __restrict__ pslot,
+                                                        const uint32_t* __restrict__ pdep,
+                                                        uint32_t* __restrict__ spair,
+                                                        uint32_t* __restrict__ tmpk,
+                                                        uint32_t* __restrict__ tmpv) {
+  __shared__ uint32_t s_k[kLongSort];
+  __shared__ uint32_t s_i[kLongSort];
+  __shared__ uint32_t s_e[kLongSort];
+  const int tid = threadIdx.x;
+  for (int64_t b = blockIdx.x; b < T; b += gridDim.x) {
+    const uint4 ti = tinfo[b];
+    const uint32_t beg = ti.y, len = ti.z - ti.y;
+    if (len < 64u) break;
+    if (len == 64u) continue;
+    if (len <= (uint32_t)kLongSort) {
+      uint32_t P = 128u;
+      while (P < len) P <<= 1;
+      for (uint32_t i = tid; i < P; i += 256u) {
+        uint32_t key = 0xffffffffu, e = 0u;
+        if (i < len) {
+          e = vals[beg + i];
+          key = pdep[e];
+        }
+        s_k[i] = key;
+        s_i[i] = i;
+        s_e[i] = e;
+      }
+      __syncthreads();
+      for (uint32_t k = 2u; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
+          for (uint32_t t = tid; t < (P >> 1); t += 256u) {
+            const uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));   // lower element
+            const uint32_t p = i | j;
+            const uint32_t ka = s_k[i], ia = s_i[i], kb = s_k[p], ib = s_i[p];
+            const bool up = (i & k) == 0u;
+            if (up == key_less(kb, ib, ka, ia)) {
+              s_k[i] = kb; s_i[i] = ib;
+              s_k[p] = ka; s_i[p] = ia;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t rk = tid; rk < len; rk += 256u) {
+        const uint32_t e = s_e[s_i[rk]];
+        vals[beg + rk] = e;
+        spair[beg + rk] = pslot[e];
+      }
+      __syncthreads();
+    } else {
+      for (uint32_t i = tid; i < len; i += 256u) {
+        tmpk[beg + i] = pdep[vals[beg + i]];
+      }
+      __syncthreads();
+      for (uint32_t i = tid; i < len; i += 256u) {
+        const uint32_t ki = tmpk[beg + i];
+        uint32_t rank = 0u;
+        for (uint32_t j = 0; j < len; ++j) rank += key_less(tmpk[beg + j], j, ki, i) ? 1u : 0u;
+        tmpv[beg + rank] = vals[beg + i];
+      }
+      __syncthreads();
+      for (uint32_t rk = tid; rk < len; rk += 256u) {
+        const uint32_t e = tmpv[beg + rk];
+        vals[beg + rk] = e;
+        spair[beg + rk] = pslot[e];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Inside each length bucket the launch positions are permuted in blocks of 64
 // (an 8 x 8 transpose), so that runs of 8 consecutive tiles of the order (one
 // tile row, mostly the same surfels) take launch positions 8 apart.  The
@@ -558,30 +718,17 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
   const int64_t p_grid = n_pairs < 0 ? L.cap : n_pairs;
   uint32_t* hist = at<uint32_t>(ws, L.o_hist);
   uint32_t* histtmp = at<uint32_t>(ws, L.o_histtmp);
-  // 1. visible slots with (view, depth) keys, in (view, surfel id) order
-  hipLaunchKernelGGL(k_compact, dim3(L.nb), dim3(kProjBlock), 0, st, L.V, L.N, L.nb,
-                     at<const uint32_t>(ws, L.o_cnt), at<const float4>(ws, L.o_rec),
-                     at<const uint32_t>(ws, L.o_partv), L.scap,
-                     at<unsigned long long>(ws, L.o_skey), at<uint32_t>(ws, L.o_sval));
-  // 2. stable sort by (view, depth): ties keep surfel-id order
-  int view_bits = 0;
-  while ((1 << view_bits) < L.V) ++view_bits;
-  unsigned long long* sk = at<unsigned long long>(ws, L.o_skey);
-  unsigned long long* sk2 = at<unsigned long long>(ws, L.o_keys2);   // free until emission
+  // 1. visible slots in (view, surfel id) order, with their emission counts
+  //    and each slot's position in that order
   uint32_t* sv = at<uint32_t>(ws, L.o_sval);
-  uint32_t* sv2 = at<uint32_t>(ws, L.o_vals2);
-  // the last pass also writes each sorted slot's emission count and the
-  // slot's sorted position
   uint32_t* scnt = at<uint32_t>(ws, L.o_scnt);
   uint32_t* soff = at<uint32_t>(ws, L.o_soff);
-  if (radix_sort<unsigned long long, 9, 4, false>(sk, sv, sk2, sv2, s_dev, s_grid, L.scap, 32 + view_bits,
-                                        hist, histtmp, st, at<const uint32_t>(ws, L.o_cnt), scnt,
-                                        at<uint32_t>(ws, L.o_pos))) {
-    sv = sv2;
-  }
-  // 3. emission offsets in depth order
+  hipLaunchKernelGGL(k_compact, dim3(L.nb), dim3(kProjBlock), 0, st, L.V, L.N, L.nb,
+                     at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_partv), L.scap, sv,
+                     scnt, at<uint32_t>(ws, L.o_pos));
+  // 2. emission offsets
   uint32_t* n_emit = p_dev ? misc + kMiscEmit : nullptr;
-  // 4. one key per covered tile
+  // 3. one key per covered tile
   const uint32_t nblk_emit = (uint32_t)((p_grid + kEmitPairs - 1) / kEmitPairs);
   bool starts = false;
   if (s_grid > 0)
@@ -601,12 +748,14 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
                          at<const uint2>(ws, L.o_rect), at<const uint16_t>(ws, L.o_rspan),
                          at<const float4>(ws, L.o_rec), L.q_cut,
                          L.tw, L.th, at<const uint32_t>(ws, L.o_bstart), at<uint32_t>(ws, L.o_keys),
-                         at<uint32_t>(ws, L.o_vals), at<uint32_t>(ws, L.o_pslot), n_emit);
+                         at<uint32_t>(ws, L.o_vals), at<uint32_t>(ws, L.o_pslot),
+                         at<uint32_t>(ws, L.o_pdep), n_emit);
     } else if (n_emit) {
       fill_u32(n_emit, 0u, 1, st);
     }
   }
-  // 5. stable sort of the pairs by tile
+  // 4. stable sort of the pairs by tile (each tile's list stays in id order;
+  //    launch_ranges orders it by depth)
   return radix_sort<uint32_t, 9, 8, true>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
                                  at<uint32_t>(ws, L.o_keys2), at<uint32_t>(ws, L.o_vals2), n_emit,
                                  p_grid, L.cap, L.tile_bits, hist, histtmp, st);
@@ -620,10 +769,20 @@ void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st,
   const int64_t n_grid = n_host < 0 ? L.cap : n_host;
   if (n_grid > 0)
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_grid + 255) / 256)), dim3(256), 0, st,
-                       at<const uint32_t>(ws, L.o_keys), at<const uint32_t>(ws, L.o_vals),
-                       at<const uint32_t>(ws, L.o_pslot), n_dev, n_grid, L.cap, ranges,
-                       at<uint32_t>(ws, L.o_spair));
+                       at<const uint32_t>(ws, L.o_keys), n_dev, n_grid, L.cap, ranges);
   launch_tile_order(L, ws, st);
+  // each tile's list by depth, and the slot of every sorted pair
+  const int64_t T = L.total_tiles;
+  hipLaunchKernelGGL(k_tile_sort_short, dim3((unsigned)std::min<int64_t>(T, kShortBlocks)),
+                     dim3(64), 0, st, at<const uint4>(ws, L.o_tinfo),
+                     at<const uint32_t>(ws, L.o_histtmp), at<uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_pslot), at<const uint32_t>(ws, L.o_pdep),
+                     at<uint32_t>(ws, L.o_spair));
+  hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)std::min<int64_t>(T, kLongBlocks)), dim3(256),
+                     0, st, at<const uint4>(ws, L.o_tinfo), T, at<uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_pslot), at<const uint32_t>(ws, L.o_pdep),
+                     at<uint32_t>(ws, L.o_spair), at<uint32_t>(ws, L.o_keys2),
+                     at<uint32_t>(ws, L.o_vals2));
 }
 
 void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {

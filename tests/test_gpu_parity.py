@@ -50,6 +50,14 @@ def make_scene(name):
         sc.cams = [synth.ortho_bev_camera((p[0], p[1]), 20.0, 200, 136, m_per_px=0.05)]
         sc.targets = synth._targets(sc.cams, sc.n_sem, 9000, 0.9)
         return sc
+    if name == "stack":
+        # 6400 surfels squeezed into a 8 cm square: one tile's list holds all
+        # of them (ranked through global memory), neighbours hold hundreds
+        # to thousands (sorted in LDS), the rest a few (sorted in one wave)
+        sc = synth.tiny_scene(nx=80, ny=80, n_sem=2, w=64, h=48, f=60.0, seed=33)
+        sc.x[:] = (1.0 + 0.001 * (sc.x - sc.x.min()) / synth.SPACING).astype(np.float32)
+        sc.y[:] = (0.001 * (sc.y - sc.y.mean()) / synth.SPACING).astype(np.float32)
+        return sc
     raise KeyError(name)
 
 
@@ -92,7 +100,7 @@ def test_projection_records_bitexact(gpu, name):
         assert np.all(cnt[v][vis] <= (r[:, 1] - r[:, 0]) * (r[:, 3] - r[:, 2]))
 
 
-@pytest.mark.parametrize("name", SCENES)
+@pytest.mark.parametrize("name", SCENES + ["stack"])
 def test_keys_order_ranges_bitexact(gpu, name):
     sc = make_scene(name)
     st, ws, n = batched_state(sc)
@@ -139,7 +147,7 @@ def fwd_compare(sc, st, opts=None, views=None):
     return worst
 
 
-@pytest.mark.parametrize("name", SCENES)
+@pytest.mark.parametrize("name", SCENES + ["stack"])
 def test_forward_matches_oracle(gpu, name):
     sc = make_scene(name)
     st = TrainState(sc)
