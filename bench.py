@@ -40,18 +40,15 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) 
     if kernel == "project":
         return N * (40 + 4 * FS) + slots * 4 + S * 40
     if kernel == "sort":
-        # compaction (counts, depth keys) + depth sort of the S visible slots
-        # (64-bit keys, digits of at most 9 bits) + emission offsets + one
-        # tile key, value and slot per pair + tile sort of the pairs (32-bit
-        # keys)
-        view_bits = max(0, (V - 1).bit_length())
-        s_passes = (32 + view_bits + 8) // 9
-        return slots * 4 + S * 16 + s_passes * S * 32 + S * 24 + P * 12 + passes * P * 20
+        # compaction (slot, count, position of each visible slot) + emission
+        # offsets + one tile key, value, slot and depth key per pair + tile
+        # sort of the pairs (32-bit keys)
+        return slots * 4 + S * 12 + S * 8 + P * 16 + passes * P * 20
     if kernel == "ranges":
-        # tile ranges from the sorted keys, each sorted pair's slot (emission
-        # index and slot read, slot written), the launch order and the
-        # per-tile work items
-        return P * 20 + stats["tiles"] * 36
+        # tile ranges from the sorted keys, the launch order and the per-tile
+        # work items, then the depth order inside each tile (emission index,
+        # slot and depth key read, emission index and slot written per pair)
+        return P * 4 + stats["tiles"] * 36 + P * 20
     if kernel == "render_step":
         # fused forward + loss + backward of a tile: targets (12 B colour,
         # label, mask) in, the work item of each tile (16 B), the slot and
