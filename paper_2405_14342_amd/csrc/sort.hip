@@ -616,8 +616,32 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
         s_e[i] = e;
       }
       __syncthreads();
-      for (uint32_t k = 2u; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
+      // distances below 64 stay inside a wave's 64-element chunk: those steps
+      // run on registers with cross-lane exchanges, the longer ones on LDS
+      const int lane = tid & 63, wave = tid >> 6;
+      auto chunk_steps = [&](uint32_t kfrom, uint32_t kto) {   // stages kfrom ... kto
+        for (uint32_t c = (uint32_t)wave; c < (P >> 6); c += 4u) {
+          const uint32_t gi = (c << 6) | (uint32_t)lane;
+          uint32_t key = s_k[gi], idx = s_i[gi];
+          for (uint32_t kk = kfrom; kk <= kto; kk <<= 1) {
+            for (uint32_t j = min(kk >> 1, 32u); j > 0u; j >>= 1) {
+              const uint32_t ok = (uint32_t)__shfl_xor((int)key, (int)j, 64);
+              const uint32_t oi = (uint32_t)__shfl_xor((int)idx, (int)j, 64);
+              const bool keep_min = (((uint32_t)lane & j) == 0u) == ((gi & kk) == 0u);
+              if (keep_min == key_less(ok, oi, key, idx)) {
+                key = ok;
+                idx = oi;
+              }
+            }
+          }
+          s_k[gi] = key;
+          s_i[gi] = idx;
+        }
+        __syncthreads();
+      };
+      chunk_steps(2u, 64u);
+      for (uint32_t k = 128u; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= 64u; j >>= 1) {
           for (uint32_t t = tid; t < (P >> 1); t += 256u) {
             const uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));   // lower element
             const uint32_t p = i | j;
@@ -630,6 +654,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
           }
           __syncthreads();
         }
+        chunk_steps(k, k);
       }
       for (uint32_t rk = tid; rk < len; rk += 256u) {
         const uint32_t e = s_e[s_i[rk]];
