@@ -159,7 +159,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   int tb = 1;
   while ((int64_t(1) << tb) < l.total_tiles) ++tb;
   l.tile_bits = tb;
-  l.sort_blocks = std::max<int64_t>(1, (std::max<int64_t>(cap, l.total_tiles) + kSortTileMin - 1) /
+  l.sort_blocks = std::max<int64_t>(1, (l.total_tiles + kSortTileMin - 1) /
                                             kSortTileMin);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
@@ -186,6 +186,9 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_pslot = take(4 * (size_t)cap);
   l.o_spair = take(4 * (size_t)cap);
   l.o_pdep = take(4 * (size_t)cap);
+  l.o_tcnt = take(4 * (size_t)l.total_tiles);
+  l.o_tstart = take(4 * (size_t)l.total_tiles);
+  l.o_tscan = take(4 * scan_tmp_words(l.total_tiles));
   l.o_bstart = take(4 * ((size_t)cap / 1024 + 2));   // first slot of each emission block
   l.o_sval = take(4 * (size_t)scap);
   l.o_scnt = take(4 * (size_t)scap);
@@ -520,14 +523,10 @@ int rogs_bin_sort(rogs_ctx* c, void* ws, int64_t* n_pairs_out, uint32_t flags, v
   }
   Layout& L = c->L;
   prof_begin(c, 3, st);
-  int alt = rogs::launch_binning(L, ws, n_host, n_vis, st);
+  rogs::launch_binning(L, ws, n_host, n_vis, st);
   prof_end(c, st);
-  if (alt) {
-    std::swap(L.o_keys, L.o_keys2);
-    std::swap(L.o_vals, L.o_vals2);
-  }
   prof_begin(c, 4, st);
-  rogs::launch_ranges(L, ws, n_host, st);
+  rogs::launch_ranges(L, ws, st);
   prof_end(c, st);
   r = check_launch(c, "rogs_bin_sort");
   if (r != ROGS_OK) return r;
@@ -640,12 +639,12 @@ int rogs_debug_pairs(rogs_ctx* c, void* ws, uint64_t* keys, int32_t* surfel_ids,
   if (P > L.cap) P = L.cap;
   if (cap < P || !keys || !surfel_ids || !views) return fail(c, ROGS_EINVAL, "output capacity too small");
   if (ranges && n_tiles < L.total_tiles) return fail(c, ROGS_EINVAL, "ranges capacity too small");
-  std::vector<uint32_t> tiles(P), vals(P), pslot(P);
+  std::vector<uint32_t> tiles(P), vals(P), pslot(P), rg(2 * (size_t)L.total_tiles);
   std::vector<float> rec(8 * (size_t)L.slots);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = hipSuccess;
+  hipError_t e = hipMemcpyAsync(rg.data(), rogs::at<void>(ws, L.o_ranges), 8 * L.total_tiles,
+                                hipMemcpyDeviceToHost, st);
   if (P > 0) {
-    e = hipMemcpyAsync(tiles.data(), rogs::at<void>(ws, L.o_keys), 4 * P, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(vals.data(), rogs::at<void>(ws, L.o_vals), 4 * P, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
@@ -654,11 +653,12 @@ int rogs_debug_pairs(rogs_ctx* c, void* ws, uint64_t* keys, int32_t* surfel_ids,
       e = hipMemcpyAsync(rec.data(), rogs::at<void>(ws, L.o_rec), 32 * (size_t)L.slots,
                          hipMemcpyDeviceToHost, st);
   }
-  if (e == hipSuccess && ranges)
-    e = hipMemcpyAsync(ranges, rogs::at<void>(ws, L.o_ranges), 8 * L.total_tiles,
-                       hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(c, e, "rogs_debug_pairs");
+  if (ranges) memcpy(ranges, rg.data(), 8 * (size_t)L.total_tiles);
+  // tile of each sorted position, from the ranges (they partition [0, P))
+  for (int64_t t = 0; t < L.total_tiles; ++t)
+    for (uint32_t k = rg[2 * t]; k < rg[2 * t + 1] && (int64_t)k < P; ++k) tiles[k] = (uint32_t)t;
   for (int64_t k = 0; k < P; ++k) {
     const uint32_t sl = pslot[vals[k]];
     surfel_ids[k] = (int32_t)(sl % (uint32_t)L.N);
@@ -762,21 +762,17 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
                    const rogs_optim* o, void* ws, hipStream_t st) {
   rogs_surfels s = fused_surfels(t);
   prof_begin(c, 0, st);
-  // the same launch counts the loss mask per view and clears the tile ranges
+  // the same launch counts the loss mask per view and clears the tile counters
   rogs::launch_project(L, ws, &s, true, st, tg->mask);
   prof_end(c, st);
   prof_begin(c, 1, st);
   rogs::launch_scan_part(L, ws, st, true);
   prof_end(c, st);
   prof_begin(c, 3, st);
-  int alt = rogs::launch_binning(L, ws, -1, -1, st);
+  rogs::launch_binning(L, ws, -1, -1, st, true);
   prof_end(c, st);
-  if (alt) {
-    std::swap(L.o_keys, L.o_keys2);
-    std::swap(L.o_vals, L.o_vals2);
-  }
   prof_begin(c, 4, st);
-  rogs::launch_ranges(L, ws, -1, st, true);
+  rogs::launch_ranges(L, ws, st);
   prof_end(c, st);
   rogs::FusedLoss fl;
   fl.tgt = tg->rgb;

@@ -19,7 +19,7 @@ __device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t x) {
 // Extra blocks of the fused step's projection launch, block (nb + c, v):
 // the nonzero bytes of chunk c (kMaskChunk bytes) of view v's loss mask into
 // mpart[v * nmb + c] (summed per view by the count-table scan), and a share
-// of clearing the n_zero words of the tile-range table.  Work the step needs
+// of clearing the n_zero per-tile pair counters.  Work the step needs
 // anyway, done here instead of in two launches of its own.
 __device__ void project_side_block(const ViewDev* __restrict__ views, int V, int nb,
                                    const uint8_t* __restrict__ mask, int nmb,
@@ -432,8 +432,8 @@ void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_
                      at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
                      at<float>(ws, L.o_feat), mask, nmb,
                      mask ? at<uint32_t>(ws, L.o_mpart) : nullptr,
-                     mask ? at<uint32_t>(ws, L.o_ranges) : nullptr,
-                     mask ? 2 * L.total_tiles : (int64_t)0);
+                     mask ? at<uint32_t>(ws, L.o_tcnt) : nullptr,
+                     mask ? L.total_tiles : (int64_t)0);
 }
 
 void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts) {

@@ -49,12 +49,13 @@ struct Layout {
   int64_t total_pix = 0, total_tiles = 0, max_view_pix = 0, max_view_tiles = 0, cap = 0;
   int64_t scap = 0;            // visible-slot capacity (<= cap)
   int64_t slots = 0;           // V * N
-  int64_t sort_blocks = 0;     // ceil(max(cap, tiles) / kSortTileMin)
+  int64_t sort_blocks = 0;     // ceil(tiles / kSortTileMin)
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
   size_t o_views, o_order, o_tkey, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_rspan, o_bstart, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_spair;              // slot of each tile-sorted pair
   size_t o_pdep;               // t_z bits of each emitted pair (the tile sort's key)
+  size_t o_tcnt, o_tstart, o_tscan;   // pairs per tile, first list position, scan partials
   size_t o_tinfo;              // per launch position: tile, list begin, list end, view
   size_t o_mpart = 0;          // fused path: per-view mask counts of the projection's side blocks
   size_t o_sval, o_scnt, o_soff;               // visible slots in (view, surfel id) order
@@ -571,11 +572,14 @@ struct AdamArgs {
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
                     hipStream_t st, const uint8_t* mask = nullptr);
 void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts = false);
-// Compaction and depth sort of the visible slots, emission, sort of the pairs
-// by tile.  Counts < 0 are read on the device.  Returns the buffer parity.
-int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st);
-void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st,
-                   bool ranges_cleared = false);
+// Compaction of the visible slots, emission with per-tile counting, the
+// tiles' first list positions and the pairs grouped by tile (o_vals).  Counts
+// < 0 are read on the device.  counts_cleared: the per-tile counters were
+// zeroed by the projection launch.
+void launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st,
+                    bool counts_cleared = false);
+// Tile ranges, compositing launch order and each tile's list by depth.
+void launch_ranges(const Layout& L, void* ws, hipStream_t st);
 void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st);
 int64_t elev_reg_blocks(int n);
 void launch_elev_reg(int n, const float* z, const int32_t* nbr, float lam_s, const float* zbar,

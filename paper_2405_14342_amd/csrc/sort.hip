@@ -277,6 +277,46 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
   }
 }
 
+// Ranks of pairs among the pairs of their tiles, from the tiles' counters,
+// for kR rounds of one wave at once: in each round the lanes that hold the
+// same tile form one group whose lowest lane adds the group's size, and each
+// lane's rank is the count before that add plus its place among the group's
+// lanes.  The adds of all rounds are issued before the first result is used,
+// so the wave waits for one atomic round trip, not kR.  Per tile the ranks
+// are a permutation of 0 ... count - 1 whose order depends on timing; the
+// depth sort inside each tile (key t_z bits, then emission index) removes it.
+// Every lane of the wave calls this together (act = holds a pair).
+template <int kR>
+__device__ __forceinline__ void tile_ranks(uint32_t* __restrict__ tcnt, const uint32_t (&t)[kR],
+                                           const bool (&act)[kR], uint32_t (&rank)[kR]) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  uint32_t lead[kR], base[kR];
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    unsigned long long todo = __ballot(act[r]);
+    uint32_t size = 0u;
+    lead[r] = 0u;
+    rank[r] = 0u;
+    while (todo) {
+      const int l = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t tl = (uint32_t)__builtin_amdgcn_readlane((int)t[r], l);
+      const bool mine = act[r] && t[r] == tl;
+      const unsigned long long grp = __ballot(mine);
+      if (mine) {
+        lead[r] = (uint32_t)l;
+        rank[r] = (uint32_t)__popcll(grp & lt);
+        size = (uint32_t)__popcll(grp);
+      }
+      todo &= ~grp;
+    }
+    base[r] = 0u;
+    if (act[r] && lane == lead[r]) base[r] = atomicAdd(&tcnt[t[r]], size);
+  }
+#pragma unroll
+  for (int r = 0; r < kR; ++r) rank[r] += (uint32_t)__shfl((int)base[r], (int)lead[r], 64);
+}
+
 // Emission in (view, surfel id) slot order, balanced by pairs: block b writes the
 // pairs e in [b * kEmitPairs, (b + 1) * kEmitPairs).  Its first slot comes from
 // k_emit_starts; the following slots that start before the block's end (each
@@ -287,10 +327,11 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
 // slot has more rows or a wider rectangle than a descriptor holds), an
 // exclusive scan turns the span lengths into pair offsets, and each pair
 // finds its row by binary search.  A block whose slots hold more
-// than kEmitRows rows walks each pair's rows instead.  Per pair: key = global
-// tile, value = e, pslot[e] = slot.  The number of pairs written (the pair
+// than kEmitRows rows walks each pair's rows instead.  Per pair e: keys[e] =
+// global tile, rank[e] = its rank in that tile's counter tcnt, pslot[e] =
+// slot, pdep[e] = the slot's t_z bits.  The number of pairs written (the pair
 // count, clipped to the capacity and to the pairs of the slots within the
-// slot capacity) goes to *n_emit for the sort.
+// slot capacity) goes to *n_emit.
 constexpr int kEmitThreads = 256;
 constexpr int kEmitPairs = 1024;
 constexpr int kEmitRows = 2048;
@@ -347,8 +388,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const uint32_t* __restrict__ scnt, const uint2* __restrict__ rect,
     const uint16_t* __restrict__ rspan, const float4* __restrict__ rec, float qcut, int tw,
     int th, const uint32_t* __restrict__ bstart, uint32_t* __restrict__ keys,
-    uint32_t* __restrict__ vals, uint32_t* __restrict__ pslot, uint32_t* __restrict__ pdep,
-    uint32_t* __restrict__ n_emit) {
+    uint32_t* __restrict__ rank, uint32_t* __restrict__ pslot, uint32_t* __restrict__ pdep,
+    uint32_t* __restrict__ tcnt, uint32_t* __restrict__ n_emit) {
   static_assert(kEmitThreads == kProjBlock, "block scan width");
   __shared__ uint32_t s_off[kEmitPairs + 1];
   __shared__ uint32_t s_slot[kEmitPairs];
@@ -427,74 +468,102 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     }
     __syncthreads();
     emit_scan(s_rx, (int)R, s_w);                 // pair offsets from the first slot's first pair
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kEmitThreads) {
-      const uint32_t t = e - s_off[0];
-      const int rr = last_le(s_rx, (int)R, t);
-      const uint32_t info = s_rinfo[rr];
-      const uint32_t js = s_rslot[rr];
-      const uint32_t slot = s_slot[js];
-      const int tx = (int)(info & 0xffff) + (int)(t - s_rx[rr]);
-      const int ty = (int)(info >> 16);
-      const ViewDev& vw = views[slot / (uint32_t)N];
-      keys[e] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
-      vals[e] = e;
-      pslot[e] = slot;
-      pdep[e] = s_dep[js];
+    // pair e0 + threadIdx.x + r * kEmitThreads in round r
+    uint32_t tile[kPer], rk[kPer];
+    bool act[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const uint32_t e = e0 + threadIdx.x + (uint32_t)(r * kEmitThreads);
+      act[r] = e < e1;
+      tile[r] = 0u;
+      if (act[r]) {
+        const uint32_t t = e - s_off[0];
+        const int rr = last_le(s_rx, (int)R, t);
+        const uint32_t info = s_rinfo[rr];
+        const uint32_t js = s_rslot[rr];
+        const uint32_t slot = s_slot[js];
+        const int tx = (int)(info & 0xffff) + (int)(t - s_rx[rr]);
+        const int ty = (int)(info >> 16);
+        const ViewDev& vw = views[slot / (uint32_t)N];
+        tile[r] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
+        keys[e] = tile[r];
+        pslot[e] = slot;
+        pdep[e] = s_dep[js];
+      }
     }
+    tile_ranks<kPer>(tcnt, tile, act, rk);
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+      if (act[r]) rank[e0 + threadIdx.x + (uint32_t)(r * kEmitThreads)] = rk[r];
     return;
   }
-  for (uint32_t e = e0 + threadIdx.x; e < e1; e += kEmitThreads) {
-    const int j = last_le(s_off, ns, e);
-    const uint32_t slot = s_slot[j];
-    const uint2 r = rect[slot];
-    const int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
-    const ViewDev& vw = views[slot / (uint32_t)N];
-    const bool desc = span_desc_ok(x0, x1, y0, y1);
-    const Span sp = desc ? Span{} : emit_span(rec, slot, qcut, x0, x1);
-    // walk the rectangle's rows to the one holding the kk-th reached tile
-    int kk = (int)(e - s_off[j]);
-    int ty = y0, tx = x0;
-    for (; ty < y1; ++ty) {
-      int a, b;
-      if (desc) {
-        const uint32_t d = rspan[(size_t)slot * kSpanRows + (ty - y0)];
-        a = x0 + (int)(d & 0xffu);
-        b = x0 + (int)(d >> 8);
-      } else {
-        span_row(sp, tw, th, vw.w, vw.h, ty, a, b);
+  uint32_t tile[kPer], rk[kPer];
+  bool act[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + threadIdx.x + (uint32_t)(q * kEmitThreads);
+    act[q] = e < e1;
+    tile[q] = 0u;
+    if (act[q]) {
+      const int j = last_le(s_off, ns, e);
+      const uint32_t slot = s_slot[j];
+      const uint2 r = rect[slot];
+      const int x0 = r.x & 0xffff, x1 = r.x >> 16, y0 = r.y & 0xffff, y1 = r.y >> 16;
+      const ViewDev& vw = views[slot / (uint32_t)N];
+      const bool desc = span_desc_ok(x0, x1, y0, y1);
+      const Span sp = desc ? Span{} : emit_span(rec, slot, qcut, x0, x1);
+      // walk the rectangle's rows to the one holding the kk-th reached tile
+      int kk = (int)(e - s_off[j]);
+      int ty = y0, tx = x0;
+      for (; ty < y1; ++ty) {
+        int a, b;
+        if (desc) {
+          const uint32_t d = rspan[(size_t)slot * kSpanRows + (ty - y0)];
+          a = x0 + (int)(d & 0xffu);
+          b = x0 + (int)(d >> 8);
+        } else {
+          span_row(sp, tw, th, vw.w, vw.h, ty, a, b);
+        }
+        if (kk < b - a) {
+          tx = a + kk;
+          break;
+        }
+        kk -= b - a;
       }
-      if (kk < b - a) {
-        tx = a + kk;
-        break;
-      }
-      kk -= b - a;
+      if (ty >= y1) ty = y1 - 1;   // unreachable: the counts come from the same spans
+      tile[q] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
+      keys[e] = tile[q];
+      pslot[e] = slot;
+      pdep[e] = s_dep[j];
     }
-    if (ty >= y1) ty = y1 - 1;   // unreachable: the counts come from the same spans
-    keys[e] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
-    vals[e] = e;
-    pslot[e] = slot;
-    pdep[e] = s_dep[j];
   }
+  tile_ranks<kPer>(tcnt, tile, act, rk);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q)
+    if (act[q]) rank[e0 + threadIdx.x + (uint32_t)(q * kEmitThreads)] = rk[q];
 }
 
-// Per-tile list ranges of the sorted pairs.
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-                         int64_t n_host, int64_t cap, uint2* __restrict__ ranges) {
+// Pairs grouped by tile: pair e goes to the first list position of its tile
+// plus its rank (n = the emitted pairs).
+__global__ __launch_bounds__(256) void k_place(const uint32_t* __restrict__ keys,
+                                               const uint32_t* __restrict__ rank,
+                                               const uint32_t* __restrict__ tstart,
+                                               const uint32_t* __restrict__ n_dev, int64_t n_host,
+                                               int64_t cap, uint32_t* __restrict__ vals) {
   const uint32_t n = count_n(n_dev, n_host, cap);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n) return;
-  const uint32_t t = keys[i];
-  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-  if (i == (int64_t)n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n) return;
+  vals[tstart[keys[e]] + rank[e]] = (uint32_t)e;
 }
 
 // Compositing work item of each launch position b: (tile, list begin, list
 // end, view) of the tile order[b], so a compositing wave starts from one load.
-// Depth order inside each tile.  The pair sort leaves a tile's list in
-// emission order, i.e. by surfel id (a tile belongs to one view); these
-// kernels reorder it by (t_z bits, list position), which is the binary32
-// depth with ties by id, and write each sorted pair's slot.  t_z > 0 for a
-// visible slot, so its bits order like its value.
+// Depth order inside each tile.  A tile's list holds its pairs in the order
+// the counters ranked them; these kernels order it by (t_z bits, emission
+// index e), which is the binary32 depth with ties by surfel id (emission runs
+// in (view, surfel id) order and a tile belongs to one view), and write each
+// sorted pair's slot.  t_z > 0 for a visible slot, so its bits order like its
+// value; padding takes (0xffffffff, 0xffffffff) and sorts last.
 __device__ __forceinline__ bool key_less(uint32_t ka, uint32_t ia, uint32_t kb, uint32_t ib) {
   return ka < kb || (ka == kb && ia < ib);
 }
@@ -502,8 +571,8 @@ __device__ __forceinline__ bool key_less(uint32_t ka, uint32_t ia, uint32_t kb, 
 // Lists of 1 to 64 entries, packed by length: the launch order groups the
 // tiles by the bit length bl of their list length, so a wave takes 64 / 2^bl
 // consecutive tiles of one group, each on a segment of 2^bl lanes, and sorts
-// every segment with one bitonic network over (key, lane) (lanes are
-// distinct, so the order is strict; a segment's padding sorts last).  Work
+// every segment with one bitonic network over (key, e) (the e of a tile are
+// distinct, so the order is strict).  Work
 // items (waves) of a group: ceil(tiles / (64 / 2^bl)); the blocks stride
 // over all groups' items.  Lists of 65 or more entries (bl = 7 holds 64 to
 // 127) are left to k_tile_sort_long.
@@ -550,30 +619,26 @@ __global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict_
       len = ti.z - ti.y;
       if (len > 64u) len = 0u;                                 // k_tile_sort_long's
     }
-    uint32_t e = 0u, slot = 0u, key = 0xffffffffu;
+    uint32_t e = 0xffffffffu, key = 0xffffffffu;
     if (seg_lane < len) {
       e = vals[beg + seg_lane];
-      slot = pslot[e];
       key = pdep[e];
     }
-    uint32_t idx = (uint32_t)lane;
     for (int k = 2; k <= S; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
         const uint32_t ok = (uint32_t)__shfl_xor((int)key, j, 64);
-        const uint32_t oi = (uint32_t)__shfl_xor((int)idx, j, 64);
+        const uint32_t oe = (uint32_t)__shfl_xor((int)e, j, 64);
         const bool keep_min = ((lane & j) == 0) == ((seg_lane & (uint32_t)k) == 0u);
-        const bool other_less = key_less(ok, oi, key, idx);
+        const bool other_less = key_less(ok, oe, key, e);
         if (keep_min == other_less) {
           key = ok;
-          idx = oi;
+          e = oe;
         }
       }
     }
-    const uint32_t se = (uint32_t)__shfl((int)e, (int)idx, 64);
-    const uint32_t ss = (uint32_t)__shfl((int)slot, (int)idx, 64);
     if (seg_lane < len) {
-      vals[beg + seg_lane] = se;
-      spair[beg + seg_lane] = ss;
+      vals[beg + seg_lane] = e;
+      spair[beg + seg_lane] = pslot[e];
     }
   }
 }
@@ -594,8 +659,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
                                                         uint32_t* __restrict__ tmpk,
                                                         uint32_t* __restrict__ tmpv) {
   __shared__ uint32_t s_k[kLongSort];
-  __shared__ uint32_t s_i[kLongSort];
-  __shared__ uint32_t s_e[kLongSort];
+  __shared__ uint32_t s_i[kLongSort];   // e of each entry
   const int tid = threadIdx.x;
   for (int64_t b = blockIdx.x; b < T; b += gridDim.x) {
     const uint4 ti = tinfo[b];
@@ -606,14 +670,13 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
       uint32_t P = 128u;
       while (P < len) P <<= 1;
       for (uint32_t i = tid; i < P; i += 256u) {
-        uint32_t key = 0xffffffffu, e = 0u;
+        uint32_t key = 0xffffffffu, e = 0xffffffffu;
         if (i < len) {
           e = vals[beg + i];
           key = pdep[e];
         }
         s_k[i] = key;
-        s_i[i] = i;
-        s_e[i] = e;
+        s_i[i] = e;
       }
       __syncthreads();
       // distances below 64 stay inside a wave's 64-element chunk: those steps
@@ -657,7 +720,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
         chunk_steps(k, k);
       }
       for (uint32_t rk = tid; rk < len; rk += 256u) {
-        const uint32_t e = s_e[s_i[rk]];
+        const uint32_t e = s_i[rk];
         vals[beg + rk] = e;
         spair[beg + rk] = pslot[e];
       }
@@ -668,10 +731,11 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
       }
       __syncthreads();
       for (uint32_t i = tid; i < len; i += 256u) {
-        const uint32_t ki = tmpk[beg + i];
+        const uint32_t ki = tmpk[beg + i], ei = vals[beg + i];
         uint32_t rank = 0u;
-        for (uint32_t j = 0; j < len; ++j) rank += key_less(tmpk[beg + j], j, ki, i) ? 1u : 0u;
-        tmpv[beg + rank] = vals[beg + i];
+        for (uint32_t j = 0; j < len; ++j)
+          rank += key_less(tmpk[beg + j], vals[beg + j], ki, ei) ? 1u : 0u;
+        tmpv[beg + rank] = ei;
       }
       __syncthreads();
       for (uint32_t rk = tid; rk < len; rk += 256u) {
@@ -719,12 +783,16 @@ __global__ void k_tile_info(const uint32_t* __restrict__ order, const uint2* __r
 // a bucket.  A tile's results do not depend on when it runs; the order keeps
 // the few very long lists (far field) from starting last and setting the
 // kernel's end.
-__global__ void k_tile_keys(const uint2* __restrict__ ranges, int64_t T, uint32_t* __restrict__ key,
+// The same pass writes each tile's range (begin, end) of the grouped pairs,
+// (0, 0) for an empty tile.
+__global__ void k_tile_keys(const uint32_t* __restrict__ tcnt, const uint32_t* __restrict__ tstart,
+                            int64_t T, uint2* __restrict__ ranges, uint32_t* __restrict__ key,
                             uint32_t* __restrict__ val) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T) return;
-  const uint2 r = ranges[i];
-  const uint32_t len = r.y - r.x;             // empty tiles hold (0, 0)
+  const uint32_t len = tcnt[i];
+  const uint32_t b = len ? tstart[i] : 0u;
+  ranges[i] = make_uint2(b, b + len);
   const int bl = len ? 32 - __clz((int)len) : 0;
   key[i] = 15u - (uint32_t)min(bl, 15);
   val[i] = (uint32_t)i;
@@ -734,15 +802,17 @@ __global__ void k_tile_keys(const uint2* __restrict__ ranges, int64_t T, uint32_
 
 // Binning of the current batch.  n_pairs / n_vis >= 0: counts known on the
 // host (exact grids); < 0: read on the device (grids sized by the capacity).
-// Returns 1 when the sorted pairs are in the alternate buffers.
-int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st) {
+void launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st,
+                    bool counts_cleared) {
   uint32_t* misc = at<uint32_t>(ws, L.o_misc);
   const uint32_t* p_dev = n_pairs < 0 ? misc + kMiscPairs : nullptr;
   const uint32_t* s_dev = n_vis < 0 ? misc + kMiscVisible : nullptr;
   const int64_t s_grid = n_vis < 0 ? L.scap : n_vis;
   const int64_t p_grid = n_pairs < 0 ? L.cap : n_pairs;
-  uint32_t* hist = at<uint32_t>(ws, L.o_hist);
-  uint32_t* histtmp = at<uint32_t>(ws, L.o_histtmp);
+  const int64_t T = L.total_tiles;
+  uint32_t* tcnt = at<uint32_t>(ws, L.o_tcnt);
+  uint32_t* tstart = at<uint32_t>(ws, L.o_tstart);
+  if (!counts_cleared) fill_u32(tcnt, 0u, T, st);
   // 1. visible slots in (view, surfel id) order, with their emission counts
   //    and each slot's position in that order
   uint32_t* sv = at<uint32_t>(ws, L.o_sval);
@@ -753,13 +823,15 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
                      scnt, at<uint32_t>(ws, L.o_pos));
   // 2. emission offsets
   uint32_t* n_emit = p_dev ? misc + kMiscEmit : nullptr;
-  // 3. one key per covered tile
+  // 3. one (tile, rank) per covered tile, counted per tile
   const uint32_t nblk_emit = (uint32_t)((p_grid + kEmitPairs - 1) / kEmitPairs);
   bool starts = false;
   if (s_grid > 0)
     starts = scan_u32_dev(scnt, soff, s_dev, s_grid, at<uint32_t>(ws, L.o_parttmp2), st,
                           p_grid > 0 ? at<uint32_t>(ws, L.o_bstart) : nullptr, nblk_emit,
                           (uint32_t)kEmitPairs);
+  uint32_t* keys = at<uint32_t>(ws, L.o_keys);
+  uint32_t* rank = at<uint32_t>(ws, L.o_vals2);
   if (p_grid > 0) {
     if (s_grid > 0) {
       const uint32_t nblk = nblk_emit;
@@ -767,34 +839,25 @@ int launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hi
         hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0,
                            st, s_dev, s_grid, L.scap, soff, scnt, nblk,
                            at<uint32_t>(ws, L.o_bstart));
-      hipLaunchKernelGGL(k_emit, dim3((unsigned)((p_grid + kEmitPairs - 1) / kEmitPairs)),
-                         dim3(kEmitThreads), 0, st, at<const ViewDev>(ws, L.o_views), L.N, p_dev,
-                         p_grid, s_dev, s_grid, L.scap, L.cap, sv, soff, scnt,
-                         at<const uint2>(ws, L.o_rect), at<const uint16_t>(ws, L.o_rspan),
-                         at<const float4>(ws, L.o_rec), L.q_cut,
-                         L.tw, L.th, at<const uint32_t>(ws, L.o_bstart), at<uint32_t>(ws, L.o_keys),
-                         at<uint32_t>(ws, L.o_vals), at<uint32_t>(ws, L.o_pslot),
-                         at<uint32_t>(ws, L.o_pdep), n_emit);
+      hipLaunchKernelGGL(k_emit, dim3(nblk), dim3(kEmitThreads), 0, st,
+                         at<const ViewDev>(ws, L.o_views), L.N, p_dev, p_grid, s_dev, s_grid,
+                         L.scap, L.cap, sv, soff, scnt, at<const uint2>(ws, L.o_rect),
+                         at<const uint16_t>(ws, L.o_rspan), at<const float4>(ws, L.o_rec),
+                         L.q_cut, L.tw, L.th, at<const uint32_t>(ws, L.o_bstart), keys, rank,
+                         at<uint32_t>(ws, L.o_pslot), at<uint32_t>(ws, L.o_pdep), tcnt, n_emit);
     } else if (n_emit) {
       fill_u32(n_emit, 0u, 1, st);
     }
   }
-  // 4. stable sort of the pairs by tile (each tile's list stays in id order;
-  //    launch_ranges orders it by depth)
-  return radix_sort<uint32_t, 9, 8, true>(at<uint32_t>(ws, L.o_keys), at<uint32_t>(ws, L.o_vals),
-                                 at<uint32_t>(ws, L.o_keys2), at<uint32_t>(ws, L.o_vals2), n_emit,
-                                 p_grid, L.cap, L.tile_bits, hist, histtmp, st);
+  // 4. first list position of every tile, then the pairs grouped by tile
+  //    (launch_ranges orders each tile's list by depth)
+  scan_u32_dev(tcnt, tstart, nullptr, T, at<uint32_t>(ws, L.o_tscan), st);
+  if (p_grid > 0 && s_grid > 0)
+    hipLaunchKernelGGL(k_place, dim3((unsigned)((p_grid + 255) / 256)), dim3(256), 0, st, keys,
+                       rank, tstart, n_emit, p_grid, L.cap, at<uint32_t>(ws, L.o_vals));
 }
 
-void launch_ranges(const Layout& L, void* ws, int64_t n_host, hipStream_t st,
-                   bool ranges_cleared) {
-  uint2* ranges = at<uint2>(ws, L.o_ranges);
-  if (!ranges_cleared) fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.total_tiles, st);
-  const uint32_t* n_dev = n_host < 0 ? at<uint32_t>(ws, L.o_misc) + kMiscEmit : nullptr;
-  const int64_t n_grid = n_host < 0 ? L.cap : n_host;
-  if (n_grid > 0)
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_grid + 255) / 256)), dim3(256), 0, st,
-                       at<const uint32_t>(ws, L.o_keys), n_dev, n_grid, L.cap, ranges);
+void launch_ranges(const Layout& L, void* ws, hipStream_t st) {
   launch_tile_order(L, ws, st);
   // each tile's list by depth, and the slot of every sorted pair
   const int64_t T = L.total_tiles;
@@ -816,7 +879,8 @@ void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {
   uint32_t* val = key + T;
   uint32_t* key2 = val + T;
   hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
-                     at<const uint2>(ws, L.o_ranges), T, key, val);
+                     at<const uint32_t>(ws, L.o_tcnt), at<const uint32_t>(ws, L.o_tstart), T,
+                     at<uint2>(ws, L.o_ranges), key, val);
   // one 4-bit pass: the result lands in the alternate buffers (key2, order)
   radix_sort<uint32_t, 4, 4, false>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
                           at<uint32_t>(ws, L.o_hist), at<uint32_t>(ws, L.o_histtmp), st);
