@@ -2,7 +2,7 @@
 """Benchmark of the surfel-splatting training step on one MI355X.
 
 A step is the whole hot path over one batch: cull + EWA projection, tile-key
-emission + radix sort + ranges, forward compositing, L1 + cross-entropy loss
+emission with per-tile counting + placement + ranges, forward compositing, L1 + cross-entropy loss
 seed, backward compositing, projection adjoint, and the Adam update.
 
 Default workload: 200,000 surfels (1000 x 200 grid at 0.1 m along a curved
@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 VALU_PEAK_TFLOPS = 78.6    # FP32 FMA without packed-FP32 ops: 256 CU x 64 lanes x 2 x 2.4 GHz
 
 
-def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) -> float:
+def algorithmic_bytes(kernel: str, st, stats, C: int, fused: bool) -> float:
     """Compulsory HBM bytes of one launch group of one step.
     P pairs, S visible (view, surfel) slots, X pixels, N surfels, V views."""
     N, V = st.N, st.V
@@ -41,14 +41,16 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, passes: int, fused: bool) 
         return N * (40 + 4 * FS) + slots * 4 + S * 40
     if kernel == "sort":
         # compaction (slot, count, position of each visible slot) + emission
-        # offsets + one tile key, value, slot and depth key per pair + tile
-        # sort of the pairs (32-bit keys)
-        return slots * 4 + S * 12 + S * 8 + P * 16 + passes * P * 20
+        # offsets + one tile key, rank, slot and depth key per pair + the
+        # per-tile counters and their scan + placement (key and rank read,
+        # emission index written per pair)
+        return slots * 4 + S * 12 + S * 8 + P * 16 + stats["tiles"] * 12 + P * 12
     if kernel == "ranges":
-        # tile ranges from the sorted keys, the launch order and the per-tile
-        # work items, then the depth order inside each tile (emission index,
-        # slot and depth key read, emission index and slot written per pair)
-        return P * 4 + stats["tiles"] * 36 + P * 20
+        # tile ranges from the counters and their scan, the launch order and
+        # the per-tile work items, then the depth order inside each tile
+        # (emission index, slot and depth key read, emission index and slot
+        # written per pair)
+        return stats["tiles"] * (16 + 36) + P * 20
     if kernel == "render_step":
         # fused forward + loss + backward of a tile: targets (12 B colour,
         # label, mask) in, the work item of each tile (16 B), the slot and
@@ -392,14 +394,12 @@ def main():
                  "value": round(scene.npix / (ms_p * 1e-3) / 1e6, 2)}
         print(f"[bench] plain: {ms_p:.3f} ms/step", file=sys.stderr, flush=True)
 
-    tile_bits = max(1, (stats["tiles"] - 1).bit_length())
-    passes = (tile_bits + 8) // 9          # pair sort: 32-bit tile keys, up to 9-bit digits
     kernels = {}
     for name, (ms, n) in prof.items():
         if n == 0 or name == "fused_graph":
             continue
         per = ms / args.steps
-        b = algorithmic_bytes(name, st, stats, C, passes, fused=True)
+        b = algorithmic_bytes(name, st, stats, C, fused=True)
         kernels[name] = {"ms_per_step": round(per, 4), "launches_per_step": n // args.steps,
                          "alg_GBs": round(b / (per * 1e-3) / 1e9, 1) if per > 0 else None}
     # work counts of this workload: one batched forward of the same surfels
@@ -418,7 +418,7 @@ def main():
     dom_ms = prof[dom][0] / prof[dom][1]          # average duration of one launch
     per_launch = prof[dom][1] / args.steps
     dom_flops = flops[dom] / per_launch
-    dom_bytes = algorithmic_bytes(dom, st, stats, C, passes, True) / per_launch
+    dom_bytes = algorithmic_bytes(dom, st, stats, C, True) / per_launch
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2),
                 "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -335,6 +335,7 @@ __device__ __forceinline__ void tile_ranks(uint32_t* __restrict__ tcnt, const ui
 constexpr int kEmitThreads = 256;
 constexpr int kEmitPairs = 1024;
 constexpr int kEmitRows = 2048;
+constexpr int kEmitWin = 2 * kEmitRows;   // tiles of a block's count window
 
 __device__ __forceinline__ Span emit_span(const float4* __restrict__ rec, uint32_t slot, float qcut,
                                           int x0, int x1) {
@@ -395,10 +396,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
   __shared__ uint32_t s_slot[kEmitPairs];
   __shared__ uint32_t s_dep[kEmitPairs];        // t_z bits of each staged slot
   __shared__ uint32_t s_roff[kEmitPairs + 1];   // first row item of each slot
-  __shared__ uint32_t s_rx[kEmitRows];          // row span length, then its first pair
-  __shared__ uint32_t s_rinfo[kEmitRows];       // span start tile | tile row << 16
+  // row items while the tiles are found, then the block's tile-count window
+  __shared__ uint32_t s_rows[2 * kEmitRows];
+  uint32_t* s_rx = s_rows;                      // row span length, then its first pair
+  uint32_t* s_rinfo = s_rows + kEmitRows;       // span start tile | tile row << 16
   __shared__ uint16_t s_rslot[kEmitRows];
   __shared__ uint32_t s_w[kEmitThreads / 64];
+  __shared__ uint32_t s_mm[2 * (kEmitThreads / 64)];
   const uint32_t S = count_n(s_dev, s_host, scap);
   const uint32_t P = count_n(p_dev, p_host, cap);
   const uint32_t pend = S ? soff[S - 1] + scnt[S - 1] : 0u;
@@ -444,6 +448,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     pre += nrow[k];
   }
   __syncthreads();
+  uint32_t tile[kPer];
+  bool act[kPer];
   if (R <= (uint32_t)kEmitRows) {
     // row items: span of each rectangle row of the staged slots
     for (int k = threadIdx.x; k < (int)R; k += kEmitThreads) {
@@ -469,8 +475,6 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     __syncthreads();
     emit_scan(s_rx, (int)R, s_w);                 // pair offsets from the first slot's first pair
     // pair e0 + threadIdx.x + r * kEmitThreads in round r
-    uint32_t tile[kPer], rk[kPer];
-    bool act[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
       const uint32_t e = e0 + threadIdx.x + (uint32_t)(r * kEmitThreads);
@@ -491,14 +495,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         pdep[e] = s_dep[js];
       }
     }
-    tile_ranks<kPer>(tcnt, tile, act, rk);
-#pragma unroll
-    for (int r = 0; r < kPer; ++r)
-      if (act[r]) rank[e0 + threadIdx.x + (uint32_t)(r * kEmitThreads)] = rk[r];
-    return;
-  }
-  uint32_t tile[kPer], rk[kPer];
-  bool act[kPer];
+  } else {
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const uint32_t e = e0 + threadIdx.x + (uint32_t)(q * kEmitThreads);
@@ -537,7 +534,63 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
       pdep[e] = s_dep[j];
     }
   }
-  tile_ranks<kPer>(tcnt, tile, act, rk);
+  }
+  // ranks: the block's tiles in [lo, hi]
+  uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q)
+    if (act[q]) {
+      lo = min(lo, tile[q]);
+      hi = max(hi, tile[q]);
+    }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int kWaves = kEmitThreads / 64;
+  if (lane == 0) {
+    s_mm[wv] = lo;
+    s_mm[kWaves + wv] = hi;
+  }
+  __syncthreads();                      // the row items are no longer read
+  lo = s_mm[0];
+  hi = s_mm[kWaves];
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) {
+    lo = min(lo, s_mm[w]);
+    hi = max(hi, s_mm[kWaves + w]);
+  }
+  uint32_t rk[kPer];
+  if (hi - lo < (uint32_t)kEmitWin) {
+    // one global add per distinct tile of the block: local ranks from LDS
+    // counters over the window, then each nonzero window count takes its
+    // tile's global base
+    constexpr int kWinPer = kEmitWin / kEmitThreads;
+    uint32_t* s_win = s_rows;
+#pragma unroll
+    for (int k = 0; k < kWinPer; ++k) s_win[threadIdx.x + k * kEmitThreads] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) rk[q] = act[q] ? atomicAdd(&s_win[tile[q] - lo], 1u) : 0u;
+    __syncthreads();
+    uint32_t c[kWinPer];
+#pragma unroll
+    for (int k = 0; k < kWinPer; ++k) {
+      const uint32_t w = threadIdx.x + (uint32_t)(k * kEmitThreads);
+      c[k] = s_win[w];
+      if (c[k]) c[k] = atomicAdd(&tcnt[lo + w], c[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kWinPer; ++k) s_win[threadIdx.x + k * kEmitThreads] = c[k];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (act[q]) rk[q] += s_win[tile[q] - lo];
+  } else {
+    tile_ranks<kPer>(tcnt, tile, act, rk);
+  }
 #pragma unroll
   for (int q = 0; q < kPer; ++q)
     if (act[q]) rank[e0 + threadIdx.x + (uint32_t)(q * kEmitThreads)] = rk[q];
