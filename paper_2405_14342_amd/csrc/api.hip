@@ -60,6 +60,8 @@ struct rogs_ctx {
     int64_t launched = 0;                // steps launched so far
     int last = 0;                        // buffer of the last launched step
     hipStream_t cap_stream = nullptr;    // capture happens here (the null stream cannot be captured)
+    hipStream_t side = nullptr;          // the long lists' depth sort, beside the short ones
+    hipEvent_t fork = nullptr, join = nullptr;
   } fz;
 };
 
@@ -188,7 +190,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_pdep = take(4 * (size_t)cap);
   l.o_tcnt = take(4 * (size_t)l.total_tiles);
   l.o_tstart = take(4 * (size_t)l.total_tiles);
-  l.o_tscan = take(4 * scan_tmp_words(l.total_tiles));
+  l.o_tscan = take(4 * (17 * (size_t)((l.total_tiles + 1023) / 1024) + 17));   // tile layout partials
   l.o_bstart = take(4 * ((size_t)cap / 1024 + 2));   // first slot of each emission block
   l.o_sval = take(4 * (size_t)scap);
   l.o_scnt = take(4 * (size_t)scap);
@@ -379,6 +381,9 @@ void rogs_destroy(rogs_ctx* c) {
     if (c->fz.done[k]) (void)hipEventDestroy(c->fz.done[k]);
   }
   if (c->fz.cap_stream) (void)hipStreamDestroy(c->fz.cap_stream);
+  if (c->fz.side) (void)hipStreamDestroy(c->fz.side);
+  if (c->fz.fork) (void)hipEventDestroy(c->fz.fork);
+  if (c->fz.join) (void)hipEventDestroy(c->fz.join);
   if (!c->recs.empty()) (void)hipEventSynchronize(c->recs.back().b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->stage_pending) (void)hipEventSynchronize(c->stage_evt);
@@ -526,7 +531,7 @@ int rogs_bin_sort(rogs_ctx* c, void* ws, int64_t* n_pairs_out, uint32_t flags, v
   rogs::launch_binning(L, ws, n_host, n_vis, st);
   prof_end(c, st);
   prof_begin(c, 4, st);
-  rogs::launch_ranges(L, ws, st);
+  (void)rogs::launch_ranges(L, ws, st);
   prof_end(c, st);
   r = check_launch(c, "rogs_bin_sort");
   if (r != ROGS_OK) return r;
@@ -772,8 +777,9 @@ int fused_sequence(rogs_ctx* c, Layout& L, const rogs_train_state* t, const rogs
   rogs::launch_binning(L, ws, -1, -1, st, true);
   prof_end(c, st);
   prof_begin(c, 4, st);
-  rogs::launch_ranges(L, ws, st);
+  hipError_t e = rogs::launch_ranges(L, ws, st, c->fz.side, c->fz.fork, c->fz.join);
   prof_end(c, st);
+  if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused: depth sort streams");
   rogs::FusedLoss fl;
   fl.tgt = tg->rgb;
   fl.label = tg->label;
@@ -909,6 +915,12 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
     e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), F.stage[p], vbytes + fbytes,
                        hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused: camera table");
+  }
+  if (!F.side) {
+    e = hipStreamCreateWithFlags(&F.side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&F.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&F.join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(c, e, "rogs_step_fused: side stream");
   }
   if (eager) {
     Layout Lr = L;

@@ -573,13 +573,18 @@ void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_
                     hipStream_t st, const uint8_t* mask = nullptr);
 void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts = false);
 // Compaction of the visible slots, emission with per-tile counting, the
-// tiles' first list positions and the pairs grouped by tile (o_vals).  Counts
+// tiles' first list positions, ranges and compositing work items, and the
+// pairs grouped by tile (o_vals).  Counts
 // < 0 are read on the device.  counts_cleared: the per-tile counters were
 // zeroed by the projection launch.
 void launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, hipStream_t st,
                     bool counts_cleared = false);
-// Tile ranges, compositing launch order and each tile's list by depth.
-void launch_ranges(const Layout& L, void* ws, hipStream_t st);
+// Each tile's list by depth.  With a side stream (and two events) the lists
+// longer than 64 entries are sorted there, concurrently with the short ones,
+// and st waits for them before returning; the events' record / wait results
+// are returned.
+hipError_t launch_ranges(const Layout& L, void* ws, hipStream_t st, hipStream_t side = nullptr,
+                         hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st);
 int64_t elev_reg_blocks(int n);
 void launch_elev_reg(int n, const float* z, const int32_t* nbr, float lam_s, const float* zbar,
@@ -593,7 +598,6 @@ void launch_layout_mask(const rogs_pose* poses, int np, double x0, double y0, fl
 void launch_layout_fill(const rogs_pose* poses, int np, double x0, double y0, float h, int W,
                         int H, void* scratch, int64_t n, int32_t* idx, float* x, float* y,
                         float* z, float* q, int32_t* nbr, hipStream_t st);
-void launch_tile_order(const Layout& L, void* ws, hipStream_t st);
 int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* out, hipStream_t st);
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,
                  float* loss_out, float* d_exp, hipStream_t st);

@@ -242,16 +242,30 @@ int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, 
   return passes & 1;
 }
 
-// Visible slots in (view, surfel) order, their emission counts, and each
-// slot's position in that order.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitPairs = 1024;
+constexpr int kEmitRows = 2048;
+constexpr int kEmitWin = 2 * kEmitRows;   // tiles of a block's count window
+
+// Visible slots in (view, surfel) order: each slot's position in that order
+// (from the per-block visible counts, scanned), its emission count and first
+// pair (from the per-block pair counts, scanned, plus the block's exclusive
+// scan of the counts), and the first slot of every emission block of
+// kEmitPairs pairs (each block start lies in exactly one slot; only the nblk
+// launched blocks).
 __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
                                                         const uint32_t* __restrict__ cnt,
+                                                        const uint32_t* __restrict__ part,
                                                         const uint32_t* __restrict__ partv,
                                                         int64_t scap,
                                                         uint32_t* __restrict__ sval,
                                                         uint32_t* __restrict__ scnt,
-                                                        uint32_t* __restrict__ spos) {
+                                                        uint32_t* __restrict__ soff,
+                                                        uint32_t* __restrict__ spos,
+                                                        uint32_t* __restrict__ bstart,
+                                                        uint32_t nblk) {
   __shared__ uint32_t s_w[kProjBlock / 64];
+  __shared__ uint32_t s_p[kProjBlock / 64];
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   const bool valid = i < N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -261,17 +275,29 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
     const uint32_t c = valid ? cnt[slot] : 0u;
     const bool vis = c != 0;
     const unsigned long long b = __ballot(vis);
+    const uint32_t inc = wave_incl_scan(c, lane);
     if (lane == 0) s_w[wv] = (uint32_t)__popcll(b);
+    if (lane == 63) s_p[wv] = inc;
     __syncthreads();
     uint32_t pre = partv[(size_t)v * nb + blockIdx.x];
-    for (int w = 0; w < wv; ++w) pre += s_w[w];
+    uint32_t off = part[(size_t)v * nb + blockIdx.x] + inc - c;
+    for (int w = 0; w < wv; ++w) {
+      pre += s_w[w];
+      off += s_p[w];
+    }
     __syncthreads();
     if (vis) {
       const uint32_t pos = pre + (uint32_t)__popcll(b & lt_mask);
       if ((int64_t)pos < scap) {
         sval[pos] = (uint32_t)slot;
         scnt[pos] = c;
+        soff[pos] = off;
         spos[slot] = pos;
+        if (nblk) {
+          const uint32_t b0 = (off + (uint32_t)kEmitPairs - 1u) / (uint32_t)kEmitPairs;
+          const uint32_t b1 = min((off + c - 1u) / (uint32_t)kEmitPairs, nblk - 1u);
+          for (uint32_t bb = b0; bb <= b1; ++bb) bstart[bb] = pos;
+        }
       }
     }
   }
@@ -319,7 +345,7 @@ __device__ __forceinline__ void tile_ranks(uint32_t* __restrict__ tcnt, const ui
 
 // Emission in (view, surfel id) slot order, balanced by pairs: block b writes the
 // pairs e in [b * kEmitPairs, (b + 1) * kEmitPairs).  Its first slot comes from
-// k_emit_starts; the following slots that start before the block's end (each
+// the compaction (bstart); the following slots that start before the block's end (each
 // visible slot has at least one pair, so the offsets are strictly increasing
 // and the range holds at most kEmitPairs slots) are staged in LDS.  The rectangle rows of the staged slots
 // become row items: each gets its tile span (the same row spans that gave the
@@ -332,10 +358,6 @@ __device__ __forceinline__ void tile_ranks(uint32_t* __restrict__ tcnt, const ui
 // slot, pdep[e] = the slot's t_z bits.  The number of pairs written (the pair
 // count, clipped to the capacity and to the pairs of the slots within the
 // slot capacity) goes to *n_emit.
-constexpr int kEmitThreads = 256;
-constexpr int kEmitPairs = 1024;
-constexpr int kEmitRows = 2048;
-constexpr int kEmitWin = 2 * kEmitRows;   // tiles of a block's count window
 
 __device__ __forceinline__ Span emit_span(const float4* __restrict__ rec, uint32_t slot, float qcut,
                                           int x0, int x1) {
@@ -362,24 +384,6 @@ __device__ uint32_t emit_scan(uint32_t* a, int n, uint32_t* s_w) {
   }
   __syncthreads();
   return total;
-}
-
-// First slot of every emission block: the slot whose pair range holds the
-// block's first emission index (one thread per slot; each block start lies in
-// exactly one slot).
-__global__ __launch_bounds__(256) void k_emit_starts(const uint32_t* __restrict__ s_dev,
-                                                     int64_t s_host, int64_t scap,
-                                                     const uint32_t* __restrict__ soff,
-                                                     const uint32_t* __restrict__ scnt,
-                                                     uint32_t nblk, uint32_t* __restrict__ bstart) {
-  const uint32_t S = count_n(s_dev, s_host, scap);
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= (int64_t)S) return;
-  const uint32_t a = soff[k], c = scnt[k];
-  if (c == 0) return;
-  const uint32_t b0 = (a + (uint32_t)kEmitPairs - 1u) / (uint32_t)kEmitPairs;
-  const uint32_t b1 = min((a + c - 1u) / (uint32_t)kEmitPairs, nblk - 1u);   // launched blocks only
-  for (uint32_t b = b0; b <= b1; ++b) bstart[b] = (uint32_t)k;
 }
 
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
@@ -801,54 +805,145 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
   }
 }
 
-// Inside each length bucket the launch positions are permuted in blocks of 64
-// (an 8 x 8 transpose), so that runs of 8 consecutive tiles of the order (one
-// tile row, mostly the same surfels) take launch positions 8 apart.  The
-// workgroups of one launch go to the 8 XCDs in turn, so such a run is
-// composited by one XCD and its surfels' records stay in that XCD's L2.
-__global__ void k_tile_info(const uint32_t* __restrict__ order, const uint2* __restrict__ ranges,
-                            const ViewDev* __restrict__ views, int V, int64_t T,
-                            const uint32_t* __restrict__ bucket_tot, int nbucket,
-                            uint4* __restrict__ tinfo) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= T) return;
-  int64_t start = 0, size = 0;
-  for (int d = 0; d < nbucket; ++d) {
-    const int64_t n = bucket_tot[d];
-    if (b < start + n) { size = n; break; }
-    start += n;
-  }
-  const int64_t q = b - start;
-  int64_t src = q;
-  if (q < (size & ~(int64_t)63)) src = (q & ~(int64_t)63) + 8 * (q & 7) + ((q >> 3) & 7);
-  const uint32_t gt = order[start + src];
-  const uint2 r = ranges[gt];
-  int lo = 0, hi = V - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (views[mid].tile_off <= (int32_t)gt) lo = mid; else hi = mid - 1;
-  }
-  tinfo[b] = make_uint4(gt, r.x, r.y, (uint32_t)lo);
+// Tile layout: list start and range of every tile, and the compositing launch
+// order with a work item per launch position.  The launch order takes the
+// longest lists first: bucket d = 15 - (bit length of the list length,
+// capped at 15) ascending, tile index order inside a bucket (a tile's results
+// do not depend on when it runs; the order keeps the few very long far-field
+// lists from starting last and setting the kernel's end).  Inside each bucket
+// the launch positions are permuted in blocks of 64 (an 8 x 8 transpose), so
+// that runs of 8 consecutive tiles of the order (one tile row, mostly the
+// same surfels) take launch positions 8 apart: the workgroups of one launch
+// go to the 8 XCDs in turn, so such a run is composited by one XCD and its
+// surfels' records stay in that XCD's L2.  Three launches: per block of
+// kTileBlk tiles the pair count and the bucket sizes (k_tile_part), their
+// exclusive scans down the blocks and the totals (k_tile_top), then the
+// placement (k_tile_layout).
+constexpr int kTileBlk = 1024;      // tiles per block (4 rounds of 256)
+constexpr int kTPart = 17;          // per block: pairs, then the 16 bucket sizes
+
+__device__ __forceinline__ uint32_t tile_bucket(uint32_t len) {
+  const int bl = len ? 32 - __clz((int)len) : 0;
+  return 15u - (uint32_t)min(bl, 15);
 }
 
-// Launch order of the tiles for compositing: the longest lists first (keys =
-// bucket of the list length's bit length, descending), tile index order inside
-// a bucket.  A tile's results do not depend on when it runs; the order keeps
-// the few very long lists (far field) from starting last and setting the
-// kernel's end.
-// The same pass writes each tile's range (begin, end) of the grouped pairs,
-// (0, 0) for an empty tile.
-__global__ void k_tile_keys(const uint32_t* __restrict__ tcnt, const uint32_t* __restrict__ tstart,
-                            int64_t T, uint2* __restrict__ ranges, uint32_t* __restrict__ key,
-                            uint32_t* __restrict__ val) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= T) return;
-  const uint32_t len = tcnt[i];
-  const uint32_t b = len ? tstart[i] : 0u;
-  ranges[i] = make_uint2(b, b + len);
-  const int bl = len ? 32 - __clz((int)len) : 0;
-  key[i] = 15u - (uint32_t)min(bl, 15);
-  val[i] = (uint32_t)i;
+__global__ __launch_bounds__(256) void k_tile_part(const uint32_t* __restrict__ tcnt, int64_t T,
+                                                   uint32_t* __restrict__ tpart) {
+  __shared__ uint32_t s_h[16];
+  __shared__ uint32_t s_w[4];
+  if (threadIdx.x < 16) s_h[threadIdx.x] = 0u;
+  __syncthreads();
+  uint32_t sum = 0u;
+#pragma unroll
+  for (int r = 0; r < kTileBlk / 256; ++r) {
+    const int64_t i = (int64_t)blockIdx.x * kTileBlk + r * 256 + threadIdx.x;
+    if (i < T) {
+      const uint32_t c = tcnt[i];
+      sum += c;
+      atomicAdd(&s_h[tile_bucket(c)], 1u);
+    }
+  }
+  uint32_t total;
+  (void)block_excl_scan(sum, s_w, &total);
+  uint32_t* row = tpart + (size_t)blockIdx.x * kTPart;
+  if (threadIdx.x == 0) row[0] = total;
+  if (threadIdx.x < 16) row[1 + threadIdx.x] = s_h[threadIdx.x];
+}
+
+// One wave per column j of the nblk x kTPart table: its exclusive scan down
+// the blocks, in place, and its total; the bucket sizes also go to
+// bucket_tot for the depth sorts.
+__global__ __launch_bounds__(64) void k_tile_top(uint32_t* __restrict__ tpart, int64_t nblk,
+                                                 uint32_t* __restrict__ tot,
+                                                 uint32_t* __restrict__ bucket_tot) {
+  const int j = blockIdx.x, lane = threadIdx.x;
+  uint32_t carry = 0u;
+  for (int64_t r0 = 0; r0 < nblk; r0 += 64) {
+    const int64_t r = r0 + lane;
+    const uint32_t v = r < nblk ? tpart[r * kTPart + j] : 0u;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (r < nblk) tpart[r * kTPart + j] = carry + inc - v;
+    carry += (uint32_t)__shfl((int)inc, 63, 64);
+  }
+  if (lane == 0) {
+    tot[j] = carry;
+    if (j > 0) bucket_tot[j - 1] = carry;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_layout(const uint32_t* __restrict__ tcnt, int64_t T,
+                                                     const uint32_t* __restrict__ tpart,
+                                                     const uint32_t* __restrict__ tot,
+                                                     const ViewDev* __restrict__ views, int V,
+                                                     uint32_t* __restrict__ tstart,
+                                                     uint2* __restrict__ ranges,
+                                                     uint4* __restrict__ tinfo) {
+  __shared__ uint32_t s_bst[16], s_bsz[16], s_run[16];
+  __shared__ uint32_t s_wc[4][16];
+  __shared__ uint32_t s_ws[4];
+  __shared__ uint32_t s_prun;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const uint32_t* row = tpart + (size_t)blockIdx.x * kTPart;
+  if (threadIdx.x < 16) {
+    const int d = threadIdx.x;
+    uint32_t st = 0u;
+    for (int k = 0; k < d; ++k) st += tot[1 + k];
+    s_bst[d] = st;
+    s_bsz[d] = tot[1 + d];
+    s_run[d] = row[1 + d];                 // this block's first rank in bucket d
+  }
+  if (threadIdx.x == 0) s_prun = row[0];
+  if (threadIdx.x < 64) (&s_wc[0][0])[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int r = 0; r < kTileBlk / 256; ++r) {
+    const int64_t i = (int64_t)blockIdx.x * kTileBlk + r * 256 + threadIdx.x;
+    const bool valid = i < T;
+    const uint32_t c = valid ? tcnt[i] : 0u;
+    const uint32_t d = tile_bucket(c);
+    const uint32_t inc = wave_incl_scan(c, lane);
+    // lanes of the wave in the same bucket
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bb = __ballot(valid && on);
+      m &= on ? bb : ~bb;
+    }
+    const uint32_t below = (uint32_t)__popcll(m & lt);
+    if (valid && below == 0u) s_wc[wv][d] = (uint32_t)__popcll(m);
+    if (lane == 63) s_ws[wv] = inc;
+    __syncthreads();
+    if (valid) {
+      uint32_t pst = s_prun + inc - c, rk = s_run[d] + below;
+      for (int w = 0; w < wv; ++w) {
+        pst += s_ws[w];
+        rk += s_wc[w][d];
+      }
+      tstart[i] = pst;
+      ranges[i] = c ? make_uint2(pst, pst + c) : make_uint2(0u, 0u);
+      // launch position: the 8 x 8 transpose inside full blocks of 64
+      uint32_t q = rk;
+      if (q < (s_bsz[d] & ~63u)) q = (q & ~63u) + 8u * (q & 7u) + ((q >> 3) & 7u);
+      int lo = 0, hi = V - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= (int32_t)i) lo = mid; else hi = mid - 1;
+      }
+      tinfo[s_bst[d] + q] = c ? make_uint4((uint32_t)i, pst, pst + c, (uint32_t)lo)
+                              : make_uint4((uint32_t)i, 0u, 0u, (uint32_t)lo);
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      uint32_t add = 0u;
+      for (int w = 0; w < 4; ++w) add += s_wc[w][threadIdx.x];
+      s_run[threadIdx.x] += add;
+    }
+    if (threadIdx.x == 0) s_prun += s_ws[0] + s_ws[1] + s_ws[2] + s_ws[3];
+    __syncthreads();
+    if (threadIdx.x < 64) (&s_wc[0][0])[threadIdx.x] = 0u;
+    __syncthreads();
+  }
 }
 
 }  // namespace
@@ -867,31 +962,22 @@ void launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, h
   uint32_t* tstart = at<uint32_t>(ws, L.o_tstart);
   if (!counts_cleared) fill_u32(tcnt, 0u, T, st);
   // 1. visible slots in (view, surfel id) order, with their emission counts
-  //    and each slot's position in that order
   uint32_t* sv = at<uint32_t>(ws, L.o_sval);
   uint32_t* scnt = at<uint32_t>(ws, L.o_scnt);
   uint32_t* soff = at<uint32_t>(ws, L.o_soff);
-  hipLaunchKernelGGL(k_compact, dim3(L.nb), dim3(kProjBlock), 0, st, L.V, L.N, L.nb,
-                     at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_partv), L.scap, sv,
-                     scnt, at<uint32_t>(ws, L.o_pos));
-  // 2. emission offsets
-  uint32_t* n_emit = p_dev ? misc + kMiscEmit : nullptr;
-  // 3. one (tile, rank) per covered tile, counted per tile
+  //    and first pairs, and the first slot of every emission block
   const uint32_t nblk_emit = (uint32_t)((p_grid + kEmitPairs - 1) / kEmitPairs);
-  bool starts = false;
-  if (s_grid > 0)
-    starts = scan_u32_dev(scnt, soff, s_dev, s_grid, at<uint32_t>(ws, L.o_parttmp2), st,
-                          p_grid > 0 ? at<uint32_t>(ws, L.o_bstart) : nullptr, nblk_emit,
-                          (uint32_t)kEmitPairs);
+  hipLaunchKernelGGL(k_compact, dim3(L.nb), dim3(kProjBlock), 0, st, L.V, L.N, L.nb,
+                     at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_part),
+                     at<const uint32_t>(ws, L.o_partv), L.scap, sv, scnt, soff,
+                     at<uint32_t>(ws, L.o_pos), at<uint32_t>(ws, L.o_bstart), nblk_emit);
+  uint32_t* n_emit = p_dev ? misc + kMiscEmit : nullptr;
+  // 2. one (tile, rank) per covered tile, counted per tile
   uint32_t* keys = at<uint32_t>(ws, L.o_keys);
   uint32_t* rank = at<uint32_t>(ws, L.o_vals2);
   if (p_grid > 0) {
     if (s_grid > 0) {
       const uint32_t nblk = nblk_emit;
-      if (!starts)
-        hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((s_grid + 255) / 256)), dim3(256), 0,
-                           st, s_dev, s_grid, L.scap, soff, scnt, nblk,
-                           at<uint32_t>(ws, L.o_bstart));
       hipLaunchKernelGGL(k_emit, dim3(nblk), dim3(kEmitThreads), 0, st,
                          at<const ViewDev>(ws, L.o_views), L.N, p_dev, p_grid, s_dev, s_grid,
                          L.scap, L.cap, sv, soff, scnt, at<const uint2>(ws, L.o_rect),
@@ -902,45 +988,50 @@ void launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, h
       fill_u32(n_emit, 0u, 1, st);
     }
   }
-  // 4. first list position of every tile, then the pairs grouped by tile
-  //    (launch_ranges orders each tile's list by depth)
-  scan_u32_dev(tcnt, tstart, nullptr, T, at<uint32_t>(ws, L.o_tscan), st);
+  // 3. first list position and range of every tile and the compositing
+  //    launch order, then the pairs grouped by tile (launch_ranges orders
+  //    each tile's list by depth)
+  const int64_t nbt = (T + kTileBlk - 1) / kTileBlk;
+  uint32_t* tpart = at<uint32_t>(ws, L.o_tscan);
+  uint32_t* ttot = tpart + nbt * kTPart;
+  hipLaunchKernelGGL(k_tile_part, dim3((unsigned)nbt), dim3(256), 0, st, tcnt, T, tpart);
+  hipLaunchKernelGGL(k_tile_top, dim3(kTPart), dim3(64), 0, st, tpart, nbt, ttot,
+                     at<uint32_t>(ws, L.o_histtmp));
+  hipLaunchKernelGGL(k_tile_layout, dim3((unsigned)nbt), dim3(256), 0, st, tcnt, T, tpart, ttot,
+                     at<const ViewDev>(ws, L.o_views), L.V, tstart, at<uint2>(ws, L.o_ranges),
+                     at<uint4>(ws, L.o_tinfo));
   if (p_grid > 0 && s_grid > 0)
     hipLaunchKernelGGL(k_place, dim3((unsigned)((p_grid + 255) / 256)), dim3(256), 0, st, keys,
                        rank, tstart, n_emit, p_grid, L.cap, at<uint32_t>(ws, L.o_vals));
 }
 
-void launch_ranges(const Layout& L, void* ws, hipStream_t st) {
-  launch_tile_order(L, ws, st);
-  // each tile's list by depth, and the slot of every sorted pair
+hipError_t launch_ranges(const Layout& L, void* ws, hipStream_t st, hipStream_t side,
+                         hipEvent_t fork, hipEvent_t join) {
+  // each tile's list by depth, and the slot of every sorted pair; the two
+  // kernels touch disjoint tiles
   const int64_t T = L.total_tiles;
+  hipStream_t lst = st;
+  if (side) {
+    hipError_t e = hipEventRecord(fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
+    lst = side;
+  }
+  hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)std::min<int64_t>(T, kLongBlocks)), dim3(256),
+                     0, lst, at<const uint4>(ws, L.o_tinfo), T, at<uint32_t>(ws, L.o_vals),
+                     at<const uint32_t>(ws, L.o_pslot), at<const uint32_t>(ws, L.o_pdep),
+                     at<uint32_t>(ws, L.o_spair), at<uint32_t>(ws, L.o_keys2),
+                     at<uint32_t>(ws, L.o_vals2));
+  if (side) {
+    hipError_t e = hipEventRecord(join, side);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_tile_sort_short, dim3((unsigned)std::min<int64_t>(T, kShortBlocks)),
                      dim3(64), 0, st, at<const uint4>(ws, L.o_tinfo),
                      at<const uint32_t>(ws, L.o_histtmp), at<uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_pslot), at<const uint32_t>(ws, L.o_pdep),
                      at<uint32_t>(ws, L.o_spair));
-  hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)std::min<int64_t>(T, kLongBlocks)), dim3(256),
-                     0, st, at<const uint4>(ws, L.o_tinfo), T, at<uint32_t>(ws, L.o_vals),
-                     at<const uint32_t>(ws, L.o_pslot), at<const uint32_t>(ws, L.o_pdep),
-                     at<uint32_t>(ws, L.o_spair), at<uint32_t>(ws, L.o_keys2),
-                     at<uint32_t>(ws, L.o_vals2));
-}
-
-void launch_tile_order(const Layout& L, void* ws, hipStream_t st) {
-  const int64_t T = L.total_tiles;
-  uint32_t* key = at<uint32_t>(ws, L.o_tkey);
-  uint32_t* val = key + T;
-  uint32_t* key2 = val + T;
-  hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
-                     at<const uint32_t>(ws, L.o_tcnt), at<const uint32_t>(ws, L.o_tstart), T,
-                     at<uint2>(ws, L.o_ranges), key, val);
-  // one 4-bit pass: the result lands in the alternate buffers (key2, order)
-  radix_sort<uint32_t, 4, 4, false>(key, val, key2, at<uint32_t>(ws, L.o_order), nullptr, T, T, 4,
-                          at<uint32_t>(ws, L.o_hist), at<uint32_t>(ws, L.o_histtmp), st);
-  hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
-                     at<const uint32_t>(ws, L.o_order), at<const uint2>(ws, L.o_ranges),
-                     at<const ViewDev>(ws, L.o_views), L.V, T,
-                     at<const uint32_t>(ws, L.o_histtmp), 16, at<uint4>(ws, L.o_tinfo));
+  return side ? hipStreamWaitEvent(st, join, 0) : hipSuccess;
 }
 
 }  // namespace rogs

@@ -123,21 +123,27 @@ def test_batches_overlap_on_two_lanes():
         cam = sc.cams[1]
         alone = _out(cam, ALL, sc.n_sem)
         srv.wait(srv.submit(cam, ALL, alone))
-        big = synth.pinhole_camera((0.0, 0.0, 1.5), 0.0, math.radians(-10.0), 4096, 2048, 2900.0)
+        # a request long enough that the small one, submitted at most a
+        # millisecond later, starts while it still runs
+        big = synth.pinhole_camera((0.0, 0.0, 1.5), 0.0, math.radians(-10.0), 6144, 3072, 4350.0)
         ob = _out(big, B.CH_RGB, sc.n_sem)
         seen = False
+        spans = []
         for k in range(10):
             tb = srv.submit(big, B.CH_RGB, ob)
-            time.sleep(0.0002 * (k + 1))
+            time.sleep(0.0001 * k)
             mixed = _out(cam, ALL, sc.n_sem)
             tr = srv.submit(cam, ALL, mixed)
             rb, rr = srv.wait(tb), srv.wait(tr)
             assert rb["status"] == B.OK and rr["status"] == B.OK
             assert torch.equal(torch.nan_to_num(mixed, nan=-1.0), torch.nan_to_num(alone, nan=-1.0))
+            spans.append(tuple((r[key] - rb["t_start_ns"]) // 1000 for r in (rb, rr)
+                               for key in ("t_start_ns", "t_done_ns")))
             if rr["t_start_ns"] < rb["t_done_ns"] and rb["t_start_ns"] < rr["t_done_ns"]:
                 seen = True
                 break
-        assert seen and srv.stats()["max_in_flight"] == 2
+        # spans: (big start, big done, small start, small done) in us
+        assert seen and srv.stats()["max_in_flight"] == 2, (spans, srv.stats())
     finally:
         srv.close()
 
