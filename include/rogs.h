@@ -217,9 +217,10 @@ ROGS_API int rogs_project(rogs_ctx* ctx, const rogs_surfels* s, const rogs_camer
                  const rogs_render_opts* opts, void* ws, size_t ws_bytes, int64_t pair_capacity,
                  int64_t slot_capacity, void* stream);
 
-/* a3-a5, Sec. 3.3.1 ("ascending order of original depth").  Emits one
- * (tile, depth) key per covered tile, radix-sorts the keys stably (ties keep
- * surfel-id order) and writes per-tile ranges.  With ROGS_SYNC_COUNT the pair
+/* a3-a5, Sec. 3.3.1 ("ascending order of original depth").  Emits one pair
+ * per covered tile and orders the pairs by (tile, depth), ties by surfel id
+ * (the order a stable sort of (tile, depth) keys in surfel-id order gives),
+ * and writes per-tile ranges ((0, 0) for an empty tile).  With ROGS_SYNC_COUNT the pair
  * count P is read back first (host sync): if P > pair_capacity or the
  * visible-slot count exceeds slot_capacity the call returns ROGS_ECAPACITY
  * with *n_pairs_out = P and enqueues nothing more (rogs_batch_stats gives
@@ -269,7 +270,7 @@ ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* para
 
 /* ------------------------------------------------------ fused step
  * The whole training step (a1-a10) over all views of a batch in one graph:
- * cull + projection, emission, radix sort and ranges with the pair count kept
+ * cull + projection, emission, binning and ranges with the pair count kept
  * on the device, forward compositing with the loss seed fused into its
  * epilogue (per-pixel dL/dO, G.O, T and n_last kept in a tile-major
  * workspace record; the images themselves are not written), backward

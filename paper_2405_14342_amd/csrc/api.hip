@@ -158,11 +158,6 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   }
   l.slots = (int64_t)l.V * l.N;
   if (l.slots >= (int64_t(1) << 32)) { *why = "n_views * n must be < 2^32"; return ROGS_EINVAL; }
-  int tb = 1;
-  while ((int64_t(1) << tb) < l.total_tiles) ++tb;
-  l.tile_bits = tb;
-  l.sort_blocks = std::max<int64_t>(1, (l.total_tiles + kSortTileMin - 1) /
-                                            kSortTileMin);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1)); return r; };
   // the view table and the loss first-block table are contiguous, as in the
@@ -180,7 +175,6 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_part = take(4 * (size_t)l.V * l.nb);
   l.o_partv = take(4 * (size_t)l.V * l.nb);
   l.o_parttmp = take(4 * scan_tmp_words((int64_t)l.V * l.nb));
-  l.o_parttmp2 = take(4 * scan_tmp_words(scap));
   l.o_keys = take(4 * (size_t)cap);          // tile of each pair
   l.o_keys2 = take(4 * (size_t)cap);         // alternate keys of the pair sort
   l.o_vals = take(4 * (size_t)cap);
@@ -199,14 +193,11 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_long = take(4 * (size_t)scap);
   l.o_pos = take(4 * (size_t)l.slots);
   l.o_ranges = take(8 * (size_t)l.total_tiles);
-  l.o_order = take(4 * (size_t)l.total_tiles);      // tile launch order (longest lists first)
   l.o_tinfo = take(16 * (size_t)l.total_tiles);
-  l.o_tkey = take(4 * 3 * (size_t)l.total_tiles);   // its sort keys / values / keys out
   l.o_tfin = take(4 * (size_t)l.total_pix);
   l.o_nlast = take(4 * (size_t)l.total_pix);
   l.o_gpair = take(4 * (size_t)cap * l.GS);
-  l.o_hist = take(4 * (size_t)kRadixMax * l.sort_blocks);
-  l.o_histtmp = take(4 * (size_t)kRadixMax);  // digit totals of a sort pass
+  l.o_histtmp = take(4 * 16);                  // tiles per launch-order bucket
   if (fused) {
     l.o_tpart = take(4 * 3 * (size_t)l.total_tiles);
     l.o_dzr = take(4 * (size_t)l.N);                          // grid-side dL/dz

@@ -240,14 +240,9 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, 
 }
 
 // in and out may be the same array (each block reads its chunk before writing it).
-// With bstart: for the emission, also each block start b * bpairs (b < nblk)
-// goes to the element whose range [out, out + in) holds it (elements with a
-// zero count hold none).
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n_cap,
                                                    const uint32_t* __restrict__ n_dev,
-                                                   const uint32_t* __restrict__ sums,
-                                                   uint32_t* __restrict__ bstart, uint32_t nblk,
-                                                   uint32_t bpairs) {
+                                                   const uint32_t* __restrict__ sums) {
   __shared__ uint32_t s_v[kScanChunk];
   __shared__ uint32_t s_w[4];
   const int64_t n = scan_count(n_dev, n_cap);
@@ -276,18 +271,7 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t*
   __syncthreads();
   for (int k = threadIdx.x; k < kScanChunk; k += 256) {
     int64_t j = base + k;
-    if (j < n) {
-      const uint32_t a = s_v[k];
-      out[j] = a;
-      if (bstart) {
-        const uint32_t c = in[j];
-        if (c != 0u) {
-          const uint32_t b0 = (a + bpairs - 1u) / bpairs;
-          const uint32_t b1 = min((a + c - 1u) / bpairs, nblk - 1u);
-          for (uint32_t b = b0; b <= b1; ++b) bstart[b] = (uint32_t)j;
-        }
-      }
-    }
+    if (j < n) out[j] = s_v[k];
   }
 }
 
@@ -393,24 +377,7 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uin
                      (const uint32_t*)nullptr, tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, m, total);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)m), dim3(256), 0, st, in, out, n,
-                     (const uint32_t*)nullptr, tmp, (uint32_t*)nullptr, 0u, 1u);
-}
-
-bool scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
-                  uint32_t* tmp, hipStream_t st, uint32_t* bstart, uint32_t nblk,
-                  uint32_t bpairs) {
-  if (n_cap <= 0) return false;
-  if (n_cap <= kSmallScan) {
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, out, n_cap, n_dev,
-                       (uint32_t*)nullptr);
-    return false;
-  }
-  int64_t m = (n_cap + kScanChunk - 1) / kScanChunk;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)m), dim3(256), 0, st, in, n_cap, n_dev, tmp);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, m, (uint32_t*)nullptr);
-  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)m), dim3(256), 0, st, in, out, n_cap, n_dev, tmp,
-                     bstart, nblk, bpairs);
-  return bstart != nullptr;
+                     (const uint32_t*)nullptr, tmp);
 }
 
 void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {

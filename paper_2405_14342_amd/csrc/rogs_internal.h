@@ -12,9 +12,6 @@
 namespace rogs {
 
 constexpr int kProjBlock = 256;     // threads per block of the per-surfel kernels
-constexpr int kSortBlock = 256;     // threads per radix-sort block
-constexpr int kSortTileMin = kSortBlock * 4;   // fewest keys per radix-sort block (sizes the tables)
-constexpr int kRadixMax = 512;     // largest radix of the sorts (9-bit digits)
 constexpr int kMaskChunk = 8192;   // mask bytes per side block of the projection launch
 constexpr int kScanChunk = 4096;    // elements per block of the generic scan
 constexpr int kMaxViews = 4096;
@@ -45,13 +42,11 @@ struct Layout {
   int32_t tw = 16, th = 16, ppl = 4;
   int32_t FS = 0, GS = 0;
   int32_t nb = 0;              // blocks of kProjBlock surfels
-  int32_t tile_bits = 1;
   int64_t total_pix = 0, total_tiles = 0, max_view_pix = 0, max_view_tiles = 0, cap = 0;
   int64_t scap = 0;            // visible-slot capacity (<= cap)
   int64_t slots = 0;           // V * N
-  int64_t sort_blocks = 0;     // ceil(tiles / kSortTileMin)
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
-  size_t o_views, o_order, o_tkey, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_rspan, o_bstart, o_feat, o_part, o_partv, o_parttmp, o_parttmp2;
+  size_t o_views, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_rspan, o_bstart, o_feat, o_part, o_partv, o_parttmp;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
   size_t o_spair;              // slot of each tile-sorted pair
   size_t o_pdep;               // t_z bits of each emitted pair (the tile sort's key)
@@ -60,7 +55,7 @@ struct Layout {
   size_t o_mpart = 0;          // fused path: per-view mask counts of the projection's side blocks
   size_t o_sval, o_scnt, o_soff;               // visible slots in (view, surfel id) order
   size_t o_ssum, o_pos, o_long;                 // per-slot gradient sums, slot -> sorted position
-  size_t o_hist, o_histtmp, o_misc, o_lpart, o_mcount;
+  size_t o_histtmp, o_misc, o_lpart, o_mcount;
   size_t o_tpart = 0, o_status = 0;   // fused path only (0 = absent)
   size_t total = 0;
 };
@@ -632,13 +627,6 @@ void launch_step_end(const Layout& L, void* ws, StepState* state, const AdamArgs
 // Exclusive scan of n uint32 values; total written to *total (device) if non-null.
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
               hipStream_t st);
-// Same with the count read on the device (at most n_cap).
-// Exclusive scan of the first min(*n_dev, n_cap) values.  With bstart, also
-// the element holding each block start b * bpairs (b < nblk); returns whether
-// it wrote them (small tables take a one-block scan that does not).
-bool scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, int64_t n_cap,
-                  uint32_t* tmp, hipStream_t st, uint32_t* bstart = nullptr, uint32_t nblk = 0,
-                  uint32_t bpairs = 1);
 
 size_t scan_tmp_words(int64_t n);
 // Stores msg as the context's last error and returns code.

@@ -1,21 +1,10 @@
 // Binning: the visible (view, surfel) slots in (view, surfel id) order,
-// emission of one (tile) key per covered tile in that order, a stable radix
-// sort of the pairs by tile, per-tile ranges, then each tile's list ordered by
-// depth inside the tile.  The result is every tile's list in ascending order
-// of original depth with ties by surfel id (Sec. 3.3.1).
-//
-// Stable LSD radix sort: per pass, per-block digit histograms (LDS atomics),
-// an exclusive scan of each digit's column of that table with the digit
-// totals (one block per digit), then a stable scatter.  A block owns
-// 256 * IPT consecutive keys (IPT = 8 for the pair sort, 4 for the launch
-// order); the scatter starts each digit
-// at the scan of the totals plus its column entry, and each of its four waves
-// ranks a contiguous quarter, 64 keys at a time, finding lanes with equal
-// digits with one ballot per digit bit, so ranks follow the input order.  In
-// the pair sort (STAGE) the block first reorders its keys by digit in LDS and
-// then writes them out in that order, so neighbouring lanes store to
-// neighbouring addresses (the emission order spreads a block's keys over all
-// digits; this halved the first pass).
+// emission of one (tile) pair per covered tile in that order with a rank in
+// its tile's counter, the tiles' list starts, ranges and compositing launch
+// order from the counters, the pairs placed into their tiles' lists, then
+// each tile's list ordered by depth inside the tile.  The result is every
+// tile's list in ascending order of original depth with ties by surfel id
+// (Sec. 3.3.1), the order a stable sort by (tile, depth) gives.
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -26,220 +15,6 @@ __device__ __forceinline__ uint32_t count_n(const uint32_t* n_dev, int64_t n_hos
   if (!n_dev) return (uint32_t)n_host;
   int64_t n = (int64_t)(*n_dev);
   return (uint32_t)(n < cap ? n : cap);
-}
-
-template <typename K, int RB, int IPT>
-__global__ __launch_bounds__(kSortBlock) void k_hist(const K* __restrict__ keys,
-                                                     const uint32_t* __restrict__ n_dev,
-                                                     int64_t n_host, int64_t cap, int shift,
-                                                     uint32_t mask, uint32_t* __restrict__ hist,
-                                                     int64_t nblk) {
-  constexpr int R = 1 << RB;
-  __shared__ uint32_t h[R];
-  for (int d = threadIdx.x; d < R; d += kSortBlock) h[d] = 0;
-  __syncthreads();
-  const uint32_t n = count_n(n_dev, n_host, cap);
-  const int64_t base = (int64_t)blockIdx.x * (kSortBlock * IPT);
-  for (int it = 0; it < IPT; ++it) {
-    int64_t idx = base + it * kSortBlock + threadIdx.x;
-    if (idx < (int64_t)n) {
-      uint32_t d = (uint32_t)(keys[idx] >> shift) & mask;
-      atomicAdd(&h[d], 1u);
-    }
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < R; d += kSortBlock) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
-}
-
-// Exclusive scan of each digit's column of the block histogram table (one
-// block per digit, the column in rounds of 1024 with a carry) and the digit
-// totals.
-__global__ __launch_bounds__(kProjBlock) void k_colscan(uint32_t* __restrict__ hist, int64_t nblk,
-                                                        uint32_t* __restrict__ tot) {
-  __shared__ uint32_t s_w[kProjBlock / 64];
-  uint32_t* col = hist + (int64_t)blockIdx.x * nblk;
-  uint32_t carry = 0;
-  for (int64_t c0 = 0; c0 < nblk; c0 += 4 * kProjBlock) {
-    const int64_t b = c0 + 4 * (int64_t)threadIdx.x;
-    uint32_t v[4], loc = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = (b + k < nblk) ? col[b + k] : 0u;
-      loc += v[k];
-    }
-    uint32_t total;
-    uint32_t run = carry + block_excl_scan(loc, s_w, &total);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (b + k < nblk) col[b + k] = run;
-      run += v[k];
-    }
-    carry += total;
-  }
-  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
-}
-
-template <typename K, int RB, int IPT, bool STAGE>
-__global__ __launch_bounds__(kSortBlock) void k_scatter(
-    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int64_t cap,
-    int shift, uint32_t mask, int nbits, const uint32_t* __restrict__ hist_scan, int64_t nblk,
-    const uint32_t* __restrict__ tot) {
-  static_assert(kSortBlock == kProjBlock, "block scan width");
-  constexpr int R = 1 << RB;
-  constexpr int kWaves = kSortBlock / 64;
-  constexpr int kPerWave = kSortBlock * IPT / kWaves;
-  constexpr int kIters = kPerWave / 64;
-  constexpr int kDig = (R + kSortBlock - 1) / kSortBlock;
-  __shared__ uint32_t wcnt[kWaves][R];
-  __shared__ uint32_t s_base[R];
-  __shared__ uint32_t s_loc[R];
-  __shared__ K s_key[STAGE ? kSortBlock * IPT : 1];
-  __shared__ uint32_t s_val[STAGE ? kSortBlock * IPT : 1];
-  __shared__ uint32_t s_w[kSortBlock / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint32_t n = count_n(n_dev, n_host, cap);
-  const int64_t base = (int64_t)blockIdx.x * (kSortBlock * IPT);
-  if (base >= (int64_t)n) return;
-  for (int k = threadIdx.x; k < kWaves * R; k += kSortBlock) (&wcnt[0][0])[k] = 0;
-  {
-    // first output position of each digit: exclusive scan of the totals
-    uint32_t v[kDig], loc = 0;
-#pragma unroll
-    for (int k = 0; k < kDig; ++k) {
-      const int d = threadIdx.x * kDig + k;
-      v[k] = d < R ? tot[d] : 0u;
-      loc += v[k];
-    }
-    uint32_t total;
-    uint32_t run = block_excl_scan(loc, s_w, &total);
-#pragma unroll
-    for (int k = 0; k < kDig; ++k) {
-      const int d = threadIdx.x * kDig + k;
-      if (d < R) s_base[d] = run;
-      run += v[k];
-    }
-  }
-  __syncthreads();
-  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t rank[kIters];
-  uint32_t dig[kIters];
-  for (int it = 0; it < kIters; ++it) {
-    const int64_t idx = base + (int64_t)wv * kPerWave + it * 64 + lane;
-    const bool valid = idx < (int64_t)n;
-    uint32_t d = valid ? ((uint32_t)(kin[idx] >> shift) & mask) : 0u;
-    unsigned long long m = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      unsigned long long bb = __ballot(valid && bit);
-      m &= bit ? bb : ~bb;
-    }
-    uint32_t before = __popcll(m & lt_mask);
-    uint32_t pre = 0;
-    if (valid) pre = wcnt[wv][d];
-    __builtin_amdgcn_wave_barrier();
-    if (valid && before == 0) wcnt[wv][d] = pre + (uint32_t)__popcll(m);
-    __builtin_amdgcn_wave_barrier();
-    rank[it] = pre + before;
-    dig[it] = d;
-  }
-  __syncthreads();
-  if constexpr (!STAGE) {
-    // per digit: global start of this block, then the waves one after another
-    for (int d = threadIdx.x; d < R; d += kSortBlock) {
-      uint32_t run = s_base[d] + hist_scan[(int64_t)d * nblk + blockIdx.x];
-      for (int w = 0; w < kWaves; ++w) {
-        uint32_t c = wcnt[w][d];
-        wcnt[w][d] = run;
-        run += c;
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < kIters; ++it) {
-      const int64_t idx = base + (int64_t)wv * kPerWave + it * 64 + lane;
-      if (idx < (int64_t)n) {
-        uint32_t dst = wcnt[wv][dig[it]] + rank[it];
-        kout[dst] = kin[idx];
-        vout[dst] = vin[idx];
-      }
-    }
-    return;
-  }
-  // per digit: the waves one after another inside the block, the block's
-  // count, and the digit's first output position for this block
-  uint32_t v[kDig], cloc = 0;
-#pragma unroll
-  for (int k = 0; k < kDig; ++k) {
-    const int d = threadIdx.x * kDig + k;
-    v[k] = 0;
-    if (d < R) {
-      s_base[d] += hist_scan[(int64_t)d * nblk + blockIdx.x];
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = wcnt[w][d];
-        wcnt[w][d] = v[k];
-        v[k] += c;
-      }
-    }
-    cloc += v[k];
-  }
-  // block-local order: keys grouped by digit (exclusive scan of the counts)
-  uint32_t total;
-  uint32_t run = block_excl_scan(cloc, s_w, &total);
-#pragma unroll
-  for (int k = 0; k < kDig; ++k) {
-    const int d = threadIdx.x * kDig + k;
-    if (d < R) s_loc[d] = run;
-    run += v[k];
-  }
-  __syncthreads();
-  for (int it = 0; it < kIters; ++it) {
-    const int64_t idx = base + (int64_t)wv * kPerWave + it * 64 + lane;
-    if (idx < (int64_t)n) {
-      const uint32_t lp = s_loc[dig[it]] + wcnt[wv][dig[it]] + rank[it];
-      s_key[lp] = kin[idx];
-      s_val[lp] = vin[idx];
-    }
-  }
-  __syncthreads();
-  // write out in block order: each digit's keys are consecutive in LDS and
-  // land on consecutive output positions, so neighbouring lanes store
-  // neighbouring addresses
-  const int nk = (int)min<int64_t>((int64_t)n - base, (int64_t)kSortBlock * IPT);
-  for (int i = threadIdx.x; i < nk; i += kSortBlock) {
-    const K key = s_key[i];
-    const uint32_t d = (uint32_t)(key >> shift) & mask;
-    const uint32_t dst = s_base[d] + (uint32_t)i - s_loc[d];
-    kout[dst] = key;
-    vout[dst] = s_val[i];
-  }
-}
-
-// Stable LSD sort of (keys, vals) over the low key_bits bits in as few passes
-// of at most RB bits as possible.  Returns 1 when the result is in the
-// alternate buffers, 0 when it is back in keys / vals.
-template <typename K, int RB, int IPT, bool STAGE>
-int radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const uint32_t* n_dev, int64_t n_host,
-               int64_t cap, int key_bits, uint32_t* hist, uint32_t* histtmp, hipStream_t st) {
-  const int passes = (key_bits + RB - 1) / RB;
-  const int width = (key_bits + passes - 1) / passes;
-  const int64_t n_grid = n_dev ? cap : n_host;
-  if (n_grid <= 0 || passes == 0) return passes & 1;
-  static_assert(IPT >= 4 && kSortBlock * IPT >= kSortTileMin, "histogram table sizing");
-  constexpr int64_t kTile = kSortBlock * IPT;
-  const int64_t nblk = (n_grid + kTile - 1) / kTile;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = p * width;
-    const int nbits = (key_bits - shift) < width ? (key_bits - shift) : width;
-    const uint32_t mask = (1u << nbits) - 1u;
-    hipLaunchKernelGGL((k_hist<K, RB, IPT>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, n_dev,
-                       n_grid, cap, shift, mask, hist, nblk);
-    hipLaunchKernelGGL(k_colscan, dim3(1u << RB), dim3(kProjBlock), 0, st, hist, nblk, histtmp);
-    hipLaunchKernelGGL((k_scatter<K, RB, IPT, STAGE>), dim3((unsigned)nblk), dim3(kSortBlock), 0, st, k0, v0,
-                       k1, v1, n_dev, n_grid, cap, shift, mask, nbits, hist, nblk, histtmp);
-    K* tk = k0; k0 = k1; k1 = tk;
-    uint32_t* tv = v0; v0 = v1; v1 = tv;
-  }
-  return passes & 1;
 }
 
 constexpr int kEmitThreads = 256;
