@@ -340,14 +340,15 @@ __global__ __launch_bounds__(1024) void k_scan_part(uint32_t* part, uint32_t* pa
                                                     uint32_t* __restrict__ misc, int64_t cap,
                                                     int64_t scap,
                                                     const uint32_t* __restrict__ mpart, int nmb,
-                                                    int V, uint32_t* __restrict__ mcount) {
+                                                    int V, uint32_t* __restrict__ mcount,
+                                                    int check) {
   if (blockIdx.x == 2) {
     sum_mask_parts(mpart, nmb, V, mcount);
   } else {
     uint32_t* a = blockIdx.x == 0 ? part : partv;
     block_scan_small(a, a, n, misc + (blockIdx.x == 0 ? kMiscPairs : kMiscVisible));
   }
-  if (last_block(misc + kMiscTicketScan) && threadIdx.x == 0) {
+  if (check && last_block(misc + kMiscTicketScan) && threadIdx.x == 0) {
     const uint32_t pairs = __atomic_load_n(misc + kMiscPairs, __ATOMIC_RELAXED);
     const uint32_t vis = __atomic_load_n(misc + kMiscVisible, __ATOMIC_RELAXED);
     misc[kMiscOverflow] = ((int64_t)pairs > cap || (int64_t)vis > scap) ? 1u : 0u;
@@ -411,7 +412,8 @@ void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts
   if ((int64_t)L.V * L.nb <= kSmallScan) {
     hipLaunchKernelGGL(k_scan_part, dim3(mask_parts ? 3 : 2), dim3(1024), 0, st,
                        at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
-                       (int64_t)L.V * L.nb, misc, L.cap, L.scap, mpart, nmb, L.V, mcount);
+                       (int64_t)L.V * L.nb, misc, L.cap, L.scap, mpart, nmb, L.V, mcount,
+                       mask_parts ? 0 : 1);   // the fused step's compaction sets the flag
     return;
   }
   scan_u32(at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_part), (int64_t)L.V * L.nb,

@@ -27,7 +27,8 @@ constexpr int kEmitWin = 2 * kEmitRows;   // tiles of a block's count window
 // pair (from the per-block pair counts, scanned, plus the block's exclusive
 // scan of the counts), and the first slot of every emission block of
 // kEmitPairs pairs (each block start lies in exactly one slot; only the nblk
-// launched blocks).
+// launched blocks).  Block 0 also sets the overflow flag from the totals of
+// the count scans (the fused step's scan launch leaves it to this one).
 __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
                                                         const uint32_t* __restrict__ cnt,
                                                         const uint32_t* __restrict__ part,
@@ -38,9 +39,13 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
                                                         uint32_t* __restrict__ soff,
                                                         uint32_t* __restrict__ spos,
                                                         uint32_t* __restrict__ bstart,
-                                                        uint32_t nblk) {
+                                                        uint32_t nblk, uint32_t* __restrict__ misc,
+                                                        int64_t cap) {
   __shared__ uint32_t s_w[kProjBlock / 64];
   __shared__ uint32_t s_p[kProjBlock / 64];
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    misc[kMiscOverflow] =
+        ((int64_t)misc[kMiscPairs] > cap || (int64_t)misc[kMiscVisible] > scap) ? 1u : 0u;
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   const bool valid = i < N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -745,7 +750,8 @@ void launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, h
   hipLaunchKernelGGL(k_compact, dim3(L.nb), dim3(kProjBlock), 0, st, L.V, L.N, L.nb,
                      at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_part),
                      at<const uint32_t>(ws, L.o_partv), L.scap, sv, scnt, soff,
-                     at<uint32_t>(ws, L.o_pos), at<uint32_t>(ws, L.o_bstart), nblk_emit);
+                     at<uint32_t>(ws, L.o_pos), at<uint32_t>(ws, L.o_bstart), nblk_emit, misc,
+                     L.cap);
   uint32_t* n_emit = p_dev ? misc + kMiscEmit : nullptr;
   // 2. one (tile, rank) per covered tile, counted per tile
   uint32_t* keys = at<uint32_t>(ws, L.o_keys);
