@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
   uint32_t* s_rinfo = s_rows + kEmitRows;       // span start tile | tile row << 16
   __shared__ uint16_t s_rslot[kEmitRows];
   __shared__ uint32_t s_w[kEmitThreads / 64];
-  __shared__ uint32_t s_mm[2 * (kEmitThreads / 64)];
+  __shared__ uint32_t s_mm[8 * (kEmitThreads / 64)];
   const uint32_t S = count_n(s_dev, s_host, scap);
   const uint32_t P = count_n(p_dev, p_host, cap);
   const uint32_t pend = S ? soff[S - 1] + scnt[S - 1] : 0u;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     pre += nrow[k];
   }
   __syncthreads();
-  uint32_t tile[kPer];
+  uint32_t tile[kPer], vq[kPer], txq[kPer], tyq[kPer];   // global tile; view, column, row
   bool act[kPer];
   if (R <= (uint32_t)kEmitRows) {
     // row items: span of each rectangle row of the staged slots
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     for (int r = 0; r < kPer; ++r) {
       const uint32_t e = e0 + threadIdx.x + (uint32_t)(r * kEmitThreads);
       act[r] = e < e1;
-      tile[r] = 0u;
+      tile[r] = vq[r] = txq[r] = tyq[r] = 0u;
       if (act[r]) {
         const uint32_t t = e - s_off[0];
         const int rr = last_le(s_rx, (int)R, t);
@@ -274,6 +274,9 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         const int ty = (int)(info >> 16);
         const ViewDev& vw = views[slot / (uint32_t)N];
         tile[r] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
+        vq[r] = slot / (uint32_t)N;
+        txq[r] = (uint32_t)tx;
+        tyq[r] = (uint32_t)ty;
         keys[e] = tile[r];
         pslot[e] = slot;
         pdep[e] = s_dep[js];
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
   for (int q = 0; q < kPer; ++q) {
     const uint32_t e = e0 + threadIdx.x + (uint32_t)(q * kEmitThreads);
     act[q] = e < e1;
-    tile[q] = 0u;
+    tile[q] = vq[q] = txq[q] = tyq[q] = 0u;
     if (act[q]) {
       const int j = last_le(s_off, ns, e);
       const uint32_t slot = s_slot[j];
@@ -313,41 +316,72 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
       }
       if (ty >= y1) ty = y1 - 1;   // unreachable: the counts come from the same spans
       tile[q] = (uint32_t)vw.tile_off + (uint32_t)(ty * vw.tiles_x + tx);
+      vq[q] = slot / (uint32_t)N;
+      txq[q] = (uint32_t)tx;
+      tyq[q] = (uint32_t)ty;
       keys[e] = tile[q];
       pslot[e] = slot;
       pdep[e] = s_dep[j];
     }
   }
   }
-  // ranks: the block's tiles in [lo, hi]
-  uint32_t lo = 0xffffffffu, hi = 0u;
+  // ranks: the block's extent in tile index, view, column and row (maxima
+  // kept as complements so that every reduction is a minimum)
+  constexpr int kX = 8;
+  uint32_t m[kX];
+#pragma unroll
+  for (int k = 0; k < kX; ++k) m[k] = 0xffffffffu;
 #pragma unroll
   for (int q = 0; q < kPer; ++q)
     if (act[q]) {
-      lo = min(lo, tile[q]);
-      hi = max(hi, tile[q]);
+      const uint32_t x[4] = {tile[q], vq[q], txq[q], tyq[q]};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        m[2 * k] = min(m[2 * k], x[k]);
+        m[2 * k + 1] = min(m[2 * k + 1], ~x[k]);
+      }
     }
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
-    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
-  }
+  for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+    for (int k = 0; k < kX; ++k) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], d, 64));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int kWaves = kEmitThreads / 64;
-  if (lane == 0) {
-    s_mm[wv] = lo;
-    s_mm[kWaves + wv] = hi;
+  if (lane < kX) {
+    uint32_t mine = m[0];
+#pragma unroll
+    for (int k = 1; k < kX; ++k) mine = (lane == k) ? m[k] : mine;
+    s_mm[lane * kWaves + wv] = mine;
   }
   __syncthreads();                      // the row items are no longer read
-  lo = s_mm[0];
-  hi = s_mm[kWaves];
 #pragma unroll
-  for (int w = 1; w < kWaves; ++w) {
-    lo = min(lo, s_mm[w]);
-    hi = max(hi, s_mm[kWaves + w]);
+  for (int k = 0; k < kX; ++k) {
+    m[k] = s_mm[k * kWaves];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) m[k] = min(m[k], s_mm[k * kWaves + w]);
   }
+  const uint32_t lo = m[0], hi = ~m[1];
+  const uint32_t v0 = m[2], v1 = ~m[3], x0 = m[4], x1 = ~m[5], y0 = m[6], y1 = ~m[7];
+  // window layout: a single-view block whose rows x (columns rounded up to a
+  // power of two) fit counts by (row, column); otherwise by tile index when
+  // the index span fits
+  int lwx = 0;
+  while (lwx < 31 && (1u << lwx) < x1 - x0 + 1u) ++lwx;
+  const bool win2d = v0 == v1 && (uint64_t)(y1 - y0 + 1u) << lwx <= (uint64_t)kEmitWin;
+  const bool win1d = hi - lo < (uint32_t)kEmitWin;
+  uint32_t toff = 0u, tcols = 0u;
+  if (win2d) {
+    toff = (uint32_t)views[v0].tile_off;
+    tcols = (uint32_t)views[v0].tiles_x;
+  }
+  auto widx = [&](int q) -> uint32_t {
+    return win2d ? ((tyq[q] - y0) << lwx) + (txq[q] - x0) : tile[q] - lo;
+  };
+  auto wtile = [&](uint32_t w) -> uint32_t {
+    return win2d ? toff + (y0 + (w >> lwx)) * tcols + x0 + (w & ((1u << lwx) - 1u)) : lo + w;
+  };
   uint32_t rk[kPer];
-  if (hi - lo < (uint32_t)kEmitWin) {
+  if (win2d || win1d) {
     // one global add per distinct tile of the block: local ranks from LDS
     // counters over the window, then each nonzero window count takes its
     // tile's global base
@@ -357,21 +391,21 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     for (int k = 0; k < kWinPer; ++k) s_win[threadIdx.x + k * kEmitThreads] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) rk[q] = act[q] ? atomicAdd(&s_win[tile[q] - lo], 1u) : 0u;
+    for (int q = 0; q < kPer; ++q) rk[q] = act[q] ? atomicAdd(&s_win[widx(q)], 1u) : 0u;
     __syncthreads();
     uint32_t c[kWinPer];
 #pragma unroll
     for (int k = 0; k < kWinPer; ++k) {
       const uint32_t w = threadIdx.x + (uint32_t)(k * kEmitThreads);
       c[k] = s_win[w];
-      if (c[k]) c[k] = atomicAdd(&tcnt[lo + w], c[k]);
+      if (c[k]) c[k] = atomicAdd(&tcnt[wtile(w)], c[k]);
     }
 #pragma unroll
     for (int k = 0; k < kWinPer; ++k) s_win[threadIdx.x + k * kEmitThreads] = c[k];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPer; ++q)
-      if (act[q]) rk[q] += s_win[tile[q] - lo];
+      if (act[q]) rk[q] += s_win[widx(q)];
   } else {
     tile_ranks<kPer>(tcnt, tile, act, rk);
   }
