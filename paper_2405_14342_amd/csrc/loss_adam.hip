@@ -374,7 +374,6 @@ template <int C>
 __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ views, int V,
                                              int N, float eps, float x, float y, float z,
                                              const float q[4], float sx, float sy,
-                                             const uint32_t* __restrict__ cnt,
                                              const uint32_t* __restrict__ pos, int64_t scap,
                                              const float* __restrict__ ssum,
                                              const float4* __restrict__ rec, float* vals) {
@@ -384,13 +383,23 @@ __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ 
   float dft[3 + C];
 #pragma unroll
   for (int c = 0; c < 3 + C; ++c) dft[c] = 0.0f;
+  // the slots' positions (0xffffffff for a culled slot; after a slot-capacity
+  // overflow a visible slot may have none either, and the results are flagged
+  // invalid) are requested kPre views at a time, ahead of their sums
+  constexpr int kPre = 8;
+  uint32_t pv[kPre];
   for (int v = 0; v < V; ++v) {
-    const size_t slot = (size_t)v * N + i;
-    if (!cnt[slot]) continue;
-    // after a slot-capacity overflow a visible slot may have no sum (results
-    // are flagged invalid; the read stays inside the table)
-    const uint32_t p = pos[slot];
+    const int k = v & (kPre - 1);
+    if (k == 0) {
+#pragma unroll
+      for (int j = 0; j < kPre; ++j)
+        pv[j] = (v + j < V) ? pos[(size_t)(v + j) * N + i] : 0xffffffffu;
+    }
+    uint32_t p = pv[0];
+#pragma unroll
+    for (int j = 1; j < kPre; ++j) p = (k == j) ? pv[j] : p;
     if ((int64_t)p >= scap) continue;
+    const size_t slot = (size_t)v * N + i;
     const float4* r4 = reinterpret_cast<const float4*>(ssum) + (size_t)p * Q;
     float rg[4 * Q];
 #pragma unroll
@@ -430,14 +439,14 @@ template <int C>
 __global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
     const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
     const float* __restrict__ py, const float* __restrict__ pz, const float* __restrict__ pq,
-    const float* __restrict__ ps, const uint32_t* __restrict__ cnt,
+    const float* __restrict__ ps,
     const uint32_t* __restrict__ pos, int64_t scap, const float* __restrict__ ssum,
     const float4* __restrict__ rec, float* __restrict__ grads, int accumulate) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   const float q[4] = {pq[i], pq[N + i], pq[2 * (size_t)N + i], pq[3 * (size_t)N + i]};
   float vals[11 + C];
-  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], cnt, pos, scap,
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], pos, scap,
                   ssum, rec, vals);
   const size_t Nn = (size_t)N;
 #pragma unroll
@@ -455,7 +464,7 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
     const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
     const float* __restrict__ py, float* __restrict__ P, float* __restrict__ M,
     float* __restrict__ Vv, float* __restrict__ s_act, float* __restrict__ a_act,
-    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ pos, int64_t scap,
+    const uint32_t* __restrict__ pos, int64_t scap,
     const float* __restrict__ ssum, const float4* __restrict__ rec, const float* __restrict__ dzr,
     float* __restrict__ grads_out, AdamArgs aa) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
@@ -464,7 +473,7 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
   const size_t Nn = (size_t)N;
   const float q[4] = {P[Nn + i], P[2 * Nn + i], P[3 * Nn + i], P[4 * Nn + i]};
   float vals[11 + C];
-  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], cnt, pos,
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], pos,
                   scap, ssum, rec, vals);
   if (dzr) vals[0] += dzr[i];
   if (grads_out) {
@@ -483,7 +492,7 @@ void proj_bwd_launch(const Layout& L, void* ws, const rogs_surfels* s, float* gr
                      hipStream_t st) {
   hipLaunchKernelGGL((k_proj_bwd<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, s->x, s->y, s->z, s->q,
-                     s->s, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_pos),
+                     s->s, at<const uint32_t>(ws, L.o_pos),
                      L.scap, at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), grads,
                      acc ? 1 : 0);
 }
@@ -744,7 +753,7 @@ void proj_bwd_adam_launch(const Layout& L, void* ws, const float* x, const float
                           float* grads_out, const AdamArgs& aa, const float* dzr, hipStream_t st) {
   hipLaunchKernelGGL((k_proj_bwd_adam<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, x, y, params, m, v,
-                     s_act, a_act, at<const uint32_t>(ws, L.o_cnt), at<const uint32_t>(ws, L.o_pos),
+                     s_act, a_act, at<const uint32_t>(ws, L.o_pos),
                      L.scap, at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), dzr,
                      grads_out, aa);
 }

@@ -66,13 +66,16 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
       off += s_p[w];
     }
     __syncthreads();
+    // every slot's position, 0xffffffff for a culled one or one beyond the
+    // slot capacity
+    uint32_t sp = 0xffffffffu;
     if (vis) {
       const uint32_t pos = pre + (uint32_t)__popcll(b & lt_mask);
       if ((int64_t)pos < scap) {
         sval[pos] = (uint32_t)slot;
         scnt[pos] = c;
         soff[pos] = off;
-        spos[slot] = pos;
+        sp = pos;
         if (nblk) {
           const uint32_t b0 = (off + (uint32_t)kEmitPairs - 1u) / (uint32_t)kEmitPairs;
           const uint32_t b1 = min((off + c - 1u) / (uint32_t)kEmitPairs, nblk - 1u);
@@ -80,6 +83,7 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
         }
       }
     }
+    if (valid) spos[slot] = sp;
   }
 }
 
