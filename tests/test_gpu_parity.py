@@ -50,6 +50,13 @@ def make_scene(name):
         sc.cams = [synth.ortho_bev_camera((p[0], p[1]), 20.0, 200, 136, m_per_px=0.05)]
         sc.targets = synth._targets(sc.cams, sc.n_sem, 9000, 0.9)
         return sc
+    if name == "flat":
+        # one height for every surfel under a top-down orthographic camera:
+        # all centre depths are equal, so each tile's order rests on the
+        # tie rule alone (ascending surfel id)
+        sc = make_scene("ortho")
+        sc.z[:] = np.float32(np.median(sc.z))
+        return sc
     if name == "stack":
         # 6400 surfels squeezed into a 8 cm square: one tile's list holds all
         # of them (ranked through global memory), neighbours hold hundreds
@@ -100,7 +107,7 @@ def test_projection_records_bitexact(gpu, name):
         assert np.all(cnt[v][vis] <= (r[:, 1] - r[:, 0]) * (r[:, 3] - r[:, 2]))
 
 
-@pytest.mark.parametrize("name", SCENES + ["stack"])
+@pytest.mark.parametrize("name", SCENES + ["stack", "flat"])
 def test_keys_order_ranges_bitexact(gpu, name):
     sc = make_scene(name)
     st, ws, n = batched_state(sc)
@@ -147,7 +154,7 @@ def fwd_compare(sc, st, opts=None, views=None):
     return worst
 
 
-@pytest.mark.parametrize("name", SCENES + ["stack"])
+@pytest.mark.parametrize("name", SCENES + ["stack", "flat"])
 def test_forward_matches_oracle(gpu, name):
     sc = make_scene(name)
     st = TrainState(sc)
