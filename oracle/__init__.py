@@ -68,11 +68,16 @@ def _load():
         _lib.orc_tile_lists.argtypes = [I, I, P, P, P, P, P, I64, P, P, P]
         _lib.orc_tile_lists.restype = I64
         _lib.orc_render_fwd.argtypes = [I, I, P, P, P, P, P, P, I64, P, P, P]
-        _lib.orc_render_bwd.argtypes = [I, I, P, P, P, P, P, P, I64, P, P, P, P, P]
+        _lib.orc_render_bwd.argtypes = [I, I, P, P, P, P, P, P, I64, P, P, P, P]
         _lib.orc_loss.argtypes = [I, I64, P, P, P, P, I64, D, D, D, D, D, P, P]
         _lib.orc_loss.restype = D
         _lib.orc_adam.argtypes = [I64, P, P, P, P, D, D, D, D, I64]
         _lib.orc_num_threads.restype = I
+        _lib.orc_set_threads.argtypes = [I]
+        _lib.orc_z_rate.argtypes = [D, D, D, I64, I64]
+        _lib.orc_z_rate.restype = D
+        _lib.orc_adam_raw.argtypes = [I, I, P, P, P, P, P, D, D, I64, I64, D, D, D, P, P, I, P, P,
+                                      P, P]
         _lib.orc_row_spans.argtypes = [P, I, I, I, I, ctypes.c_float, I, I, I, I, P, P]
         _lib.orc_q32.argtypes = [I, P, I, P, P, P]
         _lib.orc_smooth.argtypes = [I64, P, P, D, P]
@@ -232,10 +237,12 @@ def render_fwd(prm: Params, cam, opts: Opts = Opts(), pix: Optional[np.ndarray] 
     return out, tf, nl
 
 
-def render_bwd(prm: Params, cam, out, G, tfinal, nlast, opts: Opts = Opts(),
+def render_bwd(prm: Params, cam, G, tfinal, nlast, opts: Opts = Opts(),
                pix: Optional[np.ndarray] = None, grads: Optional[np.ndarray] = None):
-    """Adjoint of :func:`render_fwd`: accumulates dL/d(z q s alpha rgb sem)
-    into ``grads`` (flat FP64 block, see :func:`split_grads`) and returns it."""
+    """Adjoint of :func:`render_fwd`: given dL/d(outputs) ``G`` and the
+    forward's T_final and n_last at the same pixels, accumulates dL/d(z q s
+    alpha rgb sem) into ``grads`` (flat FP64 block, see :func:`split_grads`)
+    and returns it."""
     L = _load()
     io, fo = opts.arrays()
     npix = cam.w * cam.h if pix is None else len(pix)
@@ -244,8 +251,8 @@ def render_bwd(prm: Params, cam, out, G, tfinal, nlast, opts: Opts = Opts(),
         grads = np.zeros((11 + prm.C) * prm.n, np.float64)
     c = lambda a, t: np.ascontiguousarray(a, t)
     L.orc_render_bwd(prm.n, prm.C, _p(prm.f32), _p(prm.f64()), _p(pack_camera(cam)), _p(io),
-                     _p(fo), _p(pix), npix, _p(c(out, np.float64)), _p(c(G, np.float64)),
-                     _p(c(tfinal, np.float64)), _p(c(nlast, np.int32)), _p(grads))
+                     _p(fo), _p(pix), npix, _p(c(G, np.float64)), _p(c(tfinal, np.float64)),
+                     _p(c(nlast, np.int32)), _p(grads))
     return grads
 
 
@@ -275,6 +282,78 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (OpenMP)."""
+    _load().orc_set_threads(int(n))
+
+
+# Sec. 4.2: learning rates of the parameter groups; the height rate is
+# proportional to the scene size and falls from 1.6e-4 to 1.6e-6 of it.
+RATE_Q = RATE_S = RATE_ALPHA = 1e-4
+RATE_RGB, RATE_SEM, RATE_EXPOSURE = 8e-3, 0.1, 1e-3
+RATE_Z_START, RATE_Z_END = 1.6e-4, 1.6e-6
+
+
+@dataclass
+class Rates:
+    """Per-group Adam rates; z_start / z_end: the height schedule (used when
+    total_steps > 0), z: the constant height rate otherwise."""
+    z: float
+    q: float
+    s: float
+    alpha: float
+    rgb: float
+    sem: float
+    exposure: float
+    z_start: float = 0.0
+    z_end: float = 0.0
+    total_steps: int = 0
+
+    def array(self):
+        return np.array([self.z, self.q, self.s, self.alpha, self.rgb, self.sem, self.exposure],
+                        np.float64)
+
+
+def paper_rates(extent: float, total_steps: int) -> Rates:
+    """The rates of Sec. 4.2 for a scene whose size (grid bounding-box
+    diagonal, metres) is ``extent``, over a run of ``total_steps`` steps."""
+    z0, z1 = RATE_Z_START * extent, RATE_Z_END * extent
+    return Rates(z0, RATE_Q, RATE_S, RATE_ALPHA, RATE_RGB, RATE_SEM, RATE_EXPOSURE, z0, z1,
+                 int(total_steps))
+
+
+def z_rate(rates: Rates, step: int) -> float:
+    """The height learning rate of step ``step`` (1-based) under ``rates``."""
+    return float(_load().orc_z_rate(rates.z, rates.z_start, rates.z_end, int(rates.total_steps),
+                                    int(step)))
+
+
+def adam_raw(params, grads_act, m, v, rates: Rates, step: int, b1=0.9, b2=0.999, eps=1e-8,
+             exposure=None, d_exposure=None, m_exp=None, v_exp=None):
+    """One Adam step (Sec. 4.2) on the raw block params[11 + C][n] (rows z,
+    q0..q3, log s_x, log s_y, logit alpha, rgb, sem), in place, from the
+    gradients w.r.t. the activated values the renderer reads (chained here
+    through exp and sigmoid), with per-group rates and the height schedule.
+    Optionally steps the per-view exposure [V, 2] too.  Returns the refreshed
+    activated (s[2][n], alpha[n])."""
+    L = _load()
+    for a in (params, grads_act, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == params.shape
+    K, n = params.shape
+    C = K - 11
+    s_act = np.zeros((2, n), np.float64)
+    a_act = np.zeros(n, np.float64)
+    nv = 0
+    if exposure is not None:
+        for a in (exposure, d_exposure, m_exp, v_exp):
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+        nv = exposure.shape[0]
+    L.orc_adam_raw(n, C, _p(params), _p(grads_act), _p(m), _p(v), _p(rates.array()),
+                   rates.z_start, rates.z_end, int(rates.total_steps), int(step), b1, b2, eps,
+                   _p(s_act), _p(a_act), nv, _p(exposure), _p(d_exposure), _p(m_exp), _p(v_exp))
+    return s_act, a_act
+
+
 # ------------------------------------------------------------ whole step
 
 def forward_views(prm: Params, cams: Sequence, opts: Opts = Opts()):
@@ -300,7 +379,7 @@ def loss_and_grads(prm: Params, cams: Sequence, targets: Sequence, exposure=None
                         exposure[v, 0], exposure[v, 1], lam_c, lam_s, 1.0 / V)
         total += l
         dexp[v] = de
-        render_bwd(prm, c, out, G, tf, nl, opts, grads=grads)
+        render_bwd(prm, c, G, tf, nl, opts, grads=grads)
     return total, grads, dexp, fwd
 
 

@@ -532,54 +532,76 @@ inline int n_rg(int C) { return 10 + C; }
 
 // Adjoint of pixel_forward for one pixel: G = dL/d(outputs) (5 + C values),
 // accumulated into rg[vis_index][n_rg].
-void pixel_backward(const Surfels& S, const ViewData& V, int px, int py, const double* O,
-                    size_t ostride, const double* G, size_t gstride, double Tfinal, int nlast,
-                    double* rg) {
+//
+// Eq. 6 written out for one pixel: O = sum_k w_k f_k with w_k = a_k T_k,
+// T_k = prod_{j<k} (1 - a_j), A = 1 - T_final.  For the opacity a_k after
+// the clamp, d(G.O)/da_k = T_k Gf_k - S_k / (1 - a_k) with the suffix
+// S_k = sum_{j>k} w_j Gf_j (every later weight carries the factor 1 - a_k),
+// and dA/da_k = T_final / (1 - a_k).  The entries the pixel reached are first
+// collected front to back, then the suffix is accumulated back to front.
+struct Hit {
+  int i, vi;
+  double dx, dy, gg, a, T, w, Gf;
+  bool clamped;
+};
+
+void pixel_backward(const Surfels& S, const ViewData& V, int px, int py, const double* G,
+                    size_t gstride, double Tfinal, int nlast, double* rg) {
   const int C = S.C, n = S.n, NR = n_rg(C);
   const int tile = (py / V.opts.th) * V.TX + (px / V.opts.tw);
   const std::vector<int>& L = V.lists[tile];
   const double pxc = px + 0.5, pyc = py + 0.5;
   const double GA = G[(4 + C) * gstride], GD = G[(3 + C) * gstride];
-  double GO = 0.0;   // G . O over the composited channels (rgb, sem, D)
-  for (int ch = 0; ch < 4 + C; ++ch) GO += G[ch * gstride] * O[ch * ostride];
-  double T = 1.0, Spre = 0.0;
+  thread_local std::vector<Hit> hits;
+  hits.clear();
+  double T = 1.0;
   for (int k = 0; k < nlast; ++k) {
     const int i = L[k];
     const Rec32& r = V.rec[i];
     if (!(q32(r, px, py) <= V.opts.qcut)) continue;
-    const int vi = V.vis_index[i];
-    const Geo& g = V.geo[vi];
-    double dx = pxc - g.u, dy = pyc - g.v;
-    double q = g.A * dx * dx + g.C * dy * dy + 2.0 * g.B * dx * dy;
-    double gg = std::exp(-0.5 * q);
-    double araw = S.alpha[i] * gg;
-    bool clamped = araw > (double)V.opts.amax;
-    double a = clamped ? (double)V.opts.amax : araw;
-    double w = a * T;
-    double Gf = GD * g.t[2];
-    for (int ch = 0; ch < 3; ++ch) Gf += G[ch * gstride] * S.rgb[(size_t)ch * n + i];
-    for (int ch = 0; ch < C; ++ch) Gf += G[(3 + ch) * gstride] * S.sem[(size_t)ch * n + i];
-    double* R = rg + (size_t)vi * NR;
+    Hit h;
+    h.i = i;
+    h.vi = V.vis_index[i];
+    const Geo& g = V.geo[h.vi];
+    h.dx = pxc - g.u;
+    h.dy = pyc - g.v;
+    const double q = g.A * h.dx * h.dx + g.C * h.dy * h.dy + 2.0 * g.B * h.dx * h.dy;
+    h.gg = std::exp(-0.5 * q);
+    const double araw = S.alpha[i] * h.gg;
+    h.clamped = araw > (double)V.opts.amax;
+    h.a = h.clamped ? (double)V.opts.amax : araw;
+    h.T = T;
+    h.w = h.a * T;
+    // Gf = dL/dO . (f_k, t_z): the pixel's output gradient against this
+    // surfel's composited features and depth
+    h.Gf = GD * g.t[2];
+    for (int ch = 0; ch < 3; ++ch) h.Gf += G[ch * gstride] * S.rgb[(size_t)ch * n + i];
+    for (int ch = 0; ch < C; ++ch) h.Gf += G[(3 + ch) * gstride] * S.sem[(size_t)ch * n + i];
+    hits.push_back(h);
+    T *= (1.0 - h.a);
+  }
+  double suffix = 0.0;   // sum over the entries behind the current one of w Gf
+  for (size_t kk = hits.size(); kk-- > 0;) {
+    const Hit& h = hits[kk];
+    const Geo& g = V.geo[h.vi];
+    double* R = rg + (size_t)h.vi * NR;
     // features: dO/df = w
-    for (int ch = 0; ch < 3; ++ch) R[7 + ch] += w * G[ch * gstride];
-    for (int ch = 0; ch < C; ++ch) R[10 + ch] += w * G[(3 + ch) * gstride];
-    R[6] += w * GD;
-    // opacity after the clamp: d(G.O)/da_k = T_k Gf_k - sum_{j>k} w_j Gf_j / (1 - a_k),
-    // dA/da_k = T_final / (1 - a_k)
-    double suffix = GO - Spre - w * Gf;
-    double da = T * Gf - suffix / (1.0 - a) + GA * Tfinal / (1.0 - a);
-    Spre += w * Gf;
-    if (!clamped) {
-      R[5] += gg * da;                 // d alpha
-      double dg = S.alpha[i] * da;
-      double dq = -0.5 * gg * dg;
-      R[2] += dx * dx * dq;            // dA
-      R[4] += dy * dy * dq;            // dC
-      R[3] += 2.0 * dx * dy * dq;      // dB
-      R[0] += -(2.0 * g.A * dx + 2.0 * g.B * dy) * dq;   // du
-      R[1] += -(2.0 * g.C * dy + 2.0 * g.B * dx) * dq;   // dv
+    for (int ch = 0; ch < 3; ++ch) R[7 + ch] += h.w * G[ch * gstride];
+    for (int ch = 0; ch < C; ++ch) R[10 + ch] += h.w * G[(3 + ch) * gstride];
+    R[6] += h.w * GD;
+    const double da = h.T * h.Gf - suffix / (1.0 - h.a) + GA * Tfinal / (1.0 - h.a);
+    suffix += h.w * h.Gf;
+    // the clamp a = min(alpha g, a_max) cuts the dependence on alpha and g
+    if (!h.clamped) {
+      R[5] += h.gg * da;                 // d alpha
+      const double dg = S.alpha[h.i] * da;
+      const double dq = -0.5 * h.gg * dg;
+      R[2] += h.dx * h.dx * dq;          // dA
+      R[4] += h.dy * h.dy * dq;          // dC
+      R[3] += 2.0 * h.dx * h.dy * dq;    // dB
+      R[0] += -(2.0 * g.A * h.dx + 2.0 * g.B * h.dy) * dq;   // du
+      R[1] += -(2.0 * g.C * h.dy + 2.0 * g.B * h.dx) * dq;   // dv
     }
-    T *= (1.0 - a);
   }
 }
 
@@ -737,13 +759,12 @@ void orc_render_fwd(int n, int C, const float* f32, const double* f64, const flo
   }
 }
 
-// Backward of one view: given the forward outputs O and dL/dO at the same
-// pixels (layout as orc_render_fwd), accumulate dL/d(params) into
+// Backward of one view: given dL/dO, T_final and n_last at the pixels of a
+// forward call (layout as orc_render_fwd), accumulate dL/d(params) into
 // grads = dz[n] dq[4][n] ds[2][n] dalpha[n] drgb[3][n] dsem[C][n].
 void orc_render_bwd(int n, int C, const float* f32, const double* f64, const float* cam,
                     const int* iopts, const float* fopts, const int32_t* pix, int64_t npix,
-                    const double* O, const double* G, const double* tfinal, const int32_t* nlast,
-                    double* grads) {
+                    const double* G, const double* tfinal, const int32_t* nlast, double* grads) {
   Surfels S = make_surfels(n, C, f32, f64);
   ViewData V;
   Cam cm = unpack_cam(cam);
@@ -762,8 +783,8 @@ void orc_render_bwd(int n, int C, const float* f32, const double* f64, const flo
 #pragma omp for schedule(dynamic, 256)
     for (int64_t k = 0; k < npix; ++k) {
       int64_t p = pix ? pix[k] : k;
-      pixel_backward(S, V, (int)(p % W), (int)(p / W), O + k, (size_t)npix, G + k, (size_t)npix,
-                     tfinal[k], nlast[k], part[tid].data());
+      pixel_backward(S, V, (int)(p % W), (int)(p / W), G + k, (size_t)npix, tfinal[k], nlast[k],
+                     part[tid].data());
     }
   }
   std::vector<double> rg(nv * NR, 0.0);
@@ -847,6 +868,68 @@ void orc_adam(int64_t n, double* p, const double* g, double* m, double* v, doubl
   }
 }
 
+// One optimiser step on the raw parameter block, as Sec. 4.2 sets it up.
+// The renderer reads the activated scale s = exp(l) and opacity
+// alpha = sigmoid(o); the optimiser moves the raw l and o, so their
+// gradients are chained through the activations (ds/dl = s, dalpha/do =
+// alpha (1 - alpha)), taken at the raw values before this step.  Rows of the
+// block [11 + C][n]: z | q (4) | l (2) | o | rgb (3) | sem (C).  Every group
+// has its own rate (lr[0..6] = z, q, s, alpha, rgb, sem, exposure); the z
+// rate follows the schedule below.  Afterwards the activated copies are
+// refreshed.  When n_views > 0 the per-view exposure (a, b) of Eq. 7 is
+// stepped too, with its own rate and moments.
+//
+// z rate: proportional to the scene size, starting at z_start and ending at
+// z_end after total_steps steps, moving linearly in log(rate) in between:
+// log r(t) = (1 - t) log z_start + t log z_end, t = (step - 1) / (total - 1).
+// total_steps = 1 uses z_start; total_steps = 0 (no schedule) uses lr[0].
+double orc_z_rate(double lr_z, double z_start, double z_end, int64_t total_steps, int64_t step) {
+  if (total_steps <= 0) return lr_z;
+  if (total_steps == 1) return z_start;
+  double t = (double)(step - 1) / (double)(total_steps - 1);
+  t = std::min(std::max(t, 0.0), 1.0);
+  return std::exp((1.0 - t) * std::log(z_start) + t * std::log(z_end));
+}
+
+void orc_adam_raw(int n, int C, double* p, const double* g_act, double* m, double* v,
+                  const double* lr, double z_start, double z_end, int64_t total_steps,
+                  int64_t step, double b1, double b2, double eps, double* s_act, double* a_act,
+                  int n_views, double* expo, const double* d_expo, double* m_e, double* v_e) {
+  const int K = 11 + C;
+  const double lr_z = orc_z_rate(lr[0], z_start, z_end, total_steps, step);
+  std::vector<double> graw(n);
+  for (int r = 0; r < K; ++r) {
+    double rate;
+    if (r == 0) rate = lr_z;
+    else if (r <= 4) rate = lr[1];
+    else if (r <= 6) rate = lr[2];
+    else if (r == 7) rate = lr[3];
+    else if (r <= 10) rate = lr[4];
+    else rate = lr[5];
+    double* pr = p + (size_t)r * n;
+    const double* gr = g_act + (size_t)r * n;
+    for (int i = 0; i < n; ++i) {
+      if (r == 5 || r == 6) {
+        graw[i] = gr[i] * std::exp(pr[i]);            // d/dl = s d/ds
+      } else if (r == 7) {
+        const double a = 1.0 / (1.0 + std::exp(-pr[i]));
+        graw[i] = gr[i] * a * (1.0 - a);              // d/do = alpha (1 - alpha) d/dalpha
+      } else {
+        graw[i] = gr[i];
+      }
+    }
+    orc_adam(n, pr, graw.data(), m + (size_t)r * n, v + (size_t)r * n, rate, b1, b2, eps, step);
+  }
+  for (int i = 0; i < n; ++i) {
+    s_act[i] = std::exp(p[5 * (size_t)n + i]);
+    s_act[(size_t)n + i] = std::exp(p[6 * (size_t)n + i]);
+    a_act[i] = 1.0 / (1.0 + std::exp(-p[7 * (size_t)n + i]));
+  }
+  if (n_views > 0) orc_adam(2 * (int64_t)n_views, expo, d_expo, m_e, v_e, lr[6], b1, b2, eps, step);
+}
+
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+void orc_set_threads(int n) { omp_set_num_threads(n); }
 
 }  // extern "C"

@@ -483,3 +483,14 @@ def tiny_scene(nx=8, ny=8, n_sem=4, w=32, h=32, f=40.0, seed=5, alpha_range=(0.3
         cams.append(pinhole_camera((0.3, -0.4, 0.7), math.radians(25.0), math.radians(-25.0),
                                    w + 8, h - 8, f * 1.1, cull=True))
     return custom_scene(x, y, z, q, s, alpha, rgb, sem, cams, name="tiny", seed=seed)
+
+
+def clamp_scene() -> Scene:
+    """The tiny scene's recipe with opacities in [0.995, 0.999] and footprints
+    three times larger, seen by a 48 x 40 camera (f = 60): near the centre of
+    every surfel alpha g exceeds the opacity clamp 0.99, on about 70
+    (pixel, surfel) pairs."""
+    sc = tiny_scene(w=48, h=40, f=60.0, alpha_range=(0.995, 0.999))
+    sc.s[:] = sc.s * np.float32(3.0)
+    sc.log_s[:] = np.log(sc.s.astype(np.float64)).astype(np.float32)
+    return sc

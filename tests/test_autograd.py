@@ -62,7 +62,7 @@ def test_backward_matches_oracle_adjoint(name):
         G = W[o:o + (5 + sc.n_sem) * npx].reshape(5 + sc.n_sem, npx).astype(np.float64)
         o += (5 + sc.n_sem) * npx
         fo, tf, nl = oracle.render_fwd(prm, cam)
-        oracle.render_bwd(prm, cam, fo, G, tf, nl, grads=ref)
+        oracle.render_bwd(prm, cam, G, tf, nl, grads=ref)
     r = oracle.split_grads(ref, sc.n, sc.n_sem)
     for nm, sl in ROWS.items():
         a = got[sl].reshape(r[nm].shape) if r[nm].ndim > 1 else got[sl].reshape(-1)

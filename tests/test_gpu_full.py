@@ -126,7 +126,7 @@ def test_full_size_gradients_from_sampled_pixels(name):
         gv = gv.astype(np.float32)
         block = G[NO * st.pix_off[v]: NO * st.pix_off[v + 1]].reshape(NO, npx)
         block[:, pix] = gv
-        oracle.render_bwd(prm, cam, o, gv.astype(np.float64), tf, nl, oopts(), pix=pix, grads=ref)
+        oracle.render_bwd(prm, cam, gv.astype(np.float64), tf, nl, oopts(), pix=pix, grads=ref)
     Gd = torch.as_tensor(G, device="cuda")
     grads = torch.empty((11 + sc.n_sem, sc.n), dtype=torch.float32, device="cuda")
     st.rg.render_bwd(surf, ws, st.out, Gd, grads, 0)
@@ -221,7 +221,7 @@ def test_c4_patch_finite_differences_and_autograd():
     o, tf, nl = oracle.render_fwd(sub, cam, oopts(), pix=pix)
     full = oracle.render_fwd(prm, cam, oopts(), pix=pix[::97])[0]
     np.testing.assert_array_equal(o[:, ::97], full)
-    ref = oracle.render_bwd(sub, cam, o, G, tf, nl, oopts(), pix=pix)
+    ref = oracle.render_bwd(sub, cam, G, tf, nl, oopts(), pix=pix)
     r = oracle.split_grads(ref, sub.n, sc.n_sem)
     fields = [("z", None), ("q", 1), ("s", 0), ("alpha", None), ("rgb", 2), ("sem", 5)]
     checked = 0

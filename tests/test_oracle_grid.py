@@ -139,8 +139,20 @@ def test_lidar_nearest_neighbour_and_loss():
         np.stack([x, y], -1).astype(np.float64), k=2)
     unique = d[:, 1] - d[:, 0] > 1e-9
     np.testing.assert_array_equal(idx[unique], ref[unique, 0])
-    zbar = rng.normal(0, 0.2, 800)
+    # Eq. 11, closed form: targets a constant c above the surfels give
+    # lambda N c^2, and every height is pulled up by 2 lambda c
     z = rng.normal(0, 0.2, 800)
-    val, dz = oracle.lidar_loss(z, zbar, 0.02)
-    assert val == pytest.approx(0.02 * ((z - zbar) ** 2).sum(), rel=1e-12)
-    np.testing.assert_allclose(dz, 0.04 * (z - zbar), rtol=1e-12)
+    c = 0.37
+    val, dz = oracle.lidar_loss(z, z + c, 0.02)
+    assert val == pytest.approx(0.02 * 800 * c * c, rel=1e-12)
+    np.testing.assert_allclose(dz, np.full(800, -2.0 * 0.02 * c), rtol=1e-12)
+    assert oracle.lidar_loss(z, z, 0.02)[0] == 0.0
+    # gradient against central differences at random targets (the loss is
+    # quadratic in each height, so a large step is exact up to rounding)
+    zbar = rng.normal(0, 0.2, 800)
+    _, dz = oracle.lidar_loss(z, zbar, 0.02)
+    for k in rng.choice(800, 12, replace=False):
+        e = np.zeros(800)
+        e[k] = 1e-2
+        fd = (oracle.lidar_loss(z + e, zbar, 0.02)[0] - oracle.lidar_loss(z - e, zbar, 0.02)[0]) / 2e-2
+        assert fd == pytest.approx(dz[k], rel=1e-9, abs=1e-13)

@@ -14,10 +14,14 @@ definition is exactly such a routine.
   P5  Eq. 6: 0 <= A < 1, A = 1 - T_final, n_last <= list length
   P6  sort (Sec. 3.3.1): ties ordered by id, ranges partition the pairs, the
       tile rectangle covers every pixel that passes the 3-sigma test
-  P7  adjoint of Eq. 5-6 vs central finite differences of the FP64 forward
+  P7  adjoint of Eq. 5-6 vs central finite differences of the FP64 forward,
+      also on a scene where the opacity clamp alpha_max is reached
   P8  adjoint of the projection vs finite differences of the projection
   P9  Eq. 7-9, 12 vs torch l1 / cross_entropy in FP64
-  P10 Adam vs torch.optim.Adam in FP64
+  P10 Adam vs torch.optim.Adam in FP64; the optimiser of Sec. 4.2 on the raw
+      parameters (chain rule through exp / sigmoid, per-group rates, height
+      rate decaying log-linearly) vs torch autograd + torch.optim.Adam with
+      parameter groups and a multiplicative rate schedule
 """
 import math
 
@@ -423,7 +427,7 @@ def test_p7_render_adjoint_matches_finite_differences(n_views):
     grads = np.zeros((11 + prm.C) * prm.n)
     for cam, G in zip(sc.cams, Gs):
         out, tf, nl = oracle.render_fwd(prm, cam, opts)
-        oracle.render_bwd(prm, cam, out, G, tf, nl, opts, grads=grads)
+        oracle.render_bwd(prm, cam, G, tf, nl, opts, grads=grads)
     g = oracle.split_grads(grads, prm.n, prm.C)
     h = 1e-6
     worst = 0.0
@@ -445,6 +449,63 @@ def test_p7_render_adjoint_matches_finite_differences(n_views):
             assert err < 1e-6, (name, k, fd, an[k])
         assert np.abs(an).max() > 0, name
     assert worst < 1e-6
+
+
+def clamp_margin(prm, cam, opts):
+    """Per pixel: the smallest |alpha g - alpha_max| over the surfels whose
+    3-sigma ellipse covers it (FP64), and the number of (pixel, surfel) pairs
+    with alpha g > alpha_max."""
+    g = oracle.geo64(prm, cam, opts)
+    vis, _, _ = oracle.contract(prm, cam, opts)
+    ys, xs = np.mgrid[0:cam.h, 0:cam.w]
+    pxc, pyc = xs.reshape(-1) + 0.5, ys.reshape(-1) + 0.5
+    margin = np.full(pxc.size, np.inf)
+    clamped = np.zeros(pxc.size, np.int64)
+    for i in np.nonzero(vis)[0]:
+        u, v, A, B, C, _ = g[i]
+        dx, dy = pxc - u, pyc - v
+        q = A * dx * dx + C * dy * dy + 2.0 * B * dx * dy
+        ag = prm.alpha[i] * np.exp(-0.5 * q)
+        inside = q <= opts.q_cut
+        margin = np.where(inside, np.minimum(margin, np.abs(ag - opts.alpha_max)), margin)
+        clamped += (inside & (ag > opts.alpha_max)).astype(np.int64)
+    return margin, clamped
+
+
+def test_p7_clamp_branch_matches_finite_differences():
+    """The adjoint through alpha' = min(alpha g, alpha_max) (Eq. 6 with the
+    opacity clamp): where the clamp holds, alpha' does not depend on alpha or
+    on the footprint, so those pixels add nothing to dL/dalpha or to the
+    geometry gradients, while their transmittance still scales everything
+    behind.  Pixels within 1e-4 of the kink get no weight, so that no +-h
+    step crosses it."""
+    sc = synth.clamp_scene()
+    opts = oracle.Opts(t_eps=0.0)
+    prm = oracle.Params.from_scene(sc)
+    cam = sc.cams[0]
+    margin, clamped = clamp_margin(prm, cam, opts)
+    rng = np.random.default_rng(17)
+    G = rng.normal(size=(5 + prm.C, cam.w * cam.h))
+    G[:, margin < 1e-4] = 0.0
+    assert clamped[margin >= 1e-4].sum() >= 50
+    out, tf, nl = oracle.render_fwd(prm, cam, opts)
+    grads = oracle.render_bwd(prm, cam, G, tf, nl, opts)
+    g = oracle.split_grads(grads, prm.n, prm.C)
+    h = 1e-6
+    for name in oracle.GRAD_NAMES:
+        flat = getattr(prm, name).reshape(-1)
+        an = g[name].reshape(-1)
+        scale = max(np.abs(an).max(), 1e-12)
+        for k in range(flat.size):
+            old = flat[k]
+            flat[k] = old + h
+            lp = _functional(prm, [cam], [G], opts)
+            flat[k] = old - h
+            lm = _functional(prm, [cam], [G], opts)
+            flat[k] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - an[k]) < 1e-6 * scale, (name, k, fd, an[k])
+        assert np.abs(an).max() > 0, name
 
 
 def test_p7_loss_chain_matches_finite_differences():
@@ -536,6 +597,62 @@ def test_p9_loss_matches_torch():
     # an empty mask contributes nothing
     L0, G0, d0 = oracle.loss(C, out, tgt, label, np.zeros(npix, np.uint8), 0)
     assert L0 == 0.0 and not G0.any() and not d0.any()
+
+
+@pytest.mark.parametrize("total", [3, 5])
+def test_p10_raw_adam_schedule_matches_torch(total):
+    """Sec. 4.2 optimiser on the raw parameters: torch differentiates the
+    activations s = exp(l) and alpha = sigmoid(o) (autograd), torch.optim.Adam
+    steps one parameter group per row group with the paper's rates, and
+    MultiplicativeLR shrinks the height rate by a constant factor per step so
+    that it goes from 1.6e-4 to 1.6e-6 of the scene size over the run (a
+    geometric sequence: linear in log(rate)); steps t = 0, 1/2, 1 for three
+    steps.  The exposure (a, b) is one more group."""
+    rng = np.random.default_rng(6)
+    n, C, V = 37, 3, 2
+    K = 11 + C
+    f64 = torch.float64
+    raw = rng.normal(size=(K, n))
+    raw[5:7] = np.log(rng.uniform(0.03, 0.1, (2, n)))
+    raw[7] = rng.normal(0.0, 2.0, n)
+    expo = rng.normal(0.0, 0.1, (V, 2))
+    rates = oracle.paper_rates(123.4, total)
+    assert rates.z_start == pytest.approx(123.4 * 1.6e-4) and rates.z_end == pytest.approx(123.4 * 1.6e-6)
+    rows = [slice(0, 1), slice(1, 5), slice(5, 7), slice(7, 8), slice(8, 11), slice(11, K)]
+    lrs = [rates.z_start, rates.q, rates.s, rates.alpha, rates.rgb, rates.sem]
+    leaves = [torch.tensor(raw[r], dtype=f64, requires_grad=True) for r in rows]
+    te = torch.tensor(expo, dtype=f64, requires_grad=True)
+    opt = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in zip(leaves, lrs)] +
+                           [{"params": [te], "lr": rates.exposure}], betas=(0.9, 0.999), eps=1e-8)
+    gamma = (rates.z_end / rates.z_start) ** (1.0 / (total - 1))
+    sched = torch.optim.lr_scheduler.MultiplicativeLR(
+        opt, [lambda k: gamma] + [lambda k: 1.0] * 6)
+    p, m, v = raw.copy(), np.zeros_like(raw), np.zeros_like(raw)
+    e, me, ve = expo.copy(), np.zeros_like(expo), np.zeros_like(expo)
+    for step in range(1, total + 1):
+        G = rng.normal(size=(K, n))            # dL / d(activated values)
+        Ge = rng.normal(size=(V, 2))
+        assert oracle.z_rate(rates, step) == pytest.approx(opt.param_groups[0]["lr"], rel=1e-13)
+        z, q, l, o, rgb, sem = leaves
+        act = [z, q, torch.exp(l), torch.sigmoid(o), rgb, sem]
+        loss = sum((torch.tensor(G[r], dtype=f64) * a).sum() for r, a in zip(rows, act))
+        loss = loss + (torch.tensor(Ge, dtype=f64) * te).sum()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        sched.step()
+        s_act, a_act = oracle.adam_raw(p, G, m, v, rates, step, exposure=e, d_exposure=Ge,
+                                       m_exp=me, v_exp=ve)
+        got = np.concatenate([t.detach().numpy() for t in leaves])
+        np.testing.assert_allclose(p, got, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(e, te.detach().numpy(), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(s_act, np.exp(got[5:7]), rtol=1e-15)
+        np.testing.assert_allclose(a_act, 1.0 / (1.0 + np.exp(-got[7])), rtol=1e-15)
+    assert oracle.z_rate(rates, total) == pytest.approx(rates.z_end, rel=1e-13)
+    assert oracle.z_rate(rates, 1) == pytest.approx(rates.z_start, rel=1e-15)
+    # no schedule: the constant height rate
+    flat = oracle.Rates(2e-3, 1e-4, 1e-4, 1e-4, 8e-3, 0.1, 1e-3)
+    assert oracle.z_rate(flat, 7) == 2e-3
 
 
 def test_p10_adam_matches_torch():
