@@ -2,17 +2,21 @@
 """Benchmark of the surfel-splatting training step on one MI355X.
 
 A step is the whole hot path over one batch: cull + EWA projection, tile-key
-emission with per-tile counting + placement + ranges, forward compositing, L1 + cross-entropy loss
-seed, backward compositing, projection adjoint, and the Adam update.
+emission with per-tile counting + placement + ranges, forward compositing, L1
++ cross-entropy loss seed, backward compositing, projection adjoint, and the
+Adam update.
 
-Default workload: 200,000 surfels (1000 x 200 grid at 0.1 m along a curved
-trajectory, 8 semantic classes) seen by six 1600 x 900 surround cameras.
-The headline is the fused step (loss fused into the forward, Adam into the
+Default workload: the batched step of 800,000 surfels (2000 x 400 grid at
+0.1 m along a curved trajectory, 8 semantic classes) seen by 24 views (4
+frames of a six-camera rig: front/back 1600 x 900, sides 1280 x 720).  The
+headline is the fused step (loss fused into the forward, Adam into the
 projection adjoint, the whole step one replayed hipGraph).  On the same
 workload it also times the same kernels launched one by one (each bracketed
 by HIP events: the per-kernel breakdown), the batched path (all views in one
 launch sequence) and the plain path (one launch sequence per view with a host
-read-back of the pair count).
+read-back of the pair count).  Extra keys: the fused step on the 3M-surfel,
+6 x 1920 x 1080, C = 16 workload, the grid-side loss terms, serving, and the
+FP64 oracle on a stated subset of the views at all host threads and at one.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -27,7 +31,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
-VALU_PEAK_TFLOPS = 78.6    # FP32 FMA without packed-FP32 ops: 256 CU x 64 lanes x 2 x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed FP32)
+VALU_NOPK_TFLOPS = 78.6    # FP32 FMA without packed-FP32 ops: 256 CU x 64 lanes x 2 x 2.4 GHz
 
 
 def algorithmic_bytes(kernel: str, st, stats, C: int, fused: bool) -> float:
@@ -76,14 +81,14 @@ def algorithmic_bytes(kernel: str, st, stats, C: int, fused: bool) -> float:
 
 
 def compositing_flops(kernel: str, n_eval: int, n_contrib: int, C: int, fused: bool) -> float:
-    """Arithmetic of the compositing kernels (FMA = 2 FLOPs).  Per evaluated
-    (pixel, list entry): the pixel offsets and the 3-sigma quadratic form, 14.
-    Per contributing entry, forward: exp, clamp, weight, 4 + C accumulations,
-    transmittance update and test, 9 + 2 (4 + C).  Backward: the same alpha
-    and weight plus the (3 + C)-channel dot product, the (3 + C) feature
-    gradients, the suffix/alpha adjoint and the five moments of dL/dq over
-    the pixel offsets, 31 + 4 (3 + C) without the depth and alpha loss terms
-    (fused loss), +7 with them."""
+    """Issued arithmetic of the compositing kernels (FMA = 2 FLOPs), a
+    diagnostic.  Per evaluated (pixel, list entry): the pixel offsets and the
+    3-sigma quadratic form, 14.  Per contributing entry, forward: exp, clamp,
+    weight, 4 + C accumulations, transmittance update and test, 9 + 2 (4 + C).
+    Backward: the same alpha and weight plus the (3 + C)-channel dot product,
+    the (3 + C) feature gradients, the suffix/alpha adjoint and the five
+    moments of dL/dq over the pixel offsets, 31 + 4 (3 + C) without the depth
+    and alpha loss terms (fused loss), +7 with them."""
     if kernel == "render_fwd":
         return 14.0 * n_eval + (9 + 2 * (4 + C)) * n_contrib
     if kernel == "render_bwd":
@@ -92,6 +97,15 @@ def compositing_flops(kernel: str, n_eval: int, n_contrib: int, C: int, fused: b
         return (compositing_flops("render_fwd", n_eval, n_contrib, C, True) +
                 compositing_flops("render_bwd", n_eval, n_contrib, C, True))
     return 0.0
+
+
+def algorithmic_flops(n_contrib: int, C: int) -> float:
+    """Algorithmic work of forward + backward compositing: per contributing
+    (pixel, surfel) entry 17 + 2 (4 + C) FLOPs forward (q 6, exp 2, clamp 2,
+    transmittance and weight 3, 2 per accumulated channel) and 35 + 5 (4 + C)
+    backward; 136 at C = 8.  Entries that are evaluated but rejected by the
+    3-sigma test are tiling overhead and are not counted."""
+    return float((17 + 2 * (4 + C) + 35 + 5 * (4 + C)) * n_contrib)
 
 
 def profiled_traffic(kernel: str, workload: str, tile: str):
@@ -110,28 +124,42 @@ def profiled_traffic(kernel: str, workload: str, tile: str):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(scene, budget_s: float = 12.0):
-    """The FP64 oracle's full training step (all views: forward, loss,
-    backward, Adam) on the host cores; repeated until budget_s is used."""
+def cpu_baseline(scene, views, threads: int, budget_s: float = 10.0):
+    """The FP64 oracle's training step restricted to the given views (forward,
+    loss and backward of those views, then the Sec. 4.2 optimiser on every
+    row of every surfel), on `threads` host threads; repeated until budget_s
+    is used.  Rate = pixels of those views per second."""
     import numpy as np
     import oracle
 
+    oracle.set_threads(threads)
     prm = oracle.Params.from_scene(scene)
+    cams = [scene.cams[v] for v in views]
+    tgts = [scene.targets[v] for v in views]
+    N, C = scene.n, scene.n_sem
+    raw = np.concatenate([scene.z[None], scene.q, scene.log_s, scene.logit_a[None], scene.rgb,
+                          scene.sem]).astype(np.float64)
+    m, v = np.zeros_like(raw), np.zeros_like(raw)
+    rates = oracle.paper_rates(scene.extent, 1)
+    npx = sum(c.w * c.h for c in cams)
     t0 = time.perf_counter()
     reps = 0
     while True:
-        L, g, dexp, _ = oracle.loss_and_grads(prm, scene.cams, scene.targets)
-        p = prm.z.copy()
-        oracle.adam(p, np.ascontiguousarray(g[:scene.n]), np.zeros_like(p), np.zeros_like(p), 1e-4, 1)
+        L, g, dexp, _ = oracle.loss_and_grads(prm, cams, tgts)
+        G = np.concatenate([g[:N][None], g[N:5 * N].reshape(4, N), g[5 * N:7 * N].reshape(2, N),
+                            g[7 * N:8 * N][None], g[8 * N:11 * N].reshape(3, N),
+                            g[11 * N:].reshape(C, N)])
+        oracle.adam_raw(raw, G, m, v, rates, reps + 1)
         reps += 1
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 20:
             break
-    px = scene.npix * reps
-    return {"value": round(px / el / 1e6, 3), "unit": "Mpixel/s", "cores": oracle.num_threads(),
+    desc = ", ".join(f"view {k} ({scene.cams[k].w}x{scene.cams[k].h})" for k in views)
+    return {"value": round(npx * reps / el / 1e6, 3), "unit": "Mpixel/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{reps} full FP64 oracle step(s) of the same workload "
-                      f"({scene.n_views} views, {scene.npix} px each step), {el:.1f} s"}
+            "sample": f"{reps} FP64 oracle step(s) on {len(views)} of the {scene.n_views} views "
+                      f"({desc}; {npx} px each step: forward, loss, backward, then Adam on all "
+                      f"{11 + C} rows of the {N} surfels), {el:.1f} s"}
 
 
 def grid_terms_bench(st, scene, run, steps: int, n_points: int = 1_000_000):
@@ -201,6 +229,40 @@ def bev_bench(surf, sc, opts, m_per_px: float = 0.05, chunk_px: int = 2000):
     return {"image": f"{W}x{H}", "m_per_px": m_per_px, "chunk_px": chunk_px, "chunks": chunks,
             "planes": "RGB+ELEV", "ms": round(ms, 2),
             "Mpixel_per_s": round(W * H / (ms * 1e-3) / 1e6, 1), "max_chunk_pairs": worst}
+
+
+def c4_bench(steps: int, warmup: int):
+    """The fused step (graph) on the 3M-surfel, C = 16 map seen by six
+    1920 x 1080 cameras (per-view culling), tile 16 x 4."""
+    import torch
+    from paper_2405_14342_amd import binding as B
+    from paper_2405_14342_amd import synth
+    from paper_2405_14342_amd.pipeline import TrainState
+
+    sc = synth.config4()
+    st = TrainState(sc, device="cuda:0", opts=B.make_opts(tile_w=16, tile_h=4))
+    total = warmup + steps + 1
+    st.step_fused(total_steps=total)
+    st.fit_fused_capacity()
+    for _ in range(max(0, warmup - 1)):
+        st.step_fused(total_steps=total, check=False)
+    torch.cuda.synchronize()
+    skipped0 = st.fused_status()["skipped"]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.step_fused(total_steps=total, check=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(1, steps)
+    fst = st.fused_status()
+    if fst["overflow"] or fst["skipped"] != skipped0:
+        raise RuntimeError("C4: pair capacity overflow during the timed steps")
+    out = {"workload": sc.name, "surfels": sc.n, "views": sc.n_views, "sem_classes": sc.n_sem,
+           "pixels_per_step": sc.npix, "path": "fused (hipGraph)", "tile": "16x4",
+           "ms_per_step": round(ms, 4), "value": round(sc.npix / (ms * 1e-3) / 1e6, 2),
+           "unit": "Mpixel/s", "pairs": fst["pairs"], "visible_slots": fst["visible"]}
+    del st
+    torch.cuda.empty_cache()
+    return out
 
 
 def serve_bench(seconds: float, warmup_s: float = 1.0, rate: float = 200.0,
@@ -292,7 +354,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="1..4: workload (default 2)")
+    ap.add_argument("--config", type=int, default=3, help="1..4: workload (default 3)")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the fused step on the 3M-surfel, 6 x 1920 x 1080 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -370,10 +434,11 @@ def main():
     st.fit_fused_capacity()
     run("fused", max(0, args.warmup - 1))
     print("[bench] warmup done", file=sys.stderr, flush=True)
+    skipped0 = st.fused_status()["skipped"]
     ms_f, ev_f, _ = run("fused", args.steps)
     fst = st.fused_status()
-    if fst["overflow"]:
-        raise RuntimeError("pair capacity overflow during the timed steps")
+    if fst["overflow"] or fst["skipped"] != skipped0:
+        raise RuntimeError("pair capacity overflow during the timed steps (steps skipped)")
     stats = {k: fst[k] for k in ("pairs", "visible", "pixels", "tiles", "slots")}
     print(f"[bench] fused (graph): {ms_f:.3f} ms/step, pairs {stats['pairs']}", file=sys.stderr,
           flush=True)
@@ -412,24 +477,33 @@ def main():
         if k in kernels and kernels[k]["ms_per_step"] > 0:
             kernels[k]["alg_TFLOPs"] = round(f / (kernels[k]["ms_per_step"] * 1e-3) / 1e12, 2)
     # roofline of the dominant single kernel (the fused step's compositing:
-    # forward, loss and backward of a tile), priced in FLOP/s against the
-    # non-packed FP32 VALU peak
+    # forward, loss and backward of a tile): algorithmic FLOPs (per
+    # contributing entry) per launch over its average launch duration, timed
+    # with HIP events on its launch stream, against the published FP32 peak
     dom = "render_step"
     dom_ms = prof[dom][0] / prof[dom][1]          # average duration of one launch
     per_launch = prof[dom][1] / args.steps
-    dom_flops = flops[dom] / per_launch
+    dom_flops = algorithmic_flops(n_contrib, C)    # one launch covers the whole step
     dom_bytes = algorithmic_bytes(dom, st, stats, C, True) / per_launch
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    issued = flops[dom] / per_launch
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2),
-                "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": profiled_traffic(dom, scene.name, f"{st.opts.tile_w}x{st.opts.tile_h}"),
                 "avg_launch_ms": round(dom_ms, 4), "alg_flops_per_launch": int(dom_flops),
+                "flops_per_contributing_entry": int(algorithmic_flops(1, C)),
                 "alg_bytes_per_launch": int(dom_bytes),
                 "hbm_achieved_GBs": round(dom_bytes / (dom_ms * 1e-3) / 1e9, 1),
                 "hbm_frac": round(dom_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "evaluated_entries": n_eval, "contributing_entries": n_contrib,
-                "peak_note": "non-packed FP32 FMA issue: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz"}
+                "peak_no_packed_fp32": VALU_NOPK_TFLOPS,
+                "frac_no_packed_fp32": round(achieved / VALU_NOPK_TFLOPS, 4),
+                "issued_flops_per_launch": int(issued),
+                "issued_TFLOPs": round(issued / (dom_ms * 1e-3) / 1e12, 2),
+                "peak_note": "157.3 TFLOP/s published FP32 vector peak (packed FP32); this build "
+                             "issues no packed FP32, whose ceiling is 256 CU x 64 lanes x 2 FLOP "
+                             "x 2.4 GHz = 78.6"}
 
     value = scene.npix / (ms_f * 1e-3) / 1e6
     line = {
@@ -450,16 +524,20 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
-    if not args.no_grid_terms:
+    if not args.no_grid_terms and hasattr(scene, "trajectory"):
         line["grid_terms"] = grid_terms_bench(st, scene, run, args.steps)
         g = line["grid_terms"]
         print(f"[bench] fused step with smoothness + LiDAR loss: {g['ms_per_step']} ms/step; "
               f"LiDAR targets {g['lidar_targets_ms']} ms; meshgrid layout {g['layout']['ms']} ms",
               file=sys.stderr, flush=True)
+    del st, ws_b
+    torch.cuda.empty_cache()
+    if not args.no_c4 and args.config != 4:
+        line["c4"] = c4_bench(args.steps, args.warmup)
+        print(f"[bench] C4 fused: {line['c4']['ms_per_step']} ms/step, "
+              f"{line['c4']['value']} Mpixel/s", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         print("[bench] serving (3M-surfel map, Poisson 200 req/s)...", file=sys.stderr, flush=True)
-        del st
-        torch.cuda.empty_cache()
         line["serve"] = serve_bench(args.serve_seconds)
         sv = line["serve"]
         print(f"[bench] serve: {sv['renders_per_s']} renders/s, p50 {sv['p50_ms']} ms, "
@@ -467,7 +545,13 @@ def main():
               flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(scene)
+        # the host's CPU share: OMP_NUM_THREADS where set, else the affinity mask
+        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        # a bounded sample: the first two views (one front, one side camera
+        # at C3) of the same workload
+        views = list(range(min(2, scene.n_views)))
+        line["cpu_baseline"] = cpu_baseline(scene, views, threads)
+        line["cpu_baseline_1_thread"] = cpu_baseline(scene, views, 1)
     print(json.dumps(line), flush=True)
 
 

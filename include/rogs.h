@@ -191,6 +191,19 @@ typedef struct {
   float z, q, s, alpha, rgb, sem, exposure;
 } rogs_lr;
 
+/* Optimiser settings (Sec. 4.2): per-group rates, and the height rate
+ * z(t) = z_start (z_end / z_start)^t, t = (step - 1) / (total_steps - 1)
+ * clamped to [0, 1] (log-linear from z_start to z_end over the run; the
+ * paper sets it proportional to the scene size, 1.6e-4 to 1.6e-6 of it);
+ * total_steps = 1 uses z_start, total_steps = 0 the constant lr.z.
+ * beta1, beta2 in [0, 1), eps > 0. */
+typedef struct {
+  rogs_lr lr;            /* per-group rates (lr.z used only when total_steps == 0) */
+  float z_start, z_end;  /* height rate at the first and at the last step (> 0) */
+  int64_t total_steps;   /* length of the height schedule; 0 = constant lr.z */
+  float beta1, beta2, eps;
+} rogs_optim;
+
 /* ------------------------------------------------------ context */
 ROGS_API int rogs_create(rogs_ctx** ctx);
 ROGS_API void rogs_destroy(rogs_ctx* ctx);
@@ -258,15 +271,16 @@ ROGS_API int rogs_render_bwd(rogs_ctx* ctx, const rogs_surfels* s, void* ws, con
 /* a10, Adam (Sec. 4.2) with torch semantics (bias correction, dense update)
  * on the packed raw block params[11 + C][N] (rows 5-6 log-scales, row 7
  * opacity logit) with moments m, v of the same shape; grads are w.r.t. the
- * activated values and are chained through exp / sigmoid.  Writes the
- * refreshed activated scales s_act[2][N] and opacity alpha_act[N].  When
- * exposure != NULL also steps exposure[n_views][2] with d_exposure and its
- * moments m_exp, v_exp.  step >= 1. */
+ * activated values and are chained through exp / sigmoid using the current
+ * s_act and alpha_act.  The height row's rate for this step comes from the
+ * schedule in optim.  Writes the refreshed activated scales s_act[2][N] =
+ * exp(log s) and opacity alpha_act[N] = sigmoid(logit).  When exposure !=
+ * NULL also steps exposure[n_views][2] with d_exposure and its moments m_exp,
+ * v_exp (rate lr.exposure).  step >= 1; n_sem 1..8 or 16. */
 ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* params, const float* grads,
-                   float* m, float* v, float* s_act, float* alpha_act, const rogs_lr* lr,
-                   int64_t step, float beta1, float beta2, float eps, float* exposure,
-                   const float* d_exposure, float* m_exp, float* v_exp, int32_t n_views,
-                   void* stream);
+                   float* m, float* v, float* s_act, float* alpha_act, const rogs_optim* optim,
+                   int64_t step, float* exposure, const float* d_exposure, float* m_exp,
+                   float* v_exp, int32_t n_views, void* stream);
 
 /* ------------------------------------------------------ fused step
  * The whole training step (a1-a10) over all views of a batch in one graph:
@@ -305,14 +319,6 @@ typedef struct {
   void* step_state;      /* 64 bytes of device memory, zeroed before the first step:
                             step count, skipped steps, last loss (16-byte aligned) */
 } rogs_train_state;
-
-typedef struct {
-  rogs_lr lr;            /* per-group rates (lr.z used only when total_steps == 0) */
-  float z_start, z_end;  /* z rate at the first and at the last step, log-linear between
-                            (Sec. 4.2: proportional to the scene size) */
-  int64_t total_steps;   /* length of the z schedule; 0 = constant lr.z */
-  float beta1, beta2, eps;
-} rogs_optim;
 
 #define ROGS_FUSED_EAGER 4u   /* run the same kernels without graph capture */
 

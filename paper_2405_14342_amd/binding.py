@@ -143,7 +143,7 @@ def load_library(path: str = LIB_PATH):
             "rogs_render_fwd": ([P, ctypes.POINTER(Surfels), P, P, P], I32),
             "rogs_loss": ([P, P, P, ctypes.POINTER(Targets), P, P, P, P], I32),
             "rogs_render_bwd": ([P, ctypes.POINTER(Surfels), P, P, P, P, U32, P], I32),
-            "rogs_adam_step": ([P, I32, I32, P, P, P, P, P, P, ctypes.POINTER(LR), I64, F, F, F,
+            "rogs_adam_step": ([P, I32, I32, P, P, P, P, P, P, ctypes.POINTER(Optim), I64,
                                 P, P, P, P, I32, P], I32),
             "rogs_debug_pairs": ([P, P, P, P, P, I64, P, I64, P], I32),
             "rogs_debug_records": ([P, P, P, P, P, P], I32),
@@ -349,14 +349,13 @@ class Rogs:
                                            ptr(dL_dout), ptr(grads), flags, _stream(stream)),
                     "rogs_render_bwd")
 
-    def adam_step(self, n, n_sem, params, grads, m, v, s_act, alpha_act, lr: LR, step, beta1=0.9,
-                  beta2=0.999, eps=1e-8, exposure=None, d_exposure=None, m_exp=None, v_exp=None,
-                  n_views=0, stream=None):
+    def adam_step(self, n, n_sem, params, grads, m, v, s_act, alpha_act, optim: "Optim", step,
+                  exposure=None, d_exposure=None, m_exp=None, v_exp=None, n_views=0, stream=None):
         self._check(self.L.rogs_adam_step(self.h, int(n), int(n_sem), ptr(params), ptr(grads), ptr(m),
-                                          ptr(v), ptr(s_act), ptr(alpha_act), ctypes.byref(lr),
-                                          int(step), beta1, beta2, eps, ptr(exposure),
-                                          ptr(d_exposure), ptr(m_exp), ptr(v_exp), int(n_views),
-                                          _stream(stream)), "rogs_adam_step")
+                                          ptr(v), ptr(s_act), ptr(alpha_act), ctypes.byref(optim),
+                                          int(step), ptr(exposure), ptr(d_exposure), ptr(m_exp),
+                                          ptr(v_exp), int(n_views), _stream(stream)),
+                    "rogs_adam_step")
 
     def batch_stats(self, ws, stream=None) -> dict:
         st = np.zeros(6, np.int64)

@@ -196,6 +196,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_tinfo = take(16 * (size_t)l.total_tiles);
   l.o_tfin = take(4 * (size_t)l.total_pix);
   l.o_nlast = take(4 * (size_t)l.total_pix);
+  l.o_drel = take(8 * (size_t)l.total_pix);
   l.o_gpair = take(4 * (size_t)cap * l.GS);
   l.o_histtmp = take(4 * 16);                  // tiles per launch-order bucket
   if (fused) {
@@ -330,6 +331,15 @@ int need_batch(rogs_ctx* c, void* ws, bool sorted) {
   if (ws != c->ws) return fail(c, ROGS_EINVAL, "workspace differs from the one given to rogs_project");
   if (sorted && !c->sorted) return fail(c, ROGS_ESTATE, "pairs not sorted: call rogs_bin_sort first");
   return ROGS_OK;
+}
+
+// Range check of the optimiser settings; the reason, or nullptr when valid.
+const char* check_optim(const rogs_optim* o) {
+  if (!(o->beta1 >= 0.0f && o->beta1 < 1.0f) || !(o->beta2 >= 0.0f && o->beta2 < 1.0f) ||
+      !(o->eps > 0.0f) || o->total_steps < 0 || !is_fin(o->z_start) || !is_fin(o->z_end) ||
+      (o->total_steps > 0 && !(o->z_start > 0.0f && o->z_end > 0.0f)))
+    return "optimizer settings out of range";
+  return nullptr;
 }
 
 int check_surfels(rogs_ctx* c, const rogs_surfels* s, const Layout& L) {
@@ -601,24 +611,23 @@ int rogs_render_bwd(rogs_ctx* c, const rogs_surfels* s, void* ws, const float* o
 }
 
 int rogs_adam_step(rogs_ctx* c, int32_t n, int32_t n_sem, float* params, const float* grads,
-                   float* m, float* v, float* s_act, float* alpha_act, const rogs_lr* lr,
-                   int64_t step, float beta1, float beta2, float eps, float* exposure,
-                   const float* d_exposure, float* m_exp, float* v_exp, int32_t n_views,
-                   void* stream) {
+                   float* m, float* v, float* s_act, float* alpha_act, const rogs_optim* optim,
+                   int64_t step, float* exposure, const float* d_exposure, float* m_exp,
+                   float* v_exp, int32_t n_views, void* stream) {
   if (!c) return ROGS_EINVAL;
   if (n < 1) return fail(c, ROGS_EINVAL, "n must be >= 1");
-  if (n_sem < 1 || n_sem > 64) return fail(c, ROGS_EINVAL, "n_sem out of range");
-  if (!params || !grads || !m || !v || !s_act || !alpha_act || !lr)
+  if (!rogs::sem_supported(n_sem)) return fail(c, ROGS_EINVAL, "n_sem must be 1..8 or 16");
+  if (!params || !grads || !m || !v || !s_act || !alpha_act || !optim)
     return fail(c, ROGS_EINVAL, "null argument");
   if (step < 1) return fail(c, ROGS_EINVAL, "step must be >= 1");
-  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
-    return fail(c, ROGS_EINVAL, "Adam hyper-parameters out of range");
+  const char* why = check_optim(optim);
+  if (why) return fail(c, ROGS_EINVAL, why);
   if (exposure && (!d_exposure || !m_exp || !v_exp || n_views < 1))
     return fail(c, ROGS_EINVAL, "exposure group needs gradients, moments and n_views >= 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
   prof_begin(c, 9, st);
-  rogs::launch_adam(n, n_sem, params, grads, m, v, s_act, alpha_act, lr, step, beta1, beta2, eps,
-                    exposure, d_exposure, m_exp, v_exp, n_views, st);
+  rogs::launch_adam(n, n_sem, params, grads, m, v, s_act, alpha_act, *optim, step, exposure,
+                    d_exposure, m_exp, v_exp, n_views, st);
   prof_end(c, st);
   return check_launch(c, "rogs_adam_step");
 }
@@ -730,10 +739,8 @@ int check_fused_args(rogs_ctx* c, const rogs_train_state* t, const rogs_targets*
     return fail(c, ROGS_EINVAL, "targets incomplete, or targets.exposure differs from the state's");
   if ((tg->nbr && !is_fin(tg->lambda_smooth)) || (tg->zbar && !is_fin(tg->lambda_z)))
     return fail(c, ROGS_EINVAL, "grid-side loss weights must be finite");
-  if (!(o->beta1 >= 0.0f && o->beta1 < 1.0f) || !(o->beta2 >= 0.0f && o->beta2 < 1.0f) ||
-      !(o->eps > 0.0f) || o->total_steps < 0 || !is_fin(o->z_start) || !is_fin(o->z_end) ||
-      (o->total_steps > 1 && !(o->z_start > 0.0f && o->z_end > 0.0f)))
-    return fail(c, ROGS_EINVAL, "optimizer settings out of range");
+  const char* why = check_optim(o);
+  if (why) return fail(c, ROGS_EINVAL, why);
   return ROGS_OK;
 }
 

@@ -774,15 +774,16 @@ void proj_bwd_adam_launch(const Layout& L, void* ws, const float* x, const float
   }
 
 void launch_adam(int n, int C, float* params, const float* grads, float* m, float* v,
-                 float* s_act, float* a_act, const rogs_lr* lr, int64_t step, float b1, float b2,
-                 float eps, float* expo, const float* dexpo, float* me, float* ve, int nv,
-                 hipStream_t st) {
+                 float* s_act, float* a_act, const rogs_optim& o, int64_t step, float* expo,
+                 const float* dexpo, float* me, float* ve, int nv, hipStream_t st) {
   AdamArgs aa{};
-  aa.lr = *lr;
-  aa.b1 = b1;
-  aa.b2 = b2;
-  aa.eps = eps;
-  aa.total_steps = 0;
+  aa.lr = o.lr;
+  aa.b1 = o.beta1;
+  aa.b2 = o.beta2;
+  aa.eps = o.eps;
+  aa.z_start = o.z_start;
+  aa.z_end = o.z_end;
+  aa.total_steps = o.total_steps;
   aa.step = step;
   aa.state = nullptr;
   aa.misc = nullptr;

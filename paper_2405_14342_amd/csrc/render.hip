@@ -12,6 +12,13 @@
 // order.  A pixel stops after the surfel that takes its transmittance below
 // t_eps; the wave leaves the list once all of its pixels have stopped.
 //
+// Depth is composited relative to a reference depth t0 per pixel, the depth
+// of the first (nearest) list entry that reaches the pixel: D' = sum w (t_z -
+// t0), D = D' + t0 A.  The backward differentiates D' and A, so the FP32
+// suffix term below cancels in proportion to the spread of the depths a pixel
+// sees instead of the absolute depth (tens of metres).  The entries a pixel
+// sees, and so t0, do not depend on the tile shape.
+//
 // The backward walks the list front to back again, recomputing T exactly as
 // the forward did, and uses sum_{j>k} w_j f_j = O - prefix - w_k f_k for the
 // suffix term of dO/d(alpha_k).  Per (tile, pair) it writes one record of
@@ -26,6 +33,8 @@
 // kernel (k_render_step): the per-pixel loss gradient, G.O, T_final and n_last
 // stay in registers between the two passes instead of going through HBM, and
 // a list the forward staged whole is not staged again.
+#include <cfloat>
+
 #include "rogs_internal.h"
 
 namespace rogs {
@@ -102,9 +111,12 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 }
 
 // Forward pass over the tile's list (Eq. 6): acc = sum w f (features, then
-// depth), T, and nl = entries up to the one that stopped the pixel.  With kE,
-// e_first = this lane's emission index in the first staged batch.
-template <int C, int PPL, bool kE>
+// with kD the relative depth sum w (t_z - t0)), T, and nl = entries up to the
+// one that stopped the pixel.  With kD, t0 = the depth of the pixel's first
+// contributing entry: the list is in ascending depth, so the running minimum
+// of the contributing depths (FLT_MAX while none).  With kE, e_first = this
+// lane's emission index in the first staged batch.
+template <int C, int PPL, bool kE, bool kD>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
                                              const uint32_t* __restrict__ spair,
@@ -112,7 +124,7 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
                                              const float4* __restrict__ feat, float4* s_r0,
                                              float4* s_r1, float4* s_f, const float* pyc,
                                              float (*acc)[3 + C + 1], float* T, uint32_t* nl,
-                                             uint32_t& e_first) {
+                                             uint32_t& e_first, float* t0) {
   // every multiply-add is written out: the forward rounds the same in every
   // kernel it is inlined into
 #pragma clang fp contract(off)
@@ -125,6 +137,7 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
     done[k] = !(tg.px < tg.W && py < tg.H);
     T[k] = 1.0f;
     nl[k] = 0;
+    if (kD) t0[k] = FLT_MAX;
 #pragma unroll
     for (int f = 0; f <= F; ++f) acc[k][f] = 0.0f;
   }
@@ -156,7 +169,10 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
           const float w = a * T[k];
 #pragma unroll
           for (int f = 0; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-          acc[k][F] = __builtin_fmaf(w, r1.w, acc[k][F]);
+          if (kD) {
+            t0[k] = fminf(t0[k], r1.w);
+            acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
+          }
           T[k] *= (1.0f - a);
           if (T[k] < teps) {
             done[k] = true;
@@ -239,8 +255,9 @@ __device__ __forceinline__ void feature_gemm(const float* s_w, const uint32_t* s
 }
 
 // Backward pass over the tile's list, given per pixel the output gradient
-// Gv (features, depth, alpha), G.O, T_final and n_last.  Writes one record of
-// NV gradient values per pair at its emission index: the five moments and
+// Gv (features, depth, alpha), G.O (with the relative depth D'), T_final,
+// n_last and the reference depth t0 (used with kDA).  Writes one record of NV
+// gradient values per pair at its emission index: the five moments and
 // dalpha are summed across the wave with a reduce-scatter, the feature and
 // depth gradients come from feature_gemm once per 16 entries.
 template <int C, int PPL, bool kDA>
@@ -254,7 +271,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
                                               const float (*Gv)[3 + C + 2], const float* GO,
                                               const float* Tf, const uint32_t* nl,
                                               float* __restrict__ gpair, int GS, bool staged,
-                                              uint32_t e_pre) {
+                                              uint32_t e_pre, const float* t0) {
   // every multiply-add is written out: the backward rounds the same in the
   // fused step and in the stand-alone backward
 #pragma clang fp contract(off)
@@ -269,13 +286,16 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
   const int lane = threadIdx.x;
   const int my_comp = rs_comp(lane, NR);
   const bool writer = my_comp >= 0 && (lane & rs_dup_bits(NR)) == 0;
-  float T[PPL], Spre[PPL];
+  float T[PPL], Spre[PPL], GAf[PPL];
   uint32_t maxn = 0;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     T[k] = 1.0f;
     Spre[k] = 0.0f;
     maxn = max(maxn, nl[k]);
+    // D = D' + t0 A: the alpha channel's gradient carries t0 dL/dD, times
+    // T_final for dA/d(alpha_k) = T_final / (1 - alpha_k)
+    GAf[k] = kDA ? __builtin_fmaf(t0[k], Gv[k][F], Gv[k][F + 1]) * Tf[k] : 0.0f;
   }
   for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, (uint32_t)__shfl_xor((int)maxn, o, 64));
   const uint32_t stop = tg.rbeg + min(maxn, tg.rend - tg.rbeg);
@@ -353,14 +373,14 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           const float a = clamped ? amax : araw;
           const float w = a * T[k];
           wrow[k * 64] = w;
-          float gf = kDA ? Gv[k][F] * tz : 0.0f;
+          float gf = kDA ? Gv[k][F] * (tz - t0[k]) : 0.0f;
 #pragma unroll
           for (int f = 0; f < F; ++f) gf = __builtin_fmaf(Gv[k][f], fv[f], gf);
           const float om = 1.0f - a;
           const float inv = __builtin_amdgcn_rcpf(om);
           const float suffix = __builtin_fmaf(-w, gf, GO[k] - Spre[k]);
           float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
-          if (kDA) da = __builtin_fmaf(Gv[k][F + 1] * Tf[k], inv, da);
+          if (kDA) da = __builtin_fmaf(GAf[k], inv, da);
           Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
           const float gd = clamped ? 0.0f : g;    // the clamp cuts alpha's dependence on g
           pv[5] = __builtin_fmaf(gd, da, pv[5]);
@@ -394,15 +414,16 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
   }
 }
 
-// Forward compositing of the batch: the 5 + C output planes per view, T_final
-// and n_last per pixel.
+// Forward compositing of the batch: the 5 + C output planes per view, and per
+// pixel T_final, n_last, the relative depth D' and its reference t0 for the
+// backward.
 template <int C, int PPL>
 __global__ __launch_bounds__(64) void k_render_fwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
     float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, float* __restrict__ out,
-    float* __restrict__ tfin, uint32_t* __restrict__ nlast) {
+    float* __restrict__ tfin, uint32_t* __restrict__ nlast, float2* __restrict__ drel) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;           // output channels
@@ -414,8 +435,9 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 #pragma unroll
   for (int k = 0; k < PPL; ++k) pyc[k] = (float)(tg.py0 + k * tg.rows) + 0.5f;
   uint32_t e_first;
-  forward_tile<C, PPL, false>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1, s_f, pyc,
-                              acc, T, nl, e_first);
+  float t0[PPL];
+  forward_tile<C, PPL, false, true>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1, s_f,
+                                    pyc, acc, T, nl, e_first, t0);
   const uint32_t len = tg.rend - tg.rbeg;
   const size_t HW = (size_t)tg.W * tg.H;
   float* o = out + (size_t)NO * tg.vw->pix_off;
@@ -425,10 +447,14 @@ __global__ __launch_bounds__(64) void k_render_fwd(
     if (!(tg.px < tg.W && py < tg.H)) continue;
     const size_t p = (size_t)py * tg.W + tg.px;
 #pragma unroll
-    for (int f = 0; f <= F; ++f) o[f * HW + p] = acc[k][f];
-    o[(F + 1) * HW + p] = 1.0f - T[k];
+    for (int f = 0; f < F; ++f) o[f * HW + p] = acc[k][f];
+    const float al = 1.0f - T[k];
+    const float t0k = t0[k] < FLT_MAX ? t0[k] : 0.0f;        // 0 where nothing contributed
+    o[F * HW + p] = __builtin_fmaf(t0k, al, acc[k][F]);      // D = D' + t0 A
+    o[(F + 1) * HW + p] = al;
     tfin[tg.vw->pix_off + p] = T[k];
     nlast[tg.vw->pix_off + p] = (T[k] < teps) ? nl[k] : len;
+    drel[tg.vw->pix_off + p] = make_float2(acc[k][F], t0k);
   }
 }
 
@@ -441,7 +467,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, const float* __restrict__ out,
     const float* __restrict__ G, const float* __restrict__ tfin,
-    const uint32_t* __restrict__ nlast, float* __restrict__ gpair, int GS) {
+    const uint32_t* __restrict__ nlast, const float2* __restrict__ drel,
+    float* __restrict__ gpair, int GS) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
@@ -451,7 +478,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   __shared__ uint32_t s_e[kStage];
   const TileGeom tg = tile_geom(views, N, tw, th, tinfo);
   const size_t HW = (size_t)tg.W * tg.H;
-  float Gv[PPL][F + 2], GO[PPL], Tf[PPL], pyc[PPL];
+  float Gv[PPL][F + 2], GO[PPL], Tf[PPL], pyc[PPL], t0[PPL];
   uint32_t nl[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
@@ -460,6 +487,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     GO[k] = 0.0f;
     Tf[k] = 1.0f;
     nl[k] = 0;
+    t0[k] = 0.0f;
 #pragma unroll
     for (int f = 0; f < F + 2; ++f) Gv[k][f] = 0.0f;
     if (tg.px < tg.W && py < tg.H) {
@@ -470,15 +498,18 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 #pragma unroll
       for (int f = 0; f < F + 2; ++f) Gv[k][f] = g[f * HW];
 #pragma unroll
-      for (int f = 0; f <= F; ++f) go = __builtin_fmaf(Gv[k][f], o[f * HW], go);
+      for (int f = 0; f < F; ++f) go = __builtin_fmaf(Gv[k][f], o[f * HW], go);
+      const float2 dr = drel[tg.vw->pix_off + p];          // D' and t0 of the forward
+      go = __builtin_fmaf(Gv[k][F], dr.x, go);
       GO[k] = go;
+      t0[k] = dr.y;
       Tf[k] = tfin[tg.vw->pix_off + p];
       nl[k] = nlast[tg.vw->pix_off + p];
     }
   }
   backward_tile<C, PPL, true>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
                               reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair, GS,
-                              false, 0u);
+                              false, 0u, t0);
 }
 
 // The fused step's compositing: forward, the loss of Eq. 7-9 and 12 per pixel
@@ -533,8 +564,11 @@ __global__ __launch_bounds__(64) void k_render_step(
     float T[PPL], acc[PPL][F + 1];
     uint32_t nlf[PPL];
     uint32_t e_first = 0;
-    forward_tile<C, PPL, true>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1, s_f,
-                               pyc, acc, T, nlf, e_first);
+    float t0[PPL];          // not used: the fused loss has no depth term
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) t0[k] = 0.0f;
+    forward_tile<C, PPL, true, false>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1,
+                                      s_f, pyc, acc, T, nlf, e_first, t0);
     // loss epilogue: dL/dO and G.O per pixel, this tile's loss partials
     const uint32_t len = tg.rend - tg.rbeg;
     float l = 0.0f, dal = 0.0f, dbl = 0.0f;
@@ -550,11 +584,11 @@ __global__ __launch_bounds__(64) void k_render_step(
       for (int f = 0; f < F; ++f) Gv[k][f] = g[f];
       Gv[k][F] = 0.0f;         // the fused loss has no depth or alpha term
       Gv[k][F + 1] = 0.0f;
-      // G.O over the composited channels and depth, in the same form as the
-      // stand-alone backward so that both round alike
+      // G.O over the composited channels, in the same form as the stand-alone
+      // backward so that both round alike (its depth term adds 0 * D' = +0)
       float go = 0.0f;
 #pragma unroll
-      for (int f = 0; f <= F; ++f) go = __builtin_fmaf(Gv[k][f], acc[k][f], go);
+      for (int f = 0; f < F; ++f) go = __builtin_fmaf(Gv[k][f], acc[k][f], go);
       const bool in_img = tg.px < tg.W && py < tg.H;
       const float tf = in_img ? T[k] : 1.0f;
       const uint32_t nlk = in_img ? ((T[k] < teps) ? nlf[k] : len) : 0u;
@@ -571,7 +605,7 @@ __global__ __launch_bounds__(64) void k_render_step(
     // the fused loss has no depth or alpha term: their gradient rows are zero
     backward_tile<C, PPL, false>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
                                  reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair,
-                                 GS, len <= (uint32_t)kStage, e_first);
+                                 GS, len <= (uint32_t)kStage, e_first, t0);
   }
 }
 
@@ -635,7 +669,8 @@ void fwd_launch(const Layout& L, void* ws, float* out, hipStream_t st) {
                      L.t_eps, at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out,
-                     at<float>(ws, L.o_tfin), at<uint32_t>(ws, L.o_nlast));
+                     at<float>(ws, L.o_tfin), at<uint32_t>(ws, L.o_nlast),
+                     at<float2>(ws, L.o_drel));
 }
 
 template <int C, int PPL>
@@ -646,7 +681,7 @@ void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hip
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out, G,
                      at<const float>(ws, L.o_tfin), at<const uint32_t>(ws, L.o_nlast),
-                     at<float>(ws, L.o_gpair), L.GS);
+                     at<const float2>(ws, L.o_drel), at<float>(ws, L.o_gpair), L.GS);
 }
 
 template <int C, int PPL>

@@ -48,6 +48,7 @@ struct Layout {
   float eps2d = 0.3f, q_cut = 9.0f, alpha_max = 0.99f, t_eps = 1e-6f;
   size_t o_views, o_dzr, o_regpart, o_regtot, o_cnt, o_rec, o_rect, o_rspan, o_bstart, o_feat, o_part, o_partv, o_parttmp;
   size_t o_keys, o_vals, o_keys2, o_vals2, o_pslot, o_ranges, o_tfin, o_nlast, o_gpair;
+  size_t o_drel = 0;           // per pixel: relative depth sum w (t_z - t0) and t0 (float2)
   size_t o_spair;              // slot of each tile-sorted pair
   size_t o_pdep;               // t_z bits of each emitted pair (the tile sort's key)
   size_t o_tcnt, o_tstart, o_tscan;   // pairs per tile, first list position, scan partials
@@ -607,9 +608,8 @@ void launch_slot_sums(const Layout& L, void* ws, hipStream_t st, bool clear = tr
 void launch_proj_bwd(const Layout& L, void* ws, const rogs_surfels* s, float* grads,
                      bool accumulate, hipStream_t st);
 void launch_adam(int n, int C, float* params, const float* grads, float* m, float* v,
-                 float* s_act, float* a_act, const rogs_lr* lr, int64_t step, float b1, float b2,
-                 float eps, float* expo, const float* dexpo, float* me, float* ve, int nv,
-                 hipStream_t st);
+                 float* s_act, float* a_act, const rogs_optim& o, int64_t step, float* expo,
+                 const float* dexpo, float* me, float* ve, int nv, hipStream_t st);
 // Fused: projection adjoint of every surfel followed by its Adam update (and
 // the exposure update); optional gradient output.  Skipped on overflow.
 // dzr (nullable): per-surfel dL/dz of the grid-side terms, added to the

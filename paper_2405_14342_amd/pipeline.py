@@ -31,27 +31,14 @@ LR_RGB, LR_SEM, LR_EXPOSURE = 0.008, 0.1, 0.001
 LR_Z_START, LR_Z_END = 1.6e-4, 1.6e-6      # times the scene size
 
 
-def z_learning_rate(extent: float, step: int, total_steps: int) -> float:
-    """z learning rate: proportional to the scene size, decaying log-linearly
-    from 1.6e-4 to 1.6e-6 of it over the run (Sec. 4.2).  Same expression as
-    the fused step's device schedule: z_start (z_end / z_start)^t."""
+def paper_optim(extent: float, total_steps: int) -> B.Optim:
+    """Optimizer settings of Sec. 4.2: the per-group rates, and the height
+    rate proportional to the scene size, from 1.6e-4 to 1.6e-6 of it over
+    ``total_steps`` steps (the library evaluates the schedule per step)."""
     z0 = float(np.float32(extent * LR_Z_START))
     z1 = float(np.float32(extent * LR_Z_END))
-    if total_steps <= 1:
-        return z0
-    t = min(max((step - 1) / (total_steps - 1), 0.0), 1.0)
-    return z0 * (z1 / z0) ** t
-
-
-def paper_lr(extent: float, step: int = 1, total_steps: int = 1) -> B.LR:
-    return B.LR(z_learning_rate(extent, step, total_steps), LR_ROT, LR_SCALE, LR_ALPHA, LR_RGB,
-                LR_SEM, LR_EXPOSURE)
-
-
-def paper_optim(extent: float, total_steps: int) -> B.Optim:
-    """Optimizer settings of Sec. 4.2 with the device-side z schedule."""
-    return B.Optim(paper_lr(extent), float(np.float32(extent * LR_Z_START)),
-                   float(np.float32(extent * LR_Z_END)), int(total_steps), 0.9, 0.999, 1e-8)
+    lr = B.LR(z0, LR_ROT, LR_SCALE, LR_ALPHA, LR_RGB, LR_SEM, LR_EXPOSURE)
+    return B.Optim(lr, z0, z1, int(total_steps), 0.9, 0.999, 1e-8)
 
 
 def n_out(C: int) -> int:
@@ -210,10 +197,11 @@ class TrainState:
         self.rg.render_fwd(self.surfels(), ws, self.out_view(v))
         return ws, n
 
-    def step_plain(self, lr: Optional[B.LR] = None, total_steps: int = 1, adam: bool = True):
+    def step_plain(self, optim: Optional[B.Optim] = None, total_steps: int = 1,
+                   adam: bool = True):
         """One training step, one launch sequence per view (the plain path)."""
         self.step_count += 1
-        lr = lr or paper_lr(self.scene.extent, self.step_count, total_steps)
+        optim = optim or paper_optim(self.scene.extent, total_steps)
         self.loss.zero_()
         self.d_exp.zero_()
         surf = self.surfels()
@@ -224,13 +212,13 @@ class TrainState:
             self.rg.render_bwd(surf, ws, ov, gv, self.grads, B.ACCUMULATE if v else 0)
         self._grid_terms()
         if adam:
-            self.adam(lr)
+            self.adam(optim)
 
-    def step_batched(self, lr: Optional[B.LR] = None, total_steps: int = 1, adam: bool = True,
-                     sync: bool = True):
+    def step_batched(self, optim: Optional[B.Optim] = None, total_steps: int = 1,
+                     adam: bool = True, sync: bool = True):
         """One training step with every view in one batch."""
         self.step_count += 1
-        lr = lr or paper_lr(self.scene.extent, self.step_count, total_steps)
+        optim = optim or paper_optim(self.scene.extent, total_steps)
         self.loss.zero_()
         self.d_exp.zero_()
         surf = self.surfels()
@@ -240,11 +228,11 @@ class TrainState:
         self.rg.render_bwd(surf, ws, self.out, self.G, self.grads, 0)
         self._grid_terms()
         if adam:
-            self.adam(lr)
+            self.adam(optim)
 
-    def adam(self, lr: B.LR):
+    def adam(self, optim: B.Optim):
         self.rg.adam_step(self.N, self.C, self.params, self.grads, self.m, self.v, self.s_act,
-                          self.alpha_act, lr, self.step_count, exposure=self.exposure,
+                          self.alpha_act, optim, self.step_count, exposure=self.exposure,
                           d_exposure=self.d_exp, m_exp=self.m_exp, v_exp=self.v_exp,
                           n_views=self.V)
 

@@ -69,6 +69,8 @@ def test_backward_matches_oracle_adjoint(name):
         mx = np.abs(r[nm]).max()
         d = np.abs(a - r[nm])
         assert d.max() <= 1e-4 * mx, (nm, d.max() / mx)
+        big = np.abs(r[nm]) >= 1e-2 * mx
+        assert (d[big] / np.abs(r[nm][big])).max() <= 1e-4, nm
 
 
 @pytest.mark.gpu
