@@ -354,6 +354,19 @@ ROGS_API int rogs_elev_loss(rogs_ctx* ctx, int32_t n, const float* z, const int3
                             float lambda_smooth, const float* zbar, float lambda_z, float* dz,
                             float* loss_out, void* scratch, size_t scratch_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as rogs_elev_loss, without a scratch argument.  The
+ * block partial sums live in a fixed device array of the library, sized for
+ * n <= ROGS_ELEV_STATIC_MAX_N (256 KiB per GPU, held until the process ends);
+ * larger n returns ROGS_EINVAL.  The call allocates nothing.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialised by the caller. */
+#define ROGS_ELEV_STATIC_MAX_N 16777216
+ROGS_API int rogs_elev_loss_static(rogs_ctx* ctx, int32_t n, const float* z, const int32_t* nbr,
+                                   float lambda_smooth, const float* zbar, float lambda_z,
+                                   float* dz, float* loss_out, void* stream);
+
 /* LiDAR targets of Eq. 11: zbar[i] = pz of the point nearest to (x_i, y_i) in
  * the xy-plane (squared distance in binary64 of the binary32 inputs, ties to
  * the lower point index; brute force over the points), idx[i] its index

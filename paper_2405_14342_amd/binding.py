@@ -31,7 +31,8 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_prof_read", "rogs_prof_name", "rogs_fused_workspace_size", "rogs_step_fused",
             "rogs_fused_status", "rogs_autotune", "rogs_server_create", "rogs_serve_submit",
             "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy", "rogs_debug_work",
-            "rogs_elev_scratch_bytes", "rogs_elev_loss", "rogs_lidar_targets",
+            "rogs_elev_scratch_bytes", "rogs_elev_loss", "rogs_elev_loss_static",
+            "rogs_lidar_targets",
             "rogs_meshgrid_scratch_bytes", "rogs_meshgrid_layout", "rogs_bev_camera",
             "rogs_bev_workspace_size", "rogs_bev_export")
 PROF_GROUPS = 12
@@ -175,6 +176,7 @@ def load_library(path: str = LIB_PATH):
                                  ctypes.c_size_t, I64, ctypes.POINTER(I64), P], I32),
             "rogs_elev_scratch_bytes": ([I32], ctypes.c_size_t),
             "rogs_elev_loss": ([P, I32, P, P, F, P, F, P, P, P, ctypes.c_size_t, P], I32),
+            "rogs_elev_loss_static": ([P, I32, P, P, F, P, F, P, P, P], I32),
             "rogs_lidar_targets": ([P, I32, P, P, I32, P, P, P, P, P, P], I32),
             "rogs_meshgrid_scratch_bytes": ([I32, I32, I32], ctypes.c_size_t),
             "rogs_meshgrid_layout": ([P, P, I32, ctypes.c_double, ctypes.c_double, F, I32, I32, I32,
@@ -407,6 +409,18 @@ class Rogs:
                                           ptr(zbar), float(lambda_z), ptr(dz), ptr(loss_out),
                                           ptr(scratch), scratch.numel() * scratch.element_size(),
                                           _stream(stream)), "rogs_elev_loss")
+
+    def elev_loss_static(self, n, z, nbr, lambda_smooth, zbar, lambda_z, dz, loss_out,
+                         stream=None, check=True):
+        """rogs_elev_loss_static: rogs_elev_loss with the library's fixed
+        partial-sum array (allocates nothing).  Returns the status when check
+        is False."""
+        r = self.L.rogs_elev_loss_static(self.h, int(n), ptr(z), ptr(nbr), float(lambda_smooth),
+                                         ptr(zbar), float(lambda_z), ptr(dz), ptr(loss_out),
+                                         _stream(stream))
+        if check:
+            self._check(r, "rogs_elev_loss_static")
+        return r
 
     def lidar_targets(self, x, y, px, py, pz, zbar, idx=None, stream=None):
         """rogs_lidar_targets: zbar (and idx) of the nearest point in xy."""

@@ -12,15 +12,24 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "rogs_internal.h"
 
 namespace rogs {
 
+
 namespace {
 
 constexpr int kRegBlock = 256;
+
+// Block partial sums of rogs_elev_loss_static: one float per block of the
+// largest accepted surfel count (ROGS_ELEV_STATIC_MAX_N).  Each GPU the
+// library runs on holds its own copy until the process ends.  Host code uses
+// only the per-device address from hipGetSymbolAddress, never this name.
+constexpr int64_t kElevStaticFloats = ((int64_t)ROGS_ELEV_STATIC_MAX_N + kRegBlock - 1) / kRegBlock + 1;
+static __device__ __align__(256) float scratch[kElevStaticFloats];
 
 // Per surfel i, with r_d = z_i - z_{nbr[d][i]} and a symmetric table (a
 // neighbour's opposite neighbour is the surfel itself):
@@ -304,6 +313,54 @@ int rogs_elev_loss(rogs_ctx* c, int32_t n, const float* z, const int32_t* nbr, f
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ROGS_OK
                          : rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_elev_loss: ") +
+                                                            hipGetErrorString(e));
+}
+
+int rogs_elev_loss_static(rogs_ctx* c, int32_t n, const float* z, const int32_t* nbr,
+                          float lambda_smooth, const float* zbar, float lambda_z, float* dz,
+                          float* loss_out, void* stream) {
+  if (!c) return ROGS_EINVAL;
+  if (n < 1 || !z || !dz || !loss_out)
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_elev_loss_static: null argument or n < 1");
+  if (n > ROGS_ELEV_STATIC_MAX_N)
+    return rogs::ctx_fail(c, ROGS_EINVAL,
+                          "rogs_elev_loss_static: n exceeds ROGS_ELEV_STATIC_MAX_N (" +
+                              std::to_string(ROGS_ELEV_STATIC_MAX_N) + ")");
+  if ((nbr && !std::isfinite(lambda_smooth)) || (zbar && !std::isfinite(lambda_z)))
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_elev_loss_static: weights must be finite");
+  // the array's device address, looked up once per device with that device current
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess)
+    return rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_elev_loss_static: hipGetDevice: ") +
+                                            hipGetErrorString(e));
+  if (dev < 0 || dev >= 64)
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_elev_loss_static: device ordinal above 63");
+  void* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(rogs::scratch));
+      if (e != hipSuccess || !p)
+        return rogs::ctx_fail(c, ROGS_EHIP,
+                              std::string("rogs_elev_loss_static: hipGetSymbolAddress: ") +
+                                  hipGetErrorString(e));
+      addr[dev] = p;
+    }
+    part = addr[dev];
+  }
+  if (!nbr && !zbar) return ROGS_OK;
+  // every block overwrites its own partial before the total reads it: nothing
+  // in the array needs clearing between calls
+  rogs::launch_elev_reg(n, z, nbr, lambda_smooth, zbar, lambda_z, nullptr, dz,
+                        static_cast<float*>(part), loss_out, true,
+                        static_cast<hipStream_t>(stream));
+  e = hipGetLastError();
+  return e == hipSuccess ? ROGS_OK
+                         : rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_elev_loss_static: ") +
                                                             hipGetErrorString(e));
 }
 
