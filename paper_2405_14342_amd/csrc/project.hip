@@ -57,14 +57,36 @@ __device__ void project_side_block(const ViewDev* __restrict__ views, int V, int
     zero_words[k] = 0u;
 }
 
+// Feature records feat[N][FS] (rgb, sem[C], alpha, zero padding) from the
+// surfel SoA: one thread per float4 of the output, so the stores are
+// contiguous; the four values of a float4 are read from four rows.
+__global__ __launch_bounds__(256) void k_pack_feat(int N, int C, int FS,
+                                                   const float* __restrict__ pa,
+                                                   const float* __restrict__ prgb,
+                                                   const float* __restrict__ psem,
+                                                   float4* __restrict__ feat) {
+  const int Q = FS / 4;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)N * Q) return;
+  const int64_t i = t / Q;
+  const int q = (int)(t - i * Q);
+  float v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = 4 * q + k;      // record column: rgb 0-2, sem 3..3+C-1, alpha 3+C
+    v[k] = r < 3 ? prgb[(size_t)r * N + i]
+                 : r < 3 + C ? psem[(size_t)(r - 3) * N + i] : r == 3 + C ? pa[i] : 0.0f;
+  }
+  feat[t] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
 __global__ __launch_bounds__(kProjBlock) void k_project(
     const ViewDev* __restrict__ views, int V, int N, int nb, float eps, float qcut, int tw, int th,
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
-    const float* __restrict__ pq, const float* __restrict__ ps, const float* __restrict__ pa,
-    const float* __restrict__ prgb, const float* __restrict__ psem, int C, int FS, int pack,
+    const float* __restrict__ pq, const float* __restrict__ ps,
     uint32_t* __restrict__ cnt, float4* __restrict__ rec, uint2* __restrict__ rect,
     uint16_t* __restrict__ rspan, uint32_t* __restrict__ part, uint32_t* __restrict__ partv,
-    float* __restrict__ feat, const uint8_t* __restrict__ mask, int nmb,
+    const uint8_t* __restrict__ mask, int nmb,
     uint32_t* __restrict__ mpart, uint32_t* __restrict__ zero_words, int64_t n_zero) {
   __shared__ uint32_t s_w[kProjBlock / 64];
   if (blockIdx.x >= (unsigned)nb) {
@@ -82,21 +104,23 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
   const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
   const bool valid = i < N;
   (void)V;
-  if (valid && pack && v == 0) {
-    float* f = feat + (size_t)i * FS;
-    f[0] = prgb[i];
-    f[1] = prgb[N + i];
-    f[2] = prgb[2 * (size_t)N + i];
-    for (int c = 0; c < C; ++c) f[3 + c] = psem[(size_t)c * N + i];
-    f[3 + C] = pa[i];
-    for (int c = 4 + C; c < FS; ++c) f[c] = 0.0f;
-  }
   const ViewDev& vw = views[v];
+  const size_t slot = (size_t)v * N + i;
+  // a block none of whose surfels lies in the view's ground rectangle (most
+  // blocks of a long road) is culled whole: the same test the contract takes
+  // first, without the projection, scans and barriers of the full path
+  if (!__syncthreads_or(valid && ground_inside(vw, px[i], py[i]))) {
+    if (valid) cnt[slot] = 0u;
+    if (threadIdx.x == 0) {
+      part[(size_t)v * nb + blockIdx.x] = 0u;
+      partv[(size_t)v * nb + blockIdx.x] = 0u;
+    }
+    return;
+  }
   uint32_t nt = 0, rows = 0;
   Proj p;
   p.vis = false;
   p.y0 = 0;
-  const size_t slot = (size_t)v * N + i;
   if (valid) {
     p = project_contract(vw, eps, qcut, tw, th, px[i], py[i], pz[i], pq[i], pq[N + i],
                          pq[2 * (size_t)N + i], pq[3 * (size_t)N + i], ps[i], ps[N + i]);
@@ -391,14 +415,18 @@ void fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
 void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_feat,
                     hipStream_t st, const uint8_t* mask) {
   fill_u32(at<uint32_t>(ws, L.o_misc), 0u, kMiscCount, st);
+  if (pack_feat) {
+    const int64_t n4 = (int64_t)L.N * (L.FS / 4);
+    hipLaunchKernelGGL(k_pack_feat, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, L.N,
+                       L.C, L.FS, s->alpha, s->rgb, s->sem, at<float4>(ws, L.o_feat));
+  }
   const int nmb = mask ? mask_chunks(L) : 0;
   hipLaunchKernelGGL(k_project, dim3(L.nb + nmb, L.V), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
-                     L.th, s->x, s->y, s->z, s->q, s->s, s->alpha, s->rgb, s->sem, L.C, L.FS,
-                     pack_feat ? 1 : 0, at<uint32_t>(ws, L.o_cnt), at<float4>(ws, L.o_rec),
-                     at<uint2>(ws, L.o_rect), at<uint16_t>(ws, L.o_rspan),
-                     at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_partv),
-                     at<float>(ws, L.o_feat), mask, nmb,
+                     L.th, s->x, s->y, s->z, s->q, s->s, at<uint32_t>(ws, L.o_cnt),
+                     at<float4>(ws, L.o_rec), at<uint2>(ws, L.o_rect),
+                     at<uint16_t>(ws, L.o_rspan), at<uint32_t>(ws, L.o_part),
+                     at<uint32_t>(ws, L.o_partv), mask, nmb,
                      mask ? at<uint32_t>(ws, L.o_mpart) : nullptr,
                      mask ? at<uint32_t>(ws, L.o_tcnt) : nullptr,
                      mask ? L.total_tiles : (int64_t)0);

@@ -364,8 +364,6 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
         // with g = 0: alpha = w = 0, T and the prefix unchanged, terms +-0.
         float pv[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) pv[c] = 0.0f;
-#pragma unroll
         for (int k = 0; k < PPL; ++k) {
           const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
           const float araw = al * g;
@@ -382,18 +380,30 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
           if (kDA) da = __builtin_fmaf(GAf[k], inv, da);
           Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
-          const float gd = clamped ? 0.0f : g;    // the clamp cuts alpha's dependence on g
-          pv[5] = __builtin_fmaf(gd, da, pv[5]);
-          const float dq = ((-0.5f * gd) * al) * da;
+          // the clamp cuts alpha's dependence on g: dL/d(alpha) = g da and
+          // dL/dq = -(alpha g / 2) da where it does not hold, 0 where it does
+          const float gd = clamped ? 0.0f : g;
+          const float dq = (-0.5f * (clamped ? 0.0f : araw)) * da;
           // moments of dq over the pixel offsets; the projection adjoint
-          // turns them into dL/d(u, v, A, B, C) with the pair's conic
+          // turns them into dL/d(u, v, A, B, C) with the pair's conic (the
+          // first pixel of a lane sets the values, later ones add to them)
           const float dyk = dy[k];
           const float dqx = dq * dx, dqy = dq * dyk;
-          pv[0] += dqx;
-          pv[1] += dqy;
-          pv[2] = __builtin_fmaf(dqx, dx, pv[2]);
-          pv[3] = __builtin_fmaf(dqx, dyk, pv[3]);
-          pv[4] = __builtin_fmaf(dqy, dyk, pv[4]);
+          if (k == 0) {
+            pv[5] = gd * da;
+            pv[0] = dqx;
+            pv[1] = dqy;
+            pv[2] = dqx * dx;
+            pv[3] = dqx * dyk;
+            pv[4] = dqy * dyk;
+          } else {
+            pv[5] = __builtin_fmaf(gd, da, pv[5]);
+            pv[0] += dqx;
+            pv[1] += dqy;
+            pv[2] = __builtin_fmaf(dqx, dx, pv[2]);
+            pv[3] = __builtin_fmaf(dqx, dyk, pv[3]);
+            pv[4] = __builtin_fmaf(dqy, dyk, pv[4]);
+          }
           T[k] *= om;
         }
         const float tot = wave_reduce_scatter<NR>(pv, lane);

@@ -121,6 +121,19 @@ __device__ __forceinline__ int clamp_tile(double f, int hi) {
   return (int)f;
 }
 
+// The ground-rectangle part of the cull (supp. Sec. 2.1) in the contract's
+// binary64 arithmetic: |d.ex| <= lat and 0 <= d.ez <= fwd, d = (x, y) - o.
+// True when the rectangle is disabled (lat <= 0).
+__device__ inline bool ground_inside(const ViewDev& c, float xf, float yf) {
+#pragma clang fp contract(off)
+  if (!(c.lat > 0.0f)) return true;
+  const double dx = (double)xf - (double)c.o[0];
+  const double dy = (double)yf - (double)c.o[1];
+  const double a = dx * (double)c.ex[0] + dy * (double)c.ex[1];
+  const double b = dx * (double)c.ez[0] + dy * (double)c.ez[1];
+  return fabs(a) <= (double)c.lat && b >= 0.0 && b <= (double)c.fwd;
+}
+
 // Key contract (see rogs.h): the projection in binary64 from the binary32
 // inputs, without FMA contraction, one rounded operation per step in the
 // documented order, rounded once into the binary32 record.
@@ -141,14 +154,7 @@ __device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcu
   const double tz = ((R6 * x + R7 * y) + R8 * z) + (double)c.t[2];
   r.tz = (float)tz;
   if (!(tz >= (double)c.znear)) return r;
-  if (c.lat > 0.0f) {
-    const double dx = x - (double)c.o[0];
-    const double dy = y - (double)c.o[1];
-    const double a = dx * (double)c.ex[0] + dy * (double)c.ex[1];
-    const double b = dx * (double)c.ez[0] + dy * (double)c.ez[1];
-    if (!(fabs(a) <= (double)c.lat)) return r;
-    if (!(b >= 0.0 && b <= (double)c.fwd)) return r;
-  }
+  if (!ground_inside(c, xf, yf)) return r;
   const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
   if (!(nn > 0.0) || !isfinite(nn)) return r;
   const double nq = sqrt(nn);

@@ -50,8 +50,17 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
   const bool valid = i < N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const size_t nparts = (size_t)V * nb;
   for (int v = 0; v < V; ++v) {
     const size_t slot = (size_t)v * N + i;
+    // the scanned visible counts give this block's count in view v: none
+    // visible (a block the view's ground rectangle misses) needs no scan
+    const size_t pb = (size_t)v * nb + blockIdx.x;
+    const uint32_t vnext = pb + 1 < nparts ? partv[pb + 1] : misc[kMiscVisible];
+    if (vnext == partv[pb]) {
+      if (valid) spos[slot] = 0xffffffffu;
+      continue;
+    }
     const uint32_t c = valid ? cnt[slot] : 0u;
     const bool vis = c != 0;
     const unsigned long long b = __ballot(vis);
