@@ -245,12 +245,27 @@ ROGS_API int rogs_bin_sort(rogs_ctx* ctx, void* ws, int64_t* n_pairs_out, uint32
 /* Reads the device pair count and overflow flag of the current batch (host sync). */
 ROGS_API int rogs_pair_count(rogs_ctx* ctx, void* ws, int64_t* n_pairs, int32_t* overflow, void* stream);
 
+/* Channel sets.  Planes of a rendered view: RGB (3), SEM (the C semantic
+ * logits, composited like colour, Sec. 3.3.1), D (sum w t_z), A (1 - T);
+ * ELEV (serving and BEV export) is formed from D and A. */
+#define ROGS_CH_RGB  1u
+#define ROGS_CH_SEM  2u
+#define ROGS_CH_D    4u
+#define ROGS_CH_A    8u
+#define ROGS_CH_ELEV 16u
+#define ROGS_CH_ALL  31u
+
 /* a6, Eq. 6.  Front-to-back compositing of R, G, B, sem[C], D = sum w t_z and
- * A = 1 - T into out_images (5 + C channels, image layout above).  Keeps
- * T_final and the number of list entries each pixel visited in the workspace
- * for the backward. */
+ * A = 1 - T into out_images (5 + C channels, image layout above).  Only the
+ * planes selected by channel_mask (a non-empty OR of ROGS_CH_*; ELEV selects D
+ * and A) are composited and written; the others are left untouched, and the
+ * per-pixel sums they would need are not formed (an RGB-only render skips the
+ * C semantic accumulations).  The selected planes are bitwise the same as in
+ * an all-plane render.  Only a render of every plane (ROGS_CH_ALL) keeps
+ * T_final, the number of list entries each pixel visited and the relative
+ * depth sum in the workspace for rogs_render_bwd. */
 ROGS_API int rogs_render_fwd(rogs_ctx* ctx, const rogs_surfels* s, void* ws, float* out_images,
-                    void* stream);
+                    uint32_t channel_mask, void* stream);
 
 /* a7, Eq. 7, 8, 9, 12.  For every pixel of the batch: c' = e^a c + b,
  * masked L1 over the three colour channels and masked cross-entropy of the
@@ -262,7 +277,8 @@ ROGS_API int rogs_loss(rogs_ctx* ctx, void* ws, const float* out_images, const r
               float* dL_dout, float* loss_out, float* d_exposure, void* stream);
 
 /* a8-a9, adjoint of Eq. 5-6.  Given the forward images and dL/d(out) of
- * the current batch, writes dL/d(surfel parameters) into the packed block
+ * the current batch (after a rogs_render_fwd of every plane, else
+ * ROGS_ESTATE), writes dL/d(surfel parameters) into the packed block
  * grads[11 + C][N] (rows: z, q, s, alpha, rgb, sem; w.r.t. the activated
  * s and alpha), summed over the batch's views.  ROGS_ACCUMULATE adds. */
 ROGS_API int rogs_render_bwd(rogs_ctx* ctx, const rogs_surfels* s, void* ws, const float* out_images,
@@ -468,13 +484,6 @@ ROGS_API int rogs_autotune(rogs_ctx* ctx, const rogs_surfels* s, const rogs_came
  * set: RGB (3 planes), SEM (C), D, A, ELEV.  ELEV = elev_ref - D / A (for an
  * orthographic camera looking straight down from height elev_ref this is the
  * surface height: D / A is the opacity-weighted depth); NaN where A = 0. */
-#define ROGS_CH_RGB  1u
-#define ROGS_CH_SEM  2u
-#define ROGS_CH_D    4u
-#define ROGS_CH_A    8u
-#define ROGS_CH_ELEV 16u
-#define ROGS_CH_ALL  31u
-
 typedef struct rogs_server rogs_server;
 
 typedef struct {

@@ -75,6 +75,7 @@ class Result(ctypes.Structure):
 
 
 CH_RGB, CH_SEM, CH_D, CH_A, CH_ELEV = 1, 2, 4, 8, 16
+CH_ALL = CH_RGB | CH_SEM | CH_D | CH_A | CH_ELEV
 
 
 def channel_planes(channels: int, C: int) -> int:
@@ -141,7 +142,7 @@ def load_library(path: str = LIB_PATH):
                               ctypes.POINTER(RenderOpts), P, ctypes.c_size_t, I64, I64, P], I32),
             "rogs_bin_sort": ([P, P, ctypes.POINTER(I64), U32, P], I32),
             "rogs_pair_count": ([P, P, ctypes.POINTER(I64), ctypes.POINTER(I32), P], I32),
-            "rogs_render_fwd": ([P, ctypes.POINTER(Surfels), P, P, P], I32),
+            "rogs_render_fwd": ([P, ctypes.POINTER(Surfels), P, P, ctypes.c_uint32, P], I32),
             "rogs_loss": ([P, P, P, ctypes.POINTER(Targets), P, P, P, P], I32),
             "rogs_render_bwd": ([P, ctypes.POINTER(Surfels), P, P, P, P, U32, P], I32),
             "rogs_adam_step": ([P, I32, I32, P, P, P, P, P, P, ctypes.POINTER(Optim), I64,
@@ -338,8 +339,10 @@ class Rogs:
                                            _stream(stream)), "rogs_pair_count")
         return int(n.value), int(o.value)
 
-    def render_fwd(self, surf: Surfels, ws, out, stream=None):
-        self._check(self.L.rogs_render_fwd(self.h, ctypes.byref(surf), ptr(ws), ptr(out),
+    def render_fwd(self, surf: Surfels, ws, out, stream=None, channels: int = None):
+        """rogs_render_fwd; channels: OR of CH_* (default: every plane)."""
+        ch = CH_ALL if channels is None else int(channels)
+        self._check(self.L.rogs_render_fwd(self.h, ctypes.byref(surf), ptr(ws), ptr(out), ch,
                                            _stream(stream)), "rogs_render_fwd")
 
     def loss(self, ws, out, targets: Targets, dL_dout, loss_out, d_exposure, stream=None):

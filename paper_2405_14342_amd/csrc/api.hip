@@ -17,6 +17,12 @@ struct rogs_ctx {
   std::string err;
   bool have_batch = false;
   bool sorted = false;
+  // per-view channel sets for the next rogs_project (render server); the
+  // batch's views had sets of their own; the last forward wrote every plane
+  // and the backward's per-pixel state
+  std::vector<uint32_t> view_ch;
+  bool batch_view_ch = false;
+  bool fwd_full = false;
   Layout L;
   void* ws = nullptr;
   int64_t n_pairs_host = -1;
@@ -212,13 +218,23 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   return ROGS_OK;
 }
 
+int ctx_set_view_channels(rogs_ctx* c, const uint32_t* ch, int n) {
+  if (!c || n < 0 || (n > 0 && !ch)) return ROGS_EINVAL;
+  c->view_ch.assign(ch, ch + n);
+  // elevation is formed from depth and alpha
+  for (uint32_t& k : c->view_ch)
+    if (k & ROGS_CH_ELEV) k |= ROGS_CH_D | ROGS_CH_A;
+  return ROGS_OK;
+}
+
 }  // namespace rogs
 
 namespace {
 
 // Writes the device view table and the per-view first loss-block table of a
 // batch into host memory at dst (sizeof(ViewDev) * V + 8 * (V + 1) bytes).
-void fill_view_table(const Layout& L, const rogs_camera* cams, void* dst) {
+void fill_view_table(const Layout& L, const rogs_camera* cams, void* dst,
+                     const uint32_t* ch = nullptr) {
   const size_t vbytes = sizeof(ViewDev) * L.V;
   ViewDev* vt = static_cast<ViewDev*>(dst);
   int64_t* fb = reinterpret_cast<int64_t*>(static_cast<char*>(dst) + vbytes);
@@ -240,6 +256,7 @@ void fill_view_table(const Layout& L, const rogs_camera* cams, void* dst) {
     d.tiles_x = (k.w + L.tw - 1) / L.tw;
     d.tiles_y = (k.h + L.th - 1) / L.th;
     d.tile_off = (int32_t)tiles;
+    d.ch = ch ? ch[v] : (uint32_t)ROGS_CH_ALL;
     vt[v] = d;
     fb[v] = blk;
     pix += (int64_t)k.w * k.h;
@@ -266,7 +283,10 @@ int upload_views(rogs_ctx* c, const Layout& L, const rogs_camera* cams, void* ws
     if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
     c->stage_bytes = need;
   }
-  fill_view_table(L, cams, c->stage);
+  const bool own = c->view_ch.size() == (size_t)L.V;
+  fill_view_table(L, cams, c->stage, own ? c->view_ch.data() : nullptr);
+  c->batch_view_ch = own;
+  c->view_ch.clear();
   hipError_t e = hipMemcpyAsync(rogs::at<void>(ws, L.o_views), c->stage, vbytes + fbytes,
                                 hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventRecord(c->stage_evt, st);
@@ -435,6 +455,7 @@ int rogs_project(rogs_ctx* c, const rogs_surfels* s, const rogs_camera* cams, in
   hipStream_t st = static_cast<hipStream_t>(stream);
   c->have_batch = false;
   c->sorted = false;
+  c->fwd_full = false;
   r = upload_views(c, L, cams, ws, st);
   if (r != ROGS_OK) return r;
   prof_begin(c, 0, st);
@@ -541,15 +562,23 @@ int rogs_bin_sort(rogs_ctx* c, void* ws, int64_t* n_pairs_out, uint32_t flags, v
   return ROGS_OK;
 }
 
-int rogs_render_fwd(rogs_ctx* c, const rogs_surfels* s, void* ws, float* out_images, void* stream) {
+int rogs_render_fwd(rogs_ctx* c, const rogs_surfels* s, void* ws, float* out_images,
+                    uint32_t channel_mask, void* stream) {
   int r = need_batch(c, ws, true);
   if (r != ROGS_OK) return r;
   r = check_surfels(c, s, c->L);
   if (r != ROGS_OK) return r;
   if (!out_images) return fail(c, ROGS_EINVAL, "out_images is null");
+  if (channel_mask == 0u || (channel_mask & ~(uint32_t)ROGS_CH_ALL) != 0u)
+    return fail(c, ROGS_EINVAL, "channel_mask must be a non-empty OR of ROGS_CH_* bits");
+  // elevation is formed from depth and alpha
+  uint32_t mask = channel_mask;
+  if (mask & ROGS_CH_ELEV) mask |= ROGS_CH_D | ROGS_CH_A;
+  constexpr uint32_t kPlanes = ROGS_CH_RGB | ROGS_CH_SEM | ROGS_CH_D | ROGS_CH_A;
   hipStream_t st = static_cast<hipStream_t>(stream);
   prof_begin(c, 5, st);
-  int rr = rogs::launch_render_fwd(c->L, ws, s, out_images, st);
+  int rr = rogs::launch_render_fwd(c->L, ws, s, out_images, mask, st);
+  c->fwd_full = (mask & kPlanes) == kPlanes && !c->batch_view_ch;
   prof_end(c, st);
   if (rr != 0) return fail(c, ROGS_EINVAL, "unsupported n_sem / tile shape");
   return check_launch(c, "rogs_render_fwd");
@@ -598,6 +627,9 @@ int rogs_render_bwd(rogs_ctx* c, const rogs_surfels* s, void* ws, const float* o
   r = check_surfels(c, s, c->L);
   if (r != ROGS_OK) return r;
   if (!out_images || !dL_dout || !grads) return fail(c, ROGS_EINVAL, "null argument");
+  if (!c->fwd_full)
+    return fail(c, ROGS_ESTATE,
+                "rogs_render_bwd needs a rogs_render_fwd of every plane (RGB, SEM, D, A) first");
   hipStream_t st = static_cast<hipStream_t>(stream);
   prof_begin(c, 7, st);
   int rr = rogs::launch_render_bwd(c->L, ws, s, out_images, dL_dout, st);

@@ -203,7 +203,7 @@ extern "C" int rogs_autotune(rogs_ctx* c, const rogs_surfels* s, const rogs_came
       status = rogs_project(c, s, cams, n_views, &o, ws.p, bytes, cap, scap, stream);
       if (status == ROGS_OK) status = rogs_bin_sort(c, ws.p, nullptr, 0u, stream);
       if (status == ROGS_OK)
-        status = rogs_render_fwd(c, s, ws.p, static_cast<float*>(out.p), stream);
+        status = rogs_render_fwd(c, s, ws.p, static_cast<float*>(out.p), ROGS_CH_ALL, stream);
       if (status == ROGS_OK)
         status = rogs_render_bwd(c, s, ws.p, static_cast<const float*>(out.p),
                                  static_cast<const float*>(g.p), static_cast<float*>(grads.p), 0u,

@@ -104,7 +104,8 @@ int rogs_bev_export(rogs_ctx* c, const rogs_surfels* s, const rogs_render_opts* 
       worst = std::max(worst, n);
       if (n_pairs_max) *n_pairs_max = worst;
       if (r != ROGS_OK) return r;
-      r = rogs_render_fwd(c, s, ws, img, stream);
+      // only the planes the export asks for are composited
+      r = rogs_render_fwd(c, s, ws, img, channels, stream);
       if (r != ROGS_OK) return r;
       const int64_t np = (int64_t)cw * ch;
       hipLaunchKernelGGL(k_stitch, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, img, cw,

@@ -115,7 +115,9 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 // one that stopped the pixel.  With kD, t0 = the depth of the pixel's first
 // contributing entry: the list is in ascending depth, so the running minimum
 // of the contributing depths (FLT_MAX while none).  With kE, e_first = this
-// lane's emission index in the first staged batch.
+// lane's emission index in the first staged batch.  ch (ROGS_CH_* bits,
+// uniform): the colour, semantic and depth sums are formed only when
+// selected; T, n_last and the order of operations do not depend on it.
 template <int C, int PPL, bool kE, bool kD>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
@@ -124,7 +126,7 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
                                              const float4* __restrict__ feat, float4* s_r0,
                                              float4* s_r1, float4* s_f, const float* pyc,
                                              float (*acc)[3 + C + 1], float* T, uint32_t* nl,
-                                             uint32_t& e_first, float* t0) {
+                                             uint32_t& e_first, float* t0, uint32_t ch) {
   // every multiply-add is written out: the forward rounds the same in every
   // kernel it is inlined into
 #pragma clang fp contract(off)
@@ -167,9 +169,13 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
           const float g = gauss_weight(q);
           const float a = clamp_alpha(al * g, amax);
           const float w = a * T[k];
+          if (ch & ROGS_CH_RGB)
 #pragma unroll
-          for (int f = 0; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-          if (kD) {
+            for (int f = 0; f < 3; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+          if (ch & ROGS_CH_SEM)
+#pragma unroll
+            for (int f = 3; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+          if (kD && (ch & ROGS_CH_D)) {
             t0[k] = fminf(t0[k], r1.w);
             acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
           }
@@ -424,16 +430,18 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
   }
 }
 
-// Forward compositing of the batch: the 5 + C output planes per view, and per
-// pixel T_final, n_last, the relative depth D' and its reference t0 for the
-// backward.
+// Forward compositing of the batch: of the 5 + C output planes per view the
+// ones selected by mask and the view's own channel set, and, when all are
+// selected, per pixel T_final, n_last, the relative depth D' and its
+// reference t0 for the backward.
 template <int C, int PPL>
 __global__ __launch_bounds__(64) void k_render_fwd(
     const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
     float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, float* __restrict__ out,
-    float* __restrict__ tfin, uint32_t* __restrict__ nlast, float2* __restrict__ drel) {
+    float* __restrict__ tfin, uint32_t* __restrict__ nlast, float2* __restrict__ drel,
+    uint32_t mask) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;           // output channels
@@ -446,8 +454,10 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   for (int k = 0; k < PPL; ++k) pyc[k] = (float)(tg.py0 + k * tg.rows) + 0.5f;
   uint32_t e_first;
   float t0[PPL];
+  const uint32_t ch = (uint32_t)tg.vw->ch & mask;
+  constexpr uint32_t kPlanes = ROGS_CH_RGB | ROGS_CH_SEM | ROGS_CH_D | ROGS_CH_A;
   forward_tile<C, PPL, false, true>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1, s_f,
-                                    pyc, acc, T, nl, e_first, t0);
+                                    pyc, acc, T, nl, e_first, t0, ch);
   const uint32_t len = tg.rend - tg.rbeg;
   const size_t HW = (size_t)tg.W * tg.H;
   float* o = out + (size_t)NO * tg.vw->pix_off;
@@ -456,15 +466,21 @@ __global__ __launch_bounds__(64) void k_render_fwd(
     const int py = tg.py0 + k * tg.rows;
     if (!(tg.px < tg.W && py < tg.H)) continue;
     const size_t p = (size_t)py * tg.W + tg.px;
+    if (ch & ROGS_CH_RGB)
 #pragma unroll
-    for (int f = 0; f < F; ++f) o[f * HW + p] = acc[k][f];
+      for (int f = 0; f < 3; ++f) o[f * HW + p] = acc[k][f];
+    if (ch & ROGS_CH_SEM)
+#pragma unroll
+      for (int f = 3; f < F; ++f) o[f * HW + p] = acc[k][f];
     const float al = 1.0f - T[k];
     const float t0k = t0[k] < FLT_MAX ? t0[k] : 0.0f;        // 0 where nothing contributed
-    o[F * HW + p] = __builtin_fmaf(t0k, al, acc[k][F]);      // D = D' + t0 A
-    o[(F + 1) * HW + p] = al;
-    tfin[tg.vw->pix_off + p] = T[k];
-    nlast[tg.vw->pix_off + p] = (T[k] < teps) ? nl[k] : len;
-    drel[tg.vw->pix_off + p] = make_float2(acc[k][F], t0k);
+    if (ch & ROGS_CH_D) o[F * HW + p] = __builtin_fmaf(t0k, al, acc[k][F]);   // D = D' + t0 A
+    if (ch & ROGS_CH_A) o[(F + 1) * HW + p] = al;
+    if ((ch & kPlanes) == kPlanes) {
+      tfin[tg.vw->pix_off + p] = T[k];
+      nlast[tg.vw->pix_off + p] = (T[k] < teps) ? nl[k] : len;
+      drel[tg.vw->pix_off + p] = make_float2(acc[k][F], t0k);
+    }
   }
 }
 
@@ -578,7 +594,8 @@ __global__ __launch_bounds__(64) void k_render_step(
 #pragma unroll
     for (int k = 0; k < PPL; ++k) t0[k] = 0.0f;
     forward_tile<C, PPL, true, false>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1,
-                                      s_f, pyc, acc, T, nlf, e_first, t0);
+                                      s_f, pyc, acc, T, nlf, e_first, t0,
+                                      ROGS_CH_RGB | ROGS_CH_SEM);
     // loss epilogue: dL/dO and G.O per pixel, this tile's loss partials
     const uint32_t len = tg.rend - tg.rbeg;
     float l = 0.0f, dal = 0.0f, dbl = 0.0f;
@@ -673,14 +690,14 @@ __global__ __launch_bounds__(64) void k_count_work(
 }
 
 template <int C, int PPL>
-void fwd_launch(const Layout& L, void* ws, float* out, hipStream_t st) {
+void fwd_launch(const Layout& L, void* ws, float* out, uint32_t mask, hipStream_t st) {
   hipLaunchKernelGGL((k_render_fwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
                      L.t_eps, at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out,
                      at<float>(ws, L.o_tfin), at<uint32_t>(ws, L.o_nlast),
-                     at<float2>(ws, L.o_drel));
+                     at<float2>(ws, L.o_drel), mask);
 }
 
 template <int C, int PPL>
@@ -707,50 +724,51 @@ void step_launch(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st)
 // which: 0 forward, 1 backward, 2 fused step
 template <int C, int PPL>
 void launch_one(const Layout& L, void* ws, const float* out, const float* G, float* outw,
-                const FusedLoss* fl, int which, hipStream_t st) {
-  if (which == 0) fwd_launch<C, PPL>(L, ws, outw, st);
+                const FusedLoss* fl, int which, uint32_t mask, hipStream_t st) {
+  if (which == 0) fwd_launch<C, PPL>(L, ws, outw, mask, st);
   else if (which == 1) bwd_launch<C, PPL>(L, ws, out, G, st);
   else step_launch<C, PPL>(L, ws, *fl, st);
 }
 
 template <int C>
 int dispatch_ppl(const Layout& L, void* ws, const float* out, const float* G, float* outw,
-                 const FusedLoss* fl, int which, hipStream_t st) {
+                 const FusedLoss* fl, int which, uint32_t mask, hipStream_t st) {
   switch (L.ppl) {
-    case 1: launch_one<C, 1>(L, ws, out, G, outw, fl, which, st); return 0;
-    case 2: launch_one<C, 2>(L, ws, out, G, outw, fl, which, st); return 0;
-    case 4: launch_one<C, 4>(L, ws, out, G, outw, fl, which, st); return 0;
+    case 1: launch_one<C, 1>(L, ws, out, G, outw, fl, which, mask, st); return 0;
+    case 2: launch_one<C, 2>(L, ws, out, G, outw, fl, which, mask, st); return 0;
+    case 4: launch_one<C, 4>(L, ws, out, G, outw, fl, which, mask, st); return 0;
     default: return -1;
   }
 }
 
 int dispatch(const Layout& L, void* ws, const float* out, const float* G, float* outw,
-             const FusedLoss* fl, int which, hipStream_t st) {
+             const FusedLoss* fl, int which, uint32_t mask, hipStream_t st) {
   switch (L.C) {
-    case 1: return dispatch_ppl<1>(L, ws, out, G, outw, fl, which, st);
-    case 2: return dispatch_ppl<2>(L, ws, out, G, outw, fl, which, st);
-    case 3: return dispatch_ppl<3>(L, ws, out, G, outw, fl, which, st);
-    case 4: return dispatch_ppl<4>(L, ws, out, G, outw, fl, which, st);
-    case 5: return dispatch_ppl<5>(L, ws, out, G, outw, fl, which, st);
-    case 6: return dispatch_ppl<6>(L, ws, out, G, outw, fl, which, st);
-    case 7: return dispatch_ppl<7>(L, ws, out, G, outw, fl, which, st);
-    case 8: return dispatch_ppl<8>(L, ws, out, G, outw, fl, which, st);
-    case 16: return dispatch_ppl<16>(L, ws, out, G, outw, fl, which, st);
+    case 1: return dispatch_ppl<1>(L, ws, out, G, outw, fl, which, mask, st);
+    case 2: return dispatch_ppl<2>(L, ws, out, G, outw, fl, which, mask, st);
+    case 3: return dispatch_ppl<3>(L, ws, out, G, outw, fl, which, mask, st);
+    case 4: return dispatch_ppl<4>(L, ws, out, G, outw, fl, which, mask, st);
+    case 5: return dispatch_ppl<5>(L, ws, out, G, outw, fl, which, mask, st);
+    case 6: return dispatch_ppl<6>(L, ws, out, G, outw, fl, which, mask, st);
+    case 7: return dispatch_ppl<7>(L, ws, out, G, outw, fl, which, mask, st);
+    case 8: return dispatch_ppl<8>(L, ws, out, G, outw, fl, which, mask, st);
+    case 16: return dispatch_ppl<16>(L, ws, out, G, outw, fl, which, mask, st);
     default: return -1;
   }
 }
 
 }  // namespace
 
-int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels*, float* out, hipStream_t st) {
+int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels*, float* out, uint32_t mask,
+                      hipStream_t st) {
   if (L.total_tiles <= 0) return 0;
-  return dispatch(L, ws, nullptr, nullptr, out, nullptr, 0, st);
+  return dispatch(L, ws, nullptr, nullptr, out, nullptr, 0, mask, st);
 }
 
 int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels*, const float* out,
                       const float* G, hipStream_t st) {
   if (L.total_tiles <= 0) return 0;
-  return dispatch(L, ws, out, G, nullptr, nullptr, 1, st);
+  return dispatch(L, ws, out, G, nullptr, nullptr, 1, 0u, st);
 }
 
 void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st) {
@@ -764,7 +782,7 @@ void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hi
 
 int launch_render_step(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st) {
   if (L.total_tiles <= 0) return 0;
-  return dispatch(L, ws, nullptr, nullptr, nullptr, &fl, 2, st);
+  return dispatch(L, ws, nullptr, nullptr, nullptr, &fl, 2, 0u, st);
 }
 
 }  // namespace rogs

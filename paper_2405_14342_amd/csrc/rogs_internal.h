@@ -28,7 +28,8 @@ struct ViewDev {
   int32_t w, h, model;
   int32_t tiles_x, tiles_y;
   int32_t tile_off;     // first global tile index of the view
-  int32_t pad[2];
+  uint32_t ch;          // ROGS_CH_* planes to composite (rogs_render_fwd ANDs its mask)
+  int32_t pad;
 };
 
 // Number of semantic classes with a compiled kernel set.
@@ -600,7 +601,12 @@ void launch_layout_mask(const rogs_pose* poses, int np, double x0, double y0, fl
 void launch_layout_fill(const rogs_pose* poses, int np, double x0, double y0, float h, int W,
                         int H, void* scratch, int64_t n, int32_t* idx, float* x, float* y,
                         float* z, float* q, int32_t* nbr, hipStream_t st);
-int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* out, hipStream_t st);
+int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* out, uint32_t mask,
+                      hipStream_t st);
+// Channel sets (ROGS_CH_*) of the views of the next rogs_project call on this
+// context (n entries, one per view; n = 0 clears: every view gets all
+// planes).  Used by the render server for per-request channel sets.
+int ctx_set_view_channels(rogs_ctx* c, const uint32_t* ch, int n);
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,
                  float* loss_out, float* d_exp, hipStream_t st);
 int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels* s, const float* out,

@@ -8,8 +8,9 @@
 // arrive while other batches are on the GPU start on a free lane and their
 // work overlaps on the device.  A lane renders its requests as one batch
 // (rogs_project + rogs_bin_sort with the pair count on the device +
-// rogs_render_fwd into its arena share), copies each request's channels into
-// its buffer, and waits for the batch.  If the batch overflowed the pair
+// rogs_render_fwd into its arena share, each view compositing only the planes
+// its request asked for), copies each request's channels into its buffer, and
+// waits for the batch.  If the batch overflowed the pair
 // capacity that the arena allows, it is split in two and both halves run
 // again; a single view that does not fit fails with ROGS_ECAPACITY.  Each
 // view is rendered independently of the others in its batch (per-view tile
@@ -154,10 +155,15 @@ bool run_batch(rogs_server* s, ServeLane& ln, std::vector<Item>& batch) {
   (void)rogs_workspace_size(&s->map, cams.data(), (int)cams.size(), &s->opts, cap, 0, &wsb);
   void* ws = ln.arena;
   float* images = reinterpret_cast<float*>(ln.arena + wsb);
-  int r = rogs_project(ln.ctx, &s->map, cams.data(), (int)cams.size(), &s->opts, ws, wsb, cap, 0,
-                       ln.st);
+  // each view composites only the planes its request asked for
+  std::vector<uint32_t> chans;
+  for (const Item& it : batch) chans.push_back(it.req.channels);
+  int r = rogs::ctx_set_view_channels(ln.ctx, chans.data(), (int)chans.size());
+  if (r == ROGS_OK)
+    r = rogs_project(ln.ctx, &s->map, cams.data(), (int)cams.size(), &s->opts, ws, wsb, cap, 0,
+                     ln.st);
   if (r == ROGS_OK) r = rogs_bin_sort(ln.ctx, ws, nullptr, 0u, ln.st);
-  if (r == ROGS_OK) r = rogs_render_fwd(ln.ctx, &s->map, ws, images, ln.st);
+  if (r == ROGS_OK) r = rogs_render_fwd(ln.ctx, &s->map, ws, images, ROGS_CH_ALL, ln.st);
   int64_t off = 0;
   const int C = s->map.n_sem;
   for (size_t k = 0; k < batch.size() && r == ROGS_OK; ++k) {

@@ -534,3 +534,43 @@ def test_work_counts_match_oracle_lists(gpu, name):
                 q = oracle.q32(rec[lst], [px], [py])[:, 0] if len(lst) else np.zeros(0)
                 k_ref += int((q <= np.float32(o.q_cut)).sum())
     assert (ev, co) == (e_ref, k_ref)
+
+
+@pytest.mark.parametrize("name", ["mini16", "c1"])
+def test_channel_masks_render_only_selected_planes(gpu, name):
+    """rogs_render_fwd with a channel set: the selected planes are bitwise
+    those of an all-plane render, the others are left as they were; ELEV
+    selects depth and alpha; the backward needs an all-plane forward."""
+    sc = make_scene(name)
+    st = TrainState(sc)
+    ws, _ = st.project_and_sort(st.cams, "cap_batch", "_ws_batch")
+    surf = st.surfels()
+    st.rg.render_fwd(surf, ws, st.out)
+    full = st.out.clone()
+    C, NO = sc.n_sem, n_out(sc.n_sem)
+    planes = {B.CH_RGB: [0, 1, 2], B.CH_SEM: list(range(3, 3 + C)), B.CH_D: [3 + C],
+              B.CH_A: [4 + C], B.CH_ELEV: [3 + C, 4 + C]}
+    sentinel = -12345.0
+    for mask in (B.CH_RGB, B.CH_SEM, B.CH_RGB | B.CH_SEM, B.CH_D | B.CH_A, B.CH_ELEV,
+                 B.CH_ELEV | B.CH_SEM, B.CH_A):
+        st.out.fill_(sentinel)
+        st.rg.render_fwd(surf, ws, st.out, channels=mask)
+        torch.cuda.synchronize()
+        sel = sorted({p for bit, ps in planes.items() if mask & bit for p in ps})
+        for v in range(st.V):
+            got, ref = st.image(v), full[NO * st.pix_off[v]: NO * st.pix_off[v + 1]].view(
+                NO, sc.cams[v].h, sc.cams[v].w)
+            for p in range(NO):
+                if p in sel:
+                    assert torch.equal(got[p], ref[p]), (mask, v, p)
+                else:
+                    assert bool((got[p] == sentinel).all()), (mask, v, p)
+        with pytest.raises(B.RogsError) as e:
+            st.rg.render_bwd(surf, ws, st.out, st.G, st.grads, 0)
+        assert e.value.code == B.ESTATE
+    with pytest.raises(B.RogsError) as e:
+        st.rg.render_fwd(surf, ws, st.out, channels=0)
+    assert e.value.code == B.EINVAL
+    # an all-plane forward again allows the backward
+    st.rg.render_fwd(surf, ws, st.out)
+    st.rg.render_bwd(surf, ws, st.out, st.G, st.grads, 0)
