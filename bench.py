@@ -169,6 +169,7 @@ def grid_terms_bench(st, scene, run, steps: int, n_points: int = 1_000_000):
     one-off LiDAR target lookup, and the meshgrid layout + pose-based
     initialisation of the 3M-surfel road (1 km of poses every 0.5 m)."""
     import torch
+    from paper_2405_14342_amd import binding as B
     from paper_2405_14342_amd import synth
 
     pts = synth.lidar_points(scene.trajectory, n_points, 4242)
@@ -197,9 +198,23 @@ def grid_terms_bench(st, scene, run, steps: int, n_points: int = 1_000_000):
     out = st.rg.meshgrid_layout(pd, float(lo[0]), float(lo[1]), h, W, H, 150)
     torch.cuda.synchronize()
     t_lay = (time.perf_counter() - t0) * 1e3
+    # LiDAR targets of the laid-out 1 km road (about 3M surfels) from 1M
+    # returns along the same trajectory
+    pts1k = torch.as_tensor(synth.lidar_points(traj, n_points, 4243), device=st.dev)
+    n3 = int(out["n"])
+    xg, yg = out["x"][:n3], out["y"][:n3]
+    z3 = torch.empty(n3, dtype=torch.float32, device=st.dev)
+    scr = torch.empty(B.lidar_scratch_bytes(n3, n_points), dtype=torch.uint8, device=st.dev)
+    st.rg.lidar_targets(xg, yg, pts1k[0], pts1k[1], pts1k[2], z3, scratch=scr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.rg.lidar_targets(xg, yg, pts1k[0], pts1k[1], pts1k[2], z3, scratch=scr)
+    torch.cuda.synchronize()
+    t_nn3 = (time.perf_counter() - t0) * 1e3
     return {"ms_per_step": round(ms, 4), "value": round(scene.npix / (ms * 1e-3) / 1e6, 2),
             "unit": "Mpixel/s", "lambda_smooth": 1.0, "lambda_z": 0.02,
             "lidar_points": n_points, "lidar_targets_ms": round(t_nn, 3),
+            "lidar_targets_3M": {"surfels": n3, "points": n_points, "ms": round(t_nn3, 3)},
             "layout": {"poses": int(poses.shape[0]), "raster": f"{W}x{H}", "radius_px": 150,
                        "surfels": out["n"], "ms": round(t_lay, 3)}}
 

@@ -385,11 +385,18 @@ ROGS_API int rogs_elev_loss_static(rogs_ctx* ctx, int32_t n, const float* z, con
 
 /* LiDAR targets of Eq. 11: zbar[i] = pz of the point nearest to (x_i, y_i) in
  * the xy-plane (squared distance in binary64 of the binary32 inputs, ties to
- * the lower point index; brute force over the points), idx[i] its index
- * (nullable).  Device arrays; m >= 1. */
+ * the lower point index: the brute-force result), idx[i] its index
+ * (nullable).  The points are bucketed into a uniform grid of about 2m cells
+ * over the bounding box of surfels and points, and each surfel searches
+ * rings of cells outward until no unvisited cell can hold a nearer point:
+ * O(n + m) work for points spread like road returns.  Device arrays; 1 <= m <=
+ * 2^29.  scratch: caller-owned device memory, 256-byte aligned, of
+ * rogs_lidar_scratch_bytes(n, m) bytes (the grid, the points in cell order). */
+ROGS_API size_t rogs_lidar_scratch_bytes(int32_t n, int32_t m);
 ROGS_API int rogs_lidar_targets(rogs_ctx* ctx, int32_t n, const float* x, const float* y,
                                 int32_t m, const float* px, const float* py, const float* pz,
-                                float* zbar, int32_t* idx, void* stream);
+                                float* zbar, int32_t* idx, void* scratch, size_t scratch_bytes,
+                                void* stream);
 
 /* Meshgrid layout and pose-based initialisation (Sec. 3.1, Eq. 4; supp.
  * Sec. 1 and 3.3).  A raster of W x H cells of `spacing` metres with cell

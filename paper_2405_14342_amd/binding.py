@@ -32,7 +32,7 @@ EXPORTED = ("rogs_create", "rogs_destroy", "rogs_last_error", "rogs_default_opts
             "rogs_fused_status", "rogs_autotune", "rogs_server_create", "rogs_serve_submit",
             "rogs_serve_poll", "rogs_server_stats", "rogs_server_destroy", "rogs_debug_work",
             "rogs_elev_scratch_bytes", "rogs_elev_loss", "rogs_elev_loss_static",
-            "rogs_lidar_targets",
+            "rogs_lidar_scratch_bytes", "rogs_lidar_targets",
             "rogs_meshgrid_scratch_bytes", "rogs_meshgrid_layout", "rogs_bev_camera",
             "rogs_bev_workspace_size", "rogs_bev_export")
 PROF_GROUPS = 12
@@ -178,7 +178,8 @@ def load_library(path: str = LIB_PATH):
             "rogs_elev_scratch_bytes": ([I32], ctypes.c_size_t),
             "rogs_elev_loss": ([P, I32, P, P, F, P, F, P, P, P, ctypes.c_size_t, P], I32),
             "rogs_elev_loss_static": ([P, I32, P, P, F, P, F, P, P, P], I32),
-            "rogs_lidar_targets": ([P, I32, P, P, I32, P, P, P, P, P, P], I32),
+            "rogs_lidar_scratch_bytes": ([I32, I32], ctypes.c_size_t),
+            "rogs_lidar_targets": ([P, I32, P, P, I32, P, P, P, P, P, P, ctypes.c_size_t, P], I32),
             "rogs_meshgrid_scratch_bytes": ([I32, I32, I32], ctypes.c_size_t),
             "rogs_meshgrid_layout": ([P, P, I32, ctypes.c_double, ctypes.c_double, F, I32, I32, I32,
                                       P, I64, P, P, P, P, P, ctypes.POINTER(I64), P,
@@ -264,6 +265,10 @@ def bev_camera(x0, y0, W, H, m_per_px, ox, oy, cw, ch, height) -> Camera:
 
 def elev_scratch_bytes(n: int) -> int:
     return int(load_library().rogs_elev_scratch_bytes(int(n)))
+
+
+def lidar_scratch_bytes(n: int, m: int) -> int:
+    return int(load_library().rogs_lidar_scratch_bytes(int(n), int(m)))
 
 
 def workspace_size(surf: Surfels, cams, opts: RenderOpts, pair_capacity: int,
@@ -425,11 +430,18 @@ class Rogs:
             self._check(r, "rogs_elev_loss_static")
         return r
 
-    def lidar_targets(self, x, y, px, py, pz, zbar, idx=None, stream=None):
-        """rogs_lidar_targets: zbar (and idx) of the nearest point in xy."""
+    def lidar_targets(self, x, y, px, py, pz, zbar, idx=None, stream=None, scratch=None):
+        """rogs_lidar_targets: zbar (and idx) of the nearest point in xy.
+        scratch: a uint8 device tensor of rogs_lidar_scratch_bytes bytes
+        (allocated from PyTorch when None)."""
+        import torch
+        need = int(self.L.rogs_lidar_scratch_bytes(x.numel(), px.numel()))
+        if scratch is None:
+            scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
         self._check(self.L.rogs_lidar_targets(self.h, x.numel(), ptr(x), ptr(y), px.numel(), ptr(px),
                                               ptr(py), ptr(pz), ptr(zbar), ptr(idx),
-                                              _stream(stream)), "rogs_lidar_targets")
+                                              ptr(scratch), scratch.numel(), _stream(stream)),
+                    "rogs_lidar_targets")
 
     def meshgrid_layout(self, poses, x0, y0, spacing, W, H, radius_px, stream=None):
         """rogs_meshgrid_layout on device poses (uint8 view of rogs_pose

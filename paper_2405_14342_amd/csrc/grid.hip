@@ -89,45 +89,193 @@ __global__ __launch_bounds__(64) void k_reg_total(const float* __restrict__ part
 }
 
 // Nearest point in the xy-plane: squared distance in binary64 of the binary32
-// inputs, ties to the lower point index.  Points are staged in LDS tiles.
+// inputs, ties to the lower point index.  The points are bucketed into a
+// uniform grid over the bounding box of surfels and points (about 2 m cells,
+// m = point count; the cell size is chosen on the device), sorted into cell
+// order by counting, and each surfel searches rings of cells around its own
+// cell outward.  After ring r every point not yet visited lies at least
+// r h - (rounding) from the surfel, so the search stops once the best
+// distance is below r h - 1e-6 m: the result is the brute-force one.
 constexpr int kNNBlock = 256;
-constexpr int kNNTile = 1024;
 
-__global__ __launch_bounds__(kNNBlock) void k_lidar_nn(int n, const float* __restrict__ x,
-                                                       const float* __restrict__ y, int m,
-                                                       const float* __restrict__ px,
-                                                       const float* __restrict__ py,
-                                                       const float* __restrict__ pz,
-                                                       float* __restrict__ zbar,
-                                                       int32_t* __restrict__ idx) {
+struct NNGrid {
+  double x0, y0, h, inv_h;
+  int32_t W, H;
+  int32_t pad[2];
+};
+static_assert(sizeof(NNGrid) == 48, "grid header");
+
+__device__ __forceinline__ void nn_cell(const NNGrid& g, float x, float y, int& cx, int& cy) {
 #pragma clang fp contract(off)
-  __shared__ float s_x[kNNTile], s_y[kNNTile];
+  const double fx = floor(((double)x - g.x0) * g.inv_h);
+  const double fy = floor(((double)y - g.y0) * g.inv_h);
+  cx = fx < 0.0 ? 0 : (fx > (double)(g.W - 1) ? g.W - 1 : (int)fx);
+  cy = fy < 0.0 ? 0 : (fy > (double)(g.H - 1) ? g.H - 1 : (int)fy);
+}
+
+// Per-block minimum and maximum of x and y over the surfels and the points.
+__global__ __launch_bounds__(kNNBlock) void k_nn_bbox(int n, const float* __restrict__ x,
+                                                      const float* __restrict__ y, int m,
+                                                      const float* __restrict__ px,
+                                                      const float* __restrict__ py,
+                                                      float4* __restrict__ part) {
+  __shared__ float4 s[kNNBlock / 64];
+  float4 b = make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY);
+  const int64_t tot = (int64_t)n + m;
+  for (int64_t k = (int64_t)blockIdx.x * kNNBlock + threadIdx.x; k < tot;
+       k += (int64_t)gridDim.x * kNNBlock) {
+    const float u = k < n ? x[k] : px[k - n];
+    const float v = k < n ? y[k] : py[k - n];
+    b.x = fminf(b.x, u); b.y = fminf(b.y, v); b.z = fmaxf(b.z, u); b.w = fmaxf(b.w, v);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    b.x = fminf(b.x, __shfl_xor(b.x, o, 64)); b.y = fminf(b.y, __shfl_xor(b.y, o, 64));
+    b.z = fmaxf(b.z, __shfl_xor(b.z, o, 64)); b.w = fmaxf(b.w, __shfl_xor(b.w, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kNNBlock / 64; ++w) {
+      b.x = fminf(b.x, s[w].x); b.y = fminf(b.y, s[w].y);
+      b.z = fmaxf(b.z, s[w].z); b.w = fmaxf(b.w, s[w].w);
+    }
+    part[blockIdx.x] = b;
+  }
+}
+
+// The grid over the bounding box (block 0): cell size h with about 2m cells,
+// enlarged until W * H <= max_cells.  Every block clears its share of the
+// max_cells + 1 cell counters.
+__global__ __launch_bounds__(256) void k_nn_grid(const float4* __restrict__ part, int nparts,
+                                                 int m, int64_t max_cells,
+                                                 NNGrid* __restrict__ g,
+                                                 uint32_t* __restrict__ cnt) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k <= max_cells;
+       k += (int64_t)gridDim.x * 256)
+    cnt[k] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float4 b = part[0];
+    for (int k = 1; k < nparts; ++k) {
+      b.x = fminf(b.x, part[k].x); b.y = fminf(b.y, part[k].y);
+      b.z = fmaxf(b.z, part[k].z); b.w = fmaxf(b.w, part[k].w);
+    }
+    const double ex = (double)b.z - (double)b.x, ey = (double)b.w - (double)b.y;
+    double h = sqrt((ex * ey) / (2.0 * (double)m));
+    if (!(h > 0.0)) h = fmax(fmax(ex, ey) / (2.0 * (double)m), 1e-3);
+    for (int it = 0; it < 200; ++it) {
+      const double w = floor(ex / h) + 1.0, hh = floor(ey / h) + 1.0;
+      if (w * hh <= (double)max_cells) break;
+      h *= 1.25;
+    }
+    NNGrid gg;
+    gg.x0 = (double)b.x;
+    gg.y0 = (double)b.y;
+    gg.h = h;
+    gg.inv_h = 1.0 / h;
+    gg.W = (int32_t)(floor(ex / h) + 1.0);
+    gg.H = (int32_t)(floor(ey / h) + 1.0);
+    gg.pad[0] = gg.pad[1] = 0;
+    *g = gg;
+  }
+}
+
+// Cell of every point and its rank among the points of its cell.
+__global__ __launch_bounds__(kNNBlock) void k_nn_count(int m, const float* __restrict__ px,
+                                                       const float* __restrict__ py,
+                                                       const NNGrid* __restrict__ g,
+                                                       uint32_t* __restrict__ cnt,
+                                                       uint32_t* __restrict__ rank) {
+  const int k = blockIdx.x * kNNBlock + threadIdx.x;
+  if (k >= m) return;
+  const NNGrid gg = *g;
+  int cx, cy;
+  nn_cell(gg, px[k], py[k], cx, cy);
+  rank[k] = atomicAdd(&cnt[(int64_t)cy * gg.W + cx], 1u);
+}
+
+// Points in cell order: index, x, y at their cell's start plus their rank.
+__global__ __launch_bounds__(kNNBlock) void k_nn_scatter(int m, const float* __restrict__ px,
+                                                         const float* __restrict__ py,
+                                                         const NNGrid* __restrict__ g,
+                                                         const uint32_t* __restrict__ start,
+                                                         const uint32_t* __restrict__ rank,
+                                                         int32_t* __restrict__ sidx,
+                                                         float2* __restrict__ sxy) {
+  const int k = blockIdx.x * kNNBlock + threadIdx.x;
+  if (k >= m) return;
+  const NNGrid gg = *g;
+  int cx, cy;
+  const float u = px[k], v = py[k];
+  nn_cell(gg, u, v, cx, cy);
+  const uint32_t p = start[(int64_t)cy * gg.W + cx] + rank[k];
+  sidx[p] = k;
+  sxy[p] = make_float2(u, v);
+}
+
+__device__ __forceinline__ void nn_visit(const uint32_t* __restrict__ start,
+                                         const int32_t* __restrict__ sidx,
+                                         const float2* __restrict__ sxy, int64_t cell, double xi,
+                                         double yi, double& best, int& bi) {
+#pragma clang fp contract(off)
+  const uint32_t a = start[cell], b = start[cell + 1];
+  for (uint32_t s = a; s < b; ++s) {
+    const float2 p = sxy[s];
+    const double dx = xi - (double)p.x;
+    const double dy = yi - (double)p.y;
+    const double d2 = dx * dx + dy * dy;
+    const int k = sidx[s];
+    if (d2 < best || (d2 == best && k < bi)) {
+      best = d2;
+      bi = k;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kNNBlock) void k_nn_search(int n, const float* __restrict__ x,
+                                                        const float* __restrict__ y,
+                                                        const NNGrid* __restrict__ g,
+                                                        const uint32_t* __restrict__ start,
+                                                        const int32_t* __restrict__ sidx,
+                                                        const float2* __restrict__ sxy,
+                                                        const float* __restrict__ pz,
+                                                        float* __restrict__ zbar,
+                                                        int32_t* __restrict__ idx) {
+#pragma clang fp contract(off)
   const int i = blockIdx.x * kNNBlock + threadIdx.x;
-  const double xi = i < n ? (double)x[i] : 0.0, yi = i < n ? (double)y[i] : 0.0;
+  if (i >= n) return;
+  const NNGrid gg = *g;
+  const float xf = x[i], yf = y[i];
+  const double xi = (double)xf, yi = (double)yf;
+  int cx, cy;
+  nn_cell(gg, xf, yf, cx, cy);
   double best = __longlong_as_double(0x7ff0000000000000ll);
   int bi = -1;
-  for (int k0 = 0; k0 < m; k0 += kNNTile) {
-    const int cnt = min(kNNTile, m - k0);
-    for (int t = threadIdx.x; t < cnt; t += kNNBlock) {
-      s_x[t] = px[k0 + t];
-      s_y[t] = py[k0 + t];
-    }
-    __syncthreads();
-    for (int t = 0; t < cnt; ++t) {
-      const double dx = xi - (double)s_x[t];
-      const double dy = yi - (double)s_y[t];
-      const double d2 = dx * dx + dy * dy;
-      if (d2 < best) {
-        best = d2;
-        bi = k0 + t;
+  const int rmax = max(gg.W, gg.H);
+  for (int r = 0; r <= rmax; ++r) {
+    if (r == 0) {
+      nn_visit(start, sidx, sxy, (int64_t)cy * gg.W + cx, xi, yi, best, bi);
+    } else {
+      // the ring at Chebyshev distance r: its rows cy - r and cy + r, then
+      // the columns cx - r and cx + r between them
+      for (int dy = -r; dy <= r; dy += 2 * r) {
+        const int j = cy + dy;
+        if (j < 0 || j >= gg.H) continue;
+        for (int ii = max(cx - r, 0); ii <= min(cx + r, gg.W - 1); ++ii)
+          nn_visit(start, sidx, sxy, (int64_t)j * gg.W + ii, xi, yi, best, bi);
+      }
+      for (int dx = -r; dx <= r; dx += 2 * r) {
+        const int ii = cx + dx;
+        if (ii < 0 || ii >= gg.W) continue;
+        for (int j = max(cy - r + 1, 0); j <= min(cy + r - 1, gg.H - 1); ++j)
+          nn_visit(start, sidx, sxy, (int64_t)j * gg.W + ii, xi, yi, best, bi);
       }
     }
-    __syncthreads();
+    // points outside rings 0..r are at least r h from the surfel
+    const double bound = (double)r * gg.h - 1e-6;
+    if (bi >= 0 && bound > 0.0 && best < bound * bound) break;
   }
-  if (i < n) {
-    zbar[i] = bi >= 0 ? pz[bi] : 0.0f;
-    if (idx) idx[i] = bi;
-  }
+  zbar[i] = bi >= 0 ? pz[bi] : 0.0f;
+  if (idx) idx[i] = bi;
 }
 
 // ------------------------------------------------------------ meshgrid layout
@@ -247,10 +395,48 @@ void launch_elev_reg(int n, const float* z, const int32_t* nbr, float lam_s, con
                      accumulate_total ? 1 : 0);
 }
 
+size_t lidar_scratch_bytes(int n, int m) {
+  const int64_t cells = 2 * (int64_t)m + 64;
+  const int64_t nparts = std::min<int64_t>(((int64_t)n + m + kNNBlock - 1) / kNNBlock, 1024);
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o = (o + b + 255) / 256 * 256; return r; };
+  take(sizeof(NNGrid));
+  take(16 * (size_t)nparts);
+  take(4 * (size_t)(cells + 2));
+  take(4 * scan_tmp_words(cells + 1));
+  take(4 * (size_t)m);       // rank
+  take(4 * (size_t)m);       // sorted index
+  take(8 * (size_t)m);       // sorted x, y
+  return o;
+}
+
 void launch_lidar_nn(int n, const float* x, const float* y, int m, const float* px,
-                     const float* py, const float* pz, float* zbar, int32_t* idx, hipStream_t st) {
-  hipLaunchKernelGGL(k_lidar_nn, dim3((unsigned)((n + kNNBlock - 1) / kNNBlock)), dim3(kNNBlock),
-                     0, st, n, x, y, m, px, py, pz, zbar, idx);
+                     const float* py, const float* pz, float* zbar, int32_t* idx, void* scratch,
+                     hipStream_t st) {
+  const int64_t cells = 2 * (int64_t)m + 64;
+  const int64_t nparts = std::min<int64_t>(((int64_t)n + m + kNNBlock - 1) / kNNBlock, 1024);
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o = (o + b + 255) / 256 * 256; return r; };
+  char* base = static_cast<char*>(scratch);
+  NNGrid* g = reinterpret_cast<NNGrid*>(base + take(sizeof(NNGrid)));
+  float4* part = reinterpret_cast<float4*>(base + take(16 * (size_t)nparts));
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(base + take(4 * (size_t)(cells + 2)));
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(base + take(4 * scan_tmp_words(cells + 1)));
+  uint32_t* rank = reinterpret_cast<uint32_t*>(base + take(4 * (size_t)m));
+  int32_t* sidx = reinterpret_cast<int32_t*>(base + take(4 * (size_t)m));
+  float2* sxy = reinterpret_cast<float2*>(base + take(8 * (size_t)m));
+  hipLaunchKernelGGL(k_nn_bbox, dim3((unsigned)nparts), dim3(kNNBlock), 0, st, n, x, y, m, px, py,
+                     part);
+  const unsigned cb = (unsigned)std::min<int64_t>((cells + 1 + 2047) / 2048, 4096);
+  hipLaunchKernelGGL(k_nn_grid, dim3(cb), dim3(256), 0, st, part, (int)nparts, m, cells, g, cnt);
+  const unsigned pb = (unsigned)((m + kNNBlock - 1) / kNNBlock);
+  hipLaunchKernelGGL(k_nn_count, dim3(pb), dim3(kNNBlock), 0, st, m, px, py, g, cnt, rank);
+  // cells beyond the grid's W * H hold zeros: the scan runs over the bound
+  scan_u32(cnt, cnt, cells + 1, nullptr, tmp, st);
+  hipLaunchKernelGGL(k_nn_scatter, dim3(pb), dim3(kNNBlock), 0, st, m, px, py, g, cnt, rank, sidx,
+                     sxy);
+  hipLaunchKernelGGL(k_nn_search, dim3((unsigned)((n + kNNBlock - 1) / kNNBlock)), dim3(kNNBlock),
+                     0, st, n, x, y, g, cnt, sidx, sxy, pz, zbar, idx);
 }
 
 size_t layout_scratch_bytes(int W, int H, int np) {
@@ -364,13 +550,25 @@ int rogs_elev_loss_static(rogs_ctx* c, int32_t n, const float* z, const int32_t*
                                                             hipGetErrorString(e));
 }
 
+size_t rogs_lidar_scratch_bytes(int32_t n, int32_t m) {
+  if (n < 1 || m < 1) return 0;
+  return rogs::lidar_scratch_bytes(n, m);
+}
+
 int rogs_lidar_targets(rogs_ctx* c, int32_t n, const float* x, const float* y, int32_t m,
                        const float* px, const float* py, const float* pz, float* zbar,
-                       int32_t* idx, void* stream) {
+                       int32_t* idx, void* scratch, size_t scratch_bytes, void* stream) {
   if (!c) return ROGS_EINVAL;
-  if (n < 1 || m < 1 || !x || !y || !px || !py || !pz || !zbar)
+  if (n < 1 || m < 1 || !x || !y || !px || !py || !pz || !zbar || !scratch)
     return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_lidar_targets: null argument or empty set");
-  rogs::launch_lidar_nn(n, x, y, m, px, py, pz, zbar, idx, static_cast<hipStream_t>(stream));
+  if (m > (1 << 29))
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_lidar_targets: at most 2^29 points");
+  if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0)
+    return rogs::ctx_fail(c, ROGS_EINVAL, "rogs_lidar_targets: scratch must be 256-byte aligned");
+  if (scratch_bytes < rogs_lidar_scratch_bytes(n, m))
+    return rogs::ctx_fail(c, ROGS_ENOMEM, "rogs_lidar_targets: scratch too small");
+  rogs::launch_lidar_nn(n, x, y, m, px, py, pz, zbar, idx, scratch,
+                        static_cast<hipStream_t>(stream));
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ROGS_OK
                          : rogs::ctx_fail(c, ROGS_EHIP, std::string("rogs_lidar_targets: ") +

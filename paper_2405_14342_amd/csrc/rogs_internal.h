@@ -593,8 +593,10 @@ int64_t elev_reg_blocks(int n);
 void launch_elev_reg(int n, const float* z, const int32_t* nbr, float lam_s, const float* zbar,
                      float lam_z, float* out_dz, float* acc_dz, float* part, float* total,
                      bool accumulate_total, hipStream_t st);
+size_t lidar_scratch_bytes(int n, int m);
 void launch_lidar_nn(int n, const float* x, const float* y, int m, const float* px,
-                     const float* py, const float* pz, float* zbar, int32_t* idx, hipStream_t st);
+                     const float* py, const float* pz, float* zbar, int32_t* idx, void* scratch,
+                     hipStream_t st);
 size_t layout_scratch_bytes(int W, int H, int np);
 void launch_layout_mask(const rogs_pose* poses, int np, double x0, double y0, float h, int W,
                         int H, int r, void* scratch, uint32_t* n_dev, hipStream_t st);

@@ -74,6 +74,52 @@ def test_lidar_targets_bitexact():
     np.testing.assert_array_equal(zb2.cpu().numpy(), pts[2][ref])
 
 
+def _nn_gpu(x, y, px, py):
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device="cuda")
+    rg = B.Rogs()
+    zbar = torch.empty(len(x), dtype=torch.float32, device="cuda")
+    idx = torch.empty(len(x), dtype=torch.int32, device="cuda")
+    pz = np.arange(len(px), dtype=np.float32)
+    rg.lidar_targets(d(x), d(y), d(px), d(py), d(pz), zbar, idx)
+    torch.cuda.synchronize()
+    i = idx.cpu().numpy()
+    np.testing.assert_array_equal(zbar.cpu().numpy(), pz[i])
+    return i
+
+
+def test_lidar_targets_ties_far_and_degenerate():
+    """Bucketed search = brute force (ties to the lower index) on duplicated
+    points, surfels far outside the points, a single repeated location and a
+    curved band of returns with surfels up to 15 m off it."""
+    rng = np.random.default_rng(19)
+    f = np.float32
+    px = np.repeat(rng.uniform(0, 2, 50), 4).astype(f)
+    py = np.repeat(rng.uniform(0, 2, 50), 4).astype(f)
+    cases = [(px[::3].copy(), py[::3].copy(), px, py),
+             (rng.uniform(0, 1, 50).astype(f), rng.uniform(0, 1, 50).astype(f),
+              np.full(7, 0.5, f), np.full(7, 0.5, f)),
+             (np.array([1e3, -40.0], f), np.array([-1e3, 3.0], f), np.array([0.0, 1.0], f),
+              np.array([0.0, 0.0], f))]
+    t = np.linspace(0, 100, 40000)
+    cases.append(((rng.uniform(0, 100, 4000)).astype(f), None,
+                  (t + rng.normal(0, 0.1, t.size)).astype(f),
+                  (0.1 * t + rng.normal(0, 3, t.size)).astype(f)))
+    x4 = cases[3][0]
+    cases[3] = (x4, (0.1 * x4 + rng.uniform(-15, 15, x4.size)).astype(f), cases[3][2], cases[3][3])
+    for x, y, qx, qy in cases:
+        np.testing.assert_array_equal(_nn_gpu(x, y, qx, qy), oracle.lidar_nn(x, y, qx, qy))
+
+
+def test_lidar_targets_full_size_sampled():
+    """800k surfels of the 200 m strip and 1M synthetic returns: the targets
+    of 3000 sampled surfels against the oracle's brute force."""
+    sc = synth.config3(with_targets=False)
+    pts = synth.lidar_points(sc.trajectory, 1_000_000, 4242)
+    idx = _nn_gpu(sc.x, sc.y, pts[0], pts[1])
+    sel = np.random.default_rng(3).choice(sc.n, 3000, replace=False)
+    np.testing.assert_array_equal(idx[sel], oracle.lidar_nn(sc.x[sel], sc.y[sel], pts[0], pts[1]))
+
+
 @pytest.mark.parametrize("radius", [0, 7, 25])
 def test_meshgrid_layout_bitexact(radius):
     traj = synth.Trajectory(40.0, 31)
