@@ -294,6 +294,37 @@ class TrainState:
         """Waits for the last fused step and returns its statistics."""
         return self.rg.fused_status()
 
+    # ------------------------------------------------------- checkpoints
+    _CKPT = ("params", "m", "v", "s_act", "alpha_act", "exposure", "m_exp", "v_exp")
+
+    def save_checkpoint(self, path: str) -> None:
+        """Writes the optimisation state to an .npz file: raw parameters,
+        Adam moments, the activated copies, exposure and its moments, the
+        host step count and the fused step's device state (step count,
+        skipped steps, last loss).  Waits for the device."""
+        torch.cuda.synchronize(self.dev)
+        arrs = {k: getattr(self, k).detach().cpu().numpy() for k in self._CKPT}
+        arrs["step_count"] = np.array([self.step_count], np.int64)
+        if hasattr(self, "step_state"):
+            arrs["step_state"] = self.step_state.cpu().numpy()
+        arrs["shape"] = np.array([self.N, self.C, self.V], np.int64)
+        np.savez(path, **arrs)
+
+    def load_checkpoint(self, path: str) -> None:
+        """Restores a state written by save_checkpoint for the same surfel
+        count, classes and views (no pickled objects are read)."""
+        with np.load(path, allow_pickle=False) as f:
+            if tuple(int(t) for t in f["shape"]) != (self.N, self.C, self.V):
+                raise ValueError("checkpoint is for another surfel count, class count or views")
+            for k in self._CKPT:
+                getattr(self, k).copy_(torch.as_tensor(f[k], device=self.dev))
+            self.step_count = int(f["step_count"][0])
+            if "step_state" in f.files:
+                if not hasattr(self, "step_state"):
+                    self.step_state = torch.zeros(16, dtype=torch.int32, device=self.dev)
+                self.step_state.copy_(torch.as_tensor(f["step_state"], device=self.dev))
+        torch.cuda.synchronize(self.dev)
+
     def render_all_plain(self):
         for v in range(self.V):
             self.forward_view(v)

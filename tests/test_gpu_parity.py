@@ -574,3 +574,35 @@ def test_channel_masks_render_only_selected_planes(gpu, name):
     # an all-plane forward again allows the backward
     st.rg.render_fwd(surf, ws, st.out)
     st.rg.render_bwd(surf, ws, st.out, st.G, st.grads, 0)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_checkpoint_resume_is_bitwise(gpu, tmp_path, fused):
+    """Two steps, checkpoint, a third step; a fresh state loaded from the
+    checkpoint takes the same third step: parameters, moments, activated
+    copies, exposure and the device step state are identical."""
+    sc = make_scene("c1")
+    total = 3
+    a = TrainState(sc)
+    a.exposure.copy_(torch.as_tensor(exposure_for(sc)))
+    step = (lambda s: s.step_fused(total_steps=total)) if fused else \
+        (lambda s: s.step_batched(total_steps=total))
+    for _ in range(2):
+        step(a)
+    path = str(tmp_path / "ckpt.npz")
+    a.save_checkpoint(path)
+    step(a)
+    b = TrainState(sc)
+    b.load_checkpoint(path)
+    step(b)
+    torch.cuda.synchronize()
+    for k in ("params", "m", "v", "s_act", "alpha_act", "exposure", "m_exp", "v_exp"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    if fused:       # the fused step counts its steps on the device
+        assert torch.equal(a.step_state, b.step_state)
+        assert b.fused_status()["step"] == total
+    else:
+        assert a.step_count == b.step_count == total
+    other = TrainState(make_scene("tiny2"))
+    with pytest.raises(ValueError):
+        other.load_checkpoint(path)
