@@ -124,6 +124,53 @@ def profiled_traffic(kernel: str, workload: str, tile: str):
     return rec["hbm_bytes_per_launch"]
 
 
+def tile_choice(st) -> dict:
+    """The launch configuration a TrainState runs: the options' tile shape and
+    LDS staging depth, and the tile shape of every resolution class."""
+    o = st.opts
+    classes = {}
+    for c in st.cams:
+        t = getattr(c, "tile", 0)
+        shape = (t & 0xFFFF, t >> 16) if t else (o.tile_w, o.tile_h)
+        classes[f"{c.w}x{c.h}/m{c.model}"] = f"{shape[0]}x{shape[1]}"
+    return {"tile": f"{o.tile_w}x{o.tile_h}", "stage": o.stage or 32, "classes": classes}
+
+
+def tile_label(choice: dict) -> str:
+    """Short name of a launch configuration (profile summaries are keyed by it)."""
+    parts = [choice["tile"] + (f"s{choice['stage']}" if choice["stage"] != 32 else "")]
+    parts += sorted(f"{k.split('/')[0]}-{v}" for k, v in choice["classes"].items()
+                    if v != choice["tile"])
+    return "_".join(parts)
+
+
+def make_state(scene, tile: str, cache):
+    """TrainState in a fixed tile shape 'WxH', or 'auto' (rogs_autotune over
+    fused training steps: tile shape, staging depth and a shape per
+    resolution class)."""
+    from paper_2405_14342_amd import binding as B
+    from paper_2405_14342_amd.pipeline import TrainState
+    if tile == "auto":
+        import tempfile
+        tmp = None
+        if cache is None:            # tune on this run; the file only carries the table out
+            tmp = tempfile.mkdtemp()
+            cache = os.path.join(tmp, "autotune.json")
+        st = TrainState(scene, device="cuda:0", opts="auto", autotune_cache=cache)
+        entries = json.load(open(cache))
+        # the entry of this workload: every configuration timed and the choice
+        key = [k for k in entries if k.startswith("step;") and f"n={scene.n};" in k]
+        st.autotune_entry = entries[key[0]] if len(key) == 1 else None
+        if tmp is not None:
+            os.remove(cache)
+            os.rmdir(tmp)
+        print(f"[bench] {scene.name}: autotuned {tile_choice(st)} "
+              f"({st.autotune_ms:.3f} ms per eager fused step)", file=sys.stderr, flush=True)
+        return st
+    tw, th = (int(t) for t in tile.split("x"))
+    return TrainState(scene, device="cuda:0", opts=B.make_opts(tile_w=tw, tile_h=th))
+
+
 def cpu_baseline(scene, views, threads: int, budget_s: float = 10.0):
     """The FP64 oracle's training step restricted to the given views (forward,
     loss and backward of those views, then the Sec. 4.2 optimiser on every
@@ -246,16 +293,14 @@ def bev_bench(surf, sc, opts, m_per_px: float = 0.05, chunk_px: int = 2000):
             "Mpixel_per_s": round(W * H / (ms * 1e-3) / 1e6, 1), "max_chunk_pairs": worst}
 
 
-def c4_bench(steps: int, warmup: int):
+def c4_bench(steps: int, warmup: int, tile: str, cache):
     """The fused step (graph) on the 3M-surfel, C = 16 map seen by six
-    1920 x 1080 cameras (per-view culling), tile 16 x 4."""
+    1920 x 1080 cameras (per-view culling), in the given tile configuration."""
     import torch
-    from paper_2405_14342_amd import binding as B
     from paper_2405_14342_amd import synth
-    from paper_2405_14342_amd.pipeline import TrainState
 
     sc = synth.config4()
-    st = TrainState(sc, device="cuda:0", opts=B.make_opts(tile_w=16, tile_h=4))
+    st = make_state(sc, tile, cache)
     total = warmup + steps + 1
     st.step_fused(total_steps=total)
     st.fit_fused_capacity()
@@ -272,7 +317,8 @@ def c4_bench(steps: int, warmup: int):
     if fst["overflow"] or fst["skipped"] != skipped0:
         raise RuntimeError("C4: pair capacity overflow during the timed steps")
     out = {"workload": sc.name, "surfels": sc.n, "views": sc.n_views, "sem_classes": sc.n_sem,
-           "pixels_per_step": sc.npix, "path": "fused (hipGraph)", "tile": "16x4",
+           "pixels_per_step": sc.npix, "path": "fused (hipGraph)", "tile": tile,
+           "tile_choice": tile_choice(st), "autotune": getattr(st, "autotune_entry", None),
            "ms_per_step": round(ms, 4), "value": round(sc.npix / (ms * 1e-3) / 1e6, 2),
            "unit": "Mpixel/s", "pairs": fst["pairs"], "visible_slots": fst["visible"]}
     del st
@@ -389,8 +435,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--tile", default="16x4",
-                    help="tile shape WxH, or 'auto' (rogs_autotune; default 16x4)")
+    ap.add_argument("--tile", default="auto",
+                    help="tile shape WxH, or 'auto' (default: rogs_autotune chooses the tile "
+                         "shape, the LDS staging depth and a shape per resolution class)")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON cache file of rogs_autotune (default: tune on every run)")
     ap.add_argument("--no-grid-terms", action="store_true",
                     help="skip the step with the smoothness and LiDAR losses")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -418,16 +467,8 @@ def main():
     scene = synth.CONFIGS[args.config]()
     C = scene.n_sem
     total_steps = args.warmup + args.steps
-    from paper_2405_14342_amd import binding as B
-    if args.tile == "auto":
-        # rogs_autotune times every supported tile shape on this workload first
-        st = TrainState(scene, device="cuda:0", opts="auto")
-        print(f"[bench] autotuned tile {st.opts.tile_w}x{st.opts.tile_h} "
-              f"({st.autotune_ms:.3f} ms per project+sort+fwd+bwd)", file=sys.stderr, flush=True)
-    else:
-        tw, th = (int(t) for t in args.tile.split("x"))
-        st = TrainState(scene, device="cuda:0", opts=B.make_opts(tile_w=tw, tile_h=th))
-    tile = f"{st.opts.tile_w}x{st.opts.tile_h}"
+    st = make_state(scene, args.tile, args.autotune_cache)
+    choice = tile_choice(st)
     print(f"[bench] {scene.name}: {scene.n} surfels, {scene.n_views} views, "
           f"{scene.npix} px/step", file=sys.stderr, flush=True)
 
@@ -519,7 +560,7 @@ def main():
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": profiled_traffic(dom, scene.name, f"{st.opts.tile_w}x{st.opts.tile_h}"),
+                "traffic": profiled_traffic(dom, scene.name, tile_label(choice)),
                 "avg_launch_ms": round(dom_ms, 4), "alg_flops_per_launch": int(dom_flops),
                 "flops_per_contributing_entry": int(algorithmic_flops(1, C)),
                 "alg_bytes_per_launch": int(dom_bytes),
@@ -542,7 +583,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded surfel grid, cameras and random targets)",
         "config": {"workload": scene.name, "surfels": scene.n, "views": scene.n_views,
-                   "tile": tile, "pixels_per_step": scene.npix, "sem_classes": C,
+                   "tile": args.tile, "tile_choice": choice,
+                   "autotune_ms": (round(st.autotune_ms, 4) if args.tile == "auto" else None),
+                   "autotune": getattr(st, "autotune_entry", None),
+                   "pixels_per_step": scene.npix, "sem_classes": C,
                    "path": "fused (hipGraph)", "pairs": stats["pairs"],
                    "visible_slots": stats["visible"]},
         "fused_eager_ms_per_step": round(ms_fe, 4),
@@ -562,7 +606,7 @@ def main():
     del st, ws_b
     torch.cuda.empty_cache()
     if not args.no_c4 and args.config != 4:
-        line["c4"] = c4_bench(args.steps, args.warmup)
+        line["c4"] = c4_bench(args.steps, args.warmup, args.tile, args.autotune_cache)
         print(f"[bench] C4 fused: {line['c4']['ms_per_step']} ms/step, "
               f"{line['c4']['value']} Mpixel/s", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:

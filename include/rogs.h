@@ -146,11 +146,16 @@ typedef struct {
  * pixels.  Orthographic (Sec. 3.3.1, J = identity): fx, fy in pixels per
  * metre.  The ground cull rectangle (supp. Sec. 2.1) is given by its origin
  * (camera centre xy), unit ground directions of the camera x and z axes, a
- * half-width and a forward length; cull_lat <= 0 disables it. */
+ * half-width and a forward length; cull_lat <= 0 disables it.
+ * tile: 0 renders the view in the options' tile shape; otherwise
+ * tile_w | tile_h << 16 gives this view its own shape, of the same area
+ * (tile_w * tile_h) as the options' and with tile_w dividing 64
+ * (ROGS_EINVAL otherwise).  Every shape renders the same values; rogs_autotune
+ * chooses shapes per resolution class this way. */
 typedef struct {
   int32_t w, h;         /* image size, 1..16384 */
   int32_t model;        /* ROGS_PINHOLE or ROGS_ORTHO */
-  int32_t reserved;     /* must be 0 */
+  int32_t tile;         /* 0, or this view's tile_w | tile_h << 16 */
   float fx, fy, cx, cy;
   float R_cw[9];        /* row-major */
   float t_cw[3];
@@ -166,6 +171,9 @@ typedef struct {
   float q_cut;             /* Mahalanobis cut, default 9 (3 sigma) */
   float alpha_max;         /* opacity clamp, default 0.99 */
   float t_eps;             /* termination threshold on T, default 1e-6 */
+  int32_t stage;           /* list entries the compositing waves stage in LDS per
+                              batch: 16, 32 or 64 (0 means 32, the default).
+                              Values are the same for each; only speed differs. */
 } rogs_render_opts;
 
 /* Loss targets of a batch (Eq. 8, 9), device arrays in the image layout. */
@@ -301,15 +309,15 @@ ROGS_API int rogs_adam_step(rogs_ctx* ctx, int32_t n, int32_t n_sem, float* para
 /* ------------------------------------------------------ fused step
  * The whole training step (a1-a10) over all views of a batch in one graph:
  * cull + projection, emission, binning and ranges with the pair count kept
- * on the device, forward compositing with the loss seed fused into its
- * epilogue (per-pixel dL/dO, G.O, T and n_last kept in a tile-major
- * workspace record; the images themselves are not written), backward
- * compositing, and the projection adjoint fused with Adam.  The step number
+ * on the device; then one kernel per tile that composites the forward, forms
+ * the loss and its per-pixel seed dL/dO in registers and runs the backward
+ * pass over the same list (neither the images nor the seed are written to
+ * memory); then the projection adjoint fused with Adam.  The step number
  * lives on the device (step_state), so no host value changes between steps.
  *
  * The sequence is captured into a hipGraph on the first call and replayed by
- * later calls with the same arguments (same pointers, sizes, options and
- * view resolutions; camera poses may change: each call copies the camera
+ * later calls with the same arguments (same pointers, sizes, options, view
+ * resolutions and per-view tile shapes; camera poses may change: each call copies the camera
  * table from one of two pinned buffers ahead of the graph).  Two steps stay
  * in flight: each call first waits for the step launched two calls before,
  * then launches, so the device runs the previous step meanwhile.  A step
@@ -452,28 +460,50 @@ ROGS_API int rogs_bev_export(rogs_ctx* ctx, const rogs_surfels* s, const rogs_re
                              int64_t* n_pairs_max, void* stream);
 
 /* ------------------------------------------------------ autotuner
- * Chooses the tile shape for a workload.  Every supported shape (tile_w in
- * {4, 8, 16, 32, 64}, tile_w * tile_h in {64, 128, 256}) renders the same
- * values, since the per-pixel rule does not depend on it (Sec. 3.3.1 with
- * the 3-sigma cut); shapes differ in the number of (surfel, tile) pairs and in
- * the work each wave rejects.  For each shape the call sizes the capacities
- * with one counted run, then times `reps` runs (after one warm-up) of
- * rogs_project + rogs_bin_sort (device count) + rogs_render_fwd +
- * rogs_render_bwd with dL/d(out) = 1 over the given surfels and views, and
- * writes the fastest shape into opts->tile_w / tile_h (other fields kept);
- * *ms_out (nullable) receives its time per run.
- * cache_json (nullable): path of a JSON cache keyed by the workload (n,
- * n_sem, every view's size, model and fx).  A cached entry is returned
- * without timing; a new result is added to the file, which this call
- * rewrites whole.  A file not written by this call is rejected (ROGS_EINVAL)
- * and left untouched.
+ * Chooses the launch configuration for a workload: the tile shape (which
+ * also sets the pixels per lane, tile_w * tile_h / 64), the LDS staging depth
+ * (opts->stage) and a tile shape per resolution class.  Every configuration
+ * renders the same values, since the per-pixel rule does not depend on it
+ * (Sec. 3.3.1 with the 3-sigma cut); they differ in the number of (surfel,
+ * tile) pairs, in the work each wave rejects and in LDS occupancy.  One run
+ * is rogs_project + rogs_bin_sort (device count) + rogs_render_fwd +
+ * rogs_render_bwd with dL/d(out) = 1 over the given surfels and views; each
+ * configuration is sized with one counted run and then timed over `reps`
+ * runs after one warm-up.  The search is a descent: (1) every shape with
+ * tile_w in {4, 8, 16, 32, 64} and tile_w * tile_h in {64, 128, 256}, all
+ * views alike, staging depth 32; (2) staging depth 16, 32, 64 at that shape;
+ * (3) with more than one resolution class (views of equal w, h and model),
+ * each class in turn tries the other shapes of the same area while the rest
+ * keep theirs.  With step != NULL the timed run is instead one fused
+ * training step (rogs_step_fused with ROGS_FUSED_EAGER) on copies of
+ * step->state that the call makes and restores before each configuration,
+ * so the caller's state is only read; each configuration's capacities come
+ * from one untimed step.  The result goes to opts->tile_w / tile_h / stage (other
+ * fields kept) and, when view_tiles is not null, view_tiles[v] receives the
+ * rogs_camera.tile code of view v (0 where the view keeps the options'
+ * shape); pass those codes in the cameras of later calls.  *ms_out
+ * (nullable) receives the time per run of the result.
+ * cache_json (nullable): path of a JSON cache keyed by the workload (what
+ * is timed, n, n_sem, every view's size, model and fx).  A cached entry, which lists the
+ * shape of each class, is returned without timing; a new result is added to
+ * the file, which this call rewrites whole.  A file not written by this call
+ * is rejected (ROGS_EINVAL) and left untouched.  The cameras' own tile fields
+ * are ignored.  In step mode the context's fused-step status is reset: it
+ * holds no step of the caller afterwards (read it first if needed).
  * Unlike the calls above this one allocates (hipMalloc: workspace, images,
  * gradients) and frees before returning, synchronises the stream, and leaves
  * the context's batch state at the last shape timed (call rogs_project
  * again before rogs_bin_sort / render). */
+typedef struct {
+  const rogs_train_state* state;   /* read only; targets->exposure == state->exposure */
+  const rogs_targets* targets;
+  const rogs_optim* optim;
+} rogs_tune_step;
+
 ROGS_API int rogs_autotune(rogs_ctx* ctx, const rogs_surfels* s, const rogs_camera* cams,
-                           int32_t n_views, rogs_render_opts* opts, const char* cache_json,
-                           int32_t reps, float* ms_out, void* stream);
+                           int32_t n_views, rogs_render_opts* opts, int32_t* view_tiles,
+                           const rogs_tune_step* step, const char* cache_json, int32_t reps,
+                           float* ms_out, void* stream);
 
 /* ------------------------------------------------------ serving
  * Render server over a resident map (the served form of a6: forward only).

@@ -55,7 +55,7 @@ class Surfels(ctypes.Structure):
 
 class Camera(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("model", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("tile", ctypes.c_int32), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
                 ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("R_cw", ctypes.c_float * 9),
                 ("t_cw", ctypes.c_float * 3), ("z_near", ctypes.c_float),
                 ("cull_o", ctypes.c_float * 2), ("cull_ex", ctypes.c_float * 2),
@@ -85,7 +85,8 @@ def channel_planes(channels: int, C: int) -> int:
 
 class RenderOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("eps2d", ctypes.c_float),
-                ("q_cut", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_eps", ctypes.c_float)]
+                ("q_cut", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_eps", ctypes.c_float),
+                ("stage", ctypes.c_int32)]
 
 
 class Targets(ctypes.Structure):
@@ -117,6 +118,11 @@ class Optim(ctypes.Structure):
     _fields_ = [("lr", LR), ("z_start", ctypes.c_float), ("z_end", ctypes.c_float),
                 ("total_steps", ctypes.c_int64), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class TuneStep(ctypes.Structure):
+    _fields_ = [("state", ctypes.POINTER(TrainStateC)), ("targets", ctypes.POINTER(Targets)),
+                ("optim", ctypes.POINTER(Optim))]
 
 
 _lib = None
@@ -186,7 +192,8 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.c_size_t, P], I32),
             "rogs_server_destroy": ([P], None),
             "rogs_autotune": ([P, ctypes.POINTER(Surfels), ctypes.POINTER(Camera), I32,
-                               ctypes.POINTER(RenderOpts), ctypes.c_char_p, I32,
+                               ctypes.POINTER(RenderOpts), ctypes.POINTER(I32),
+                               ctypes.POINTER(TuneStep), ctypes.c_char_p, I32,
                                ctypes.POINTER(ctypes.c_float), P], I32),
         }
         for name, (args, res) in sig.items():
@@ -209,7 +216,8 @@ def ptr(t) -> Optional[int]:
 def make_camera(cam) -> Camera:
     """rogs_camera from a camera description with the fields of synth.Camera."""
     c = Camera()
-    c.w, c.h, c.model, c.reserved = int(cam.w), int(cam.h), int(cam.model), 0
+    c.w, c.h, c.model = int(cam.w), int(cam.h), int(cam.model)
+    c.tile = int(getattr(cam, "tile", 0))
     c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
     R = np.asarray(cam.R_cw, np.float32).reshape(9)
     t = np.asarray(cam.t_cw, np.float32).reshape(3)
@@ -239,8 +247,14 @@ def default_opts() -> RenderOpts:
     return o
 
 
-def make_opts(tile_w=16, tile_h=16, eps2d=0.3, q_cut=9.0, alpha_max=0.99, t_eps=1e-6) -> RenderOpts:
-    return RenderOpts(tile_w, tile_h, eps2d, q_cut, alpha_max, t_eps)
+def make_opts(tile_w=16, tile_h=16, eps2d=0.3, q_cut=9.0, alpha_max=0.99, t_eps=1e-6,
+              stage=32) -> RenderOpts:
+    return RenderOpts(tile_w, tile_h, eps2d, q_cut, alpha_max, t_eps, stage)
+
+
+def tile_code(tile_w: int, tile_h: int) -> int:
+    """rogs_camera.tile value giving a view its own tile shape."""
+    return int(tile_w) | int(tile_h) << 16
 
 
 def fused_workspace_size(ts: TrainStateC, cams, opts: RenderOpts, pair_capacity: int,
@@ -399,16 +413,25 @@ class Rogs:
         return r
 
     def autotune(self, surf: Surfels, cams, opts: Optional[RenderOpts] = None,
-                 cache_json: Optional[str] = None, reps: int = 3, stream=None):
-        """rogs_autotune: returns (opts with the fastest tile shape, ms per run)."""
+                 cache_json: Optional[str] = None, reps: int = 3, stream=None, step=None):
+        """rogs_autotune: returns (opts with the chosen tile shape and staging
+        depth, ms per run, the rogs_camera.tile code of every view).  step:
+        None times the render passes; (TrainStateC, Targets, Optim) times
+        fused training steps on copies of that state."""
         o = RenderOpts.from_buffer_copy(opts if opts is not None else default_opts())
         arr = camera_array(cams)
         ms = ctypes.c_float(0.0)
+        tiles = (ctypes.c_int32 * len(arr))()
         path = cache_json.encode() if cache_json else None
+        ts = None
+        if step is not None:
+            ts = TuneStep(ctypes.pointer(step[0]), ctypes.pointer(step[1]),
+                          ctypes.pointer(step[2]))
         self._check(self.L.rogs_autotune(self.h, ctypes.byref(surf), arr, len(arr), ctypes.byref(o),
+                                         tiles, ctypes.byref(ts) if ts is not None else None,
                                          path, int(reps), ctypes.byref(ms), _stream(stream)),
                     "rogs_autotune")
-        return o, float(ms.value)
+        return o, float(ms.value), [int(t) for t in tiles]
 
     def elev_loss(self, n, z, nbr, lambda_smooth, zbar, lambda_z, dz, loss_out, scratch,
                   stream=None):

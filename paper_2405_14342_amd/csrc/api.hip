@@ -56,7 +56,7 @@ struct rogs_ctx {
     rogs_targets tg{};
     rogs_optim opt{};
     rogs_render_opts opts{};
-    std::vector<int32_t> sizes;         // w, h, model of every view
+    std::vector<int32_t> sizes;         // w, h, model and tile code of every view
     // two steps in flight: step k uses buffer k & 1, and step k + 2 waits for it
     void* stage[2] = {nullptr, nullptr}; // pinned: view table + first-block table
     size_t stage_bytes = 0;
@@ -98,6 +98,22 @@ namespace rogs {
 
 int ctx_fail(rogs_ctx* c, int code, const std::string& msg) { return fail(c, code, msg); }
 
+// Tile shape of a view: the options' (tw, th) unless camera.tile gives its
+// own, tile_w | tile_h << 16 with tile_w dividing 64 and the same area.
+bool view_shape(const rogs_camera& c, int tw, int th, int* vtw, int* vth) {
+  if (c.tile == 0) {
+    *vtw = tw;
+    *vth = th;
+    return true;
+  }
+  const uint32_t code = (uint32_t)c.tile;
+  const int w = (int)(code & 0xffffu), h = (int)(code >> 16);
+  if (w < 1 || w > 64 || (64 % w) != 0 || h < 1 || w * h != tw * th) return false;
+  *vtw = w;
+  *vth = h;
+  return true;
+}
+
 int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
                 const rogs_render_opts* opts, int64_t cap, int64_t scap, Layout* L,
                 const char** why, bool fused) {
@@ -121,6 +137,10 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
     *why = "render options out of range";
     return ROGS_EINVAL;
   }
+  if (opts->stage != 0 && opts->stage != 16 && opts->stage != 32 && opts->stage != 64) {
+    *why = "stage must be 0, 16, 32 or 64";
+    return ROGS_EINVAL;
+  }
   Layout l;
   l.N = s->n;
   l.C = s->n_sem;
@@ -128,6 +148,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.tw = tw;
   l.th = th;
   l.ppl = tw * th / 64;
+  l.stage = opts->stage ? opts->stage : 32;
   l.FS = feat_stride(l.C);
   l.GS = grad_stride(l.C);
   l.nb = (l.N + kProjBlock - 1) / kProjBlock;
@@ -142,7 +163,11 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
     const rogs_camera& c = cams[v];
     if (c.w < 1 || c.h < 1 || c.w > 16384 || c.h > 16384) { *why = "camera size out of range"; return ROGS_EINVAL; }
     if (c.model != ROGS_PINHOLE && c.model != ROGS_ORTHO) { *why = "unknown camera model"; return ROGS_EINVAL; }
-    if (c.reserved != 0) { *why = "camera.reserved must be 0"; return ROGS_EINVAL; }
+    int vtw = tw, vth = th;
+    if (!view_shape(c, tw, th, &vtw, &vth)) {
+      *why = "camera.tile: tile_w must divide 64 and tile_w*tile_h must equal the options' area";
+      return ROGS_EINVAL;
+    }
     if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !is_fin(c.fx) || !is_fin(c.fy) || !is_fin(c.cx) ||
         !is_fin(c.cy) || !is_fin(c.z_near)) {
       *why = "camera intrinsics must be finite with fx, fy > 0";
@@ -153,7 +178,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
     const int64_t np = (int64_t)c.w * c.h;
     l.total_pix += np;
     l.max_view_pix = std::max(l.max_view_pix, np);
-    const int64_t vt = (int64_t)((c.w + tw - 1) / tw) * ((c.h + th - 1) / th);
+    const int64_t vt = (int64_t)((c.w + vtw - 1) / vtw) * ((c.h + vth - 1) / vth);
     l.total_tiles += vt;
     l.max_view_tiles = std::max(l.max_view_tiles, vt);
     loss_blocks += (np + 255) / 256;
@@ -218,6 +243,20 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   return ROGS_OK;
 }
 
+void ctx_fused_forget(rogs_ctx* c) {
+  auto& F = c->fz;
+  for (int k = 0; k < 2; ++k) {
+    if (F.pending[k]) (void)hipEventSynchronize(F.done[k]);
+    F.pending[k] = false;
+  }
+  if (F.exec) (void)hipGraphExecDestroy(F.exec);
+  if (F.graph) (void)hipGraphDestroy(F.graph);
+  F.exec = nullptr;
+  F.graph = nullptr;
+  F.valid = false;
+  F.launched = 0;
+}
+
 int ctx_set_view_channels(rogs_ctx* c, const uint32_t* ch, int n) {
   if (!c || n < 0 || (n > 0 && !ch)) return ROGS_EINVAL;
   c->view_ch.assign(ch, ch + n);
@@ -253,8 +292,12 @@ void fill_view_table(const Layout& L, const rogs_camera* cams, void* dst,
     d.ez[0] = k.cull_ez[0]; d.ez[1] = k.cull_ez[1];
     d.lat = k.cull_lat; d.fwd = k.cull_fwd;
     d.w = k.w; d.h = k.h; d.model = k.model;
-    d.tiles_x = (k.w + L.tw - 1) / L.tw;
-    d.tiles_y = (k.h + L.th - 1) / L.th;
+    int vtw = L.tw, vth = L.th;
+    (void)rogs::view_shape(k, L.tw, L.th, &vtw, &vth);     // validated by make_layout
+    d.tw = (int16_t)vtw;
+    d.th = (int16_t)vth;
+    d.tiles_x = (k.w + vtw - 1) / vtw;
+    d.tiles_y = (k.h + vth - 1) / vth;
     d.tile_off = (int32_t)tiles;
     d.ch = ch ? ch[v] : (uint32_t)ROGS_CH_ALL;
     vt[v] = d;
@@ -424,6 +467,7 @@ void rogs_default_opts(rogs_render_opts* o) {
   o->q_cut = 9.0f;
   o->alpha_max = 0.99f;
   o->t_eps = 1e-6f;
+  o->stage = 32;
 }
 
 int rogs_workspace_size(const rogs_surfels* s, const rogs_camera* cams, int32_t n_views,
@@ -905,6 +949,7 @@ int rogs_step_fused(rogs_ctx* c, const rogs_train_state* t, const rogs_camera* c
     sizes.push_back(cams[v].w);
     sizes.push_back(cams[v].h);
     sizes.push_back(cams[v].model);
+    sizes.push_back(cams[v].tile);
   }
   const bool eager = (flags & ROGS_FUSED_EAGER) != 0;
   const bool same = F.valid && F.ws == ws && F.st == st && F.flags == flags &&

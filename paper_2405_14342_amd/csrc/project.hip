@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_pack_feat(int N, int C, int FS,
 }
 
 __global__ __launch_bounds__(kProjBlock) void k_project(
-    const ViewDev* __restrict__ views, int V, int N, int nb, float eps, float qcut, int tw, int th,
+    const ViewDev* __restrict__ views, int V, int N, int nb, float eps, float qcut,
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
     const float* __restrict__ pq, const float* __restrict__ ps,
     uint32_t* __restrict__ cnt, float4* __restrict__ rec, uint2* __restrict__ rect,
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
   p.vis = false;
   p.y0 = 0;
   if (valid) {
-    p = project_contract(vw, eps, qcut, tw, th, px[i], py[i], pz[i], pq[i], pq[N + i],
+    p = project_contract(vw, eps, qcut, px[i], py[i], pz[i], pq[i], pq[N + i],
                          pq[2 * (size_t)N + i], pq[3 * (size_t)N + i], ps[i], ps[N + i]);
     if (p.vis) {
       const Span sp = span_setup(p.uh, p.vh, p.ul, p.vl, p.A, p.B, p.C, qcut, p.x0, p.x1);
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
     const int r = (int)(k - s_roff[j]);
     const Span& sj = s_sp[j];
     int lo, hi;
-    span_row(sj, tw, th, vw.w, vw.h, (int)s_y0[j] + r, lo, hi);
+    span_row(sj, vw.tw, vw.th, vw.w, vw.h, (int)s_y0[j] + r, lo, hi);
     if (hi > lo) atomicAdd(&s_cnt[j], (uint32_t)(hi - lo));
     if (span_desc_ok(sj.x0, sj.x1, (int)s_y0[j], (int)s_y1[j]))
       rspan[((size_t)v * N + blockIdx.x * kProjBlock + (j & (kProjBlock - 1))) * kSpanRows + r] =
@@ -422,8 +422,8 @@ void launch_project(const Layout& L, void* ws, const rogs_surfels* s, bool pack_
   }
   const int nmb = mask ? mask_chunks(L) : 0;
   hipLaunchKernelGGL(k_project, dim3(L.nb + nmb, L.V), dim3(kProjBlock), 0, st,
-                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, L.tw,
-                     L.th, s->x, s->y, s->z, s->q, s->s, at<uint32_t>(ws, L.o_cnt),
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.nb, L.eps2d, L.q_cut, s->x, s->y, s->z,
+                     s->q, s->s, at<uint32_t>(ws, L.o_cnt),
                      at<float4>(ws, L.o_rec), at<uint2>(ws, L.o_rect),
                      at<uint16_t>(ws, L.o_rspan), at<uint32_t>(ws, L.o_part),
                      at<uint32_t>(ws, L.o_partv), mask, nmb,

@@ -7,7 +7,7 @@
 // from LDS feeds PPL pixels.  A wave starts from one precomputed record
 // (tile, list range, view) and reads each entry's slot directly, so the
 // prologue is two dependent global loads before the records arrive.
-// The wave stages kStage list entries at a time in LDS (projection record +
+// The wave stages KS list entries at a time in LDS (projection record +
 // the surfel's colour/semantic features), then every lane walks them in
 // order.  A pixel stops after the surfel that takes its transmittance below
 // t_eps; the wave leaves the list once all of its pixels have stopped.
@@ -51,8 +51,8 @@ __device__ __forceinline__ int find_view(const ViewDev* __restrict__ views, int 
 }
 
 
-// List entries staged in LDS at a time (a multiple of 16, at most 64).
-constexpr int kStage = 32;
+// List entries staged in LDS at a time: the template parameter KS of the
+// compositing kernels, 16, 32 or 64 (rogs_render_opts.stage).
 
 // Per-tile constants of the compositing kernels.
 struct TileGeom {
@@ -62,8 +62,8 @@ struct TileGeom {
   const ViewDev* vw;
 };
 
-__device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views, int N, int tw,
-                                              int th, const uint4* __restrict__ tinfo) {
+__device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views, int N,
+                                              const uint4* __restrict__ tinfo) {
   TileGeom t;
   const int lane = threadIdx.x;
   const uint4 ti = tinfo[blockIdx.x];      // tile, list begin, list end, view
@@ -74,6 +74,7 @@ __device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views,
   t.H = t.vw->h;
   const int lt = t.gt - t.vw->tile_off;
   const int ty = lt / t.vw->tiles_x, tx = lt - ty * t.vw->tiles_x;
+  const int tw = t.vw->tw, th = t.vw->th;
   const int sh = __builtin_ctz((unsigned)tw);      // tile_w divides 64: a power of two
   t.rows = 64 >> sh;
   t.px = tx * tw + (lane & (tw - 1));
@@ -118,7 +119,7 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 // lane's emission index in the first staged batch.  ch (ROGS_CH_* bits,
 // uniform): the colour, semantic and depth sums are formed only when
 // selected; T, n_last and the order of operations do not depend on it.
-template <int C, int PPL, bool kE, bool kD>
+template <int C, int PPL, int KS, bool kE, bool kD>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
                                              const uint32_t* __restrict__ spair,
@@ -144,8 +145,8 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
     for (int f = 0; f <= F; ++f) acc[k][f] = 0.0f;
   }
   bool stop_all = false;
-  for (uint32_t base = tg.rbeg; base < tg.rend && !stop_all; base += kStage) {
-    const int cnt = (int)min((uint32_t)kStage, tg.rend - base);
+  for (uint32_t base = tg.rbeg; base < tg.rend && !stop_all; base += KS) {
+    const int cnt = (int)min((uint32_t)KS, tg.rend - base);
     const uint32_t e =
         stage_entries<FS4, kE>(base, cnt, tg.sbase, vals, spair, rec, feat, s_r0, s_r1, s_f);
     if (base == tg.rbeg) e_first = e;
@@ -266,7 +267,7 @@ __device__ __forceinline__ void feature_gemm(const float* s_w, const uint32_t* s
 // gradient values per pair at its emission index: the five moments and
 // dalpha are summed across the wave with a reduce-scatter, the feature and
 // depth gradients come from feature_gemm once per 16 entries.
-template <int C, int PPL, bool kDA>
+template <int C, int PPL, int KS, bool kDA>
 __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, float amax,
                                               const uint32_t* __restrict__ vals,
                                               const uint32_t* __restrict__ spair,
@@ -328,14 +329,14 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           bG[nb][kk][c] = s_w[(kk * 64 + kgrp * 16 + c) * GR + nb * 16 + mrow];
     __syncthreads();
   }
-  for (uint32_t base = tg.rbeg; base < stop; base += kStage) {
-    const int cnt = (int)min((uint32_t)kStage, stop - base);
+  for (uint32_t base = tg.rbeg; base < stop; base += KS) {
+    const int cnt = (int)min((uint32_t)KS, stop - base);
     // a list the forward staged whole is still in LDS
     const uint32_t e_mine =
         staged ? e_pre
                : stage_entries<FS4, true>(base, cnt, tg.sbase, vals, spair, rec, feat, s_r0,
                                           s_r1, s_f);
-    if (lane < kStage) s_e[lane] = e_mine;
+    if (lane < KS) s_e[lane] = e_mine;
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
       const uint32_t idx = base - tg.rbeg + (uint32_t)j;
@@ -434,9 +435,9 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
 // ones selected by mask and the view's own channel set, and, when all are
 // selected, per pixel T_final, n_last, the relative depth D' and its
 // reference t0 for the backward.
-template <int C, int PPL>
+template <int C, int PPL, int KS>
 __global__ __launch_bounds__(64) void k_render_fwd(
-    const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
+    const ViewDev* __restrict__ views, int V, int N, float qcut, float amax,
     float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, float* __restrict__ out,
@@ -445,9 +446,9 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;           // output channels
-  __shared__ float4 s_r0[kStage], s_r1[kStage];
-  __shared__ float4 s_f[kStage * FS4];
-  const TileGeom tg = tile_geom(views, N, tw, th, tinfo);
+  __shared__ float4 s_r0[KS], s_r1[KS];
+  __shared__ float4 s_f[KS * FS4];
+  const TileGeom tg = tile_geom(views, N, tinfo);
   float T[PPL], acc[PPL][F + 1], pyc[PPL];
   uint32_t nl[PPL];
 #pragma unroll
@@ -456,8 +457,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   float t0[PPL];
   const uint32_t ch = (uint32_t)tg.vw->ch & mask;
   constexpr uint32_t kPlanes = ROGS_CH_RGB | ROGS_CH_SEM | ROGS_CH_D | ROGS_CH_A;
-  forward_tile<C, PPL, false, true>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1, s_f,
-                                    pyc, acc, T, nl, e_first, t0, ch);
+  forward_tile<C, PPL, KS, false, true>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1,
+                                        s_f, pyc, acc, T, nl, e_first, t0, ch);
   const uint32_t len = tg.rend - tg.rbeg;
   const size_t HW = (size_t)tg.W * tg.H;
   float* o = out + (size_t)NO * tg.vw->pix_off;
@@ -486,9 +487,9 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 
 // Backward compositing of the batch from the output gradient G (5 + C planes
 // per view), the outputs, T_final and n_last.
-template <int C, int PPL>
+template <int C, int PPL, int KS>
 __global__ __launch_bounds__(64) void k_render_bwd(
-    const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
+    const ViewDev* __restrict__ views, int V, int N, float qcut, float amax,
     const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, const float* __restrict__ out,
@@ -498,11 +499,11 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
-  __shared__ float4 s_r0[kStage], s_r1[kStage];
-  __shared__ float4 s_f[kStage * FS4];
+  __shared__ float4 s_r0[KS], s_r1[KS];
+  __shared__ float4 s_f[KS * FS4];
   __shared__ float4 s_w4[bwd_lds_floats<C, PPL>() / 4];
-  __shared__ uint32_t s_e[kStage];
-  const TileGeom tg = tile_geom(views, N, tw, th, tinfo);
+  __shared__ uint32_t s_e[KS];
+  const TileGeom tg = tile_geom(views, N, tinfo);
   const size_t HW = (size_t)tg.W * tg.H;
   float Gv[PPL][F + 2], GO[PPL], Tf[PPL], pyc[PPL], t0[PPL];
   uint32_t nl[PPL];
@@ -533,7 +534,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       nl[k] = nlast[tg.vw->pix_off + p];
     }
   }
-  backward_tile<C, PPL, true>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
+  backward_tile<C, PPL, KS, true>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
                               reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair, GS,
                               false, 0u, t0);
 }
@@ -541,21 +542,21 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 // The fused step's compositing: forward, the loss of Eq. 7-9 and 12 per pixel
 // (its gradient, G.O, and this tile's share of the loss and of dL/d(a, b)),
 // then the backward, in one kernel per tile.
-template <int C, int PPL>
+template <int C, int PPL, int KS>
 __global__ __launch_bounds__(64) void k_render_step(
-    const ViewDev* __restrict__ views, int V, int N, int tw, int th, float qcut, float amax,
+    const ViewDev* __restrict__ views, int V, int N, float qcut, float amax,
     float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, float* __restrict__ gpair,
     int GS, FusedLoss fl) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
-  __shared__ float4 s_r0[kStage], s_r1[kStage];
-  __shared__ float4 s_f[kStage * FS4];
+  __shared__ float4 s_r0[KS], s_r1[KS];
+  __shared__ float4 s_f[KS * FS4];
   __shared__ float4 s_w4[bwd_lds_floats<C, PPL>() / 4];
-  __shared__ uint32_t s_e[kStage];
+  __shared__ uint32_t s_e[KS];
   const int lane = threadIdx.x;
-  const TileGeom tg = tile_geom(views, N, tw, th, tinfo);
+  const TileGeom tg = tile_geom(views, N, tinfo);
   float pyc[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) pyc[k] = (float)(tg.py0 + k * tg.rows) + 0.5f;
@@ -593,9 +594,9 @@ __global__ __launch_bounds__(64) void k_render_step(
     float t0[PPL];          // not used: the fused loss has no depth term
 #pragma unroll
     for (int k = 0; k < PPL; ++k) t0[k] = 0.0f;
-    forward_tile<C, PPL, true, false>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0, s_r1,
-                                      s_f, pyc, acc, T, nlf, e_first, t0,
-                                      ROGS_CH_RGB | ROGS_CH_SEM);
+    forward_tile<C, PPL, KS, true, false>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0,
+                                          s_r1, s_f, pyc, acc, T, nlf, e_first, t0,
+                                          ROGS_CH_RGB | ROGS_CH_SEM);
     // loss epilogue: dL/dO and G.O per pixel, this tile's loss partials
     const uint32_t len = tg.rend - tg.rbeg;
     float l = 0.0f, dal = 0.0f, dbl = 0.0f;
@@ -630,9 +631,9 @@ __global__ __launch_bounds__(64) void k_render_step(
       if (c >= 0 && (lane & rs_dup_bits(3)) == 0) fl.part[3 * (size_t)tg.gt + c] = tot;
     }
     // the fused loss has no depth or alpha term: their gradient rows are zero
-    backward_tile<C, PPL, false>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
-                                 reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair,
-                                 GS, len <= (uint32_t)kStage, e_first, t0);
+    backward_tile<C, PPL, KS, false>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
+                                     reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl,
+                                     gpair, GS, len <= (uint32_t)KS, e_first, t0);
   }
 }
 
@@ -641,7 +642,7 @@ __global__ __launch_bounds__(64) void k_render_step(
 // those, the ones whose 3-sigma test passes.  Summed over the batch into
 // counts[0] (evaluated) and counts[1] (contributing) with 64-bit atomics.
 __global__ __launch_bounds__(64) void k_count_work(
-    const ViewDev* __restrict__ views, int V, int tw, int th, int ppl, float qcut,
+    const ViewDev* __restrict__ views, int V, int ppl, float qcut,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ pslot, const float4* __restrict__ rec,
     const uint32_t* __restrict__ nlast, unsigned long long* __restrict__ counts) {
@@ -651,6 +652,7 @@ __global__ __launch_bounds__(64) void k_count_work(
   const ViewDev& vw = views[v];
   const int lt = gt - vw.tile_off;
   const int ty = lt / vw.tiles_x, tx = lt - ty * vw.tiles_x;
+  const int tw = vw.tw, th = vw.th;
   const int rows = 64 / tw;
   const int px = tx * tw + (lane % tw);
   const float pxc = (float)px + 0.5f;
@@ -689,10 +691,10 @@ __global__ __launch_bounds__(64) void k_count_work(
   }
 }
 
-template <int C, int PPL>
+template <int C, int PPL, int KS>
 void fwd_launch(const Layout& L, void* ws, float* out, uint32_t mask, hipStream_t st) {
-  hipLaunchKernelGGL((k_render_fwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
-                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
+  hipLaunchKernelGGL((k_render_fwd<C, PPL, KS>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.q_cut, L.alpha_max,
                      L.t_eps, at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out,
@@ -700,10 +702,10 @@ void fwd_launch(const Layout& L, void* ws, float* out, uint32_t mask, hipStream_
                      at<float2>(ws, L.o_drel), mask);
 }
 
-template <int C, int PPL>
+template <int C, int PPL, int KS>
 void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hipStream_t st) {
-  hipLaunchKernelGGL((k_render_bwd<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
-                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
+  hipLaunchKernelGGL((k_render_bwd<C, PPL, KS>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.q_cut, L.alpha_max,
                      at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out, G,
@@ -711,10 +713,10 @@ void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hip
                      at<const float2>(ws, L.o_drel), at<float>(ws, L.o_gpair), L.GS);
 }
 
-template <int C, int PPL>
+template <int C, int PPL, int KS>
 void step_launch(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st) {
-  hipLaunchKernelGGL((k_render_step<C, PPL>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
-                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.tw, L.th, L.q_cut, L.alpha_max,
+  hipLaunchKernelGGL((k_render_step<C, PPL, KS>), dim3((unsigned)L.total_tiles), dim3(64), 0, st,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.N, L.q_cut, L.alpha_max,
                      L.t_eps, at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat),
@@ -722,21 +724,32 @@ void step_launch(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st)
 }
 
 // which: 0 forward, 1 backward, 2 fused step
-template <int C, int PPL>
+template <int C, int PPL, int KS>
 void launch_one(const Layout& L, void* ws, const float* out, const float* G, float* outw,
                 const FusedLoss* fl, int which, uint32_t mask, hipStream_t st) {
-  if (which == 0) fwd_launch<C, PPL>(L, ws, outw, mask, st);
-  else if (which == 1) bwd_launch<C, PPL>(L, ws, out, G, st);
-  else step_launch<C, PPL>(L, ws, *fl, st);
+  if (which == 0) fwd_launch<C, PPL, KS>(L, ws, outw, mask, st);
+  else if (which == 1) bwd_launch<C, PPL, KS>(L, ws, out, G, st);
+  else step_launch<C, PPL, KS>(L, ws, *fl, st);
+}
+
+template <int C, int PPL>
+int dispatch_stage(const Layout& L, void* ws, const float* out, const float* G, float* outw,
+                   const FusedLoss* fl, int which, uint32_t mask, hipStream_t st) {
+  switch (L.stage) {
+    case 16: launch_one<C, PPL, 16>(L, ws, out, G, outw, fl, which, mask, st); return 0;
+    case 32: launch_one<C, PPL, 32>(L, ws, out, G, outw, fl, which, mask, st); return 0;
+    case 64: launch_one<C, PPL, 64>(L, ws, out, G, outw, fl, which, mask, st); return 0;
+    default: return -1;
+  }
 }
 
 template <int C>
 int dispatch_ppl(const Layout& L, void* ws, const float* out, const float* G, float* outw,
                  const FusedLoss* fl, int which, uint32_t mask, hipStream_t st) {
   switch (L.ppl) {
-    case 1: launch_one<C, 1>(L, ws, out, G, outw, fl, which, mask, st); return 0;
-    case 2: launch_one<C, 2>(L, ws, out, G, outw, fl, which, mask, st); return 0;
-    case 4: launch_one<C, 4>(L, ws, out, G, outw, fl, which, mask, st); return 0;
+    case 1: return dispatch_stage<C, 1>(L, ws, out, G, outw, fl, which, mask, st);
+    case 2: return dispatch_stage<C, 2>(L, ws, out, G, outw, fl, which, mask, st);
+    case 4: return dispatch_stage<C, 4>(L, ws, out, G, outw, fl, which, mask, st);
     default: return -1;
   }
 }
@@ -774,7 +787,7 @@ int launch_render_bwd(const Layout& L, void* ws, const rogs_surfels*, const floa
 void launch_count_work(const Layout& L, void* ws, unsigned long long* counts, hipStream_t st) {
   if (L.total_tiles <= 0) return;
   hipLaunchKernelGGL(k_count_work, dim3((unsigned)L.total_tiles), dim3(64), 0, st,
-                     at<const ViewDev>(ws, L.o_views), L.V, L.tw, L.th, L.ppl, L.q_cut,
+                     at<const ViewDev>(ws, L.o_views), L.V, L.ppl, L.q_cut,
                      at<const uint2>(ws, L.o_ranges), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_pslot), at<const float4>(ws, L.o_rec),
                      at<const uint32_t>(ws, L.o_nlast), counts);

@@ -29,7 +29,7 @@ struct ViewDev {
   int32_t tiles_x, tiles_y;
   int32_t tile_off;     // first global tile index of the view
   uint32_t ch;          // ROGS_CH_* planes to composite (rogs_render_fwd ANDs its mask)
-  int32_t pad;
+  int16_t tw, th;       // the view's tile shape (tw divides 64; tw * th is the batch's tile area)
 };
 
 // Number of semantic classes with a compiled kernel set.
@@ -40,7 +40,8 @@ inline int grad_stride(int C) { return ((10 + C) + 3) & ~3; }     // per-pair gr
 // Layout of one batch inside the caller's workspace (byte offsets).
 struct Layout {
   int32_t N = 0, C = 0, V = 0;
-  int32_t tw = 16, th = 16, ppl = 4;
+  int32_t tw = 16, th = 16, ppl = 4;   // the options' tile shape (views may differ, same area)
+  int32_t stage = 32;                   // list entries staged in LDS per batch
   int32_t FS = 0, GS = 0;
   int32_t nb = 0;              // blocks of kProjBlock surfels
   int64_t total_pix = 0, total_tiles = 0, max_view_pix = 0, max_view_tiles = 0, cap = 0;
@@ -138,9 +139,8 @@ __device__ inline bool ground_inside(const ViewDev& c, float xf, float yf) {
 // Key contract (see rogs.h): the projection in binary64 from the binary32
 // inputs, without FMA contraction, one rounded operation per step in the
 // documented order, rounded once into the binary32 record.
-__device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcut_f, int tw,
-                                        int th, float xf, float yf, float zf, float qwf,
-                                        float qxf, float qyf, float qzf, float sxf, float syf) {
+__device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcut_f, float xf,
+                                        float yf, float zf, float qwf, float qxf, float qyf, float qzf, float sxf, float syf) {
 #pragma clang fp contract(off)
   Proj r;
   r.vis = false;
@@ -215,6 +215,7 @@ __device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcu
   if (!isfinite(u) || !isfinite(v) || !isfinite(hx) || !isfinite(hy) || !isfinite(A) ||
       !isfinite(B) || !isfinite(C))
     return r;
+  const int tw = c.tw, th = c.th;
   const int x0 = clamp_tile(floor((u - hx) / (double)tw), c.tiles_x);
   const int x1 = clamp_tile(floor((u + hx) / (double)tw) + 1.0, c.tiles_x);
   const int y0 = clamp_tile(floor((v - hy) / (double)th), c.tiles_y);
@@ -608,6 +609,10 @@ int launch_render_fwd(const Layout& L, void* ws, const rogs_surfels* s, float* o
 // Channel sets (ROGS_CH_*) of the views of the next rogs_project call on this
 // context (n entries, one per view; n = 0 clears: every view gets all
 // planes).  Used by the render server for per-request channel sets.
+// Waits for the fused steps in flight and forgets them and the captured
+// graph: the next rogs_step_fused starts afresh and rogs_fused_status reports
+// no step until then.
+void ctx_fused_forget(rogs_ctx* c);
 int ctx_set_view_channels(rogs_ctx* c, const uint32_t* ch, int n);
 void launch_loss(const Layout& L, void* ws, const float* out, const rogs_targets* t, float* G,
                  float* loss_out, float* d_exp, hipStream_t st);

@@ -184,8 +184,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const uint32_t* __restrict__ s_dev, int64_t s_host, int64_t scap, int64_t cap,
     const uint32_t* __restrict__ sval, const uint32_t* __restrict__ soff,
     const uint32_t* __restrict__ scnt, const uint2* __restrict__ rect,
-    const uint16_t* __restrict__ rspan, const float4* __restrict__ rec, float qcut, int tw,
-    int th, const uint32_t* __restrict__ bstart, uint32_t* __restrict__ keys,
+    const uint16_t* __restrict__ rspan, const float4* __restrict__ rec, float qcut,
+    const uint32_t* __restrict__ bstart, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ rank, uint32_t* __restrict__ pslot, uint32_t* __restrict__ pdep,
     uint32_t* __restrict__ tcnt, uint32_t* __restrict__ n_emit) {
   static_assert(kEmitThreads == kProjBlock, "block scan width");
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         hi = x0 + (int)(d >> 8);
       } else {
         const ViewDev& vw = views[slot / (uint32_t)N];
-        span_row(emit_span(rec, slot, qcut, x0, x1), tw, th, vw.w, vw.h, ty, lo, hi);
+        span_row(emit_span(rec, slot, qcut, x0, x1), vw.tw, vw.th, vw.w, vw.h, ty, lo, hi);
       }
       s_rx[k] = (uint32_t)(hi - lo);
       s_rinfo[k] = (uint32_t)lo | ((uint32_t)ty << 16);
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
           a = x0 + (int)(d & 0xffu);
           b = x0 + (int)(d >> 8);
         } else {
-          span_row(sp, tw, th, vw.w, vw.h, ty, a, b);
+          span_row(sp, vw.tw, vw.th, vw.w, vw.h, ty, a, b);
         }
         if (kk < b - a) {
           tx = a + kk;
@@ -810,7 +810,7 @@ void launch_binning(const Layout& L, void* ws, int64_t n_pairs, int64_t n_vis, h
                          at<const ViewDev>(ws, L.o_views), L.N, p_dev, p_grid, s_dev, s_grid,
                          L.scap, L.cap, sv, soff, scnt, at<const uint2>(ws, L.o_rect),
                          at<const uint16_t>(ws, L.o_rspan), at<const float4>(ws, L.o_rec),
-                         L.q_cut, L.tw, L.th, at<const uint32_t>(ws, L.o_bstart), keys, rank,
+                         L.q_cut, at<const uint32_t>(ws, L.o_bstart), keys, rank,
                          at<uint32_t>(ws, L.o_pslot), at<uint32_t>(ws, L.o_pdep), tcnt, n_emit);
     } else if (n_emit) {
       fill_u32(n_emit, 0u, 1, st);

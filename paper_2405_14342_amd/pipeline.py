@@ -14,6 +14,7 @@ librogs through :mod:`binding`.  Two sequences are provided:
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
@@ -49,10 +50,13 @@ class TrainState:
     """Surfel parameters, Adam moments, targets and output buffers on the GPU."""
 
     def __init__(self, scene, device="cuda", opts=None, pair_capacity: Optional[int] = None,
-                 autotune_cache: Optional[str] = None):
+                 autotune_cache: Optional[str] = None, autotune_for: str = "step"):
         """opts: RenderOpts, None (defaults) or "auto" (rogs_autotune picks the
-        tile shape for these surfels and views, optionally through a JSON
-        cache file)."""
+        tile shape, the staging depth and a tile shape per resolution class for
+        these surfels and views, optionally through a JSON cache file; the
+        per-view shapes go into the cameras' tile codes).  autotune_for:
+        "step" times the fused training step (on copies of this state; scenes
+        without targets fall back to "render"), "render" the render passes."""
         self.scene = scene
         self.dev = torch.device(device)
         N, C = scene.n, scene.n_sem
@@ -96,12 +100,12 @@ class TrainState:
         else:
             self.tgt_rgb = self.tgt_label = self.tgt_mask = None
         self.rg = B.Rogs()
-        if isinstance(opts, str):
-            if opts != "auto":
-                raise ValueError("opts must be RenderOpts, None or 'auto'")
-            opts, self.autotune_ms = self.rg.autotune(self.surfels(), self.cams,
-                                                      cache_json=autotune_cache)
-        self.opts = opts or B.make_opts()
+        auto = isinstance(opts, str)
+        if auto and opts != "auto":
+            raise ValueError("opts must be RenderOpts, None or 'auto'")
+        if autotune_for not in ("step", "render"):
+            raise ValueError("autotune_for must be 'step' or 'render'")
+        self.opts = B.make_opts() if auto or opts is None else opts
         self.cap_view = pair_capacity or 1 << 20
         self.cap_batch = pair_capacity or 1 << 22
         self.cap_fused = self.cap_batch
@@ -111,6 +115,14 @@ class TrainState:
         self.step_count = 0
         self.nbr = self.zbar = None
         self.lambda_smooth = self.lambda_z = 0.0
+        if auto:
+            step = None
+            if autotune_for == "step" and self.tgt_rgb is not None:
+                step = (self.train_state(), self.targets(0, self.V),
+                        paper_optim(self.scene.extent, 1000))
+            self.opts, self.autotune_ms, tiles = self.rg.autotune(
+                self.surfels(), self.cams, self.opts, cache_json=autotune_cache, step=step)
+            self.cams = [dataclasses.replace(c, tile=t) for c, t in zip(self.cams, tiles)]
 
     # -------------------------------------------------------------- views
     def surfels(self) -> B.Surfels:

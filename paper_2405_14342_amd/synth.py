@@ -62,6 +62,8 @@ class Camera:
     fx, fy are pixels per metre.  The cull rectangle is given by its origin
     (camera centre, xy), the unit ground directions of the camera x and z axes,
     a half-width and a forward length; ``cull_lat <= 0`` disables it.
+    ``tile`` is the renderer's per-view tile code (``tile_w | tile_h << 16``,
+    0 = the render options' shape); it changes no rendered value.
     """
     w: int
     h: int
@@ -78,6 +80,7 @@ class Camera:
     cull_ez: np.ndarray = field(default_factory=lambda: np.array([0, 1], np.float32))
     cull_lat: float = 0.0
     cull_fwd: float = 0.0
+    tile: int = 0
 
     @property
     def npix(self) -> int:

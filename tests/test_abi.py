@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header():
     # rogs_camera: 4 ints + 4 + 9 + 3 + 1 + 6 + 2 floats
     assert ctypes.sizeof(B.Camera) == 4 * (4 + 4 + 9 + 3 + 1 + 6 + 2)
-    assert ctypes.sizeof(B.RenderOpts) == 24
+    assert ctypes.sizeof(B.RenderOpts) == 28
     assert ctypes.sizeof(B.Surfels) == 8 + 8 * 8
     # 4 pointers, 3 floats (+4 padding), 2 pointers, 2 floats
     assert ctypes.sizeof(B.Targets) == 4 * 8 + 3 * 4 + 4 + 2 * 8 + 2 * 4
@@ -73,7 +73,8 @@ def test_workspace_size_grows_with_capacity_and_views():
 
 
 @pytest.mark.parametrize("bad", ["n", "sem", "views", "cap", "tile", "tile2", "eps", "amax",
-                                 "cam_w", "cam_model", "cam_reserved", "cam_fx", "cam_nan"])
+                                 "cam_w", "cam_model", "cam_tile", "cam_tile2", "cam_fx", "cam_nan",
+                                 "stage"])
 def test_workspace_size_rejects_invalid(bad):
     sc = synth.config1()
     cams = [B.make_camera(c) for c in sc.cams]
@@ -100,8 +101,12 @@ def test_workspace_size_rejects_invalid(bad):
         cams[0].w = 0
     elif bad == "cam_model":
         cams[0].model = 7
-    elif bad == "cam_reserved":
-        cams[0].reserved = 1
+    elif bad == "cam_tile":          # area differs from the options' 16 x 16
+        cams[0].tile = B.tile_code(16, 4)
+    elif bad == "cam_tile2":         # tile_w must divide 64
+        cams[0].tile = B.tile_code(12, 16)
+    elif bad == "stage":
+        o.stage = 48
     elif bad == "cam_fx":
         cams[0].fx = -1.0
     elif bad == "cam_nan":
@@ -129,3 +134,28 @@ def test_null_context_is_rejected():
     assert L.rogs_create(None) == B.EINVAL
     assert L.rogs_last_error(None) == b"null context"
     L.rogs_destroy(None)
+
+
+def test_per_view_tile_and_stage_accepted():
+    """A view's own tile shape of the options' area, and every staging depth,
+    are valid; the per-tile arrays follow the view's own tile count."""
+    sc = synth.config1()
+    s = _surf(sc.n, 8)
+    L = B.load_library()
+    sizes = {}
+    for code in (0, B.tile_code(64, 4), B.tile_code(4, 64), B.tile_code(32, 8)):
+        cams = [B.make_camera(c) for c in sc.cams]
+        cams[0].tile = code
+        for stage in (0, 16, 32, 64):
+            o = B.make_opts(stage=stage)
+            out = ctypes.c_size_t(0)
+            r = L.rogs_workspace_size(ctypes.byref(s), B.camera_array(cams), 1, ctypes.byref(o),
+                                      1000, 0, ctypes.byref(out))
+            assert r == B.OK, (code, stage)
+            sizes.setdefault(code, set()).add(out.value)
+    # the staging depth changes no buffer; a 16 x 16 code equals the default
+    assert all(len(v) == 1 for v in sizes.values())
+    w, h = sc.cams[0].w, sc.cams[0].h
+    tiles = lambda tw, th: -(-w // tw) * -(-h // th)
+    if tiles(64, 4) != tiles(16, 16):
+        assert sizes[B.tile_code(64, 4)] != sizes[0]
