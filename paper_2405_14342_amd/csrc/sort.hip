@@ -452,14 +452,89 @@ __device__ __forceinline__ bool key_less(uint32_t ka, uint32_t ia, uint32_t kb, 
   return ka < kb || (ka == kb && ia < ib);
 }
 
-// Lists of 1 to 64 entries, packed by length: the launch order groups the
-// tiles by the bit length bl of their list length, so a wave takes 64 / 2^bl
+// One wave's bitonic network over 64 R elements held R per lane (element
+// r * 64 + lane in register r): distances of 64 and more compare registers of
+// the same lane, shorter ones exchange across lanes.
+template <int R>
+__device__ __forceinline__ void wave_sort_regs(uint32_t (&key)[R], uint32_t (&e)[R], int lane) {
+  constexpr uint32_t P = 64u * R;
+#pragma unroll
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64u) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int pr = r ^ (int)(j >> 6);
+          if (r < pr) {
+            const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
+            const bool up = (i & k) == 0u;
+            if (up == key_less(key[pr], e[pr], key[r], e[r])) {
+              const uint32_t tk = key[r], te = e[r];
+              key[r] = key[pr];
+              e[r] = e[pr];
+              key[pr] = tk;
+              e[pr] = te;
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t ok = (uint32_t)__shfl_xor((int)key[r], (int)j, 64);
+          const uint32_t oe = (uint32_t)__shfl_xor((int)e[r], (int)j, 64);
+          const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
+          const bool keep_min = (((uint32_t)lane & j) == 0u) == ((i & k) == 0u);
+          if (keep_min == key_less(ok, oe, key[r], e[r])) {
+            key[r] = ok;
+            e[r] = oe;
+          }
+        }
+      }
+    }
+  }
+}
+
+// One list of 64 R / 2 to 64 R entries on one wave: loaded R per lane,
+// sorted in registers, written back with each pair's slot.
+template <int R>
+__device__ __forceinline__ void wave_sort_list(uint32_t beg, uint32_t len,
+                                               uint32_t* __restrict__ vals,
+                                               const uint32_t* __restrict__ pslot,
+                                               const uint32_t* __restrict__ pdep,
+                                               uint32_t* __restrict__ spair, int lane) {
+  uint32_t key[R], e[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
+    e[r] = key[r] = 0xffffffffu;
+    if (i < len) e[r] = vals[beg + i];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if ((uint32_t)r * 64u + (uint32_t)lane < len) key[r] = pdep[e[r]];
+  wave_sort_regs<R>(key, e, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
+    if (i < len) {
+      vals[beg + i] = e[r];
+      spair[beg + i] = pslot[e[r]];
+    }
+  }
+}
+
+// Lists of 1 to 511 entries.  The launch order groups the tiles by the bit
+// length bl of their list length.  For bl <= 6 a wave takes 64 / 2^bl
 // consecutive tiles of one group, each on a segment of 2^bl lanes, and sorts
 // every segment with one bitonic network over (key, e) (the e of a tile are
-// distinct, so the order is strict).  Work
-// items (waves) of a group: ceil(tiles / (64 / 2^bl)); the blocks stride
-// over all groups' items.  Lists of 65 or more entries (bl = 7 holds 64 to
-// 127) are left to k_tile_sort_long.
+// distinct, so the order is strict); for bl = 7, 8, 9 (64 to 511 entries) a
+// wave takes one tile and holds 2, 4 or 8 entries per lane (wave_sort_list).
+// Work items (waves) of a group: ceil(tiles / tiles per wave); the blocks
+// stride over all groups' items, longest lists first.  Lists of 512 or more
+// entries are left to k_tile_sort_long.
+constexpr uint32_t kWaveSortMax = 511;
+
 __global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict__ tinfo,
                                                         const uint32_t* __restrict__ bucket_tot,
                                                         uint32_t* __restrict__ vals,
@@ -478,8 +553,8 @@ __global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict_
       s_start[d] = st;
       st += s_cnt[d];
       s_items[d] = 0u;
-      if (bl >= 1 && bl <= 7) {
-        const uint32_t per = 64u >> (bl == 7 ? 6 : bl);       // tiles per wave
+      if (bl >= 1 && bl <= 9) {
+        const uint32_t per = bl >= 6 ? 1u : 64u >> bl;         // tiles per wave
         s_items[d] = (s_cnt[d] + per - 1u) / per;
       }
     }
@@ -492,7 +567,15 @@ __global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict_
     uint32_t wi = w;
     while (wi >= s_items[d]) { wi -= s_items[d]; ++d; }
     const int bl = 15 - d;
-    const int S = bl == 7 ? 64 : (1 << bl);                    // segment lanes
+    if (bl >= 7) {
+      const uint4 ti = tinfo[s_start[d] + wi];
+      const uint32_t beg = ti.y, len = ti.z - ti.y;
+      if (bl == 7) wave_sort_list<2>(beg, len, vals, pslot, pdep, spair, lane);
+      else if (bl == 8) wave_sort_list<4>(beg, len, vals, pslot, pdep, spair, lane);
+      else wave_sort_list<8>(beg, len, vals, pslot, pdep, spair, lane);
+      continue;
+    }
+    const int S = 1 << bl;                                     // segment lanes
     const uint32_t per = 64u / (uint32_t)S;
     const uint32_t pos = s_start[d] + wi * per + (uint32_t)(lane / S);
     const uint32_t seg_lane = (uint32_t)(lane & (S - 1));
@@ -501,7 +584,6 @@ __global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict_
       const uint4 ti = tinfo[pos];
       beg = ti.y;
       len = ti.z - ti.y;
-      if (len > 64u) len = 0u;                                 // k_tile_sort_long's
     }
     uint32_t e = 0xffffffffu, key = 0xffffffffu;
     if (seg_lane < len) {
@@ -527,10 +609,11 @@ __global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict_
   }
 }
 
-// Lists of more than 64 entries, taken in launch order (longest first, so a
-// block stops at the first list shorter than 64): up to kLongSort entries in
-// an LDS bitonic network; longer lists by ranking every entry against all
-// others through the free sort buffers (quadratic, for rare extreme lists).
+// Lists of more than kWaveSortMax entries, taken in launch order (longest
+// first, so a block stops at the first shorter list): up to kLongSort
+// entries in an LDS bitonic network; longer lists by ranking every entry
+// against all others through the free sort buffers (quadratic, for rare
+// extreme lists).
 constexpr int kLongSort = 4096;
 constexpr int kLongBlocks = 4096;
 constexpr int kShortBlocks = 16384;
@@ -548,8 +631,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
   for (int64_t b = blockIdx.x; b < T; b += gridDim.x) {
     const uint4 ti = tinfo[b];
     const uint32_t beg = ti.y, len = ti.z - ti.y;
-    if (len < 64u) break;
-    if (len == 64u) continue;
+    if (len <= kWaveSortMax) break;
     if (len <= (uint32_t)kLongSort) {
       uint32_t P = 128u;
       while (P < len) P <<= 1;
