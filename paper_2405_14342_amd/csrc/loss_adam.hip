@@ -369,16 +369,18 @@ __global__ __launch_bounds__(64) void k_slot_sums_long(const uint32_t* __restric
 // Projection adjoint of surfel i summed over the batch's views: each visible
 // (view, surfel) slot's gradient sum is chained through the projection of
 // that view and accumulated.  vals[11 + C]: dL/d(z, q, s, alpha, rgb, sem)
-// w.r.t. the activated values.
+// w.r.t. the activated values; alpha is the activated opacity the forward
+// used.
 template <int C>
 __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ views, int V,
                                              int N, float eps, float x, float y, float z,
-                                             const float q[4], float sx, float sy,
+                                             const float q[4], float sx, float sy, float alpha,
                                              const uint32_t* __restrict__ pos, int64_t scap,
                                              const float* __restrict__ ssum,
                                              const float4* __restrict__ rec, float* vals) {
   constexpr int GSC = ((10 + C) + 3) & ~3;
   constexpr int Q = GSC / 4;
+  const float ha = -0.5f * alpha;
   float dz = 0.0f, dq[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsx = 0.0f, dsy = 0.0f, dal = 0.0f;
   float dft[3 + C];
 #pragma unroll
@@ -409,16 +411,19 @@ __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ 
     }
     // this view's contribution first, then one add per component into the
     // running sum, so summing views here or across calls gives the same bits
-    // the records hold moments of dL/dq over the pixel offsets (dx, dy):
-    // with the conic the forward used, du = -(2A m_x + 2B m_y),
-    // dv = -(2C m_y + 2B m_x), dA = m_xx, dB = 2 m_xy, dC = m_yy
+    // the records hold moments of gda = dL/d(alpha) per pixel over the
+    // pixel offsets (dx, dy); dL/dq = -(alpha / 2) gda, so the moments of
+    // dL/dq are m = -(alpha / 2) times them, and with the conic the forward
+    // used du = -(2A m_x + 2B m_y), dv = -(2C m_y + 2B m_x), dA = m_xx,
+    // dB = 2 m_xy, dC = m_yy
     const float4 cn = rec[2 * slot + 1];
+    const float mx = ha * rg[0], my = ha * rg[1];
     const float A2 = 2.0f * cn.x, B2 = 2.0f * cn.y, C2 = 2.0f * cn.z;
-    const float du = -(A2 * rg[0] + B2 * rg[1]);
-    const float dv = -(C2 * rg[1] + B2 * rg[0]);
+    const float du = -(A2 * mx + B2 * my);
+    const float dv = -(C2 * my + B2 * mx);
     float dzv = 0.0f, dqv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsxv = 0.0f, dsyv = 0.0f;
-    proj_adjoint(views[v], eps, x, y, z, q, sx, sy, du, dv, rg[2], 2.0f * rg[3], rg[4], rg[6], dzv,
-                 dqv, dsxv, dsyv);
+    proj_adjoint(views[v], eps, x, y, z, q, sx, sy, du, dv, ha * rg[2], 2.0f * (ha * rg[3]),
+                 ha * rg[4], rg[6], dzv, dqv, dsxv, dsyv);
     dz += dzv;
 #pragma unroll
     for (int c = 0; c < 4; ++c) dq[c] += dqv[c];
@@ -439,15 +444,15 @@ template <int C>
 __global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
     const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
     const float* __restrict__ py, const float* __restrict__ pz, const float* __restrict__ pq,
-    const float* __restrict__ ps,
+    const float* __restrict__ ps, const float* __restrict__ pa,
     const uint32_t* __restrict__ pos, int64_t scap, const float* __restrict__ ssum,
     const float4* __restrict__ rec, float* __restrict__ grads, int accumulate) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   const float q[4] = {pq[i], pq[N + i], pq[2 * (size_t)N + i], pq[3 * (size_t)N + i]};
   float vals[11 + C];
-  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], pos, scap,
-                  ssum, rec, vals);
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], pa[i], pos,
+                  scap, ssum, rec, vals);
   const size_t Nn = (size_t)N;
 #pragma unroll
   for (int r = 0; r < 11 + C; ++r) {
@@ -473,8 +478,8 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
   const size_t Nn = (size_t)N;
   const float q[4] = {P[Nn + i], P[2 * Nn + i], P[3 * Nn + i], P[4 * Nn + i]};
   float vals[11 + C];
-  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], pos,
-                  scap, ssum, rec, vals);
+  surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], a_act[i],
+                  pos, scap, ssum, rec, vals);
   if (dzr) vals[0] += dzr[i];
   if (grads_out) {
 #pragma unroll
@@ -492,7 +497,7 @@ void proj_bwd_launch(const Layout& L, void* ws, const rogs_surfels* s, float* gr
                      hipStream_t st) {
   hipLaunchKernelGGL((k_proj_bwd<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, s->x, s->y, s->z, s->q,
-                     s->s, at<const uint32_t>(ws, L.o_pos),
+                     s->s, s->alpha, at<const uint32_t>(ws, L.o_pos),
                      L.scap, at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), grads,
                      acc ? 1 : 0);
 }

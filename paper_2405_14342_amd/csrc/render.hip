@@ -284,8 +284,9 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
 #pragma clang fp contract(off)
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
-  // per pair: sum dq dx, sum dq dy, sum dq dx^2, sum dq dx dy, sum dq dy^2
-  // (dq = dL/dq of the quadratic form), dalpha, dtz, drgb[3], dsem[C]
+  // per pair: sum gda dx, sum gda dy, sum gda dx^2, sum gda dx dy,
+  // sum gda dy^2 (gda = dL/d(alpha) per pixel; dL/dq = -(alpha / 2) gda),
+  // dalpha = sum gda, dtz, drgb[3], dsem[C]
   constexpr int NV = 10 + C;
   constexpr int NR = 6;                       // reduced across the wave
   constexpr int NFB = (F + 1 + 15) / 16;
@@ -374,8 +375,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
         for (int k = 0; k < PPL; ++k) {
           const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
           const float araw = al * g;
-          const bool clamped = araw > amax;
-          const float a = clamped ? amax : araw;
+          const float a = clamp_alpha(araw, amax);
           const float w = a * T[k];
           wrow[k * 64] = w;
           float gf = kDA ? Gv[k][F] * (tz - t0[k]) : 0.0f;
@@ -383,33 +383,35 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           for (int f = 0; f < F; ++f) gf = __builtin_fmaf(Gv[k][f], fv[f], gf);
           const float om = 1.0f - a;
           const float inv = __builtin_amdgcn_rcpf(om);
-          const float suffix = __builtin_fmaf(-w, gf, GO[k] - Spre[k]);
+          // the suffix G.O - sum over entries up to this one of w gf
+          Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
+          const float suffix = GO[k] - Spre[k];
           float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
           if (kDA) da = __builtin_fmaf(GAf[k], inv, da);
-          Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
-          // the clamp cuts alpha's dependence on g: dL/d(alpha) = g da and
-          // dL/dq = -(alpha g / 2) da where it does not hold, 0 where it does
-          const float gd = clamped ? 0.0f : g;
-          const float dq = (-0.5f * (clamped ? 0.0f : araw)) * da;
-          // moments of dq over the pixel offsets; the projection adjoint
+          // the clamp cuts alpha's dependence on g: gda = g da is dL/d(alpha)
+          // where it does not hold (0 where it does), and dL/dq = -(alpha / 2)
+          // gda, the factor -alpha / 2 being applied to the slot's sums by
+          // the projection adjoint
+          const float gda = araw > amax ? 0.0f : g * da;
+          // moments of gda over the pixel offsets; the projection adjoint
           // turns them into dL/d(u, v, A, B, C) with the pair's conic (the
           // first pixel of a lane sets the values, later ones add to them)
           const float dyk = dy[k];
-          const float dqx = dq * dx, dqy = dq * dyk;
+          const float gx = gda * dx, gy = gda * dyk;
           if (k == 0) {
-            pv[5] = gd * da;
-            pv[0] = dqx;
-            pv[1] = dqy;
-            pv[2] = dqx * dx;
-            pv[3] = dqx * dyk;
-            pv[4] = dqy * dyk;
+            pv[5] = gda;
+            pv[0] = gx;
+            pv[1] = gy;
+            pv[2] = gx * dx;
+            pv[3] = gx * dyk;
+            pv[4] = gy * dyk;
           } else {
-            pv[5] = __builtin_fmaf(gd, da, pv[5]);
-            pv[0] += dqx;
-            pv[1] += dqy;
-            pv[2] = __builtin_fmaf(dqx, dx, pv[2]);
-            pv[3] = __builtin_fmaf(dqx, dyk, pv[3]);
-            pv[4] = __builtin_fmaf(dqy, dyk, pv[4]);
+            pv[5] += gda;
+            pv[0] += gx;
+            pv[1] += gy;
+            pv[2] = __builtin_fmaf(gx, dx, pv[2]);
+            pv[3] = __builtin_fmaf(gx, dyk, pv[3]);
+            pv[4] = __builtin_fmaf(gy, dyk, pv[4]);
           }
           T[k] *= om;
         }
