@@ -348,76 +348,70 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
       float* wrow = s_w + (j & 15) * WS + lane;
       float dy[PPL], q[PPL];
       bool hit[PPL];
-      bool any = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         dy[k] = pixel_offset(pyc[k], r0.y, r0.w);
         q[k] = pixel_q32(A, B2, Cc, dx, dy[k]);
         hit[k] = idx < nl[k] && q[k] <= qcut;
-        any = any || hit[k];
       }
-      if (!__any(any)) {            // no pixel of the tile reached by this pair
-        if (writer) gpair[(size_t)e * GS + my_comp] = 0.0f;
+      float fv[FS4 * 4];
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) wrow[k * 64] = 0.0f;
-      } else {
-        float fv[FS4 * 4];
-#pragma unroll
-        for (int f = 0; f < FS4; ++f) {
-          const float4 t4 = s_f[j * FS4 + f];
-          fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
-        }
-        const float al = fv[F];
-        // Lanes whose pixel the pair does not reach run the same arithmetic
-        // with g = 0: alpha = w = 0, T and the prefix unchanged, terms +-0.
-        float pv[NR];
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-          const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
-          const float araw = al * g;
-          const float a = clamp_alpha(araw, amax);
-          const float w = a * T[k];
-          wrow[k * 64] = w;
-          float gf = kDA ? Gv[k][F] * (tz - t0[k]) : 0.0f;
-#pragma unroll
-          for (int f = 0; f < F; ++f) gf = __builtin_fmaf(Gv[k][f], fv[f], gf);
-          const float om = 1.0f - a;
-          const float inv = __builtin_amdgcn_rcpf(om);
-          // the suffix G.O - sum over entries up to this one of w gf
-          Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
-          const float suffix = GO[k] - Spre[k];
-          float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
-          if (kDA) da = __builtin_fmaf(GAf[k], inv, da);
-          // the clamp cuts alpha's dependence on g: gda = g da is dL/d(alpha)
-          // where it does not hold (0 where it does), and dL/dq = -(alpha / 2)
-          // gda, the factor -alpha / 2 being applied to the slot's sums by
-          // the projection adjoint
-          const float gda = araw > amax ? 0.0f : g * da;
-          // moments of gda over the pixel offsets; the projection adjoint
-          // turns them into dL/d(u, v, A, B, C) with the pair's conic (the
-          // first pixel of a lane sets the values, later ones add to them)
-          const float dyk = dy[k];
-          const float gx = gda * dx, gy = gda * dyk;
-          if (k == 0) {
-            pv[5] = gda;
-            pv[0] = gx;
-            pv[1] = gy;
-            pv[2] = gx * dx;
-            pv[3] = gx * dyk;
-            pv[4] = gy * dyk;
-          } else {
-            pv[5] += gda;
-            pv[0] += gx;
-            pv[1] += gy;
-            pv[2] = __builtin_fmaf(gx, dx, pv[2]);
-            pv[3] = __builtin_fmaf(gx, dyk, pv[3]);
-            pv[4] = __builtin_fmaf(gy, dyk, pv[4]);
-          }
-          T[k] *= om;
-        }
-        const float tot = wave_reduce_scatter<NR>(pv, lane);
-        if (writer) gpair[(size_t)e * GS + my_comp] = tot;
+      for (int f = 0; f < FS4; ++f) {
+        const float4 t4 = s_f[j * FS4 + f];
+        fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
       }
+      const float al = fv[F];
+      // Lanes whose pixel the pair does not reach run the same arithmetic
+      // with g = 0: alpha = w = 0, T and the prefix unchanged, terms +-0 (a
+      // pair that reaches no pixel of the tile gets a zero record this way;
+      // a branch around it would copy T and the prefix on every entry).
+      float pv[NR];
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
+        const float araw = al * g;
+        const float a = clamp_alpha(araw, amax);
+        const float w = a * T[k];
+        wrow[k * 64] = w;
+        float gf = kDA ? Gv[k][F] * (tz - t0[k]) : 0.0f;
+#pragma unroll
+        for (int f = 0; f < F; ++f) gf = __builtin_fmaf(Gv[k][f], fv[f], gf);
+        const float om = 1.0f - a;
+        const float inv = __builtin_amdgcn_rcpf(om);
+        // the suffix G.O - sum over entries up to this one of w gf
+        Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
+        const float suffix = GO[k] - Spre[k];
+        float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
+        if (kDA) da = __builtin_fmaf(GAf[k], inv, da);
+        // the clamp cuts alpha's dependence on g: gda = g da is dL/d(alpha)
+        // where it does not hold (0 where it does), and dL/dq = -(alpha / 2)
+        // gda, the factor -alpha / 2 being applied to the slot's sums by
+        // the projection adjoint
+        const float gda = araw > amax ? 0.0f : g * da;
+        // moments of gda over the pixel offsets; the projection adjoint
+        // turns them into dL/d(u, v, A, B, C) with the pair's conic (the
+        // first pixel of a lane sets the values, later ones add to them)
+        const float dyk = dy[k];
+        const float gx = gda * dx, gy = gda * dyk;
+        if (k == 0) {
+          pv[5] = gda;
+          pv[0] = gx;
+          pv[1] = gy;
+          pv[2] = gx * dx;
+          pv[3] = gx * dyk;
+          pv[4] = gy * dyk;
+        } else {
+          pv[5] += gda;
+          pv[0] += gx;
+          pv[1] += gy;
+          pv[2] = __builtin_fmaf(gx, dx, pv[2]);
+          pv[3] = __builtin_fmaf(gx, dyk, pv[3]);
+          pv[4] = __builtin_fmaf(gy, dyk, pv[4]);
+        }
+        T[k] *= om;
+      }
+      const float tot = wave_reduce_scatter<NR>(pv, lane);
+      if (writer) gpair[(size_t)e * GS + my_comp] = tot;
       if ((j & 15) == 15 || j == cnt - 1) {
         __syncthreads();
         feature_gemm<C, PPL>(s_w, s_e + (j & ~15), (j & 15) + 1, bG, gpair, GS);
