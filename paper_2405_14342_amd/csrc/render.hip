@@ -87,8 +87,10 @@ __device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views,
 }
 
 // Stages list entries [base, base + cnt) of the tile in LDS: the projection
-// record (with 2B in place of B) and the surfel's feature record.  With kE,
-// returns this lane's emission index (lane < cnt).
+// record (with 2B in place of B) and the surfel's feature record, entry j at
+// s_r0[j (2 + FS4)], s_r1[j (2 + FS4)] and s_f[j (2 + FS4) + f] of one
+// interleaved array (so one address serves all of an entry's reads).  With
+// kE, returns this lane's emission index (lane < cnt).
 template <int FS4, bool kE>
 __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32_t sbase,
                                                   const uint32_t* __restrict__ vals,
@@ -101,12 +103,12 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
   if (lane < cnt) {
     if (kE) e = vals[base + lane];
     const uint32_t slot = spair[base + lane];
-    s_r0[lane] = rec[2 * (size_t)slot];
+    s_r0[lane * (2 + FS4)] = rec[2 * (size_t)slot];
     const float4 r1 = rec[2 * (size_t)slot + 1];
-    s_r1[lane] = make_float4(r1.x, 2.0f * r1.y, r1.z, r1.w);     // A, 2B, C, t_z
+    s_r1[lane * (2 + FS4)] = make_float4(r1.x, 2.0f * r1.y, r1.z, r1.w);   // A, 2B, C, t_z
     const uint32_t i = slot - sbase;
 #pragma unroll
-    for (int f = 0; f < FS4; ++f) s_f[lane * FS4 + f] = feat[(size_t)i * FS4 + f];
+    for (int f = 0; f < FS4; ++f) s_f[lane * (2 + FS4) + f] = feat[(size_t)i * FS4 + f];
   }
   return e;
 }
@@ -152,11 +154,11 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
     if (base == tg.rbeg) e_first = e;
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
-      const float4 r0 = s_r0[j], r1 = s_r1[j];   // u_hi v_hi u_lo v_lo | A 2B C tz
+      const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];   // u_hi v_hi u_lo v_lo | A 2B C tz
       float fv[FS4 * 4];
 #pragma unroll
       for (int f = 0; f < FS4; ++f) {
-        const float4 t4 = s_f[j * FS4 + f];
+        const float4 t4 = s_f[j * (2 + FS4) + f];
         fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
       }
       const float al = fv[F];
@@ -180,7 +182,7 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
             t0[k] = fminf(t0[k], r1.w);
             acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
           }
-          T[k] *= (1.0f - a);
+          T[k] -= w;                   // T (1 - alpha)
           if (T[k] < teps) {
             done[k] = true;
             nl[k] = base - tg.rbeg + (uint32_t)j + 1u;
@@ -342,7 +344,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
     for (int j = 0; j < cnt; ++j) {
       const uint32_t idx = base - tg.rbeg + (uint32_t)j;
       const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)e_mine, j);
-      const float4 r0 = s_r0[j], r1 = s_r1[j];
+      const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];
       const float A = r1.x, B2 = r1.y, Cc = r1.z, tz = r1.w;
       const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
       float* wrow = s_w + (j & 15) * WS + lane;
@@ -357,7 +359,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
       float fv[FS4 * 4];
 #pragma unroll
       for (int f = 0; f < FS4; ++f) {
-        const float4 t4 = s_f[j * FS4 + f];
+        const float4 t4 = s_f[j * (2 + FS4) + f];
         fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
       }
       const float al = fv[F];
@@ -408,7 +410,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           pv[3] = __builtin_fmaf(gx, dyk, pv[3]);
           pv[4] = __builtin_fmaf(gy, dyk, pv[4]);
         }
-        T[k] *= om;
+        T[k] -= w;                       // as in the forward
       }
       const float tot = wave_reduce_scatter<NR>(pv, lane);
       if (writer) gpair[(size_t)e * GS + my_comp] = tot;
@@ -442,8 +444,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;           // output channels
-  __shared__ float4 s_r0[KS], s_r1[KS];
-  __shared__ float4 s_f[KS * FS4];
+  // staged entries: projection record, conic, features, one record per entry
+  __shared__ float4 s_st[KS * (2 + FS4)];
+  float4* const s_r0 = s_st;
+  float4* const s_r1 = s_st + 1;
+  float4* const s_f = s_st + 2;
   const TileGeom tg = tile_geom(views, N, tinfo);
   float T[PPL], acc[PPL][F + 1], pyc[PPL];
   uint32_t nl[PPL];
@@ -495,8 +500,11 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
-  __shared__ float4 s_r0[KS], s_r1[KS];
-  __shared__ float4 s_f[KS * FS4];
+  // staged entries: projection record, conic, features, one record per entry
+  __shared__ float4 s_st[KS * (2 + FS4)];
+  float4* const s_r0 = s_st;
+  float4* const s_r1 = s_st + 1;
+  float4* const s_f = s_st + 2;
   __shared__ float4 s_w4[bwd_lds_floats<C, PPL>() / 4];
   __shared__ uint32_t s_e[KS];
   const TileGeom tg = tile_geom(views, N, tinfo);
@@ -547,8 +555,11 @@ __global__ __launch_bounds__(64) void k_render_step(
     int GS, FusedLoss fl) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
-  __shared__ float4 s_r0[KS], s_r1[KS];
-  __shared__ float4 s_f[KS * FS4];
+  // staged entries: projection record, conic, features, one record per entry
+  __shared__ float4 s_st[KS * (2 + FS4)];
+  float4* const s_r0 = s_st;
+  float4* const s_r1 = s_st + 1;
+  float4* const s_f = s_st + 2;
   __shared__ float4 s_w4[bwd_lds_floats<C, PPL>() / 4];
   __shared__ uint32_t s_e[KS];
   const int lane = threadIdx.x;
