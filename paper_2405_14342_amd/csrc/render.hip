@@ -308,6 +308,8 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
     GAf[k] = kDA ? __builtin_fmaf(t0[k], Gv[k][F], Gv[k][F + 1]) * Tf[k] : 0.0f;
   }
   for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, (uint32_t)__shfl_xor((int)maxn, o, 64));
+  // every lane holds the maximum: as a scalar the list loop is scalar control
+  maxn = (uint32_t)__builtin_amdgcn_readfirstlane((int)maxn);
   const uint32_t stop = tg.rbeg + min(maxn, tg.rend - tg.rbeg);
   // B operand of feature_gemm: gamma[pixel][n] for pixel kk * 64 + kgrp * 16
   // + c, transposed through LDS (pixel-major rows of 16 * NFB + 1 floats);
@@ -488,8 +490,12 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 
 // Backward compositing of the batch from the output gradient G (5 + C planes
 // per view), the outputs, T_final and n_last.
+// Register budgets of the backward kernels: 6 waves per SIMD (7 with 16-entry
+// staging, whose LDS block allows 7); the compiler meets them without
+// spilling or extra instructions, and the extra waves hide LDS and memory
+// latency of the VALU-bound loops.
 template <int C, int PPL, int KS>
-__global__ __launch_bounds__(64) void k_render_bwd(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KS <= 16 ? 7 : 6))) void k_render_bwd(
     const ViewDev* __restrict__ views, int V, int N, float qcut, float amax,
     const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
@@ -546,8 +552,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(
 // The fused step's compositing: forward, the loss of Eq. 7-9 and 12 per pixel
 // (its gradient, G.O, and this tile's share of the loss and of dL/d(a, b)),
 // then the backward, in one kernel per tile.
+// Register budget as for k_render_bwd.
 template <int C, int PPL, int KS>
-__global__ __launch_bounds__(64) void k_render_step(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KS <= 16 ? 7 : 6))) void k_render_step(
     const ViewDev* __restrict__ views, int V, int N, float qcut, float amax,
     float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
