@@ -185,8 +185,9 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
 // Per-view mask counts from the projection's side blocks (exact integer
 // sums): per view, the block's threads stride over the chunks, then a wave
 // sum and the waves' totals.  blockDim.x is a multiple of 64, at most 1024.
-__device__ __forceinline__ void sum_mask_parts(const uint32_t* __restrict__ mpart, int nmb, int V,
-                                               uint32_t* __restrict__ mcount) {
+// One block for all views (small batches, inside k_scan_part) ...
+__device__ __forceinline__ void sum_mask_parts_all(const uint32_t* __restrict__ mpart, int nmb,
+                                                   int V, uint32_t* __restrict__ mcount) {
   __shared__ uint32_t s_t[16];
   for (int v = 0; v < V; ++v) {
     uint32_t t = 0;
@@ -203,13 +204,24 @@ __device__ __forceinline__ void sum_mask_parts(const uint32_t* __restrict__ mpar
   }
 }
 
-__global__ void k_check_cap(uint32_t* misc, int64_t cap, int64_t scap,
-                            const uint32_t* __restrict__ mpart, int nmb, int V,
-                            uint32_t* __restrict__ mcount) {
+// ... or one 64-lane block per view (view v's count).
+__device__ __forceinline__ void sum_mask_parts(const uint32_t* __restrict__ mpart, int nmb, int v,
+                                               uint32_t* __restrict__ mcount) {
+  uint32_t t = 0;
+  for (int c = threadIdx.x; c < nmb; c += 64) t += mpart[(size_t)v * nmb + c];
+  t = wave_sum_u32(t);
+  if (threadIdx.x == 0) mcount[v] = t;
+}
+
+// Grid: one 64-lane block per view (at least one block).  Block 0 sets the
+// overflow flag; with mpart, block v sums view v's mask count.
+__global__ __launch_bounds__(64) void k_check_cap(uint32_t* misc, int64_t cap, int64_t scap,
+                                                  const uint32_t* __restrict__ mpart, int nmb,
+                                                  int V, uint32_t* __restrict__ mcount) {
   if (threadIdx.x == 0 && blockIdx.x == 0)
     misc[kMiscOverflow] =
         ((int64_t)misc[kMiscPairs] > cap || (int64_t)misc[kMiscVisible] > scap) ? 1u : 0u;
-  if (mpart) sum_mask_parts(mpart, nmb, V, mcount);
+  if (mpart && (int)blockIdx.x < V) sum_mask_parts(mpart, nmb, (int)blockIdx.x, mcount);
 }
 
 // ------------------------------------------------------------ generic scan
@@ -367,7 +379,7 @@ __global__ __launch_bounds__(1024) void k_scan_part(uint32_t* part, uint32_t* pa
                                                     int V, uint32_t* __restrict__ mcount,
                                                     int check) {
   if (blockIdx.x == 2) {
-    sum_mask_parts(mpart, nmb, V, mcount);
+    sum_mask_parts_all(mpart, nmb, V, mcount);
   } else {
     uint32_t* a = blockIdx.x == 0 ? part : partv;
     block_scan_small(a, a, n, misc + (blockIdx.x == 0 ? kMiscPairs : kMiscVisible));
@@ -448,8 +460,8 @@ void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts
            misc + kMiscPairs, at<uint32_t>(ws, L.o_parttmp), st);
   scan_u32(at<uint32_t>(ws, L.o_partv), at<uint32_t>(ws, L.o_partv), (int64_t)L.V * L.nb,
            misc + kMiscVisible, at<uint32_t>(ws, L.o_parttmp), st);
-  hipLaunchKernelGGL(k_check_cap, dim3(1), dim3(64), 0, st, misc, L.cap, L.scap, mpart, nmb, L.V,
-                     mcount);
+  hipLaunchKernelGGL(k_check_cap, dim3((unsigned)std::max(1, mpart ? L.V : 1)), dim3(64), 0, st,
+                     misc, L.cap, L.scap, mpart, nmb, L.V, mcount);
 }
 
 }  // namespace rogs
