@@ -601,6 +601,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KS <= 16 ? 7
     }
     lmask[k] = m != 0;
   }
+  if (tg.rend == tg.rbeg) {
+    // a tile without entries: its pixels' outputs are 0 and there is nothing
+    // to differentiate, so only its shares of the loss and of dL/db are
+    // formed (dL/da is 0 at a zero output)
+    float l = 0.0f, dbl = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k)
+      pixel_loss_empty<C>(tv[k], lmask[k] ? lv.wc : 0.0f, lmask[k] ? lv.ws : 0.0f, lv.ea, lv.b,
+                          l, dbl);
+    const float lp[3] = {l, 0.0f, dbl};
+    const float tot = wave_reduce_scatter<3>(lp, lane);
+    const int c = rs_comp(lane, 3);
+    if (c >= 0 && (lane & rs_dup_bits(3)) == 0) fl.part[3 * (size_t)tg.gt + c] = tot;
+    return;
+  }
   {
     float T[PPL], acc[PPL][F + 1];
     uint32_t nlf[PPL];

@@ -518,6 +518,25 @@ __device__ __forceinline__ void pixel_loss(const float* o, const float* t, int l
   for (int c = 0; c < C; ++c) g[3 + c] = ws * (sv[c] * inv - ((c == label) ? 1.0f : 0.0f));
 }
 
+// pixel_loss for a pixel whose outputs are all 0 (a tile without entries):
+// the loss and its dL/db term with every step rounded as pixel_loss rounds
+// it at o = 0 (dL/da is +-0 there and dL/dO is not formed).
+template <int C>
+__device__ __forceinline__ void pixel_loss_empty(const float* t, float wc, float ws, float ea,
+                                                 float b, float& l, float& db) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float r = (ea * 0.0f + b) - t[c];
+    const float sg = (r > 0.0f) ? 1.0f : ((r < 0.0f) ? -1.0f : 0.0f);
+    l += wc * fabsf(r);
+    db += wc * sg;
+  }
+  // softmax of C zeros: the exponentials are exactly 1 and their sum C
+  constexpr float kLn2 = 0.69314718055994531f;
+  l += ws * (__builtin_amdgcn_logf((float)C) * kLn2);
+}
+
 // Per-view loss constants (uniform over a view).
 struct LossView {
   float wc, ws, ea, b;
