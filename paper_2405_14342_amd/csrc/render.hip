@@ -490,12 +490,18 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 
 // Backward compositing of the batch from the output gradient G (5 + C planes
 // per view), the outputs, T_final and n_last.
-// Register budgets of the backward kernels: 6 waves per SIMD (7 with 16-entry
-// staging, whose LDS block allows 7); the compiler meets them without
-// spilling or extra instructions, and the extra waves hide LDS and memory
-// latency of the VALU-bound loops.
+// Register budgets of the backward kernels: with one pixel per lane, up to 8
+// classes and 16- or 32-entry staging, 7 or 6 waves per SIMD (what the LDS
+// block allows); the compiler meets them without spilling or extra
+// instructions, and the extra waves hide LDS and memory latency of the
+// VALU-bound loops.  Other instances keep the compiler's own budget (1).
 template <int C, int PPL, int KS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KS <= 16 ? 7 : 6))) void k_render_bwd(
+constexpr int kWavesPerEu() {
+  return (PPL == 1 && C <= 8 && KS <= 32) ? (KS <= 16 ? 7 : 6) : 1;
+}
+template <int C, int PPL, int KS>
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_bwd(
     const ViewDev* __restrict__ views, int V, int N, float qcut, float amax,
     const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
@@ -554,7 +560,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KS <= 16 ? 7
 // then the backward, in one kernel per tile.
 // Register budget as for k_render_bwd.
 template <int C, int PPL, int KS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KS <= 16 ? 7 : 6))) void k_render_step(
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_step(
     const ViewDev* __restrict__ views, int V, int N, float qcut, float amax,
     float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
