@@ -163,36 +163,41 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
       }
       const float al = fv[F];
       const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
+      // Lanes whose pixel the entry does not reach, or has stopped, run the
+      // same arithmetic with g = 0: w = 0 leaves T and the sums as they are
+      // (T > 0 and every feature is finite), so the result is that of a
+      // branch around the update without its exec-mask bookkeeping.
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        if (done[k]) continue;
         const float dy = pixel_offset(pyc[k], r0.y, r0.w);
         const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
-        if (q <= qcut) {
-          const float g = gauss_weight(q);
-          const float a = clamp_alpha(al * g, amax);
-          const float w = a * T[k];
-          if (ch & ROGS_CH_RGB)
+        const bool hit = !done[k] && q <= qcut;
+        const float g = hit ? gauss_weight(q) : 0.0f;
+        const float a = clamp_alpha(al * g, amax);
+        const float w = a * T[k];
+        if (ch & ROGS_CH_RGB)
 #pragma unroll
-            for (int f = 0; f < 3; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-          if (ch & ROGS_CH_SEM)
+          for (int f = 0; f < 3; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+        if (ch & ROGS_CH_SEM)
 #pragma unroll
-            for (int f = 3; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-          if (kD && (ch & ROGS_CH_D)) {
-            t0[k] = fminf(t0[k], r1.w);
-            acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
-          }
-          T[k] -= w;                   // T (1 - alpha)
-          if (T[k] < teps) {
-            done[k] = true;
-            nl[k] = base - tg.rbeg + (uint32_t)j + 1u;
-          }
+          for (int f = 3; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+        if (kD && (ch & ROGS_CH_D)) {
+          t0[k] = hit ? fminf(t0[k], r1.w) : t0[k];
+          acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
         }
+        T[k] -= w;                     // T (1 - alpha)
+        const bool stop = hit && T[k] < teps;
+        nl[k] = stop ? base - tg.rbeg + (uint32_t)j + 1u : nl[k];
+        done[k] = done[k] || stop;
       }
       bool mine = true;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) mine = mine && done[k];
-      if (__all(mine)) { stop_all = true; break; }
+      // every lane of the wave runs this loop: the ballot is the stop test
+      if (__builtin_amdgcn_ballot_w64(mine) == __builtin_amdgcn_read_exec()) {
+        stop_all = true;
+        break;
+      }
     }
     __syncthreads();
   }
