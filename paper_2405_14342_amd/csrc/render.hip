@@ -225,8 +225,9 @@ __host__ __device__ constexpr int bwd_lds_floats() {
 template <int C, int PPL>
 __device__ __forceinline__ void feature_gemm(const float* s_w, const uint32_t* s_e, int nrows,
                                              const float (&bG)[(3 + C + 1 + 15) / 16][PPL][16],
-                                             float* __restrict__ gpair, int GS) {
+                                             float* __restrict__ gpair) {
   constexpr int F = 3 + C;
+  constexpr uint32_t GS = grad_stride_c(C);
   constexpr int NG = F + 1;
   constexpr int NFB = (NG + 15) / 16;
   constexpr int WS = 64 * PPL + 4;
@@ -284,7 +285,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
                                               uint32_t* s_e, const float* pyc,
                                               const float (*Gv)[3 + C + 2], const float* GO,
                                               const float* Tf, const uint32_t* nl,
-                                              float* __restrict__ gpair, int GS, bool staged,
+                                              float* __restrict__ gpair, bool staged,
                                               uint32_t e_pre, const float* t0) {
   // every multiply-add is written out: the backward rounds the same in the
   // fused step and in the stand-alone backward
@@ -295,6 +296,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
   // sum gda dy^2 (gda = dL/d(alpha) per pixel; dL/dq = -(alpha / 2) gda),
   // dalpha = sum gda, dtz, drgb[3], dsem[C]
   constexpr int NV = 10 + C;
+  constexpr uint32_t GS = grad_stride_c(C);   // floats per record
   constexpr int NR = 6;                       // reduced across the wave
   constexpr int NFB = (F + 1 + 15) / 16;
   constexpr int WS = 64 * PPL + 4;
@@ -339,8 +341,10 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           bG[nb][kk][c] = s_w[(kk * 64 + kgrp * 16 + c) * GR + nb * 16 + mrow];
     __syncthreads();
   }
+  // this lane's column of the reduced values in every record it writes
+  float* const gcol = gpair + (writer ? my_comp : 0);
   for (uint32_t base = tg.rbeg; base < stop; base += KS) {
-    const int cnt = (int)min((uint32_t)KS, stop - base);
+    const int cnt = __builtin_amdgcn_readfirstlane((int)min((uint32_t)KS, stop - base));
     // a list the forward staged whole is still in LDS
     const uint32_t e_mine =
         staged ? e_pre
@@ -348,13 +352,16 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
                                           s_r1, s_f);
     if (lane < KS) s_e[lane] = e_mine;
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
+    // blocks of 16 entries: the per-entry pass, then their feature gradients
+    for (int j0 = 0; j0 < cnt; j0 += 16) {
+    const int j1 = min(j0 + 16, cnt);
+    for (int j = j0; j < j1; ++j) {
       const uint32_t idx = base - tg.rbeg + (uint32_t)j;
       const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)e_mine, j);
       const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];
       const float A = r1.x, B2 = r1.y, Cc = r1.z, tz = r1.w;
       const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
-      float* wrow = s_w + (j & 15) * WS + lane;
+      float* wrow = s_w + (j - j0) * WS + lane;
       float dy[PPL], q[PPL];
       bool hit[PPL];
 #pragma unroll
@@ -420,12 +427,11 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
         T[k] -= w;                       // as in the forward
       }
       const float tot = wave_reduce_scatter<NR>(pv, lane);
-      if (writer) gpair[(size_t)e * GS + my_comp] = tot;
-      if ((j & 15) == 15 || j == cnt - 1) {
-        __syncthreads();
-        feature_gemm<C, PPL>(s_w, s_e + (j & ~15), (j & 15) + 1, bG, gpair, GS);
-        __syncthreads();
-      }
+      if (writer) gcol[(size_t)e * GS] = tot;
+    }
+    __syncthreads();
+    feature_gemm<C, PPL>(s_w, s_e + j0, j1 - j0, bG, gpair);
+    __syncthreads();
     }
     __syncthreads();
   }
@@ -513,7 +519,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_bw
     const float4* __restrict__ rec, const float4* __restrict__ feat, const float* __restrict__ out,
     const float* __restrict__ G, const float* __restrict__ tfin,
     const uint32_t* __restrict__ nlast, const float2* __restrict__ drel,
-    float* __restrict__ gpair, int GS) {
+    float* __restrict__ gpair) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   constexpr int NO = 5 + C;
@@ -556,7 +562,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_bw
     }
   }
   backward_tile<C, PPL, KS, true>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
-                              reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair, GS,
+                              reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl, gpair,
                               false, 0u, t0);
 }
 
@@ -571,7 +577,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_st
     float teps, const uint4* __restrict__ tinfo, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ spair,
     const float4* __restrict__ rec, const float4* __restrict__ feat, float* __restrict__ gpair,
-    int GS, FusedLoss fl) {
+    FusedLoss fl) {
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   // staged entries: projection record, conic, features, one record per entry
@@ -674,7 +680,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_st
     // the fused loss has no depth or alpha term: their gradient rows are zero
     backward_tile<C, PPL, KS, false>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
                                      reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl,
-                                     gpair, GS, len <= (uint32_t)KS, e_first, t0);
+                                     gpair, len <= (uint32_t)KS, e_first, t0);
   }
 }
 
@@ -751,7 +757,7 @@ void bwd_launch(const Layout& L, void* ws, const float* out, const float* G, hip
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat), out, G,
                      at<const float>(ws, L.o_tfin), at<const uint32_t>(ws, L.o_nlast),
-                     at<const float2>(ws, L.o_drel), at<float>(ws, L.o_gpair), L.GS);
+                     at<const float2>(ws, L.o_drel), at<float>(ws, L.o_gpair));
 }
 
 template <int C, int PPL, int KS>
@@ -761,7 +767,7 @@ void step_launch(const Layout& L, void* ws, const FusedLoss& fl, hipStream_t st)
                      L.t_eps, at<const uint4>(ws, L.o_tinfo), at<const uint32_t>(ws, L.o_vals),
                      at<const uint32_t>(ws, L.o_spair),
                      at<const float4>(ws, L.o_rec), at<const float4>(ws, L.o_feat),
-                     at<float>(ws, L.o_gpair), L.GS, fl);
+                     at<float>(ws, L.o_gpair), fl);
 }
 
 // which: 0 forward, 1 backward, 2 fused step

@@ -35,7 +35,9 @@ struct ViewDev {
 // Number of semantic classes with a compiled kernel set.
 inline bool sem_supported(int C) { return (C >= 1 && C <= 8) || C == 16; }
 inline int feat_stride(int C) { return ((4 + C) + 3) & ~3; }      // rgb, sem, alpha; float4-padded
-inline int grad_stride(int C) { return ((10 + C) + 3) & ~3; }     // per-pair gradient record
+// floats per per-pair gradient record: 10 + C values padded to whole float4
+__host__ __device__ constexpr uint32_t grad_stride_c(int C) { return ((10 + C) + 3) & ~3; }
+inline int grad_stride(int C) { return (int)grad_stride_c(C); }
 
 // Layout of one batch inside the caller's workspace (byte offsets).
 struct Layout {
