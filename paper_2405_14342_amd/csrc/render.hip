@@ -121,6 +121,8 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 // lane's emission index in the first staged batch.  ch (ROGS_CH_* bits,
 // uniform): the colour, semantic and depth sums are formed only when
 // selected; T, n_last and the order of operations do not depend on it.
+constexpr int kFwdUnroll = 4;       // forward entries per stop test
+
 template <int C, int PPL, int KS, bool kE, bool kD>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
@@ -135,12 +137,12 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
 #pragma clang fp contract(off)
   constexpr int F = 3 + C;            // composited features besides depth
   constexpr int FS4 = (F + 4) / 4;    // float4 per feature record (features, alpha)
-  bool done[PPL];
+  // a pixel is live while T >= t_eps (T only falls, and t_eps < 1); a pixel
+  // outside the image starts at T = 0, which no update changes
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int py = tg.py0 + k * tg.rows;
-    done[k] = !(tg.px < tg.W && py < tg.H);
-    T[k] = 1.0f;
+    T[k] = (tg.px < tg.W && py < tg.H) ? 1.0f : 0.0f;
     nl[k] = 0;
     if (kD) t0[k] = FLT_MAX;
 #pragma unroll
@@ -153,7 +155,14 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
         stage_entries<FS4, kE>(base, cnt, tg.sbase, vals, spair, rec, feat, s_r0, s_r1, s_f);
     if (base == tg.rbeg) e_first = e;
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
+    // groups of kFwdUnroll entries, the stop test after each group: entries
+    // past a pixel's stop change nothing for it, so the results are those
+    // of a test after every entry
+    for (int j0 = 0; j0 < cnt; j0 += kFwdUnroll) {
+#pragma unroll
+    for (int u = 0; u < kFwdUnroll; ++u) {
+      const int j = j0 + u;
+      if (j >= cnt) break;
       const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];   // u_hi v_hi u_lo v_lo | A 2B C tz
       float fv[FS4 * 4];
 #pragma unroll
@@ -171,7 +180,7 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
       for (int k = 0; k < PPL; ++k) {
         const float dy = pixel_offset(pyc[k], r0.y, r0.w);
         const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
-        const bool hit = !done[k] && q <= qcut;
+        const bool hit = T[k] >= teps && q <= qcut;
         const float g = hit ? gauss_weight(q) : 0.0f;
         const float a = clamp_alpha(al * g, amax);
         const float w = a * T[k];
@@ -185,16 +194,15 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
           t0[k] = hit ? fminf(t0[k], r1.w) : t0[k];
           acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
         }
-        T[k] -= w;                     // T (1 - alpha)
-        const bool stop = hit && T[k] < teps;
-        nl[k] = stop ? base - tg.rbeg + (uint32_t)j + 1u : nl[k];
-        done[k] = done[k] || stop;
+        const float Tn = T[k] - w;     // T (1 - alpha)
+        nl[k] = (hit && Tn < teps) ? base - tg.rbeg + (uint32_t)j + 1u : nl[k];
+        T[k] = Tn;
       }
-      bool mine = true;
+    }
+      bool live = false;
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) mine = mine && done[k];
-      // every lane of the wave runs this loop: the ballot is the stop test
-      if (__builtin_amdgcn_ballot_w64(mine) == __builtin_amdgcn_read_exec()) {
+      for (int k = 0; k < PPL; ++k) live = live || T[k] >= teps;
+      if (__builtin_amdgcn_ballot_w64(live) == 0) {
         stop_all = true;
         break;
       }
