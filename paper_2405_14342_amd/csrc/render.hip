@@ -160,45 +160,47 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
     // of a test after every entry
     for (int j0 = 0; j0 < cnt; j0 += kFwdUnroll) {
 #pragma unroll
-    for (int u = 0; u < kFwdUnroll; ++u) {
-      const int j = j0 + u;
-      if (j >= cnt) break;
-      const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];   // u_hi v_hi u_lo v_lo | A 2B C tz
-      float fv[FS4 * 4];
+      for (int u = 0; u < kFwdUnroll; ++u) {
+        const int j = j0 + u;
+        if (j >= cnt) break;
+        const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];   // u_hi v_hi u_lo v_lo | A 2B C tz
+        float fv[FS4 * 4];
 #pragma unroll
-      for (int f = 0; f < FS4; ++f) {
-        const float4 t4 = s_f[j * (2 + FS4) + f];
-        fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
-      }
-      const float al = fv[F];
-      const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
-      // Lanes whose pixel the entry does not reach, or has stopped, run the
-      // same arithmetic with g = 0: w = 0 leaves T and the sums as they are
-      // (T > 0 and every feature is finite), so the result is that of a
-      // branch around the update without its exec-mask bookkeeping.
-#pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        const float dy = pixel_offset(pyc[k], r0.y, r0.w);
-        const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
-        const bool hit = T[k] >= teps && q <= qcut;
-        const float g = hit ? gauss_weight(q) : 0.0f;
-        const float a = clamp_alpha(al * g, amax);
-        const float w = a * T[k];
-        if (ch & ROGS_CH_RGB)
-#pragma unroll
-          for (int f = 0; f < 3; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-        if (ch & ROGS_CH_SEM)
-#pragma unroll
-          for (int f = 3; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-        if (kD && (ch & ROGS_CH_D)) {
-          t0[k] = hit ? fminf(t0[k], r1.w) : t0[k];
-          acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
+        for (int f = 0; f < FS4; ++f) {
+          const float4 t4 = s_f[j * (2 + FS4) + f];
+          fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
         }
-        const float Tn = T[k] - w;     // T (1 - alpha)
-        nl[k] = (hit && Tn < teps) ? base - tg.rbeg + (uint32_t)j + 1u : nl[k];
-        T[k] = Tn;
+        const float al = fv[F];
+        const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
+        // Lanes whose pixel the entry does not reach, or has stopped, run the
+        // same arithmetic with g = 0: w = 0 leaves T and the sums as they are
+        // (T >= 0 and every feature is finite), so the result is that of a
+        // branch around the update without its exec-mask bookkeeping.
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          const float dy = pixel_offset(pyc[k], r0.y, r0.w);
+          const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
+          const bool live = T[k] >= teps;
+          const bool hit = live && q <= qcut;
+          const float g = hit ? gauss_weight(q) : 0.0f;
+          const float a = clamp_alpha(al * g, amax);
+          const float w = a * T[k];
+          if (ch & ROGS_CH_RGB)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+          if (ch & ROGS_CH_SEM)
+#pragma unroll
+            for (int f = 3; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+          if (kD && (ch & ROGS_CH_D)) {
+            t0[k] = hit ? fminf(t0[k], r1.w) : t0[k];
+            acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
+          }
+          T[k] -= w;                     // T (1 - alpha)
+          // entries seen while live: at the entry that stops the pixel, its
+          // position in the list plus one
+          nl[k] += live ? 1u : 0u;
+        }
       }
-    }
       bool live = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) live = live || T[k] >= teps;
@@ -349,8 +351,12 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
           bG[nb][kk][c] = s_w[(kk * 64 + kgrp * 16 + c) * GR + nb * 16 + mrow];
     __syncthreads();
   }
-  // this lane's column of the reduced values in every record it writes
-  float* const gcol = gpair + (writer ? my_comp : 0);
+  // this lane's column of the reduced values in every record: lanes that
+  // hold a copy of a component write the same bits to the same address, and
+  // where the record has padding, the lanes without a component write
+  // theirs into its first padding column, so the store needs no lane mask
+  constexpr bool kPadCol = GS > (uint32_t)NV;
+  float* const gcol = gpair + (my_comp >= 0 ? my_comp : (kPadCol ? NV : 0));
   for (uint32_t base = tg.rbeg; base < stop; base += KS) {
     const int cnt = __builtin_amdgcn_readfirstlane((int)min((uint32_t)KS, stop - base));
     // a list the forward staged whole is still in LDS
@@ -362,84 +368,90 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
     __syncthreads();
     // blocks of 16 entries: the per-entry pass, then their feature gradients
     for (int j0 = 0; j0 < cnt; j0 += 16) {
-    const int j1 = min(j0 + 16, cnt);
-    for (int j = j0; j < j1; ++j) {
-      const uint32_t idx = base - tg.rbeg + (uint32_t)j;
-      const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)e_mine, j);
-      const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];
-      const float A = r1.x, B2 = r1.y, Cc = r1.z, tz = r1.w;
-      const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
-      float* wrow = s_w + (j - j0) * WS + lane;
-      float dy[PPL], q[PPL];
-      bool hit[PPL];
+      const int j1 = min(j0 + 16, cnt);
+      // two entries per iteration (immediate LDS offsets, half the loop
+      // bookkeeping); the second is skipped past the block's end
+      auto entry = [&](const int j) {
+        const uint32_t idx = base - tg.rbeg + (uint32_t)j;
+        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)e_mine, j);
+        const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];
+        const float A = r1.x, B2 = r1.y, Cc = r1.z, tz = r1.w;
+        const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
+        float* wrow = s_w + (j - j0) * WS + lane;
+        float dy[PPL], q[PPL];
+        bool hit[PPL];
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        dy[k] = pixel_offset(pyc[k], r0.y, r0.w);
-        q[k] = pixel_q32(A, B2, Cc, dx, dy[k]);
-        hit[k] = idx < nl[k] && q[k] <= qcut;
-      }
-      float fv[FS4 * 4];
-#pragma unroll
-      for (int f = 0; f < FS4; ++f) {
-        const float4 t4 = s_f[j * (2 + FS4) + f];
-        fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
-      }
-      const float al = fv[F];
-      // Lanes whose pixel the pair does not reach run the same arithmetic
-      // with g = 0: alpha = w = 0, T and the prefix unchanged, terms +-0 (a
-      // pair that reaches no pixel of the tile gets a zero record this way;
-      // a branch around it would copy T and the prefix on every entry).
-      float pv[NR];
-#pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
-        const float araw = al * g;
-        const float a = clamp_alpha(araw, amax);
-        const float w = a * T[k];
-        wrow[k * 64] = w;
-        float gf = kDA ? Gv[k][F] * (tz - t0[k]) : 0.0f;
-#pragma unroll
-        for (int f = 0; f < F; ++f) gf = __builtin_fmaf(Gv[k][f], fv[f], gf);
-        const float om = 1.0f - a;
-        const float inv = __builtin_amdgcn_rcpf(om);
-        // the suffix G.O - sum over entries up to this one of w gf
-        Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
-        const float suffix = GO[k] - Spre[k];
-        float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
-        if (kDA) da = __builtin_fmaf(GAf[k], inv, da);
-        // the clamp cuts alpha's dependence on g: gda = g da is dL/d(alpha)
-        // where it does not hold (0 where it does), and dL/dq = -(alpha / 2)
-        // gda, the factor -alpha / 2 being applied to the slot's sums by
-        // the projection adjoint
-        const float gda = araw > amax ? 0.0f : g * da;
-        // moments of gda over the pixel offsets; the projection adjoint
-        // turns them into dL/d(u, v, A, B, C) with the pair's conic (the
-        // first pixel of a lane sets the values, later ones add to them)
-        const float dyk = dy[k];
-        const float gx = gda * dx, gy = gda * dyk;
-        if (k == 0) {
-          pv[5] = gda;
-          pv[0] = gx;
-          pv[1] = gy;
-          pv[2] = gx * dx;
-          pv[3] = gx * dyk;
-          pv[4] = gy * dyk;
-        } else {
-          pv[5] += gda;
-          pv[0] += gx;
-          pv[1] += gy;
-          pv[2] = __builtin_fmaf(gx, dx, pv[2]);
-          pv[3] = __builtin_fmaf(gx, dyk, pv[3]);
-          pv[4] = __builtin_fmaf(gy, dyk, pv[4]);
+        for (int k = 0; k < PPL; ++k) {
+          dy[k] = pixel_offset(pyc[k], r0.y, r0.w);
+          q[k] = pixel_q32(A, B2, Cc, dx, dy[k]);
+          hit[k] = idx < nl[k] && q[k] <= qcut;
         }
-        T[k] -= w;                       // as in the forward
+        float fv[FS4 * 4];
+#pragma unroll
+        for (int f = 0; f < FS4; ++f) {
+          const float4 t4 = s_f[j * (2 + FS4) + f];
+          fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
+        }
+        const float al = fv[F];
+        // Lanes whose pixel the pair does not reach run the same arithmetic
+        // with g = 0: alpha = w = 0, T and the prefix unchanged, terms +-0 (a
+        // pair that reaches no pixel of the tile gets a zero record this way;
+        // a branch around it would copy T and the prefix on every entry).
+        float pv[NR];
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
+          const float araw = al * g;
+          const float a = clamp_alpha(araw, amax);
+          const float w = a * T[k];
+          wrow[k * 64] = w;
+          float gf = kDA ? Gv[k][F] * (tz - t0[k]) : 0.0f;
+#pragma unroll
+          for (int f = 0; f < F; ++f) gf = __builtin_fmaf(Gv[k][f], fv[f], gf);
+          const float om = 1.0f - a;
+          const float inv = __builtin_amdgcn_rcpf(om);
+          // the suffix G.O - sum over entries up to this one of w gf
+          Spre[k] = __builtin_fmaf(w, gf, Spre[k]);
+          const float suffix = GO[k] - Spre[k];
+          float da = __builtin_fmaf(T[k], gf, -(suffix * inv));
+          if (kDA) da = __builtin_fmaf(GAf[k], inv, da);
+          // the clamp cuts alpha's dependence on g: gda = g da is dL/d(alpha)
+          // where it does not hold (0 where it does), and dL/dq = -(alpha / 2)
+          // gda, the factor -alpha / 2 being applied to the slot's sums by
+          // the projection adjoint
+          const float gda = araw > amax ? 0.0f : g * da;
+          // moments of gda over the pixel offsets; the projection adjoint
+          // turns them into dL/d(u, v, A, B, C) with the pair's conic (the
+          // first pixel of a lane sets the values, later ones add to them)
+          const float dyk = dy[k];
+          const float gx = gda * dx, gy = gda * dyk;
+          if (k == 0) {
+            pv[5] = gda;
+            pv[0] = gx;
+            pv[1] = gy;
+            pv[2] = gx * dx;
+            pv[3] = gx * dyk;
+            pv[4] = gy * dyk;
+          } else {
+            pv[5] += gda;
+            pv[0] += gx;
+            pv[1] += gy;
+            pv[2] = __builtin_fmaf(gx, dx, pv[2]);
+            pv[3] = __builtin_fmaf(gx, dyk, pv[3]);
+            pv[4] = __builtin_fmaf(gy, dyk, pv[4]);
+          }
+          T[k] -= w;                       // as in the forward
+        }
+        const float tot = wave_reduce_scatter<NR>(pv, lane);
+        if (kPadCol || writer) gcol[(size_t)e * GS] = tot;
+      };
+      for (int j = j0; j < j1; j += 2) {
+        entry(j);
+        if (j + 1 < j1) entry(j + 1);
       }
-      const float tot = wave_reduce_scatter<NR>(pv, lane);
-      if (writer) gcol[(size_t)e * GS] = tot;
-    }
-    __syncthreads();
-    feature_gemm<C, PPL>(s_w, s_e + j0, j1 - j0, bG, gpair);
-    __syncthreads();
+      __syncthreads();
+      feature_gemm<C, PPL>(s_w, s_e + j0, j1 - j0, bG, gpair);
+      __syncthreads();
     }
     __syncthreads();
   }
