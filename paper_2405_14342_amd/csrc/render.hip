@@ -521,14 +521,14 @@ __global__ __launch_bounds__(64) void k_render_fwd(
 
 // Backward compositing of the batch from the output gradient G (5 + C planes
 // per view), the outputs, T_final and n_last.
-// Register budgets of the backward kernels: with one pixel per lane, up to 8
-// classes and 16- or 32-entry staging, 7 or 6 waves per SIMD (what the LDS
-// block allows); the compiler meets them without spilling or extra
-// instructions, and the extra waves hide LDS and memory latency of the
-// VALU-bound loops.  Other instances keep the compiler's own budget (1).
+// Register budgets of the backward kernels: with one pixel per lane and up
+// to 8 classes, 7 waves per SIMD at 16-entry staging (what its LDS block
+// allows) and 5 at 32 entries (timed slightly faster than 6, the most its
+// LDS block allows); the compiler meets them without spilling in the entry
+// loops.  Other instances keep the compiler's own budget (1).
 template <int C, int PPL, int KS>
 constexpr int kWavesPerEu() {
-  return (PPL == 1 && C <= 8 && KS <= 32) ? (KS <= 16 ? 7 : 6) : 1;
+  return (PPL == 1 && C <= 8 && KS <= 32) ? (KS <= 16 ? 7 : 5) : 1;
 }
 template <int C, int PPL, int KS>
 __global__ __launch_bounds__(64)
