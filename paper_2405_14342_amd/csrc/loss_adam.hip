@@ -256,23 +256,42 @@ __device__ __forceinline__ void adam_surfel(int i, size_t N, float* __restrict__
                                             float b1, float b2, float eps, float bc1,
                                             float bc2s) {
   const float sx = s_act[i], sy = s_act[N + i], al = a_act[i];
+  // rows in groups of kRows: a group's loads are all issued before its
+  // stores, so one memory round trip serves kRows rows (the rows of one
+  // array are distinct addresses, which the compiler cannot prove itself)
+  constexpr int NR = 11 + C, kRows = 8;
 #pragma unroll
-  for (int r = 0; r < 11 + C; ++r) {
-    const size_t j = r * N + i;
-    float gr = g[r];
-    float lrr;
-    if (r == 0) lrr = lr_z;
-    else if (r <= 4) lrr = lr.q;
-    else if (r <= 6) { lrr = lr.s; gr *= (r == 5) ? sx : sy; }      // d/d log s = s d/ds
-    else if (r == 7) { lrr = lr.alpha; gr *= al * (1.0f - al); }   // d/d logit = a(1-a) d/da
-    else if (r <= 10) lrr = lr.rgb;
-    else lrr = lr.sem;
-    const float m = b1 * M[j] + (1.0f - b1) * gr;
-    const float v = b2 * Vv[j] + (1.0f - b2) * gr * gr;
-    M[j] = m;
-    Vv[j] = v;
-    const float denom = sqrtf(v) / bc2s + eps;
-    P[j] -= (lrr / bc1) * (m / denom);
+  for (int r0 = 0; r0 < NR; r0 += kRows) {
+    float pm[kRows], pv[kRows], pp[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+      if (r0 + u < NR) {
+        const size_t j = (size_t)(r0 + u) * N + i;
+        pm[u] = M[j];
+        pv[u] = Vv[j];
+        pp[u] = P[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+      const int r = r0 + u;
+      if (r >= NR) break;
+      const size_t j = (size_t)r * N + i;
+      float gr = g[r];
+      float lrr;
+      if (r == 0) lrr = lr_z;
+      else if (r <= 4) lrr = lr.q;
+      else if (r <= 6) { lrr = lr.s; gr *= (r == 5) ? sx : sy; }      // d/d log s = s d/ds
+      else if (r == 7) { lrr = lr.alpha; gr *= al * (1.0f - al); }   // d/d logit = a(1-a) d/da
+      else if (r <= 10) lrr = lr.rgb;
+      else lrr = lr.sem;
+      const float m = b1 * pm[u] + (1.0f - b1) * gr;
+      const float v = b2 * pv[u] + (1.0f - b2) * gr * gr;
+      M[j] = m;
+      Vv[j] = v;
+      const float denom = sqrtf(v) / bc2s + eps;
+      P[j] = pp[u] - (lrr / bc1) * (m / denom);
+    }
   }
   s_act[i] = expf(P[5 * N + i]);
   s_act[N + i] = expf(P[6 * N + i]);
