@@ -840,7 +840,7 @@ void slot_sums_launch(const Layout& L, void* ws, hipStream_t st, bool clear) {
                      misc, L.scap, L.cap, at<const uint32_t>(ws, L.o_scnt),
                      at<const uint32_t>(ws, L.o_soff), at<const float>(ws, L.o_gpair),
                      at<float>(ws, L.o_ssum), at<uint32_t>(ws, L.o_long), misc + kMiscLong);
-  hipLaunchKernelGGL((k_slot_sums_long<C>), dim3(4096), dim3(64), 0, st,
+  hipLaunchKernelGGL((k_slot_sums_long<C>), dim3(16384), dim3(64), 0, st,
                      at<const uint32_t>(ws, L.o_long), misc + kMiscLong, L.cap,
                      at<const uint32_t>(ws, L.o_scnt), at<const uint32_t>(ws, L.o_soff),
                      at<const float>(ws, L.o_gpair), at<float>(ws, L.o_ssum));

@@ -324,9 +324,8 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
     // T_final for dA/d(alpha_k) = T_final / (1 - alpha_k)
     GAf[k] = kDA ? __builtin_fmaf(t0[k], Gv[k][F], Gv[k][F + 1]) * Tf[k] : 0.0f;
   }
-  for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, (uint32_t)__shfl_xor((int)maxn, o, 64));
   // every lane holds the maximum: as a scalar the list loop is scalar control
-  maxn = (uint32_t)__builtin_amdgcn_readfirstlane((int)maxn);
+  maxn = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(maxn));
   const uint32_t stop = tg.rbeg + min(maxn, tg.rend - tg.rbeg);
   // B operand of feature_gemm: gamma[pixel][n] for pixel kk * 64 + kgrp * 16
   // + c, transposed through LDS (pixel-major rows of 16 * NFB + 1 floats);

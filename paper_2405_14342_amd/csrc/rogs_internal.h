@@ -454,6 +454,22 @@ __device__ __forceinline__ void rs_stage(const float* in, float* out, int lane) 
   }
 }
 
+// Maximum over the wave, in every lane: the exchanges of the reduce-scatter
+// (lane bits 32 and 16 by half-wave swaps, then the row mirrors and quad
+// swaps, which together reach all 16 lanes of a row) with max in place of
+// the sum.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  const auto r32 = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  x = max((uint32_t)r32[0], (uint32_t)r32[1]);
+  const auto r16 = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  x = max((uint32_t)r16[0], (uint32_t)r16[1]);
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xf, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xf, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xf, 0xf, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xf, 0xf, false));
+  return x;
+}
+
 template <int N>
 __device__ __forceinline__ float wave_reduce_scatter(const float* v, int lane) {
   constexpr int N1 = N > 1 ? rs_half(N) : 1;
