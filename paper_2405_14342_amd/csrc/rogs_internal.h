@@ -454,6 +454,25 @@ __device__ __forceinline__ void rs_stage(const float* in, float* out, int lane) 
   }
 }
 
+// x of lane (lane ^ j) for j = 1, 2, 4, 8, 16 or 32, a constant once the
+// caller's loop is unrolled: DPP quad swaps for 1 and 2, a swizzle inside
+// each half-wave for 4, a row rotation by 8 (which is lane ^ 8 inside each
+// row of 16) for 8, and for 16 and 32 the half-wave swaps, whose two results
+// hold x and x[lane ^ j] in some order, so their sum minus x is the latter
+// (exact in 32-bit wrap-around).
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, uint32_t j) {
+  if (j == 1u) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xf, 0xf, false);
+  if (j == 2u) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xf, 0xf, false);
+  if (j == 4u) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x101F);
+  if (j == 8u) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xf, 0xf, false);
+  if (j == 16u) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (uint32_t)r[0] + (uint32_t)r[1] - x;
+  }
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return (uint32_t)r[0] + (uint32_t)r[1] - x;
+}
+
 // Maximum over the wave, in every lane: the exchanges of the reduce-scatter
 // (lane bits 32 and 16 by half-wave swaps, then the row mirrors and quad
 // swaps, which together reach all 16 lanes of a row) with max in place of

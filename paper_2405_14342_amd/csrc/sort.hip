@@ -355,9 +355,9 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
       }
     }
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1)
+  for (uint32_t d = 1; d < 64u; d <<= 1)
 #pragma unroll
-    for (int k = 0; k < kX; ++k) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], d, 64));
+    for (int k = 0; k < kX; ++k) m[k] = min(m[k], lane_xor(m[k], d));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int kWaves = kEmitThreads / 64;
   if (lane < kX) {
@@ -481,8 +481,8 @@ __device__ __forceinline__ void wave_sort_regs(uint32_t (&key)[R], uint32_t (&e)
       } else {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const uint32_t ok = (uint32_t)__shfl_xor((int)key[r], (int)j, 64);
-          const uint32_t oe = (uint32_t)__shfl_xor((int)e[r], (int)j, 64);
+          const uint32_t ok = lane_xor(key[r], j);
+          const uint32_t oe = lane_xor(e[r], j);
           const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
           const bool keep_min = (((uint32_t)lane & j) == 0u) == ((i & k) == 0u);
           if (keep_min == key_less(ok, oe, key[r], e[r])) {
