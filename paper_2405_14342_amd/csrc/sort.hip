@@ -592,8 +592,10 @@ __global__ __launch_bounds__(64) void k_tile_sort_short(const uint4* __restrict_
     }
     for (int k = 2; k <= S; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
-        const uint32_t ok = (uint32_t)__shfl_xor((int)key, j, 64);
-        const uint32_t oe = (uint32_t)__shfl_xor((int)e, j, 64);
+        // partner lane ^ j (inside the wave: j < 64), one address for both
+        const int src = (lane ^ j) << 2;
+        const uint32_t ok = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)key);
+        const uint32_t oe = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)e);
         const bool keep_min = ((lane & j) == 0) == ((seg_lane & (uint32_t)k) == 0u);
         const bool other_less = key_less(ok, oe, key, e);
         if (keep_min == other_less) {
