@@ -215,8 +215,9 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_pdep = take(4 * (size_t)cap);
   l.o_tcnt = take(4 * (size_t)l.total_tiles);
   l.o_tstart = take(4 * (size_t)l.total_tiles);
-  l.o_tscan = take(4 * (17 * (size_t)((l.total_tiles + 1023) / 1024) + 17));   // tile layout partials
-  l.o_bstart = take(4 * ((size_t)cap / 1024 + 2));   // first slot of each emission block
+  l.o_tscan = take(4 * ((size_t)rogs::kTPart * ((l.total_tiles + rogs::kTileBlk - 1) / rogs::kTileBlk) +
+                         rogs::kTPart));                          // tile layout partials
+  l.o_bstart = take(4 * ((size_t)cap / rogs::kEmitPairs + 2));   // first slot of each emission block
   l.o_sval = take(4 * (size_t)scap);
   l.o_scnt = take(4 * (size_t)scap);
   l.o_soff = take(4 * (size_t)scap);

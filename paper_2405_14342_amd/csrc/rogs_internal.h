@@ -15,6 +15,12 @@ constexpr int kProjBlock = 256;     // threads per block of the per-surfel kerne
 constexpr int kMaskChunk = 8192;   // mask bytes per side block of the projection launch
 constexpr int kScanChunk = 4096;    // elements per block of the generic scan
 constexpr int kMaxViews = 4096;
+// Binning block sizes, shared with the workspace layout that sizes their
+// tables: pairs per emission block (one first-slot entry per block) and
+// tiles per block of the tile layout (kTPart partial words per block).
+constexpr int kEmitPairs = 1024;
+constexpr int kTileBlk = 1024;
+constexpr int kTPart = 17;          // per block: pairs, then the 16 bucket sizes
 
 // Device view table entry (one per camera of a batch).
 struct ViewDev {

@@ -18,7 +18,6 @@ __device__ __forceinline__ uint32_t count_n(const uint32_t* n_dev, int64_t n_hos
 }
 
 constexpr int kEmitThreads = 256;
-constexpr int kEmitPairs = 1024;
 constexpr int kEmitRows = 2048;
 constexpr int kEmitWin = 2 * kEmitRows;   // tiles of a block's count window
 
@@ -730,8 +729,6 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint4* __restrict_
 // kTileBlk tiles the pair count and the bucket sizes (k_tile_part), their
 // exclusive scans down the blocks and the totals (k_tile_top), then the
 // placement (k_tile_layout).
-constexpr int kTileBlk = 1024;      // tiles per block (4 rounds of 256)
-constexpr int kTPart = 17;          // per block: pairs, then the 16 bucket sizes
 
 __device__ __forceinline__ uint32_t tile_bucket(uint32_t len) {
   const int bl = len ? 32 - __clz((int)len) : 0;
