@@ -18,7 +18,7 @@ __device__ __forceinline__ uint32_t count_n(const uint32_t* n_dev, int64_t n_hos
 }
 
 constexpr int kEmitThreads = 256;
-constexpr int kEmitRows = 2048;
+constexpr int kEmitRows = 1024;
 constexpr int kEmitWin = 2 * kEmitRows;   // tiles of a block's count window
 
 // Visible slots in (view, surfel) order: each slot's position in that order
