@@ -297,6 +297,12 @@ void fill_view_table(const Layout& L, const rogs_camera* cams, void* dst,
     (void)rogs::view_shape(k, L.tw, L.th, &vtw, &vth);     // validated by make_layout
     d.tw = (int16_t)vtw;
     d.th = (int16_t)vth;
+    // the contract's clamp limits, rounded as the device rounded them in
+    // binary64, and the exact reciprocals of the tile sides
+    d.limx = (0.65 * (double)k.w) / (double)k.fx;
+    d.limy = (0.65 * (double)k.h) / (double)k.fy;
+    d.itw = 1.0 / (double)vtw;
+    d.ith = 1.0 / (double)vth;
     d.tiles_x = (k.w + vtw - 1) / vtw;
     d.tiles_y = (k.h + vth - 1) / vth;
     d.tile_off = (int32_t)tiles;

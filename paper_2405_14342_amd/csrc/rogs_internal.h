@@ -36,6 +36,11 @@ struct ViewDev {
   int32_t tile_off;     // first global tile index of the view
   uint32_t ch;          // ROGS_CH_* planes to composite (rogs_render_fwd ANDs its mask)
   int16_t tw, th;       // the view's tile shape (tw divides 64; tw * th is the batch's tile area)
+  // binary64 constants of the key contract, formed on the host with the
+  // contract's own operations: the pinhole clamp limits 0.65 W / f_x and
+  // 0.65 H / f_y, and 1 / tw, 1 / th (exact: the tile sides are powers of
+  // two, so multiplying by them rounds exactly as dividing by the sides)
+  double limx, limy, itw, ith;
 };
 
 // Number of semantic classes with a compiled kernel set.
@@ -185,8 +190,8 @@ __device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcu
   const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
   double j00, j11, j02, j12, u, v;
   if (c.model == ROGS_PINHOLE) {
-    const double limx = (0.65 * (double)c.w) / fx;
-    const double limy = (0.65 * (double)c.h) / fy;
+    const double limx = c.limx;
+    const double limy = c.limy;
     const double xr = tx / tz, yr = ty / tz;
     double xc = (xr < -limx) ? -limx : xr;
     xc = (limx < xc) ? limx : xc;
@@ -223,11 +228,10 @@ __device__ inline Proj project_contract(const ViewDev& c, float eps_f, float qcu
   if (!isfinite(u) || !isfinite(v) || !isfinite(hx) || !isfinite(hy) || !isfinite(A) ||
       !isfinite(B) || !isfinite(C))
     return r;
-  const int tw = c.tw, th = c.th;
-  const int x0 = clamp_tile(floor((u - hx) / (double)tw), c.tiles_x);
-  const int x1 = clamp_tile(floor((u + hx) / (double)tw) + 1.0, c.tiles_x);
-  const int y0 = clamp_tile(floor((v - hy) / (double)th), c.tiles_y);
-  const int y1 = clamp_tile(floor((v + hy) / (double)th) + 1.0, c.tiles_y);
+  const int x0 = clamp_tile(floor((u - hx) * c.itw), c.tiles_x);
+  const int x1 = clamp_tile(floor((u + hx) * c.itw) + 1.0, c.tiles_x);
+  const int y0 = clamp_tile(floor((v - hy) * c.ith), c.tiles_y);
+  const int y1 = clamp_tile(floor((v + hy) * c.ith) + 1.0, c.tiles_y);
   if (x0 >= x1 || y0 >= y1) return r;
   r.vis = true;
   r.uh = (float)u;
@@ -315,8 +319,9 @@ __device__ inline void span_row(const Span& s, int tw, int th, int W, int H, int
   if (!(pl <= pr) || pl > (double)(W - 1) || pr < 0.0) return;
   const int cl = pl < 0.0 ? 0 : (int)pl;
   const int cr = pr > (double)(W - 1) ? W - 1 : (int)pr;
-  const int l = max(cl / tw, s.x0);
-  const int h = min(cr / tw + 1, s.x1);
+  const int sh = __builtin_ctz((unsigned)tw);      // tw is a power of two; cl, cr >= 0
+  const int l = max(cl >> sh, s.x0);
+  const int h = min((cr >> sh) + 1, s.x1);
   if (l < h) {
     lo = l;
     hi = h;
