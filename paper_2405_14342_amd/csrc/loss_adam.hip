@@ -331,20 +331,19 @@ __global__ __launch_bounds__(256) void k_slot_sums(const uint32_t* __restrict__ 
   // after a pair-capacity overflow the records past the capacity were never written
   const uint32_t m = ((int64_t)o + n <= cap) ? n : (((int64_t)o < cap) ? (uint32_t)(cap - o) : 0u);
   const float4* col = reinterpret_cast<const float4*>(gpair) + (size_t)o * Q + q;
+  // rows in groups of four whose loads are issued together, the last group
+  // padded with +0 (the sum starts at +0 and never becomes -0, so adding +0
+  // changes no bit): the records are added in row order as before
   float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  uint32_t r = 0;
-  for (; r + 4 <= m; r += 4) {
+  for (uint32_t r = 0; r < m; r += 4) {
     float4 a[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = col[(size_t)(r + u) * Q];
+    for (int u = 0; u < 4; ++u)
+      a[u] = r + u < m ? col[(size_t)(r + u) * Q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       acc.x += a[u].x; acc.y += a[u].y; acc.z += a[u].z; acc.w += a[u].w;
     }
-  }
-  for (; r < m; ++r) {
-    const float4 a = col[(size_t)r * Q];
-    acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
   }
   reinterpret_cast<float4*>(ssum)[(size_t)k * Q + q] = acc;
 }
