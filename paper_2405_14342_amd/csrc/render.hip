@@ -66,14 +66,15 @@ __device__ __forceinline__ TileGeom tile_geom(const ViewDev* __restrict__ views,
                                               const uint4* __restrict__ tinfo) {
   TileGeom t;
   const int lane = threadIdx.x;
-  const uint4 ti = tinfo[blockIdx.x];      // tile, list begin, list end, view
+  // tile, list begin, list end, view | tile row << kViewBits
+  const uint4 ti = tinfo[blockIdx.x];
   t.gt = (int)ti.x;
-  t.v = (int)ti.w;
+  t.v = (int)(ti.w & ((1u << kViewBits) - 1u));
   t.vw = &views[t.v];
   t.W = t.vw->w;
   t.H = t.vw->h;
   const int lt = t.gt - t.vw->tile_off;
-  const int ty = lt / t.vw->tiles_x, tx = lt - ty * t.vw->tiles_x;
+  const int ty = (int)(ti.w >> kViewBits), tx = lt - ty * t.vw->tiles_x;
   const int tw = t.vw->tw, th = t.vw->th;
   const int sh = __builtin_ctz((unsigned)tw);      // tile_w divides 64: a power of two
   t.rows = 64 >> sh;

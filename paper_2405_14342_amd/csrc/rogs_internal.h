@@ -15,6 +15,10 @@ constexpr int kProjBlock = 256;     // threads per block of the per-surfel kerne
 constexpr int kMaskChunk = 8192;   // mask bytes per side block of the projection launch
 constexpr int kScanChunk = 4096;    // elements per block of the generic scan
 constexpr int kMaxViews = 4096;
+// A tile's work item (tile, list begin, list end, view | tile row << kViewBits):
+// the view index takes the low bits, the tile's row in its view the rest.
+constexpr int kViewBits = 12;
+static_assert(kMaxViews <= (1 << kViewBits), "view index field");
 // Binning block sizes, shared with the workspace layout that sizes their
 // tables: pairs per emission block (one first-slot entry per block) and
 // tiles per block of the tile layout (kTPart partial words per block).

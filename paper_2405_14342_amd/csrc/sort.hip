@@ -440,7 +440,8 @@ __global__ __launch_bounds__(256) void k_place(const uint32_t* __restrict__ keys
 }
 
 // Compositing work item of each launch position b: (tile, list begin, list
-// end, view) of the tile order[b], so a compositing wave starts from one load.
+// end, view | the tile's row in its view << kViewBits) of the tile order[b],
+// so a compositing wave starts from one load and needs no division.
 // Depth order inside each tile.  A tile's list holds its pairs in the order
 // the counters ranked them; these kernels order it by (t_z bits, emission
 // index e), which is the binary32 depth with ties by surfel id (emission runs
@@ -838,8 +839,11 @@ __global__ __launch_bounds__(256) void k_tile_layout(const uint32_t* __restrict_
         const int mid = (lo + hi + 1) >> 1;
         if (views[mid].tile_off <= (int32_t)i) lo = mid; else hi = mid - 1;
       }
-      tinfo[s_bst[d] + q] = c ? make_uint4((uint32_t)i, pst, pst + c, (uint32_t)lo)
-                              : make_uint4((uint32_t)i, 0u, 0u, (uint32_t)lo);
+      // the view and the tile's row in it (images are at most 16384 rows)
+      const uint32_t row_in_view = (uint32_t)(((int32_t)i - views[lo].tile_off) / views[lo].tiles_x);
+      const uint32_t vr = (uint32_t)lo | (row_in_view << kViewBits);
+      tinfo[s_bst[d] + q] = c ? make_uint4((uint32_t)i, pst, pst + c, vr)
+                              : make_uint4((uint32_t)i, 0u, 0u, vr);
     }
     __syncthreads();
     if (threadIdx.x < 16) {
