@@ -431,8 +431,8 @@ def serve_bench(seconds: float, warmup_s: float = 1.0, rates=(200.0, 8000.0),
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=3, help="1..4: workload (default 3)")
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the fused step on the 3M-surfel, 6 x 1920 x 1080 workload")
