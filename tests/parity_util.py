@@ -28,3 +28,25 @@ def grads_compare(g_gpu, ref_flat, n, C, tol=1e-4, cols=None):
         big = np.abs(r) >= 1e-2 * mx
         rel = d[big] / np.abs(r[big])
         assert rel.max() <= tol, (name, rel.max(), np.argmax(rel))
+
+
+def oracle_work_counts(prm, cams, o):
+    """Per batch, from the oracle's tile lists and forward: the list entries
+    every pixel visits up to its termination (its n_last) and those whose
+    binary32 3-sigma test passes; compared with rogs_debug_work."""
+    e_ref = k_ref = 0
+    for cam in cams:
+        _, rec, _ = oracle.contract(prm, cam, o)
+        _, ids, ranges = oracle.tile_lists(prm, cam, o)
+        _, _, nl = oracle.render_fwd(prm, cam, o)
+        tx = (cam.w + o.tile_w - 1) // o.tile_w
+        for py in range(cam.h):
+            for px in range(cam.w):
+                t = (py // o.tile_h) * tx + px // o.tile_w
+                a, _ = ranges[t]
+                n = int(nl[py * cam.w + px])
+                lst = ids[a:a + n]
+                e_ref += len(lst)
+                q = oracle.q32(rec[lst], [px], [py])[:, 0] if len(lst) else np.zeros(0)
+                k_ref += int((q <= np.float32(o.q_cut)).sum())
+    return e_ref, k_ref

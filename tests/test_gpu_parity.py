@@ -16,7 +16,7 @@ import oracle
 from paper_2405_14342_amd import binding as B
 from paper_2405_14342_amd import synth
 from paper_2405_14342_amd.pipeline import TrainState, n_out, paper_optim
-from parity_util import ROWS, grads_compare
+from parity_util import ROWS, grads_compare, oracle_work_counts
 
 pytestmark = pytest.mark.gpu
 
@@ -517,23 +517,7 @@ def test_work_counts_match_oracle_lists(gpu, name):
     st.rg.render_fwd(st.surfels(), ws, st.out)
     ev, co = st.rg.debug_work(ws)
     prm = oracle.Params.from_scene(sc)
-    o = oopts(st.opts)
-    e_ref = k_ref = 0
-    for cam in sc.cams:
-        _, rec, _ = oracle.contract(prm, cam, o)
-        keys, ids, ranges = oracle.tile_lists(prm, cam, o)
-        _, _, nl = oracle.render_fwd(prm, cam, o)
-        tx = (cam.w + o.tile_w - 1) // o.tile_w
-        for py in range(cam.h):
-            for px in range(cam.w):
-                t = (py // o.tile_h) * tx + px // o.tile_w
-                a, b = ranges[t]
-                n = int(nl[py * cam.w + px])
-                lst = ids[a:a + n]
-                e_ref += len(lst)
-                q = oracle.q32(rec[lst], [px], [py])[:, 0] if len(lst) else np.zeros(0)
-                k_ref += int((q <= np.float32(o.q_cut)).sum())
-    assert (ev, co) == (e_ref, k_ref)
+    assert (ev, co) == oracle_work_counts(prm, sc.cams, oopts(st.opts))
 
 
 @pytest.mark.parametrize("name", ["mini16", "c1"])
