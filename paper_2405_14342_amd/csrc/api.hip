@@ -205,7 +205,7 @@ int make_layout(const rogs_surfels* s, const rogs_camera* cams, int n_views,
   l.o_feat = take(4 * (size_t)l.N * l.FS);
   l.o_part = take(4 * (size_t)l.V * l.nb);
   l.o_partv = take(4 * (size_t)l.V * l.nb);
-  l.o_parttmp = take(4 * scan_tmp_words((int64_t)l.V * l.nb));
+  l.o_parttmp = take(4 * 2 * scan_tmp_words((int64_t)l.V * l.nb));   // one sums table each
   l.o_keys = take(4 * (size_t)cap);          // tile of each pair
   l.o_keys2 = take(4 * (size_t)cap);         // alternate keys of the pair sort
   l.o_vals = take(4 * (size_t)cap);

@@ -232,11 +232,12 @@ __device__ __forceinline__ int64_t scan_count(const uint32_t* n_dev, int64_t n) 
   return d < n ? d : n;
 }
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n_cap,
-                                                     const uint32_t* __restrict__ n_dev,
-                                                     uint32_t* __restrict__ sums) {
+// The three passes of the multi-block scan as block bodies: the single-table
+// kernels below and the paired ones (both projection count tables in one set
+// of launches) share them.
+__device__ __forceinline__ void scan_reduce_block(const uint32_t* __restrict__ in, int64_t n,
+                                                  uint32_t* __restrict__ sums) {
   __shared__ uint32_t s_w[4];
-  const int64_t n = scan_count(n_dev, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   uint32_t acc = 0;
   for (int k = threadIdx.x; k < kScanChunk; k += 256) {
@@ -249,9 +250,15 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
   if (threadIdx.x == 0) sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n_cap,
+                                                     const uint32_t* __restrict__ n_dev,
+                                                     uint32_t* __restrict__ sums) {
+  scan_reduce_block(in, scan_count(n_dev, n_cap), sums);
+}
+
 // Exclusive scan in place of m values with one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, int64_t m,
-                                                   uint32_t* __restrict__ total) {
+__device__ __forceinline__ void scan_top_block(uint32_t* __restrict__ sums, int64_t m,
+                                               uint32_t* __restrict__ total) {
   __shared__ uint32_t s_w[16];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t per = (m + 1023) / 1024;
@@ -275,13 +282,16 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, 
   if (t == 0 && total) *total = tot;
 }
 
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, int64_t m,
+                                                   uint32_t* __restrict__ total) {
+  scan_top_block(sums, m, total);
+}
+
 // in and out may be the same array (each block reads its chunk before writing it).
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n_cap,
-                                                   const uint32_t* __restrict__ n_dev,
-                                                   const uint32_t* __restrict__ sums) {
+__device__ __forceinline__ void scan_down_block(const uint32_t* in, uint32_t* out, int64_t n,
+                                                const uint32_t* __restrict__ sums) {
   __shared__ uint32_t s_v[kScanChunk];
   __shared__ uint32_t s_w[4];
-  const int64_t n = scan_count(n_dev, n_cap);
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   if (base >= n) return;
   for (int k = threadIdx.x; k < kScanChunk; k += 256) {
@@ -309,6 +319,33 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t*
     int64_t j = base + k;
     if (j < n) out[j] = s_v[k];
   }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n_cap,
+                                                   const uint32_t* __restrict__ n_dev,
+                                                   const uint32_t* __restrict__ sums) {
+  scan_down_block(in, out, scan_count(n_dev, n_cap), sums);
+}
+
+// Both projection count tables (pairs, visible slots; n values each, scanned
+// in place): table blockIdx.y of the reduce and down passes, block b of the
+// top pass; the sums of table a at sums + a * ms.
+__global__ __launch_bounds__(256) void k_scan2_reduce(uint32_t* t0, uint32_t* t1, int64_t n,
+                                                      uint32_t* __restrict__ sums, int64_t ms) {
+  scan_reduce_block(blockIdx.y ? t1 : t0, n, sums + blockIdx.y * ms);
+}
+
+__global__ __launch_bounds__(1024) void k_scan2_top(uint32_t* __restrict__ sums, int64_t ms,
+                                                    int64_t m, uint32_t* __restrict__ total0,
+                                                    uint32_t* __restrict__ total1) {
+  scan_top_block(sums + blockIdx.x * ms, m, blockIdx.x ? total1 : total0);
+}
+
+__global__ __launch_bounds__(256) void k_scan2_down(uint32_t* t0, uint32_t* t1, int64_t n,
+                                                    const uint32_t* __restrict__ sums,
+                                                    int64_t ms) {
+  uint32_t* t = blockIdx.y ? t1 : t0;
+  scan_down_block(t, t, n, sums + blockIdx.y * ms);
 }
 
 // Exclusive scan of at most kSmallScan values in one block of 1024 threads
@@ -456,10 +493,19 @@ void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts
                        mask_parts ? 0 : 1);   // the fused step's compaction sets the flag
     return;
   }
-  scan_u32(at<uint32_t>(ws, L.o_part), at<uint32_t>(ws, L.o_part), (int64_t)L.V * L.nb,
-           misc + kMiscPairs, at<uint32_t>(ws, L.o_parttmp), st);
-  scan_u32(at<uint32_t>(ws, L.o_partv), at<uint32_t>(ws, L.o_partv), (int64_t)L.V * L.nb,
-           misc + kMiscVisible, at<uint32_t>(ws, L.o_parttmp), st);
+  // both tables at once: three launches instead of six
+  const int64_t n = (int64_t)L.V * L.nb;
+  const int64_t m = (n + kScanChunk - 1) / kScanChunk;
+  const int64_t ms = (int64_t)scan_tmp_words(n);   // sums of one table
+  uint32_t* sums = at<uint32_t>(ws, L.o_parttmp);
+  uint32_t* part = at<uint32_t>(ws, L.o_part);
+  uint32_t* partv = at<uint32_t>(ws, L.o_partv);
+  hipLaunchKernelGGL(k_scan2_reduce, dim3((unsigned)m, 2), dim3(256), 0, st, part, partv, n, sums,
+                     ms);
+  hipLaunchKernelGGL(k_scan2_top, dim3(2), dim3(1024), 0, st, sums, ms, m, misc + kMiscPairs,
+                     misc + kMiscVisible);
+  hipLaunchKernelGGL(k_scan2_down, dim3((unsigned)m, 2), dim3(256), 0, st, part, partv, n, sums,
+                     ms);
   hipLaunchKernelGGL(k_check_cap, dim3((unsigned)std::max(1, mpart ? L.V : 1)), dim3(64), 0, st,
                      misc, L.cap, L.scap, mpart, nmb, L.V, mcount);
 }
