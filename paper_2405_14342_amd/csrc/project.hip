@@ -213,17 +213,6 @@ __device__ __forceinline__ void sum_mask_parts(const uint32_t* __restrict__ mpar
   if (threadIdx.x == 0) mcount[v] = t;
 }
 
-// Grid: one 64-lane block per view (at least one block).  Block 0 sets the
-// overflow flag; with mpart, block v sums view v's mask count.
-__global__ __launch_bounds__(64) void k_check_cap(uint32_t* misc, int64_t cap, int64_t scap,
-                                                  const uint32_t* __restrict__ mpart, int nmb,
-                                                  int V, uint32_t* __restrict__ mcount) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    misc[kMiscOverflow] =
-        ((int64_t)misc[kMiscPairs] > cap || (int64_t)misc[kMiscVisible] > scap) ? 1u : 0u;
-  if (mpart && (int)blockIdx.x < V) sum_mask_parts(mpart, nmb, (int)blockIdx.x, mcount);
-}
-
 // ------------------------------------------------------------ generic scan
 
 __device__ __forceinline__ int64_t scan_count(const uint32_t* n_dev, int64_t n) {
@@ -341,9 +330,24 @@ __global__ __launch_bounds__(1024) void k_scan2_top(uint32_t* __restrict__ sums,
   scan_top_block(sums + blockIdx.x * ms, m, blockIdx.x ? total1 : total0);
 }
 
+// A third row of blocks (blockIdx.y == 2) runs once the totals are known:
+// block 0 sets the overflow flag, and with mpart block x sums view x's mask
+// count.
 __global__ __launch_bounds__(256) void k_scan2_down(uint32_t* t0, uint32_t* t1, int64_t n,
                                                     const uint32_t* __restrict__ sums,
-                                                    int64_t ms) {
+                                                    int64_t ms, uint32_t* misc, int64_t cap,
+                                                    int64_t scap,
+                                                    const uint32_t* __restrict__ mpart, int nmb,
+                                                    int V, uint32_t* __restrict__ mcount) {
+  if (blockIdx.y == 2) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+      misc[kMiscOverflow] =
+          ((int64_t)misc[kMiscPairs] > cap || (int64_t)misc[kMiscVisible] > scap) ? 1u : 0u;
+    // one wave per view
+    if (mpart && (int)blockIdx.x < V && threadIdx.x < 64)
+      sum_mask_parts(mpart, nmb, (int)blockIdx.x, mcount);
+    return;
+  }
   uint32_t* t = blockIdx.y ? t1 : t0;
   scan_down_block(t, t, n, sums + blockIdx.y * ms);
 }
@@ -504,10 +508,9 @@ void launch_scan_part(const Layout& L, void* ws, hipStream_t st, bool mask_parts
                      ms);
   hipLaunchKernelGGL(k_scan2_top, dim3(2), dim3(1024), 0, st, sums, ms, m, misc + kMiscPairs,
                      misc + kMiscVisible);
-  hipLaunchKernelGGL(k_scan2_down, dim3((unsigned)m, 2), dim3(256), 0, st, part, partv, n, sums,
-                     ms);
-  hipLaunchKernelGGL(k_check_cap, dim3((unsigned)std::max(1, mpart ? L.V : 1)), dim3(64), 0, st,
-                     misc, L.cap, L.scap, mpart, nmb, L.V, mcount);
+  const int64_t gx = std::max<int64_t>(m, mpart ? L.V : 1);   // the scan's blocks, the views
+  hipLaunchKernelGGL(k_scan2_down, dim3((unsigned)gx, 3), dim3(256), 0, st, part, partv, n, sums,
+                     ms, misc, L.cap, L.scap, mpart, nmb, L.V, mcount);
 }
 
 }  // namespace rogs
