@@ -124,7 +124,9 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 // selected; T, n_last and the order of operations do not depend on it.
 constexpr int kFwdUnroll = 4;       // forward entries per stop test
 
-template <int C, int PPL, int KS, bool kE, bool kD>
+// With kG (16, one pixel per lane) the footprint weights g of the list's
+// first kG entries are kept in gsave for the backward.
+template <int C, int PPL, int KS, bool kE, bool kD, int kG = 0>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
                                              const uint32_t* __restrict__ spair,
@@ -132,10 +134,12 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
                                              const float4* __restrict__ feat, float4* s_r0,
                                              float4* s_r1, float4* s_f, const float* pyc,
                                              float (*acc)[3 + C + 1], float* T, uint32_t* nl,
-                                             uint32_t& e_first, float* t0, uint32_t ch) {
+                                             uint32_t& e_first, float* t0, uint32_t ch,
+                                             float* gsave = nullptr) {
   // every multiply-add is written out: the forward rounds the same in every
   // kernel it is inlined into
 #pragma clang fp contract(off)
+  static_assert(kG == 0 || (kG == 16 && PPL == 1 && KS >= kG), "kept weights");
   constexpr int F = 3 + C;            // composited features besides depth
   constexpr int FS4 = (F + 4) / 4;    // float4 per feature record (features, alpha)
   // a pixel is live while T >= t_eps (T only falls, and t_eps < 1); a pixel
@@ -156,59 +160,80 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
         stage_entries<FS4, kE>(base, cnt, tg.sbase, vals, spair, rec, feat, s_r0, s_r1, s_f);
     if (base == tg.rbeg) e_first = e;
     __syncthreads();
+    // one list entry for every pixel of the lane (gout: its g, or nullptr)
+    auto fentry = [&](const int j, float* gout) {
+      const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];   // u_hi v_hi u_lo v_lo | A 2B C tz
+      float fv[FS4 * 4];
+#pragma unroll
+      for (int f = 0; f < FS4; ++f) {
+        const float4 t4 = s_f[j * (2 + FS4) + f];
+        fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
+      }
+      const float al = fv[F];
+      const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
+      // Lanes whose pixel the entry does not reach, or has stopped, run the
+      // same arithmetic with g = 0: w = 0 leaves T and the sums as they are
+      // (T >= 0 and every feature is finite), so the result is that of a
+      // branch around the update without its exec-mask bookkeeping.
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        const float dy = pixel_offset(pyc[k], r0.y, r0.w);
+        const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
+        const bool live = T[k] >= teps;
+        const bool hit = live && q <= qcut;
+        // the exponential of every lane, then a select (no branch around it)
+        const float ge = gauss_weight(q);
+        const float g = hit ? ge : 0.0f;
+        if (gout) gout[k] = g;
+        const float a = clamp_alpha(al * g, amax);
+        const float w = a * T[k];
+        if (ch & ROGS_CH_RGB)
+#pragma unroll
+          for (int f = 0; f < 3; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+        if (ch & ROGS_CH_SEM)
+#pragma unroll
+          for (int f = 3; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
+        if (kD && (ch & ROGS_CH_D)) {
+          t0[k] = hit ? fminf(t0[k], r1.w) : t0[k];
+          acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
+        }
+        T[k] -= w;                     // T (1 - alpha)
+        // entries seen while live: at the entry that stops the pixel, its
+        // position in the list plus one
+        nl[k] += live ? 1u : 0u;
+      }
+    };
+    // every lane of the wave runs this loop: the ballot is the stop test
+    auto all_stopped = [&]() {
+      bool live = false;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) live = live || T[k] >= teps;
+      return __builtin_amdgcn_ballot_w64(live) == 0;
+    };
     // groups of kFwdUnroll entries, the stop test after each group: entries
     // past a pixel's stop change nothing for it, so the results are those
-    // of a test after every entry
-    for (int j0 = 0; j0 < cnt; j0 += kFwdUnroll) {
+    // of a test after every entry.  The first kG entries of the list are
+    // unrolled whole, so that their weights land in registers.
+    // (a constant trip count without early exits: it unrolls fully)
+    int jstart = 0;
+    if (kG > 0 && base == tg.rbeg) {
+#pragma unroll
+      for (int j = 0; j < kG; ++j) {
+        if (j < cnt && !stop_all) {
+          fentry(j, gsave + j);
+          if (j % kFwdUnroll == kFwdUnroll - 1 && all_stopped()) stop_all = true;
+        }
+      }
+      jstart = kG;
+    }
+    for (int j0 = jstart; j0 < cnt && !stop_all; j0 += kFwdUnroll) {
 #pragma unroll
       for (int u = 0; u < kFwdUnroll; ++u) {
         const int j = j0 + u;
         if (j >= cnt) break;
-        const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];   // u_hi v_hi u_lo v_lo | A 2B C tz
-        float fv[FS4 * 4];
-#pragma unroll
-        for (int f = 0; f < FS4; ++f) {
-          const float4 t4 = s_f[j * (2 + FS4) + f];
-          fv[4 * f] = t4.x; fv[4 * f + 1] = t4.y; fv[4 * f + 2] = t4.z; fv[4 * f + 3] = t4.w;
-        }
-        const float al = fv[F];
-        const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
-        // Lanes whose pixel the entry does not reach, or has stopped, run the
-        // same arithmetic with g = 0: w = 0 leaves T and the sums as they are
-        // (T >= 0 and every feature is finite), so the result is that of a
-        // branch around the update without its exec-mask bookkeeping.
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-          const float dy = pixel_offset(pyc[k], r0.y, r0.w);
-          const float q = pixel_q32(r1.x, r1.y, r1.z, dx, dy);
-          const bool live = T[k] >= teps;
-          const bool hit = live && q <= qcut;
-          const float g = hit ? gauss_weight(q) : 0.0f;
-          const float a = clamp_alpha(al * g, amax);
-          const float w = a * T[k];
-          if (ch & ROGS_CH_RGB)
-#pragma unroll
-            for (int f = 0; f < 3; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-          if (ch & ROGS_CH_SEM)
-#pragma unroll
-            for (int f = 3; f < F; ++f) acc[k][f] = __builtin_fmaf(w, fv[f], acc[k][f]);
-          if (kD && (ch & ROGS_CH_D)) {
-            t0[k] = hit ? fminf(t0[k], r1.w) : t0[k];
-            acc[k][F] = __builtin_fmaf(w, r1.w - t0[k], acc[k][F]);
-          }
-          T[k] -= w;                     // T (1 - alpha)
-          // entries seen while live: at the entry that stops the pixel, its
-          // position in the list plus one
-          nl[k] += live ? 1u : 0u;
-        }
+        fentry(j, nullptr);
       }
-      bool live = false;
-#pragma unroll
-      for (int k = 0; k < PPL; ++k) live = live || T[k] >= teps;
-      if (__builtin_amdgcn_ballot_w64(live) == 0) {
-        stop_all = true;
-        break;
-      }
+      if (all_stopped()) stop_all = true;
     }
     __syncthreads();
   }
@@ -285,8 +310,10 @@ __device__ __forceinline__ void feature_gemm(const float* s_w, const uint32_t* s
 // n_last and the reference depth t0 (used with kDA).  Writes one record of NV
 // gradient values per pair at its emission index: the five moments and
 // dalpha are summed across the wave with a reduce-scatter, the feature and
-// depth gradients come from feature_gemm once per 16 entries.
-template <int C, int PPL, int KS, bool kDA>
+// depth gradients come from feature_gemm once per 16 entries.  With kG (16,
+// one pixel per lane) gsave holds the forward's footprint weights of the
+// list's first kG entries, valid for the entries before n_last.
+template <int C, int PPL, int KS, bool kDA, int kG = 0>
 __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, float amax,
                                               const uint32_t* __restrict__ vals,
                                               const uint32_t* __restrict__ spair,
@@ -297,10 +324,12 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
                                               const float (*Gv)[3 + C + 2], const float* GO,
                                               const float* Tf, const uint32_t* nl,
                                               float* __restrict__ gpair, bool staged,
-                                              uint32_t e_pre, const float* t0) {
+                                              uint32_t e_pre, const float* t0,
+                                              const float* gsave = nullptr) {
   // every multiply-add is written out: the backward rounds the same in the
   // fused step and in the stand-alone backward
 #pragma clang fp contract(off)
+  static_assert(kG == 0 || (kG == 16 && PPL == 1 && KS >= kG), "kept weights");
   constexpr int F = 3 + C;
   constexpr int FS4 = (F + 4) / 4;
   // per pair: sum gda dx, sum gda dy, sum gda dx^2, sum gda dx dy,
@@ -371,20 +400,25 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
       const int j1 = min(j0 + 16, cnt);
       // two entries per iteration (immediate LDS offsets, half the loop
       // bookkeeping); the second is skipped past the block's end
-      auto entry = [&](const int j) {
+      // gk: the pixels' kept weights of entry j, or nullptr
+      auto entry = [&](const int j, const float* gk) {
         const uint32_t idx = base - tg.rbeg + (uint32_t)j;
         const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)e_mine, j);
         const float4 r0 = s_r0[j * (2 + FS4)], r1 = s_r1[j * (2 + FS4)];
         const float A = r1.x, B2 = r1.y, Cc = r1.z, tz = r1.w;
         const float dx = pixel_offset(tg.pxc, r0.x, r0.z);
         float* wrow = s_w + (j - j0) * WS + lane;
-        float dy[PPL], q[PPL];
-        bool hit[PPL];
+        float dy[PPL], gw[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
           dy[k] = pixel_offset(pyc[k], r0.y, r0.w);
-          q[k] = pixel_q32(A, B2, Cc, dx, dy[k]);
-          hit[k] = idx < nl[k] && q[k] <= qcut;
+          if (gk) {
+            gw[k] = idx < nl[k] ? gk[k] : 0.0f;
+          } else {
+            const float q = pixel_q32(A, B2, Cc, dx, dy[k]);
+            const float ge = gauss_weight(q);
+            gw[k] = (idx < nl[k] && q <= qcut) ? ge : 0.0f;
+          }
         }
         float fv[FS4 * 4];
 #pragma unroll
@@ -400,7 +434,7 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
         float pv[NR];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-          const float g = hit[k] ? gauss_weight(q[k]) : 0.0f;
+          const float g = gw[k];
           const float araw = al * g;
           const float a = clamp_alpha(araw, amax);
           const float w = a * T[k];
@@ -445,9 +479,17 @@ __device__ __forceinline__ void backward_tile(const TileGeom& tg, float qcut, fl
         const float tot = wave_reduce_scatter<NR>(pv, lane);
         if (kPadCol || writer) gcol[(size_t)e * GS] = tot;
       };
-      for (int j = j0; j < j1; j += 2) {
-        entry(j);
-        if (j + 1 < j1) entry(j + 1);
+      if (kG > 0 && base == tg.rbeg && j0 == 0) {
+        // the list's first block, unrolled whole so that the kept weights
+        // are read from registers
+#pragma unroll
+        for (int j = 0; j < kG; ++j)
+          if (j < j1) entry(j, gsave + j);
+      } else {
+        for (int j = j0; j < j1; j += 2) {
+          entry(j, nullptr);
+          if (j + 1 < j1) entry(j + 1, nullptr);
+        }
       }
       __syncthreads();
       feature_gemm<C, PPL>(s_w, s_e + j0, j1 - j0, bG, gpair);
@@ -661,9 +703,16 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_st
     float t0[PPL];          // not used: the fused loss has no depth term
 #pragma unroll
     for (int k = 0; k < PPL; ++k) t0[k] = 0.0f;
-    forward_tile<C, PPL, KS, true, false>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0,
-                                          s_r1, s_f, pyc, acc, T, nlf, e_first, t0,
-                                          ROGS_CH_RGB | ROGS_CH_SEM);
+    // the footprint weights of the list's first 16 entries, kept from the
+    // forward for the backward where the register budget has room for them
+    // (one pixel per lane, 32-entry staging: at 16 they would spill)
+    constexpr int kG = (PPL == 1 && KS == 32 && C <= 8) ? 16 : 0;
+    float gsv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gsv[j] = 0.0f;
+    forward_tile<C, PPL, KS, true, false, kG>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0,
+                                              s_r1, s_f, pyc, acc, T, nlf, e_first, t0,
+                                              ROGS_CH_RGB | ROGS_CH_SEM, gsv);
     // loss epilogue: dL/dO and G.O per pixel, this tile's loss partials
     const uint32_t len = tg.rend - tg.rbeg;
     float l = 0.0f, dal = 0.0f, dbl = 0.0f;
@@ -698,9 +747,9 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_st
       if (c >= 0 && (lane & rs_dup_bits(3)) == 0) fl.part[3 * (size_t)tg.gt + c] = tot;
     }
     // the fused loss has no depth or alpha term: their gradient rows are zero
-    backward_tile<C, PPL, KS, false>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1, s_f,
-                                     reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO, Tf, nl,
-                                     gpair, len <= (uint32_t)KS, e_first, t0);
+    backward_tile<C, PPL, KS, false, kG>(tg, qcut, amax, vals, spair, rec, feat, s_r0, s_r1,
+                                         s_f, reinterpret_cast<float*>(s_w4), s_e, pyc, Gv, GO,
+                                         Tf, nl, gpair, len <= (uint32_t)KS, e_first, t0, gsv);
   }
 }
 
