@@ -772,9 +772,21 @@ int rogs_debug_records(rogs_ctx* c, void* ws, float* rec, int32_t* rect, uint32_
     e = hipMemcpyAsync(rc.data(), rogs::at<void>(ws, L.o_rect), 8 * S, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(count, rogs::at<void>(ws, L.o_cnt), 4 * S, hipMemcpyDeviceToHost, st);
+  // the scanned visible counts per (view, projection block) and their total:
+  // a block with no visible slot in a view writes no counts
+  const size_t nparts = (size_t)L.V * L.nb;
+  std::vector<uint32_t> partv(nparts + 1);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(partv.data(), rogs::at<void>(ws, L.o_partv), 4 * nparts,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(partv.data() + nparts, rogs::at<uint32_t>(ws, L.o_misc) + rogs::kMiscVisible,
+                       4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(c, e, "rogs_debug_records");
   for (size_t k = 0; k < S; ++k) {
+    const size_t pb = (k / (size_t)L.N) * (size_t)L.nb + (k % (size_t)L.N) / rogs::kProjBlock;
+    if (partv[pb + 1] == partv[pb]) count[k] = 0;
     if (count[k] == 0) {   // culled slots keep no record
       for (int j = 0; j < 8; ++j) rec[8 * k + j] = 0.0f;
       for (int j = 0; j < 4; ++j) rect[4 * k + j] = 0;

@@ -394,6 +394,8 @@ __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ 
                                              int N, float eps, float x, float y, float z,
                                              const float q[4], float sx, float sy, float alpha,
                                              const uint32_t* __restrict__ pos, int64_t scap,
+                                             const uint32_t* __restrict__ partv,
+                                             uint32_t vis_total, int nb, int blk,
                                              const float* __restrict__ ssum,
                                              const float4* __restrict__ rec, float* vals) {
   constexpr int GSC = ((10 + C) + 3) & ~3;
@@ -405,7 +407,15 @@ __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ 
   for (int c = 0; c < 3 + C; ++c) dft[c] = 0.0f;
   // the slots' positions (0xffffffff for a culled slot; after a slot-capacity
   // overflow a visible slot may have none either, and the results are flagged
-  // invalid) are requested kPre views at a time, ahead of their sums
+  // invalid) are requested kPre views at a time, ahead of their sums.  Where
+  // the projection block blk (kProjBlock surfels) has no visible slot in a
+  // view (its scanned visible count, partv, does not grow), the slots have no
+  // position and are culled.
+  const size_t nparts = (size_t)V * nb;
+  auto block_vis = [&](int v) {
+    const size_t pb = (size_t)v * nb + blk;
+    return (pb + 1 < nparts ? partv[pb + 1] : vis_total) != partv[pb];
+  };
   constexpr int kPre = 8;
   uint32_t pv[kPre];
   for (int v = 0; v < V; ++v) {
@@ -413,7 +423,7 @@ __device__ __forceinline__ void surfel_grads(int i, const ViewDev* __restrict__ 
     if (k == 0) {
 #pragma unroll
       for (int j = 0; j < kPre; ++j)
-        pv[j] = (v + j < V) ? pos[(size_t)(v + j) * N + i] : 0xffffffffu;
+        pv[j] = (v + j < V && block_vis(v + j)) ? pos[(size_t)(v + j) * N + i] : 0xffffffffu;
     }
     uint32_t p = pv[0];
 #pragma unroll
@@ -463,14 +473,16 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd(
     const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
     const float* __restrict__ py, const float* __restrict__ pz, const float* __restrict__ pq,
     const float* __restrict__ ps, const float* __restrict__ pa,
-    const uint32_t* __restrict__ pos, int64_t scap, const float* __restrict__ ssum,
+    const uint32_t* __restrict__ pos, int64_t scap, const uint32_t* __restrict__ partv,
+    const uint32_t* __restrict__ misc, const float* __restrict__ ssum,
     const float4* __restrict__ rec, float* __restrict__ grads, int accumulate) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
   if (i >= N) return;
   const float q[4] = {pq[i], pq[N + i], pq[2 * (size_t)N + i], pq[3 * (size_t)N + i]};
   float vals[11 + C];
   surfel_grads<C>(i, views, V, N, eps, px[i], py[i], pz[i], q, ps[i], ps[N + i], pa[i], pos,
-                  scap, ssum, rec, vals);
+                  scap, partv, misc[kMiscVisible], (int)gridDim.x, (int)blockIdx.x, ssum, rec,
+                  vals);
   const size_t Nn = (size_t)N;
 #pragma unroll
   for (int r = 0; r < 11 + C; ++r) {
@@ -487,7 +499,7 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
     const ViewDev* __restrict__ views, int V, int N, float eps, const float* __restrict__ px,
     const float* __restrict__ py, float* __restrict__ P, float* __restrict__ M,
     float* __restrict__ Vv, float* __restrict__ s_act, float* __restrict__ a_act,
-    const uint32_t* __restrict__ pos, int64_t scap,
+    const uint32_t* __restrict__ pos, int64_t scap, const uint32_t* __restrict__ partv,
     const float* __restrict__ ssum, const float4* __restrict__ rec, const float* __restrict__ dzr,
     float* __restrict__ grads_out, AdamArgs aa) {
   const int i = blockIdx.x * kProjBlock + threadIdx.x;
@@ -497,7 +509,8 @@ __global__ __launch_bounds__(kProjBlock) void k_proj_bwd_adam(
   const float q[4] = {P[Nn + i], P[2 * Nn + i], P[3 * Nn + i], P[4 * Nn + i]};
   float vals[11 + C];
   surfel_grads<C>(i, views, V, N, eps, px[i], py[i], P[i], q, s_act[i], s_act[Nn + i], a_act[i],
-                  pos, scap, ssum, rec, vals);
+                  pos, scap, partv, aa.misc[kMiscVisible], (int)gridDim.x, (int)blockIdx.x, ssum,
+                  rec, vals);
   if (dzr) vals[0] += dzr[i];
   if (grads_out) {
 #pragma unroll
@@ -516,7 +529,8 @@ void proj_bwd_launch(const Layout& L, void* ws, const rogs_surfels* s, float* gr
   hipLaunchKernelGGL((k_proj_bwd<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, s->x, s->y, s->z, s->q,
                      s->s, s->alpha, at<const uint32_t>(ws, L.o_pos),
-                     L.scap, at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), grads,
+                     L.scap, at<const uint32_t>(ws, L.o_partv), at<const uint32_t>(ws, L.o_misc),
+                     at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), grads,
                      acc ? 1 : 0);
 }
 
@@ -777,8 +791,8 @@ void proj_bwd_adam_launch(const Layout& L, void* ws, const float* x, const float
   hipLaunchKernelGGL((k_proj_bwd_adam<C>), dim3(L.nb), dim3(kProjBlock), 0, st,
                      at<const ViewDev>(ws, L.o_views), L.V, L.N, L.eps2d, x, y, params, m, v,
                      s_act, a_act, at<const uint32_t>(ws, L.o_pos),
-                     L.scap, at<const float>(ws, L.o_ssum), at<const float4>(ws, L.o_rec), dzr,
-                     grads_out, aa);
+                     L.scap, at<const uint32_t>(ws, L.o_partv), at<const float>(ws, L.o_ssum),
+                     at<const float4>(ws, L.o_rec), dzr, grads_out, aa);
 }
 }  // namespace
 

@@ -108,9 +108,10 @@ __global__ __launch_bounds__(kProjBlock) void k_project(
   const size_t slot = (size_t)v * N + i;
   // a block none of whose surfels lies in the view's ground rectangle (most
   // blocks of a long road) is culled whole: the same test the contract takes
-  // first, without the projection, scans and barriers of the full path
+  // first, without the projection, scans and barriers of the full path.  Its
+  // slots' counts are not written: every reader of per-slot arrays tests the
+  // block's visible count (partv) first.
   if (!__syncthreads_or(valid && ground_inside(vw, px[i], py[i]))) {
-    if (valid) cnt[slot] = 0u;
     if (threadIdx.x == 0) {
       part[(size_t)v * nb + blockIdx.x] = 0u;
       partv[(size_t)v * nb + blockIdx.x] = 0u;

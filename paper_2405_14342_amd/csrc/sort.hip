@@ -53,13 +53,11 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
   for (int v = 0; v < V; ++v) {
     const size_t slot = (size_t)v * N + i;
     // the scanned visible counts give this block's count in view v: none
-    // visible (a block the view's ground rectangle misses) needs no scan
+    // visible (a block the view's ground rectangle misses) needs no scan, and
+    // its slots get no position (the projection adjoint makes the same test)
     const size_t pb = (size_t)v * nb + blockIdx.x;
     const uint32_t vnext = pb + 1 < nparts ? partv[pb + 1] : misc[kMiscVisible];
-    if (vnext == partv[pb]) {
-      if (valid) spos[slot] = 0xffffffffu;
-      continue;
-    }
+    if (vnext == partv[pb]) continue;
     const uint32_t c = valid ? cnt[slot] : 0u;
     const bool vis = c != 0;
     const unsigned long long b = __ballot(vis);
@@ -74,8 +72,8 @@ __global__ __launch_bounds__(kProjBlock) void k_compact(int V, int N, int nb,
       off += s_p[w];
     }
     __syncthreads();
-    // every slot's position, 0xffffffff for a culled one or one beyond the
-    // slot capacity
+    // every slot's position in a block with visible slots, 0xffffffff for a
+    // culled one or one beyond the slot capacity
     uint32_t sp = 0xffffffffu;
     if (vis) {
       const uint32_t pos = pre + (uint32_t)__popcll(b & lt_mask);
