@@ -705,8 +705,10 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_st
     for (int k = 0; k < PPL; ++k) t0[k] = 0.0f;
     // the footprint weights of the list's first 16 entries, kept from the
     // forward for the backward where the register budget has room for them
-    // (one pixel per lane, 32-entry staging: at 16 they would spill)
-    constexpr int kG = (PPL == 1 && KS == 32 && C <= 8) ? 16 : 0;
+    // (one pixel per lane; up to 8 classes only with 32-entry staging, since
+    // at 16 they would spill; with 16 classes the kernel runs 3 waves per
+    // SIMD with or without them)
+    constexpr int kG = (PPL == 1 && (C > 8 || KS == 32)) ? 16 : 0;
     float gsv[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) gsv[j] = 0.0f;
