@@ -125,7 +125,10 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 constexpr int kFwdUnroll = 4;       // forward entries per stop test
 
 // With kG (16, one pixel per lane) the footprint weights g of the list's
-// first kG entries are kept in gsave for the backward.
+// first kG entries are kept in gsave for the backward: gsave[j] is written
+// for every entry the forward evaluates, which covers each pixel's entries
+// before n_last, the only ones the backward reads it for (entries after the
+// whole wave has stopped keep the caller's values).
 template <int C, int PPL, int KS, bool kE, bool kD, int kG = 0>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
