@@ -108,6 +108,36 @@ def test_projection_records_bitexact(gpu, name):
         assert np.all(cnt[v][vis] <= (r[:, 1] - r[:, 0]) * (r[:, 3] - r[:, 2]))
 
 
+def test_projection_records_after_workspace_reuse(gpu):
+    # a second batch on the same workspace with the views in reverse order:
+    # projection blocks that a view of the first batch reached and the same
+    # view slot of the second culls whole keep the first batch's per-slot
+    # values in memory, and must still report no pairs
+    sc = make_scene("mini")
+    assert len(sc.cams) > 1 and sc.n > 4 * 256
+    st, ws, _ = batched_state(sc)
+    cams = list(reversed(st.cams))
+    ws2, _ = st.project_and_sort(cams, "cap_batch", "_ws_batch")
+    assert ws2.data_ptr() == ws.data_ptr()
+    _, _, cnt = st.rg.debug_records(ws2, st.V, st.N)
+    prm = oracle.Params.from_scene(sc)
+    stale = 0
+    for v, cam in enumerate(reversed(sc.cams)):
+        vis, _, _ = oracle.contract(prm, cam, oopts(st.opts))
+        _, oids, _ = oracle.tile_lists(prm, cam, oopts(st.opts))
+        ocnt = np.bincount(oids, minlength=sc.n)
+        np.testing.assert_array_equal(cnt[v], np.where(vis, ocnt, 0))
+        # blocks culled here whose surfels the first batch's view v reached
+        vis1, _, _ = oracle.contract(prm, sc.cams[v], oopts(st.opts))
+        b2 = np.zeros(-(-sc.n // 256) * 256, bool)
+        b2[:sc.n] = vis
+        culled = ~b2.reshape(-1, 256).any(1)
+        b1 = np.zeros_like(b2)
+        b1[:sc.n] = vis1
+        stale += int((culled & b1.reshape(-1, 256).any(1)).sum())
+    assert stale > 0
+
+
 @pytest.mark.parametrize("name", SCENES + ["stack", "flat"])
 def test_keys_order_ranges_bitexact(gpu, name):
     sc = make_scene(name)
