@@ -125,10 +125,10 @@ __device__ __forceinline__ uint32_t stage_entries(uint32_t base, int cnt, uint32
 constexpr int kFwdUnroll = 4;       // forward entries per stop test
 
 // With kG (16, one pixel per lane) the footprint weights g of the list's
-// first kG entries are kept in gsave for the backward: gsave[j] is written
-// for every entry the forward evaluates, which covers each pixel's entries
-// before n_last, the only ones the backward reads it for (entries after the
-// whole wave has stopped keep the caller's values).
+// first kG entries are kept in gsave for the backward: gsave[j] is the
+// weight of every entry the forward evaluates, which covers each pixel's
+// entries before n_last, the only ones the backward reads it for, and 0 for
+// the others (past the list's end or after the whole wave has stopped).
 template <int C, int PPL, int KS, bool kE, bool kD, int kG = 0>
 __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, float amax,
                                              float teps, const uint32_t* __restrict__ vals,
@@ -225,6 +225,8 @@ __device__ __forceinline__ void forward_tile(const TileGeom& tg, float qcut, flo
         if (j < cnt && !stop_all) {
           fentry(j, gsave + j);
           if (j % kFwdUnroll == kFwdUnroll - 1 && all_stopped()) stop_all = true;
+        } else {
+          gsave[j] = 0.0f;
         }
       }
       jstart = kG;
@@ -713,8 +715,6 @@ __attribute__((amdgpu_waves_per_eu(kWavesPerEu<C, PPL, KS>()))) void k_render_st
     // SIMD with or without them)
     constexpr int kG = (PPL == 1 && (C > 8 || KS == 32)) ? 16 : 0;
     float gsv[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) gsv[j] = 0.0f;
     forward_tile<C, PPL, KS, true, false, kG>(tg, qcut, amax, teps, vals, spair, rec, feat, s_r0,
                                               s_r1, s_f, pyc, acc, T, nlf, e_first, t0,
                                               ROGS_CH_RGB | ROGS_CH_SEM, gsv);
