@@ -492,6 +492,25 @@ def test_fused_step_equals_batched_plus_adam(gpu, name, eager):
     assert abs(stf["loss"] - a.loss.item()) <= 1e-5 * abs(a.loss.item())
 
 
+@pytest.mark.parametrize("name,stage", [("mini", 32), ("mini16", 16), ("mini16", 32),
+                                        ("mini16", 64)])
+def test_fused_step_one_pixel_per_lane_equals_batched(gpu, name, stage):
+    # 16 x 4 tiles (one pixel per lane): where the fused step keeps the
+    # forward's footprint weights of each list's first 16 entries for its
+    # backward (up to 8 classes at 32-entry staging; 16 classes at every
+    # staging depth), they must be the bits the batched backward recomputes
+    sc = make_scene(name)
+    a = TrainState(sc, opts=B.make_opts(tile_w=16, tile_h=4, stage=stage))
+    a.step_batched(total_steps=5)
+    b = TrainState(sc, opts=B.make_opts(tile_w=16, tile_h=4, stage=stage))
+    b.step_fused(total_steps=5, grads_out=True)
+    torch.cuda.synchronize()
+    sa, sb = _snapshot(a), _snapshot(b)
+    for k in ("params", "m", "v", "s_act", "alpha_act"):
+        assert torch.equal(sa[k], sb[k]), k
+    assert torch.equal(a.grads.cpu(), b.grads.cpu())
+
+
 def test_fused_graph_replays_match_eager(gpu):
     sc = make_scene("mini")
     a = TrainState(sc)
